@@ -1,0 +1,232 @@
+#!/usr/bin/env python3
+"""Reconstructed faces/s of the NENO6 hot path on one MI355X.
+
+Workload: 256 independent 1D Euler Riemann problems of 4000 cells each
+(seeded synthetic states, gamma = 1.4, transmissive boundaries), the
+6-64-32-16-8-4 classifier with oracle-trained weights.  One step = one SSP-RK3
+step of the whole batch (time step from the CFL condition, three right-hand
+sides: characteristic projection, Rusanov split, classifier per field and
+sign, re-normalised combine, back-projection, flux difference, stage update),
+captured once in a HIP graph and replayed.
+
+Headline path: FP32 state, classifier in BF16 on MFMA with the FP32 re-check.
+Also measured on the same GPU: the plain FP64 path and FP16-MFMA, the flip
+rate of the BF16 labels against the FP64 labels on the same input state, the
+L1 / Linf distance of the BF16 state from the FP64 state after the timed
+steps, the fused face kernel alone (roofline), and the FP64 CPU oracle on a
+bounded sample (cpu_baseline).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_PROBLEMS, N_CELLS, CFL = 256, 4000, 0.4
+MARGIN = {2: 0.5, 3: 0.25}
+PEAK_MFMA_BF16 = 2500.0  # TFLOP/s dense, MI355X
+FLOP_PER_EVAL = 6208      # 2 x 3104 MAC of the 6-64-32-16-8-4 network
+EVALS_PER_FACE = 6        # 3 characteristic fields x 2 split signs
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2207_08500_amd import inputs, native
+
+    native.load()
+    dev = torch.device("cuda:0")
+    P = np.load(os.path.join(ROOT, "tests", "golden", "neno6_mlp_trained.npy"), allow_pickle=False)
+    q0, off, dx = inputs.riemann1d_batch(inputs.BASE_SEED, (N_CELLS,) * N_PROBLEMS)
+    faces_stage = int(off[-1]) + N_PROBLEMS
+    faces_step = 3 * faces_stage
+    q32 = torch.as_tensor(q0, dtype=torch.float32, device=dev).contiguous()
+    q64_from32 = q32.double().contiguous()  # the same (FP32-rounded) state for both paths
+
+    def make(prec, margin=0.0):
+        mlp = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=margin)
+        prob = native.Problem(native.EULER1D, prec, native.SEL_MLP, native.TRANSMISSIVE, off, dx,
+                              device=dev)
+        return mlp, prob, prob.workspace(dev)
+
+    def run_steps(prec, q_init, steps, warmup, graph=True):
+        mlp, prob, ws = make(prec, MARGIN.get(prec, 0.0))
+        q = q_init.clone()
+        t = torch.zeros(N_PROBLEMS, dtype=torch.float64, device=dev)
+        st = torch.zeros(N_PROBLEMS, dtype=torch.int32, device=dev)
+
+        def step():
+            native.neno6_step(prob, mlp, q, CFL, 1, t, st, ws)
+
+        g = None
+        if graph:
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                step()  # one eager step before capture
+            torch.cuda.current_stream().wait_stream(s)
+            q.copy_(q_init)
+            t.zero_()
+            st.zero_()
+            try:
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g):
+                    step()
+            except Exception as e:  # pragma: no cover - capture problems are reported
+                print("graph capture failed, eager launches: %s" % e, file=sys.stderr)
+                g = None
+            q.copy_(q_init)
+            t.zero_()
+            st.zero_()
+        go = g.replay if g is not None else step
+        for _ in range(warmup):
+            go()
+        torch.cuda.synchronize()
+        q.copy_(q_init)  # timed steps start from the initial state
+        t.zero_()
+        st.zero_()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(steps):
+            go()
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1)
+        return q, t, st, ms, wall, g is not None
+
+    # ---- headline: BF16-MFMA ---------------------------------------------------
+    qb, tb, stb, ms_b, wall_b, graphed = run_steps(native.BF16, q32, a.steps, a.warmup,
+                                                   graph=not a.no_graph)
+    value = faces_step * a.steps / (ms_b / 1e3)
+    # ---- same GPU: FP64 plain and FP16-MFMA --------------------------------------
+    k64 = max(2, a.steps // 4)
+    q64, t64, st64, ms_64, _, _ = run_steps(native.FP64, q64_from32, k64, 1, graph=not a.no_graph)
+    fp64_rate = faces_step * k64 / (ms_64 / 1e3)
+    qh, th, sth, ms_h, _, _ = run_steps(native.FP16, q32, a.steps, 1, graph=not a.no_graph)
+    fp16_rate = faces_step * a.steps / (ms_h / 1e3)
+    # accuracy of the timed BF16 run against an FP64 run of the same number of steps
+    q64b, t64b, st64b, _, _, _ = run_steps(native.FP64, q64_from32, a.steps, 0, graph=not a.no_graph)
+    dq = (qb.double() - q64b).abs().reshape(3, -1)
+    ref = q64b.reshape(3, -1)
+    l1 = float((dq.mean(dim=1) / ref.abs().mean(dim=1)).max())
+    linf = float((dq.max(dim=1).values / ref.abs().max(dim=1).values).max())
+
+    # ---- labels on an identical input state: BF16 (+re-check) vs FP64 ---------------
+    def labels(prec, q):
+        mlp, prob, ws = make(prec, MARGIN.get(prec, 0.0))
+        r = torch.zeros_like(q)
+        m = torch.zeros(prob.mask_count(), dtype=torch.uint8, device=dev)
+        native.neno6_rhs(prob, mlp, q, r, ws, masks_out=m)
+        return m
+
+    m64 = labels(native.FP64, q64_from32)
+    mb16 = labels(native.BF16, q32)
+    mh16 = labels(native.FP16, q32)
+    torch.cuda.synchronize()
+
+    def flip(ma, mb):
+        x = (ma ^ mb).cpu().numpy()
+        return float(np.unpackbits(x.reshape(-1, 1), axis=1).sum() / (8.0 * x.size))
+
+    flip_b, flip_h = flip(mb16, m64), flip(mh16, m64)
+
+    # ---- fused face kernel alone, BF16 (roofline) ------------------------------------
+    mlp0, prob0, ws0 = make(native.BF16, 0.0)  # margin 0: exactly the fused kernel
+    F = torch.zeros(3 * faces_stage, dtype=torch.float32, device=dev)
+    for _ in range(3):
+        native.neno6_face_fluxes(prob0, mlp0, q32, F, ws0)
+    torch.cuda.synchronize()
+    reps = 50
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        native.neno6_face_fluxes(prob0, mlp0, q32, F, ws0)
+    e1.record()
+    torch.cuda.synchronize()
+    k_ms = e0.elapsed_time(e1) / reps
+    flop = faces_stage * EVALS_PER_FACE * FLOP_PER_EVAL
+    achieved = flop / (k_ms / 1e3) / 1e12
+
+    # ---- CPU oracle on a bounded sample ------------------------------------------------
+    cpu = None
+    if not a.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        done_faces, t_cpu, p = 0, 0.0, 0
+        while t_cpu < a.cpu_seconds and p < N_PROBLEMS:
+            k = min(16, N_PROBLEMS - p)
+            sub = q0[:, off[p]:off[p + k]]
+            o_sub = off[p:p + k + 1] - off[p]
+            c0 = time.perf_counter()
+            oracle.euler1d_step(sub, o_sub, dx[p:p + k], CFL, 1, 1.4, oracle.BC_TRANSMISSIVE, P,
+                                oracle.SEL_MLP)
+            t_cpu += time.perf_counter() - c0
+            done_faces += 3 * (int(o_sub[-1]) + k)
+            p += k
+        cpu = {"value": done_faces / t_cpu, "unit": "faces/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": "%d of the %d problems, one RK3 step each (%d faces, %.1f s), FP64 C oracle"
+                         % (p, N_PROBLEMS, done_faces, t_cpu)}
+
+    out = {
+        "metric": "reconstructed faces/s: plain FP64 vs BF16-MFMA NENO6 at stated flip rate/L1 error",
+        "value": value,
+        "unit": "faces/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_b / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "1D Euler Riemann batch: %d problems x %d cells, characteristic NENO6, "
+                               "LF splitting, SSP-RK3 CFL %.1f; FP32 state, BF16-MFMA classifier, "
+                               "FP32 re-check margin %.2f" % (N_PROBLEMS, N_CELLS, CFL, MARGIN[2]),
+                   "faces_per_step": faces_step, "hip_graph": graphed},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_BF16,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_MFMA_BF16, "traffic": None,
+                     "kernel": "k_fast_euler1d<bf16>", "kernel_ms": k_ms,
+                     "algorithmic_flop_per_launch": flop},
+        "fp64_plain": {"value": fp64_rate, "unit": "faces/s", "ms_per_step": ms_64 / k64,
+                       "steps": k64},
+        "fp16_mfma": {"value": fp16_rate, "unit": "faces/s", "ms_per_step": ms_h / a.steps,
+                      "flip_rate": flip_h},
+        "speedup_bf16_vs_fp64": value / fp64_rate,
+        "flip_rate": flip_b,
+        "l1_rel_vs_fp64": l1,
+        "linf_rel_vs_fp64": linf,
+        "status_ok": bool((stb == 0).all().item()),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

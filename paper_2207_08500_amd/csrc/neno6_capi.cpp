@@ -1,0 +1,430 @@
+// C-ABI entry points of libneno6.so: argument checks, workspace carving and
+// the launch sequence of each call.  All numerical work is in the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "../../include/neno6.h"
+#include "neno6_fast.h"
+#include "neno6_internal.h"
+
+using namespace n6;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+
+// Bump allocator over the caller's workspace.
+struct Carve {
+  char *base;
+  size_t used = 0;
+  template <typename T> T *take(size_t n) {
+    T *p = base ? (T *)(base + used) : nullptr;
+    used = align_up(used + n * sizeof(T));
+    return p;
+  }
+};
+
+inline int32_t hip_status(hipError_t e) { return e == hipSuccess ? NENO6_OK : NENO6_HIP_ERROR; }
+
+bool valid_precision(int32_t p) { return p >= NENO6_FP64 && p <= NENO6_FP16; }
+bool valid_selector(int32_t s) { return s >= NENO6_SEL_MLP && s <= NENO6_SEL_MASKS_IN; }
+
+int32_t check_mlp(const neno6_mlp *mlp, int32_t selector, int32_t precision) {
+  if (selector != NENO6_SEL_MLP) return NENO6_OK;
+  if (!mlp || !mlp->params) return NENO6_BAD_ARG;
+  if (precision != NENO6_FP64 && !mlp->prepared) return NENO6_BAD_ARG;
+  return NENO6_OK;
+}
+
+int nvar_of(int32_t eq) { return eq == NENO6_ADVECTION ? 1 : (eq == NENO6_EULER1D ? 3 : 4); }
+
+int32_t check_problem(const neno6_problem *pb) {
+  if (!pb) return NENO6_BAD_ARG;
+  if (pb->equation != NENO6_ADVECTION && pb->equation != NENO6_EULER1D &&
+      pb->equation != NENO6_EULER2D)
+    return NENO6_BAD_ARG;
+  if (pb->bc != NENO6_PERIODIC && pb->bc != NENO6_TRANSMISSIVE) return NENO6_BAD_ARG;
+  if (!valid_precision(pb->precision) || !valid_selector(pb->selector)) return NENO6_BAD_ARG;
+  if (pb->equation == NENO6_EULER2D) {
+    if (pb->nx < 1 || pb->ny < 1 || !(pb->dx2d > 0) || !(pb->dy2d > 0) || !(pb->gamma > 1))
+      return NENO6_BAD_ARG;
+    if (pb->nx > (1 << 20) || pb->ny > (1 << 20)) return NENO6_BAD_ARG;
+    return NENO6_OK;
+  }
+  if (pb->n_problems < 1 || !pb->offsets || !pb->offsets_host || !pb->dx) return NENO6_BAD_ARG;
+  if (pb->offsets_host[0] != 0 || pb->offsets_host[pb->n_problems] != pb->total_cells)
+    return NENO6_BAD_ARG;
+  for (int32_t p = 0; p < pb->n_problems; ++p)
+    if (pb->offsets_host[p + 1] <= pb->offsets_host[p]) return NENO6_BAD_ARG;
+  if (pb->equation == NENO6_EULER1D && !(pb->gamma > 1)) return NENO6_BAD_ARG;
+  return NENO6_OK;
+}
+
+Line1D line_of(const neno6_problem *pb) {
+  Line1D ln;
+  ln.offsets = pb->offsets;
+  ln.dx = pb->dx;
+  ln.np = pb->n_problems;
+  ln.total = pb->total_cells;
+  ln.bc = pb->bc;
+  ln.gamma = pb->gamma;
+  return ln;
+}
+
+Grid2D grid_of(const neno6_problem *pb) {
+  Grid2D g;
+  g.nx = pb->nx;
+  g.ny = pb->ny;
+  g.dx = pb->dx2d;
+  g.dy = pb->dy2d;
+  g.gamma = pb->gamma;
+  g.bc = pb->bc;
+  return g;
+}
+
+size_t elem_size(int32_t prec) { return prec == NENO6_FP64 ? sizeof(double) : sizeof(float); }
+
+// Workspace layout (same carving for size query and use).
+struct Work {
+  void *F = nullptr, *G = nullptr;  // face fluxes (1D: F only)
+  void *u1 = nullptr, *u2 = nullptr;
+  double *dt = nullptr, *part = nullptr;
+  int32_t *dummy_status = nullptr;
+  FastScratch scr{};                // reduced-precision path only
+  size_t bytes = 0;
+};
+
+Work carve_work(const neno6_problem *pb, void *ws) {
+  Carve c{(char *)ws};
+  Work w;
+  const size_t es = elem_size(pb->precision);
+  const int nv = nvar_of(pb->equation);
+  if (pb->equation == NENO6_EULER2D) {
+    const size_t cells = (size_t)pb->nx * pb->ny;
+    w.F = c.take<char>(es * 4 * (size_t)(pb->nx + 1) * pb->ny);
+    w.G = c.take<char>(es * 4 * (size_t)pb->nx * (pb->ny + 1));
+    w.u1 = c.take<char>(es * 4 * cells);
+    w.u2 = c.take<char>(es * 4 * cells);
+    w.dt = c.take<double>(1);
+    w.part = c.take<double>(3 * (size_t)cfl2d_parts());
+    w.dummy_status = c.take<int32_t>(1);
+  } else {
+    const size_t faces = (size_t)pb->total_cells + pb->n_problems;
+    w.F = c.take<char>(es * nv * faces);
+    w.u1 = c.take<char>(es * nv * (size_t)pb->total_cells);
+    w.u2 = c.take<char>(es * nv * (size_t)pb->total_cells);
+    w.dt = c.take<double>(pb->n_problems);
+    w.dummy_status = c.take<int32_t>(pb->n_problems);
+  }
+  if (pb->precision >= NENO6_BF16) {
+    // masks of every face (x and y faces in 2D), re-check queue of at most
+    // one entry per evaluation (8 per face slot), its flags and counter
+    const size_t faces = pb->equation == NENO6_EULER2D
+                             ? (size_t)(pb->nx + 1) * pb->ny + (size_t)pb->nx * (pb->ny + 1)
+                             : (size_t)pb->total_cells + pb->n_problems;
+    const size_t qfaces = pb->equation == NENO6_EULER2D
+                              ? std::max((size_t)(pb->nx + 1) * pb->ny, (size_t)pb->nx * (pb->ny + 1))
+                              : faces;
+    w.scr.masks = c.take<uint8_t>(4 * faces);
+    w.scr.queue = c.take<uint32_t>(8 * qfaces);
+    w.scr.qflag = c.take<uint8_t>(8 * qfaces);
+    w.scr.qcount = c.take<uint32_t>(1);
+    w.scr.qcap = (int64_t)(8 * qfaces);
+  }
+  w.bytes = c.used;
+  return w;
+}
+
+// Face fluxes + flux difference (+ optional RK3 stage) for one state.
+template <typename T>
+int32_t rhs_impl(const neno6_problem *pb, const T *P, const void *q, void *rhs,
+                 const uint8_t *masks_in, uint8_t *masks_out, int32_t *status, const Work &w,
+                 const Stage *st, hipStream_t s) {
+  hipError_t e;
+  if (pb->equation == NENO6_EULER2D) {
+    const Grid2D g = grid_of(pb);
+    const size_t nfx = 4 * (size_t)(g.nx + 1) * g.ny;
+    e = launch_faces_euler2d<T>(g, P, pb->selector, (const T *)q, masks_in,
+                                masks_in ? masks_in + nfx : nullptr, (T *)w.F, (T *)w.G, masks_out,
+                                masks_out ? masks_out + nfx : nullptr, s);
+    if (e != hipSuccess) return NENO6_HIP_ERROR;
+    e = launch_diff2d<T>(g, (const T *)w.F, (const T *)w.G, (const T *)q, (T *)rhs, st, status, s);
+    return hip_status(e);
+  }
+  const Line1D ln = line_of(pb);
+  if (pb->equation == NENO6_ADVECTION)
+    e = launch_faces_advection<T>(ln, P, pb->selector, (const T *)q, masks_in, (T *)w.F,
+                                  masks_out, s);
+  else
+    e = launch_faces_euler1d<T>(ln, P, pb->selector, (const T *)q, masks_in, (T *)w.F, masks_out,
+                                s);
+  if (e != hipSuccess) return NENO6_HIP_ERROR;
+  e = launch_diff1d<T>(ln, nvar_of(pb->equation), (const T *)w.F, (const T *)q, (T *)rhs, st,
+                       status, s);
+  return hip_status(e);
+}
+
+const float *prepared_f32(const neno6_mlp *mlp) {
+  return mlp ? (const float *)fast_prepared_f32(mlp->prepared) : nullptr;
+}
+
+// Dispatch one right-hand side evaluation in the problem's precision.
+int32_t rhs_dispatch(const neno6_problem *pb, const neno6_mlp *mlp, const void *q, void *rhs,
+                     const uint8_t *masks_in, uint8_t *masks_out, int32_t *status, const Work &w,
+                     const Stage *st, hipStream_t s) {
+  switch (pb->precision) {
+  case NENO6_FP64:
+    return rhs_impl<double>(pb, mlp ? mlp->params : nullptr, q, rhs, masks_in, masks_out, status,
+                            w, st, s);
+  case NENO6_FP32:
+    return rhs_impl<float>(pb, prepared_f32(mlp), q, rhs, masks_in, masks_out, status, w, st, s);
+  default: {
+    FastArgs fa;
+    fa.equation = pb->equation;
+    fa.precision = pb->precision;
+    fa.selector = pb->selector;
+    fa.prepared = mlp ? mlp->prepared : nullptr;
+    fa.margin = mlp ? mlp->recheck_margin : 0.f;
+    fa.scr = w.scr;
+    if (pb->equation == NENO6_EULER2D) {
+      const Grid2D g = grid_of(pb);
+      return hip_status(launch_fast_rhs2d(g, fa, (const float *)q, (float *)rhs, masks_in,
+                                          masks_out, status, (float *)w.F, (float *)w.G, st, s));
+    }
+    return hip_status(launch_fast_rhs1d(line_of(pb), fa, (const float *)q, (float *)rhs, masks_in,
+                                        masks_out, status, (float *)w.F, st, s));
+  }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *neno6_status_string(int32_t st) {
+  switch (st) {
+  case NENO6_OK: return "ok";
+  case NENO6_BAD_ARG: return "bad argument";
+  case NENO6_BAD_LAYOUT: return "precision/layout combination not valid";
+  case NENO6_HIP_ERROR: return "HIP error";
+  case NENO6_NONPHYSICAL: return "state not physical (rho <= 0, p <= 0 or not finite)";
+  case NENO6_UNSUPPORTED: return "unsupported for this equation or precision";
+  case NENO6_WORKSPACE_SMALL: return "workspace too small";
+  default: return "unknown status";
+  }
+}
+
+int32_t neno6_version(void) { return 10000; }
+
+size_t neno6_mlp_prepared_bytes(void) { return fast_prepared_bytes(); }
+
+int32_t neno6_mlp_prepare(const neno6_mlp *mlp, hipStream_t stream) {
+  if (!mlp || !mlp->params || !mlp->prepared) return NENO6_BAD_ARG;
+  return hip_status(launch_fast_prepare(mlp->params, mlp->prepared, stream));
+}
+
+int32_t neno6_mlp_logits(const neno6_mlp *mlp, int32_t precision, const void *s, int64_t n,
+                         void *z, uint8_t *masks, hipStream_t stream) {
+  if (!valid_precision(precision) || n < 0 || (n > 0 && (!s || !z))) return NENO6_BAD_ARG;
+  if (int32_t c = check_mlp(mlp, NENO6_SEL_MLP, precision)) return c;
+  switch (precision) {
+  case NENO6_FP64:
+    return hip_status(launch_mlp_logits<double>(mlp->params, (const double *)s, n, (double *)z,
+                                                masks, stream));
+  case NENO6_FP32:
+    return hip_status(launch_mlp_logits<float>(prepared_f32(mlp), (const float *)s, n, (float *)z,
+                                               masks, stream));
+  default:
+    return hip_status(launch_fast_logits(mlp->prepared, precision, mlp->recheck_margin,
+                                         (const float *)s, n, (float *)z, masks, stream));
+  }
+}
+
+int32_t neno6_reconstruct(const neno6_mlp *mlp, const void *f, int64_t n_faces, int32_t sign,
+                          int32_t precision, int32_t selector, const uint8_t *masks_in,
+                          void *fhat, uint8_t *masks_out, hipStream_t stream) {
+  if (!valid_precision(precision) || !valid_selector(selector) || n_faces < 0 ||
+      (sign != 1 && sign != -1))
+    return NENO6_BAD_ARG;
+  if (n_faces > 0 && (!f || !fhat)) return NENO6_BAD_ARG;
+  if (selector == NENO6_SEL_MASKS_IN && !masks_in) return NENO6_BAD_ARG;
+  if (int32_t c = check_mlp(mlp, selector, precision)) return c;
+  switch (precision) {
+  case NENO6_FP64:
+    return hip_status(launch_reconstruct<double>(mlp ? mlp->params : nullptr, (const double *)f,
+                                                 n_faces, sign, selector, masks_in,
+                                                 (double *)fhat, masks_out, stream));
+  case NENO6_FP32:
+    return hip_status(launch_reconstruct<float>(prepared_f32(mlp), (const float *)f, n_faces, sign,
+                                                selector, masks_in, (float *)fhat, masks_out,
+                                                stream));
+  default:
+    return hip_status(launch_fast_reconstruct(mlp ? mlp->prepared : nullptr, precision,
+                                              mlp ? mlp->recheck_margin : 0.f, (const float *)f,
+                                              n_faces, sign, selector, masks_in, (float *)fhat,
+                                              masks_out, stream));
+  }
+}
+
+size_t neno6_workspace_size(const neno6_problem *prob) {
+  if (check_problem(prob) != NENO6_OK) return 0;
+  return carve_work(prob, nullptr).bytes;
+}
+
+int32_t neno6_rhs(const neno6_problem *prob, const neno6_mlp *mlp, const void *q, void *rhs,
+                  const uint8_t *masks_in, uint8_t *masks_out, int32_t *status, void *ws,
+                  size_t ws_bytes, hipStream_t stream) {
+  if (int32_t c = check_problem(prob)) return c;
+  if (int32_t c = check_mlp(mlp, prob->selector, prob->precision)) return c;
+  if (!q || !rhs || !ws) return NENO6_BAD_ARG;
+  if (prob->selector == NENO6_SEL_MASKS_IN && !masks_in) return NENO6_BAD_ARG;
+  const Work w = carve_work(prob, ws);
+  if (ws_bytes < w.bytes) return NENO6_WORKSPACE_SMALL;
+  return rhs_dispatch(prob, mlp, q, rhs, masks_in, masks_out, status, w, nullptr, stream);
+}
+
+int32_t neno6_face_fluxes(const neno6_problem *prob, const neno6_mlp *mlp, const void *q, void *F,
+                          uint8_t *masks_out, void *ws, size_t ws_bytes, hipStream_t stream) {
+  if (int32_t c = check_problem(prob)) return c;
+  if (int32_t c = check_mlp(mlp, prob->selector, prob->precision)) return c;
+  if (prob->selector == NENO6_SEL_MASKS_IN) return NENO6_UNSUPPORTED;
+  if (!q || !F || !ws) return NENO6_BAD_ARG;
+  const Work w = carve_work(prob, ws);
+  if (ws_bytes < w.bytes) return NENO6_WORKSPACE_SMALL;
+  const bool is2d = prob->equation == NENO6_EULER2D;
+  const size_t nfx = is2d ? 4 * (size_t)(prob->nx + 1) * prob->ny : 0;
+  hipError_t e;
+  if (prob->precision >= NENO6_BF16) {
+    FastArgs fa;
+    fa.equation = prob->equation;
+    fa.precision = prob->precision;
+    fa.selector = prob->selector;
+    fa.prepared = mlp ? mlp->prepared : nullptr;
+    fa.margin = mlp ? mlp->recheck_margin : 0.f;
+    fa.scr = w.scr;
+    e = is2d ? launch_fast_faces2d(grid_of(prob), fa, (const float *)q, nullptr, masks_out,
+                                   (float *)F, (float *)F + nfx, stream)
+             : launch_fast_faces1d(line_of(prob), fa, (const float *)q, nullptr, masks_out,
+                                   (float *)F, stream);
+    return hip_status(e);
+  }
+  const int nv = nvar_of(prob->equation);
+  const uint8_t *mx = nullptr;
+  if (prob->precision == NENO6_FP64) {
+    const double *P = mlp ? mlp->params : nullptr;
+    if (is2d)
+      e = launch_faces_euler2d<double>(grid_of(prob), P, prob->selector, (const double *)q, mx, mx,
+                                       (double *)F, (double *)F + nfx, masks_out,
+                                       masks_out ? masks_out + nfx : nullptr, stream);
+    else if (nv == 1)
+      e = launch_faces_advection<double>(line_of(prob), P, prob->selector, (const double *)q, mx,
+                                         (double *)F, masks_out, stream);
+    else
+      e = launch_faces_euler1d<double>(line_of(prob), P, prob->selector, (const double *)q, mx,
+                                       (double *)F, masks_out, stream);
+  } else {
+    const float *P = prepared_f32(mlp);
+    if (is2d)
+      e = launch_faces_euler2d<float>(grid_of(prob), P, prob->selector, (const float *)q, mx, mx,
+                                      (float *)F, (float *)F + nfx, masks_out,
+                                      masks_out ? masks_out + nfx : nullptr, stream);
+    else if (nv == 1)
+      e = launch_faces_advection<float>(line_of(prob), P, prob->selector, (const float *)q, mx,
+                                        (float *)F, masks_out, stream);
+    else
+      e = launch_faces_euler1d<float>(line_of(prob), P, prob->selector, (const float *)q, mx,
+                                      (float *)F, masks_out, stream);
+  }
+  return hip_status(e);
+}
+
+int32_t neno6_step(const neno6_problem *prob, const neno6_mlp *mlp, void *q, double cfl,
+                   int32_t n_steps, double *t, int32_t *status, void *ws, size_t ws_bytes,
+                   hipStream_t stream) {
+  if (int32_t c = check_problem(prob)) return c;
+  if (int32_t c = check_mlp(mlp, prob->selector, prob->precision)) return c;
+  if (prob->selector == NENO6_SEL_MASKS_IN) return NENO6_UNSUPPORTED;
+  if (!q || !t || !status || !ws || n_steps < 0 || !(cfl > 0)) return NENO6_BAD_ARG;
+  const Work w = carve_work(prob, ws);
+  if (ws_bytes < w.bytes) return NENO6_WORKSPACE_SMALL;
+  const bool f64 = prob->precision == NENO6_FP64;
+  for (int32_t it = 0; it < n_steps; ++it) {
+    hipError_t e;
+    if (prob->equation == NENO6_EULER2D) {
+      const Grid2D g = grid_of(prob);
+      e = f64 ? launch_cfl2d<double>(g, (const double *)q, cfl, w.part, w.dt, status, t, stream)
+              : launch_cfl2d<float>(g, (const float *)q, cfl, w.part, w.dt, status, t, stream);
+    } else {
+      const Line1D ln = line_of(prob);
+      e = f64 ? launch_cfl1d<double>(ln, prob->equation, (const double *)q, cfl, w.dt, status, t,
+                                     stream)
+              : launch_cfl1d<float>(ln, prob->equation, (const float *)q, cfl, w.dt, status, t,
+                                    stream);
+    }
+    if (e != hipSuccess) return NENO6_HIP_ERROR;
+    // u1 = stage 1 of q; u2 = stage 2 of u1; q = stage 3 of u2
+    const void *ins[3] = {q, w.u1, w.u2};
+    void *outs[3] = {w.u1, w.u2, q};
+    for (int k = 0; k < 3; ++k) {
+      Stage st;
+      st.stage = k + 1;
+      st.us = ins[k];
+      st.u0 = q;
+      st.out = outs[k];
+      st.dt = w.dt;
+      st.status = status;
+      int32_t r = rhs_dispatch(prob, mlp, ins[k], nullptr, nullptr, nullptr, nullptr, w, &st,
+                               stream);
+      if (r != NENO6_OK) return r;
+    }
+  }
+  return NENO6_OK;
+}
+
+int32_t neno6_rhs_adjoint(const neno6_problem *prob, const uint8_t *masks, const void *rbar,
+                          void *ubar, hipStream_t stream) {
+  if (int32_t c = check_problem(prob)) return c;
+  if (prob->equation != NENO6_ADVECTION || prob->n_problems != 1) return NENO6_UNSUPPORTED;
+  if (prob->precision != NENO6_FP64 && prob->precision != NENO6_FP32) return NENO6_BAD_LAYOUT;
+  if (!masks || !rbar || !ubar) return NENO6_BAD_ARG;
+  return hip_status(launch_adjoint_advection(line_of(prob), masks, rbar, ubar,
+                                             prob->precision == NENO6_FP64, stream));
+}
+
+size_t neno6_train_workspace_size(int32_t batch) { return train_workspace_bytes(batch); }
+
+int32_t neno6_classifier_train(double *params, double *adam_m, double *adam_v, int64_t *step,
+                               const float *s, const uint8_t *y, const int64_t *idx, int64_t n_idx,
+                               int32_t batch, double lr, double beta1, double beta2, double eps,
+                               int32_t precision, double *loss_out, void *ws, size_t ws_bytes,
+                               hipStream_t stream) {
+  if (!params || !adam_m || !adam_v || !step || !s || !y || !idx || n_idx < 1 || batch < 1 ||
+      batch > (1 << 20) || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) ||
+      !(eps > 0) || !ws)
+    return NENO6_BAD_ARG;
+  if (precision != NENO6_FP32 && precision != NENO6_BF16) return NENO6_BAD_LAYOUT;
+  if (ws_bytes < train_workspace_bytes(batch)) return NENO6_WORKSPACE_SMALL;
+  for (int64_t s0 = 0; s0 < n_idx; s0 += batch) {
+    const int64_t mb = n_idx - s0 < batch ? n_idx - s0 : batch;
+    *step += 1;
+    hipError_t e = launch_train_batch(params, adam_m, adam_v, *step, s, y, idx + s0, mb, lr, beta1,
+                                      beta2, eps, precision, loss_out, 1.0 / (double)n_idx,
+                                      s0 == 0, ws, stream);
+    if (e != hipSuccess) return NENO6_HIP_ERROR;
+  }
+  return NENO6_OK;
+}
+
+int32_t neno6_classifier_grad(const double *params, const float *s, const uint8_t *y, int64_t n,
+                              int32_t precision, double *grad, double *loss, void *ws,
+                              size_t ws_bytes, hipStream_t stream) {
+  if (!params || !s || !y || n < 1 || n > (1 << 20) || !grad || !loss || !ws) return NENO6_BAD_ARG;
+  if (precision != NENO6_FP32 && precision != NENO6_BF16) return NENO6_BAD_LAYOUT;
+  if (ws_bytes < train_workspace_bytes((int32_t)n)) return NENO6_WORKSPACE_SMALL;
+  return hip_status(launch_grad(params, s, y, n, precision, grad, loss, ws, stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,295 @@
+// Device helpers of the NENO6 kernels (gfx950).  Internal to libneno6.
+//
+// Everything here is written for one stencil at a time in registers; the
+// kernels decide how stencils map to lanes.  The templates are instantiated
+// for double (the plain FP64 path, compiled without FP contraction so that
+// the written fma order is the one executed) and float (fast paths).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define N6_DEV __device__ __forceinline__
+
+namespace n6 {
+
+// Status codes mirrored from the public header.
+constexpr int32_t ST_NONPHYSICAL = -4;
+
+// Linear weights of TENO6-opt, also NENO6's (Sec. 2.2 / Sec. 4).
+template <typename T> struct Lin;
+template <> struct Lin<double> {
+  static constexpr double d0 = 0.4294317718960898, d1 = 0.1727270875843552,
+                          d2 = 0.0855682281039113, d3 = 0.312272912415645;
+};
+template <> struct Lin<float> {
+  static constexpr float d0 = 0.4294317718960898f, d1 = 0.1727270875843552f,
+                         d2 = 0.0855682281039113f, d3 = 0.312272912415645f;
+};
+
+template <typename T> N6_DEV T fma_(T a, T b, T c);
+template <> N6_DEV double fma_<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <> N6_DEV float fma_<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Candidate interface values at x_{i+1/2} (eq. approximatepolynomial with
+// eq. definitionEq: cell averages of the candidate polynomial reproduce the
+// stencil values).  s[0..5] = values at cells i-2..i+3.  Each sum is an fma
+// chain from zero in ascending stencil position.
+template <typename T>
+N6_DEV void candidates(const T s[6], T &q0, T &q1, T &q2, T &q3) {
+  const T z = T(0);
+  // S0 = {i-1, i, i+1}
+  q0 = fma_<T>(T(1) / T(3), s[3], fma_<T>(T(5) / T(6), s[2], fma_<T>(T(-1) / T(6), s[1], z)));
+  // S1 = {i, i+1, i+2}
+  q1 = fma_<T>(T(-1) / T(6), s[4], fma_<T>(T(5) / T(6), s[3], fma_<T>(T(1) / T(3), s[2], z)));
+  // S2 = {i-2, i-1, i}
+  q2 = fma_<T>(T(11) / T(6), s[2], fma_<T>(T(-7) / T(6), s[1], fma_<T>(T(1) / T(3), s[0], z)));
+  // S3 = {i, i+1, i+2, i+3}
+  q3 = fma_<T>(T(1) / T(12), s[5],
+               fma_<T>(T(-5) / T(12), s[4], fma_<T>(T(13) / T(12), s[3], fma_<T>(T(1) / T(4), s[2], z))));
+}
+
+// Re-normalised convex combination of the kept candidates (eq. convex,
+// eq. TENOweight_renormalize); with nothing kept, the first-order upwind
+// value s[2] (Alg. 2, step 4).  Canonical order: D summed over kept k in k
+// order, w_k = d_k / D, fma chain over kept k from zero.
+template <typename T>
+N6_DEV T combine_canonical(const T s[6], unsigned sel) {
+  T q0, q1, q2, q3;
+  candidates<T>(s, q0, q1, q2, q3);
+  if ((sel & 15u) == 0u) return s[2];
+  T D = T(0);
+  if (sel & 1u) D = D + Lin<T>::d0;
+  if (sel & 2u) D = D + Lin<T>::d1;
+  if (sel & 4u) D = D + Lin<T>::d2;
+  if (sel & 8u) D = D + Lin<T>::d3;
+  T h = T(0);
+  if (sel & 1u) h = fma_<T>(Lin<T>::d0 / D, q0, h);
+  if (sel & 2u) h = fma_<T>(Lin<T>::d1 / D, q1, h);
+  if (sel & 4u) h = fma_<T>(Lin<T>::d2 / D, q2, h);
+  if (sel & 8u) h = fma_<T>(Lin<T>::d3 / D, q3, h);
+  return h;
+}
+
+// Branch-free combine for the fast paths (same weights, FP32, one reciprocal).
+N6_DEV float combine_fast(const float s[6], unsigned sel) {
+  float q0, q1, q2, q3;
+  candidates<float>(s, q0, q1, q2, q3);
+  const float w0 = (sel & 1u) ? Lin<float>::d0 : 0.f;
+  const float w1 = (sel & 2u) ? Lin<float>::d1 : 0.f;
+  const float w2 = (sel & 4u) ? Lin<float>::d2 : 0.f;
+  const float w3 = (sel & 8u) ? Lin<float>::d3 : 0.f;
+  const float D = (w0 + w1) + (w2 + w3);
+  const float num = fmaf(w3, q3, fmaf(w2, q2, fmaf(w1, q1, w0 * q0)));
+  return (sel & 15u) ? num / D : s[2];
+}
+
+// Input scaling of the classifier (eq. normalizainput): divide by
+// max(|s_0|, ..., |s_5|, 1).
+template <typename T>
+N6_DEV void features(const T s[6], T x[6]) {
+  T M = T(1);
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const T a = s[j] < T(0) ? -s[j] : s[j];
+    M = a > M ? a : M;
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j) x[j] = s[j] / M;
+}
+
+// Parameter block offsets (row-major [out][in] weights then biases).
+constexpr int OW1 = 0, OB1 = 384, OW2 = 448, OB2 = 2496, OW3 = 2528, OB3 = 3040, OW4 = 3056,
+              OB4 = 3184, OW5 = 3192, OB5 = 3224, NPARAM = 3228;
+
+// Dense layer with the canonical fma order (bias first, inputs ascending).
+template <typename T, int NIN, int NOUT, bool RELU>
+N6_DEV void dense(const T *__restrict__ W, const T *__restrict__ b, const T *x, T *y) {
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) {
+    T acc = b[o];
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) acc = fma_<T>(W[o * NIN + i], x[i], acc);
+    y[o] = RELU ? (acc > T(0) ? acc : T(0)) : acc;
+  }
+}
+
+// The 6-64-32-16-8-4 network (eq. reconstuction, activationfunction) up to
+// the output logits.  P: parameter block in type T (uniform across lanes, so
+// the weights come in through scalar loads).
+template <typename T>
+N6_DEV void mlp_logits(const T *__restrict__ P, const T x0[6], T z[4]) {
+  T a1[64], a2[32], a3[16], a4[8];
+  dense<T, 6, 64, true>(P + OW1, P + OB1, x0, a1);
+  dense<T, 64, 32, true>(P + OW2, P + OB2, a1, a2);
+  dense<T, 32, 16, true>(P + OW3, P + OB3, a2, a3);
+  dense<T, 16, 8, true>(P + OW4, P + OB4, a3, a4);
+  dense<T, 8, 4, false>(P + OW5, P + OB5, a4, z);
+}
+
+// Kept mask: candidate k discarded iff logit > 0 (sigmoid > 1/2).
+template <typename T>
+N6_DEV unsigned mask_from_logits(const T z[4]) {
+  unsigned m = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) m |= (z[k] > T(0)) ? 0u : (1u << k);
+  return m;
+}
+
+template <typename T>
+N6_DEV unsigned classify(const T *__restrict__ P, const T s[6]) {
+  T x[6], z[4];
+  features<T>(s, x);
+  mlp_logits<T>(P, x, z);
+  return mask_from_logits<T>(z);
+}
+
+// Ghost cells: periodic wrap, or zero-gradient copy of the nearest cell.
+N6_DEV int64_t ghost(int64_t c, int64_t n, int bc) {
+  if (bc == 0) {
+    int64_t r = c % n;
+    return r < 0 ? r + n : r;
+  }
+  return c < 0 ? 0 : (c > n - 1 ? n - 1 : c);
+}
+
+// Largest p with offsets[p] + p*extra <= g (problems are non-empty).
+N6_DEV int find_problem(const int64_t *__restrict__ offsets, int np, int64_t g, int extra) {
+  int lo = 0, hi = np - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (offsets[mid] + (int64_t)mid * extra <= g)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T> N6_DEV T sqrt_(T x);
+template <> N6_DEV double sqrt_<double>(double x) { return __builtin_sqrt(x); }
+template <> N6_DEV float sqrt_<float>(float x) { return __builtin_sqrtf(x); }
+template <typename T> N6_DEV T abs_(T x) { return x < T(0) ? -x : x; }
+
+// ---- 1D Euler (Sec. 4.4), state (rho, rho u, E) ----------------------------
+template <typename T>
+N6_DEV void prim1d(const T q[3], T gamma, T &u, T &p, T &c) {
+  u = q[1] / q[0];
+  const T t = q[1] * u;
+  const T ke = T(0.5) * t;
+  p = (gamma - T(1)) * (q[2] - ke);
+  c = sqrt_<T>((gamma * p) / q[0]);
+}
+
+template <typename T>
+N6_DEV void flux1d(const T q[3], T u, T p, T F[3]) {
+  F[0] = q[1];
+  F[1] = q[1] * u + p;
+  F[2] = (q[2] + p) * u;
+}
+
+// Roe-averaged eigenvectors of the 1D flux Jacobian: columns of R (and rows
+// of L = R^-1) are the fields of speed u-c, u, u+c.
+template <typename T>
+N6_DEV void roe1d(const T qL[3], const T qR[3], T gamma, T L[3][3], T R[3][3]) {
+  T uL, pL, cL, uR, pR, cR;
+  prim1d<T>(qL, gamma, uL, pL, cL);
+  prim1d<T>(qR, gamma, uR, pR, cR);
+  const T sL = sqrt_<T>(qL[0]), sR = sqrt_<T>(qR[0]);
+  const T HL = (qL[2] + pL) / qL[0], HR = (qR[2] + pR) / qR[0];
+  const T den = sL + sR;
+  const T ut = (sL * uL + sR * uR) / den;
+  const T Ht = (sL * HL + sR * HR) / den;
+  const T q2 = T(0.5) * (ut * ut);
+  const T c2 = (gamma - T(1)) * (Ht - q2);
+  const T ct = sqrt_<T>(c2);
+  const T b1 = (gamma - T(1)) / c2;
+  const T b2 = b1 * q2;
+  const T uc = ut / ct;
+  const T ic = T(1) / ct;
+  R[0][0] = T(1);         R[0][1] = T(1); R[0][2] = T(1);
+  R[1][0] = ut - ct;      R[1][1] = ut;   R[1][2] = ut + ct;
+  R[2][0] = Ht - ut * ct; R[2][1] = q2;   R[2][2] = Ht + ut * ct;
+  L[0][0] = T(0.5) * (b2 + uc); L[0][1] = T(-0.5) * (b1 * ut + ic); L[0][2] = T(0.5) * b1;
+  L[1][0] = T(1) - b2;          L[1][1] = b1 * ut;                  L[1][2] = -b1;
+  L[2][0] = T(0.5) * (b2 - uc); L[2][1] = T(-0.5) * (b1 * ut - ic); L[2][2] = T(0.5) * b1;
+}
+
+// ---- 2D Euler, state (rho, rho u, rho v, E); dir 0 = x, 1 = y -------------
+template <typename T>
+N6_DEV void prim2d(const T q[4], T gamma, T &u, T &v, T &p, T &c) {
+  u = q[1] / q[0];
+  v = q[2] / q[0];
+  const T t1 = q[1] * u;
+  const T t2 = q[2] * v;
+  const T ke = T(0.5) * (t1 + t2);
+  p = (gamma - T(1)) * (q[3] - ke);
+  c = sqrt_<T>((gamma * p) / q[0]);
+}
+
+template <typename T>
+N6_DEV void flux2d(const T q[4], T u, T v, T p, int dir, T F[4]) {
+  if (dir == 0) {
+    F[0] = q[1];
+    F[1] = q[1] * u + p;
+    F[2] = q[2] * u;
+    F[3] = (q[3] + p) * u;
+  } else {
+    F[0] = q[2];
+    F[1] = q[1] * v;
+    F[2] = q[2] * v + p;
+    F[3] = (q[3] + p) * v;
+  }
+}
+
+// Roe eigenvectors for the sweep direction.  Fields: u_n - c, u_n, shear
+// (tangential velocity, passive), u_n + c.
+template <typename T>
+N6_DEV void roe2d(const T qL[4], const T qR[4], T gamma, int dir, T L[4][4], T R[4][4]) {
+  T uL, vL, pL, cL, uR, vR, pR, cR;
+  prim2d<T>(qL, gamma, uL, vL, pL, cL);
+  prim2d<T>(qR, gamma, uR, vR, pR, cR);
+  const T sL = sqrt_<T>(qL[0]), sR = sqrt_<T>(qR[0]);
+  const T HL = (qL[3] + pL) / qL[0], HR = (qR[3] + pR) / qR[0];
+  const T den = sL + sR;
+  const T ut = (sL * uL + sR * uR) / den;
+  const T vt = (sL * vL + sR * vR) / den;
+  const T Ht = (sL * HL + sR * HR) / den;
+  const T q2 = T(0.5) * (ut * ut + vt * vt);
+  const T c2 = (gamma - T(1)) * (Ht - q2);
+  const T ct = sqrt_<T>(c2);
+  const T b1 = (gamma - T(1)) / c2;
+  const T b2 = b1 * q2;
+  const T ic = T(1) / ct;
+  const T un = dir == 0 ? ut : vt;
+  const T us = dir == 0 ? vt : ut;
+  const T nc = un / ct;
+  // rows/cols in the variable order (rho, rho u_n, rho u_s, E)
+  const T Rn[4][4] = {{T(1), T(1), T(0), T(1)},
+                      {un - ct, un, T(0), un + ct},
+                      {us, us, T(1), us},
+                      {Ht - un * ct, q2, us, Ht + un * ct}};
+  const T Ln[4][4] = {{T(0.5) * (b2 + nc), T(-0.5) * (b1 * un + ic), T(-0.5) * (b1 * us), T(0.5) * b1},
+                      {T(1) - b2, b1 * un, b1 * us, -b1},
+                      {-us, T(0), T(1), T(0)},
+                      {T(0.5) * (b2 - nc), T(-0.5) * (b1 * un - ic), T(-0.5) * (b1 * us), T(0.5) * b1}};
+  const int vn = dir == 0 ? 1 : 2, vs = dir == 0 ? 2 : 1;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    R[0][m] = Rn[0][m];
+    R[vn][m] = Rn[1][m];
+    R[vs][m] = Rn[2][m];
+    R[3][m] = Rn[3][m];
+    L[m][0] = Ln[m][0];
+    L[m][vn] = Ln[m][1];
+    L[m][vs] = Ln[m][2];
+    L[m][3] = Ln[m][3];
+  }
+}
+
+template <typename T>
+N6_DEV bool physical(T rho, T p) {
+  return rho > T(0) && p > T(0) && __builtin_isfinite(rho) && __builtin_isfinite(p);
+}
+
+}  // namespace n6

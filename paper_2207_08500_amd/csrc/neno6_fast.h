@@ -1,0 +1,59 @@
+// Internal interface of the reduced-precision (BF16 / FP16 MFMA) path and of
+// the classifier trainer.  Host-side declarations only.
+#pragma once
+
+#include "neno6_internal.h"
+
+namespace n6 {
+
+// Scratch of the fast path, carved from the caller's workspace.
+struct FastScratch {
+  uint8_t *masks;       // [nvar][faces] (1D) or x|y masks (2D), when the caller passes none
+  uint32_t *queue;      // re-check entries: face * 8 + (field * 2 + sign)
+  uint8_t *qflag;       // per entry: label changed by the FP32 re-check
+  uint32_t *qcount;     // [1] entries in the queue (cleared by a kernel each call)
+  int64_t qcap;         // queue capacity
+};
+
+struct FastArgs {
+  int equation = 0, precision = 2, selector = 0;
+  const void *prepared = nullptr;
+  float margin = 0.f;
+  FastScratch scr{};
+};
+
+size_t fast_prepared_bytes();
+const void *fast_prepared_f32(const void *prepared);
+hipError_t launch_fast_prepare(const double *P, void *prepared, hipStream_t s);
+
+hipError_t launch_fast_logits(const void *prepared, int precision, float margin, const float *sten,
+                              int64_t n, float *z, uint8_t *masks, hipStream_t s);
+hipError_t launch_fast_reconstruct(const void *prepared, int precision, float margin,
+                                   const float *f, int64_t n_faces, int sign, int selector,
+                                   const uint8_t *masks_in, float *fhat, uint8_t *masks_out,
+                                   hipStream_t s);
+// Face fluxes with the MFMA classifier (+ re-check when the margin is > 0).
+hipError_t launch_fast_faces1d(const Line1D &ln, const FastArgs &fa, const float *q,
+                               const uint8_t *masks_in, uint8_t *masks_out, float *F,
+                               hipStream_t s);
+hipError_t launch_fast_faces2d(const Grid2D &g, const FastArgs &fa, const float *q,
+                               const uint8_t *masks_in, uint8_t *masks_out, float *Fx, float *Gy,
+                               hipStream_t s);
+// Face fluxes with the MFMA classifier + re-check + flux difference/stage.
+hipError_t launch_fast_rhs1d(const Line1D &ln, const FastArgs &fa, const float *q, float *rhs,
+                             const uint8_t *masks_in, uint8_t *masks_out, int32_t *status,
+                             float *F, const Stage *st, hipStream_t s);
+hipError_t launch_fast_rhs2d(const Grid2D &g, const FastArgs &fa, const float *q, float *rhs,
+                             const uint8_t *masks_in, uint8_t *masks_out, int32_t *status,
+                             float *Fx, float *Gy, const Stage *st, hipStream_t s);
+
+// ---- training ----------------------------------------------------------------
+size_t train_workspace_bytes(int32_t batch);
+hipError_t launch_train_batch(double *P, double *m, double *v, int64_t step, const float *s,
+                              const uint8_t *y, const int64_t *idx, int64_t mb, double lr,
+                              double b1, double b2, double eps, int precision, double *loss_out,
+                              double loss_scale, bool first, void *ws, hipStream_t st);
+hipError_t launch_grad(const double *P, const float *s, const uint8_t *y, int64_t n,
+                       int precision, double *grad, double *loss, void *ws, hipStream_t st);
+
+}  // namespace n6

@@ -1,0 +1,841 @@
+// Reduced-precision NENO6 path for gfx950: FP32 state and reconstruction,
+// classifier layers on MFMA in BF16 or FP16 with FP32 accumulation.
+//
+// Classifier mapping (weight-stationary, activations never leave the lanes):
+// every layer is computed transposed, Y^T[out][evals] = W[out][in] X^T[in][evals],
+// with the weights as the MFMA A operand (loaded once per wave into registers
+// in a lane order prepared by k_prepare) and 32 evaluations as the B operand
+// columns.  The 32x32 accumulator layout leaves lane (j, h) = (l % 32, l / 32)
+// holding rows {8b + 4h + r : b, r = 0..3} of column j; the next layer reads
+// its K slots from exactly those registers, so the K order of each weight
+// matrix is permuted at preparation time instead of moving activations.
+//   L1 6(+1 bias slot) -> 64 : 2 x v_mfma_f32_32x32x8   (K = 8)
+//   L2 64 -> 32               : 4 x v_mfma_f32_32x32x16  (bias in the C input)
+//   L3 32 -> 16 (pad 32)      : 2 x v_mfma_f32_32x32x16
+//   L4 16 -> 8  (pad 32)      : 1 x v_mfma_f32_32x32x16
+//   L5 8 -> 4   (pad 32)      : 1 x v_mfma_f32_32x32x16, bias added in FP32
+// ReLU is applied to the packed 16-bit values with v_pk_max_i16 (a negative
+// BF16/FP16 has its sign bit set, i.e. is a negative int16).
+//
+// One lane computes one face (projection, split, features, combine); the two
+// 32-column tiles of a wave are exchanged between lane halves with
+// v_permlane32_swap.  Evaluations whose smallest |logit| is below the
+// re-check margin are queued and re-evaluated in FP32 by a second kernel; a
+// third kernel recomputes the fluxes of faces whose label changed.
+#include "neno6_device.h"
+#include "neno6_fast.h"
+
+namespace n6 {
+
+namespace {
+
+typedef uint32_t u32;
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef u32 u32x2 __attribute__((ext_vector_type(2)));
+typedef u32 u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int TPB = 256;
+constexpr int WPB = TPB / 64;
+constexpr int TAB_REGS = 84;
+constexpr int TAB_BYTES = TAB_REGS * 64 * 4;
+constexpr int PREP_BF16_OFF = 16384;
+constexpr int PREP_F16_OFF = PREP_BF16_OFF + TAB_BYTES;
+constexpr int PREP_B5_OFF = PREP_F16_OFF + TAB_BYTES;
+constexpr size_t PREP_BYTES = 65536;
+static_assert(PREP_B5_OFF + 16 <= (int)PREP_BYTES, "prepared block layout");
+
+// ---- packing -----------------------------------------------------------------
+template <int PREC> N6_DEV u32 pack2(float a, float b);
+template <> N6_DEV u32 pack2<2>(float a, float b) {
+  const f32x2 v = {a, b};
+  return __builtin_bit_cast(u32, __builtin_convertvector(v, bf16x2));
+}
+template <> N6_DEV u32 pack2<3>(float a, float b) {
+  const f32x2 v = {a, b};
+  return __builtin_bit_cast(u32, __builtin_convertvector(v, f16x2));
+}
+N6_DEV u32 relu2(u32 x) {
+  const s16x2 z = {0, 0};
+  return __builtin_bit_cast(u32, __builtin_elementwise_max(__builtin_bit_cast(s16x2, x), z));
+}
+template <int PREC> N6_DEV u32 relu_pack(float a, float b) { return relu2(pack2<PREC>(a, b)); }
+
+template <int PREC> N6_DEV f32x16 mma8(u32x2 a, u32x2 b, f32x16 c);
+template <> N6_DEV f32x16 mma8<2>(u32x2 a, u32x2 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(__builtin_bit_cast(s16x4, a),
+                                                  __builtin_bit_cast(s16x4, b), c, 0, 0, 0);
+}
+template <> N6_DEV f32x16 mma8<3>(u32x2 a, u32x2 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x8f16(__builtin_bit_cast(f16x4, a),
+                                              __builtin_bit_cast(f16x4, b), c, 0, 0, 0);
+}
+template <int PREC> N6_DEV f32x16 mma16(u32x4 a, u32x4 b, f32x16 c);
+template <> N6_DEV f32x16 mma16<2>(u32x4 a, u32x4 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+template <> N6_DEV f32x16 mma16<3>(u32x4 a, u32x4 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
+                                                __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+}
+
+// Swap lanes 32..63 of x with lanes 0..31 of y.
+N6_DEV void swap32(u32 &x, u32 &y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+  x = r[0];
+  y = r[1];
+}
+
+// ---- classifier registers ------------------------------------------------------
+struct Wts {
+  u32x2 a1[2];
+  u32x4 a2[4], a3[2], a4, a5;
+  f32x16 b2, b3, b4;
+  float b5[4];
+};
+
+template <int PREC>
+N6_DEV void load_wts(const void *prepared, int lane, Wts &w) {
+  const u32 *t = (const u32 *)((const char *)prepared + (PREC == 2 ? PREP_BF16_OFF : PREP_F16_OFF));
+#define N6R(r) t[(r)*64 + lane]
+  w.a1[0] = u32x2{N6R(0), N6R(1)};
+  w.a1[1] = u32x2{N6R(2), N6R(3)};
+#pragma unroll
+  for (int s = 0; s < 4; ++s) w.a2[s] = u32x4{N6R(4 + 4 * s), N6R(5 + 4 * s), N6R(6 + 4 * s), N6R(7 + 4 * s)};
+#pragma unroll
+  for (int s = 0; s < 2; ++s) w.a3[s] = u32x4{N6R(20 + 4 * s), N6R(21 + 4 * s), N6R(22 + 4 * s), N6R(23 + 4 * s)};
+  w.a4 = u32x4{N6R(28), N6R(29), N6R(30), N6R(31)};
+  w.a5 = u32x4{N6R(32), N6R(33), N6R(34), N6R(35)};
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    w.b2[r] = __builtin_bit_cast(float, N6R(36 + r));
+    w.b3[r] = __builtin_bit_cast(float, N6R(52 + r));
+    w.b4[r] = __builtin_bit_cast(float, N6R(68 + r));
+  }
+#undef N6R
+  const float *b5 = (const float *)((const char *)prepared + PREP_B5_OFF);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w.b5[k] = b5[k];
+}
+
+// One 32-evaluation tile through the network; `bin` is the L1 B operand
+// (features 4h..4h+3 of column j, with the constant 1 of the folded L1 bias
+// in slot 6).  Returns L5 without its bias: rows 0..3 (logits) sit in
+// registers 0..3 of lanes 0..31.
+template <int PREC>
+N6_DEV f32x16 mlp_tile(const Wts &w, u32x2 bin) {
+  const f32x16 zero = {};
+  const f32x16 c1a = mma8<PREC>(w.a1[0], bin, zero);
+  const f32x16 c1b = mma8<PREC>(w.a1[1], bin, zero);
+  u32x4 h1a0, h1a1, h1b0, h1b1;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    h1a0[p] = relu_pack<PREC>(c1a[2 * p], c1a[2 * p + 1]);
+    h1a1[p] = relu_pack<PREC>(c1a[8 + 2 * p], c1a[9 + 2 * p]);
+    h1b0[p] = relu_pack<PREC>(c1b[2 * p], c1b[2 * p + 1]);
+    h1b1[p] = relu_pack<PREC>(c1b[8 + 2 * p], c1b[9 + 2 * p]);
+  }
+  f32x16 c2 = mma16<PREC>(w.a2[0], h1a0, w.b2);
+  c2 = mma16<PREC>(w.a2[1], h1a1, c2);
+  c2 = mma16<PREC>(w.a2[2], h1b0, c2);
+  c2 = mma16<PREC>(w.a2[3], h1b1, c2);
+  u32x4 h20, h21;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    h20[p] = relu_pack<PREC>(c2[2 * p], c2[2 * p + 1]);
+    h21[p] = relu_pack<PREC>(c2[8 + 2 * p], c2[9 + 2 * p]);
+  }
+  f32x16 c3 = mma16<PREC>(w.a3[0], h20, w.b3);
+  c3 = mma16<PREC>(w.a3[1], h21, c3);
+  u32x4 h3;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) h3[p] = relu_pack<PREC>(c3[2 * p], c3[2 * p + 1]);
+  const f32x16 c4 = mma16<PREC>(w.a4, h3, w.b4);
+  u32x4 h4;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) h4[p] = relu_pack<PREC>(c4[2 * p], c4[2 * p + 1]);
+  return mma16<PREC>(w.a5, h4, zero);
+}
+
+// L1 B operand halves of one stencil: X = features 0..3, Y = features 4, 5,
+// the bias slot 1 and a zero.
+template <int PREC>
+N6_DEV void feature_pack(const float s[6], u32 &x0, u32 &x1, u32 &y0) {
+  float M = 1.f;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) M = fmaxf(M, fabsf(s[j]));
+  const float r = __builtin_amdgcn_rcpf(M);
+  x0 = pack2<PREC>(s[0] * r, s[1] * r);
+  x1 = pack2<PREC>(s[2] * r, s[3] * r);
+  y0 = pack2<PREC>(s[4] * r, s[5] * r);
+}
+template <int PREC> N6_DEV u32 one_zero() { return pack2<PREC>(1.f, 0.f); }
+
+// Kept mask (bits 0..3) and near-cutoff flag (bit 4) from four logits.
+N6_DEV u32 mask_near(const float z[4], float margin) {
+  u32 m = 0;
+  float amin = fabsf(z[0]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    m |= z[k] > 0.f ? 0u : (1u << k);
+    amin = fminf(amin, fabsf(z[k]));
+  }
+  return m | (amin < margin ? 16u : 0u);
+}
+
+// Classifies the stencil held by every lane of the wave (all 64 lanes must
+// call it together).  Returns the lane's mask | near-flag << 4; with z != 0
+// also returns the lane's four logits.
+template <int PREC>
+N6_DEV u32 classify_wave(const Wts &w, const float s[6], float margin, float *z_out) {
+  u32 x0, x1, y0;
+  feature_pack<PREC>(s, x0, x1, y0);
+  u32 y1 = one_zero<PREC>();
+  swap32(x0, y0);  // x0: tile 0 (faces of lanes 0..31), y0: tile 1
+  swap32(x1, y1);
+  const f32x16 c0 = mlp_tile<PREC>(w, u32x2{x0, x1});
+  const f32x16 c1 = mlp_tile<PREC>(w, u32x2{y0, y1});
+  float z0[4], z1[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    z0[k] = c0[k] + w.b5[k];
+    z1[k] = c1[k] + w.b5[k];
+  }
+  u32 m0 = mask_near(z0, margin), m1 = mask_near(z1, margin);
+  swap32(m0, m1);  // lane l now holds its own stencil's result in m0
+  if (z_out) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      u32 a = __builtin_bit_cast(u32, z0[k]), b = __builtin_bit_cast(u32, z1[k]);
+      swap32(a, b);
+      z_out[k] = __builtin_bit_cast(float, a);
+    }
+  }
+  return m0;
+}
+
+N6_DEV const float *uniform_f32(const void *prepared) {
+  const uint64_t v = (uint64_t)prepared;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (const float *)(((uint64_t)hi << 32) | lo);
+}
+
+// FP32 re-evaluation on the vector units (the re-check).
+N6_DEV unsigned classify_f32(const void *prepared, const float s[6]) {
+  return classify<float>(uniform_f32(prepared), s);
+}
+
+// ---- per-face setup, FP32 -----------------------------------------------------
+// 1D Euler face g of the batch: split stencils s[2m + sign][6] ('-' mirrored)
+// and the right eigenvectors R.
+N6_DEV void setup1d(const Line1D &ln, const float *__restrict__ q, int64_t g, float s[6][6],
+                    float R[3][3]) {
+  const int p = find_problem(ln.offsets, ln.np, g, 1);
+  const int64_t o = ln.offsets[p], n = ln.offsets[p + 1] - o, k = g - o - p;
+  const float gm = (float)ln.gamma, g1 = gm - 1.f;
+  float qs[6][3], lam[6][3], F[6][3];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const int64_t ci = o + ghost(k - 3 + j, n, ln.bc);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) qs[j][r] = q[r * ln.total + ci];
+  }
+  float uu[6], pp[6], ir[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    ir[j] = __builtin_amdgcn_rcpf(qs[j][0]);
+    uu[j] = qs[j][1] * ir[j];
+    pp[j] = g1 * (qs[j][2] - 0.5f * qs[j][1] * uu[j]);
+    const float c = __builtin_amdgcn_sqrtf(gm * pp[j] * ir[j]);
+    lam[j][0] = uu[j] - c;
+    lam[j][1] = uu[j];
+    lam[j][2] = uu[j] + c;
+    F[j][0] = qs[j][1];
+    F[j][1] = qs[j][1] * uu[j] + pp[j];
+    F[j][2] = (qs[j][2] + pp[j]) * uu[j];
+  }
+  // Roe average of cells i (j = 2) and i+1 (j = 3)
+  const float sL = __builtin_amdgcn_sqrtf(qs[2][0]), sR = __builtin_amdgcn_sqrtf(qs[3][0]);
+  const float id = __builtin_amdgcn_rcpf(sL + sR);
+  const float ut = (sL * uu[2] + sR * uu[3]) * id;
+  const float HL = (qs[2][2] + pp[2]) * ir[2], HR = (qs[3][2] + pp[3]) * ir[3];
+  const float Ht = (sL * HL + sR * HR) * id;
+  const float q2 = 0.5f * ut * ut;
+  const float c2 = g1 * (Ht - q2);
+  const float ct = __builtin_amdgcn_sqrtf(c2);
+  const float ic = __builtin_amdgcn_rcpf(ct);
+  const float b1 = g1 * ic * ic;
+  const float b2 = b1 * q2;
+  const float uc = ut * ic;
+  R[0][0] = 1.f;          R[0][1] = 1.f; R[0][2] = 1.f;
+  R[1][0] = ut - ct;      R[1][1] = ut;  R[1][2] = ut + ct;
+  R[2][0] = Ht - ut * ct; R[2][1] = q2;  R[2][2] = Ht + ut * ct;
+  const float L[3][3] = {{0.5f * (b2 + uc), -0.5f * (b1 * ut + ic), 0.5f * b1},
+                         {1.f - b2, b1 * ut, -b1},
+                         {0.5f * (b2 - uc), -0.5f * (b1 * ut - ic), 0.5f * b1}};
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    float alpha = 0.f;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) alpha = fmaxf(alpha, fabsf(lam[j][m]));
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const float v = L[m][0] * qs[j][0] + L[m][1] * qs[j][1] + L[m][2] * qs[j][2];
+      const float gg = L[m][0] * F[j][0] + L[m][1] * F[j][1] + L[m][2] * F[j][2];
+      s[2 * m][j] = 0.5f * (gg + alpha * v);
+      s[2 * m + 1][5 - j] = 0.5f * (gg - alpha * v);
+    }
+  }
+}
+
+// 2D Euler face f of sweep dir: s[2m + sign][6], R.
+N6_DEV void setup2d(const Grid2D &gd, int dir, const float *__restrict__ q, int64_t f,
+                    float s[8][6], float R[4][4]) {
+  const int64_t cells = gd.nx * gd.ny;
+  const float gm = (float)gd.gamma, g1 = gm - 1.f;
+  float qs[6][4];
+  if (dir == 0) {
+    const int64_t y = f / (gd.nx + 1), k = f - y * (gd.nx + 1);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int64_t ci = y * gd.nx + ghost(k - 3 + j, gd.nx, gd.bc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) qs[j][r] = q[r * cells + ci];
+    }
+  } else {
+    const int64_t k = f / gd.nx, x = f - k * gd.nx;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int64_t ci = ghost(k - 3 + j, gd.ny, gd.bc) * gd.nx + x;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) qs[j][r] = q[r * cells + ci];
+    }
+  }
+  const int vn = dir == 0 ? 1 : 2, vs = dir == 0 ? 2 : 1;
+  float un[6], us[6], pp[6], ir[6], lamc[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    ir[j] = __builtin_amdgcn_rcpf(qs[j][0]);
+    un[j] = qs[j][vn] * ir[j];
+    us[j] = qs[j][vs] * ir[j];
+    pp[j] = g1 * (qs[j][3] - 0.5f * (qs[j][vn] * un[j] + qs[j][vs] * us[j]));
+    lamc[j] = __builtin_amdgcn_sqrtf(gm * pp[j] * ir[j]);
+  }
+  const float sL = __builtin_amdgcn_sqrtf(qs[2][0]), sR = __builtin_amdgcn_sqrtf(qs[3][0]);
+  const float id = __builtin_amdgcn_rcpf(sL + sR);
+  const float nt = (sL * un[2] + sR * un[3]) * id;
+  const float st = (sL * us[2] + sR * us[3]) * id;
+  const float HL = (qs[2][3] + pp[2]) * ir[2], HR = (qs[3][3] + pp[3]) * ir[3];
+  const float Ht = (sL * HL + sR * HR) * id;
+  const float q2 = 0.5f * (nt * nt + st * st);
+  const float c2 = g1 * (Ht - q2);
+  const float ct = __builtin_amdgcn_sqrtf(c2);
+  const float ic = __builtin_amdgcn_rcpf(ct);
+  const float b1 = g1 * ic * ic;
+  const float b2 = b1 * q2;
+  const float nc = nt * ic;
+  // (rho, rho u_n, rho u_s, E) ordering, permuted into (rho, rho u, rho v, E)
+  const float Rn[4][4] = {{1.f, 1.f, 0.f, 1.f},
+                          {nt - ct, nt, 0.f, nt + ct},
+                          {st, st, 1.f, st},
+                          {Ht - nt * ct, q2, st, Ht + nt * ct}};
+  const float Ln[4][4] = {{0.5f * (b2 + nc), -0.5f * (b1 * nt + ic), -0.5f * b1 * st, 0.5f * b1},
+                          {1.f - b2, b1 * nt, b1 * st, -b1},
+                          {-st, 0.f, 1.f, 0.f},
+                          {0.5f * (b2 - nc), -0.5f * (b1 * nt - ic), -0.5f * b1 * st, 0.5f * b1}};
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    R[0][m] = Rn[0][m];
+    R[vn][m] = Rn[1][m];
+    R[vs][m] = Rn[2][m];
+    R[3][m] = Rn[3][m];
+  }
+  // normal-direction fluxes of the six cells in the (rho, n, s, E) ordering
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    float alpha = 0.f;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const float lm = m == 0 ? un[j] - lamc[j] : (m == 3 ? un[j] + lamc[j] : un[j]);
+      alpha = fmaxf(alpha, fabsf(lm));
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const float Fn0 = qs[j][vn];
+      const float Fn1 = qs[j][vn] * un[j] + pp[j];
+      const float Fn2 = qs[j][vs] * un[j];
+      const float Fn3 = (qs[j][3] + pp[j]) * un[j];
+      const float v = Ln[m][0] * qs[j][0] + Ln[m][1] * qs[j][vn] + Ln[m][2] * qs[j][vs] +
+                      Ln[m][3] * qs[j][3];
+      const float gg = Ln[m][0] * Fn0 + Ln[m][1] * Fn1 + Ln[m][2] * Fn2 + Ln[m][3] * Fn3;
+      s[2 * m][j] = 0.5f * (gg + alpha * v);
+      s[2 * m + 1][5 - j] = 0.5f * (gg - alpha * v);
+    }
+  }
+}
+
+template <int NV>
+N6_DEV void back_project(const float R[NV][NV], const float hs[NV], float Fo[NV]) {
+#pragma unroll
+  for (int r = 0; r < NV; ++r) {
+    float acc = 0.f;
+#pragma unroll
+    for (int m = 0; m < NV; ++m) acc = fmaf(R[r][m], hs[m], acc);
+    Fo[r] = acc;
+  }
+}
+
+// Wave-aggregated append of (face, eval) entries to the re-check queue.
+N6_DEV void enqueue(bool want, u32 entry, u32 *__restrict__ queue, u32 *__restrict__ qcount,
+                    int64_t qcap) {
+  const uint64_t bal = __ballot(want);
+  if (bal == 0) return;
+  const int lane = threadIdx.x & 63;
+  const u32 cnt = (u32)__popcll(bal);
+  u32 base = 0;
+  if (lane == __ffsll((unsigned long long)bal) - 1) base = atomicAdd(qcount, cnt);
+  base = __shfl(base, __ffsll((unsigned long long)bal) - 1);
+  const u32 off = (u32)__popcll(bal & ((1ull << lane) - 1));
+  if (want && (int64_t)(base + off) < qcap) queue[base + off] = entry;
+}
+
+// ---- fused face kernels ---------------------------------------------------------
+template <int PREC>
+__global__ void __launch_bounds__(TPB)
+k_fast_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float margin,
+               const float *__restrict__ q, const uint8_t *__restrict__ min,
+               float *__restrict__ Fh, uint8_t *__restrict__ masks, u32 *__restrict__ queue,
+               u32 *__restrict__ qcount, int64_t qcap) {
+  const int lane = threadIdx.x & 63;
+  const int64_t tf = ln.faces();
+  const int64_t nchunk = (tf + 63) / 64;
+  Wts w;
+  if (selector == 0) load_wts<PREC>(prepared, lane, w);
+  for (int64_t ch = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6); ch < nchunk;
+       ch += (int64_t)gridDim.x * WPB) {
+    const int64_t g = ch * 64 + lane;
+    const bool valid = g < tf;
+    const int64_t gc = valid ? g : tf - 1;
+    float s[6][6], R[3][3];
+    setup1d(ln, q, gc, s, R);
+    u32 sel[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      if (selector == 0) {
+        const u32 mk = classify_wave<PREC>(w, s[e], margin, nullptr);
+        sel[e] = mk & 15u;
+        enqueue(valid && (mk & 16u), (u32)(gc * 8 + e), queue, qcount, qcap);
+      } else if (selector == 1) {
+        sel[e] = 15u;
+      } else if (selector == 2) {
+        sel[e] = 0u;
+      } else {
+        sel[e] = (min[(e >> 1) * tf + gc] >> ((e & 1) * 4)) & 15u;
+      }
+    }
+    float hs[3], Fo[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+      hs[m] = combine_fast(s[2 * m], sel[2 * m]) + combine_fast(s[2 * m + 1], sel[2 * m + 1]);
+    back_project<3>(R, hs, Fo);
+    if (valid) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) Fh[r * tf + g] = Fo[r];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) masks[m * tf + g] = (uint8_t)(sel[2 * m] | (sel[2 * m + 1] << 4));
+    }
+  }
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(TPB)
+k_fast_euler2d(Grid2D gd, int dir, int selector, const void *__restrict__ prepared, float margin,
+               const float *__restrict__ q, const uint8_t *__restrict__ min,
+               float *__restrict__ Fh, uint8_t *__restrict__ masks, u32 *__restrict__ queue,
+               u32 *__restrict__ qcount, int64_t qcap) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nf = dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1);
+  const int64_t nchunk = (nf + 63) / 64;
+  Wts w;
+  if (selector == 0) load_wts<PREC>(prepared, lane, w);
+  for (int64_t ch = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6); ch < nchunk;
+       ch += (int64_t)gridDim.x * WPB) {
+    const int64_t f = ch * 64 + lane;
+    const bool valid = f < nf;
+    const int64_t fc = valid ? f : nf - 1;
+    float s[8][6], R[4][4];
+    setup2d(gd, dir, q, fc, s, R);
+    u32 sel[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      if (selector == 0) {
+        const u32 mk = classify_wave<PREC>(w, s[e], margin, nullptr);
+        sel[e] = mk & 15u;
+        enqueue(valid && (mk & 16u), (u32)(fc * 8 + e), queue, qcount, qcap);
+      } else if (selector == 1) {
+        sel[e] = 15u;
+      } else if (selector == 2) {
+        sel[e] = 0u;
+      } else {
+        sel[e] = (min[(e >> 1) * nf + fc] >> ((e & 1) * 4)) & 15u;
+      }
+    }
+    float hs[4], Fo[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      hs[m] = combine_fast(s[2 * m], sel[2 * m]) + combine_fast(s[2 * m + 1], sel[2 * m + 1]);
+    back_project<4>(R, hs, Fo);
+    if (valid) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Fh[r * nf + f] = Fo[r];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) masks[m * nf + f] = (uint8_t)(sel[2 * m] | (sel[2 * m + 1] << 4));
+    }
+  }
+}
+
+// FP32 re-check of queued evaluations; flips the stored nibble where the
+// FP32 label differs and flags the entry.
+template <int DIM>
+__global__ void __launch_bounds__(TPB)
+k_recheck(Line1D ln, Grid2D gd, int dir, const void *__restrict__ prepared,
+          const float *__restrict__ q, uint8_t *__restrict__ masks, const u32 *__restrict__ queue,
+          const u32 *__restrict__ qcount, int64_t qcap, uint8_t *__restrict__ qflag) {
+  const int64_t nq = (int64_t)*qcount < qcap ? (int64_t)*qcount : qcap;
+  const int64_t nf = DIM == 1 ? ln.faces() : (dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1));
+  for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < nq; i += (int64_t)gridDim.x * TPB) {
+    const u32 ent = queue[i];
+    const int64_t f = ent >> 3;
+    const int e = ent & 7;
+    float s[8][6], R[4][4];
+    if (DIM == 1) {
+      float R3[3][3];
+      setup1d(ln, q, f, *(float(*)[6][6])s, R3);
+    } else {
+      setup2d(gd, dir, q, f, s, R);
+    }
+    const u32 sel32 = classify_f32(prepared, s[e]);
+    const int64_t mi = (int64_t)(e >> 1) * nf + f;
+    const u32 shift = (u32)((mi & 3) * 8 + (e & 1) * 4);
+    u32 *word = (u32 *)(masks + (mi & ~(int64_t)3));
+    const u32 old = (masks[mi] >> ((e & 1) * 4)) & 15u;
+    const bool flip = old != sel32;
+    if (flip) atomicXor(word, (old ^ sel32) << shift);
+    qflag[i] = flip ? 1 : 0;
+  }
+}
+
+// Recomputes the flux of every face whose label the re-check changed.
+template <int DIM>
+__global__ void __launch_bounds__(TPB)
+k_fixup(Line1D ln, Grid2D gd, int dir, const float *__restrict__ q,
+        const uint8_t *__restrict__ masks, const u32 *__restrict__ queue,
+        const u32 *__restrict__ qcount, int64_t qcap, const uint8_t *__restrict__ qflag,
+        float *__restrict__ Fh) {
+  const int64_t nq = (int64_t)*qcount < qcap ? (int64_t)*qcount : qcap;
+  constexpr int NV = DIM == 1 ? 3 : 4;
+  const int64_t nf = DIM == 1 ? ln.faces() : (dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1));
+  for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < nq; i += (int64_t)gridDim.x * TPB) {
+    if (!qflag[i]) continue;
+    const int64_t f = queue[i] >> 3;
+    float s[8][6], R[4][4], hs[4], Fo[4];
+    if (DIM == 1) {
+      float R3[3][3];
+      setup1d(ln, q, f, *(float(*)[6][6])s, R3);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) R[a][b] = R3[a][b];
+    } else {
+      setup2d(gd, dir, q, f, s, R);
+    }
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      const u32 mb = masks[(int64_t)m * nf + f];
+      hs[m] = combine_fast(s[2 * m], mb & 15u) + combine_fast(s[2 * m + 1], mb >> 4);
+    }
+#pragma unroll
+    for (int r = 0; r < NV; ++r) {
+      float acc = 0.f;
+#pragma unroll
+      for (int m = 0; m < NV; ++m) acc = fmaf(R[r][m], hs[m], acc);
+      Fo[r] = acc;
+    }
+#pragma unroll
+    for (int r = 0; r < NV; ++r) Fh[(int64_t)r * nf + f] = Fo[r];
+  }
+}
+
+// Scalar stencils (reconstruction, advection, classifier on its own): one
+// lane per stencil, re-check done in place (these are the small cases).
+// mode 0: stencils from f[k..k+5] (sign) ; mode 1: advection lines (ghosts);
+// mode 2: raw stencils sten[n][6] -> logits.
+template <int PREC>
+__global__ void __launch_bounds__(TPB)
+k_fast_scalar(int mode, Line1D ln, const void *__restrict__ prepared, float margin,
+              const float *__restrict__ src, int64_t n, int sign, int selector,
+              const uint8_t *__restrict__ min, float *__restrict__ out, uint8_t *__restrict__ mout,
+              float *__restrict__ zout) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nchunk = (n + 63) / 64;
+  Wts w;
+  if (selector == 0) load_wts<PREC>(prepared, lane, w);
+  for (int64_t ch = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6); ch < nchunk;
+       ch += (int64_t)gridDim.x * WPB) {
+    const int64_t k = ch * 64 + lane;
+    const bool valid = k < n;
+    const int64_t kc = valid ? k : n - 1;
+    float s[6];
+    if (mode == 0) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) s[j] = sign > 0 ? src[kc + j] : src[kc + 5 - j];
+    } else if (mode == 1) {
+      const int p = find_problem(ln.offsets, ln.np, kc, 1);
+      const int64_t o = ln.offsets[p], nn = ln.offsets[p + 1] - o, kk = kc - o - p;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) s[j] = src[o + ghost(kk - 3 + j, nn, ln.bc)];
+    } else {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) s[j] = src[6 * kc + j];
+    }
+    u32 sel;
+    float z[4];
+    if (selector == 0) {
+      const u32 mk = classify_wave<PREC>(w, s, margin, mode == 2 ? z : nullptr);
+      sel = mk & 15u;
+      if (valid && (mk & 16u)) sel = classify_f32(prepared, s);
+    } else if (selector == 1) {
+      sel = 15u;
+    } else if (selector == 2) {
+      sel = 0u;
+    } else {
+      sel = min[kc] & 15u;
+    }
+    if (!valid) continue;
+    if (mode == 2) {
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) zout[4 * k + kk] = z[kk];
+    } else {
+      out[k] = combine_fast(s, sel);
+    }
+    if (mout) mout[k] = (uint8_t)sel;
+  }
+}
+
+__global__ void k_zero_u32(u32 *p) { *p = 0u; }
+
+__global__ void __launch_bounds__(TPB) k_copy_u8(const uint8_t *__restrict__ a, uint8_t *__restrict__ b, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) b[i] = a[i];
+}
+
+hipError_t copy_bytes(const uint8_t *a, uint8_t *b, int64_t n, hipStream_t s) {
+  const int64_t blocks = (n + TPB - 1) / TPB;
+  hipLaunchKernelGGL(k_copy_u8, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(TPB), 0, s, a, b, n);
+  return hipGetLastError();
+}
+
+// Prepared block: FP32 copy of the parameters, the BF16 and FP16 per-lane
+// operand tables, and b5 in FP32.
+__global__ void __launch_bounds__(TPB) k_prepare(const double *__restrict__ P, char *__restrict__ prep) {
+  const int t = blockIdx.x * TPB + threadIdx.x;
+  if (t < NPARAM) ((float *)prep)[t] = (float)P[t];
+  if (t < 4) ((float *)(prep + PREP_B5_OFF))[t] = (float)P[OB5 + t];
+  if (t >= TAB_REGS * 64) return;
+  const int reg = t / 64, lane = t % 64, i = lane % 32, h = lane / 32;
+  float v[2];
+  bool is_bias = false;
+  for (int q2 = 0; q2 < 2; ++q2) {
+    double x = 0.0;
+    if (reg < 4) {  // L1: tile reg/2, elements e = 2*(reg%2) + q2, K slot 4h + e
+      const int tt = reg / 2, e = 2 * (reg % 2) + q2, kk = 4 * h + e, o = 32 * tt + i;
+      x = kk < 6 ? P[OW1 + o * 6 + kk] : (kk == 6 ? P[OB1 + o] : 0.0);
+    } else if (reg < 20) {  // L2 step s
+      const int s = (reg - 4) / 4, e = 2 * ((reg - 4) % 4) + q2;
+      const int n1 = 32 * (s / 2) + 16 * (s % 2) + 8 * (e / 4) + 4 * h + e % 4;
+      x = P[OW2 + i * 64 + n1];
+    } else if (reg < 28) {  // L3 step s
+      const int s = (reg - 20) / 4, e = 2 * ((reg - 20) % 4) + q2;
+      const int n2 = 8 * (2 * s + e / 4) + 4 * h + e % 4;
+      x = i < 16 ? P[OW3 + i * 32 + n2] : 0.0;
+    } else if (reg < 32) {  // L4
+      const int e = 2 * (reg - 28) + q2;
+      const int n3 = 8 * (e / 4) + 4 * h + e % 4;
+      x = i < 8 ? P[OW4 + i * 16 + n3] : 0.0;
+    } else if (reg < 36) {  // L5
+      const int e = 2 * (reg - 32) + q2;
+      const int n4 = 8 * (e / 4) + 4 * h + e % 4;
+      x = (i < 4 && n4 < 8) ? P[OW5 + i * 8 + n4] : 0.0;
+    } else {
+      is_bias = true;
+    }
+    v[q2] = (float)x;
+  }
+  u32 wb, wh;
+  if (!is_bias) {
+    wb = pack2<2>(v[0], v[1]);
+    wh = pack2<3>(v[0], v[1]);
+  } else {
+    // bias tuples: C register r of lane (j, h) is row 8(r/4) + 4h + r%4
+    const int blk = (reg - 36) / 16, r = (reg - 36) % 16;
+    const int row = 8 * (r / 4) + 4 * h + r % 4;
+    double x;
+    if (blk == 0) x = P[OB2 + row];
+    else if (blk == 1) x = row < 16 ? P[OB3 + row] : 0.0;
+    else x = row < 8 ? P[OB4 + row] : 0.0;
+    wb = wh = __builtin_bit_cast(u32, (float)x);
+  }
+  ((u32 *)(prep + PREP_BF16_OFF))[reg * 64 + lane] = wb;
+  ((u32 *)(prep + PREP_F16_OFF))[reg * 64 + lane] = wh;
+}
+
+inline unsigned grid_for(int64_t items_per_wave_chunks) {
+  const int64_t blocks = (items_per_wave_chunks + WPB - 1) / WPB;
+  return (unsigned)(blocks < 2048 ? (blocks > 0 ? blocks : 1) : 2048);
+}
+
+constexpr unsigned RECHECK_BLOCKS = 512;
+
+}  // namespace
+
+size_t fast_prepared_bytes() { return PREP_BYTES; }
+const void *fast_prepared_f32(const void *prepared) { return prepared; }
+
+hipError_t launch_fast_prepare(const double *P, void *prepared, hipStream_t s) {
+  hipLaunchKernelGGL(k_prepare, dim3((TAB_REGS * 64 + TPB - 1) / TPB), dim3(TPB), 0, s, P,
+                     (char *)prepared);
+  return hipGetLastError();
+}
+
+hipError_t launch_fast_logits(const void *prepared, int precision, float margin, const float *sten,
+                              int64_t n, float *z, uint8_t *masks, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  Line1D ln{};
+  const unsigned grid = grid_for((n + 63) / 64);
+  if (precision == 2)
+    hipLaunchKernelGGL(k_fast_scalar<2>, dim3(grid), dim3(TPB), 0, s, 2, ln, prepared, margin, sten,
+                       n, 1, 0, nullptr, nullptr, masks, z);
+  else
+    hipLaunchKernelGGL(k_fast_scalar<3>, dim3(grid), dim3(TPB), 0, s, 2, ln, prepared, margin, sten,
+                       n, 1, 0, nullptr, nullptr, masks, z);
+  return hipGetLastError();
+}
+
+hipError_t launch_fast_reconstruct(const void *prepared, int precision, float margin,
+                                   const float *f, int64_t n_faces, int sign, int selector,
+                                   const uint8_t *masks_in, float *fhat, uint8_t *masks_out,
+                                   hipStream_t s) {
+  if (n_faces == 0) return hipSuccess;
+  Line1D ln{};
+  const unsigned grid = grid_for((n_faces + 63) / 64);
+  if (precision == 2)
+    hipLaunchKernelGGL(k_fast_scalar<2>, dim3(grid), dim3(TPB), 0, s, 0, ln, prepared, margin, f,
+                       n_faces, sign, selector, masks_in, fhat, masks_out, nullptr);
+  else
+    hipLaunchKernelGGL(k_fast_scalar<3>, dim3(grid), dim3(TPB), 0, s, 0, ln, prepared, margin, f,
+                       n_faces, sign, selector, masks_in, fhat, masks_out, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_fast_faces1d(const Line1D &ln, const FastArgs &fa, const float *q,
+                               const uint8_t *masks_in, uint8_t *masks_out, float *F,
+                               hipStream_t s) {
+  const int64_t tf = ln.faces();
+  const unsigned grid = grid_for((tf + 63) / 64);
+  uint8_t *masks = masks_out ? masks_out : fa.scr.masks;
+  if (fa.equation == 0) {
+    if (fa.precision == 2)
+      hipLaunchKernelGGL(k_fast_scalar<2>, dim3(grid), dim3(TPB), 0, s, 1, ln, fa.prepared, fa.margin,
+                         q, tf, 1, fa.selector, masks_in, F, masks, nullptr);
+    else
+      hipLaunchKernelGGL(k_fast_scalar<3>, dim3(grid), dim3(TPB), 0, s, 1, ln, fa.prepared, fa.margin,
+                         q, tf, 1, fa.selector, masks_in, F, masks, nullptr);
+    return hipGetLastError();
+  }
+  // The re-check flips labels with 32-bit atomics, so the classifier writes
+  // into the workspace buffer (whole words) and the caller's copy follows.
+  masks = fa.scr.masks;
+  const bool recheck = fa.selector == 0 && fa.margin > 0.f;
+  if (recheck) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, fa.scr.qcount);
+  if (fa.precision == 2)
+    hipLaunchKernelGGL(k_fast_euler1d<2>, dim3(grid), dim3(TPB), 0, s, ln, fa.selector, fa.prepared,
+                       fa.margin, q, masks_in, F, masks, fa.scr.queue, fa.scr.qcount, fa.scr.qcap);
+  else
+    hipLaunchKernelGGL(k_fast_euler1d<3>, dim3(grid), dim3(TPB), 0, s, ln, fa.selector, fa.prepared,
+                       fa.margin, q, masks_in, F, masks, fa.scr.queue, fa.scr.qcount, fa.scr.qcap);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (recheck) {
+    Grid2D gd{};
+    hipLaunchKernelGGL(k_recheck<1>, dim3(RECHECK_BLOCKS), dim3(TPB), 0, s, ln, gd, 0, fa.prepared, q,
+                       masks, fa.scr.queue, fa.scr.qcount, fa.scr.qcap, fa.scr.qflag);
+    hipLaunchKernelGGL(k_fixup<1>, dim3(RECHECK_BLOCKS), dim3(TPB), 0, s, ln, gd, 0, q, masks,
+                       fa.scr.queue, fa.scr.qcount, fa.scr.qcap, fa.scr.qflag, F);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && masks_out) e = copy_bytes(masks, masks_out, 3 * tf, s);
+  return e;
+}
+
+hipError_t launch_fast_rhs1d(const Line1D &ln, const FastArgs &fa, const float *q, float *rhs,
+                             const uint8_t *masks_in, uint8_t *masks_out, int32_t *status,
+                             float *F, const Stage *st, hipStream_t s) {
+  hipError_t e = launch_fast_faces1d(ln, fa, q, masks_in, masks_out, F, s);
+  if (e != hipSuccess) return e;
+  return launch_diff1d<float>(ln, fa.equation == 0 ? 1 : 3, F, q, rhs, st, status, s);
+}
+
+hipError_t launch_fast_faces2d(const Grid2D &g, const FastArgs &fa, const float *q,
+                               const uint8_t *masks_in, uint8_t *masks_out, float *Fx, float *Gy,
+                               hipStream_t s) {
+  const int64_t nfx = (g.nx + 1) * g.ny, nfy = g.nx * (g.ny + 1);
+  uint8_t *masks = fa.scr.masks;  // whole words for the re-check atomics
+  const bool recheck = fa.selector == 0 && fa.margin > 0.f;
+  for (int dir = 0; dir < 2; ++dir) {
+    const int64_t nf = dir == 0 ? nfx : nfy;
+    uint8_t *md = masks + (dir == 0 ? 0 : 4 * nfx);
+    const uint8_t *mi = masks_in ? masks_in + (dir == 0 ? 0 : 4 * nfx) : nullptr;
+    float *Fd = dir == 0 ? Fx : Gy;
+    const unsigned grid = grid_for((nf + 63) / 64);
+    if (recheck) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, fa.scr.qcount);
+    if (fa.precision == 2)
+      hipLaunchKernelGGL(k_fast_euler2d<2>, dim3(grid), dim3(TPB), 0, s, g, dir, fa.selector,
+                         fa.prepared, fa.margin, q, mi, Fd, md, fa.scr.queue, fa.scr.qcount,
+                         fa.scr.qcap);
+    else
+      hipLaunchKernelGGL(k_fast_euler2d<3>, dim3(grid), dim3(TPB), 0, s, g, dir, fa.selector,
+                         fa.prepared, fa.margin, q, mi, Fd, md, fa.scr.queue, fa.scr.qcount,
+                         fa.scr.qcap);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (recheck) {
+      Line1D ln{};
+      hipLaunchKernelGGL(k_recheck<2>, dim3(RECHECK_BLOCKS), dim3(TPB), 0, s, ln, g, dir, fa.prepared,
+                         q, md, fa.scr.queue, fa.scr.qcount, fa.scr.qcap, fa.scr.qflag);
+      hipLaunchKernelGGL(k_fixup<2>, dim3(RECHECK_BLOCKS), dim3(TPB), 0, s, ln, g, dir, q, md,
+                         fa.scr.queue, fa.scr.qcount, fa.scr.qcap, fa.scr.qflag, Fd);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  }
+  if (masks_out) return copy_bytes(masks, masks_out, 4 * (nfx + nfy), s);
+  return hipSuccess;
+}
+
+hipError_t launch_fast_rhs2d(const Grid2D &g, const FastArgs &fa, const float *q, float *rhs,
+                             const uint8_t *masks_in, uint8_t *masks_out, int32_t *status,
+                             float *Fx, float *Gy, const Stage *st, hipStream_t s) {
+  hipError_t e = launch_fast_faces2d(g, fa, q, masks_in, masks_out, Fx, Gy, s);
+  if (e != hipSuccess) return e;
+  return launch_diff2d<float>(g, Fx, Gy, q, rhs, st, status, s);
+}
+
+}  // namespace n6

@@ -1,0 +1,666 @@
+// Plain NENO6 kernels: one lane per face (or per stencil), the classifier
+// evaluated on the vector units with the canonical fma order.
+//
+// Instantiated for double -- the FP64 path, whose classification labels are
+// bit-identical to the FP64 reference implementation because this file is
+// compiled with -ffp-contract=off and every fma is written out -- and for
+// float (the FP32 vector-unit path, also the re-check path of BF16/FP16).
+#include "neno6_device.h"
+#include "neno6_internal.h"
+
+namespace n6 {
+
+namespace {
+
+constexpr int TPB = 256;
+
+template <typename T> N6_DEV const T *uniform_ptr(const T *p) {
+  // The classifier weights are the same for every lane; making the pointer
+  // wave-uniform lets the compiler fetch them with scalar loads.
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (const T *)(((uint64_t)hi << 32) | lo);
+}
+
+// One classifier evaluation (Alg. 2 steps 1-2), kept out of line so that a
+// kernel with several evaluations per lane carries a single copy of the
+// 3104-fma network.
+template <typename T>
+__device__ __attribute__((noinline)) unsigned classify_call(const T *P, T s0, T s1, T s2, T s3,
+                                                            T s4, T s5) {
+  const T s[6] = {s0, s1, s2, s3, s4, s5};
+  return classify<T>(uniform_ptr<T>(P), s);
+}
+
+template <typename T>
+N6_DEV unsigned select_mask(int selector, const T *P, const T s[6], unsigned mask_in) {
+  switch (selector) {
+  case 0: return classify_call<T>(P, s[0], s[1], s[2], s[3], s[4], s[5]);
+  case 1: return 15u;
+  case 2: return 0u;
+  default: return mask_in & 15u;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB)
+k_reconstruct(const T *__restrict__ P, const T *__restrict__ f, int64_t n_faces, int sign,
+              int selector, const uint8_t *__restrict__ min, T *__restrict__ fhat,
+              uint8_t *__restrict__ mout) {
+  const int64_t k = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  if (k >= n_faces) return;
+  T s[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) s[j] = sign > 0 ? f[k + j] : f[k + 5 - j];
+  const unsigned sel = select_mask<T>(selector, P, s, min ? min[k] : 0u);
+  fhat[k] = combine_canonical<T>(s, sel);
+  if (mout) mout[k] = (uint8_t)sel;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB)
+k_mlp_logits(const T *__restrict__ P, const T *__restrict__ sten, int64_t n, T *__restrict__ z,
+             uint8_t *__restrict__ masks) {
+  const int64_t e = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  if (e >= n) return;
+  T s[6], x[6], zz[4];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) s[j] = sten[6 * e + j];
+  features<T>(s, x);
+  mlp_logits<T>(uniform_ptr<T>(P), x, zz);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) z[4 * e + k] = zz[k];
+  if (masks) masks[e] = (uint8_t)mask_from_logits<T>(zz);
+}
+
+// Scalar advection, f = u, unit speed: the '+' split flux (f + u)/2 equals u
+// exactly and the '-' split flux is identically zero, so the face flux is the
+// '+' reconstruction of u.
+template <typename T>
+__global__ void __launch_bounds__(TPB)
+k_faces_advection(Line1D ln, const T *__restrict__ P, int selector, const T *__restrict__ u,
+                  const uint8_t *__restrict__ min, T *__restrict__ Fh, uint8_t *__restrict__ mout) {
+  const int64_t g = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  if (g >= ln.faces()) return;
+  const int p = find_problem(ln.offsets, ln.np, g, 1);
+  const int64_t o = ln.offsets[p], n = ln.offsets[p + 1] - o, k = g - o - p;
+  T s[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) s[j] = u[o + ghost(k - 3 + j, n, ln.bc)];
+  const unsigned sel = select_mask<T>(selector, P, s, min ? min[g] : 0u);
+  Fh[g] = combine_canonical<T>(s, sel);
+  if (mout) mout[g] = (uint8_t)sel;
+}
+
+// One face of a 1D Euler line from its six cells (Sec. 4.4): Roe
+// eigenvectors of cells i, i+1; projection of the six states and fluxes;
+// Rusanov split with alpha_m = max_j |lambda_m(q_j)|; NENO6 per field and
+// sign; back-projection R (h+ + h-).
+template <typename T>
+N6_DEV void euler1d_face(const T qs[6][3], T gamma, const T *P, int selector, const uint8_t *mi,
+                         int64_t mstride, T Fh[3], uint8_t *mo) {
+  T L[3][3], R[3][3];
+  roe1d<T>(qs[2], qs[3], gamma, L, R);
+  T v[6][3], g[6][3], lam[6][3];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    T u, p, c, F[3];
+    prim1d<T>(qs[j], gamma, u, p, c);
+    flux1d<T>(qs[j], u, p, F);
+    lam[j][0] = u - c;
+    lam[j][1] = u;
+    lam[j][2] = u + c;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      T av = T(0), ag = T(0);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        av = fma_<T>(L[m][r], qs[j][r], av);
+        ag = fma_<T>(L[m][r], F[r], ag);
+      }
+      v[j][m] = av;
+      g[j][m] = ag;
+    }
+  }
+  T hs[3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    T alpha = T(0);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const T a = abs_<T>(lam[j][m]);
+      alpha = a > alpha ? a : alpha;
+    }
+    T sp[6], sm[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const T t = alpha * v[j][m];
+      sp[j] = T(0.5) * (g[j][m] + t);
+      sm[5 - j] = T(0.5) * (g[j][m] - t);
+    }
+    const unsigned in = mi ? mi[m * mstride] : 0u;
+    const unsigned selp = select_mask<T>(selector, P, sp, in & 15u);
+    const unsigned selm = select_mask<T>(selector, P, sm, (in >> 4) & 15u);
+    const T hp = combine_canonical<T>(sp, selp);
+    const T hm = combine_canonical<T>(sm, selm);
+    hs[m] = hp + hm;
+    if (mo) mo[m * mstride] = (uint8_t)(selp | (selm << 4));
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    T acc = T(0);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) acc = fma_<T>(R[r][m], hs[m], acc);
+    Fh[r] = acc;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB)
+k_faces_euler1d(Line1D ln, const T *__restrict__ P, int selector, const T *__restrict__ q,
+                const uint8_t *__restrict__ min, T *__restrict__ Fh, uint8_t *__restrict__ mout) {
+  const int64_t tf = ln.faces();
+  const int64_t g = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  if (g >= tf) return;
+  const int p = find_problem(ln.offsets, ln.np, g, 1);
+  const int64_t o = ln.offsets[p], n = ln.offsets[p + 1] - o, k = g - o - p;
+  T qs[6][3];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const int64_t ci = o + ghost(k - 3 + j, n, ln.bc);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) qs[j][r] = q[r * ln.total + ci];
+  }
+  T F[3];
+  euler1d_face<T>(qs, (T)ln.gamma, P, selector, min ? min + g : nullptr, tf, F,
+                  mout ? mout + g : nullptr);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) Fh[r * tf + g] = F[r];
+}
+
+// RK3 stage update (Sec. 4.4, SSP-RK3):
+//   stage 1: u1 = u0 + dt L(u0)
+//   stage 2: u2 = 3/4 u0 + 1/4 (u1 + dt L(u1))
+//   stage 3: u  = 1/3 u0 + 2/3 (u2 + dt L(u2))
+template <typename T>
+N6_DEV T rk3(int stage, T us, T u0, T L, T dt) {
+  if (stage == 1) return fma_<T>(dt, L, us);
+  const T t = fma_<T>(dt, L, us);
+  if (stage == 2) return fma_<T>(T(0.25), t, T(0.75) * u0);
+  return fma_<T>(T(2) / T(3), t, (T(1) / T(3)) * u0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB)
+k_diff1d(Line1D ln, int nvar, const T *__restrict__ Fh, const T *__restrict__ q,
+         T *__restrict__ rhs, Stage st, int has_stage, int32_t *__restrict__ status_out) {
+  const int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  if (i >= ln.total) return;
+  const int p = find_problem(ln.offsets, ln.np, i, 0);
+  const int64_t g = i + p;  // face to the left of cell i
+  const int64_t tf = ln.faces();
+  const T dx = (T)ln.dx[p];
+  if (status_out && nvar == 3) {
+    const T qc[3] = {q[i], q[ln.total + i], q[2 * ln.total + i]};
+    T u, pr, c;
+    prim1d<T>(qc, (T)ln.gamma, u, pr, c);
+    if (!physical<T>(qc[0], pr)) status_out[p] = ST_NONPHYSICAL;
+  }
+  for (int r = 0; r < nvar; ++r) {
+    const T L = (Fh[r * tf + g] - Fh[r * tf + g + 1]) / dx;
+    if (!has_stage) {
+      rhs[r * ln.total + i] = L;
+    } else {
+      const T *us = (const T *)st.us;
+      const T *u0 = (const T *)st.u0;
+      T *out = (T *)st.out;
+      const int64_t idx = r * ln.total + i;
+      out[idx] = st.status[p] != 0 ? u0[idx] : rk3<T>(st.stage, us[idx], u0[idx], L, (T)st.dt[p]);
+    }
+  }
+}
+
+// Time step of each line at the start of an RK3 step: one block per line.
+template <typename T>
+__global__ void __launch_bounds__(TPB)
+k_cfl1d(Line1D ln, int equation, const T *__restrict__ q, double cfl, double *__restrict__ dt,
+        int32_t *__restrict__ status, double *__restrict__ t) {
+  const int p = blockIdx.x;
+  const int64_t o = ln.offsets[p], n = ln.offsets[p + 1] - o;
+  __shared__ double red[TPB];
+  __shared__ int bad[TPB];
+  double smax = 0.0;
+  int b = 0;
+  if (equation == 2) {
+    for (int64_t i = threadIdx.x; i < n; i += TPB) {
+      const T qc[3] = {q[o + i], q[ln.total + o + i], q[2 * ln.total + o + i]};
+      T u, pr, c;
+      prim1d<T>(qc, (T)ln.gamma, u, pr, c);
+      if (!physical<T>(qc[0], pr)) b = 1;
+      const double sp = (double)(abs_<T>(u) + c);
+      smax = sp > smax ? sp : smax;
+    }
+  }
+  red[threadIdx.x] = smax;
+  bad[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = TPB / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const double o2 = red[threadIdx.x + w];
+      red[threadIdx.x] = o2 > red[threadIdx.x] ? o2 : red[threadIdx.x];
+      bad[threadIdx.x] |= bad[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (status[p] != 0) {
+      dt[p] = 0.0;
+      return;
+    }
+    if (bad[0]) {
+      status[p] = ST_NONPHYSICAL;
+      dt[p] = 0.0;
+      return;
+    }
+    const double d = equation == 2 ? (cfl * ln.dx[p]) / red[0] : cfl * ln.dx[p];
+    dt[p] = d;
+    t[p] = t[p] + d;
+  }
+}
+
+// ---- 2D ---------------------------------------------------------------------
+template <typename T>
+N6_DEV void euler2d_face(const T qs[6][4], T gamma, int dir, const T *P, int selector,
+                         const uint8_t *mi, int64_t mstride, T Fh[4], uint8_t *mo) {
+  T L[4][4], R[4][4];
+  roe2d<T>(qs[2], qs[3], gamma, dir, L, R);
+  T v[6][4], g[6][4], lam[6][4];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    T u, vv, p, c, F[4];
+    prim2d<T>(qs[j], gamma, u, vv, p, c);
+    flux2d<T>(qs[j], u, vv, p, dir, F);
+    const T un = dir == 0 ? u : vv;
+    lam[j][0] = un - c;
+    lam[j][1] = un;
+    lam[j][2] = un;
+    lam[j][3] = un + c;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      T av = T(0), ag = T(0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        av = fma_<T>(L[m][r], qs[j][r], av);
+        ag = fma_<T>(L[m][r], F[r], ag);
+      }
+      v[j][m] = av;
+      g[j][m] = ag;
+    }
+  }
+  T hs[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    T alpha = T(0);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const T a = abs_<T>(lam[j][m]);
+      alpha = a > alpha ? a : alpha;
+    }
+    T sp[6], sm[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const T t = alpha * v[j][m];
+      sp[j] = T(0.5) * (g[j][m] + t);
+      sm[5 - j] = T(0.5) * (g[j][m] - t);
+    }
+    const unsigned in = mi ? mi[m * mstride] : 0u;
+    const unsigned selp = select_mask<T>(selector, P, sp, in & 15u);
+    const unsigned selm = select_mask<T>(selector, P, sm, (in >> 4) & 15u);
+    const T hp = combine_canonical<T>(sp, selp);
+    const T hm = combine_canonical<T>(sm, selm);
+    hs[m] = hp + hm;
+    if (mo) mo[m * mstride] = (uint8_t)(selp | (selm << 4));
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    T acc = T(0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) acc = fma_<T>(R[r][m], hs[m], acc);
+    Fh[r] = acc;
+  }
+}
+
+// dir 0: faces [ny][nx+1]; dir 1: faces [ny+1][nx].
+template <typename T>
+__global__ void __launch_bounds__(TPB)
+k_faces_euler2d(Grid2D gd, int dir, const T *__restrict__ P, int selector, const T *__restrict__ q,
+                const uint8_t *__restrict__ min, T *__restrict__ Fh, uint8_t *__restrict__ mout) {
+  const int64_t nf = dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1);
+  const int64_t f = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  if (f >= nf) return;
+  const int64_t cells = gd.nx * gd.ny;
+  T qs[6][4];
+  if (dir == 0) {
+    const int64_t y = f / (gd.nx + 1), k = f % (gd.nx + 1);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int64_t ci = y * gd.nx + ghost(k - 3 + j, gd.nx, gd.bc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) qs[j][r] = q[r * cells + ci];
+    }
+  } else {
+    const int64_t k = f / gd.nx, x = f % gd.nx;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int64_t ci = ghost(k - 3 + j, gd.ny, gd.bc) * gd.nx + x;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) qs[j][r] = q[r * cells + ci];
+    }
+  }
+  T F[4];
+  euler2d_face<T>(qs, (T)gd.gamma, dir, P, selector, min ? min + f : nullptr, nf, F,
+                  mout ? mout + f : nullptr);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) Fh[r * nf + f] = F[r];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB)
+k_diff2d(Grid2D gd, const T *__restrict__ Fx, const T *__restrict__ Gy, const T *__restrict__ q,
+         T *__restrict__ rhs, Stage st, int has_stage, int32_t *__restrict__ status_out) {
+  const int64_t cells = gd.nx * gd.ny;
+  const int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  if (i >= cells) return;
+  const int64_t y = i / gd.nx, x = i % gd.nx;
+  const int64_t nfx = (gd.nx + 1) * gd.ny, nfy = gd.nx * (gd.ny + 1);
+  const int64_t fx = y * (gd.nx + 1) + x, fy = y * gd.nx + x;
+  if (status_out) {
+    const T qc[4] = {q[i], q[cells + i], q[2 * cells + i], q[3 * cells + i]};
+    T u, v, pr, c;
+    prim2d<T>(qc, (T)gd.gamma, u, v, pr, c);
+    if (!physical<T>(qc[0], pr)) status_out[0] = ST_NONPHYSICAL;
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const T a = (Fx[r * nfx + fx] - Fx[r * nfx + fx + 1]) / (T)gd.dx;
+    const T b = (Gy[r * nfy + fy] - Gy[r * nfy + fy + gd.nx]) / (T)gd.dy;
+    const T L = a + b;
+    const int64_t idx = r * cells + i;
+    if (!has_stage) {
+      rhs[idx] = L;
+    } else {
+      const T *us = (const T *)st.us;
+      const T *u0 = (const T *)st.u0;
+      T *out = (T *)st.out;
+      out[idx] = st.status[0] != 0 ? u0[idx] : rk3<T>(st.stage, us[idx], u0[idx], L, (T)st.dt[0]);
+    }
+  }
+}
+
+constexpr int CFL2D_BLOCKS = 1024;
+
+template <typename T>
+__global__ void __launch_bounds__(TPB)
+k_cfl2d_partial(Grid2D gd, const T *__restrict__ q, double *__restrict__ part) {
+  const int64_t cells = gd.nx * gd.ny;
+  __shared__ double rx[TPB], ry[TPB], rb[TPB];
+  double sx = 0.0, sy = 0.0, bad = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < cells;
+       i += (int64_t)gridDim.x * TPB) {
+    const T qc[4] = {q[i], q[cells + i], q[2 * cells + i], q[3 * cells + i]};
+    T u, v, pr, c;
+    prim2d<T>(qc, (T)gd.gamma, u, v, pr, c);
+    if (!physical<T>(qc[0], pr)) bad = 1.0;
+    const double a = (double)(abs_<T>(u) + c), b = (double)(abs_<T>(v) + c);
+    sx = a > sx ? a : sx;
+    sy = b > sy ? b : sy;
+  }
+  rx[threadIdx.x] = sx;
+  ry[threadIdx.x] = sy;
+  rb[threadIdx.x] = bad;
+  __syncthreads();
+  for (int w = TPB / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      rx[threadIdx.x] = rx[threadIdx.x + w] > rx[threadIdx.x] ? rx[threadIdx.x + w] : rx[threadIdx.x];
+      ry[threadIdx.x] = ry[threadIdx.x + w] > ry[threadIdx.x] ? ry[threadIdx.x + w] : ry[threadIdx.x];
+      rb[threadIdx.x] = rb[threadIdx.x + w] > rb[threadIdx.x] ? rb[threadIdx.x + w] : rb[threadIdx.x];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x + 0] = rx[0];
+    part[3 * blockIdx.x + 1] = ry[0];
+    part[3 * blockIdx.x + 2] = rb[0];
+  }
+}
+
+__global__ void __launch_bounds__(TPB)
+k_cfl2d_final(Grid2D gd, int nparts, const double *__restrict__ part, double cfl,
+              double *__restrict__ dt, int32_t *__restrict__ status, double *__restrict__ t) {
+  __shared__ double rx[TPB], ry[TPB], rb[TPB];
+  double sx = 0.0, sy = 0.0, bad = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += TPB) {
+    sx = part[3 * i] > sx ? part[3 * i] : sx;
+    sy = part[3 * i + 1] > sy ? part[3 * i + 1] : sy;
+    bad = part[3 * i + 2] > bad ? part[3 * i + 2] : bad;
+  }
+  rx[threadIdx.x] = sx;
+  ry[threadIdx.x] = sy;
+  rb[threadIdx.x] = bad;
+  __syncthreads();
+  for (int w = TPB / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      rx[threadIdx.x] = rx[threadIdx.x + w] > rx[threadIdx.x] ? rx[threadIdx.x + w] : rx[threadIdx.x];
+      ry[threadIdx.x] = ry[threadIdx.x + w] > ry[threadIdx.x] ? ry[threadIdx.x + w] : ry[threadIdx.x];
+      rb[threadIdx.x] = rb[threadIdx.x + w] > rb[threadIdx.x] ? rb[threadIdx.x + w] : rb[threadIdx.x];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (status[0] != 0) {
+      dt[0] = 0.0;
+      return;
+    }
+    if (rb[0] != 0.0) {
+      status[0] = ST_NONPHYSICAL;
+      dt[0] = 0.0;
+      return;
+    }
+    const double d = cfl / (rx[0] / gd.dx + ry[0] / gd.dy);
+    dt[0] = d;
+    t[0] = t[0] + d;
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_params_to_f32(const double *__restrict__ P, float *__restrict__ P32) {
+  const int i = blockIdx.x * TPB + threadIdx.x;
+  if (i < NPARAM) P32[i] = (float)P[i];
+}
+
+// Fixed-mask adjoint of the advection rhs on one line (gather form).
+// Forward: h_k = sum_j a_{k,j} u_{c(k,j)}, c(k,j) = ghost(k-3+j); rhs_i =
+// (h_i - h_{i+1})/dx.  Adjoint: hbar_k = (rbar_k [k<n] - rbar_{k-1} [k>0])/dx,
+// ubar_c = sum over faces k and stencil slots j with c(k,j) = c of a_{k,j} hbar_k.
+template <typename T>
+N6_DEV void face_coeffs(unsigned sel, T a[6]) {
+  T e[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) e[i] = i == j ? T(1) : T(0);
+    a[j] = combine_canonical<T>(e, sel);
+  }
+}
+
+template <typename T>
+N6_DEV void adj_face(int64_t k, int j, int64_t n, T dx, const uint8_t *__restrict__ masks,
+                     const T *__restrict__ rbar, T &acc) {
+  T a[6];
+  face_coeffs<T>(masks[k] & 15u, a);
+  const T hb = ((k < n ? rbar[k] : T(0)) - (k > 0 ? rbar[k - 1] : T(0))) / dx;
+  acc = fma_<T>(a[j], hb, acc);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB)
+k_adjoint_advection(int64_t n, const double *__restrict__ dxp, int bc,
+                    const uint8_t *__restrict__ masks, const T *__restrict__ rbar,
+                    T *__restrict__ ubar) {
+  const int64_t c = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  if (c >= n) return;
+  const T dx = (T)dxp[0];
+  T acc = T(0);
+  if (bc == 0) {
+    // face k reads cell (k - 3 + j) mod n; faces 0 and n read the same cells
+    for (int j = 0; j < 6; ++j) {
+      const int64_t k0 = ((c + 3 - j) % n + n) % n;
+      adj_face<T>(k0, j, n, dx, masks, rbar, acc);
+      if (k0 == 0) adj_face<T>(n, j, n, dx, masks, rbar, acc);
+    }
+  } else {
+    const int64_t k_lo = c - 3 < 0 ? 0 : c - 3, k_hi = c + 3 > n ? n : c + 3;
+    for (int64_t k = k_lo; k <= k_hi; ++k)
+      for (int j = 0; j < 6; ++j)
+        if (ghost(k - 3 + j, n, bc) == c) adj_face<T>(k, j, n, dx, masks, rbar, acc);
+  }
+  ubar[c] = acc;
+}
+
+inline unsigned nblocks(int64_t n) { return (unsigned)((n + TPB - 1) / TPB); }
+
+}  // namespace
+
+// ---- launchers --------------------------------------------------------------
+template <typename T>
+hipError_t launch_reconstruct(const T *P, const T *f, int64_t n_faces, int sign, int selector,
+                              const uint8_t *masks_in, T *fhat, uint8_t *masks_out,
+                              hipStream_t s) {
+  if (n_faces == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reconstruct<T>, dim3(nblocks(n_faces)), dim3(TPB), 0, s, P, f, n_faces,
+                     sign, selector, masks_in, fhat, masks_out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mlp_logits(const T *P, const T *sten, int64_t n, T *z, uint8_t *masks,
+                             hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mlp_logits<T>, dim3(nblocks(n)), dim3(TPB), 0, s, P, sten, n, z, masks);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_faces_advection(const Line1D &ln, const T *P, int selector, const T *u,
+                                  const uint8_t *masks_in, T *Fhat, uint8_t *masks_out,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(k_faces_advection<T>, dim3(nblocks(ln.faces())), dim3(TPB), 0, s, ln, P,
+                     selector, u, masks_in, Fhat, masks_out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_faces_euler1d(const Line1D &ln, const T *P, int selector, const T *q,
+                                const uint8_t *masks_in, T *Fhat, uint8_t *masks_out,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_faces_euler1d<T>, dim3(nblocks(ln.faces())), dim3(TPB), 0, s, ln, P,
+                     selector, q, masks_in, Fhat, masks_out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_diff1d(const Line1D &ln, int nvar, const T *Fhat, const T *q, T *rhs,
+                         const Stage *st, int32_t *status_out, hipStream_t s) {
+  Stage sv{};
+  if (st) sv = *st;
+  hipLaunchKernelGGL(k_diff1d<T>, dim3(nblocks(ln.total)), dim3(TPB), 0, s, ln, nvar, Fhat, q,
+                     rhs, sv, st ? 1 : 0, status_out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cfl1d(const Line1D &ln, int equation, const T *q, double cfl, double *dt,
+                        int32_t *status, double *t, hipStream_t s) {
+  hipLaunchKernelGGL(k_cfl1d<T>, dim3(ln.np), dim3(TPB), 0, s, ln, equation, q, cfl, dt, status,
+                     t);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_faces_euler2d(const Grid2D &g, const T *P, int selector, const T *q,
+                                const uint8_t *mx_in, const uint8_t *my_in, T *Fx, T *Gy,
+                                uint8_t *mx_out, uint8_t *my_out, hipStream_t s) {
+  const int64_t nfx = (g.nx + 1) * g.ny, nfy = g.nx * (g.ny + 1);
+  hipLaunchKernelGGL(k_faces_euler2d<T>, dim3(nblocks(nfx)), dim3(TPB), 0, s, g, 0, P, selector,
+                     q, mx_in, Fx, mx_out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_faces_euler2d<T>, dim3(nblocks(nfy)), dim3(TPB), 0, s, g, 1, P, selector,
+                     q, my_in, Gy, my_out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_diff2d(const Grid2D &g, const T *Fx, const T *Gy, const T *q, T *rhs,
+                         const Stage *st, int32_t *status_out, hipStream_t s) {
+  Stage sv{};
+  if (st) sv = *st;
+  hipLaunchKernelGGL(k_diff2d<T>, dim3(nblocks(g.nx * g.ny)), dim3(TPB), 0, s, g, Fx, Gy, q, rhs,
+                     sv, st ? 1 : 0, status_out);
+  return hipGetLastError();
+}
+
+int cfl2d_parts() { return CFL2D_BLOCKS; }
+
+template <typename T>
+hipError_t launch_cfl2d(const Grid2D &g, const T *q, double cfl, double *part, double *dt,
+                        int32_t *status, double *t, hipStream_t s) {
+  hipLaunchKernelGGL(k_cfl2d_partial<T>, dim3(CFL2D_BLOCKS), dim3(TPB), 0, s, g, q, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cfl2d_final, dim3(1), dim3(TPB), 0, s, g, CFL2D_BLOCKS, part, cfl, dt,
+                     status, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_advection(const Line1D &ln, const uint8_t *masks, const void *rbar,
+                                    void *ubar, int is_fp64, hipStream_t s) {
+  if (is_fp64)
+    hipLaunchKernelGGL(k_adjoint_advection<double>, dim3(nblocks(ln.total)), dim3(TPB), 0, s,
+                       ln.total, ln.dx, ln.bc, masks, (const double *)rbar, (double *)ubar);
+  else
+    hipLaunchKernelGGL(k_adjoint_advection<float>, dim3(nblocks(ln.total)), dim3(TPB), 0, s,
+                       ln.total, ln.dx, ln.bc, masks, (const float *)rbar, (float *)ubar);
+  return hipGetLastError();
+}
+
+hipError_t launch_params_to_f32(const double *P, float *P32, hipStream_t s) {
+  hipLaunchKernelGGL(k_params_to_f32, dim3(nblocks(NPARAM)), dim3(TPB), 0, s, P, P32);
+  return hipGetLastError();
+}
+
+#define N6_INST(T)                                                                               \
+  template hipError_t launch_reconstruct<T>(const T *, const T *, int64_t, int, int,              \
+                                            const uint8_t *, T *, uint8_t *, hipStream_t);       \
+  template hipError_t launch_mlp_logits<T>(const T *, const T *, int64_t, T *, uint8_t *,        \
+                                           hipStream_t);                                         \
+  template hipError_t launch_faces_advection<T>(const Line1D &, const T *, int, const T *,       \
+                                                const uint8_t *, T *, uint8_t *, hipStream_t);   \
+  template hipError_t launch_faces_euler1d<T>(const Line1D &, const T *, int, const T *,         \
+                                              const uint8_t *, T *, uint8_t *, hipStream_t);     \
+  template hipError_t launch_diff1d<T>(const Line1D &, int, const T *, const T *, T *,           \
+                                       const Stage *, int32_t *, hipStream_t);                   \
+  template hipError_t launch_cfl1d<T>(const Line1D &, int, const T *, double, double *,          \
+                                      int32_t *, double *, hipStream_t);                         \
+  template hipError_t launch_faces_euler2d<T>(const Grid2D &, const T *, int, const T *,         \
+                                              const uint8_t *, const uint8_t *, T *, T *,        \
+                                              uint8_t *, uint8_t *, hipStream_t);                \
+  template hipError_t launch_diff2d<T>(const Grid2D &, const T *, const T *, const T *, T *,     \
+                                       const Stage *, int32_t *, hipStream_t);                   \
+  template hipError_t launch_cfl2d<T>(const Grid2D &, const T *, double, double *, double *,     \
+                                      int32_t *, double *, hipStream_t);
+
+N6_INST(double)
+N6_INST(float)
+
+}  // namespace n6

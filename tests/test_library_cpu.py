@@ -1,0 +1,89 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every entry point declared in include/neno6.h, and rejects bad arguments on
+the host before touching a device."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "neno6.h")
+
+
+def _lib():
+    from paper_2207_08500_amd import native
+    if not os.path.exists(native.LIB_PATH):
+        from paper_2207_08500_amd import build
+        build.build()
+    return native, native.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(neno6_[a-z_0-9]+)\s*\(",
+                                 text, re.M)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for must in ("neno6_reconstruct", "neno6_rhs", "neno6_step", "neno6_classifier_train",
+                 "neno6_mlp_prepare", "neno6_workspace_size", "neno6_status_string"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    native, lib = _lib()
+    names = declared_functions()
+    out = subprocess.run(["nm", "-D", "--defined-only", native.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if l.strip())
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(lib, n)
+    assert set(native.EXPORTS) == set(names)
+
+
+def test_host_argument_checks():
+    native, lib = _lib()
+    assert lib.neno6_version() >= 10000
+    assert lib.neno6_status_string(-4).decode().startswith("state not physical")
+    assert lib.neno6_mlp_prepared_bytes() >= 3228 * 4
+    # invalid problems: workspace size 0, entry points return BAD_ARG before any launch
+    ps = native.ProblemStruct()
+    ps.equation = 7
+    assert lib.neno6_workspace_size(C.byref(ps)) == 0
+    ps.equation = native.EULER2D
+    ps.nx, ps.ny, ps.dx2d, ps.dy2d, ps.gamma = 0, 4, 0.1, 0.1, 1.4
+    assert lib.neno6_workspace_size(C.byref(ps)) == 0
+    ps.nx = 8
+    assert lib.neno6_workspace_size(C.byref(ps)) > 0
+    assert lib.neno6_rhs(C.byref(ps), None, None, None, None, None, None, None, 0, None) == native.BAD_ARG
+    # 1D: offsets must start at 0, increase strictly and end at total_cells
+    import numpy as np
+    off = np.array([0, 5, 5, 9], np.int64)
+    p1 = native.ProblemStruct()
+    p1.equation, p1.bc, p1.precision, p1.selector = native.EULER1D, 1, native.FP64, 1
+    p1.n_problems, p1.total_cells, p1.gamma = 3, 9, 1.4
+    p1.offsets = p1.dx = 1  # non-null device placeholders, never dereferenced on the host
+    p1.offsets_host = off.ctypes.data
+    assert lib.neno6_workspace_size(C.byref(p1)) == 0
+    off[2] = 7
+    assert lib.neno6_workspace_size(C.byref(p1)) > 0
+    assert lib.neno6_reconstruct(None, None, 10, 2, 0, 1, None, None, None, None) == native.BAD_ARG
+    assert lib.neno6_reconstruct(None, None, 10, 1, 0, 0, None, None, None, None) == native.BAD_ARG
+    assert lib.neno6_classifier_train(None, None, None, None, None, None, None, 0, 0, 0.0, 0.9,
+                                      0.999, 1e-8, native.BF16, None, None, 0, None) == native.BAD_ARG
+
+
+def test_product_path_does_not_import_the_oracle():
+    """The HIP binding never reaches the CPU oracle."""
+    pkg = os.path.join(ROOT, "paper_2207_08500_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "neno6_oracle" not in text, f
