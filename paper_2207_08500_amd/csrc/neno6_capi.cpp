@@ -406,6 +406,7 @@ int32_t neno6_classifier_train(double *params, double *adam_m, double *adam_v, i
       !(eps > 0) || !ws)
     return NENO6_BAD_ARG;
   if (precision != NENO6_FP32 && precision != NENO6_BF16) return NENO6_BAD_LAYOUT;
+  if (!train_precision_supported(precision)) return NENO6_UNSUPPORTED;
   if (ws_bytes < train_workspace_bytes(batch)) return NENO6_WORKSPACE_SMALL;
   for (int64_t s0 = 0; s0 < n_idx; s0 += batch) {
     const int64_t mb = n_idx - s0 < batch ? n_idx - s0 : batch;
@@ -423,6 +424,7 @@ int32_t neno6_classifier_grad(const double *params, const float *s, const uint8_
                               size_t ws_bytes, hipStream_t stream) {
   if (!params || !s || !y || n < 1 || n > (1 << 20) || !grad || !loss || !ws) return NENO6_BAD_ARG;
   if (precision != NENO6_FP32 && precision != NENO6_BF16) return NENO6_BAD_LAYOUT;
+  if (!train_precision_supported(precision)) return NENO6_UNSUPPORTED;
   if (ws_bytes < train_workspace_bytes((int32_t)n)) return NENO6_WORKSPACE_SMALL;
   return hip_status(launch_grad(params, s, y, n, precision, grad, loss, ws, stream));
 }

@@ -49,6 +49,7 @@ hipError_t launch_fast_rhs2d(const Grid2D &g, const FastArgs &fa, const float *q
 
 // ---- training ----------------------------------------------------------------
 size_t train_workspace_bytes(int32_t batch);
+bool train_precision_supported(int precision);
 hipError_t launch_train_batch(double *P, double *m, double *v, int64_t step, const float *s,
                               const uint8_t *y, const int64_t *idx, int64_t mb, double lr,
                               double b1, double b2, double eps, int precision, double *loss_out,
