@@ -179,6 +179,13 @@ int32_t neno6_rhs(const neno6_problem *prob, const neno6_mlp *mlp, const void *q
 int32_t neno6_face_fluxes(const neno6_problem *prob, const neno6_mlp *mlp, const void *q, void *F,
                           uint8_t *masks_out, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Diagnostic (synchronous: waits for `stream`): after neno6_face_fluxes in
+ * BF16/FP16 mode, the number of classifier evaluations of each sweep
+ * direction (count[0]: 1D or x, count[1]: y) that fell inside the re-check
+ * margin and were re-evaluated in FP32.  count [host, 2 values]. */
+int32_t neno6_recheck_count(const neno6_problem *prob, const void *ws, size_t ws_bytes,
+                            uint32_t *count, hipStream_t stream);
+
 /* ---- time stepping -------------------------------------------------------- */
 /* n_steps SSP-RK3 steps (Sec. 4.4), in place on q [dev].  Each step first
  * takes every problem's time step from its current state --

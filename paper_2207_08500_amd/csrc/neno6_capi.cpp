@@ -63,8 +63,9 @@ int32_t check_problem(const neno6_problem *pb) {
   return NENO6_OK;
 }
 
-Line1D line_of(const neno6_problem *pb) {
+Line1D line_of(const neno6_problem *pb, const int32_t *fmap = nullptr) {
   Line1D ln;
+  ln.fmap = fmap;
   ln.offsets = pb->offsets;
   ln.dx = pb->dx;
   ln.np = pb->n_problems;
@@ -93,6 +94,8 @@ struct Work {
   void *u1 = nullptr, *u2 = nullptr;
   double *dt = nullptr, *part = nullptr;
   int32_t *dummy_status = nullptr;
+  int32_t *fmap = nullptr;          // 1D: line of every face
+  void *evals = nullptr;            // FP64/FP32 Euler: value and mask per evaluation
   FastScratch scr{};                // reduced-precision path only
   size_t bytes = 0;
 };
@@ -118,6 +121,13 @@ Work carve_work(const neno6_problem *pb, void *ws) {
     w.u2 = c.take<char>(es * nv * (size_t)pb->total_cells);
     w.dt = c.take<double>(pb->n_problems);
     w.dummy_status = c.take<int32_t>(pb->n_problems);
+    w.fmap = c.take<int32_t>(faces);
+  }
+  if (pb->precision <= NENO6_FP32 && pb->equation != NENO6_ADVECTION) {
+    const int64_t nf = pb->equation == NENO6_EULER2D
+                           ? std::max((pb->nx + 1) * pb->ny, pb->nx * (pb->ny + 1))
+                           : pb->total_cells + pb->n_problems;
+    w.evals = c.take<char>(plain_eval_bytes(pb->equation == NENO6_EULER2D ? 8 : 6, nf, es));
   }
   if (pb->precision >= NENO6_BF16) {
     // masks of every face (x and y faces in 2D), re-check queue of at most
@@ -131,7 +141,7 @@ Work carve_work(const neno6_problem *pb, void *ws) {
     w.scr.masks = c.take<uint8_t>(4 * faces);
     w.scr.queue = c.take<uint32_t>(8 * qfaces);
     w.scr.qflag = c.take<uint8_t>(8 * qfaces);
-    w.scr.qcount = c.take<uint32_t>(1);
+    w.scr.qcount = c.take<uint32_t>(2);
     w.scr.qcap = (int64_t)(8 * qfaces);
   }
   w.bytes = c.used;
@@ -149,22 +159,43 @@ int32_t rhs_impl(const neno6_problem *pb, const T *P, const void *q, void *rhs,
     const size_t nfx = 4 * (size_t)(g.nx + 1) * g.ny;
     e = launch_faces_euler2d<T>(g, P, pb->selector, (const T *)q, masks_in,
                                 masks_in ? masks_in + nfx : nullptr, (T *)w.F, (T *)w.G, masks_out,
-                                masks_out ? masks_out + nfx : nullptr, s);
+                                masks_out ? masks_out + nfx : nullptr, w.evals, s);
     if (e != hipSuccess) return NENO6_HIP_ERROR;
     e = launch_diff2d<T>(g, (const T *)w.F, (const T *)w.G, (const T *)q, (T *)rhs, st, status, s);
     return hip_status(e);
   }
-  const Line1D ln = line_of(pb);
+  const Line1D ln = line_of(pb, w.fmap);
   if (pb->equation == NENO6_ADVECTION)
     e = launch_faces_advection<T>(ln, P, pb->selector, (const T *)q, masks_in, (T *)w.F,
                                   masks_out, s);
   else
     e = launch_faces_euler1d<T>(ln, P, pb->selector, (const T *)q, masks_in, (T *)w.F, masks_out,
-                                s);
+                                w.evals, s);
   if (e != hipSuccess) return NENO6_HIP_ERROR;
   e = launch_diff1d<T>(ln, nvar_of(pb->equation), (const T *)w.F, (const T *)q, (T *)rhs, st,
                        status, s);
   return hip_status(e);
+}
+
+FastArgs fast_args(const neno6_problem *pb, const neno6_mlp *mlp, const Work &w) {
+  FastArgs fa;
+  fa.equation = pb->equation;
+  fa.precision = pb->precision;
+  fa.selector = pb->selector;
+  fa.prepared = mlp ? mlp->prepared : nullptr;
+  fa.margin = mlp ? mlp->recheck_margin : 0.f;
+  fa.scr = w.scr;
+  return fa;
+}
+
+// Per-call setup enqueued before the first kernel of an entry point: the
+// face -> line map of a 1D batch and the re-check counters.
+int32_t begin_call(const neno6_problem *pb, const neno6_mlp *mlp, const Work &w, hipStream_t s) {
+  if (pb->equation != NENO6_EULER2D && launch_build_fmap(line_of(pb), w.fmap, s) != hipSuccess)
+    return NENO6_HIP_ERROR;
+  if (pb->precision >= NENO6_BF16 && launch_fast_reset(fast_args(pb, mlp, w), s) != hipSuccess)
+    return NENO6_HIP_ERROR;
+  return NENO6_OK;
 }
 
 const float *prepared_f32(const neno6_mlp *mlp) {
@@ -194,7 +225,7 @@ int32_t rhs_dispatch(const neno6_problem *pb, const neno6_mlp *mlp, const void *
       return hip_status(launch_fast_rhs2d(g, fa, (const float *)q, (float *)rhs, masks_in,
                                           masks_out, status, (float *)w.F, (float *)w.G, st, s));
     }
-    return hip_status(launch_fast_rhs1d(line_of(pb), fa, (const float *)q, (float *)rhs, masks_in,
+    return hip_status(launch_fast_rhs1d(line_of(pb, w.fmap), fa, (const float *)q, (float *)rhs, masks_in,
                                         masks_out, status, (float *)w.F, st, s));
   }
   }
@@ -283,6 +314,7 @@ int32_t neno6_rhs(const neno6_problem *prob, const neno6_mlp *mlp, const void *q
   if (prob->selector == NENO6_SEL_MASKS_IN && !masks_in) return NENO6_BAD_ARG;
   const Work w = carve_work(prob, ws);
   if (ws_bytes < w.bytes) return NENO6_WORKSPACE_SMALL;
+  if (int32_t c = begin_call(prob, mlp, w, stream)) return c;
   return rhs_dispatch(prob, mlp, q, rhs, masks_in, masks_out, status, w, nullptr, stream);
 }
 
@@ -294,6 +326,7 @@ int32_t neno6_face_fluxes(const neno6_problem *prob, const neno6_mlp *mlp, const
   if (!q || !F || !ws) return NENO6_BAD_ARG;
   const Work w = carve_work(prob, ws);
   if (ws_bytes < w.bytes) return NENO6_WORKSPACE_SMALL;
+  if (int32_t c = begin_call(prob, mlp, w, stream)) return c;
   const bool is2d = prob->equation == NENO6_EULER2D;
   const size_t nfx = is2d ? 4 * (size_t)(prob->nx + 1) * prob->ny : 0;
   hipError_t e;
@@ -307,7 +340,7 @@ int32_t neno6_face_fluxes(const neno6_problem *prob, const neno6_mlp *mlp, const
     fa.scr = w.scr;
     e = is2d ? launch_fast_faces2d(grid_of(prob), fa, (const float *)q, nullptr, masks_out,
                                    (float *)F, (float *)F + nfx, stream)
-             : launch_fast_faces1d(line_of(prob), fa, (const float *)q, nullptr, masks_out,
+             : launch_fast_faces1d(line_of(prob, w.fmap), fa, (const float *)q, nullptr, masks_out,
                                    (float *)F, stream);
     return hip_status(e);
   }
@@ -318,27 +351,38 @@ int32_t neno6_face_fluxes(const neno6_problem *prob, const neno6_mlp *mlp, const
     if (is2d)
       e = launch_faces_euler2d<double>(grid_of(prob), P, prob->selector, (const double *)q, mx, mx,
                                        (double *)F, (double *)F + nfx, masks_out,
-                                       masks_out ? masks_out + nfx : nullptr, stream);
+                                       masks_out ? masks_out + nfx : nullptr, w.evals, stream);
     else if (nv == 1)
-      e = launch_faces_advection<double>(line_of(prob), P, prob->selector, (const double *)q, mx,
+      e = launch_faces_advection<double>(line_of(prob, w.fmap), P, prob->selector, (const double *)q, mx,
                                          (double *)F, masks_out, stream);
     else
-      e = launch_faces_euler1d<double>(line_of(prob), P, prob->selector, (const double *)q, mx,
-                                       (double *)F, masks_out, stream);
+      e = launch_faces_euler1d<double>(line_of(prob, w.fmap), P, prob->selector, (const double *)q, mx,
+                                       (double *)F, masks_out, w.evals, stream);
   } else {
     const float *P = prepared_f32(mlp);
     if (is2d)
       e = launch_faces_euler2d<float>(grid_of(prob), P, prob->selector, (const float *)q, mx, mx,
                                       (float *)F, (float *)F + nfx, masks_out,
-                                      masks_out ? masks_out + nfx : nullptr, stream);
+                                      masks_out ? masks_out + nfx : nullptr, w.evals, stream);
     else if (nv == 1)
-      e = launch_faces_advection<float>(line_of(prob), P, prob->selector, (const float *)q, mx,
+      e = launch_faces_advection<float>(line_of(prob, w.fmap), P, prob->selector, (const float *)q, mx,
                                         (float *)F, masks_out, stream);
     else
-      e = launch_faces_euler1d<float>(line_of(prob), P, prob->selector, (const float *)q, mx,
-                                      (float *)F, masks_out, stream);
+      e = launch_faces_euler1d<float>(line_of(prob, w.fmap), P, prob->selector, (const float *)q, mx,
+                                      (float *)F, masks_out, w.evals, stream);
   }
   return hip_status(e);
+}
+
+int32_t neno6_recheck_count(const neno6_problem *prob, const void *ws, size_t ws_bytes,
+                            uint32_t *count, hipStream_t stream) {
+  if (int32_t c = check_problem(prob)) return c;
+  if (!ws || !count) return NENO6_BAD_ARG;
+  if (prob->precision < NENO6_BF16) return NENO6_BAD_LAYOUT;
+  const Work w = carve_work(prob, (void *)ws);
+  if (ws_bytes < w.bytes) return NENO6_WORKSPACE_SMALL;
+  if (hipStreamSynchronize(stream) != hipSuccess) return NENO6_HIP_ERROR;
+  return hip_status(hipMemcpy(count, w.scr.qcount, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost));
 }
 
 int32_t neno6_step(const neno6_problem *prob, const neno6_mlp *mlp, void *q, double cfl,
@@ -350,6 +394,7 @@ int32_t neno6_step(const neno6_problem *prob, const neno6_mlp *mlp, void *q, dou
   if (!q || !t || !status || !ws || n_steps < 0 || !(cfl > 0)) return NENO6_BAD_ARG;
   const Work w = carve_work(prob, ws);
   if (ws_bytes < w.bytes) return NENO6_WORKSPACE_SMALL;
+  if (int32_t c = begin_call(prob, mlp, w, stream)) return c;
   const bool f64 = prob->precision == NENO6_FP64;
   for (int32_t it = 0; it < n_steps; ++it) {
     hipError_t e;
@@ -358,7 +403,7 @@ int32_t neno6_step(const neno6_problem *prob, const neno6_mlp *mlp, void *q, dou
       e = f64 ? launch_cfl2d<double>(g, (const double *)q, cfl, w.part, w.dt, status, t, stream)
               : launch_cfl2d<float>(g, (const float *)q, cfl, w.part, w.dt, status, t, stream);
     } else {
-      const Line1D ln = line_of(prob);
+      const Line1D ln = line_of(prob, w.fmap);
       e = f64 ? launch_cfl1d<double>(ln, prob->equation, (const double *)q, cfl, w.dt, status, t,
                                      stream)
               : launch_cfl1d<float>(ln, prob->equation, (const float *)q, cfl, w.dt, status, t,

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "neno6_internal.h"
+
 #define N6_DEV __device__ __forceinline__
 
 namespace n6 {
@@ -164,6 +166,12 @@ N6_DEV int find_problem(const int64_t *__restrict__ offsets, int np, int64_t g, 
       hi = mid - 1;
   }
   return lo;
+}
+
+// Line of face g: one load from the face map when it was built for this
+// call, else a binary search over the offsets.
+N6_DEV int line_of_face(const Line1D &ln, int64_t g) {
+  return ln.fmap ? ln.fmap[g] : find_problem(ln.offsets, ln.np, g, 1);
 }
 
 template <typename T> N6_DEV T sqrt_(T x);

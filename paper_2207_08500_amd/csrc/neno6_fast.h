@@ -11,7 +11,7 @@ struct FastScratch {
   uint8_t *masks;       // [nvar][faces] (1D) or x|y masks (2D), when the caller passes none
   uint32_t *queue;      // re-check entries: face * 8 + (field * 2 + sign)
   uint8_t *qflag;       // per entry: label changed by the FP32 re-check
-  uint32_t *qcount;     // [1] entries in the queue (cleared by a kernel each call)
+  uint32_t *qcount;     // [2] entries in the queue, per sweep direction
   int64_t qcap;         // queue capacity
 };
 
@@ -32,6 +32,9 @@ hipError_t launch_fast_reconstruct(const void *prepared, int precision, float ma
                                    const float *f, int64_t n_faces, int sign, int selector,
                                    const uint8_t *masks_in, float *fhat, uint8_t *masks_out,
                                    hipStream_t s);
+// Clears the re-check counters at the start of an API call (afterwards each
+// stage's flux-difference kernel clears them for the next stage).
+hipError_t launch_fast_reset(const FastArgs &fa, hipStream_t s);
 // Face fluxes with the MFMA classifier (+ re-check when the margin is > 0).
 hipError_t launch_fast_faces1d(const Line1D &ln, const FastArgs &fa, const float *q,
                                const uint8_t *masks_in, uint8_t *masks_out, float *F,

@@ -195,9 +195,7 @@ N6_DEV u32 mask_near(const float z[4], float margin) {
 // call it together).  Returns the lane's mask | near-flag << 4; with z != 0
 // also returns the lane's four logits.
 template <int PREC>
-N6_DEV u32 classify_wave(const Wts &w, const float s[6], float margin, float *z_out) {
-  u32 x0, x1, y0;
-  feature_pack<PREC>(s, x0, x1, y0);
+N6_DEV u32 classify_packed(const Wts &w, u32 x0, u32 x1, u32 y0, float margin, float *z_out) {
   u32 y1 = one_zero<PREC>();
   swap32(x0, y0);  // x0: tile 0 (faces of lanes 0..31), y0: tile 1
   swap32(x1, y1);
@@ -222,6 +220,13 @@ N6_DEV u32 classify_wave(const Wts &w, const float s[6], float margin, float *z_
   return m0;
 }
 
+template <int PREC>
+N6_DEV u32 classify_wave(const Wts &w, const float s[6], float margin, float *z_out) {
+  u32 x0, x1, y0;
+  feature_pack<PREC>(s, x0, x1, y0);
+  return classify_packed<PREC>(w, x0, x1, y0, margin, z_out);
+}
+
 N6_DEV const float *uniform_f32(const void *prepared) {
   const uint64_t v = (uint64_t)prepared;
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -239,7 +244,7 @@ N6_DEV unsigned classify_f32(const void *prepared, const float s[6]) {
 // and the right eigenvectors R.
 N6_DEV void setup1d(const Line1D &ln, const float *__restrict__ q, int64_t g, float s[6][6],
                     float R[3][3]) {
-  const int p = find_problem(ln.offsets, ln.np, g, 1);
+  const int p = line_of_face(ln, g);
   const int64_t o = ln.offsets[p], n = ln.offsets[p + 1] - o, k = g - o - p;
   const float gm = (float)ln.gamma, g1 = gm - 1.f;
   float qs[6][3], lam[6][3], F[6][3];
@@ -408,77 +413,56 @@ N6_DEV void enqueue(bool want, u32 entry, u32 *__restrict__ queue, u32 *__restri
   if (want && (int64_t)(base + off) < qcap) queue[base + off] = entry;
 }
 
-// ---- fused face kernels ---------------------------------------------------------
-template <int PREC>
-__global__ void __launch_bounds__(TPB)
-k_fast_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float margin,
-               const float *__restrict__ q, const uint8_t *__restrict__ min,
-               float *__restrict__ Fh, uint8_t *__restrict__ masks, u32 *__restrict__ queue,
-               u32 *__restrict__ qcount, int64_t qcap) {
-  const int lane = threadIdx.x & 63;
-  const int64_t tf = ln.faces();
-  const int64_t nchunk = (tf + 63) / 64;
-  Wts w;
-  if (selector == 0) load_wts<PREC>(prepared, lane, w);
-  for (int64_t ch = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6); ch < nchunk;
-       ch += (int64_t)gridDim.x * WPB) {
-    const int64_t g = ch * 64 + lane;
-    const bool valid = g < tf;
-    const int64_t gc = valid ? g : tf - 1;
-    float s[6][6], R[3][3];
-    setup1d(ln, q, gc, s, R);
-    u32 sel[6];
-#pragma unroll
-    for (int e = 0; e < 6; ++e) {
-      if (selector == 0) {
-        const u32 mk = classify_wave<PREC>(w, s[e], margin, nullptr);
-        sel[e] = mk & 15u;
-        enqueue(valid && (mk & 16u), (u32)(gc * 8 + e), queue, qcount, qcap);
-      } else if (selector == 1) {
-        sel[e] = 15u;
-      } else if (selector == 2) {
-        sel[e] = 0u;
-      } else {
-        sel[e] = (min[(e >> 1) * tf + gc] >> ((e & 1) * 4)) & 15u;
-      }
-    }
-    float hs[3], Fo[3];
-#pragma unroll
-    for (int m = 0; m < 3; ++m)
-      hs[m] = combine_fast(s[2 * m], sel[2 * m]) + combine_fast(s[2 * m + 1], sel[2 * m + 1]);
-    back_project<3>(R, hs, Fo);
-    if (valid) {
-#pragma unroll
-      for (int r = 0; r < 3; ++r) Fh[r * tf + g] = Fo[r];
-#pragma unroll
-      for (int m = 0; m < 3; ++m) masks[m * tf + g] = (uint8_t)(sel[2 * m] | (sel[2 * m + 1] << 4));
-    }
-  }
-}
-
-template <int PREC>
-__global__ void __launch_bounds__(TPB)
-k_fast_euler2d(Grid2D gd, int dir, int selector, const void *__restrict__ prepared, float margin,
-               const float *__restrict__ q, const uint8_t *__restrict__ min,
-               float *__restrict__ Fh, uint8_t *__restrict__ masks, u32 *__restrict__ queue,
-               u32 *__restrict__ qcount, int64_t qcap) {
-  const int lane = threadIdx.x & 63;
-  const int64_t nf = dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1);
+// ---- fused face kernel ------------------------------------------------------------
+// NV = 3: faces of a batch of 1D lines; NV = 4: faces of one 2D sweep.
+// One lane per face, 64 consecutive faces per wave and iteration.  The split
+// stencils and R of the lane's face wait in LDS (a lane-private slot, no
+// barrier) while the classifier runs, so that the live registers during the
+// MFMA phase are the weights, the packed features and one pair of tiles.
+template <int PREC, int NV>
+__global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2)))
+k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict__ prepared,
+             float margin, const float *__restrict__ q, const uint8_t *__restrict__ min,
+             float *__restrict__ Fh, uint8_t *__restrict__ masks, u32 *__restrict__ queue,
+             u32 *__restrict__ qcount, int64_t qcap) {
+  constexpr int NE = 2 * NV;
+  constexpr int NS = NE * 6 + NV * NV;
+  __shared__ float stash[WPB][NS][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t nf = NV == 3 ? ln.faces() : (dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1));
   const int64_t nchunk = (nf + 63) / 64;
   Wts w;
   if (selector == 0) load_wts<PREC>(prepared, lane, w);
-  for (int64_t ch = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6); ch < nchunk;
-       ch += (int64_t)gridDim.x * WPB) {
+  for (int64_t ch = (int64_t)blockIdx.x * WPB + wv; ch < nchunk; ch += (int64_t)gridDim.x * WPB) {
     const int64_t f = ch * 64 + lane;
     const bool valid = f < nf;
     const int64_t fc = valid ? f : nf - 1;
-    float s[8][6], R[4][4];
-    setup2d(gd, dir, q, fc, s, R);
-    u32 sel[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    u32 fx[NE][3];
+    {
+      float s[NE][6], R[NV][NV];
+      if constexpr (NV == 3)
+        setup1d(ln, q, fc, s, R);
+      else
+        setup2d(gd, dir, q, fc, s, R);
       if (selector == 0) {
-        const u32 mk = classify_wave<PREC>(w, s[e], margin, nullptr);
+#pragma unroll
+        for (int e = 0; e < NE; ++e) feature_pack<PREC>(s[e], fx[e][0], fx[e][1], fx[e][2]);
+      }
+#pragma unroll
+      for (int e = 0; e < NE; ++e)
+#pragma unroll
+        for (int j = 0; j < 6; ++j) stash[wv][e * 6 + j][lane] = s[e][j];
+#pragma unroll
+      for (int a = 0; a < NV; ++a)
+#pragma unroll
+        for (int b = 0; b < NV; ++b) stash[wv][NE * 6 + a * NV + b][lane] = R[a][b];
+    }
+    u32 sel[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      if (selector == 0) {
+        __builtin_amdgcn_sched_barrier(0);
+        const u32 mk = classify_packed<PREC>(w, fx[e][0], fx[e][1], fx[e][2], margin, nullptr);
         sel[e] = mk & 15u;
         enqueue(valid && (mk & 16u), (u32)(fc * 8 + e), queue, qcount, qcap);
       } else if (selector == 1) {
@@ -489,16 +473,28 @@ k_fast_euler2d(Grid2D gd, int dir, int selector, const void *__restrict__ prepar
         sel[e] = (min[(e >> 1) * nf + fc] >> ((e & 1) * 4)) & 15u;
       }
     }
-    float hs[4], Fo[4];
+    __builtin_amdgcn_sched_barrier(0);
+    float hs[NV], Fo[NV], R[NV][NV];
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
-      hs[m] = combine_fast(s[2 * m], sel[2 * m]) + combine_fast(s[2 * m + 1], sel[2 * m + 1]);
-    back_project<4>(R, hs, Fo);
+    for (int m = 0; m < NV; ++m) {
+      float sp[6], sm[6];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        sp[j] = stash[wv][(2 * m) * 6 + j][lane];
+        sm[j] = stash[wv][(2 * m + 1) * 6 + j][lane];
+      }
+      hs[m] = combine_fast(sp, sel[2 * m]) + combine_fast(sm, sel[2 * m + 1]);
+    }
+#pragma unroll
+    for (int a = 0; a < NV; ++a)
+#pragma unroll
+      for (int b = 0; b < NV; ++b) R[a][b] = stash[wv][NE * 6 + a * NV + b][lane];
+    back_project<NV>(R, hs, Fo);
     if (valid) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Fh[r * nf + f] = Fo[r];
+      for (int r = 0; r < NV; ++r) Fh[r * nf + f] = Fo[r];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) masks[m * nf + f] = (uint8_t)(sel[2 * m] | (sel[2 * m + 1] << 4));
+      for (int m = 0; m < NV; ++m) masks[m * nf + f] = (uint8_t)(sel[2 * m] | (sel[2 * m + 1] << 4));
     }
   }
 }
@@ -523,7 +519,15 @@ k_recheck(Line1D ln, Grid2D gd, int dir, const void *__restrict__ prepared,
     } else {
       setup2d(gd, dir, q, f, s, R);
     }
-    const u32 sel32 = classify_f32(prepared, s[e]);
+    float se[6];  // the queued stencil, selected without a dynamic register index
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      float v = s[0][j];
+#pragma unroll
+      for (int k = 1; k < 2 * (DIM == 1 ? 3 : 4); ++k) v = e == k ? s[k][j] : v;
+      se[j] = v;
+    }
+    const u32 sel32 = classify_f32(prepared, se);
     const int64_t mi = (int64_t)(e >> 1) * nf + f;
     const u32 shift = (u32)((mi & 3) * 8 + (e & 1) * 4);
     u32 *word = (u32 *)(masks + (mi & ~(int64_t)3));
@@ -599,7 +603,7 @@ k_fast_scalar(int mode, Line1D ln, const void *__restrict__ prepared, float marg
 #pragma unroll
       for (int j = 0; j < 6; ++j) s[j] = sign > 0 ? src[kc + j] : src[kc + 5 - j];
     } else if (mode == 1) {
-      const int p = find_problem(ln.offsets, ln.np, kc, 1);
+      const int p = line_of_face(ln, kc);
       const int64_t o = ln.offsets[p], nn = ln.offsets[p + 1] - o, kk = kc - o - p;
 #pragma unroll
       for (int j = 0; j < 6; ++j) s[j] = src[o + ghost(kk - 3 + j, nn, ln.bc)];
@@ -631,7 +635,11 @@ k_fast_scalar(int mode, Line1D ln, const void *__restrict__ prepared, float marg
   }
 }
 
-__global__ void k_zero_u32(u32 *p) { *p = 0u; }
+// Clears the two re-check counters (one per sweep direction).
+__global__ void k_zero_u32(u32 *p) {
+  p[0] = 0u;
+  p[1] = 0u;
+}
 
 __global__ void __launch_bounds__(TPB) k_copy_u8(const uint8_t *__restrict__ a, uint8_t *__restrict__ b, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) b[i] = a[i];
@@ -762,15 +770,19 @@ hipError_t launch_fast_faces1d(const Line1D &ln, const FastArgs &fa, const float
   }
   // The re-check flips labels with 32-bit atomics, so the classifier writes
   // into the workspace buffer (whole words) and the caller's copy follows.
+  // The re-check counter (qcount[0]) was cleared at the start of the call or
+  // by the previous stage's flux-difference kernel.
   masks = fa.scr.masks;
   const bool recheck = fa.selector == 0 && fa.margin > 0.f;
-  if (recheck) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, fa.scr.qcount);
+  const Grid2D g0{};
   if (fa.precision == 2)
-    hipLaunchKernelGGL(k_fast_euler1d<2>, dim3(grid), dim3(TPB), 0, s, ln, fa.selector, fa.prepared,
-                       fa.margin, q, masks_in, F, masks, fa.scr.queue, fa.scr.qcount, fa.scr.qcap);
+    hipLaunchKernelGGL((k_fast_faces<2, 3>), dim3(grid), dim3(TPB), 0, s, ln, g0, 0, fa.selector,
+                       fa.prepared, fa.margin, q, masks_in, F, masks, fa.scr.queue, fa.scr.qcount,
+                       fa.scr.qcap);
   else
-    hipLaunchKernelGGL(k_fast_euler1d<3>, dim3(grid), dim3(TPB), 0, s, ln, fa.selector, fa.prepared,
-                       fa.margin, q, masks_in, F, masks, fa.scr.queue, fa.scr.qcount, fa.scr.qcap);
+    hipLaunchKernelGGL((k_fast_faces<3, 3>), dim3(grid), dim3(TPB), 0, s, ln, g0, 0, fa.selector,
+                       fa.prepared, fa.margin, q, masks_in, F, masks, fa.scr.queue, fa.scr.qcount,
+                       fa.scr.qcap);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (recheck) {
@@ -790,7 +802,14 @@ hipError_t launch_fast_rhs1d(const Line1D &ln, const FastArgs &fa, const float *
                              float *F, const Stage *st, hipStream_t s) {
   hipError_t e = launch_fast_faces1d(ln, fa, q, masks_in, masks_out, F, s);
   if (e != hipSuccess) return e;
-  return launch_diff1d<float>(ln, fa.equation == 0 ? 1 : 3, F, q, rhs, st, status, s);
+  return launch_diff1d<float>(ln, fa.equation == 0 ? 1 : 3, F, q, rhs, st, status, s,
+                              fa.scr.qcount);
+}
+
+hipError_t launch_fast_reset(const FastArgs &fa, hipStream_t s) {
+  if (!(fa.selector == 0 && fa.margin > 0.f) || !fa.scr.qcount) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, fa.scr.qcount);
+  return hipGetLastError();
 }
 
 hipError_t launch_fast_faces2d(const Grid2D &g, const FastArgs &fa, const float *q,
@@ -805,23 +824,21 @@ hipError_t launch_fast_faces2d(const Grid2D &g, const FastArgs &fa, const float 
     const uint8_t *mi = masks_in ? masks_in + (dir == 0 ? 0 : 4 * nfx) : nullptr;
     float *Fd = dir == 0 ? Fx : Gy;
     const unsigned grid = grid_for((nf + 63) / 64);
-    if (recheck) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, fa.scr.qcount);
+    u32 *qc = fa.scr.qcount + dir;  // one counter per sweep direction
+    const Line1D l0{};
     if (fa.precision == 2)
-      hipLaunchKernelGGL(k_fast_euler2d<2>, dim3(grid), dim3(TPB), 0, s, g, dir, fa.selector,
-                         fa.prepared, fa.margin, q, mi, Fd, md, fa.scr.queue, fa.scr.qcount,
-                         fa.scr.qcap);
+      hipLaunchKernelGGL((k_fast_faces<2, 4>), dim3(grid), dim3(TPB), 0, s, l0, g, dir, fa.selector,
+                         fa.prepared, fa.margin, q, mi, Fd, md, fa.scr.queue, qc, fa.scr.qcap);
     else
-      hipLaunchKernelGGL(k_fast_euler2d<3>, dim3(grid), dim3(TPB), 0, s, g, dir, fa.selector,
-                         fa.prepared, fa.margin, q, mi, Fd, md, fa.scr.queue, fa.scr.qcount,
-                         fa.scr.qcap);
+      hipLaunchKernelGGL((k_fast_faces<3, 4>), dim3(grid), dim3(TPB), 0, s, l0, g, dir, fa.selector,
+                         fa.prepared, fa.margin, q, mi, Fd, md, fa.scr.queue, qc, fa.scr.qcap);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (recheck) {
-      Line1D ln{};
-      hipLaunchKernelGGL(k_recheck<2>, dim3(RECHECK_BLOCKS), dim3(TPB), 0, s, ln, g, dir, fa.prepared,
-                         q, md, fa.scr.queue, fa.scr.qcount, fa.scr.qcap, fa.scr.qflag);
-      hipLaunchKernelGGL(k_fixup<2>, dim3(RECHECK_BLOCKS), dim3(TPB), 0, s, ln, g, dir, q, md,
-                         fa.scr.queue, fa.scr.qcount, fa.scr.qcap, fa.scr.qflag, Fd);
+      hipLaunchKernelGGL(k_recheck<2>, dim3(RECHECK_BLOCKS), dim3(TPB), 0, s, l0, g, dir, fa.prepared,
+                         q, md, fa.scr.queue, qc, fa.scr.qcap, fa.scr.qflag);
+      hipLaunchKernelGGL(k_fixup<2>, dim3(RECHECK_BLOCKS), dim3(TPB), 0, s, l0, g, dir, q, md,
+                         fa.scr.queue, qc, fa.scr.qcap, fa.scr.qflag, Fd);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
@@ -835,7 +852,7 @@ hipError_t launch_fast_rhs2d(const Grid2D &g, const FastArgs &fa, const float *q
                              float *Fx, float *Gy, const Stage *st, hipStream_t s) {
   hipError_t e = launch_fast_faces2d(g, fa, q, masks_in, masks_out, Fx, Gy, s);
   if (e != hipSuccess) return e;
-  return launch_diff2d<float>(g, Fx, Gy, q, rhs, st, status, s);
+  return launch_diff2d<float>(g, Fx, Gy, q, rhs, st, status, s, fa.scr.qcount);
 }
 
 }  // namespace n6

@@ -17,7 +17,11 @@ struct Line1D {            // a batch of independent 1D lines
   __host__ __device__ int64_t faces() const { return total + np; }
   int32_t bc;
   double gamma;
+  const int32_t *fmap = nullptr;  // [dev] line of every face, or null (binary search)
 };
+
+// Fills fmap[g] = line of face g for every face of the batch.
+hipError_t launch_build_fmap(const Line1D &ln, int32_t *fmap, hipStream_t s);
 
 struct Grid2D {
   int64_t nx, ny;
@@ -51,29 +55,37 @@ template <typename T>
 hipError_t launch_faces_advection(const Line1D &ln, const T *P, int selector, const T *u,
                                   const uint8_t *masks_in, T *Fhat, uint8_t *masks_out,
                                   hipStream_t s);
+// evals: scratch of plain_eval_bytes(6, faces, sizeof(T)) bytes.
 template <typename T>
 hipError_t launch_faces_euler1d(const Line1D &ln, const T *P, int selector, const T *q,
-                                const uint8_t *masks_in, T *Fhat, uint8_t *masks_out,
+                                const uint8_t *masks_in, T *Fhat, uint8_t *masks_out, void *evals,
                                 hipStream_t s);
+// Scratch of the plain Euler face kernels: one value and one mask per
+// evaluation.
+size_t plain_eval_bytes(int nevals, int64_t faces, size_t elem);
 // Flux difference (and, with st != nullptr, the RK3 stage update) of 1D lines;
 // writes rhs (st == nullptr) or the stage output; sets status for cells that
 // are not physical when status_out != nullptr.
+// zero_after (may be null): two counters the kernel clears once it has run.
 template <typename T>
 hipError_t launch_diff1d(const Line1D &ln, int nvar, const T *Fhat, const T *q, T *rhs,
-                         const Stage *st, int32_t *status_out, hipStream_t s);
+                         const Stage *st, int32_t *status_out, hipStream_t s,
+                         uint32_t *zero_after = nullptr);
 // Per-line time step and status check at the start of a step; t += dt.
 template <typename T>
 hipError_t launch_cfl1d(const Line1D &ln, int equation, const T *q, double cfl, double *dt,
                         int32_t *status, double *t, hipStream_t s);
 
 // 2D: x faces [4][ny][nx+1], y faces [4][ny+1][nx].
+// evals: scratch of plain_eval_bytes(8, max(x faces, y faces), sizeof(T)).
 template <typename T>
 hipError_t launch_faces_euler2d(const Grid2D &g, const T *P, int selector, const T *q,
                                 const uint8_t *mx_in, const uint8_t *my_in, T *Fx, T *Gy,
-                                uint8_t *mx_out, uint8_t *my_out, hipStream_t s);
+                                uint8_t *mx_out, uint8_t *my_out, void *evals, hipStream_t s);
 template <typename T>
 hipError_t launch_diff2d(const Grid2D &g, const T *Fx, const T *Gy, const T *q, T *rhs,
-                         const Stage *st, int32_t *status_out, hipStream_t s);
+                         const Stage *st, int32_t *status_out, hipStream_t s,
+                         uint32_t *zero_after = nullptr);
 // Grid-wide time step: partial maxima in `part` (>= cfl2d_parts() doubles x 2).
 int cfl2d_parts();
 template <typename T>

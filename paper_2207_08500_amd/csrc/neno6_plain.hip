@@ -1,10 +1,20 @@
-// Plain NENO6 kernels: one lane per face (or per stencil), the classifier
-// evaluated on the vector units with the canonical fma order.
+// Plain NENO6 kernels: the classifier on the vector units with the canonical
+// fma order, one lane per classifier evaluation.
 //
-// Instantiated for double -- the FP64 path, whose classification labels are
-// bit-identical to the FP64 reference implementation because this file is
-// compiled with -ffp-contract=off and every fma is written out -- and for
-// float (the FP32 vector-unit path, also the re-check path of BF16/FP16).
+// Instantiated for double -- the FP64 path, whose classification labels and
+// values are bit-identical to the FP64 reference implementation because this
+// file is compiled with -ffp-contract=off and every fma is written out -- and
+// for float (the FP32 vector-unit path).
+//
+// Face fluxes of the Euler equations take two kernels: k_evals_* gives one
+// lane to each (face, characteristic field, split sign) -- the field and sign
+// are uniform across a block -- which reconstructs that one stencil; k_back_*
+// adds the two signs of every field and back-projects with R.  The classifier
+// weights are staged once per block in LDS, transposed so that the network
+// runs input-stationary: the loop over a layer's inputs is outermost and all
+// of the layer's accumulators advance together, which keeps ~100 FP64
+// registers live while every accumulator still sees bias first and then its
+// inputs in ascending order.
 #include "neno6_device.h"
 #include "neno6_internal.h"
 
@@ -14,29 +24,101 @@ namespace {
 
 constexpr int TPB = 256;
 
-template <typename T> N6_DEV const T *uniform_ptr(const T *p) {
-  // The classifier weights are the same for every lane; making the pointer
-  // wave-uniform lets the compiler fetch them with scalar loads.
-  const uint64_t v = (uint64_t)p;
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-  return (const T *)(((uint64_t)hi << 32) | lo);
-}
-
-// One classifier evaluation (Alg. 2 steps 1-2), kept out of line so that a
-// kernel with several evaluations per lane carries a single copy of the
-// 3104-fma network.
-template <typename T>
-__device__ __attribute__((noinline)) unsigned classify_call(const T *P, T s0, T s1, T s2, T s3,
-                                                            T s4, T s5) {
-  const T s[6] = {s0, s1, s2, s3, s4, s5};
-  return classify<T>(uniform_ptr<T>(P), s);
-}
+// LDS image of the parameters (values of type T):
+//   W1b [64][8]  (W1 row, b1, pad)   W2T [64][32]  b2 [32]
+//   W3T [32][16] b3 [16]   W4T [16][8] b4 [8]   W5T [8][4] b5 [4]
+constexpr int S_W1 = 0, S_W2 = 512, S_B2 = 2560, S_W3 = 2592, S_B3 = 3104, S_W4 = 3120,
+              S_B4 = 3248, S_W5 = 3256, S_B5 = 3288, S_SIZE = 3292;
 
 template <typename T>
-N6_DEV unsigned select_mask(int selector, const T *P, const T s[6], unsigned mask_in) {
+N6_DEV void stage_params(const T *__restrict__ P, T *S) {
+  for (int t = threadIdx.x; t < S_SIZE; t += blockDim.x) {
+    T v = T(0);
+    if (t < S_W2) {
+      const int o = t >> 3, k = t & 7;
+      v = k < 6 ? P[OW1 + o * 6 + k] : (k == 6 ? P[OB1 + o] : T(0));
+    } else if (t < S_B2) {
+      const int i = (t - S_W2) >> 5, o = (t - S_W2) & 31;
+      v = P[OW2 + o * 64 + i];
+    } else if (t < S_W3) {
+      v = P[OB2 + t - S_B2];
+    } else if (t < S_B3) {
+      const int i = (t - S_W3) >> 4, o = (t - S_W3) & 15;
+      v = P[OW3 + o * 32 + i];
+    } else if (t < S_W4) {
+      v = P[OB3 + t - S_B3];
+    } else if (t < S_B4) {
+      const int i = (t - S_W4) >> 3, o = (t - S_W4) & 7;
+      v = P[OW4 + o * 16 + i];
+    } else if (t < S_W5) {
+      v = P[OB4 + t - S_B4];
+    } else if (t < S_B5) {
+      const int i = (t - S_W5) >> 2, o = (t - S_W5) & 3;
+      v = P[OW5 + o * 8 + i];
+    } else {
+      v = P[OB5 + t - S_B5];
+    }
+    S[t] = v;
+  }
+}
+
+// The 6-64-32-16-8-4 network up to the logits, input-stationary, same
+// per-accumulator operation sequence as the reference (bias, then fma over
+// inputs in ascending order; ReLU as "x > 0 ? x : 0").
+template <typename T>
+N6_DEV void mlp_lean(const T *S, const T x0[6], T z[4]) {
+  T acc2[32];
+#pragma unroll
+  for (int o = 0; o < 32; ++o) acc2[o] = S[S_B2 + o];
+#pragma unroll 2
+  for (int i = 0; i < 64; ++i) {
+    T a = S[S_W1 + i * 8 + 6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a = fma_<T>(S[S_W1 + i * 8 + k], x0[k], a);
+    a = a > T(0) ? a : T(0);
+#pragma unroll
+    for (int o = 0; o < 32; ++o) acc2[o] = fma_<T>(S[S_W2 + i * 32 + o], a, acc2[o]);
+  }
+  T acc3[16];
+#pragma unroll
+  for (int o = 0; o < 16; ++o) acc3[o] = S[S_B3 + o];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    const T a = acc2[i] > T(0) ? acc2[i] : T(0);
+#pragma unroll
+    for (int o = 0; o < 16; ++o) acc3[o] = fma_<T>(S[S_W3 + i * 16 + o], a, acc3[o]);
+  }
+  T acc4[8];
+#pragma unroll
+  for (int o = 0; o < 8; ++o) acc4[o] = S[S_B4 + o];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const T a = acc3[i] > T(0) ? acc3[i] : T(0);
+#pragma unroll
+    for (int o = 0; o < 8; ++o) acc4[o] = fma_<T>(S[S_W4 + i * 8 + o], a, acc4[o]);
+  }
+#pragma unroll
+  for (int o = 0; o < 4; ++o) z[o] = S[S_B5 + o];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const T a = acc4[i] > T(0) ? acc4[i] : T(0);
+#pragma unroll
+    for (int o = 0; o < 4; ++o) z[o] = fma_<T>(S[S_W5 + i * 4 + o], a, z[o]);
+  }
+}
+
+template <typename T>
+N6_DEV unsigned classify_lean(const T *S, const T s[6]) {
+  T x[6], z[4];
+  features<T>(s, x);
+  mlp_lean<T>(S, x, z);
+  return mask_from_logits<T>(z);
+}
+
+template <typename T>
+N6_DEV unsigned select_mask(int selector, const T *S, const T s[6], unsigned mask_in) {
   switch (selector) {
-  case 0: return classify_call<T>(P, s[0], s[1], s[2], s[3], s[4], s[5]);
+  case 0: return classify_lean<T>(S, s);
   case 1: return 15u;
   case 2: return 0u;
   default: return mask_in & 15u;
@@ -48,12 +130,17 @@ __global__ void __launch_bounds__(TPB)
 k_reconstruct(const T *__restrict__ P, const T *__restrict__ f, int64_t n_faces, int sign,
               int selector, const uint8_t *__restrict__ min, T *__restrict__ fhat,
               uint8_t *__restrict__ mout) {
+  __shared__ T S[S_SIZE];
+  if (selector == 0) {
+    stage_params<T>(P, S);
+    __syncthreads();
+  }
   const int64_t k = blockIdx.x * (int64_t)TPB + threadIdx.x;
   if (k >= n_faces) return;
   T s[6];
 #pragma unroll
   for (int j = 0; j < 6; ++j) s[j] = sign > 0 ? f[k + j] : f[k + 5 - j];
-  const unsigned sel = select_mask<T>(selector, P, s, min ? min[k] : 0u);
+  const unsigned sel = select_mask<T>(selector, S, s, min ? min[k] : 0u);
   fhat[k] = combine_canonical<T>(s, sel);
   if (mout) mout[k] = (uint8_t)sel;
 }
@@ -62,13 +149,16 @@ template <typename T>
 __global__ void __launch_bounds__(TPB)
 k_mlp_logits(const T *__restrict__ P, const T *__restrict__ sten, int64_t n, T *__restrict__ z,
              uint8_t *__restrict__ masks) {
+  __shared__ T S[S_SIZE];
+  stage_params<T>(P, S);
+  __syncthreads();
   const int64_t e = blockIdx.x * (int64_t)TPB + threadIdx.x;
   if (e >= n) return;
   T s[6], x[6], zz[4];
 #pragma unroll
   for (int j = 0; j < 6; ++j) s[j] = sten[6 * e + j];
   features<T>(s, x);
-  mlp_logits<T>(uniform_ptr<T>(P), x, zz);
+  mlp_lean<T>(S, x, zz);
 #pragma unroll
   for (int k = 0; k < 4; ++k) z[4 * e + k] = zz[k];
   if (masks) masks[e] = (uint8_t)mask_from_logits<T>(zz);
@@ -81,90 +171,58 @@ template <typename T>
 __global__ void __launch_bounds__(TPB)
 k_faces_advection(Line1D ln, const T *__restrict__ P, int selector, const T *__restrict__ u,
                   const uint8_t *__restrict__ min, T *__restrict__ Fh, uint8_t *__restrict__ mout) {
+  __shared__ T S[S_SIZE];
+  if (selector == 0) {
+    stage_params<T>(P, S);
+    __syncthreads();
+  }
   const int64_t g = blockIdx.x * (int64_t)TPB + threadIdx.x;
   if (g >= ln.faces()) return;
-  const int p = find_problem(ln.offsets, ln.np, g, 1);
+  const int p = line_of_face(ln, g);
   const int64_t o = ln.offsets[p], n = ln.offsets[p + 1] - o, k = g - o - p;
   T s[6];
 #pragma unroll
   for (int j = 0; j < 6; ++j) s[j] = u[o + ghost(k - 3 + j, n, ln.bc)];
-  const unsigned sel = select_mask<T>(selector, P, s, min ? min[g] : 0u);
+  const unsigned sel = select_mask<T>(selector, S, s, min ? min[g] : 0u);
   Fh[g] = combine_canonical<T>(s, sel);
   if (mout) mout[g] = (uint8_t)sel;
 }
 
-// One face of a 1D Euler line from its six cells (Sec. 4.4): Roe
-// eigenvectors of cells i, i+1; projection of the six states and fluxes;
-// Rusanov split with alpha_m = max_j |lambda_m(q_j)|; NENO6 per field and
-// sign; back-projection R (h+ + h-).
-template <typename T>
-N6_DEV void euler1d_face(const T qs[6][3], T gamma, const T *P, int selector, const uint8_t *mi,
-                         int64_t mstride, T Fh[3], uint8_t *mo) {
-  T L[3][3], R[3][3];
-  roe1d<T>(qs[2], qs[3], gamma, L, R);
-  T v[6][3], g[6][3], lam[6][3];
+// Row m of L selected without a dynamic register index (m is block-uniform).
+template <typename T, int NV>
+N6_DEV void row_of(const T L[NV][NV], int m, T row[NV]) {
 #pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    T u, p, c, F[3];
-    prim1d<T>(qs[j], gamma, u, p, c);
-    flux1d<T>(qs[j], u, p, F);
-    lam[j][0] = u - c;
-    lam[j][1] = u;
-    lam[j][2] = u + c;
+  for (int r = 0; r < NV; ++r) {
+    T v = L[0][r];
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      T av = T(0), ag = T(0);
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        av = fma_<T>(L[m][r], qs[j][r], av);
-        ag = fma_<T>(L[m][r], F[r], ag);
-      }
-      v[j][m] = av;
-      g[j][m] = ag;
-    }
-  }
-  T hs[3];
-#pragma unroll
-  for (int m = 0; m < 3; ++m) {
-    T alpha = T(0);
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      const T a = abs_<T>(lam[j][m]);
-      alpha = a > alpha ? a : alpha;
-    }
-    T sp[6], sm[6];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      const T t = alpha * v[j][m];
-      sp[j] = T(0.5) * (g[j][m] + t);
-      sm[5 - j] = T(0.5) * (g[j][m] - t);
-    }
-    const unsigned in = mi ? mi[m * mstride] : 0u;
-    const unsigned selp = select_mask<T>(selector, P, sp, in & 15u);
-    const unsigned selm = select_mask<T>(selector, P, sm, (in >> 4) & 15u);
-    const T hp = combine_canonical<T>(sp, selp);
-    const T hm = combine_canonical<T>(sm, selm);
-    hs[m] = hp + hm;
-    if (mo) mo[m * mstride] = (uint8_t)(selp | (selm << 4));
-  }
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    T acc = T(0);
-#pragma unroll
-    for (int m = 0; m < 3; ++m) acc = fma_<T>(R[r][m], hs[m], acc);
-    Fh[r] = acc;
+    for (int k = 1; k < NV; ++k) v = m == k ? L[k][r] : v;
+    row[r] = v;
   }
 }
 
+// One evaluation of a 1D Euler face (Sec. 4.4): Roe eigenvectors of cells i,
+// i+1; projection of the six states and fluxes on field m; Rusanov split with
+// alpha_m = max_j |lambda_m(q_j)|; stencil of sign sgn (the '-' one mirrored);
+// classifier; re-normalised combine.  Writes h and the kept mask.
 template <typename T>
 __global__ void __launch_bounds__(TPB)
-k_faces_euler1d(Line1D ln, const T *__restrict__ P, int selector, const T *__restrict__ q,
-                const uint8_t *__restrict__ min, T *__restrict__ Fh, uint8_t *__restrict__ mout) {
+k_evals_euler1d(Line1D ln, const T *__restrict__ P, int selector, const T *__restrict__ q,
+                const uint8_t *__restrict__ min, int64_t tfpad, T *__restrict__ hbuf,
+                uint8_t *__restrict__ sbuf) {
+  __shared__ T S[S_SIZE];
+  if (selector == 0) {
+    stage_params<T>(P, S);
+    __syncthreads();
+  }
+  const int64_t idx = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  const int e = (int)(idx / tfpad);
+  const int64_t g = idx - e * tfpad;
   const int64_t tf = ln.faces();
-  const int64_t g = blockIdx.x * (int64_t)TPB + threadIdx.x;
-  if (g >= tf) return;
-  const int p = find_problem(ln.offsets, ln.np, g, 1);
+  if (e >= 6 || g >= tf) return;
+  const int m = e >> 1, sgn = e & 1;
+  const int p = line_of_face(ln, g);
   const int64_t o = ln.offsets[p], n = ln.offsets[p + 1] - o, k = g - o - p;
+  const T gamma = (T)ln.gamma;
   T qs[6][3];
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
@@ -172,11 +230,195 @@ k_faces_euler1d(Line1D ln, const T *__restrict__ P, int selector, const T *__res
 #pragma unroll
     for (int r = 0; r < 3; ++r) qs[j][r] = q[r * ln.total + ci];
   }
-  T F[3];
-  euler1d_face<T>(qs, (T)ln.gamma, P, selector, min ? min + g : nullptr, tf, F,
-                  mout ? mout + g : nullptr);
+  T L[3][3], R[3][3], Lm[3];
+  roe1d<T>(qs[2], qs[3], gamma, L, R);
+  row_of<T, 3>(L, m, Lm);
+  T v[6], gg[6], alpha = T(0);
 #pragma unroll
-  for (int r = 0; r < 3; ++r) Fh[r * tf + g] = F[r];
+  for (int j = 0; j < 6; ++j) {
+    T u, pr, c, F[3];
+    prim1d<T>(qs[j], gamma, u, pr, c);
+    flux1d<T>(qs[j], u, pr, F);
+    const T lam = m == 0 ? u - c : (m == 1 ? u : u + c);
+    const T a = abs_<T>(lam);
+    alpha = a > alpha ? a : alpha;
+    T av = T(0), ag = T(0);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      av = fma_<T>(Lm[r], qs[j][r], av);
+      ag = fma_<T>(Lm[r], F[r], ag);
+    }
+    v[j] = av;
+    gg[j] = ag;
+  }
+  T sp[6], sm[6], s[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const T t = alpha * v[j];
+    sp[j] = T(0.5) * (gg[j] + t);
+    sm[5 - j] = T(0.5) * (gg[j] - t);
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j) s[j] = sgn ? sm[j] : sp[j];
+  const unsigned in = min ? (min[m * tf + g] >> (4 * sgn)) & 15u : 0u;
+  const unsigned sel = select_mask<T>(selector, S, s, in);
+  hbuf[e * tf + g] = combine_canonical<T>(s, sel);
+  sbuf[e * tf + g] = (uint8_t)sel;
+}
+
+// Sum of the two signs per field and back-projection R (h+ + h-).
+template <typename T>
+__global__ void __launch_bounds__(TPB)
+k_back_euler1d(Line1D ln, const T *__restrict__ q, const T *__restrict__ hbuf,
+               const uint8_t *__restrict__ sbuf, T *__restrict__ Fh, uint8_t *__restrict__ mout) {
+  const int64_t tf = ln.faces();
+  const int64_t g = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  if (g >= tf) return;
+  const int p = line_of_face(ln, g);
+  const int64_t o = ln.offsets[p], n = ln.offsets[p + 1] - o, k = g - o - p;
+  T qL[3], qR[3];
+  const int64_t cL = o + ghost(k - 1, n, ln.bc), cR = o + ghost(k, n, ln.bc);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    qL[r] = q[r * ln.total + cL];
+    qR[r] = q[r * ln.total + cR];
+  }
+  T L[3][3], R[3][3];
+  roe1d<T>(qL, qR, (T)ln.gamma, L, R);
+  T hs[3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    hs[m] = hbuf[(2 * m) * tf + g] + hbuf[(2 * m + 1) * tf + g];
+    if (mout) mout[m * tf + g] = (uint8_t)(sbuf[(2 * m) * tf + g] | (sbuf[(2 * m + 1) * tf + g] << 4));
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    T acc = T(0);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) acc = fma_<T>(R[r][m], hs[m], acc);
+    Fh[r * tf + g] = acc;
+  }
+}
+
+// 2D: faces of one sweep, dir 0: [ny][nx+1], dir 1: [ny+1][nx].
+template <typename T>
+N6_DEV void load_stencil2d(const Grid2D &gd, int dir, const T *__restrict__ q, int64_t f,
+                           T qs[6][4]) {
+  const int64_t cells = gd.nx * gd.ny;
+  if (dir == 0) {
+    const int64_t y = f / (gd.nx + 1), k = f % (gd.nx + 1);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int64_t ci = y * gd.nx + ghost(k - 3 + j, gd.nx, gd.bc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) qs[j][r] = q[r * cells + ci];
+    }
+  } else {
+    const int64_t k = f / gd.nx, x = f % gd.nx;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int64_t ci = ghost(k - 3 + j, gd.ny, gd.bc) * gd.nx + x;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) qs[j][r] = q[r * cells + ci];
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB)
+k_evals_euler2d(Grid2D gd, int dir, const T *__restrict__ P, int selector, const T *__restrict__ q,
+                const uint8_t *__restrict__ min, int64_t nfpad, T *__restrict__ hbuf,
+                uint8_t *__restrict__ sbuf) {
+  __shared__ T S[S_SIZE];
+  if (selector == 0) {
+    stage_params<T>(P, S);
+    __syncthreads();
+  }
+  const int64_t nf = dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1);
+  const int64_t idx = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  const int e = (int)(idx / nfpad);
+  const int64_t f = idx - e * nfpad;
+  if (e >= 8 || f >= nf) return;
+  const int m = e >> 1, sgn = e & 1;
+  const T gamma = (T)gd.gamma;
+  T qs[6][4];
+  load_stencil2d<T>(gd, dir, q, f, qs);
+  T L[4][4], R[4][4], Lm[4];
+  roe2d<T>(qs[2], qs[3], gamma, dir, L, R);
+  row_of<T, 4>(L, m, Lm);
+  T v[6], gg[6], alpha = T(0);
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    T u, vv, pr, c, F[4];
+    prim2d<T>(qs[j], gamma, u, vv, pr, c);
+    flux2d<T>(qs[j], u, vv, pr, dir, F);
+    const T un = dir == 0 ? u : vv;
+    const T lam = m == 0 ? un - c : (m == 3 ? un + c : un);
+    const T a = abs_<T>(lam);
+    alpha = a > alpha ? a : alpha;
+    T av = T(0), ag = T(0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      av = fma_<T>(Lm[r], qs[j][r], av);
+      ag = fma_<T>(Lm[r], F[r], ag);
+    }
+    v[j] = av;
+    gg[j] = ag;
+  }
+  T sp[6], sm[6], s[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const T t = alpha * v[j];
+    sp[j] = T(0.5) * (gg[j] + t);
+    sm[5 - j] = T(0.5) * (gg[j] - t);
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j) s[j] = sgn ? sm[j] : sp[j];
+  const unsigned in = min ? (min[m * nf + f] >> (4 * sgn)) & 15u : 0u;
+  const unsigned sel = select_mask<T>(selector, S, s, in);
+  hbuf[e * nf + f] = combine_canonical<T>(s, sel);
+  sbuf[e * nf + f] = (uint8_t)sel;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB)
+k_back_euler2d(Grid2D gd, int dir, const T *__restrict__ q, const T *__restrict__ hbuf,
+               const uint8_t *__restrict__ sbuf, T *__restrict__ Fh, uint8_t *__restrict__ mout) {
+  const int64_t nf = dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1);
+  const int64_t f = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  if (f >= nf) return;
+  const int64_t cells = gd.nx * gd.ny;
+  int64_t cL, cR;
+  if (dir == 0) {
+    const int64_t y = f / (gd.nx + 1), k = f % (gd.nx + 1);
+    cL = y * gd.nx + ghost(k - 1, gd.nx, gd.bc);
+    cR = y * gd.nx + ghost(k, gd.nx, gd.bc);
+  } else {
+    const int64_t k = f / gd.nx, x = f % gd.nx;
+    cL = ghost(k - 1, gd.ny, gd.bc) * gd.nx + x;
+    cR = ghost(k, gd.ny, gd.bc) * gd.nx + x;
+  }
+  T qL[4], qR[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    qL[r] = q[r * cells + cL];
+    qR[r] = q[r * cells + cR];
+  }
+  T L[4][4], R[4][4];
+  roe2d<T>(qL, qR, (T)gd.gamma, dir, L, R);
+  T hs[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    hs[m] = hbuf[(2 * m) * nf + f] + hbuf[(2 * m + 1) * nf + f];
+    if (mout) mout[m * nf + f] = (uint8_t)(sbuf[(2 * m) * nf + f] | (sbuf[(2 * m + 1) * nf + f] << 4));
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    T acc = T(0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) acc = fma_<T>(R[r][m], hs[m], acc);
+    Fh[r * nf + f] = acc;
+  }
 }
 
 // RK3 stage update (Sec. 4.4, SSP-RK3):
@@ -194,12 +436,20 @@ N6_DEV T rk3(int stage, T us, T u0, T L, T dt) {
 template <typename T>
 __global__ void __launch_bounds__(TPB)
 k_diff1d(Line1D ln, int nvar, const T *__restrict__ Fh, const T *__restrict__ q,
-         T *__restrict__ rhs, Stage st, int has_stage, int32_t *__restrict__ status_out) {
-  const int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
-  if (i >= ln.total) return;
-  const int p = find_problem(ln.offsets, ln.np, i, 0);
-  const int64_t g = i + p;  // face to the left of cell i
+         T *__restrict__ rhs, Stage st, int has_stage, int32_t *__restrict__ status_out,
+         uint32_t *__restrict__ zero_after) {
+  if (zero_after && blockIdx.x == 0 && threadIdx.x == 0) {
+    zero_after[0] = 0u;
+    zero_after[1] = 0u;
+  }
+  // one lane per face g; the face to the left of cell i of line p is i + p,
+  // and the last face of every line has no cell to its right
   const int64_t tf = ln.faces();
+  const int64_t g = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  if (g >= tf) return;
+  const int p = line_of_face(ln, g);
+  const int64_t i = g - p;
+  if (i >= ln.offsets[p + 1]) return;
   const T dx = (T)ln.dx[p];
   if (status_out && nvar == 3) {
     const T qc[3] = {q[i], q[ln.total + i], q[2 * ln.total + i]};
@@ -269,106 +519,15 @@ k_cfl1d(Line1D ln, int equation, const T *__restrict__ q, double cfl, double *__
   }
 }
 
-// ---- 2D ---------------------------------------------------------------------
-template <typename T>
-N6_DEV void euler2d_face(const T qs[6][4], T gamma, int dir, const T *P, int selector,
-                         const uint8_t *mi, int64_t mstride, T Fh[4], uint8_t *mo) {
-  T L[4][4], R[4][4];
-  roe2d<T>(qs[2], qs[3], gamma, dir, L, R);
-  T v[6][4], g[6][4], lam[6][4];
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    T u, vv, p, c, F[4];
-    prim2d<T>(qs[j], gamma, u, vv, p, c);
-    flux2d<T>(qs[j], u, vv, p, dir, F);
-    const T un = dir == 0 ? u : vv;
-    lam[j][0] = un - c;
-    lam[j][1] = un;
-    lam[j][2] = un;
-    lam[j][3] = un + c;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      T av = T(0), ag = T(0);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        av = fma_<T>(L[m][r], qs[j][r], av);
-        ag = fma_<T>(L[m][r], F[r], ag);
-      }
-      v[j][m] = av;
-      g[j][m] = ag;
-    }
-  }
-  T hs[4];
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    T alpha = T(0);
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      const T a = abs_<T>(lam[j][m]);
-      alpha = a > alpha ? a : alpha;
-    }
-    T sp[6], sm[6];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      const T t = alpha * v[j][m];
-      sp[j] = T(0.5) * (g[j][m] + t);
-      sm[5 - j] = T(0.5) * (g[j][m] - t);
-    }
-    const unsigned in = mi ? mi[m * mstride] : 0u;
-    const unsigned selp = select_mask<T>(selector, P, sp, in & 15u);
-    const unsigned selm = select_mask<T>(selector, P, sm, (in >> 4) & 15u);
-    const T hp = combine_canonical<T>(sp, selp);
-    const T hm = combine_canonical<T>(sm, selm);
-    hs[m] = hp + hm;
-    if (mo) mo[m * mstride] = (uint8_t)(selp | (selm << 4));
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    T acc = T(0);
-#pragma unroll
-    for (int m = 0; m < 4; ++m) acc = fma_<T>(R[r][m], hs[m], acc);
-    Fh[r] = acc;
-  }
-}
-
-// dir 0: faces [ny][nx+1]; dir 1: faces [ny+1][nx].
-template <typename T>
-__global__ void __launch_bounds__(TPB)
-k_faces_euler2d(Grid2D gd, int dir, const T *__restrict__ P, int selector, const T *__restrict__ q,
-                const uint8_t *__restrict__ min, T *__restrict__ Fh, uint8_t *__restrict__ mout) {
-  const int64_t nf = dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1);
-  const int64_t f = blockIdx.x * (int64_t)TPB + threadIdx.x;
-  if (f >= nf) return;
-  const int64_t cells = gd.nx * gd.ny;
-  T qs[6][4];
-  if (dir == 0) {
-    const int64_t y = f / (gd.nx + 1), k = f % (gd.nx + 1);
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      const int64_t ci = y * gd.nx + ghost(k - 3 + j, gd.nx, gd.bc);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) qs[j][r] = q[r * cells + ci];
-    }
-  } else {
-    const int64_t k = f / gd.nx, x = f % gd.nx;
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      const int64_t ci = ghost(k - 3 + j, gd.ny, gd.bc) * gd.nx + x;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) qs[j][r] = q[r * cells + ci];
-    }
-  }
-  T F[4];
-  euler2d_face<T>(qs, (T)gd.gamma, dir, P, selector, min ? min + f : nullptr, nf, F,
-                  mout ? mout + f : nullptr);
-#pragma unroll
-  for (int r = 0; r < 4; ++r) Fh[r * nf + f] = F[r];
-}
-
 template <typename T>
 __global__ void __launch_bounds__(TPB)
 k_diff2d(Grid2D gd, const T *__restrict__ Fx, const T *__restrict__ Gy, const T *__restrict__ q,
-         T *__restrict__ rhs, Stage st, int has_stage, int32_t *__restrict__ status_out) {
+         T *__restrict__ rhs, Stage st, int has_stage, int32_t *__restrict__ status_out,
+         uint32_t *__restrict__ zero_after) {
+  if (zero_after && blockIdx.x == 0 && threadIdx.x == 0) {
+    zero_after[0] = 0u;
+    zero_after[1] = 0u;
+  }
   const int64_t cells = gd.nx * gd.ny;
   const int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
   if (i >= cells) return;
@@ -528,8 +687,21 @@ k_adjoint_advection(int64_t n, const double *__restrict__ dxp, int bc,
 }
 
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + TPB - 1) / TPB); }
+inline int64_t pad_to_block(int64_t n) { return (n + TPB - 1) / TPB * TPB; }
+
+// Face-flux scratch of the plain Euler path: h per evaluation, mask per
+// evaluation (NE x faces each).
+struct EvalBufs {
+  void *h;
+  uint8_t *sel;
+};
 
 }  // namespace
+
+size_t plain_eval_bytes(int nevals, int64_t faces, size_t elem) {
+  const size_t h = ((size_t)nevals * faces * elem + 255) & ~(size_t)255;
+  return h + (((size_t)nevals * faces + 255) & ~(size_t)255);
+}
 
 // ---- launchers --------------------------------------------------------------
 template <typename T>
@@ -562,19 +734,39 @@ hipError_t launch_faces_advection(const Line1D &ln, const T *P, int selector, co
 template <typename T>
 hipError_t launch_faces_euler1d(const Line1D &ln, const T *P, int selector, const T *q,
                                 const uint8_t *masks_in, T *Fhat, uint8_t *masks_out,
-                                hipStream_t s) {
-  hipLaunchKernelGGL(k_faces_euler1d<T>, dim3(nblocks(ln.faces())), dim3(TPB), 0, s, ln, P,
-                     selector, q, masks_in, Fhat, masks_out);
+                                void *evals, hipStream_t s) {
+  const int64_t tf = ln.faces(), tfpad = pad_to_block(tf);
+  T *h = (T *)evals;
+  uint8_t *sel = (uint8_t *)evals + ((6 * tf * sizeof(T) + 255) & ~(size_t)255);
+  hipLaunchKernelGGL(k_evals_euler1d<T>, dim3((unsigned)(6 * tfpad / TPB)), dim3(TPB), 0, s, ln, P,
+                     selector, q, masks_in, tfpad, h, sel);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_back_euler1d<T>, dim3(nblocks(tf)), dim3(TPB), 0, s, ln, q, h, sel, Fhat,
+                     masks_out);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_diff1d(const Line1D &ln, int nvar, const T *Fhat, const T *q, T *rhs,
-                         const Stage *st, int32_t *status_out, hipStream_t s) {
+                         const Stage *st, int32_t *status_out, hipStream_t s,
+                         uint32_t *zero_after) {
   Stage sv{};
   if (st) sv = *st;
-  hipLaunchKernelGGL(k_diff1d<T>, dim3(nblocks(ln.total)), dim3(TPB), 0, s, ln, nvar, Fhat, q,
-                     rhs, sv, st ? 1 : 0, status_out);
+  hipLaunchKernelGGL(k_diff1d<T>, dim3(nblocks(ln.faces())), dim3(TPB), 0, s, ln, nvar, Fhat, q,
+                     rhs, sv, st ? 1 : 0, status_out, zero_after);
+  return hipGetLastError();
+}
+
+// Face -> line map: one block per line writes the line index of its faces.
+__global__ void __launch_bounds__(TPB) k_build_fmap(Line1D ln, int32_t *__restrict__ fmap) {
+  const int p = blockIdx.x;
+  const int64_t a = ln.offsets[p] + p, b = ln.offsets[p + 1] + p + 1;
+  for (int64_t g = a + threadIdx.x; g < b; g += TPB) fmap[g] = p;
+}
+
+hipError_t launch_build_fmap(const Line1D &ln, int32_t *fmap, hipStream_t s) {
+  hipLaunchKernelGGL(k_build_fmap, dim3(ln.np), dim3(TPB), 0, s, ln, fmap);
   return hipGetLastError();
 }
 
@@ -589,24 +781,33 @@ hipError_t launch_cfl1d(const Line1D &ln, int equation, const T *q, double cfl, 
 template <typename T>
 hipError_t launch_faces_euler2d(const Grid2D &g, const T *P, int selector, const T *q,
                                 const uint8_t *mx_in, const uint8_t *my_in, T *Fx, T *Gy,
-                                uint8_t *mx_out, uint8_t *my_out, hipStream_t s) {
+                                uint8_t *mx_out, uint8_t *my_out, void *evals, hipStream_t s) {
   const int64_t nfx = (g.nx + 1) * g.ny, nfy = g.nx * (g.ny + 1);
-  hipLaunchKernelGGL(k_faces_euler2d<T>, dim3(nblocks(nfx)), dim3(TPB), 0, s, g, 0, P, selector,
-                     q, mx_in, Fx, mx_out);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_faces_euler2d<T>, dim3(nblocks(nfy)), dim3(TPB), 0, s, g, 1, P, selector,
-                     q, my_in, Gy, my_out);
-  return hipGetLastError();
+  const int64_t nmax = nfx > nfy ? nfx : nfy;
+  T *h = (T *)evals;
+  uint8_t *sel = (uint8_t *)evals + ((8 * nmax * sizeof(T) + 255) & ~(size_t)255);
+  for (int dir = 0; dir < 2; ++dir) {
+    const int64_t nf = dir == 0 ? nfx : nfy, nfpad = pad_to_block(nf);
+    hipLaunchKernelGGL(k_evals_euler2d<T>, dim3((unsigned)(8 * nfpad / TPB)), dim3(TPB), 0, s, g,
+                       dir, P, selector, q, dir == 0 ? mx_in : my_in, nfpad, h, sel);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_back_euler2d<T>, dim3(nblocks(nf)), dim3(TPB), 0, s, g, dir, q, h, sel,
+                       dir == 0 ? Fx : Gy, dir == 0 ? mx_out : my_out);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template <typename T>
 hipError_t launch_diff2d(const Grid2D &g, const T *Fx, const T *Gy, const T *q, T *rhs,
-                         const Stage *st, int32_t *status_out, hipStream_t s) {
+                         const Stage *st, int32_t *status_out, hipStream_t s,
+                         uint32_t *zero_after) {
   Stage sv{};
   if (st) sv = *st;
   hipLaunchKernelGGL(k_diff2d<T>, dim3(nblocks(g.nx * g.ny)), dim3(TPB), 0, s, g, Fx, Gy, q, rhs,
-                     sv, st ? 1 : 0, status_out);
+                     sv, st ? 1 : 0, status_out, zero_after);
   return hipGetLastError();
 }
 
@@ -647,16 +848,17 @@ hipError_t launch_params_to_f32(const double *P, float *P32, hipStream_t s) {
   template hipError_t launch_faces_advection<T>(const Line1D &, const T *, int, const T *,       \
                                                 const uint8_t *, T *, uint8_t *, hipStream_t);   \
   template hipError_t launch_faces_euler1d<T>(const Line1D &, const T *, int, const T *,         \
-                                              const uint8_t *, T *, uint8_t *, hipStream_t);     \
+                                              const uint8_t *, T *, uint8_t *, void *,           \
+                                              hipStream_t);                                      \
   template hipError_t launch_diff1d<T>(const Line1D &, int, const T *, const T *, T *,           \
-                                       const Stage *, int32_t *, hipStream_t);                   \
+                                       const Stage *, int32_t *, hipStream_t, uint32_t *);       \
   template hipError_t launch_cfl1d<T>(const Line1D &, int, const T *, double, double *,          \
                                       int32_t *, double *, hipStream_t);                         \
   template hipError_t launch_faces_euler2d<T>(const Grid2D &, const T *, int, const T *,         \
                                               const uint8_t *, const uint8_t *, T *, T *,        \
-                                              uint8_t *, uint8_t *, hipStream_t);                \
+                                              uint8_t *, uint8_t *, void *, hipStream_t);        \
   template hipError_t launch_diff2d<T>(const Grid2D &, const T *, const T *, const T *, T *,     \
-                                       const Stage *, int32_t *, hipStream_t);                   \
+                                       const Stage *, int32_t *, hipStream_t, uint32_t *);       \
   template hipError_t launch_cfl2d<T>(const Grid2D &, const T *, double, double *, double *,     \
                                       int32_t *, double *, hipStream_t);
 

@@ -27,7 +27,7 @@ NPARAM = 3228
 EXPORTS = (
     "neno6_status_string", "neno6_version", "neno6_mlp_prepared_bytes", "neno6_mlp_prepare",
     "neno6_mlp_logits", "neno6_reconstruct", "neno6_workspace_size", "neno6_rhs",
-    "neno6_face_fluxes", "neno6_step",
+    "neno6_face_fluxes", "neno6_recheck_count", "neno6_step",
     "neno6_rhs_adjoint", "neno6_train_workspace_size", "neno6_classifier_train",
     "neno6_classifier_grad",
 )
@@ -77,6 +77,7 @@ def load(path: str = LIB_PATH):
         lib.neno6_workspace_size.restype = sz
         lib.neno6_rhs.argtypes = [P(ProblemStruct), P(MlpStruct), vp, vp, vp, vp, vp, vp, sz, vp]
         lib.neno6_face_fluxes.argtypes = [P(ProblemStruct), P(MlpStruct), vp, vp, vp, vp, sz, vp]
+        lib.neno6_recheck_count.argtypes = [P(ProblemStruct), vp, sz, P(C.c_uint32), vp]
         lib.neno6_step.argtypes = [P(ProblemStruct), P(MlpStruct), vp, f64, i32, vp, vp, vp, sz, vp]
         lib.neno6_rhs_adjoint.argtypes = [P(ProblemStruct), vp, vp, vp, vp]
         lib.neno6_train_workspace_size.argtypes = [i32]
@@ -259,6 +260,15 @@ def neno6_face_fluxes(prob: Problem, mlp: Mlp | None, q: torch.Tensor, F: torch.
     ps = prob.struct()
     _check(load().neno6_face_fluxes(C.byref(ps), _mlp(mlp), _ptr(q), _ptr(F), _ptr(masks_out),
                                     _ptr(ws), ws.numel(), _stream(stream)), "neno6_face_fluxes")
+
+
+def neno6_recheck_count(prob: Problem, ws: torch.Tensor, stream=None):
+    """Evaluations re-checked in FP32 by the last neno6_face_fluxes call (x, y)."""
+    cnt = (C.c_uint32 * 2)()
+    ps = prob.struct()
+    _check(load().neno6_recheck_count(C.byref(ps), _ptr(ws), ws.numel(), cnt, _stream(stream)),
+           "neno6_recheck_count")
+    return int(cnt[0]), int(cnt[1])
 
 
 def neno6_step(prob: Problem, mlp: Mlp | None, q: torch.Tensor, cfl: float, n_steps: int,
