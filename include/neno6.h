@@ -100,8 +100,9 @@ typedef struct neno6_mlp {
  *    mask arrays are [field][total_cells + n_problems].
  *    ADVECTION uses var = field = 1 and only the '+' nibble (the '-' split
  *    flux is identically zero, so its nibble is reported as 0).
- *  2D (EULER2D): one nx x ny grid, SoA [4][ny][nx] (x fastest), spacings
- *    dx2d, dy2d; x-face masks [4][ny][nx+1], y-face masks [4][ny+1][nx]. */
+ *  2D (EULER2D): one nx x ny grid (nx, ny <= 2^20, nx * ny <= 2^28), SoA
+ *    [4][ny][nx] (x fastest), spacings dx2d, dy2d; x-face masks
+ *    [4][ny][nx+1], y-face masks [4][ny+1][nx]. */
 typedef struct neno6_problem {
   int32_t equation;
   int32_t bc;

@@ -51,7 +51,8 @@ int32_t check_problem(const neno6_problem *pb) {
   if (pb->equation == NENO6_EULER2D) {
     if (pb->nx < 1 || pb->ny < 1 || !(pb->dx2d > 0) || !(pb->dy2d > 0) || !(pb->gamma > 1))
       return NENO6_BAD_ARG;
-    if (pb->nx > (1 << 20) || pb->ny > (1 << 20)) return NENO6_BAD_ARG;
+    if (pb->nx > (1 << 20) || pb->ny > (1 << 20) || pb->nx * pb->ny > (int64_t(1) << 28))
+      return NENO6_BAD_ARG;  // in-grid indices are 32-bit
     return NENO6_OK;
   }
   if (pb->n_problems < 1 || !pb->offsets || !pb->offsets_host || !pb->dx) return NENO6_BAD_ARG;

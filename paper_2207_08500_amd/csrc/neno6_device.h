@@ -83,7 +83,7 @@ N6_DEV float combine_fast(const float s[6], unsigned sel) {
   const float w3 = (sel & 8u) ? Lin<float>::d3 : 0.f;
   const float D = (w0 + w1) + (w2 + w3);
   const float num = fmaf(w3, q3, fmaf(w2, q2, fmaf(w1, q1, w0 * q0)));
-  return (sel & 15u) ? num / D : s[2];
+  return (sel & 15u) ? num * __builtin_amdgcn_rcpf(D) : s[2];
 }
 
 // Input scaling of the classifier (eq. normalizainput): divide by
@@ -151,6 +151,17 @@ N6_DEV int64_t ghost(int64_t c, int64_t n, int bc) {
   if (bc == 0) {
     int64_t r = c % n;
     return r < 0 ? r + n : r;
+  }
+  return c < 0 ? 0 : (c > n - 1 ? n - 1 : c);
+}
+
+// The same in 32-bit arithmetic for indices within one line (c in
+// [-3, n + 2]); the periodic wrap needs at most three corrections.
+N6_DEV int ghost32(int c, int n, int bc) {
+  if (bc == 0) {
+    while (c < 0) c += n;
+    while (c >= n) c -= n;
+    return c;
   }
   return c < 0 ? 0 : (c > n - 1 ? n - 1 : c);
 }
@@ -298,6 +309,100 @@ N6_DEV void roe2d(const T qL[4], const T qR[4], T gamma, int dir, T L[4][4], T R
 template <typename T>
 N6_DEV bool physical(T rho, T p) {
   return rho > T(0) && p > T(0) && __builtin_isfinite(rho) && __builtin_isfinite(p);
+}
+
+// ---- classifier on the vector units, weights staged in LDS ------------------
+// LDS image of the parameters (values of type T):
+//   W1b [64][8]  (W1 row, b1, pad)   W2T [64][32]  b2 [32]
+//   W3T [32][16] b3 [16]   W4T [16][8] b4 [8]   W5T [8][4] b5 [4]
+constexpr int S_W1 = 0, S_W2 = 512, S_B2 = 2560, S_W3 = 2592, S_B3 = 3104, S_W4 = 3120,
+              S_B4 = 3248, S_W5 = 3256, S_B5 = 3288, S_SIZE = 3292;
+
+template <typename T>
+N6_DEV void stage_params(const T *__restrict__ P, T *S) {
+  for (int t = threadIdx.x; t < S_SIZE; t += blockDim.x) {
+    T v = T(0);
+    if (t < S_W2) {
+      const int o = t >> 3, k = t & 7;
+      v = k < 6 ? P[OW1 + o * 6 + k] : (k == 6 ? P[OB1 + o] : T(0));
+    } else if (t < S_B2) {
+      const int i = (t - S_W2) >> 5, o = (t - S_W2) & 31;
+      v = P[OW2 + o * 64 + i];
+    } else if (t < S_W3) {
+      v = P[OB2 + t - S_B2];
+    } else if (t < S_B3) {
+      const int i = (t - S_W3) >> 4, o = (t - S_W3) & 15;
+      v = P[OW3 + o * 32 + i];
+    } else if (t < S_W4) {
+      v = P[OB3 + t - S_B3];
+    } else if (t < S_B4) {
+      const int i = (t - S_W4) >> 3, o = (t - S_W4) & 7;
+      v = P[OW4 + o * 16 + i];
+    } else if (t < S_W5) {
+      v = P[OB4 + t - S_B4];
+    } else if (t < S_B5) {
+      const int i = (t - S_W5) >> 2, o = (t - S_W5) & 3;
+      v = P[OW5 + o * 8 + i];
+    } else {
+      v = P[OB5 + t - S_B5];
+    }
+    S[t] = v;
+  }
+}
+
+// The 6-64-32-16-8-4 network up to the logits, input-stationary (the loop
+// over a layer's inputs is outermost, all of the layer's accumulators
+// advance together), with the same per-accumulator operation sequence as the
+// output-stationary form: bias, then fma over the inputs in ascending order;
+// ReLU as "x > 0 ? x : 0".
+template <typename T>
+N6_DEV void mlp_lean(const T *S, const T x0[6], T z[4]) {
+  T acc2[32];
+#pragma unroll
+  for (int o = 0; o < 32; ++o) acc2[o] = S[S_B2 + o];
+#pragma unroll 2
+  for (int i = 0; i < 64; ++i) {
+    T a = S[S_W1 + i * 8 + 6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a = fma_<T>(S[S_W1 + i * 8 + k], x0[k], a);
+    a = a > T(0) ? a : T(0);
+#pragma unroll
+    for (int o = 0; o < 32; ++o) acc2[o] = fma_<T>(S[S_W2 + i * 32 + o], a, acc2[o]);
+  }
+  T acc3[16];
+#pragma unroll
+  for (int o = 0; o < 16; ++o) acc3[o] = S[S_B3 + o];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    const T a = acc2[i] > T(0) ? acc2[i] : T(0);
+#pragma unroll
+    for (int o = 0; o < 16; ++o) acc3[o] = fma_<T>(S[S_W3 + i * 16 + o], a, acc3[o]);
+  }
+  T acc4[8];
+#pragma unroll
+  for (int o = 0; o < 8; ++o) acc4[o] = S[S_B4 + o];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const T a = acc3[i] > T(0) ? acc3[i] : T(0);
+#pragma unroll
+    for (int o = 0; o < 8; ++o) acc4[o] = fma_<T>(S[S_W4 + i * 8 + o], a, acc4[o]);
+  }
+#pragma unroll
+  for (int o = 0; o < 4; ++o) z[o] = S[S_B5 + o];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const T a = acc4[i] > T(0) ? acc4[i] : T(0);
+#pragma unroll
+    for (int o = 0; o < 4; ++o) z[o] = fma_<T>(S[S_W5 + i * 4 + o], a, z[o]);
+  }
+}
+
+template <typename T>
+N6_DEV unsigned classify_lean(const T *S, const T s[6]) {
+  T x[6], z[4];
+  features<T>(s, x);
+  mlp_lean<T>(S, x, z);
+  return mask_from_logits<T>(z);
 }
 
 }  // namespace n6

@@ -53,6 +53,13 @@ hipError_t launch_fast_rhs2d(const Grid2D &g, const FastArgs &fa, const float *q
 // ---- training ----------------------------------------------------------------
 size_t train_workspace_bytes(int32_t batch);
 bool train_precision_supported(int precision);
+// BF16 MFMA gradient: per-wave partials part[train_mfma_waves(m)][3228] and
+// lpart; tabs: train_mfma_tab_bytes() of scratch for the operand tables.
+int train_mfma_waves(int64_t m);
+size_t train_mfma_tab_bytes();
+hipError_t launch_grad_mfma(const double *P, void *tabs, const float *s, const uint8_t *y,
+                            const int64_t *idx, int64_t m, float *part, double *lpart,
+                            hipStream_t st);
 hipError_t launch_train_batch(double *P, double *m, double *v, int64_t step, const float *s,
                               const uint8_t *y, const int64_t *idx, int64_t mb, double lr,
                               double b1, double b2, double eps, int precision, double *loss_out,

@@ -245,14 +245,17 @@ N6_DEV unsigned classify_f32(const void *prepared, const float s[6]) {
 N6_DEV void setup1d(const Line1D &ln, const float *__restrict__ q, int64_t g, float s[6][6],
                     float R[3][3]) {
   const int p = line_of_face(ln, g);
-  const int64_t o = ln.offsets[p], n = ln.offsets[p + 1] - o, k = g - o - p;
+  const int64_t o = ln.offsets[p];
+  const int n = (int)(ln.offsets[p + 1] - o), k = (int)(g - o - p);
   const float gm = (float)ln.gamma, g1 = gm - 1.f;
+  const float *qv0 = q + o, *qv1 = q + ln.total + o, *qv2 = q + 2 * ln.total + o;
   float qs[6][3], lam[6][3], F[6][3];
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
-    const int64_t ci = o + ghost(k - 3 + j, n, ln.bc);
-#pragma unroll
-    for (int r = 0; r < 3; ++r) qs[j][r] = q[r * ln.total + ci];
+    const int ci = ghost32(k - 3 + j, n, ln.bc);
+    qs[j][0] = qv0[ci];
+    qs[j][1] = qv1[ci];
+    qs[j][2] = qv2[ci];
   }
   float uu[6], pp[6], ir[6];
 #pragma unroll
@@ -308,21 +311,23 @@ N6_DEV void setup2d(const Grid2D &gd, int dir, const float *__restrict__ q, int6
   const int64_t cells = gd.nx * gd.ny;
   const float gm = (float)gd.gamma, g1 = gm - 1.f;
   float qs[6][4];
+  // 32-bit in-grid indices (the C ABI limits a grid to 2^28 cells)
+  const int nx = (int)gd.nx, ny = (int)gd.ny, ff = (int)f, c32 = (int)cells;
   if (dir == 0) {
-    const int64_t y = f / (gd.nx + 1), k = f - y * (gd.nx + 1);
+    const int y = ff / (nx + 1), k = ff - y * (nx + 1);
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-      const int64_t ci = y * gd.nx + ghost(k - 3 + j, gd.nx, gd.bc);
+      const int ci = y * nx + ghost32(k - 3 + j, nx, gd.bc);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) qs[j][r] = q[r * cells + ci];
+      for (int r = 0; r < 4; ++r) qs[j][r] = q[r * c32 + ci];
     }
   } else {
-    const int64_t k = f / gd.nx, x = f - k * gd.nx;
+    const int k = ff / nx, x = ff - k * nx;
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-      const int64_t ci = ghost(k - 3 + j, gd.ny, gd.bc) * gd.nx + x;
+      const int ci = ghost32(k - 3 + j, ny, gd.bc) * nx + x;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) qs[j][r] = q[r * cells + ci];
+      for (int r = 0; r < 4; ++r) qs[j][r] = q[r * c32 + ci];
     }
   }
   const int vn = dir == 0 ? 1 : 2, vs = dir == 0 ? 2 : 1;
@@ -508,6 +513,12 @@ k_recheck(Line1D ln, Grid2D gd, int dir, const void *__restrict__ prepared,
           const u32 *__restrict__ qcount, int64_t qcap, uint8_t *__restrict__ qflag) {
   const int64_t nq = (int64_t)*qcount < qcap ? (int64_t)*qcount : qcap;
   const int64_t nf = DIM == 1 ? ln.faces() : (dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1));
+  if (blockIdx.x * (int64_t)TPB >= nq) return;  // block-uniform: nothing queued for this block
+  // FP32 weights staged in LDS; the network runs input-stationary (32
+  // independent accumulators per lane instead of one serial chain)
+  __shared__ float S[S_SIZE];
+  stage_params<float>((const float *)prepared, S);
+  __syncthreads();
   for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < nq; i += (int64_t)gridDim.x * TPB) {
     const u32 ent = queue[i];
     const int64_t f = ent >> 3;
@@ -527,7 +538,7 @@ k_recheck(Line1D ln, Grid2D gd, int dir, const void *__restrict__ prepared,
       for (int k = 1; k < 2 * (DIM == 1 ? 3 : 4); ++k) v = e == k ? s[k][j] : v;
       se[j] = v;
     }
-    const u32 sel32 = classify_f32(prepared, se);
+    const u32 sel32 = classify_lean<float>(S, se);
     const int64_t mi = (int64_t)(e >> 1) * nf + f;
     const u32 shift = (u32)((mi & 3) * 8 + (e & 1) * 4);
     u32 *word = (u32 *)(masks + (mi & ~(int64_t)3));
@@ -712,7 +723,328 @@ inline unsigned grid_for(int64_t items_per_wave_chunks) {
 
 constexpr unsigned RECHECK_BLOCKS = 512;
 
+// ---- classifier training on MFMA (BF16, FP32 accumulation) ------------------
+// Tiles of 32 samples per wave, persistent over the mini-batch.  Forward: the
+// inference tiles (activations kept, as packed BF16, for the backward pass).
+// Backward: delta_{l-1} = (W_l^T delta_l) o [h_{l-1} > 0] on MFMA with the
+// transposed weights as the A operand, K order permuted exactly like the
+// forward chaining, so deltas stay in the lanes.  Weight gradients
+// dW_l = sum over samples of delta_l h_{l-1}^T are MFMA products with K =
+// samples: delta and activation tiles go through a lane-private LDS transpose
+// ([neuron][sample], BF16), 16 samples per instruction.  Bias gradients of
+// L2..L5 are lane sums reduced across the 32 lanes of each half at the end;
+// b1 comes out of the L1 product through the constant input slot.
+constexpr int BT_REGS = 24;  // backward A tables: L5 2, L4 2, L3 4, L2 16
+
+__global__ void __launch_bounds__(TPB) k_prepare_bwd(const double *__restrict__ P, u32 *__restrict__ tab) {
+  const int t = blockIdx.x * TPB + threadIdx.x;
+  if (t >= BT_REGS * 64) return;
+  const int reg = t / 64, lane = t % 64, i = lane % 32, h = lane / 32;
+  float v[2];
+  for (int q2 = 0; q2 < 2; ++q2) {
+    double x = 0.0;
+    if (reg < 2) {  // L5^T, 32x32x8: K slot 4h + e = output neuron of L5
+      const int e = 2 * reg + q2, k = 4 * h + e;
+      x = (k < 4 && i < 8) ? P[OW5 + k * 8 + i] : 0.0;
+    } else if (reg < 4) {  // L4^T, 32x32x8
+      const int e = 2 * (reg - 2) + q2, k = 4 * h + e;
+      x = (i < 16) ? P[OW4 + k * 16 + i] : 0.0;
+    } else if (reg < 8) {  // L3^T, 32x32x16: K slot = L3 output row 8(e/4)+4h+e%4
+      const int e = 2 * (reg - 4) + q2, n3 = 8 * (e / 4) + 4 * h + e % 4;
+      x = P[OW3 + n3 * 32 + i];
+    } else {  // L2^T, output tile t (L1 neurons 32t..32t+31), K step s
+      const int r = reg - 8, tt = r / 8, s = (r % 8) / 4, e = 2 * (r % 4) + q2;
+      const int n2 = 8 * (2 * s + e / 4) + 4 * h + e % 4;
+      x = P[OW2 + n2 * 64 + 32 * tt + i];
+    }
+    v[q2] = (float)x;
+  }
+  tab[reg * 64 + lane] = pack2<2>(v[0], v[1]);
+}
+
+// Writes rows [0, nrows) of a C-layout FP32 tile (lane (j, h), register r =
+// row 8(r/4) + 4h + r%4) as BF16 into T[row][j].
+N6_DEV void tile_to_lds(const f32x16 &c, int nrows, int row0, __bf16 (*T)[32], int j, int h) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = 8 * (r / 4) + 4 * h + r % 4;
+    if (row < nrows) T[row0 + row][j] = (__bf16)c[r];
+  }
+}
+// Same for a packed BF16 tile (registers p hold C registers 2p, 2p+1).
+template <int NPACKED>
+N6_DEV void packed_to_lds(const u32 *hp, int nrows, int row0, __bf16 (*T)[32], int j, int h) {
+#pragma unroll
+  for (int p = 0; p < NPACKED; ++p) {
+    const bf16x2 v = __builtin_bit_cast(bf16x2, hp[p]);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int r = 2 * p + q, row = 8 * (r / 4) + 4 * h + r % 4;
+      if (row < nrows) T[row0 + row][j] = v[q];
+    }
+  }
+}
+// MFMA operand of 8 consecutive samples of one neuron: rows >= nrows are zero.
+N6_DEV u32x4 lds_operand(__bf16 (*T)[32], int row, int nrows, int k0) {
+  if (row >= nrows) return u32x4{0u, 0u, 0u, 0u};
+  return *(const u32x4 *)&T[row][k0];
+}
+N6_DEV float bf16_pos(u32 packed, int half) {  // ReLU derivative of a stored activation
+  const bf16x2 v = __builtin_bit_cast(bf16x2, packed);
+  return (float)v[half] > 0.f ? 1.f : 0.f;
+}
+
+__global__ void __launch_bounds__(TPB)
+k_grad_mfma(const void *__restrict__ prepared, const u32 *__restrict__ btab,
+            const float *__restrict__ s, const uint8_t *__restrict__ y,
+            const int64_t *__restrict__ idx, int64_t m, float inv_m, int nwaves,
+            float *__restrict__ part, double *__restrict__ lpart) {
+  __shared__ __attribute__((aligned(16))) __bf16 Td[WPB][64][32];
+  __shared__ __attribute__((aligned(16))) __bf16 Ta[WPB][64][32];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, j = lane & 31, h = lane >> 5;
+  const int wid = blockIdx.x * WPB + wv;
+  Wts w;
+  load_wts<2>(prepared, lane, w);
+  u32x2 bt5, bt4;
+  u32x4 bt3, bt2[2][2];
+  bt5 = u32x2{btab[0 * 64 + lane], btab[1 * 64 + lane]};
+  bt4 = u32x2{btab[2 * 64 + lane], btab[3 * 64 + lane]};
+  bt3 = u32x4{btab[4 * 64 + lane], btab[5 * 64 + lane], btab[6 * 64 + lane], btab[7 * 64 + lane]};
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      const int b = 8 + 8 * t + 4 * st;
+      bt2[t][st] = u32x4{btab[(b + 0) * 64 + lane], btab[(b + 1) * 64 + lane],
+                         btab[(b + 2) * 64 + lane], btab[(b + 3) * 64 + lane]};
+    }
+  const f32x16 zero = {};
+  f32x16 g1a = zero, g1b = zero, g2a = zero, g2b = zero, g3 = zero, g4 = zero, g5 = zero;
+  float db2[16], db3[8], db4[4], db5[4], lsum = 0.f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) db2[r] = 0.f;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) db3[r] = 0.f;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) db4[r] = db5[r] = 0.f;
+  const int64_t ntile = (m + 31) / 32;
+  for (int64_t tile = wid; tile < ntile; tile += nwaves) {
+    const int64_t smp = tile * 32 + j;
+    const bool valid = smp < m;
+    float x[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    unsigned lab = 0;
+    if (valid) {
+      const int64_t id = idx ? idx[smp] : smp;
+      float st6[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) st6[k] = s[6 * id + k];
+      features<float>(st6, x);
+      lab = y[id];
+    }
+    const float one = valid ? 1.f : 0.f;
+    const u32x2 bin = h == 0 ? u32x2{pack2<2>(x[0], x[1]), pack2<2>(x[2], x[3])}
+                             : u32x2{pack2<2>(x[4], x[5]), pack2<2>(one, 0.f)};
+    // forward
+    const f32x16 c1a = mma8<2>(w.a1[0], bin, zero);
+    const f32x16 c1b = mma8<2>(w.a1[1], bin, zero);
+    u32 h1a[8], h1b[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      h1a[p] = relu_pack<2>(c1a[2 * p], c1a[2 * p + 1]);
+      h1b[p] = relu_pack<2>(c1b[2 * p], c1b[2 * p + 1]);
+    }
+    f32x16 c2 = mma16<2>(w.a2[0], u32x4{h1a[0], h1a[1], h1a[2], h1a[3]}, w.b2);
+    c2 = mma16<2>(w.a2[1], u32x4{h1a[4], h1a[5], h1a[6], h1a[7]}, c2);
+    c2 = mma16<2>(w.a2[2], u32x4{h1b[0], h1b[1], h1b[2], h1b[3]}, c2);
+    c2 = mma16<2>(w.a2[3], u32x4{h1b[4], h1b[5], h1b[6], h1b[7]}, c2);
+    u32 h2[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) h2[p] = relu_pack<2>(c2[2 * p], c2[2 * p + 1]);
+    f32x16 c3 = mma16<2>(w.a3[0], u32x4{h2[0], h2[1], h2[2], h2[3]}, w.b3);
+    c3 = mma16<2>(w.a3[1], u32x4{h2[4], h2[5], h2[6], h2[7]}, c3);
+    u32 h3[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) h3[p] = relu_pack<2>(c3[2 * p], c3[2 * p + 1]);
+    const f32x16 c4 = mma16<2>(w.a4, u32x4{h3[0], h3[1], h3[2], h3[3]}, w.b4);
+    u32 h4[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) h4[p] = relu_pack<2>(c4[2 * p], c4[2 * p + 1]);
+    const f32x16 c5 = mma16<2>(w.a5, u32x4{h4[0], h4[1], h4[2], h4[3]}, zero);
+    // loss and output deltas (lanes of the first half hold the four logits)
+    float d5[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float z = c5[k] + w.b5[k];
+      const float yk = (float)((lab >> k) & 1u);
+      const bool act = valid && h == 0;
+      const float sp = z > 0.f ? z + log1pf(expf(-z)) : log1pf(expf(z));  // softplus(z)
+      lsum += act ? 0.25f * (sp - yk * z) : 0.f;
+      d5[k] = act ? (1.f / (1.f + expf(-z)) - yk) * 0.25f * inv_m : 0.f;
+      db5[k] += d5[k];
+    }
+    // backward through L5 (K = 4 output neurons, 32x32x8)
+    const u32x2 D5 = u32x2{pack2<2>(d5[0], d5[1]), pack2<2>(d5[2], d5[3])};
+    const f32x16 e4 = mma8<2>(bt5, D5, zero);
+    float d4[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      d4[r] = e4[r] * bf16_pos(h4[r >> 1], r & 1);
+      db4[r] += d4[r];
+    }
+    const u32x2 D4 = u32x2{pack2<2>(d4[0], d4[1]), pack2<2>(d4[2], d4[3])};
+    const f32x16 e3 = mma8<2>(bt4, D4, zero);
+    float d3[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      d3[r] = e3[r] * bf16_pos(h3[r >> 1], r & 1);
+      db3[r] += d3[r];
+    }
+    const u32x4 D3 = u32x4{pack2<2>(d3[0], d3[1]), pack2<2>(d3[2], d3[3]), pack2<2>(d3[4], d3[5]),
+                           pack2<2>(d3[6], d3[7])};
+    const f32x16 e2 = mma16<2>(bt3, D3, zero);
+    f32x16 d2;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      d2[r] = e2[r] * bf16_pos(h2[r >> 1], r & 1);
+      db2[r] += d2[r];
+    }
+    const u32x4 D2a = u32x4{pack2<2>(d2[0], d2[1]), pack2<2>(d2[2], d2[3]), pack2<2>(d2[4], d2[5]),
+                            pack2<2>(d2[6], d2[7])};
+    const u32x4 D2b = u32x4{pack2<2>(d2[8], d2[9]), pack2<2>(d2[10], d2[11]),
+                            pack2<2>(d2[12], d2[13]), pack2<2>(d2[14], d2[15])};
+    f32x16 e1a = mma16<2>(bt2[0][0], D2a, zero);
+    e1a = mma16<2>(bt2[0][1], D2b, e1a);
+    f32x16 e1b = mma16<2>(bt2[1][0], D2a, zero);
+    e1b = mma16<2>(bt2[1][1], D2b, e1b);
+    f32x16 d1a, d1b, d5t = zero, d4t = zero, d3t = zero;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      d1a[r] = e1a[r] * bf16_pos(h1a[r >> 1], r & 1);
+      d1b[r] = e1b[r] * bf16_pos(h1b[r >> 1], r & 1);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      d5t[r] = d5[r];
+      d4t[r] = d4[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) d3t[r] = d3[r];
+    // weight gradients: transpose through LDS, K = 32 samples in two steps
+    __bf16(*TD)[32] = Td[wv];
+    __bf16(*TA)[32] = Ta[wv];
+    auto wgrad = [&](f32x16 &acc, int nout, int nin, int drow0, int arow0) {
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk) {
+        const u32x4 A = lds_operand(TD, drow0 + j, drow0 + nout, 16 * kk + 8 * h);
+        const u32x4 B = lds_operand(TA, arow0 + j, arow0 + nin, 16 * kk + 8 * h);
+        acc = mma16<2>(A, B, acc);
+      }
+    };
+    // L5 and L4: deltas rows 0..3 / 4..11, activations h4 rows 0..7 / h3 rows 8..23
+    tile_to_lds(d5t, 4, 0, TD, j, h);
+    tile_to_lds(d4t, 8, 4, TD, j, h);
+    packed_to_lds<4>(h4, 8, 0, TA, j, h);
+    packed_to_lds<4>(h3, 16, 8, TA, j, h);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    wgrad(g5, 4, 8, 0, 0);
+    wgrad(g4, 8, 16, 4, 8);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    // L3: delta3 rows 0..15, h2 rows 0..31
+    tile_to_lds(d3t, 16, 0, TD, j, h);
+    packed_to_lds<8>(h2, 32, 0, TA, j, h);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    wgrad(g3, 16, 32, 0, 0);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    // L2: delta2 rows 0..31, h1 rows 0..63 (two output-column tiles)
+    tile_to_lds(d2, 32, 0, TD, j, h);
+    packed_to_lds<8>(h1a, 32, 0, TA, j, h);
+    packed_to_lds<8>(h1b, 32, 32, TA, j, h);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    wgrad(g2a, 32, 32, 0, 0);
+    wgrad(g2b, 32, 32, 0, 32);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    // L1: delta1 rows 0..63, inputs x0..x5 and the constant slot (rows 0..6)
+    tile_to_lds(d1a, 32, 0, TD, j, h);
+    tile_to_lds(d1b, 32, 32, TD, j, h);
+    if (h == 0) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) TA[k][j] = (__bf16)x[k];
+      TA[6][j] = (__bf16)one;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    wgrad(g1a, 32, 7, 0, 0);
+    wgrad(g1b, 32, 7, 32, 0);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  }
+  // partial gradient of this wave in the parameter layout
+  float *gp = part + (int64_t)wid * NPARAM;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int o = 8 * (r / 4) + 4 * h + r % 4, in = j;
+    if (o < 4 && in < 8) gp[OW5 + o * 8 + in] = g5[r];
+    if (o < 8 && in < 16) gp[OW4 + o * 16 + in] = g4[r];
+    if (o < 16) gp[OW3 + o * 32 + in] = g3[r];
+    gp[OW2 + o * 64 + in] = g2a[r];
+    gp[OW2 + o * 64 + 32 + in] = g2b[r];
+    if (in < 6) {
+      gp[OW1 + o * 6 + in] = g1a[r];
+      gp[OW1 + (32 + o) * 6 + in] = g1b[r];
+    } else if (in == 6) {
+      gp[OB1 + o] = g1a[r];
+      gp[OB1 + 32 + o] = g1b[r];
+    }
+  }
+  // bias gradients: sum over the 32 samples of each lane half
+  auto half_sum = [&](float v) {
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+  };
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const float v = half_sum(db2[r]);
+    if (j == 0) gp[OB2 + 8 * (r / 4) + 4 * h + r % 4] = v;
+  }
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const float v = half_sum(db3[r]);
+    if (j == 0) gp[OB3 + 8 * (r / 4) + 4 * h + r % 4] = v;
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const float v4 = half_sum(db4[r]);
+    if (j == 0) gp[OB4 + 4 * h + r] = v4;
+    const float v5 = half_sum(db5[r]);
+    if (j == 0 && h == 0) gp[OB5 + r] = v5;
+  }
+  float l = lsum;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off);
+  if (lane == 0) lpart[wid] = (double)l;
+}
+
 }  // namespace
+
+// Gradient partials of one mini-batch on MFMA: one partial per wave.
+int train_mfma_waves(int64_t m) {
+  const int64_t t = (m + 31) / 32;
+  const int64_t nw = t < 512 ? t : 512;
+  return (int)((nw + WPB - 1) / WPB * WPB);
+}
+size_t train_mfma_tab_bytes() { return PREP_BYTES + BT_REGS * 64 * 4; }
+
+hipError_t launch_grad_mfma(const double *P, void *tabs, const float *s, const uint8_t *y,
+                            const int64_t *idx, int64_t m, float *part, double *lpart,
+                            hipStream_t st) {
+  char *prep = (char *)tabs;
+  u32 *btab = (u32 *)(prep + PREP_BYTES);
+  hipLaunchKernelGGL(k_prepare, dim3((TAB_REGS * 64 + TPB - 1) / TPB), dim3(TPB), 0, st, P, prep);
+  hipLaunchKernelGGL(k_prepare_bwd, dim3((BT_REGS * 64 + TPB - 1) / TPB), dim3(TPB), 0, st, P, btab);
+  const int nw = train_mfma_waves(m);
+  hipLaunchKernelGGL(k_grad_mfma, dim3(nw / WPB), dim3(TPB), 0, st, prep, btab, s, y, idx, m,
+                     (float)(1.0 / (double)m), nw, part, lpart);
+  return hipGetLastError();
+}
 
 size_t fast_prepared_bytes() { return PREP_BYTES; }
 const void *fast_prepared_f32(const void *prepared) { return prepared; }

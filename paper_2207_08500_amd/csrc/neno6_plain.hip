@@ -24,97 +24,6 @@ namespace {
 
 constexpr int TPB = 256;
 
-// LDS image of the parameters (values of type T):
-//   W1b [64][8]  (W1 row, b1, pad)   W2T [64][32]  b2 [32]
-//   W3T [32][16] b3 [16]   W4T [16][8] b4 [8]   W5T [8][4] b5 [4]
-constexpr int S_W1 = 0, S_W2 = 512, S_B2 = 2560, S_W3 = 2592, S_B3 = 3104, S_W4 = 3120,
-              S_B4 = 3248, S_W5 = 3256, S_B5 = 3288, S_SIZE = 3292;
-
-template <typename T>
-N6_DEV void stage_params(const T *__restrict__ P, T *S) {
-  for (int t = threadIdx.x; t < S_SIZE; t += blockDim.x) {
-    T v = T(0);
-    if (t < S_W2) {
-      const int o = t >> 3, k = t & 7;
-      v = k < 6 ? P[OW1 + o * 6 + k] : (k == 6 ? P[OB1 + o] : T(0));
-    } else if (t < S_B2) {
-      const int i = (t - S_W2) >> 5, o = (t - S_W2) & 31;
-      v = P[OW2 + o * 64 + i];
-    } else if (t < S_W3) {
-      v = P[OB2 + t - S_B2];
-    } else if (t < S_B3) {
-      const int i = (t - S_W3) >> 4, o = (t - S_W3) & 15;
-      v = P[OW3 + o * 32 + i];
-    } else if (t < S_W4) {
-      v = P[OB3 + t - S_B3];
-    } else if (t < S_B4) {
-      const int i = (t - S_W4) >> 3, o = (t - S_W4) & 7;
-      v = P[OW4 + o * 16 + i];
-    } else if (t < S_W5) {
-      v = P[OB4 + t - S_B4];
-    } else if (t < S_B5) {
-      const int i = (t - S_W5) >> 2, o = (t - S_W5) & 3;
-      v = P[OW5 + o * 8 + i];
-    } else {
-      v = P[OB5 + t - S_B5];
-    }
-    S[t] = v;
-  }
-}
-
-// The 6-64-32-16-8-4 network up to the logits, input-stationary, same
-// per-accumulator operation sequence as the reference (bias, then fma over
-// inputs in ascending order; ReLU as "x > 0 ? x : 0").
-template <typename T>
-N6_DEV void mlp_lean(const T *S, const T x0[6], T z[4]) {
-  T acc2[32];
-#pragma unroll
-  for (int o = 0; o < 32; ++o) acc2[o] = S[S_B2 + o];
-#pragma unroll 2
-  for (int i = 0; i < 64; ++i) {
-    T a = S[S_W1 + i * 8 + 6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) a = fma_<T>(S[S_W1 + i * 8 + k], x0[k], a);
-    a = a > T(0) ? a : T(0);
-#pragma unroll
-    for (int o = 0; o < 32; ++o) acc2[o] = fma_<T>(S[S_W2 + i * 32 + o], a, acc2[o]);
-  }
-  T acc3[16];
-#pragma unroll
-  for (int o = 0; o < 16; ++o) acc3[o] = S[S_B3 + o];
-#pragma unroll
-  for (int i = 0; i < 32; ++i) {
-    const T a = acc2[i] > T(0) ? acc2[i] : T(0);
-#pragma unroll
-    for (int o = 0; o < 16; ++o) acc3[o] = fma_<T>(S[S_W3 + i * 16 + o], a, acc3[o]);
-  }
-  T acc4[8];
-#pragma unroll
-  for (int o = 0; o < 8; ++o) acc4[o] = S[S_B4 + o];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const T a = acc3[i] > T(0) ? acc3[i] : T(0);
-#pragma unroll
-    for (int o = 0; o < 8; ++o) acc4[o] = fma_<T>(S[S_W4 + i * 8 + o], a, acc4[o]);
-  }
-#pragma unroll
-  for (int o = 0; o < 4; ++o) z[o] = S[S_B5 + o];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const T a = acc4[i] > T(0) ? acc4[i] : T(0);
-#pragma unroll
-    for (int o = 0; o < 4; ++o) z[o] = fma_<T>(S[S_W5 + i * 4 + o], a, z[o]);
-  }
-}
-
-template <typename T>
-N6_DEV unsigned classify_lean(const T *S, const T s[6]) {
-  T x[6], z[4];
-  features<T>(s, x);
-  mlp_lean<T>(S, x, z);
-  return mask_from_logits<T>(z);
-}
-
 template <typename T>
 N6_DEV unsigned select_mask(int selector, const T *S, const T s[6], unsigned mask_in) {
   switch (selector) {
@@ -188,16 +97,77 @@ k_faces_advection(Line1D ln, const T *__restrict__ P, int selector, const T *__r
   if (mout) mout[g] = (uint8_t)sel;
 }
 
-// Row m of L selected without a dynamic register index (m is block-uniform).
-template <typename T, int NV>
-N6_DEV void row_of(const T L[NV][NV], int m, T row[NV]) {
+// Split stencil of characteristic field M and sign sgn ('-' mirrored) of a
+// 1D Euler face from its six cells: Roe eigenvectors of cells i, i+1,
+// projection of the six states and fluxes, Rusanov speed alpha_M =
+// max_j |lambda_M(q_j)|, s = (g +- alpha v)/2.
+template <typename T, int M>
+N6_DEV void stencil1d(const T qs[6][3], T gamma, int sgn, T s[6]) {
+  T L[3][3], R[3][3];
+  roe1d<T>(qs[2], qs[3], gamma, L, R);
+  T v[6], gg[6], alpha = T(0);
 #pragma unroll
-  for (int r = 0; r < NV; ++r) {
-    T v = L[0][r];
+  for (int j = 0; j < 6; ++j) {
+    T u, pr, c, F[3];
+    prim1d<T>(qs[j], gamma, u, pr, c);
+    flux1d<T>(qs[j], u, pr, F);
+    const T lam = M == 0 ? u - c : (M == 1 ? u : u + c);
+    const T a = abs_<T>(lam);
+    alpha = a > alpha ? a : alpha;
+    T av = T(0), ag = T(0);
 #pragma unroll
-    for (int k = 1; k < NV; ++k) v = m == k ? L[k][r] : v;
-    row[r] = v;
+    for (int r = 0; r < 3; ++r) {
+      av = fma_<T>(L[M][r], qs[j][r], av);
+      ag = fma_<T>(L[M][r], F[r], ag);
+    }
+    v[j] = av;
+    gg[j] = ag;
   }
+  T sp[6], sm[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const T t = alpha * v[j];
+    sp[j] = T(0.5) * (gg[j] + t);
+    sm[5 - j] = T(0.5) * (gg[j] - t);
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j) s[j] = sgn ? sm[j] : sp[j];
+}
+
+// Same for field M of a 2D sweep in direction dir (fields: u_n - c, u_n,
+// shear, u_n + c).
+template <typename T, int M>
+N6_DEV void stencil2d(const T qs[6][4], T gamma, int dir, int sgn, T s[6]) {
+  T L[4][4], R[4][4];
+  roe2d<T>(qs[2], qs[3], gamma, dir, L, R);
+  T v[6], gg[6], alpha = T(0);
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    T u, vv, pr, c, F[4];
+    prim2d<T>(qs[j], gamma, u, vv, pr, c);
+    flux2d<T>(qs[j], u, vv, pr, dir, F);
+    const T un = dir == 0 ? u : vv;
+    const T lam = M == 0 ? un - c : (M == 3 ? un + c : un);
+    const T a = abs_<T>(lam);
+    alpha = a > alpha ? a : alpha;
+    T av = T(0), ag = T(0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      av = fma_<T>(L[M][r], qs[j][r], av);
+      ag = fma_<T>(L[M][r], F[r], ag);
+    }
+    v[j] = av;
+    gg[j] = ag;
+  }
+  T sp[6], sm[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const T t = alpha * v[j];
+    sp[j] = T(0.5) * (gg[j] + t);
+    sm[5 - j] = T(0.5) * (gg[j] - t);
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j) s[j] = sgn ? sm[j] : sp[j];
 }
 
 // One evaluation of a 1D Euler face (Sec. 4.4): Roe eigenvectors of cells i,
@@ -230,36 +200,12 @@ k_evals_euler1d(Line1D ln, const T *__restrict__ P, int selector, const T *__res
 #pragma unroll
     for (int r = 0; r < 3; ++r) qs[j][r] = q[r * ln.total + ci];
   }
-  T L[3][3], R[3][3], Lm[3];
-  roe1d<T>(qs[2], qs[3], gamma, L, R);
-  row_of<T, 3>(L, m, Lm);
-  T v[6], gg[6], alpha = T(0);
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    T u, pr, c, F[3];
-    prim1d<T>(qs[j], gamma, u, pr, c);
-    flux1d<T>(qs[j], u, pr, F);
-    const T lam = m == 0 ? u - c : (m == 1 ? u : u + c);
-    const T a = abs_<T>(lam);
-    alpha = a > alpha ? a : alpha;
-    T av = T(0), ag = T(0);
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      av = fma_<T>(Lm[r], qs[j][r], av);
-      ag = fma_<T>(Lm[r], F[r], ag);
-    }
-    v[j] = av;
-    gg[j] = ag;
+  T s[6];
+  switch (m) {  // block-uniform: each case sees its field index at compile time
+  case 0: stencil1d<T, 0>(qs, gamma, sgn, s); break;
+  case 1: stencil1d<T, 1>(qs, gamma, sgn, s); break;
+  default: stencil1d<T, 2>(qs, gamma, sgn, s); break;
   }
-  T sp[6], sm[6], s[6];
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    const T t = alpha * v[j];
-    sp[j] = T(0.5) * (gg[j] + t);
-    sm[5 - j] = T(0.5) * (gg[j] - t);
-  }
-#pragma unroll
-  for (int j = 0; j < 6; ++j) s[j] = sgn ? sm[j] : sp[j];
   const unsigned in = min ? (min[m * tf + g] >> (4 * sgn)) & 15u : 0u;
   const unsigned sel = select_mask<T>(selector, S, s, in);
   hbuf[e * tf + g] = combine_canonical<T>(s, sel);
@@ -343,37 +289,13 @@ k_evals_euler2d(Grid2D gd, int dir, const T *__restrict__ P, int selector, const
   const T gamma = (T)gd.gamma;
   T qs[6][4];
   load_stencil2d<T>(gd, dir, q, f, qs);
-  T L[4][4], R[4][4], Lm[4];
-  roe2d<T>(qs[2], qs[3], gamma, dir, L, R);
-  row_of<T, 4>(L, m, Lm);
-  T v[6], gg[6], alpha = T(0);
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    T u, vv, pr, c, F[4];
-    prim2d<T>(qs[j], gamma, u, vv, pr, c);
-    flux2d<T>(qs[j], u, vv, pr, dir, F);
-    const T un = dir == 0 ? u : vv;
-    const T lam = m == 0 ? un - c : (m == 3 ? un + c : un);
-    const T a = abs_<T>(lam);
-    alpha = a > alpha ? a : alpha;
-    T av = T(0), ag = T(0);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      av = fma_<T>(Lm[r], qs[j][r], av);
-      ag = fma_<T>(Lm[r], F[r], ag);
-    }
-    v[j] = av;
-    gg[j] = ag;
+  T s[6];
+  switch (m) {  // block-uniform: each case sees its field index at compile time
+  case 0: stencil2d<T, 0>(qs, gamma, dir, sgn, s); break;
+  case 1: stencil2d<T, 1>(qs, gamma, dir, sgn, s); break;
+  case 2: stencil2d<T, 2>(qs, gamma, dir, sgn, s); break;
+  default: stencil2d<T, 3>(qs, gamma, dir, sgn, s); break;
   }
-  T sp[6], sm[6], s[6];
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    const T t = alpha * v[j];
-    sp[j] = T(0.5) * (gg[j] + t);
-    sm[5 - j] = T(0.5) * (gg[j] - t);
-  }
-#pragma unroll
-  for (int j = 0; j < 6; ++j) s[j] = sgn ? sm[j] : sp[j];
   const unsigned in = min ? (min[m * nf + f] >> (4 * sgn)) & 15u : 0u;
   const unsigned sel = select_mask<T>(selector, S, s, in);
   hbuf[e * nf + f] = combine_canonical<T>(s, sel);

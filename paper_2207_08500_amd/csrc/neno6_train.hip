@@ -193,13 +193,20 @@ __global__ void __launch_bounds__(256) k_to_f32(const double *__restrict__ P, fl
 
 struct TrainWs {
   float *P32;
+  void *tabs;
   float *part;
   double *lpart;
   size_t bytes;
 };
 
-TrainWs carve(void *ws, int32_t batch) {
+int64_t partial_rows(int64_t batch) {
   const int64_t nblk = (batch + TB - 1) / TB;
+  const int64_t nw = train_mfma_waves(batch);
+  return nblk > nw ? nblk : nw;
+}
+
+TrainWs carve(void *ws, int32_t batch) {
+  const int64_t rows = partial_rows(batch);
   char *b = (char *)ws;
   size_t off = 0;
   auto take = [&](size_t n) {
@@ -209,8 +216,9 @@ TrainWs carve(void *ws, int32_t batch) {
   };
   TrainWs w;
   w.P32 = (float *)take(sizeof(float) * NPARAM);
-  w.part = (float *)take(sizeof(float) * NPARAM * (size_t)nblk);
-  w.lpart = (double *)take(sizeof(double) * (size_t)nblk);
+  w.tabs = take(train_mfma_tab_bytes());
+  w.part = (float *)take(sizeof(float) * NPARAM * (size_t)rows);
+  w.lpart = (double *)take(sizeof(double) * (size_t)rows);
   w.bytes = off;
   return w;
 }
@@ -219,12 +227,18 @@ TrainWs carve(void *ws, int32_t batch) {
 
 size_t train_workspace_bytes(int32_t batch) { return carve(nullptr, batch).bytes; }
 
-bool train_precision_supported(int precision) { return precision == 1; }
+bool train_precision_supported(int precision) { return precision == 1 || precision == 2; }
 
+// Partial gradients of one mini-batch; returns the number of partial rows.
 static hipError_t grad_pass(const double *P, const float *s, const uint8_t *y, const int64_t *idx,
-                            int64_t mb, const TrainWs &w, hipStream_t st) {
+                            int64_t mb, int precision, const TrainWs &w, int *rows, hipStream_t st) {
+  if (precision == 2) {
+    *rows = train_mfma_waves(mb);
+    return launch_grad_mfma(P, w.tabs, s, y, idx, mb, w.part, w.lpart, st);
+  }
   hipLaunchKernelGGL(k_to_f32, dim3((NPARAM + 255) / 256), dim3(256), 0, st, P, w.P32);
   const int64_t nblk = (mb + TB - 1) / TB;
+  *rows = (int)nblk;
   hipLaunchKernelGGL(k_grad_f32, dim3((unsigned)nblk), dim3(TB), 0, st, w.P32, s, y, idx, mb,
                      (float)(1.0 / (double)mb), w.part, w.lpart);
   return hipGetLastError();
@@ -235,11 +249,11 @@ hipError_t launch_train_batch(double *P, double *m, double *v, int64_t step, con
                               double b1, double b2, double eps, int precision, double *loss_out,
                               double loss_scale, bool first, void *ws, hipStream_t st) {
   const TrainWs w = carve(ws, (int32_t)mb);
-  hipError_t e = grad_pass(P, s, y, idx, mb, w, st);
+  int rows = 0;
+  hipError_t e = grad_pass(P, s, y, idx, mb, precision, w, &rows, st);
   if (e != hipSuccess) return e;
-  const int nblk = (int)((mb + TB - 1) / TB);
   const double c1 = 1.0 - pow(b1, (double)step), c2 = 1.0 - pow(b2, (double)step);
-  hipLaunchKernelGGL(k_reduce_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, st, nblk, w.part,
+  hipLaunchKernelGGL(k_reduce_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, st, rows, w.part,
                      w.lpart, P, m, v, nullptr, loss_out, loss_scale, 1, first ? 0 : 1, lr, b1, b2,
                      eps, c1, c2);
   return hipGetLastError();
@@ -248,10 +262,10 @@ hipError_t launch_train_batch(double *P, double *m, double *v, int64_t step, con
 hipError_t launch_grad(const double *P, const float *s, const uint8_t *y, int64_t n, int precision,
                        double *grad, double *loss, void *ws, hipStream_t st) {
   const TrainWs w = carve(ws, (int32_t)n);
-  hipError_t e = grad_pass(P, s, y, nullptr, n, w, st);
+  int rows = 0;
+  hipError_t e = grad_pass(P, s, y, nullptr, n, precision, w, &rows, st);
   if (e != hipSuccess) return e;
-  const int nblk = (int)((n + TB - 1) / TB);
-  hipLaunchKernelGGL(k_reduce_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, st, nblk, w.part,
+  hipLaunchKernelGGL(k_reduce_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, st, rows, w.part,
                      w.lpart, nullptr, nullptr, nullptr, grad, loss, 1.0 / (double)n, 0, 0, 0.0,
                      0.0, 0.0, 0.0, 1.0, 1.0);
   return hipGetLastError();

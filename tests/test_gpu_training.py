@@ -1,0 +1,180 @@
+"""Classifier training and differentiation on the GPU against the FP64 oracle:
+BCE gradients (FP32 vector path tightly, BF16 MFMA path to BF16 tolerance),
+Adam steps, a short training run, the fixed-mask adjoint of the advection
+right-hand side, and the autograd wrappers (finite differences)."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_08500_amd import inputs
+from tests._helpers import dev, host, need_gpu, trained_params
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    need_gpu()
+    import torch
+    from paper_2207_08500_amd import native
+    return native, torch
+
+
+@pytest.mark.parametrize("n", [1, 31, 64, 1000, 4097])
+@pytest.mark.parametrize("prec", [1, 2])
+def test_gradient_against_oracle(ctx, n, prec):
+    native, torch = ctx
+    P = trained_params()
+    s, y = inputs.classifier_samples(30 + n, n)
+    loss_o, g_o = oracle.bce_grad(P, s, y)
+    g = torch.zeros(3228, dtype=torch.float64, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    native.neno6_classifier_grad(dev(P), dev(s, torch.float32), dev(y), prec, g, loss)
+    torch.cuda.synchronize()
+    g = host(g)
+    rel = np.abs(g - g_o).max() / np.abs(g_o).max()
+    cos = np.dot(g, g_o) / np.linalg.norm(g) / np.linalg.norm(g_o)
+    print("prec %d n %d: loss %.6f vs %.6f, max rel grad err %.3g, cosine %.6f"
+          % (prec, n, host(loss)[0], loss_o, rel, cos))
+    if prec == 1:
+        assert abs(host(loss)[0] - loss_o) < 1e-5 * max(1.0, loss_o)
+        assert rel < 1e-4
+    else:
+        # BF16 activations move a few uncertain samples' logits by O(1), which
+        # shifts their share of the gradient; the direction stays close
+        assert abs(host(loss)[0] - loss_o) < (0.15 if n == 1 else 0.05) * loss_o
+        assert cos > 0.98 and rel < 0.3
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_training_run_against_oracle(ctx, prec):
+    """Three epochs on 8192 samples (batch 512): the GPU run tracks the FP64
+    oracle run on the same data and sample order."""
+    native, torch = ctx
+    n, batch, epochs, lr = 8192, 512, 3, 3e-3
+    P0 = inputs.mlp_init(40)
+    s, y = inputs.classifier_samples(41, n)
+    Po, mo, vo, to = P0.copy(), np.zeros_like(P0), np.zeros_like(P0), 0
+    Pg, mg, vg = dev(P0), torch.zeros(3228, dtype=torch.float64, device="cuda"), \
+        torch.zeros(3228, dtype=torch.float64, device="cuda")
+    sg, yg = dev(s, torch.float32), dev(y)
+    loss_g = torch.zeros(1, dtype=torch.float64, device="cuda")
+    step = 0
+    lo_hist, lg_hist = [], []
+    for ep in range(epochs):
+        perm = inputs.epoch_permutation(41, ep, n)
+        lo, to = oracle.train(Po, mo, vo, to, s, y, perm, batch, lr)
+        step = native.neno6_classifier_train(Pg, mg, vg, step, sg, yg, dev(perm), batch, lr,
+                                             precision=prec, loss_out=loss_g)
+        torch.cuda.synchronize()
+        lo_hist.append(lo)
+        lg_hist.append(host(loss_g)[0])
+    assert step == to == epochs * (n // batch)
+    print("prec %d oracle loss %s gpu loss %s" % (prec, lo_hist, lg_hist))
+    assert lg_hist[-1] < 0.85 * lg_hist[0]
+    tol = 2e-3 if prec == 1 else 5e-2
+    assert np.allclose(lg_hist, lo_hist, rtol=tol)
+    dp = np.abs(host(Pg) - Po).max() / np.abs(Po).max()
+    assert dp < (1e-3 if prec == 1 else 5e-2)
+
+
+def test_adam_first_step(ctx):
+    native, torch = ctx
+    P = inputs.mlp_init(42)
+    s, y = inputs.classifier_samples(43, 2048)
+    _, g = oracle.bce_grad(P, s, y)
+    Pg = dev(P)
+    m = torch.zeros(3228, dtype=torch.float64, device="cuda")
+    v = torch.zeros(3228, dtype=torch.float64, device="cuda")
+    step = native.neno6_classifier_train(Pg, m, v, 0, dev(s, torch.float32), dev(y),
+                                         dev(np.arange(2048)), 2048, 1e-3, precision=1)
+    torch.cuda.synchronize()
+    assert step == 1
+    big = np.abs(g) > 1e-5
+    # first Adam step: every parameter moves by lr * g / (|g| + eps)
+    want = P - 1e-3 * g / (np.abs(g) + 1e-8)
+    assert np.allclose(host(Pg)[big], want[big], atol=2e-6)
+
+
+def test_c5_training_throughput(ctx):
+    """C5 shape: 2^24 synthetic samples, batch 65536, BF16 MFMA forward and
+    backward, Adam; one epoch timed (samples/s printed)."""
+    native, torch = ctx
+    n, batch = 1 << 24, 65536
+    s, y = inputs.classifier_samples(inputs.BASE_SEED, n)
+    n_train = int(0.7 * n)
+    sg, yg = dev(s, torch.float32), dev(y)
+    Pg = dev(inputs.mlp_init(inputs.BASE_SEED))
+    m = torch.zeros(3228, dtype=torch.float64, device="cuda")
+    v = torch.zeros(3228, dtype=torch.float64, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ws = torch.empty(native.neno6_train_workspace_size(batch), dtype=torch.uint8, device="cuda")
+    perm0 = dev(inputs.epoch_permutation(inputs.BASE_SEED, 0, n_train))
+    perm1 = dev(inputs.epoch_permutation(inputs.BASE_SEED, 1, n_train))
+    step = native.neno6_classifier_train(Pg, m, v, 0, sg, yg, perm0[: 4 * batch], batch, 1e-3,
+                                         precision=2, loss_out=loss, ws=ws)
+    torch.cuda.synchronize()
+    l_first = host(loss)[0]
+    t0 = time.perf_counter()
+    step = native.neno6_classifier_train(Pg, m, v, step, sg, yg, perm1, batch, 1e-3, precision=2,
+                                         loss_out=loss, ws=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    l_epoch = host(loss)[0]
+    vloss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    g = torch.zeros(3228, dtype=torch.float64, device="cuda")
+    native.neno6_classifier_grad(Pg, sg[n_train:n_train + 1000000].contiguous(),
+                                 yg[n_train:n_train + 1000000].contiguous(), 1, g, vloss)
+    torch.cuda.synchronize()
+    print("C5 epoch: %d samples in %.3f s = %.3g samples/s; loss %.4f -> %.4f, validation %.4f"
+          % (n_train, dt, n_train / dt, l_first, l_epoch, host(vloss)[0]))
+    assert np.isfinite(l_epoch) and l_epoch < l_first
+
+
+def test_adjoint_against_oracle_and_autograd(ctx):
+    native, torch = ctx
+    from paper_2207_08500_amd import autograd as ag
+    P = trained_params()
+    n = 200
+    dx = 2.0 / n
+    u = inputs.advection_c1(inputs.BASE_SEED, n)
+    _, masks = oracle.advection_rhs(u, dx, oracle.BC_PERIODIC, P, oracle.SEL_MLP)
+    rbar = np.random.default_rng(7).standard_normal(n)
+    ub_o = oracle.advection_rhs_adjoint(masks, dx, rbar)
+    for bc in (native.PERIODIC, native.TRANSMISSIVE):
+        prob = native.Problem(native.ADVECTION, native.FP64, native.SEL_MASKS_IN, bc, [0, n], [dx])
+        ub = torch.zeros(n, dtype=torch.float64, device="cuda")
+        native.neno6_rhs_adjoint(prob, dev(masks), dev(rbar), ub)
+        torch.cuda.synchronize()
+        if bc == native.PERIODIC:
+            assert np.allclose(host(ub), ub_o, rtol=1e-12, atol=1e-12 * np.abs(ub_o).max())
+        else:
+            ub_t = oracle.advection_rhs_adjoint(masks, dx, rbar, bc=oracle.BC_TRANSMISSIVE)
+            assert np.allclose(host(ub), ub_t, rtol=1e-12, atol=1e-12 * np.abs(ub_t).max())
+        # autograd wrapper: gradcheck (finite differences of a linear map)
+        uu = dev(u).requires_grad_(True)
+        mm = dev(masks)
+        assert torch.autograd.gradcheck(lambda x: ag.advection_rhs(x, mm, prob), (uu,), eps=1e-6,
+                                        atol=1e-6, rtol=1e-5)
+
+
+def test_classifier_autograd_finite_difference(ctx):
+    native, torch = ctx
+    from paper_2207_08500_amd import autograd as ag
+    P = dev(inputs.mlp_init(44)).requires_grad_(True)
+    s, y = inputs.classifier_samples(45, 256)
+    sg, yg = dev(s, torch.float32), dev(y)
+    loss = ag.classifier_bce(P, sg, yg, native.FP32)
+    loss.backward()
+    g = host(P.grad)
+    _, g_o = oracle.bce_grad(host(P.detach()), s.astype(np.float32).astype(np.float64), y)
+    assert np.abs(g - g_o).max() < 1e-4 * np.abs(g_o).max()
+    # central finite differences of the oracle loss in a few coordinates
+    Ph = host(P.detach())
+    for i in (0, 100, 500, 3000, 3227):
+        e = np.zeros_like(Ph)
+        e[i] = 1e-5
+        fd = (oracle.bce_grad(Ph + e, s, y)[0] - oracle.bce_grad(Ph - e, s, y)[0]) / 2e-5
+        assert abs(fd - g[i]) < 1e-4 * max(1e-3, np.abs(g).max())

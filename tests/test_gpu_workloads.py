@@ -1,0 +1,86 @@
+"""Full-size workloads on the GPU: reduced-precision runs against the FP64
+path (which the parity tests pin bit for bit to the oracle), with the label
+flip rate and the L1 / Linf distance printed as numbers and bounded.
+
+* 2D Euler, 2048 x 2048 four-quadrant Riemann data, 20 RK3 steps, BF16 and
+  FP16 classifier against FP64.
+* 1D advection, N = 200, CFL 0.4, t = 2 (500 steps), FP32 / BF16 against FP64.
+"""
+import numpy as np
+import pytest
+
+from paper_2207_08500_amd import inputs
+from tests._helpers import dev, host, label_flip_rate, need_gpu, trained_params
+
+pytestmark = pytest.mark.gpu
+
+MARGIN = {2: 0.5, 3: 0.25}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    need_gpu()
+    import torch
+    from paper_2207_08500_amd import native
+    return native, torch, trained_params()
+
+
+def _run2d(native, torch, P, prec, q0, n, steps):
+    mlp = native.Mlp(dev(P), recheck_margin=MARGIN.get(prec, 0.0))
+    prob = native.Problem(native.EULER2D, prec, native.SEL_MLP, native.TRANSMISSIVE, nx=n, ny=n,
+                          dx2d=1.0 / n, dy2d=1.0 / n)
+    q = q0.clone()
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ws = prob.workspace()
+    native.neno6_step(prob, mlp, q, 0.4, steps, t, st, ws)
+    m = torch.zeros(prob.mask_count(), dtype=torch.uint8, device="cuda")
+    r = torch.zeros_like(q)
+    native.neno6_rhs(prob, mlp, q0, r, ws, masks_out=m)
+    torch.cuda.synchronize()
+    return q, float(host(t)[0]), int(host(st)[0]), m
+
+
+@pytest.mark.parametrize("prec", [2, 3])
+def test_c3_2048_twenty_steps(ctx, prec):
+    native, torch, P = ctx
+    n, steps = 2048, 20
+    q0 = inputs.riemann2d(inputs.BASE_SEED, n, n)
+    q32 = dev(q0, torch.float32)
+    q64 = q32.double().contiguous()  # identical (FP32-rounded) initial state
+    qr, tr, sr, mr = _run2d(native, torch, P, prec, q32, n, steps)
+    q6, t6, s6, m6 = _run2d(native, torch, P, native.FP64, q64, n, steps)
+    assert sr == 0 and s6 == 0
+    flip = label_flip_rate(host(mr), host(m6))
+    d = (qr.double() - q6).abs().reshape(4, -1)
+    ref = q6.abs().reshape(4, -1)
+    l1 = (d.mean(dim=1) / ref.mean(dim=1)).max().item()
+    linf = (d.max(dim=1).values / ref.max(dim=1).values).max().item()
+    print("C3 prec %d: flip rate %.3g, relative L1 %.3g, Linf %.3g, t %.6g vs %.6g"
+          % (prec, flip, l1, linf, tr, t6))
+    assert flip < 1e-3
+    assert l1 < (2e-3 if prec == 2 else 1e-4)
+    assert abs(tr - t6) < 1e-3 * t6
+
+
+@pytest.mark.parametrize("prec", [1, 2, 3])
+def test_c1_advection_full_run(ctx, prec):
+    native, torch, P = ctx
+    u0 = inputs.advection_c1(inputs.BASE_SEED, 200)
+    dx = 2.0 / 200
+    out = {}
+    for pr in (native.FP64, prec):
+        mlp = native.Mlp(dev(P), recheck_margin=MARGIN.get(pr, 0.0))
+        prob = native.Problem(native.ADVECTION, pr, native.SEL_MLP, native.PERIODIC, [0, 200], [dx])
+        u = dev(u0, native.fdtype(pr))
+        t = torch.zeros(1, dtype=torch.float64, device="cuda")
+        st = torch.zeros(1, dtype=torch.int32, device="cuda")
+        native.neno6_step(prob, mlp, u, 0.4, 500, t, st, prob.workspace())
+        torch.cuda.synchronize()
+        out[pr] = host(u).astype(np.float64)
+    d = np.abs(out[prec] - out[native.FP64])
+    l1 = d.mean() / np.abs(out[native.FP64]).mean()
+    print("C1 prec %d: relative L1 %.3g, Linf %.3g" % (prec, l1, d.max()))
+    assert l1 < 1e-2
+    # conservation on the periodic line, FP32 state
+    assert abs(out[prec].sum() - u0.sum()) < 1e-3 * np.abs(u0).sum()
