@@ -34,6 +34,38 @@ FLOP_PER_EVAL = 6208      # 2 x 3104 MAC of the 6-64-32-16-8-4 network
 EVALS_PER_FACE = 6        # 3 characteristic fields x 2 split signs
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "euler1d_c2_256x4000_hbm_traffic.md")
+
+
+def _traffic_bytes():
+    """HBM bytes per launch of the fused kernel from the committed FETCH_SIZE /
+    WRITE_SIZE counter runs (scaled by the copy-kernel calibration), or None
+    when the kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        line = [ln for ln in open(TRAFFIC_RECORD) if ln.startswith("traffic-record:")][0]
+        rec = json.loads(line.split(":", 1)[1])
+        h = hashlib.sha256()
+        for f in rec["sources"]:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        return int(rec["bytes_per_launch"]) if h.hexdigest() == rec["source_sha256"] else None
+    except (OSError, IndexError, KeyError, ValueError):
+        return None
+
+
+def _physical(q, off, gamma=1.4):
+    """Per problem: every cell finite with positive density and pressure (a
+    problem can leave that range in the last step; the solver freezes it only
+    at the start of the next)."""
+    import numpy as np
+    rho, mom, E = q.double().reshape(3, -1).cpu().numpy()
+    with np.errstate(all="ignore"):
+        p = (gamma - 1.0) * (E - 0.5 * mom * mom / rho)
+        good = np.isfinite(rho) & np.isfinite(p) & (rho > 0) & (p > 0)
+    return np.minimum.reduceat(good.astype(np.int8), off[:-1]).astype(bool)
+
+
 def _args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -42,6 +74,9 @@ def _args():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--workload", choices=("c2", "c4"), default="c2",
+                    help="c2: 256 x 4000-cell batch (headline); c4: 4096 uneven problems, "
+                         "ten RK3 steps per graph replay, autotuned launch shapes")
     return ap.parse_args()
 
 
@@ -54,11 +89,13 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2207_08500_amd import inputs, native
+    from paper_2207_08500_amd import autotune, inputs, native
 
     native.load()
     dev = torch.device("cuda:0")
     P = np.load(os.path.join(ROOT, "tests", "golden", "neno6_mlp_trained.npy"), allow_pickle=False)
+    if a.workload == "c4":
+        return bench_batched(a, P, dev)
     q0, off, dx = inputs.riemann1d_batch(inputs.BASE_SEED, (N_CELLS,) * N_PROBLEMS)
     faces_stage = int(off[-1]) + N_PROBLEMS
     faces_step = 3 * faces_stage
@@ -71,8 +108,12 @@ def main():
                               device=dev)
         return mlp, prob, prob.workspace(dev)
 
+    shapes_used = {}
+
     def run_steps(prec, q_init, steps, warmup, graph=True):
         mlp, prob, ws = make(prec, MARGIN.get(prec, 0.0))
+        if prec in (native.BF16, native.FP16):  # launch shapes from the autotuner (cached)
+            shapes_used[prec] = autotune.tuned(prob, mlp, q_init, ws)[0]
         q = q_init.clone()
         t = torch.zeros(N_PROBLEMS, dtype=torch.float64, device=dev)
         st = torch.zeros(N_PROBLEMS, dtype=torch.int32, device=dev)
@@ -90,6 +131,7 @@ def main():
             q.copy_(q_init)
             t.zero_()
             st.zero_()
+            prob.flags = native.KEEP_MAP  # the workspace holds the face map from the eager step
             try:
                 g = torch.cuda.CUDAGraph()
                 with torch.cuda.graph(g):
@@ -133,7 +175,7 @@ def main():
     q64b, t64b, st64b, _, _, _ = run_steps(native.FP64, q64_from32, a.steps, 0, graph=not a.no_graph)
     # problems whose state turned non-physical (no positivity limiter in the
     # scheme) are frozen by the solver and left out of the error norms
-    okp = ((stb == 0) & (st64b == 0)).cpu().numpy()
+    okp = ((stb == 0) & (st64b == 0)).cpu().numpy() & _physical(qb, off) & _physical(q64b, off)
     frozen_b, frozen_64 = int((stb != 0).sum()), int((st64b != 0).sum())
     cell_ok = torch.as_tensor(np.repeat(okp, np.diff(off)), device=dev)
     dq = (qb.double() - q64b).abs().reshape(3, -1)[:, cell_ok]
@@ -162,8 +204,11 @@ def main():
 
     # ---- fused face kernel alone, BF16 (roofline) ------------------------------------
     mlp0, prob0, ws0 = make(native.BF16, 0.0)  # margin 0: exactly the fused kernel
+    prob0.set_tuning(shapes_used.get(native.BF16))  # the launch shape of the timed steps
     F = torch.zeros(3 * faces_stage, dtype=torch.float32, device=dev)
-    for _ in range(3):
+    native.neno6_face_fluxes(prob0, mlp0, q32, F, ws0)  # builds the face map once
+    prob0.flags = native.KEEP_MAP                      # later calls launch only the kernel
+    for _ in range(2):
         native.neno6_face_fluxes(prob0, mlp0, q32, F, ws0)
     torch.cuda.synchronize()
     reps = 50
@@ -175,6 +220,8 @@ def main():
     torch.cuda.synchronize()
     k_ms = e0.elapsed_time(e1) / reps
     flop = faces_stage * EVALS_PER_FACE * FLOP_PER_EVAL
+    # state in, face fluxes and masks out (FP32 state, one mask byte per face and field)
+    alg_bytes = 3 * int(off[-1]) * 4 + 3 * faces_stage * 4 + 3 * faces_stage
     achieved = flop / (k_ms / 1e3) / 1e12
     # share of evaluations the FP32 re-check takes at the stated margin
     mlpm, probm, wsm = make(native.BF16, MARGIN[2])
@@ -221,9 +268,11 @@ def main():
                                "FP32 re-check margin %.2f" % (N_PROBLEMS, N_CELLS, CFL, MARGIN[2]),
                    "faces_per_step": faces_step, "hip_graph": graphed},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_BF16,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_MFMA_BF16, "traffic": None,
-                     "kernel": "k_fast_euler1d<bf16>", "kernel_ms": k_ms,
-                     "algorithmic_flop_per_launch": flop},
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_MFMA_BF16,
+                     "traffic": _traffic_bytes(),
+                     "kernel": "k_fast_faces<BF16, 1D Euler>", "kernel_ms": k_ms,
+                     "algorithmic_flop_per_launch": flop,
+                     "algorithmic_bytes_per_launch": alg_bytes},
         "fp64_plain": {"value": fp64_rate, "unit": "faces/s", "ms_per_step": ms_64 / k64,
                        "steps": k64},
         "fp16_mfma": {"value": fp16_rate, "unit": "faces/s", "ms_per_step": ms_h / a.steps,
@@ -234,6 +283,120 @@ def main():
         "l1_rel_vs_fp64": l1,
         "linf_rel_vs_fp64": linf,
         "frozen_problems": {"bf16": frozen_b, "fp64": frozen_64, "of": N_PROBLEMS},
+        "problems_in_error_norms": int(okp.sum()),
+        "launch_shapes": {"bf16": shapes_used.get(native.BF16), "fp16": shapes_used.get(native.FP16)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+def bench_batched(a, P, dev):
+    """4096 independent 1D Euler problems, N log-uniform in [256, 16384];
+    FP32 state, BF16 classifier; ten RK3 steps per HIP-graph replay with the
+    autotuned launch shapes.  A step here is one replay (ten RK3 steps)."""
+    import numpy as np
+    import torch
+
+    from paper_2207_08500_amd import autotune, inputs, native
+
+    n_prob, inner = 4096, 10
+    sizes = inputs.uneven_sizes(inputs.BASE_SEED, n_prob, 256, 16384)
+    q0, off, dx = inputs.riemann1d_batch(inputs.BASE_SEED, sizes)
+    faces_stage = int(off[-1]) + n_prob
+    faces_replay = inner * 3 * faces_stage
+    q32 = torch.as_tensor(q0, dtype=torch.float32, device=dev).contiguous()
+    mlp = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=MARGIN[2])
+    prob = native.Problem(native.EULER1D, native.BF16, native.SEL_MLP, native.TRANSMISSIVE, off, dx,
+                          device=dev)
+    ws = prob.workspace(dev)
+    shapes, tune_ms = autotune.tuned(prob, mlp, q32, ws)
+    q = q32.clone()
+    t = torch.zeros(n_prob, dtype=torch.float64, device=dev)
+    st = torch.zeros(n_prob, dtype=torch.int32, device=dev)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        native.neno6_step(prob, mlp, q, CFL, 1, t, st, ws, stream=s)  # eager: builds the face map
+    torch.cuda.current_stream().wait_stream(s)
+    prob.flags = native.KEEP_MAP
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        native.neno6_step(prob, mlp, q, CFL, inner, t, st, ws)
+
+    def reset():
+        q.copy_(q32)
+        t.zero_()
+        st.zero_()
+
+    reset()
+    for _ in range(a.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    reset()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(a.steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    value = faces_replay * a.steps / (ms / 1e3)
+    # fused face kernel alone (margin 0) with the tuned shapes
+    mlp0 = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=0.0)
+    F = torch.zeros(3 * faces_stage, dtype=torch.float32, device=dev)
+    for _ in range(2):
+        native.neno6_face_fluxes(prob, mlp0, q32, F, ws)
+    torch.cuda.synchronize()
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        native.neno6_face_fluxes(prob, mlp0, q32, F, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    k_ms = e0.elapsed_time(e1) / reps
+    flop = faces_stage * EVALS_PER_FACE * FLOP_PER_EVAL
+    achieved = flop / (k_ms / 1e3) / 1e12
+    cpu = None
+    if not a.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        pick = np.random.default_rng(3).choice(n_prob, 64, replace=False)
+        sub = np.concatenate([q0[:, off[p]:off[p + 1]] for p in pick], axis=1)
+        o_sub = np.concatenate([[0], np.cumsum(sizes[pick])])
+        c0 = time.perf_counter()
+        oracle.euler1d_step(sub, o_sub, dx[pick], CFL, 1, 1.4, oracle.BC_TRANSMISSIVE, P,
+                            oracle.SEL_MLP)
+        t_cpu = time.perf_counter() - c0
+        n_f = 3 * (int(o_sub[-1]) + 64)
+        cpu = {"value": n_f / t_cpu, "unit": "faces/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": "64 random problems of the 4096 (%d cells), one RK3 step (%d faces, "
+                         "%.1f s), FP64 C oracle" % (int(o_sub[-1]), n_f, t_cpu)}
+    out = {
+        "metric": "reconstructed faces/s: plain FP64 vs BF16-MFMA NENO6 at stated flip rate/L1 error",
+        "value": value,
+        "unit": "faces/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "1D Euler batch: %d problems, N log-uniform in [256, 16384] (%d cells), "
+                               "FP32 state, BF16-MFMA classifier, re-check margin %.2f; one step = "
+                               "one HIP-graph replay of %d SSP-RK3 steps" % (n_prob, int(off[-1]),
+                                                                           MARGIN[2], inner),
+                   "faces_per_step": faces_replay, "hip_graph": True, "launch_shapes": shapes,
+                   "autotune_ms_per_face_pass": tune_ms},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_BF16,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_MFMA_BF16, "traffic": None,
+                     "kernel": "k_fast_faces<BF16, 1D Euler>", "kernel_ms": k_ms,
+                     "algorithmic_flop_per_launch": flop},
+        "frozen_problems": {"bf16": int((st != 0).sum()), "of": n_prob},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

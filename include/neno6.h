@@ -98,18 +98,42 @@ typedef struct neno6_mlp {
  *    State layout SoA [var][total_cells]; faces of line p are numbered
  *    offsets[p] + p + k, k = 0..N_p (face k between cells k-1 and k);
  *    mask arrays are [field][total_cells + n_problems].
+ *    total_cells + n_problems < 2^29.
  *    ADVECTION uses var = field = 1 and only the '+' nibble (the '-' split
  *    flux is identically zero, so its nibble is reported as 0).
  *  2D (EULER2D): one nx x ny grid (nx, ny <= 2^20, nx * ny <= 2^28), SoA
  *    [4][ny][nx] (x fastest), spacings dx2d, dy2d; x-face masks
  *    [4][ny][nx+1], y-face masks [4][ny+1][nx]. */
+/* Launch shapes of the BF16/FP16 kernels (from neno6_autotune, or chosen by
+ * hand).  Any field left 0 takes the built-in default.
+ *  face_waves:     64-lane waves per workgroup of the fused face kernel
+ *                  (2, 4 or 8); each wave handles 64 consecutive faces per
+ *                  iteration.
+ *  face_blocks:    workgroups of the fused face kernel, which loop over the
+ *                  64-face tiles (grid-stride); at most 65536.
+ *  recheck_blocks: workgroups of the FP32 re-check and fix-up kernels, 1..65536.
+ *  xcd_order:      1 = number the workgroups so that each of the eight XCDs
+ *                  (each with its own L2) walks a contiguous run of tiles;
+ *                  needs face_blocks to be a multiple of 8 (else ignored). */
+typedef struct neno6_tuning {
+  int32_t face_waves;
+  int32_t face_blocks;
+  int32_t recheck_blocks;
+  int32_t xcd_order;
+} neno6_tuning;
+
+/* neno6_problem.flags */
+#define NENO6_KEEP_MAP 1 /* 1D: the workspace already holds this problem's face -> line
+                          * map, built by an earlier call with the same workspace and
+                          * offsets on the same stream; the call skips rebuilding it */
+
 typedef struct neno6_problem {
   int32_t equation;
   int32_t bc;
   int32_t precision;
   int32_t selector;
   int32_t n_problems;
-  int32_t reserved;
+  int32_t flags;               /* NENO6_KEEP_MAP or 0 */
   int64_t total_cells;
   int64_t nx, ny;
   const int64_t *offsets;      /* [dev]  cell offsets, 1D */
@@ -117,6 +141,7 @@ typedef struct neno6_problem {
   const double *dx;            /* [dev]  spacing per line, 1D */
   double dx2d, dy2d;
   double gamma;
+  const neno6_tuning *tuning;  /* [host, may be NULL] launch shapes; NULL = defaults */
 } neno6_problem;
 
 /* ---- library ------------------------------------------------------------- */
@@ -186,6 +211,20 @@ int32_t neno6_face_fluxes(const neno6_problem *prob, const neno6_mlp *mlp, const
  * margin and were re-evaluated in FP32.  count [host, 2 values]. */
 int32_t neno6_recheck_count(const neno6_problem *prob, const void *ws, size_t ws_bytes,
                             uint32_t *count, hipStream_t stream);
+
+/* Autotuner (host-synchronous, not for graph capture): times the fused
+ * face pass (counter reset, classifier kernel, re-check, fix-up) of `prob`
+ * on state q [dev] for every launch shape of a fixed candidate set -- waves
+ * per workgroup {2, 4, 8} (2D: {4, 8}) x workgroup caps {512, 1024, 2048,
+ * 4096, 16384, 65536} x XCD ordering {0, 1} x re-check workgroups {128, 512,
+ * 2048} -- with HIP events on `stream`, `reps` (1..1000) timed passes each
+ * after one warm-up, and writes the fastest to *best [host] (its mean pass
+ * time in ms to *best_ms [host], may be NULL).  Outputs of the passes land in
+ * the workspace only; prob->tuning is ignored.  Euler problems in BF16 /
+ * FP16 with SEL_MLP; NENO6_UNSUPPORTED otherwise. */
+int32_t neno6_autotune(const neno6_problem *prob, const neno6_mlp *mlp, const void *q, void *ws,
+                       size_t ws_bytes, int32_t reps, neno6_tuning *best, float *best_ms,
+                       hipStream_t stream);
 
 /* ---- time stepping -------------------------------------------------------- */
 /* n_steps SSP-RK3 steps (Sec. 4.4), in place on q [dev].  Each step first

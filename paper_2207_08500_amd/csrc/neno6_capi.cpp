@@ -41,8 +41,20 @@ int32_t check_mlp(const neno6_mlp *mlp, int32_t selector, int32_t precision) {
 
 int nvar_of(int32_t eq) { return eq == NENO6_ADVECTION ? 1 : (eq == NENO6_EULER1D ? 3 : 4); }
 
+int32_t check_tuning(const neno6_tuning *t) {
+  if (!t) return NENO6_OK;
+  if (t->face_waves != 0 && t->face_waves != 2 && t->face_waves != 4 && t->face_waves != 8)
+    return NENO6_BAD_ARG;
+  if (t->face_blocks < 0 || t->face_blocks > 65536) return NENO6_BAD_ARG;
+  if (t->recheck_blocks < 0 || t->recheck_blocks > 65536) return NENO6_BAD_ARG;
+  if (t->xcd_order != 0 && t->xcd_order != 1) return NENO6_BAD_ARG;
+  return NENO6_OK;
+}
+
 int32_t check_problem(const neno6_problem *pb) {
   if (!pb) return NENO6_BAD_ARG;
+  if (pb->flags & ~NENO6_KEEP_MAP) return NENO6_BAD_ARG;
+  if (int32_t c = check_tuning(pb->tuning)) return c;
   if (pb->equation != NENO6_ADVECTION && pb->equation != NENO6_EULER1D &&
       pb->equation != NENO6_EULER2D)
     return NENO6_BAD_ARG;
@@ -56,6 +68,9 @@ int32_t check_problem(const neno6_problem *pb) {
     return NENO6_OK;
   }
   if (pb->n_problems < 1 || !pb->offsets || !pb->offsets_host || !pb->dx) return NENO6_BAD_ARG;
+  // re-check queue entries are 32-bit (face * 8 + evaluation)
+  if (pb->total_cells < 1 || pb->total_cells + pb->n_problems >= (int64_t(1) << 29))
+    return NENO6_BAD_ARG;
   if (pb->offsets_host[0] != 0 || pb->offsets_host[pb->n_problems] != pb->total_cells)
     return NENO6_BAD_ARG;
   for (int32_t p = 0; p < pb->n_problems; ++p)
@@ -186,13 +201,20 @@ FastArgs fast_args(const neno6_problem *pb, const neno6_mlp *mlp, const Work &w)
   fa.prepared = mlp ? mlp->prepared : nullptr;
   fa.margin = mlp ? mlp->recheck_margin : 0.f;
   fa.scr = w.scr;
+  if (const neno6_tuning *t = pb->tuning) {
+    fa.face_waves = t->face_waves;
+    fa.face_blocks = t->face_blocks;
+    fa.recheck_blocks = t->recheck_blocks;
+    fa.xcd_order = t->xcd_order;
+  }
   return fa;
 }
 
 // Per-call setup enqueued before the first kernel of an entry point: the
 // face -> line map of a 1D batch and the re-check counters.
 int32_t begin_call(const neno6_problem *pb, const neno6_mlp *mlp, const Work &w, hipStream_t s) {
-  if (pb->equation != NENO6_EULER2D && launch_build_fmap(line_of(pb), w.fmap, s) != hipSuccess)
+  if (pb->equation != NENO6_EULER2D && !(pb->flags & NENO6_KEEP_MAP) &&
+      launch_build_fmap(line_of(pb), w.fmap, s) != hipSuccess)
     return NENO6_HIP_ERROR;
   if (pb->precision >= NENO6_BF16 && launch_fast_reset(fast_args(pb, mlp, w), s) != hipSuccess)
     return NENO6_HIP_ERROR;
@@ -214,13 +236,7 @@ int32_t rhs_dispatch(const neno6_problem *pb, const neno6_mlp *mlp, const void *
   case NENO6_FP32:
     return rhs_impl<float>(pb, prepared_f32(mlp), q, rhs, masks_in, masks_out, status, w, st, s);
   default: {
-    FastArgs fa;
-    fa.equation = pb->equation;
-    fa.precision = pb->precision;
-    fa.selector = pb->selector;
-    fa.prepared = mlp ? mlp->prepared : nullptr;
-    fa.margin = mlp ? mlp->recheck_margin : 0.f;
-    fa.scr = w.scr;
+    const FastArgs fa = fast_args(pb, mlp, w);
     if (pb->equation == NENO6_EULER2D) {
       const Grid2D g = grid_of(pb);
       return hip_status(launch_fast_rhs2d(g, fa, (const float *)q, (float *)rhs, masks_in,
@@ -332,13 +348,7 @@ int32_t neno6_face_fluxes(const neno6_problem *prob, const neno6_mlp *mlp, const
   const size_t nfx = is2d ? 4 * (size_t)(prob->nx + 1) * prob->ny : 0;
   hipError_t e;
   if (prob->precision >= NENO6_BF16) {
-    FastArgs fa;
-    fa.equation = prob->equation;
-    fa.precision = prob->precision;
-    fa.selector = prob->selector;
-    fa.prepared = mlp ? mlp->prepared : nullptr;
-    fa.margin = mlp ? mlp->recheck_margin : 0.f;
-    fa.scr = w.scr;
+    const FastArgs fa = fast_args(prob, mlp, w);
     e = is2d ? launch_fast_faces2d(grid_of(prob), fa, (const float *)q, nullptr, masks_out,
                                    (float *)F, (float *)F + nfx, stream)
              : launch_fast_faces1d(line_of(prob, w.fmap), fa, (const float *)q, nullptr, masks_out,
@@ -384,6 +394,77 @@ int32_t neno6_recheck_count(const neno6_problem *prob, const void *ws, size_t ws
   if (ws_bytes < w.bytes) return NENO6_WORKSPACE_SMALL;
   if (hipStreamSynchronize(stream) != hipSuccess) return NENO6_HIP_ERROR;
   return hip_status(hipMemcpy(count, w.scr.qcount, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost));
+}
+
+int32_t neno6_autotune(const neno6_problem *prob, const neno6_mlp *mlp, const void *q, void *ws,
+                       size_t ws_bytes, int32_t reps, neno6_tuning *best, float *best_ms,
+                       hipStream_t stream) {
+  if (int32_t c = check_problem(prob)) return c;
+  if (prob->precision < NENO6_BF16 || prob->selector != NENO6_SEL_MLP ||
+      prob->equation == NENO6_ADVECTION)
+    return NENO6_UNSUPPORTED;
+  if (int32_t c = check_mlp(mlp, prob->selector, prob->precision)) return c;
+  if (!q || !ws || !best || reps < 1 || reps > 1000) return NENO6_BAD_ARG;
+  const Work w = carve_work(prob, ws);
+  if (ws_bytes < w.bytes) return NENO6_WORKSPACE_SMALL;
+  if (int32_t c = begin_call(prob, mlp, w, stream)) return c;
+  static const int waves[] = {2, 4, 8};
+  static const int blocks[] = {512, 1024, 2048, 4096, 16384, 65536};
+  static const int rblocks[] = {128, 512, 2048};
+  const bool is2d = prob->equation == NENO6_EULER2D;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return NENO6_HIP_ERROR;
+  }
+  FastArgs fa = fast_args(prob, mlp, w);
+  auto pass = [&]() -> hipError_t {
+    hipError_t e = launch_fast_reset(fa, stream);
+    if (e != hipSuccess) return e;
+    return is2d ? launch_fast_faces2d(grid_of(prob), fa, (const float *)q, nullptr, nullptr,
+                                      (float *)w.F, (float *)w.G, stream)
+                : launch_fast_faces1d(line_of(prob, w.fmap), fa, (const float *)q, nullptr,
+                                      nullptr, (float *)w.F, stream);
+  };
+  float best_t = -1.f;
+  neno6_tuning bt{};
+  int32_t rc = NENO6_OK;
+  for (int wv : waves) {
+    if (is2d && wv == 2) continue;  // 2D sweeps run with 4 or 8 waves
+    for (int nb : blocks)
+      for (int xcd = 0; xcd < 2 && rc == NENO6_OK; ++xcd)
+        for (int rb : rblocks) {
+          fa.face_waves = wv;
+          fa.face_blocks = nb;
+          fa.recheck_blocks = rb;
+          fa.xcd_order = xcd;
+          float ms = 0.f;
+          hipError_t e = pass();
+          if (e == hipSuccess) e = hipEventRecord(e0, stream);
+          for (int r = 0; r < reps && e == hipSuccess; ++r) e = pass();
+          if (e == hipSuccess) e = hipEventRecord(e1, stream);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (e != hipSuccess) {
+            rc = NENO6_HIP_ERROR;
+            break;
+          }
+          ms /= (float)reps;
+          if (best_t < 0.f || ms < best_t) {
+            best_t = ms;
+            bt.face_waves = wv;
+            bt.face_blocks = nb;
+            bt.recheck_blocks = rb;
+            bt.xcd_order = xcd;
+          }
+        }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != NENO6_OK) return rc;
+  *best = bt;
+  if (best_ms) *best_ms = best_t;
+  return NENO6_OK;
 }
 
 int32_t neno6_step(const neno6_problem *prob, const neno6_mlp *mlp, void *q, double cfl,

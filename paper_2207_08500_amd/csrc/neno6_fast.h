@@ -20,6 +20,9 @@ struct FastArgs {
   const void *prepared = nullptr;
   float margin = 0.f;
   FastScratch scr{};
+  // launch shapes (0 = default): waves per workgroup of the fused kernel,
+  // its workgroup cap, re-check / fix-up workgroups, XCD-contiguous order
+  int face_waves = 0, face_blocks = 0, recheck_blocks = 0, xcd_order = 0;
 };
 
 size_t fast_prepared_bytes();

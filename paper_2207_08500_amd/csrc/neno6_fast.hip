@@ -424,21 +424,27 @@ N6_DEV void enqueue(bool want, u32 entry, u32 *__restrict__ queue, u32 *__restri
 // stencils and R of the lane's face wait in LDS (a lane-private slot, no
 // barrier) while the classifier runs, so that the live registers during the
 // MFMA phase are the weights, the packed features and one pair of tiles.
-template <int PREC, int NV>
-__global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2)))
+// W waves per workgroup; the workgroups loop over the tiles (grid-stride).
+// With xcd != 0 the workgroup numbering is permuted so that the workgroups
+// the hardware places on one XCD (every 8th) take a contiguous run of tiles
+// (the host only sets it when gridDim.x is a multiple of 8).
+template <int PREC, int NV, int W>
+__global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(2)))
 k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict__ prepared,
              float margin, const float *__restrict__ q, const uint8_t *__restrict__ min,
              float *__restrict__ Fh, uint8_t *__restrict__ masks, u32 *__restrict__ queue,
-             u32 *__restrict__ qcount, int64_t qcap) {
+             u32 *__restrict__ qcount, int64_t qcap, int xcd) {
   constexpr int NE = 2 * NV;
   constexpr int NS = NE * 6 + NV * NV;
-  __shared__ float stash[WPB][NS][64];
+  __shared__ float stash[W][NS][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t nf = NV == 3 ? ln.faces() : (dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1));
   const int64_t nchunk = (nf + 63) / 64;
+  const int64_t nb = gridDim.x;
+  const int64_t lb = xcd ? (int64_t)(blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8 : blockIdx.x;
   Wts w;
   if (selector == 0) load_wts<PREC>(prepared, lane, w);
-  for (int64_t ch = (int64_t)blockIdx.x * WPB + wv; ch < nchunk; ch += (int64_t)gridDim.x * WPB) {
+  for (int64_t ch = lb * W + wv; ch < nchunk; ch += nb * W) {
     const int64_t f = ch * 64 + lane;
     const bool valid = f < nf;
     const int64_t fc = valid ? f : nf - 1;
@@ -504,22 +510,154 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
   }
 }
 
-// FP32 re-check of queued evaluations; flips the stored nibble where the
-// FP32 label differs and flags the entry.
+// ---- FP32 re-check, four lanes per queued evaluation -------------------------
+// The classifier in FP32 with its work split over the four lanes r = 0..3 of a
+// quad.  Layer 1 and the layer-2 partial sums are split by layer-1 neuron
+// (i = 4k + r) and summed across the quad; layers 3 and 4 are split by output
+// neuron (o = 4j + r), their outputs shared with quad broadcasts; layer 5 runs
+// in every lane.  LDS image of the FP32 parameters for this split:
+//   W1b [64][8]  (W1 row, b1, pad)              rows 4k + r read together
+//   W2T [64][36] (inputs x outputs, padded)     rows start in different banks
+//   b2  [32]
+//   W3q [32][4][4]  W3[4j + r][i] at (i, r, j)  one 16-byte read per lane and input
+//   b3q [4][4]      b3[4j + r]    at (r, j)
+//   W4q [16][4][2]  W4[4j + r][i] at (i, r, j)
+//   b4q [4][2]      b4[4j + r]    at (r, j)
+//   W5T [8][4], b5 [4]
+constexpr int Q_W1 = 0, Q_W2 = 512, Q_W2S = 36, Q_B2 = Q_W2 + 64 * Q_W2S, Q_W3 = Q_B2 + 32,
+              Q_B3 = Q_W3 + 512, Q_W4 = Q_B3 + 16, Q_B4 = Q_W4 + 128, Q_W5 = Q_B4 + 8,
+              Q_B5 = Q_W5 + 32, Q_SIZE = Q_B5 + 4;
+
+N6_DEV void stage_params_quad(const float *__restrict__ P, float *S) {
+  for (int t = threadIdx.x; t < Q_SIZE; t += blockDim.x) {
+    float v = 0.f;
+    if (t < Q_W2) {
+      const int o = t >> 3, k = t & 7;
+      v = k < 6 ? P[OW1 + o * 6 + k] : (k == 6 ? P[OB1 + o] : 0.f);
+    } else if (t < Q_B2) {
+      const int i = (t - Q_W2) / Q_W2S, o = (t - Q_W2) % Q_W2S;
+      v = o < 32 ? P[OW2 + o * 64 + i] : 0.f;
+    } else if (t < Q_W3) {
+      v = P[OB2 + t - Q_B2];
+    } else if (t < Q_B3) {
+      const int i = (t - Q_W3) >> 4, r = ((t - Q_W3) >> 2) & 3, j = (t - Q_W3) & 3;
+      v = P[OW3 + (4 * j + r) * 32 + i];
+    } else if (t < Q_W4) {
+      const int r = (t - Q_B3) >> 2, j = (t - Q_B3) & 3;
+      v = P[OB3 + 4 * j + r];
+    } else if (t < Q_B4) {
+      const int i = (t - Q_W4) >> 3, r = ((t - Q_W4) >> 1) & 3, j = (t - Q_W4) & 1;
+      v = P[OW4 + (4 * j + r) * 16 + i];
+    } else if (t < Q_W5) {
+      const int r = (t - Q_B4) >> 1, j = (t - Q_B4) & 1;
+      v = P[OB4 + 4 * j + r];
+    } else if (t < Q_B5) {
+      const int i = (t - Q_W5) >> 2, o = (t - Q_W5) & 3;
+      v = P[OW5 + o * 8 + i];
+    } else {
+      v = P[OB5 + t - Q_B5];
+    }
+    S[t] = v;
+  }
+}
+
+// quad_perm DPP controls: lane l ^ 1, lane l ^ 2, and lane 4(l / 4) + k
+constexpr int DPP_QXOR1 = 0xB1, DPP_QXOR2 = 0x4E;
+
+template <int CTRL>
+N6_DEV float quad_read(float x) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over the four lanes of a quad, (p0 + p1) + (p2 + p3) up to the order of
+// commutative additions, so every lane of the quad holds the same bits.
+N6_DEV float quad_sum(float x) {
+  x = x + quad_read<DPP_QXOR1>(x);
+  return x + quad_read<DPP_QXOR2>(x);
+}
+
+N6_DEV float relu(float a) { return a > 0.f ? a : 0.f; }
+
+N6_DEV void mlp_quad(const float *S, const float x[6], int r, float z[4]) {
+  // layer 1 (neurons 4k + r) and partial layer-2 sums over them
+  float acc2[32];
+#pragma unroll
+  for (int o = 0; o < 32; ++o) acc2[o] = 0.f;
+#pragma unroll 4
+  for (int k = 0; k < 16; ++k) {
+    const float *w1 = S + Q_W1 + (4 * k + r) * 8;
+    float a = w1[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) a = fmaf(w1[j], x[j], a);
+    a = relu(a);
+    const float *w2 = S + Q_W2 + (4 * k + r) * Q_W2S;
+#pragma unroll
+    for (int o = 0; o < 32; ++o) acc2[o] = fmaf(w2[o], a, acc2[o]);
+  }
+#pragma unroll
+  for (int o = 0; o < 32; ++o) acc2[o] = relu(quad_sum(acc2[o]) + S[Q_B2 + o]);
+  // layer 3: outputs 4j + r over all 32 inputs
+  float a3[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) a3[j] = S[Q_B3 + 4 * r + j];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    const float *w3 = S + Q_W3 + i * 16 + 4 * r;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a3[j] = fmaf(w3[j], acc2[i], a3[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) a3[j] = relu(a3[j]);
+  // layer 4: outputs 4j + r over the 16 layer-3 outputs (input 4j' + r' from lane r')
+  float a4[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) a4[j] = S[Q_B4 + 2 * r + j];
+#pragma unroll
+  for (int jp = 0; jp < 4; ++jp) {
+    const float in[4] = {quad_read<0x00>(a3[jp]), quad_read<0x55>(a3[jp]),
+                         quad_read<0xAA>(a3[jp]), quad_read<0xFF>(a3[jp])};
+#pragma unroll
+    for (int rp = 0; rp < 4; ++rp) {
+      const float *w4 = S + Q_W4 + (4 * jp + rp) * 8 + 2 * r;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) a4[j] = fmaf(w4[j], in[rp], a4[j]);
+    }
+  }
+  // layer 5 in every lane over the 8 layer-4 outputs
+#pragma unroll
+  for (int o = 0; o < 4; ++o) z[o] = S[Q_B5 + o];
+#pragma unroll
+  for (int jp = 0; jp < 2; ++jp) {
+    const float v = relu(a4[jp]);
+    const float in[4] = {quad_read<0x00>(v), quad_read<0x55>(v), quad_read<0xAA>(v),
+                         quad_read<0xFF>(v)};
+#pragma unroll
+    for (int rp = 0; rp < 4; ++rp)
+#pragma unroll
+      for (int o = 0; o < 4; ++o) z[o] = fmaf(S[Q_W5 + (4 * jp + rp) * 4 + o], in[rp], z[o]);
+  }
+}
+
+// FP32 re-check of queued evaluations, one quad of lanes per entry; flips the
+// stored nibble where the FP32 label differs and flags the entry.  Every lane
+// of a quad runs the same loop trips (the entry index is per quad), so the
+// cross-lane reads always find their partners active.
 template <int DIM>
 __global__ void __launch_bounds__(TPB)
 k_recheck(Line1D ln, Grid2D gd, int dir, const void *__restrict__ prepared,
           const float *__restrict__ q, uint8_t *__restrict__ masks, const u32 *__restrict__ queue,
           const u32 *__restrict__ qcount, int64_t qcap, uint8_t *__restrict__ qflag) {
+  constexpr int EPB = TPB / 4;  // entries per workgroup and pass
   const int64_t nq = (int64_t)*qcount < qcap ? (int64_t)*qcount : qcap;
   const int64_t nf = DIM == 1 ? ln.faces() : (dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1));
-  if (blockIdx.x * (int64_t)TPB >= nq) return;  // block-uniform: nothing queued for this block
-  // FP32 weights staged in LDS; the network runs input-stationary (32
-  // independent accumulators per lane instead of one serial chain)
-  __shared__ float S[S_SIZE];
-  stage_params<float>((const float *)prepared, S);
+  if (blockIdx.x * (int64_t)EPB >= nq) return;  // block-uniform: nothing queued for this block
+  __shared__ __attribute__((aligned(16))) float S[Q_SIZE];
+  stage_params_quad((const float *)prepared, S);
   __syncthreads();
-  for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < nq; i += (int64_t)gridDim.x * TPB) {
+  const int r = threadIdx.x & 3;
+  for (int64_t i = blockIdx.x * (int64_t)EPB + (threadIdx.x >> 2); i < nq;
+       i += (int64_t)gridDim.x * EPB) {
     const u32 ent = queue[i];
     const int64_t f = ent >> 3;
     const int e = ent & 7;
@@ -538,14 +676,19 @@ k_recheck(Line1D ln, Grid2D gd, int dir, const void *__restrict__ prepared,
       for (int k = 1; k < 2 * (DIM == 1 ? 3 : 4); ++k) v = e == k ? s[k][j] : v;
       se[j] = v;
     }
-    const u32 sel32 = classify_lean<float>(S, se);
-    const int64_t mi = (int64_t)(e >> 1) * nf + f;
-    const u32 shift = (u32)((mi & 3) * 8 + (e & 1) * 4);
-    u32 *word = (u32 *)(masks + (mi & ~(int64_t)3));
-    const u32 old = (masks[mi] >> ((e & 1) * 4)) & 15u;
-    const bool flip = old != sel32;
-    if (flip) atomicXor(word, (old ^ sel32) << shift);
-    qflag[i] = flip ? 1 : 0;
+    float x[6], z[4];
+    features<float>(se, x);
+    mlp_quad(S, x, r, z);
+    const u32 sel32 = mask_from_logits<float>(z);
+    if (r == 0) {
+      const int64_t mi = (int64_t)(e >> 1) * nf + f;
+      const u32 shift = (u32)((mi & 3) * 8 + (e & 1) * 4);
+      u32 *word = (u32 *)(masks + (mi & ~(int64_t)3));
+      const u32 old = (masks[mi] >> ((e & 1) * 4)) & 15u;
+      const bool flip = old != sel32;
+      if (flip) atomicXor(word, (old ^ sel32) << shift);
+      qflag[i] = flip ? 1 : 0;
+    }
   }
 }
 
@@ -721,7 +864,25 @@ inline unsigned grid_for(int64_t items_per_wave_chunks) {
   return (unsigned)(blocks < 2048 ? (blocks > 0 ? blocks : 1) : 2048);
 }
 
-constexpr unsigned RECHECK_BLOCKS = 512;
+constexpr unsigned RECHECK_BLOCKS = 1024;
+
+// Launch shape of the fused face kernel and of the re-check pair.
+struct FaceLaunch {
+  unsigned grid, rgrid;
+  int waves, xcd;
+};
+
+FaceLaunch face_launch(const FastArgs &fa, int64_t nchunk) {
+  FaceLaunch L;
+  L.waves = (fa.face_waves == 2 || fa.face_waves == 8) ? fa.face_waves : 4;
+  const int64_t need = (nchunk + L.waves - 1) / L.waves;
+  const int64_t cap = fa.face_blocks > 0 ? fa.face_blocks : 2048;
+  const int64_t g = need < cap ? need : cap;
+  L.grid = (unsigned)(g > 0 ? g : 1);
+  L.xcd = (fa.xcd_order && L.grid % 8 == 0) ? 1 : 0;
+  L.rgrid = fa.recheck_blocks > 0 ? (unsigned)fa.recheck_blocks : RECHECK_BLOCKS;
+  return L;
+}
 
 // ---- classifier training on MFMA (BF16, FP32 accumulation) ------------------
 // Tiles of 32 samples per wave, persistent over the mini-batch.  Forward: the
@@ -1085,6 +1246,34 @@ hipError_t launch_fast_reconstruct(const void *prepared, int precision, float ma
   return hipGetLastError();
 }
 
+template <int NV>
+hipError_t launch_faces_kernel(const FaceLaunch &L, const FastArgs &fa, hipStream_t s,
+                               const Line1D &ln, const Grid2D &g, int dir, const float *q,
+                               const uint8_t *mi, float *F, uint8_t *m, u32 *qc) {
+#define N6_FACES(P, W)                                                                        \
+  hipLaunchKernelGGL((k_fast_faces<P, NV, W>), dim3(L.grid), dim3(W * 64), 0, s, ln, g, dir,  \
+                     fa.selector, fa.prepared, fa.margin, q, mi, F, m, fa.scr.queue, qc,      \
+                     fa.scr.qcap, L.xcd)
+  // 2D sweeps: two waves per workgroup spill registers, so they take four
+  const int waves = (NV == 4 && L.waves == 2) ? 4 : L.waves;
+  if constexpr (NV == 3) {
+    if (waves == 2) {
+      if (fa.precision == 2) N6_FACES(2, 2);
+      else N6_FACES(3, 2);
+      return hipGetLastError();
+    }
+  }
+  if (fa.precision == 2) {
+    if (waves == 8) N6_FACES(2, 8);
+    else N6_FACES(2, 4);
+  } else {
+    if (waves == 8) N6_FACES(3, 8);
+    else N6_FACES(3, 4);
+  }
+#undef N6_FACES
+  return hipGetLastError();
+}
+
 hipError_t launch_fast_faces1d(const Line1D &ln, const FastArgs &fa, const float *q,
                                const uint8_t *masks_in, uint8_t *masks_out, float *F,
                                hipStream_t s) {
@@ -1107,21 +1296,14 @@ hipError_t launch_fast_faces1d(const Line1D &ln, const FastArgs &fa, const float
   masks = fa.scr.masks;
   const bool recheck = fa.selector == 0 && fa.margin > 0.f;
   const Grid2D g0{};
-  if (fa.precision == 2)
-    hipLaunchKernelGGL((k_fast_faces<2, 3>), dim3(grid), dim3(TPB), 0, s, ln, g0, 0, fa.selector,
-                       fa.prepared, fa.margin, q, masks_in, F, masks, fa.scr.queue, fa.scr.qcount,
-                       fa.scr.qcap);
-  else
-    hipLaunchKernelGGL((k_fast_faces<3, 3>), dim3(grid), dim3(TPB), 0, s, ln, g0, 0, fa.selector,
-                       fa.prepared, fa.margin, q, masks_in, F, masks, fa.scr.queue, fa.scr.qcount,
-                       fa.scr.qcap);
-  hipError_t e = hipGetLastError();
+  const FaceLaunch L = face_launch(fa, (tf + 63) / 64);
+  hipError_t e = launch_faces_kernel<3>(L, fa, s, ln, g0, 0, q, masks_in, F, masks, fa.scr.qcount);
   if (e != hipSuccess) return e;
   if (recheck) {
     Grid2D gd{};
-    hipLaunchKernelGGL(k_recheck<1>, dim3(RECHECK_BLOCKS), dim3(TPB), 0, s, ln, gd, 0, fa.prepared, q,
+    hipLaunchKernelGGL(k_recheck<1>, dim3(L.rgrid), dim3(TPB), 0, s, ln, gd, 0, fa.prepared, q,
                        masks, fa.scr.queue, fa.scr.qcount, fa.scr.qcap, fa.scr.qflag);
-    hipLaunchKernelGGL(k_fixup<1>, dim3(RECHECK_BLOCKS), dim3(TPB), 0, s, ln, gd, 0, q, masks,
+    hipLaunchKernelGGL(k_fixup<1>, dim3(L.rgrid), dim3(TPB), 0, s, ln, gd, 0, q, masks,
                        fa.scr.queue, fa.scr.qcount, fa.scr.qcap, fa.scr.qflag, F);
     e = hipGetLastError();
   }
@@ -1155,21 +1337,15 @@ hipError_t launch_fast_faces2d(const Grid2D &g, const FastArgs &fa, const float 
     uint8_t *md = masks + (dir == 0 ? 0 : 4 * nfx);
     const uint8_t *mi = masks_in ? masks_in + (dir == 0 ? 0 : 4 * nfx) : nullptr;
     float *Fd = dir == 0 ? Fx : Gy;
-    const unsigned grid = grid_for((nf + 63) / 64);
     u32 *qc = fa.scr.qcount + dir;  // one counter per sweep direction
     const Line1D l0{};
-    if (fa.precision == 2)
-      hipLaunchKernelGGL((k_fast_faces<2, 4>), dim3(grid), dim3(TPB), 0, s, l0, g, dir, fa.selector,
-                         fa.prepared, fa.margin, q, mi, Fd, md, fa.scr.queue, qc, fa.scr.qcap);
-    else
-      hipLaunchKernelGGL((k_fast_faces<3, 4>), dim3(grid), dim3(TPB), 0, s, l0, g, dir, fa.selector,
-                         fa.prepared, fa.margin, q, mi, Fd, md, fa.scr.queue, qc, fa.scr.qcap);
-    hipError_t e = hipGetLastError();
+    const FaceLaunch L = face_launch(fa, (nf + 63) / 64);
+    hipError_t e = launch_faces_kernel<4>(L, fa, s, l0, g, dir, q, mi, Fd, md, qc);
     if (e != hipSuccess) return e;
     if (recheck) {
-      hipLaunchKernelGGL(k_recheck<2>, dim3(RECHECK_BLOCKS), dim3(TPB), 0, s, l0, g, dir, fa.prepared,
+      hipLaunchKernelGGL(k_recheck<2>, dim3(L.rgrid), dim3(TPB), 0, s, l0, g, dir, fa.prepared,
                          q, md, fa.scr.queue, qc, fa.scr.qcap, fa.scr.qflag);
-      hipLaunchKernelGGL(k_fixup<2>, dim3(RECHECK_BLOCKS), dim3(TPB), 0, s, l0, g, dir, q, md,
+      hipLaunchKernelGGL(k_fixup<2>, dim3(L.rgrid), dim3(TPB), 0, s, l0, g, dir, q, md,
                          fa.scr.queue, qc, fa.scr.qcap, fa.scr.qflag, Fd);
       e = hipGetLastError();
       if (e != hipSuccess) return e;

@@ -22,12 +22,13 @@ FP64, FP32, BF16, FP16 = 0, 1, 2, 3
 ADVECTION, EULER1D, EULER2D = 0, 2, 3
 PERIODIC, TRANSMISSIVE = 0, 1
 SEL_MLP, SEL_ALL_SMOOTH, SEL_ALL_DISCARD, SEL_MASKS_IN = 0, 1, 2, 3
+KEEP_MAP = 1
 NPARAM = 3228
 
 EXPORTS = (
     "neno6_status_string", "neno6_version", "neno6_mlp_prepared_bytes", "neno6_mlp_prepare",
     "neno6_mlp_logits", "neno6_reconstruct", "neno6_workspace_size", "neno6_rhs",
-    "neno6_face_fluxes", "neno6_recheck_count", "neno6_step",
+    "neno6_face_fluxes", "neno6_recheck_count", "neno6_autotune", "neno6_step",
     "neno6_rhs_adjoint", "neno6_train_workspace_size", "neno6_classifier_train",
     "neno6_classifier_grad",
 )
@@ -42,12 +43,21 @@ class MlpStruct(C.Structure):
                 ("reserved", C.c_int32)]
 
 
+class TuningStruct(C.Structure):
+    _fields_ = [("face_waves", C.c_int32), ("face_blocks", C.c_int32),
+                ("recheck_blocks", C.c_int32), ("xcd_order", C.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 class ProblemStruct(C.Structure):
     _fields_ = [("equation", C.c_int32), ("bc", C.c_int32), ("precision", C.c_int32),
-                ("selector", C.c_int32), ("n_problems", C.c_int32), ("reserved", C.c_int32),
+                ("selector", C.c_int32), ("n_problems", C.c_int32), ("flags", C.c_int32),
                 ("total_cells", C.c_int64), ("nx", C.c_int64), ("ny", C.c_int64),
                 ("offsets", C.c_void_p), ("offsets_host", C.c_void_p), ("dx", C.c_void_p),
-                ("dx2d", C.c_double), ("dy2d", C.c_double), ("gamma", C.c_double)]
+                ("dx2d", C.c_double), ("dy2d", C.c_double), ("gamma", C.c_double),
+                ("tuning", C.POINTER(TuningStruct))]
 
 
 _lock = threading.Lock()
@@ -78,6 +88,8 @@ def load(path: str = LIB_PATH):
         lib.neno6_rhs.argtypes = [P(ProblemStruct), P(MlpStruct), vp, vp, vp, vp, vp, vp, sz, vp]
         lib.neno6_face_fluxes.argtypes = [P(ProblemStruct), P(MlpStruct), vp, vp, vp, vp, sz, vp]
         lib.neno6_recheck_count.argtypes = [P(ProblemStruct), vp, sz, P(C.c_uint32), vp]
+        lib.neno6_autotune.argtypes = [P(ProblemStruct), P(MlpStruct), vp, vp, sz, i32,
+                                       P(TuningStruct), P(C.c_float), vp]
         lib.neno6_step.argtypes = [P(ProblemStruct), P(MlpStruct), vp, f64, i32, vp, vp, vp, sz, vp]
         lib.neno6_rhs_adjoint.argtypes = [P(ProblemStruct), vp, vp, vp, vp]
         lib.neno6_train_workspace_size.argtypes = [i32]
@@ -186,9 +198,12 @@ class Problem:
 
     def __init__(self, equation: int, precision: int, selector: int = SEL_MLP, bc: int = TRANSMISSIVE,
                  offsets=None, dx=None, nx: int = 0, ny: int = 0, dx2d: float = 0.0,
-                 dy2d: float = 0.0, gamma: float = 1.4, device="cuda"):
+                 dy2d: float = 0.0, gamma: float = 1.4, device="cuda", tuning=None):
         self.equation, self.precision, self.selector, self.bc = equation, precision, selector, bc
         self.gamma = float(gamma)
+        self.flags = 0  # KEEP_MAP once the caller's workspace holds the face map
+        self.tuning = None
+        self.set_tuning(tuning)
         if equation == EULER2D:
             self.nx, self.ny, self.dx2d, self.dy2d = int(nx), int(ny), float(dx2d), float(dy2d)
             self.n_problems = 1
@@ -204,6 +219,14 @@ class Problem:
             self.nx = self.ny = 0
             self.dx2d = self.dy2d = 0.0
 
+    def set_tuning(self, tuning):
+        """Launch shapes (dict with the neno6_tuning fields, a TuningStruct,
+        or None for the library defaults)."""
+        if tuning is None or isinstance(tuning, TuningStruct):
+            self.tuning = tuning
+        else:
+            self.tuning = TuningStruct(*(int(tuning.get(k, 0)) for k, _ in TuningStruct._fields_))
+
     @property
     def nvar(self) -> int:
         return {ADVECTION: 1, EULER1D: 3, EULER2D: 4}[self.equation]
@@ -218,12 +241,14 @@ class Problem:
         return self.nvar * self.n_faces
 
     def struct(self) -> ProblemStruct:
-        return ProblemStruct(self.equation, self.bc, self.precision, self.selector, self.n_problems, 0,
+        return ProblemStruct(self.equation, self.bc, self.precision, self.selector, self.n_problems,
+                             self.flags,
                              self.total_cells, self.nx, self.ny,
                              None if self.offsets is None else self.offsets.data_ptr(),
                              None if self.offsets_host is None else self.offsets_host.data_ptr(),
                              None if self.dx is None else self.dx.data_ptr(),
-                             self.dx2d, self.dy2d, self.gamma)
+                             self.dx2d, self.dy2d, self.gamma,
+                             None if self.tuning is None else C.pointer(self.tuning))
 
     def workspace(self, device="cuda") -> torch.Tensor:
         nb = int(load().neno6_workspace_size(C.byref(self.struct())))
@@ -269,6 +294,20 @@ def neno6_recheck_count(prob: Problem, ws: torch.Tensor, stream=None):
     _check(load().neno6_recheck_count(C.byref(ps), _ptr(ws), ws.numel(), cnt, _stream(stream)),
            "neno6_recheck_count")
     return int(cnt[0]), int(cnt[1])
+
+
+def neno6_autotune(prob: Problem, mlp: Mlp, q: torch.Tensor, ws: torch.Tensor, reps: int = 3,
+                   stream=None):
+    """Times the fused face pass for the library's candidate launch shapes;
+    returns (TuningStruct of the fastest, its mean pass time in ms)."""
+    _dev(q, fdtype(prob.precision), "q")
+    if q.numel() != prob.nvar * prob.total_cells:
+        raise ValueError("state size mismatch")
+    best, ms = TuningStruct(), C.c_float(0.0)
+    ps = prob.struct()
+    _check(load().neno6_autotune(C.byref(ps), _mlp(mlp), _ptr(q), _ptr(ws), ws.numel(), int(reps),
+                                 C.byref(best), C.byref(ms), _stream(stream)), "neno6_autotune")
+    return best, float(ms.value)
 
 
 def neno6_step(prob: Problem, mlp: Mlp | None, q: torch.Tensor, cfl: float, n_steps: int,

@@ -1,0 +1,65 @@
+"""Launches the hot kernels on the benchmark workload for profiling, plus a
+plain device copy of known size that calibrates the memory counters.
+
+    rocprofv3 --pmc FETCH_SIZE --kernel-trace --output-format csv -d OUT -o run -- \
+        python3 paper_2207_08500_amd/profile_kernels.py
+    rocprofv3 --pmc WRITE_SIZE --kernel-trace --output-format csv -d OUT -o run -- \
+        python3 paper_2207_08500_amd/profile_kernels.py
+
+Workload: 256 independent 1D Euler Riemann problems of 4000 cells (the
+benchmark's), FP32 state, BF16/FP16 classifier; the FP64 plain path once.
+"""
+import argparse
+import os
+import sys
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+from paper_2207_08500_amd import inputs, native  # noqa: E402
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--no-fp64", action="store_true")
+    a = ap.parse_args()
+    native.load()
+    dev = torch.device("cuda:0")
+    P = np.load(os.path.join(ROOT, "tests", "golden", "neno6_mlp_trained.npy"), allow_pickle=False)
+    q0, off, dx = inputs.riemann1d_batch(inputs.BASE_SEED, (4000,) * 256)
+    q32 = torch.as_tensor(q0, dtype=torch.float32, device=dev).contiguous()
+    faces = int(off[-1]) + 256
+    for prec in (native.BF16, native.FP16):
+        mlp = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=0.0)
+        prob = native.Problem(native.EULER1D, prec, native.SEL_MLP, native.TRANSMISSIVE, off, dx,
+                              device=dev)
+        ws = prob.workspace(dev)
+        F = torch.zeros(3 * faces, dtype=torch.float32, device=dev)
+        for _ in range(a.reps):
+            native.neno6_face_fluxes(prob, mlp, q32, F, ws)
+        torch.cuda.synchronize()
+    if not a.no_fp64:
+        mlp = native.Mlp(torch.as_tensor(P, device=dev))
+        prob = native.Problem(native.EULER1D, native.FP64, native.SEL_MLP, native.TRANSMISSIVE,
+                              off, dx, device=dev)
+        F = torch.zeros(3 * faces, dtype=torch.float64, device=dev)
+        native.neno6_face_fluxes(prob, mlp, q32.double().contiguous(), F, prob.workspace(dev))
+        torch.cuda.synchronize()
+    # calibration: a plain copy of copy_mib MiB (reads and writes that many bytes)
+    n = a.copy_mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print("profiled: fused face kernel x%d (BF16, FP16), FP64 path x1, copy %d MiB"
+          % (a.reps, a.copy_mib))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,180 @@
+"""Batched uneven 1D Euler on the GPU: 4096 independent Riemann problems with
+N drawn log-uniformly from [256, 16384] (about 15.9 M cells, 15.9 M faces
+per stage).
+
+* FP64: one RK3 step of the whole batch, bit for bit against the oracle on a
+  sample of its problems (problems are independent, so a sub-batch gives the
+  same values); the smallest and largest problems are always in the sample.
+* BF16: the face pass gives bitwise the same fluxes and labels under every
+  launch shape tried (default, autotuned, and extremes of the candidate set):
+  a face's arithmetic does not depend on the tile or workgroup it runs in.
+* BF16: ten RK3 steps captured in one HIP graph with the autotuned shapes;
+  replays equal the eager run bit for bit, and the state is compared with
+  the FP64 run (flip rate, L1 / Linf printed and bounded).
+"""
+import os
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_08500_amd import inputs
+from tests._helpers import dev, host, label_flip_rate, need_gpu, trained_params
+
+pytestmark = pytest.mark.gpu
+
+MARGIN_BF16 = 0.5
+
+
+@pytest.fixture(scope="module")
+def c4():
+    need_gpu()
+    import torch
+    from paper_2207_08500_amd import native
+    sizes = inputs.uneven_sizes(inputs.BASE_SEED, 4096, 256, 16384)
+    q, off, dx = inputs.riemann1d_batch(inputs.BASE_SEED, sizes)
+    return native, torch, trained_params(), sizes, q, off, dx
+
+
+def _physical(q, off, gamma=1.4):
+    """Per problem: every cell finite with positive density and pressure."""
+    rho, mom, E = q
+    with np.errstate(all="ignore"):
+        p = (gamma - 1.0) * (E - 0.5 * mom * mom / rho)
+        good = np.isfinite(rho) & np.isfinite(p) & (rho > 0) & (p > 0)
+    return np.minimum.reduceat(good.astype(np.int8), off[:-1]).astype(bool)
+
+
+def _sample(sizes, k=10, seed=11):
+    order = np.argsort(sizes, kind="stable")
+    rng = np.random.default_rng(seed)
+    pick = set(order[:2].tolist()) | set(order[-2:].tolist())
+    pick |= set(rng.choice(sizes.size, k, replace=False).tolist())
+    return sorted(pick)
+
+
+def test_c4_fp64_step_sampled_bitwise(c4):
+    native, torch, P, sizes, q, off, dx = c4
+    mlp = native.Mlp(dev(P))
+    prob = native.Problem(native.EULER1D, native.FP64, native.SEL_MLP, native.TRANSMISSIVE, off, dx)
+    qg = dev(q)
+    t = torch.zeros(4096, dtype=torch.float64, device="cuda")
+    st = torch.zeros(4096, dtype=torch.int32, device="cuda")
+    native.neno6_step(prob, mlp, qg, 0.4, 1, t, st, prob.workspace())
+    torch.cuda.synchronize()
+    qh, th, sh = host(qg).reshape(3, -1), host(t), host(st)
+    pick = _sample(sizes)
+    sub = np.concatenate([q[:, off[p]:off[p + 1]] for p in pick], axis=1)
+    o_sub = np.concatenate([[0], np.cumsum(sizes[pick])])
+    q_o, t_o, s_o = oracle.euler1d_step(sub, o_sub, dx[pick], 0.4, 1, 1.4, oracle.BC_TRANSMISSIVE,
+                                        P, oracle.SEL_MLP)
+    for i, p in enumerate(pick):
+        assert sh[p] == s_o[i]
+        assert th[p] == t_o[i]
+        got = qh[:, off[p]:off[p + 1]]
+        want = q_o[:, o_sub[i]:o_sub[i + 1]]
+        assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), "problem %d (N=%d)" % (
+            p, sizes[p])
+
+
+def test_c4_launch_shapes_bitwise(c4):
+    native, torch, P, sizes, q, off, dx = c4
+    from paper_2207_08500_amd import autotune
+    q32 = dev(q, torch.float32)
+    mlp = native.Mlp(dev(P), recheck_margin=MARGIN_BF16)
+    prob = native.Problem(native.EULER1D, native.BF16, native.SEL_MLP, native.TRANSMISSIVE, off, dx)
+    ws = prob.workspace()
+    shapes, ms = autotune.tuned(prob, mlp, q32, ws, path=os.path.join(
+        os.environ.get("TMPDIR", "/tmp"), "neno6_tuning_test_%d.json" % os.getpid()), refresh=True)
+    print("C4 autotuned shapes %s: %.3f ms per face pass" % (shapes, ms))
+    nf = prob.n_faces
+    res = []
+    for tun in (None, shapes,
+                {"face_waves": 2, "face_blocks": 512, "recheck_blocks": 128, "xcd_order": 1},
+                {"face_waves": 8, "face_blocks": 65536, "recheck_blocks": 2048, "xcd_order": 0}):
+        prob.set_tuning(tun)
+        F = torch.zeros(3 * nf, dtype=torch.float32, device="cuda")
+        m = torch.zeros(3 * nf, dtype=torch.uint8, device="cuda")
+        native.neno6_face_fluxes(prob, mlp, q32, F, ws, masks_out=m)
+        torch.cuda.synchronize()
+        res.append((host(F), host(m)))
+    for F, m in res[1:]:
+        assert np.array_equal(F.view(np.uint32), res[0][0].view(np.uint32))
+        assert np.array_equal(m, res[0][1])
+
+
+def test_c4_graph_ten_steps_bf16(c4):
+    native, torch, P, sizes, q, off, dx = c4
+    from paper_2207_08500_amd import autotune
+    q32 = dev(q, torch.float32)
+    faces_step = 3 * (int(off[-1]) + 4096)
+    mlp = native.Mlp(dev(P), recheck_margin=MARGIN_BF16)
+    prob = native.Problem(native.EULER1D, native.BF16, native.SEL_MLP, native.TRANSMISSIVE, off, dx)
+    ws = prob.workspace()
+    autotune.tuned(prob, mlp, q32, ws, path=os.path.join(
+        os.environ.get("TMPDIR", "/tmp"), "neno6_tuning_test_%d.json" % os.getpid()))
+    t = torch.zeros(4096, dtype=torch.float64, device="cuda")
+    st = torch.zeros(4096, dtype=torch.int32, device="cuda")
+    # eager reference
+    qe = q32.clone()
+    native.neno6_step(prob, mlp, qe, 0.4, 10, t, st, ws)
+    torch.cuda.synchronize()
+    te, se = host(t), host(st)
+    # one graph replay = ten RK3 steps
+    qg = q32.clone()
+    t.zero_()
+    st.zero_()
+    prob.flags = native.KEEP_MAP
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            native.neno6_step(prob, mlp, qg, 0.4, 10, t, st, ws, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    times = []
+    for rep in range(3):
+        qg.copy_(q32)
+        t.zero_()
+        st.zero_()
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        g.replay()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - c0)
+        assert np.array_equal(host(qg).view(np.uint32), host(qe).view(np.uint32)), "replay %d" % rep
+        assert np.array_equal(host(t), te) and np.array_equal(host(st), se)
+    best = min(times)
+    print("C4 BF16: one graph replay = 10 RK3 steps of %d faces in %.2f ms = %.3g faces/s"
+          % (faces_step, best * 1e3, 10 * faces_step / best))
+    # FP64 run of the same ten steps from the same (FP32-rounded) state
+    mlp64 = native.Mlp(dev(P))
+    p64 = native.Problem(native.EULER1D, native.FP64, native.SEL_MLP, native.TRANSMISSIVE, off, dx)
+    q64 = q32.double().contiguous()
+    t64 = torch.zeros(4096, dtype=torch.float64, device="cuda")
+    s64 = torch.zeros(4096, dtype=torch.int32, device="cuda")
+    w64 = p64.workspace()
+    m64 = torch.zeros(p64.mask_count(), dtype=torch.uint8, device="cuda")
+    native.neno6_rhs(p64, mlp64, q64, torch.zeros_like(q64), w64, masks_out=m64)
+    mb = torch.zeros(prob.mask_count(), dtype=torch.uint8, device="cuda")
+    prob.flags = 0
+    native.neno6_rhs(prob, mlp, q32, torch.zeros_like(q32), ws, masks_out=mb)
+    native.neno6_step(p64, mlp64, q64, 0.4, 10, t64, s64, w64)
+    torch.cuda.synchronize()
+    flip = label_flip_rate(host(mb), host(m64))
+    qb, qd = host(qe).reshape(3, -1).astype(np.float64), host(q64).reshape(3, -1)
+    # problems frozen by either run, or whose state left the physical range in
+    # the last step (the solver freezes a problem at the start of a step)
+    ok = (host(s64) == 0) & (se == 0) & _physical(qb, off) & _physical(qd, off)
+    cell_ok = np.repeat(ok, sizes)
+    d = np.abs(qb - qd)[:, cell_ok]
+    ref = np.abs(qd)[:, cell_ok]
+    l1 = (d.mean(axis=1) / ref.mean(axis=1)).max()
+    linf = (d.max(axis=1) / ref.max(axis=1)).max()
+    print("C4 BF16 vs FP64 after 10 steps: flip rate %.3g, relative L1 %.3g, Linf %.3g, "
+          "frozen %d (bf16) / %d (fp64) of 4096" % (flip, l1, linf, int((se != 0).sum()),
+                                                     int((host(s64) != 0).sum())))
+    assert flip < 1e-4
+    assert ok.sum() > 0.3 * 4096
+    assert l1 < 2e-3

@@ -72,6 +72,33 @@ def test_host_argument_checks():
     assert lib.neno6_workspace_size(C.byref(p1)) == 0
     off[2] = 7
     assert lib.neno6_workspace_size(C.byref(p1)) > 0
+    # launch shapes and flags are validated on the host
+    p1.flags = 2
+    assert lib.neno6_workspace_size(C.byref(p1)) == 0
+    p1.flags = native.KEEP_MAP
+    assert lib.neno6_workspace_size(C.byref(p1)) > 0
+    for bad in ((3, 0, 0, 0), (4, -1, 0, 0), (4, 65537, 0, 0), (4, 0, 70000, 0), (4, 0, 0, 2)):
+        tun = native.TuningStruct(*bad)
+        p1.tuning = C.pointer(tun)
+        assert lib.neno6_workspace_size(C.byref(p1)) == 0, bad
+    tun = native.TuningStruct(8, 1024, 512, 1)
+    p1.tuning = C.pointer(tun)
+    assert lib.neno6_workspace_size(C.byref(p1)) > 0
+    # the autotuner takes reduced-precision Euler problems with the classifier only
+    best = native.TuningStruct()
+    assert lib.neno6_autotune(C.byref(p1), None, None, None, 0, 3, C.byref(best), None,
+                              None) == native.UNSUPPORTED
+    p1.precision, p1.selector = native.BF16, native.SEL_MLP
+    assert lib.neno6_autotune(C.byref(p1), None, None, None, 0, 3, C.byref(best), None,
+                              None) == native.BAD_ARG
+    # lines beyond 32-bit re-check queue entries are refused
+    big = np.array([0, 1 << 29], np.int64)
+    p2 = native.ProblemStruct()
+    p2.equation, p2.bc, p2.precision, p2.selector = native.EULER1D, 1, native.BF16, 1
+    p2.n_problems, p2.total_cells, p2.gamma = 1, 1 << 29, 1.4
+    p2.offsets = p2.dx = 1
+    p2.offsets_host = big.ctypes.data
+    assert lib.neno6_workspace_size(C.byref(p2)) == 0
     assert lib.neno6_reconstruct(None, None, 10, 2, 0, 1, None, None, None, None) == native.BAD_ARG
     assert lib.neno6_reconstruct(None, None, 10, 1, 0, 0, None, None, None, None) == native.BAD_ARG
     assert lib.neno6_classifier_train(None, None, None, None, None, None, None, 0, 0, 0.0, 0.9,
