@@ -49,7 +49,8 @@ constexpr int TAB_BYTES = TAB_REGS * 64 * 4;
 constexpr int PREP_BF16_OFF = 16384;
 constexpr int PREP_F16_OFF = PREP_BF16_OFF + TAB_BYTES;
 constexpr int PREP_B5_OFF = PREP_F16_OFF + TAB_BYTES;
-constexpr size_t PREP_BYTES = 65536;
+constexpr int PREP_Q_OFF = 65536;  // FP32 image for the re-check kernel (see Q_SIZE)
+constexpr size_t PREP_BYTES = 81920;
 static_assert(PREP_B5_OFF + 16 <= (int)PREP_BYTES, "prepared block layout");
 
 // ---- packing -----------------------------------------------------------------
@@ -528,15 +529,20 @@ constexpr int Q_W1 = 0, Q_W2 = 512, Q_W2S = 36, Q_B2 = Q_W2 + 64 * Q_W2S, Q_W3 =
               Q_B3 = Q_W3 + 512, Q_W4 = Q_B3 + 16, Q_B4 = Q_W4 + 128, Q_W5 = Q_B4 + 8,
               Q_B5 = Q_W5 + 32, Q_SIZE = Q_B5 + 4;
 
-N6_DEV void stage_params_quad(const float *__restrict__ P, float *S) {
-  for (int t = threadIdx.x; t < Q_SIZE; t += blockDim.x) {
-    float v = 0.f;
+static_assert(Q_SIZE % 4 == 0 && PREP_Q_OFF + 4 * Q_SIZE <= (int)PREP_BYTES &&
+                  PREP_B5_OFF + 16 <= PREP_Q_OFF,
+              "prepared block layout");
+
+// Element t of the re-check image (written once by k_prepare).
+N6_DEV float quad_image_value(const double *__restrict__ P, int t) {
+  double v = 0.0;
+  {
     if (t < Q_W2) {
       const int o = t >> 3, k = t & 7;
-      v = k < 6 ? P[OW1 + o * 6 + k] : (k == 6 ? P[OB1 + o] : 0.f);
+      v = k < 6 ? P[OW1 + o * 6 + k] : (k == 6 ? P[OB1 + o] : 0.0);
     } else if (t < Q_B2) {
       const int i = (t - Q_W2) / Q_W2S, o = (t - Q_W2) % Q_W2S;
-      v = o < 32 ? P[OW2 + o * 64 + i] : 0.f;
+      v = o < 32 ? P[OW2 + o * 64 + i] : 0.0;
     } else if (t < Q_W3) {
       v = P[OB2 + t - Q_B2];
     } else if (t < Q_B3) {
@@ -557,8 +563,8 @@ N6_DEV void stage_params_quad(const float *__restrict__ P, float *S) {
     } else {
       v = P[OB5 + t - Q_B5];
     }
-    S[t] = v;
   }
+  return (float)v;
 }
 
 // quad_perm DPP controls: lane l ^ 1, lane l ^ 2, and lane 4(l / 4) + k
@@ -584,7 +590,7 @@ N6_DEV void mlp_quad(const float *S, const float x[6], int r, float z[4]) {
   float acc2[32];
 #pragma unroll
   for (int o = 0; o < 32; ++o) acc2[o] = 0.f;
-#pragma unroll 4
+#pragma unroll 1
   for (int k = 0; k < 16; ++k) {
     const float *w1 = S + Q_W1 + (4 * k + r) * 8;
     float a = w1[6];
@@ -601,7 +607,7 @@ N6_DEV void mlp_quad(const float *S, const float x[6], int r, float z[4]) {
   float a3[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) a3[j] = S[Q_B3 + 4 * r + j];
-#pragma unroll
+#pragma unroll 4
   for (int i = 0; i < 32; ++i) {
     const float *w3 = S + Q_W3 + i * 16 + 4 * r;
 #pragma unroll
@@ -639,12 +645,22 @@ N6_DEV void mlp_quad(const float *S, const float x[6], int r, float z[4]) {
   }
 }
 
+// Split stencil E (field E / 2, sign E % 2) of 1D face f: the full set-up
+// with the other fields' work left to dead-code elimination.
+template <int E>
+N6_DEV void stencil_one(const Line1D &ln, const float *__restrict__ q, int64_t f, float se[6]) {
+  float s[6][6], R[3][3];
+  setup1d(ln, q, f, s, R);
+#pragma unroll
+  for (int j = 0; j < 6; ++j) se[j] = s[E][j];
+}
+
 // FP32 re-check of queued evaluations, one quad of lanes per entry; flips the
 // stored nibble where the FP32 label differs and flags the entry.  Every lane
 // of a quad runs the same loop trips (the entry index is per quad), so the
 // cross-lane reads always find their partners active.
 template <int DIM>
-__global__ void __launch_bounds__(TPB)
+__global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2)))
 k_recheck(Line1D ln, Grid2D gd, int dir, const void *__restrict__ prepared,
           const float *__restrict__ q, uint8_t *__restrict__ masks, const u32 *__restrict__ queue,
           const u32 *__restrict__ qcount, int64_t qcap, uint8_t *__restrict__ qflag) {
@@ -653,7 +669,10 @@ k_recheck(Line1D ln, Grid2D gd, int dir, const void *__restrict__ prepared,
   const int64_t nf = DIM == 1 ? ln.faces() : (dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1));
   if (blockIdx.x * (int64_t)EPB >= nq) return;  // block-uniform: nothing queued for this block
   __shared__ __attribute__((aligned(16))) float S[Q_SIZE];
-  stage_params_quad((const float *)prepared, S);
+  {
+    const float4 *src = (const float4 *)((const char *)prepared + PREP_Q_OFF);
+    for (int t = threadIdx.x; t < Q_SIZE / 4; t += TPB) ((float4 *)S)[t] = src[t];
+  }
   __syncthreads();
   const int r = threadIdx.x & 3;
   for (int64_t i = blockIdx.x * (int64_t)EPB + (threadIdx.x >> 2); i < nq;
@@ -661,20 +680,26 @@ k_recheck(Line1D ln, Grid2D gd, int dir, const void *__restrict__ prepared,
     const u32 ent = queue[i];
     const int64_t f = ent >> 3;
     const int e = ent & 7;
-    float s[8][6], R[4][4];
-    if (DIM == 1) {
-      float R3[3][3];
-      setup1d(ln, q, f, *(float(*)[6][6])s, R3);
-    } else {
+    float se[6];
+    if constexpr (DIM == 1) {  // 1D: only the queued evaluation's stencil is formed
+      switch (e) {
+      case 0: stencil_one<0>(ln, q, f, se); break;
+      case 1: stencil_one<1>(ln, q, f, se); break;
+      case 2: stencil_one<2>(ln, q, f, se); break;
+      case 3: stencil_one<3>(ln, q, f, se); break;
+      case 4: stencil_one<4>(ln, q, f, se); break;
+      default: stencil_one<5>(ln, q, f, se); break;
+      }
+    } else {  // 2D: all eight, the queued one selected without a dynamic register index
+      float s[8][6], R[4][4];
       setup2d(gd, dir, q, f, s, R);
-    }
-    float se[6];  // the queued stencil, selected without a dynamic register index
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      float v = s[0][j];
+      for (int j = 0; j < 6; ++j) {
+        float v = s[0][j];
 #pragma unroll
-      for (int k = 1; k < 2 * (DIM == 1 ? 3 : 4); ++k) v = e == k ? s[k][j] : v;
-      se[j] = v;
+        for (int k = 1; k < 8; ++k) v = e == k ? s[k][j] : v;
+        se[j] = v;
+      }
     }
     float x[6], z[4];
     features<float>(se, x);
@@ -811,6 +836,7 @@ __global__ void __launch_bounds__(TPB) k_prepare(const double *__restrict__ P, c
   const int t = blockIdx.x * TPB + threadIdx.x;
   if (t < NPARAM) ((float *)prep)[t] = (float)P[t];
   if (t < 4) ((float *)(prep + PREP_B5_OFF))[t] = (float)P[OB5 + t];
+  if (t < Q_SIZE) ((float *)(prep + PREP_Q_OFF))[t] = quad_image_value(P, t);
   if (t >= TAB_REGS * 64) return;
   const int reg = t / 64, lane = t % 64, i = lane % 32, h = lane / 32;
   float v[2];

@@ -393,19 +393,20 @@ k_diff1d(Line1D ln, int nvar, const T *__restrict__ Fh, const T *__restrict__ q,
   }
 }
 
-// Time step of each line at the start of an RK3 step: one block per line.
+// Time step of each line at the start of an RK3 step: one 1024-thread block
+// per line (enough loads in flight per line), wave-level max by shuffles.
+constexpr int CFL_TPB = 1024;
+
 template <typename T>
-__global__ void __launch_bounds__(TPB)
+__global__ void __launch_bounds__(CFL_TPB)
 k_cfl1d(Line1D ln, int equation, const T *__restrict__ q, double cfl, double *__restrict__ dt,
         int32_t *__restrict__ status, double *__restrict__ t) {
   const int p = blockIdx.x;
   const int64_t o = ln.offsets[p], n = ln.offsets[p + 1] - o;
-  __shared__ double red[TPB];
-  __shared__ int bad[TPB];
   double smax = 0.0;
   int b = 0;
   if (equation == 2) {
-    for (int64_t i = threadIdx.x; i < n; i += TPB) {
+    for (int64_t i = threadIdx.x; i < n; i += CFL_TPB) {
       const T qc[3] = {q[o + i], q[ln.total + o + i], q[2 * ln.total + o + i]};
       T u, pr, c;
       prim1d<T>(qc, (T)ln.gamma, u, pr, c);
@@ -414,16 +415,26 @@ k_cfl1d(Line1D ln, int equation, const T *__restrict__ q, double cfl, double *__
       smax = sp > smax ? sp : smax;
     }
   }
-  red[threadIdx.x] = smax;
-  bad[threadIdx.x] = b;
+  // the maximum of the (non-NaN) speeds and the OR of the flags do not depend
+  // on the reduction order
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) {
+    const double o2 = __shfl_xor(smax, d);
+    smax = o2 > smax ? o2 : smax;
+    b |= __shfl_xor(b, d);
+  }
+  __shared__ double red[CFL_TPB / 64];
+  __shared__ int bad[CFL_TPB / 64];
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = smax;
+    bad[threadIdx.x >> 6] = b;
+  }
   __syncthreads();
-  for (int w = TPB / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      const double o2 = red[threadIdx.x + w];
-      red[threadIdx.x] = o2 > red[threadIdx.x] ? o2 : red[threadIdx.x];
-      bad[threadIdx.x] |= bad[threadIdx.x + w];
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < CFL_TPB / 64; ++w) {
+      red[0] = red[w] > red[0] ? red[w] : red[0];
+      bad[0] |= bad[w];
     }
-    __syncthreads();
   }
   if (threadIdx.x == 0) {
     if (status[p] != 0) {
@@ -695,8 +706,8 @@ hipError_t launch_build_fmap(const Line1D &ln, int32_t *fmap, hipStream_t s) {
 template <typename T>
 hipError_t launch_cfl1d(const Line1D &ln, int equation, const T *q, double cfl, double *dt,
                         int32_t *status, double *t, hipStream_t s) {
-  hipLaunchKernelGGL(k_cfl1d<T>, dim3(ln.np), dim3(TPB), 0, s, ln, equation, q, cfl, dt, status,
-                     t);
+  hipLaunchKernelGGL(k_cfl1d<T>, dim3(ln.np), dim3(CFL_TPB), 0, s, ln, equation, q, cfl, dt,
+                     status, t);
   return hipGetLastError();
 }
 
