@@ -23,7 +23,7 @@ _SO = os.path.join(_HERE, "_build", "liboracle_neno6.so")
 _lock = threading.Lock()
 _lib = None
 
-SEL_MLP, SEL_ALL_SMOOTH, SEL_ALL_DISCARD, SEL_MASKS_IN = 0, 1, 2, 3
+SEL_MLP, SEL_ALL_SMOOTH, SEL_ALL_DISCARD, SEL_MASKS_IN, SEL_TENO = 0, 1, 2, 3, 4
 BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
 NPARAM = 3228
 
@@ -31,7 +31,8 @@ NPARAM = 3228
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain FP64, -ffp-contract=off)."""
     os.makedirs(os.path.dirname(_SO), exist_ok=True)
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+    deps = [_SRC, os.path.join(_HERE, "teno_beta.h")]
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < max(map(os.path.getmtime, deps)):
         tmp = _SO + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
                "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
@@ -52,6 +53,7 @@ def _load():
                 "oracle_reconstruct": [d, C.c_int64, C.c_int32, d, C.c_int32, u8, d, u8],
                 "oracle_mlp_logits": [d, d, C.c_int64, d, d],
                 "oracle_mlp_logits_raw": [d, d, C.c_int64, d],
+                "oracle_teno": [d, C.c_int64, d, d, d, u8],
                 "oracle_advection_rhs": [d, C.c_int64, C.c_double, C.c_int32, d, C.c_int32, u8, d, u8],
                 "oracle_advection_step": [d, C.c_int64, C.c_double, C.c_double, C.c_int32, C.c_int32,
                                           d, C.c_int32, u8],
@@ -153,6 +155,18 @@ def mlp_logits_raw(params, x):
     _check(_load().oracle_mlp_logits_raw(_p(P, C.c_double), _p(x, C.c_double), x.shape[0],
                                          _p(z, C.c_double)), "oracle_mlp_logits_raw")
     return z
+
+
+def teno(s):
+    """TENO6-opt quantities of stencils s[n][6]: (beta[n][5] = beta_0..3 and
+    beta_6, tau_6[n], chi[n][4], masks[n]) -- Sec. 2.2-2.3."""
+    s = _f64(np.atleast_2d(s))
+    n = s.shape[0]
+    beta, tau, chi = np.zeros((n, 5)), np.zeros(n), np.zeros((n, 4))
+    m = np.zeros(n, np.uint8)
+    _check(_load().oracle_teno(_p(s, C.c_double), n, _p(beta, C.c_double), _p(tau, C.c_double),
+                               _p(chi, C.c_double), _p(m, C.c_uint8)), "oracle_teno")
+    return beta, tau, chi, m
 
 
 def advection_rhs(u, dx, bc=BC_PERIODIC, params=None, selector=SEL_MLP, masks_in=None):

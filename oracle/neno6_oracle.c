@@ -38,6 +38,7 @@
 #define SEL_ALL_SMOOTH 1
 #define SEL_ALL_DISCARD 2
 #define SEL_MASKS_IN 3
+#define SEL_TENO 4
 #define BC_PERIODIC 0
 #define BC_TRANSMISSIVE 1
 #define ST_OK 0
@@ -163,11 +164,86 @@ static unsigned classify(const double *P, const double s[6]) {
   return sel;
 }
 
+/* ------------------------------------------------------------------------ */
+/* TENO6-opt stencil selection (Sec. 2.2 and 2.3): smoothness indicators     */
+/* (eq. measureTENO) with the sixth-order reference tau_6 (eq. taukTENO),    */
+/* normalisation (eq. normalize) and sharp cut-off (eq. cut-off).  The beta  */
+/* quadratic forms follow the Jiang-Shu definition the paper points to; see  */
+/* gen_teno_beta.py.  Canonical order:                                        */
+/*   d_a   = s[first+a+1] - s[first+a], a = 0 .. len-2 (differences, so    */
+/*           constant data give beta = 0 exactly);                            */
+/*   beta  = fma chain over a ascending of d_a * t_a, t_a = fma chain over   */
+/*           b ascending of D[a][b] * d_b (both from 0);                     */
+/*   tau   = |beta6 - ((beta1 + beta2) + 4 beta0) / 6|;                      */
+/*   x_k   = C + tau / (beta_k + eps); gamma_k = (x^2)^2 * x^2;              */
+/*   chi_k = gamma_k / (((gamma0 + gamma1) + gamma2) + gamma3);              */
+/*   delta_k = 0 if chi_k < C_T else 1 (bit k of the mask).                  */
+/* Constants as printed: C = 1, q = 6, eps = 1e-40, C_T = 1e-6.              */
+/* Pins: the three-point forms equal the Jiang-Shu closed forms; every form  */
+/* gives the exact derivative integrals of cell-averaged monomials; tau_6 is */
+/* sixth order on smooth data; a step removes exactly the candidates that    */
+/* cross it.                                                                 */
+/* ------------------------------------------------------------------------ */
+#include "teno_beta.h"
+
+static const double TENO_C = 1.0, TENO_EPS = 1e-40, TENO_CT = 1e-6;
+
+static double beta_form(const double D[5][5], int first, int len, const double s[6]) {
+  double d[5];
+  for (int a = 0; a < len - 1; ++a) d[a] = s[first + a + 1] - s[first + a];
+  double beta = 0.0;
+  for (int a = 0; a < len - 1; ++a) {
+    double t = 0.0;
+    for (int b = 0; b < len - 1; ++b) t = fma(D[a][b], d[b], t);
+    beta = fma(d[a], t, beta);
+  }
+  return beta;
+}
+
+/* beta[0..3] of the candidates S0..S3, beta[4] of the full stencil. */
+static unsigned teno_indicators(const double s[6], double beta[5], double *tau, double chi[4]) {
+  beta[0] = beta_form(TENO_D_S0, 1, 3, s);
+  beta[1] = beta_form(TENO_D_S1, 2, 3, s);
+  beta[2] = beta_form(TENO_D_S2, 0, 3, s);
+  beta[3] = beta_form(TENO_D_S3, 2, 4, s);
+  beta[4] = beta_form(TENO_D_S6, 0, 6, s);
+  const double t = fabs(beta[4] - ((beta[1] + beta[2]) + 4.0 * beta[0]) / 6.0);
+  double g[4];
+  for (int k = 0; k < 4; ++k) {
+    const double x = TENO_C + t / (beta[k] + TENO_EPS);
+    const double x2 = x * x;
+    g[k] = (x2 * x2) * x2;
+  }
+  const double sum = ((g[0] + g[1]) + g[2]) + g[3];
+  unsigned sel = 0;
+  for (int k = 0; k < 4; ++k) {
+    chi[k] = g[k] / sum;
+    if (!(chi[k] < TENO_CT)) sel |= 1u << k;
+  }
+  *tau = t;
+  return sel;
+}
+
+static unsigned teno_select(const double s[6]) {
+  double beta[5], tau, chi[4];
+  return teno_indicators(s, beta, &tau, chi);
+}
+
+/* The TENO6-opt quantities for n stencils s[n][6]: beta[n][5], tau[n],
+ * chi[n][4], masks[n] (bit k = candidate k kept). */
+int oracle_teno(const double *s, int64_t n, double *beta, double *tau, double *chi,
+                uint8_t *masks) {
+  for (int64_t e = 0; e < n; ++e)
+    masks[e] = (uint8_t)teno_indicators(s + 6 * e, beta + 5 * e, tau + e, chi + 4 * e);
+  return ST_OK;
+}
+
 static unsigned select_mask(int selector, const double *P, const double s[6], unsigned mask_in) {
   switch (selector) {
   case SEL_MLP: return classify(P, s);
   case SEL_ALL_SMOOTH: return 15u;
   case SEL_ALL_DISCARD: return 0u;
+  case SEL_TENO: return teno_select(s);
   default: return mask_in & 15u;
   }
 }
@@ -198,7 +274,7 @@ int oracle_mlp_logits_raw(const double *P, const double *x, int64_t n, double *z
 int oracle_reconstruct(const double *f, int64_t n_faces, int32_t sign, const double *P,
                        int32_t selector, const uint8_t *masks_in, double *fhat,
                        uint8_t *masks_out) {
-  if (n_faces < 0 || (sign != 1 && sign != -1) || selector < 0 || selector > 3) return ST_BAD_ARG;
+  if (n_faces < 0 || (sign != 1 && sign != -1) || selector < 0 || selector > 4) return ST_BAD_ARG;
   if (selector == SEL_MASKS_IN && !masks_in) return ST_BAD_ARG;
   if (selector == SEL_MLP && !P) return ST_BAD_ARG;
   for (int64_t k = 0; k < n_faces; ++k) {
@@ -432,7 +508,7 @@ int oracle_euler1d_rhs(const double *q, const int64_t *offsets, int32_t n_proble
                        const double *dx, double gamma, int32_t bc, const double *P,
                        int32_t selector, const uint8_t *masks_in, double *rhs,
                        uint8_t *masks_out, int32_t *status) {
-  if (n_problems < 0 || (bc != 0 && bc != 1) || selector < 0 || selector > 3) return ST_BAD_ARG;
+  if (n_problems < 0 || (bc != 0 && bc != 1) || selector < 0 || selector > 4) return ST_BAD_ARG;
   const int64_t total = offsets[n_problems];
   const int64_t tf = total + n_problems;
   int bad = 0;
@@ -680,7 +756,7 @@ int oracle_euler2d_rhs(const double *q, int64_t nx, int64_t ny, double dx, doubl
                        int32_t bc, const double *P, int32_t selector, const uint8_t *mx_in,
                        const uint8_t *my_in, double *rhs, uint8_t *mx_out, uint8_t *my_out,
                        int32_t *status) {
-  if (nx < 1 || ny < 1 || (bc != 0 && bc != 1) || selector < 0 || selector > 3) return ST_BAD_ARG;
+  if (nx < 1 || ny < 1 || (bc != 0 && bc != 1) || selector < 0 || selector > 4) return ST_BAD_ARG;
   if (selector == SEL_MASKS_IN && (!mx_in || !my_in)) return ST_BAD_ARG;
   const int64_t cells = nx * ny;
   const int64_t nfx = (nx + 1) * ny, nfy = nx * (ny + 1);
