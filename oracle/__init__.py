@@ -54,6 +54,10 @@ def _load():
                 "oracle_mlp_logits": [d, d, C.c_int64, d, d],
                 "oracle_mlp_logits_raw": [d, d, C.c_int64, d],
                 "oracle_teno": [d, C.c_int64, d, d, d, u8],
+                "oracle_burgers_rhs": [d, i64, C.c_int32, d, C.c_int32, d, C.c_int32, u8, d, u8,
+                                       i32],
+                "oracle_burgers_step": [d, i64, C.c_int32, d, C.c_int32, C.c_double, C.c_int32, d,
+                                        C.c_int32, d, i32],
                 "oracle_advection_rhs": [d, C.c_int64, C.c_double, C.c_int32, d, C.c_int32, u8, d, u8],
                 "oracle_advection_step": [d, C.c_int64, C.c_double, C.c_double, C.c_int32, C.c_int32,
                                           d, C.c_int32, u8],
@@ -238,6 +242,41 @@ def euler1d_step(q, offsets, dx, cfl, n_steps, gamma=1.4, bc=BC_TRANSMISSIVE, pa
                                        _p(P, C.c_double), selector, _p(tt, C.c_double),
                                        _p(st, C.c_int32)), "oracle_euler1d_step")
     return q, tt, st
+
+
+def burgers_rhs(u, offsets, dx, bc=BC_TRANSMISSIVE, params=None, selector=SEL_TENO, masks_in=None):
+    """Inviscid Burgers (Sec. 4.3) on a batch of lines u[total].
+    Returns (rhs[total], masks[total + n_problems], status[n_problems])."""
+    u = _f64(u)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    npb = off.size - 1
+    dxa = _f64(np.broadcast_to(np.asarray(dx, np.float64), (npb,)))
+    P = None if params is None else _f64(params)
+    total = int(off[-1])
+    r = np.zeros(total)
+    m = np.zeros(total + npb, np.uint8)
+    st = np.zeros(npb, np.int32)
+    mi = _u8(masks_in)
+    _check(_load().oracle_burgers_rhs(_p(u, C.c_double), _p(off, C.c_int64), npb, _p(dxa, C.c_double),
+                                      bc, _p(P, C.c_double), selector, _p(mi, C.c_uint8),
+                                      _p(r, C.c_double), _p(m, C.c_uint8), _p(st, C.c_int32)),
+           "oracle_burgers_rhs")
+    return r, m, st
+
+
+def burgers_step(u, offsets, dx, cfl, n_steps, bc=BC_TRANSMISSIVE, params=None, selector=SEL_TENO,
+                 t=None, status=None):
+    u = _f64(u).copy()
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    npb = off.size - 1
+    dxa = _f64(np.broadcast_to(np.asarray(dx, np.float64), (npb,)))
+    P = None if params is None else _f64(params)
+    tt = np.zeros(npb) if t is None else _f64(t).copy()
+    st = np.zeros(npb, np.int32) if status is None else np.ascontiguousarray(status, np.int32).copy()
+    _check(_load().oracle_burgers_step(_p(u, C.c_double), _p(off, C.c_int64), npb, _p(dxa, C.c_double),
+                                       bc, cfl, n_steps, _p(P, C.c_double), selector,
+                                       _p(tt, C.c_double), _p(st, C.c_int32)), "oracle_burgers_step")
+    return u, tt, st
 
 
 def euler2d_rhs(q, dx, dy, gamma=1.4, bc=BC_TRANSMISSIVE, params=None, selector=SEL_MLP,

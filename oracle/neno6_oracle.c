@@ -617,6 +617,133 @@ int oracle_euler1d_step(double *q, const int64_t *offsets, int32_t n_problems, c
   return bad ? ST_BAD_ARG : ST_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Inviscid Burgers equation (Sec. 4.3, eq. Burgers): f(u) = u^2/2,          */
+/* f'(u) = u.  Rusanov / Lax-Friedrichs splitting f+- = (f +- alpha u)/2 with */
+/* alpha the largest |u| over the six stencil cells (the same local reading */
+/* as the Euler splitting); f+ is reconstructed on cells i-2..i+3, f- on the */
+/* mirrored stencil, and the face flux is their sum.  Open boundaries are   */
+/* the transmissive ghost cells.  Order: f = 0.5 * (u * u), t = alpha * u,   */
+/* s+ = 0.5 * (f + t), s- = 0.5 * (f - t).                                   */
+/* Pins: conservation on periodic grids, the characteristic solution before */
+/* shock formation (order of accuracy), the Rankine-Hugoniot shock speed,   */
+/* the rarefaction fan, and the u(x) -> -u(-x) symmetry of the equation.    */
+/* ------------------------------------------------------------------------ */
+static void burgers_face(const double us[6], const double *P, int selector, unsigned mi,
+                         double *Fh, uint8_t *mout) {
+  double alpha = 0.0;
+  for (int j = 0; j < 6; ++j) {
+    double a = fabs(us[j]);
+    if (a > alpha) alpha = a;
+  }
+  double sp[6], sm[6];
+  for (int j = 0; j < 6; ++j) {
+    double f = 0.5 * (us[j] * us[j]);
+    double t = alpha * us[j];
+    sp[j] = 0.5 * (f + t);
+    sm[5 - j] = 0.5 * (f - t);
+  }
+  unsigned selp = select_mask(selector, P, sp, mi & 15u);
+  unsigned selm = select_mask(selector, P, sm, (mi >> 4) & 15u);
+  *Fh = combine(sp, selp) + combine(sm, selm);
+  if (mout) *mout = (uint8_t)(selp | (selm << 4));
+}
+
+/* Right-hand side of a batch of independent Burgers lines: u[total], masks
+ * [total + n_problems] (faces as for Euler), status -4 for a line with a
+ * non-finite value. */
+int oracle_burgers_rhs(const double *u, const int64_t *offsets, int32_t n_problems,
+                       const double *dx, int32_t bc, const double *P, int32_t selector,
+                       const uint8_t *masks_in, double *rhs, uint8_t *masks_out,
+                       int32_t *status) {
+  if (n_problems < 0 || (bc != 0 && bc != 1) || selector < 0 || selector > 4) return ST_BAD_ARG;
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
+  for (int32_t pb = 0; pb < n_problems; ++pb) {
+    const int64_t o = offsets[pb];
+    const int64_t n = offsets[pb + 1] - o;
+    if (n < 1) {
+      bad = 1;
+      continue;
+    }
+    double *Fh = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    for (int64_t i = 0; i < n; ++i)
+      if (!isfinite(u[o + i]) && status) status[pb] = ST_NONPHYSICAL;
+    for (int64_t k = 0; k <= n; ++k) {
+      double us[6];
+      for (int j = 0; j < 6; ++j) us[j] = u[o + ghost_index(k - 3 + j, n, bc)];
+      const int64_t fidx = o + pb + k;
+      uint8_t mo;
+      burgers_face(us, P, selector, masks_in ? masks_in[fidx] : 0u, &Fh[k], &mo);
+      if (masks_out) masks_out[fidx] = mo;
+    }
+    for (int64_t i = 0; i < n; ++i) rhs[o + i] = (Fh[i] - Fh[i + 1]) / dx[pb];
+    free(Fh);
+  }
+  return bad ? ST_BAD_ARG : ST_OK;
+}
+
+/* dt = cfl*dx / max|u| (cfl*dx when u is identically 0); a line with a
+ * non-finite value gets status -4 and is not advanced. */
+static void burgers_dt(const double *u, int64_t n, double cfl, double dx, double *dt, int32_t *st) {
+  double smax = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!isfinite(u[i])) {
+      *st = ST_NONPHYSICAL;
+      return;
+    }
+    double a = fabs(u[i]);
+    if (a > smax) smax = a;
+  }
+  *dt = smax > 0.0 ? (cfl * dx) / smax : cfl * dx;
+}
+
+int oracle_burgers_step(double *u, const int64_t *offsets, int32_t n_problems, const double *dx,
+                        int32_t bc, double cfl, int32_t n_steps, const double *P, int32_t selector,
+                        double *t, int32_t *status) {
+  if (n_problems < 0 || n_steps < 0 || (bc != 0 && bc != 1)) return ST_BAD_ARG;
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
+  for (int32_t pb = 0; pb < n_problems; ++pb) {
+    const int64_t o = offsets[pb], n = offsets[pb + 1] - o;
+    if (n < 1) {
+      bad = 1;
+      continue;
+    }
+    const size_t sz = sizeof(double) * (size_t)n;
+    double *u0 = (double *)malloc(sz), *u1 = (double *)malloc(sz), *u2 = (double *)malloc(sz),
+           *L = (double *)malloc(sz);
+    const int64_t off1[2] = {0, n};
+    memcpy(u0, u + o, sz);
+    for (int32_t it = 0; it < n_steps; ++it) {
+      if (status[pb] != 0) break;
+      double dt = 0.0;
+      burgers_dt(u0, n, cfl, dx[pb], &dt, &status[pb]);
+      if (status[pb] != 0) break;
+      int32_t dummy = 0;
+      oracle_burgers_rhs(u0, off1, 1, &dx[pb], bc, P, selector, NULL, L, NULL, &dummy);
+      for (int64_t i = 0; i < n; ++i) u1[i] = fma(dt, L[i], u0[i]);
+      oracle_burgers_rhs(u1, off1, 1, &dx[pb], bc, P, selector, NULL, L, NULL, &dummy);
+      for (int64_t i = 0; i < n; ++i) {
+        double tt = fma(dt, L[i], u1[i]);
+        u2[i] = fma(0.25, tt, 0.75 * u0[i]);
+      }
+      oracle_burgers_rhs(u2, off1, 1, &dx[pb], bc, P, selector, NULL, L, NULL, &dummy);
+      for (int64_t i = 0; i < n; ++i) {
+        double tt = fma(dt, L[i], u2[i]);
+        u0[i] = fma(2.0 / 3.0, tt, (1.0 / 3.0) * u0[i]);
+      }
+      t[pb] = t[pb] + dt;
+    }
+    memcpy(u + o, u0, sz);
+    free(u0);
+    free(u1);
+    free(u2);
+    free(L);
+  }
+  return bad ? ST_BAD_ARG : ST_OK;
+}
+
 /* 2D: state (rho, rho u, rho v, E); dimension-by-dimension application.
  * dir 0 = x (normal velocity u), dir 1 = y (normal velocity v). */
 static void prim2d(const double q[4], double gamma, double *u, double *v, double *p, double *c) {
