@@ -47,7 +47,8 @@ extern "C" {
 #define NENO6_BAD_ARG (-1)        /* null pointer, size or enum out of range */
 #define NENO6_BAD_LAYOUT (-2)     /* precision / layout combination not valid */
 #define NENO6_HIP_ERROR (-3)      /* a HIP launch or API call failed */
-#define NENO6_NONPHYSICAL (-4)    /* (device status word) rho <= 0, p <= 0 or NaN */
+#define NENO6_NONPHYSICAL (-4)    /* (device status word) Euler: rho <= 0, p <= 0 or NaN;
+                                   * Burgers: a non-finite value */
 #define NENO6_UNSUPPORTED (-5)    /* feature not available for this equation */
 #define NENO6_WORKSPACE_SMALL (-6)
 
@@ -66,6 +67,8 @@ extern "C" {
 #define NENO6_FP16 3
 
 #define NENO6_ADVECTION 0 /* u_t + u_x = 0 (Sec. 4.2) */
+#define NENO6_BURGERS 1   /* u_t + (u^2/2)_x = 0 (Sec. 4.3), Rusanov split with the
+                           * largest |u| over the six stencil cells */
 #define NENO6_EULER1D 2   /* 1D Euler, gamma-law gas (Sec. 4.4) */
 #define NENO6_EULER2D 3   /* 2D Euler, dimension by dimension (Sec. 4.4) */
 
@@ -76,6 +79,8 @@ extern "C" {
 #define NENO6_SEL_ALL_SMOOTH 1   /* every candidate kept: optimal linear scheme */
 #define NENO6_SEL_ALL_DISCARD 2  /* every candidate discarded: upwind fallback */
 #define NENO6_SEL_MASKS_IN 3     /* masks supplied by the caller */
+#define NENO6_SEL_TENO 4         /* TENO6-opt smoothness indicators and cut-off
+                                  * (Sec. 2.2-2.3), decided in FP64 in every mode */
 
 #define NENO6_NPARAM 3228
 
@@ -100,7 +105,8 @@ typedef struct neno6_mlp {
  *    mask arrays are [field][total_cells + n_problems].
  *    total_cells + n_problems < 2^29.
  *    ADVECTION uses var = field = 1 and only the '+' nibble (the '-' split
- *    flux is identically zero, so its nibble is reported as 0).
+ *    flux is identically zero, so its nibble is reported as 0).  BURGERS
+ *    uses var = field = 1 with both nibbles.
  *  2D (EULER2D): one nx x ny grid (nx, ny <= 2^20, nx * ny <= 2^28), SoA
  *    [4][ny][nx] (x fastest), spacings dx2d, dy2d; x-face masks
  *    [4][ny][nx+1], y-face masks [4][ny+1][nx]. */
@@ -230,7 +236,8 @@ int32_t neno6_autotune(const neno6_problem *prob, const neno6_mlp *mlp, const vo
 /* n_steps SSP-RK3 steps (Sec. 4.4), in place on q [dev].  Each step first
  * takes every problem's time step from its current state --
  * 1D: dt = cfl dx / max(|u| + c); 2D: dt = cfl / (max(|u|+c)/dx + max(|v|+c)/dy);
- * advection: dt = cfl dx (unit speed) -- and advances only problems whose
+ * advection: dt = cfl dx (unit speed); Burgers: dt = cfl dx / max|u| (cfl dx
+ * when u is identically 0) -- and advances only problems whose
  * status word is 0; a problem whose state is not physical at that point gets
  * NENO6_NONPHYSICAL and stays frozen.  t[n_problems] [dev, FP64] advances by
  * the dt taken.  status [dev]: one int32 per problem (2D: one). */

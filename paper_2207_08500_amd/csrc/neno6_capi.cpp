@@ -30,7 +30,7 @@ struct Carve {
 inline int32_t hip_status(hipError_t e) { return e == hipSuccess ? NENO6_OK : NENO6_HIP_ERROR; }
 
 bool valid_precision(int32_t p) { return p >= NENO6_FP64 && p <= NENO6_FP16; }
-bool valid_selector(int32_t s) { return s >= NENO6_SEL_MLP && s <= NENO6_SEL_MASKS_IN; }
+bool valid_selector(int32_t s) { return s >= NENO6_SEL_MLP && s <= NENO6_SEL_TENO; }
 
 int32_t check_mlp(const neno6_mlp *mlp, int32_t selector, int32_t precision) {
   if (selector != NENO6_SEL_MLP) return NENO6_OK;
@@ -39,7 +39,7 @@ int32_t check_mlp(const neno6_mlp *mlp, int32_t selector, int32_t precision) {
   return NENO6_OK;
 }
 
-int nvar_of(int32_t eq) { return eq == NENO6_ADVECTION ? 1 : (eq == NENO6_EULER1D ? 3 : 4); }
+int nvar_of(int32_t eq) { return eq <= NENO6_BURGERS ? 1 : (eq == NENO6_EULER1D ? 3 : 4); }
 
 int32_t check_tuning(const neno6_tuning *t) {
   if (!t) return NENO6_OK;
@@ -55,8 +55,8 @@ int32_t check_problem(const neno6_problem *pb) {
   if (!pb) return NENO6_BAD_ARG;
   if (pb->flags & ~NENO6_KEEP_MAP) return NENO6_BAD_ARG;
   if (int32_t c = check_tuning(pb->tuning)) return c;
-  if (pb->equation != NENO6_ADVECTION && pb->equation != NENO6_EULER1D &&
-      pb->equation != NENO6_EULER2D)
+  if (pb->equation != NENO6_ADVECTION && pb->equation != NENO6_BURGERS &&
+      pb->equation != NENO6_EULER1D && pb->equation != NENO6_EULER2D)
     return NENO6_BAD_ARG;
   if (pb->bc != NENO6_PERIODIC && pb->bc != NENO6_TRANSMISSIVE) return NENO6_BAD_ARG;
   if (!valid_precision(pb->precision) || !valid_selector(pb->selector)) return NENO6_BAD_ARG;
@@ -139,7 +139,7 @@ Work carve_work(const neno6_problem *pb, void *ws) {
     w.dummy_status = c.take<int32_t>(pb->n_problems);
     w.fmap = c.take<int32_t>(faces);
   }
-  if (pb->precision <= NENO6_FP32 && pb->equation != NENO6_ADVECTION) {
+  if (pb->precision <= NENO6_FP32 && pb->equation >= NENO6_EULER1D) {
     const int64_t nf = pb->equation == NENO6_EULER2D
                            ? std::max((pb->nx + 1) * pb->ny, pb->nx * (pb->ny + 1))
                            : pb->total_cells + pb->n_problems;
@@ -184,11 +184,14 @@ int32_t rhs_impl(const neno6_problem *pb, const T *P, const void *q, void *rhs,
   if (pb->equation == NENO6_ADVECTION)
     e = launch_faces_advection<T>(ln, P, pb->selector, (const T *)q, masks_in, (T *)w.F,
                                   masks_out, s);
+  else if (pb->equation == NENO6_BURGERS)
+    e = launch_faces_burgers<T>(ln, P, pb->selector, (const T *)q, masks_in, (T *)w.F, masks_out,
+                                s);
   else
     e = launch_faces_euler1d<T>(ln, P, pb->selector, (const T *)q, masks_in, (T *)w.F, masks_out,
                                 w.evals, s);
   if (e != hipSuccess) return NENO6_HIP_ERROR;
-  e = launch_diff1d<T>(ln, nvar_of(pb->equation), (const T *)w.F, (const T *)q, (T *)rhs, st,
+  e = launch_diff1d<T>(ln, pb->equation, (const T *)w.F, (const T *)q, (T *)rhs, st,
                        status, s);
   return hip_status(e);
 }
@@ -363,6 +366,9 @@ int32_t neno6_face_fluxes(const neno6_problem *prob, const neno6_mlp *mlp, const
       e = launch_faces_euler2d<double>(grid_of(prob), P, prob->selector, (const double *)q, mx, mx,
                                        (double *)F, (double *)F + nfx, masks_out,
                                        masks_out ? masks_out + nfx : nullptr, w.evals, stream);
+    else if (prob->equation == NENO6_BURGERS)
+      e = launch_faces_burgers<double>(line_of(prob, w.fmap), P, prob->selector, (const double *)q, mx,
+                                    (double *)F, masks_out, stream);
     else if (nv == 1)
       e = launch_faces_advection<double>(line_of(prob, w.fmap), P, prob->selector, (const double *)q, mx,
                                          (double *)F, masks_out, stream);
@@ -375,6 +381,9 @@ int32_t neno6_face_fluxes(const neno6_problem *prob, const neno6_mlp *mlp, const
       e = launch_faces_euler2d<float>(grid_of(prob), P, prob->selector, (const float *)q, mx, mx,
                                       (float *)F, (float *)F + nfx, masks_out,
                                       masks_out ? masks_out + nfx : nullptr, w.evals, stream);
+    else if (prob->equation == NENO6_BURGERS)
+      e = launch_faces_burgers<float>(line_of(prob, w.fmap), P, prob->selector, (const float *)q, mx,
+                                    (float *)F, masks_out, stream);
     else if (nv == 1)
       e = launch_faces_advection<float>(line_of(prob, w.fmap), P, prob->selector, (const float *)q, mx,
                                         (float *)F, masks_out, stream);
@@ -401,7 +410,7 @@ int32_t neno6_autotune(const neno6_problem *prob, const neno6_mlp *mlp, const vo
                        hipStream_t stream) {
   if (int32_t c = check_problem(prob)) return c;
   if (prob->precision < NENO6_BF16 || prob->selector != NENO6_SEL_MLP ||
-      prob->equation == NENO6_ADVECTION)
+      prob->equation <= NENO6_BURGERS)
     return NENO6_UNSUPPORTED;
   if (int32_t c = check_mlp(mlp, prob->selector, prob->precision)) return c;
   if (!q || !ws || !best || reps < 1 || reps > 1000) return NENO6_BAD_ARG;

@@ -10,6 +10,7 @@
 #include <stdint.h>
 
 #include "neno6_internal.h"
+#include "neno6_teno_tables.h"
 
 #define N6_DEV __device__ __forceinline__
 
@@ -403,6 +404,67 @@ N6_DEV unsigned classify_lean(const T *S, const T s[6]) {
   features<T>(s, x);
   mlp_lean<T>(S, x, z);
   return mask_from_logits<T>(z);
+}
+
+// ---- TENO6-opt selection (Sec. 2.2 and 2.3) ---------------------------------
+// Smoothness indicators (eq. measureTENO) in the Jiang-Shu form, written over
+// differences of neighbouring values so constant data give exactly zero;
+// sixth-order reference tau_6 (eq. taukTENO); normalisation (eq. normalize)
+// and the sharp cut-off C_T (eq. cut-off); C = 1, q = 6, eps = 1e-40,
+// C_T = 1e-6.  Evaluated in FP64 in every mode, from the stencil values
+// promoted exactly, in this fixed order (no contraction):
+//   d_a = s[first+a+1] - s[first+a]; t_a = fma over b ascending of D[a][b] d_b
+//   from 0; beta = fma over a ascending of d_a t_a from 0;
+//   tau = |beta6 - ((beta1 + beta2) + 4 beta0) / 6|;
+//   x_k = 1 + tau / (beta_k + eps); gamma_k = (x^2 x^2) x^2;
+//   chi_k = gamma_k / (((gamma0 + gamma1) + gamma2) + gamma3);
+//   candidate k kept unless chi_k < C_T.
+template <int FIRST, int N>
+N6_DEV double teno_beta(const double (&D)[N][N], const double s[6]) {
+#pragma clang fp contract(off)
+  double d[N];
+#pragma unroll
+  for (int a = 0; a < N; ++a) d[a] = s[FIRST + a + 1] - s[FIRST + a];
+  double beta = 0.0;
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    double t = 0.0;
+#pragma unroll
+    for (int b = 0; b < N; ++b) t = __builtin_fma(D[a][b], d[b], t);
+    beta = __builtin_fma(d[a], t, beta);
+  }
+  return beta;
+}
+
+N6_DEV unsigned teno_mask(const double s[6]) {
+#pragma clang fp contract(off)
+  const double bk[4] = {teno_beta<TENO_FIRST_S0>(TENO_D_S0, s), teno_beta<TENO_FIRST_S1>(TENO_D_S1, s),
+                        teno_beta<TENO_FIRST_S2>(TENO_D_S2, s), teno_beta<TENO_FIRST_S3>(TENO_D_S3, s)};
+  const double b6 = teno_beta<TENO_FIRST_S6>(TENO_D_S6, s);
+  const double tau = __builtin_fabs(b6 - ((bk[1] + bk[2]) + 4.0 * bk[0]) / 6.0);
+  double g[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double x = 1.0 + tau / (bk[k] + 1e-40);
+    const double x2 = x * x;
+    g[k] = (x2 * x2) * x2;
+  }
+  const double sum = ((g[0] + g[1]) + g[2]) + g[3];
+  unsigned m = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double chi = g[k] / sum;
+    if (!(chi < 1e-6)) m |= 1u << k;
+  }
+  return m;
+}
+
+template <typename T>
+N6_DEV unsigned teno_mask_of(const T s[6]) {
+  double sd[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) sd[j] = (double)s[j];
+  return teno_mask(sd);
 }
 
 }  // namespace n6

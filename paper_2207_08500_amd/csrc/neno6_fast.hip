@@ -245,6 +245,10 @@ N6_DEV unsigned classify_f32(const void *prepared, const float s[6]) {
 // and the right eigenvectors R.
 N6_DEV void setup1d(const Line1D &ln, const float *__restrict__ q, int64_t g, float s[6][6],
                     float R[3][3]) {
+  // No implicit contraction: every fused multiply-add is written out, so the
+  // six cells of a stencil go through the same operations (equal cells give
+  // bitwise equal stencil values).
+#pragma clang fp contract(off)
   const int p = line_of_face(ln, g);
   const int64_t o = ln.offsets[p];
   const int n = (int)(ln.offsets[p + 1] - o), k = (int)(g - o - p);
@@ -263,34 +267,34 @@ N6_DEV void setup1d(const Line1D &ln, const float *__restrict__ q, int64_t g, fl
   for (int j = 0; j < 6; ++j) {
     ir[j] = __builtin_amdgcn_rcpf(qs[j][0]);
     uu[j] = qs[j][1] * ir[j];
-    pp[j] = g1 * (qs[j][2] - 0.5f * qs[j][1] * uu[j]);
-    const float c = __builtin_amdgcn_sqrtf(gm * pp[j] * ir[j]);
+    pp[j] = g1 * __builtin_fmaf(-0.5f * qs[j][1], uu[j], qs[j][2]);
+    const float c = __builtin_amdgcn_sqrtf((gm * pp[j]) * ir[j]);
     lam[j][0] = uu[j] - c;
     lam[j][1] = uu[j];
     lam[j][2] = uu[j] + c;
     F[j][0] = qs[j][1];
-    F[j][1] = qs[j][1] * uu[j] + pp[j];
+    F[j][1] = __builtin_fmaf(qs[j][1], uu[j], pp[j]);
     F[j][2] = (qs[j][2] + pp[j]) * uu[j];
   }
   // Roe average of cells i (j = 2) and i+1 (j = 3)
   const float sL = __builtin_amdgcn_sqrtf(qs[2][0]), sR = __builtin_amdgcn_sqrtf(qs[3][0]);
   const float id = __builtin_amdgcn_rcpf(sL + sR);
-  const float ut = (sL * uu[2] + sR * uu[3]) * id;
+  const float ut = __builtin_fmaf(sL, uu[2], sR * uu[3]) * id;
   const float HL = (qs[2][2] + pp[2]) * ir[2], HR = (qs[3][2] + pp[3]) * ir[3];
-  const float Ht = (sL * HL + sR * HR) * id;
-  const float q2 = 0.5f * ut * ut;
+  const float Ht = __builtin_fmaf(sL, HL, sR * HR) * id;
+  const float q2 = (0.5f * ut) * ut;
   const float c2 = g1 * (Ht - q2);
   const float ct = __builtin_amdgcn_sqrtf(c2);
   const float ic = __builtin_amdgcn_rcpf(ct);
-  const float b1 = g1 * ic * ic;
+  const float b1 = (g1 * ic) * ic;
   const float b2 = b1 * q2;
   const float uc = ut * ic;
   R[0][0] = 1.f;          R[0][1] = 1.f; R[0][2] = 1.f;
   R[1][0] = ut - ct;      R[1][1] = ut;  R[1][2] = ut + ct;
-  R[2][0] = Ht - ut * ct; R[2][1] = q2;  R[2][2] = Ht + ut * ct;
-  const float L[3][3] = {{0.5f * (b2 + uc), -0.5f * (b1 * ut + ic), 0.5f * b1},
+  R[2][0] = __builtin_fmaf(-ut, ct, Ht); R[2][1] = q2; R[2][2] = __builtin_fmaf(ut, ct, Ht);
+  const float L[3][3] = {{0.5f * (b2 + uc), -0.5f * __builtin_fmaf(b1, ut, ic), 0.5f * b1},
                          {1.f - b2, b1 * ut, -b1},
-                         {0.5f * (b2 - uc), -0.5f * (b1 * ut - ic), 0.5f * b1}};
+                         {0.5f * (b2 - uc), -0.5f * __builtin_fmaf(b1, ut, -ic), 0.5f * b1}};
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
     float alpha = 0.f;
@@ -298,10 +302,10 @@ N6_DEV void setup1d(const Line1D &ln, const float *__restrict__ q, int64_t g, fl
     for (int j = 0; j < 6; ++j) alpha = fmaxf(alpha, fabsf(lam[j][m]));
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-      const float v = L[m][0] * qs[j][0] + L[m][1] * qs[j][1] + L[m][2] * qs[j][2];
-      const float gg = L[m][0] * F[j][0] + L[m][1] * F[j][1] + L[m][2] * F[j][2];
-      s[2 * m][j] = 0.5f * (gg + alpha * v);
-      s[2 * m + 1][5 - j] = 0.5f * (gg - alpha * v);
+      const float v = __builtin_fmaf(L[m][2], qs[j][2], __builtin_fmaf(L[m][1], qs[j][1], L[m][0] * qs[j][0]));
+      const float gg = __builtin_fmaf(L[m][2], F[j][2], __builtin_fmaf(L[m][1], F[j][1], L[m][0] * F[j][0]));
+      s[2 * m][j] = 0.5f * __builtin_fmaf(alpha, v, gg);
+      s[2 * m + 1][5 - j] = 0.5f * __builtin_fmaf(-alpha, v, gg);
     }
   }
 }
@@ -309,6 +313,7 @@ N6_DEV void setup1d(const Line1D &ln, const float *__restrict__ q, int64_t g, fl
 // 2D Euler face f of sweep dir: s[2m + sign][6], R.
 N6_DEV void setup2d(const Grid2D &gd, int dir, const float *__restrict__ q, int64_t f,
                     float s[8][6], float R[4][4]) {
+#pragma clang fp contract(off)
   const int64_t cells = gd.nx * gd.ny;
   const float gm = (float)gd.gamma, g1 = gm - 1.f;
   float qs[6][4];
@@ -338,31 +343,31 @@ N6_DEV void setup2d(const Grid2D &gd, int dir, const float *__restrict__ q, int6
     ir[j] = __builtin_amdgcn_rcpf(qs[j][0]);
     un[j] = qs[j][vn] * ir[j];
     us[j] = qs[j][vs] * ir[j];
-    pp[j] = g1 * (qs[j][3] - 0.5f * (qs[j][vn] * un[j] + qs[j][vs] * us[j]));
-    lamc[j] = __builtin_amdgcn_sqrtf(gm * pp[j] * ir[j]);
+    pp[j] = g1 * (qs[j][3] - 0.5f * __builtin_fmaf(qs[j][vn], un[j], qs[j][vs] * us[j]));
+    lamc[j] = __builtin_amdgcn_sqrtf((gm * pp[j]) * ir[j]);
   }
   const float sL = __builtin_amdgcn_sqrtf(qs[2][0]), sR = __builtin_amdgcn_sqrtf(qs[3][0]);
   const float id = __builtin_amdgcn_rcpf(sL + sR);
-  const float nt = (sL * un[2] + sR * un[3]) * id;
-  const float st = (sL * us[2] + sR * us[3]) * id;
+  const float nt = __builtin_fmaf(sL, un[2], sR * un[3]) * id;
+  const float st = __builtin_fmaf(sL, us[2], sR * us[3]) * id;
   const float HL = (qs[2][3] + pp[2]) * ir[2], HR = (qs[3][3] + pp[3]) * ir[3];
-  const float Ht = (sL * HL + sR * HR) * id;
-  const float q2 = 0.5f * (nt * nt + st * st);
+  const float Ht = __builtin_fmaf(sL, HL, sR * HR) * id;
+  const float q2 = 0.5f * __builtin_fmaf(nt, nt, st * st);
   const float c2 = g1 * (Ht - q2);
   const float ct = __builtin_amdgcn_sqrtf(c2);
   const float ic = __builtin_amdgcn_rcpf(ct);
-  const float b1 = g1 * ic * ic;
+  const float b1 = (g1 * ic) * ic;
   const float b2 = b1 * q2;
   const float nc = nt * ic;
   // (rho, rho u_n, rho u_s, E) ordering, permuted into (rho, rho u, rho v, E)
   const float Rn[4][4] = {{1.f, 1.f, 0.f, 1.f},
                           {nt - ct, nt, 0.f, nt + ct},
                           {st, st, 1.f, st},
-                          {Ht - nt * ct, q2, st, Ht + nt * ct}};
-  const float Ln[4][4] = {{0.5f * (b2 + nc), -0.5f * (b1 * nt + ic), -0.5f * b1 * st, 0.5f * b1},
+                          {__builtin_fmaf(-nt, ct, Ht), q2, st, __builtin_fmaf(nt, ct, Ht)}};
+  const float Ln[4][4] = {{0.5f * (b2 + nc), -0.5f * __builtin_fmaf(b1, nt, ic), (-0.5f * b1) * st, 0.5f * b1},
                           {1.f - b2, b1 * nt, b1 * st, -b1},
                           {-st, 0.f, 1.f, 0.f},
-                          {0.5f * (b2 - nc), -0.5f * (b1 * nt - ic), -0.5f * b1 * st, 0.5f * b1}};
+                          {0.5f * (b2 - nc), -0.5f * __builtin_fmaf(b1, nt, -ic), (-0.5f * b1) * st, 0.5f * b1}};
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     R[0][m] = Rn[0][m];
@@ -382,14 +387,15 @@ N6_DEV void setup2d(const Grid2D &gd, int dir, const float *__restrict__ q, int6
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
       const float Fn0 = qs[j][vn];
-      const float Fn1 = qs[j][vn] * un[j] + pp[j];
+      const float Fn1 = __builtin_fmaf(qs[j][vn], un[j], pp[j]);
       const float Fn2 = qs[j][vs] * un[j];
       const float Fn3 = (qs[j][3] + pp[j]) * un[j];
-      const float v = Ln[m][0] * qs[j][0] + Ln[m][1] * qs[j][vn] + Ln[m][2] * qs[j][vs] +
-                      Ln[m][3] * qs[j][3];
-      const float gg = Ln[m][0] * Fn0 + Ln[m][1] * Fn1 + Ln[m][2] * Fn2 + Ln[m][3] * Fn3;
-      s[2 * m][j] = 0.5f * (gg + alpha * v);
-      s[2 * m + 1][5 - j] = 0.5f * (gg - alpha * v);
+      const float v = __builtin_fmaf(Ln[m][3], qs[j][3], __builtin_fmaf(Ln[m][2], qs[j][vs],
+                      __builtin_fmaf(Ln[m][1], qs[j][vn], Ln[m][0] * qs[j][0])));
+      const float gg = __builtin_fmaf(Ln[m][3], Fn3, __builtin_fmaf(Ln[m][2], Fn2,
+                       __builtin_fmaf(Ln[m][1], Fn1, Ln[m][0] * Fn0)));
+      s[2 * m][j] = 0.5f * __builtin_fmaf(alpha, v, gg);
+      s[2 * m + 1][5 - j] = 0.5f * __builtin_fmaf(-alpha, v, gg);
     }
   }
 }
@@ -481,6 +487,11 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
         sel[e] = 15u;
       } else if (selector == 2) {
         sel[e] = 0u;
+      } else if (selector == 4) {  // TENO6-opt, decided in FP64
+        float se[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) se[j] = stash[wv][e * 6 + j][lane];
+        sel[e] = teno_mask_of<float>(se);
       } else {
         sel[e] = (min[(e >> 1) * nf + fc] >> ((e & 1) * 4)) & 15u;
       }
@@ -800,6 +811,8 @@ k_fast_scalar(int mode, Line1D ln, const void *__restrict__ prepared, float marg
       sel = 15u;
     } else if (selector == 2) {
       sel = 0u;
+    } else if (selector == 4) {
+      sel = teno_mask_of<float>(s);
     } else {
       sel = min[kc] & 15u;
     }
@@ -811,6 +824,64 @@ k_fast_scalar(int mode, Line1D ln, const void *__restrict__ prepared, float marg
       out[k] = combine_fast(s, sel);
     }
     if (mout) mout[k] = (uint8_t)sel;
+  }
+}
+
+// Label of one scalar stencil by the selector; the MFMA classification is a
+// wave-wide operation, so every lane of the wave calls this together.
+template <int PREC>
+N6_DEV u32 scalar_select(const Wts &w, int selector, const void *prepared, float margin,
+                         const float s[6], bool valid, u32 mask_in) {
+  if (selector == 0) {
+    const u32 mk = classify_wave<PREC>(w, s, margin, nullptr);
+    return (valid && (mk & 16u)) ? classify_f32(prepared, s) : (mk & 15u);
+  }
+  if (selector == 1) return 15u;
+  if (selector == 2) return 0u;
+  if (selector == 4) return teno_mask_of<float>(s);
+  return mask_in & 15u;
+}
+
+// Burgers faces (Sec. 4.3): one lane per face; f = u^2/2, Rusanov speed
+// alpha = max |u| over the six cells, f+- = (f +- alpha u)/2 ('-' mirrored);
+// both split stencils classified (FP32 re-check in place), face flux = sum of
+// the two reconstructions.
+template <int PREC>
+__global__ void __launch_bounds__(TPB)
+k_fast_burgers(Line1D ln, const void *__restrict__ prepared, float margin, int selector,
+               const float *__restrict__ u, const uint8_t *__restrict__ min,
+               float *__restrict__ Fh, uint8_t *__restrict__ mout) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nf = ln.faces(), nchunk = (nf + 63) / 64;
+  Wts w;
+  if (selector == 0) load_wts<PREC>(prepared, lane, w);
+  for (int64_t ch = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6); ch < nchunk;
+       ch += (int64_t)gridDim.x * WPB) {
+    const int64_t g = ch * 64 + lane;
+    const bool valid = g < nf;
+    const int64_t gc = valid ? g : nf - 1;
+    const int p = line_of_face(ln, gc);
+    const int64_t o = ln.offsets[p], n = ln.offsets[p + 1] - o, k = gc - o - p;
+    float us[6], alpha = 0.f;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      us[j] = u[o + ghost(k - 3 + j, n, ln.bc)];
+      alpha = fmaxf(alpha, fabsf(us[j]));
+    }
+    float sp[6], sm[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const float f = 0.5f * (us[j] * us[j]);
+      const float t = alpha * us[j];
+      sp[j] = 0.5f * (f + t);
+      sm[5 - j] = 0.5f * (f - t);
+    }
+    const u32 mi = min ? min[gc] : 0u;
+    const u32 selp = scalar_select<PREC>(w, selector, prepared, margin, sp, valid, mi);
+    const u32 selm = scalar_select<PREC>(w, selector, prepared, margin, sm, valid, mi >> 4);
+    if (!valid) continue;
+    Fh[g] = combine_fast(sp, selp) + combine_fast(sm, selm);
+    if (mout) mout[g] = (uint8_t)(selp | (selm << 4));
   }
 }
 
@@ -1315,6 +1386,15 @@ hipError_t launch_fast_faces1d(const Line1D &ln, const FastArgs &fa, const float
                          q, tf, 1, fa.selector, masks_in, F, masks, nullptr);
     return hipGetLastError();
   }
+  if (fa.equation == 1) {
+    if (fa.precision == 2)
+      hipLaunchKernelGGL(k_fast_burgers<2>, dim3(grid), dim3(TPB), 0, s, ln, fa.prepared,
+                         fa.margin, fa.selector, q, masks_in, F, masks);
+    else
+      hipLaunchKernelGGL(k_fast_burgers<3>, dim3(grid), dim3(TPB), 0, s, ln, fa.prepared,
+                         fa.margin, fa.selector, q, masks_in, F, masks);
+    return hipGetLastError();
+  }
   // The re-check flips labels with 32-bit atomics, so the classifier writes
   // into the workspace buffer (whole words) and the caller's copy follows.
   // The re-check counter (qcount[0]) was cleared at the start of the call or
@@ -1342,7 +1422,7 @@ hipError_t launch_fast_rhs1d(const Line1D &ln, const FastArgs &fa, const float *
                              float *F, const Stage *st, hipStream_t s) {
   hipError_t e = launch_fast_faces1d(ln, fa, q, masks_in, masks_out, F, s);
   if (e != hipSuccess) return e;
-  return launch_diff1d<float>(ln, fa.equation == 0 ? 1 : 3, F, q, rhs, st, status, s,
+  return launch_diff1d<float>(ln, fa.equation, F, q, rhs, st, status, s,
                               fa.scr.qcount);
 }
 

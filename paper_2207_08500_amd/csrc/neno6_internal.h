@@ -55,6 +55,10 @@ template <typename T>
 hipError_t launch_faces_advection(const Line1D &ln, const T *P, int selector, const T *u,
                                   const uint8_t *masks_in, T *Fhat, uint8_t *masks_out,
                                   hipStream_t s);
+template <typename T>
+hipError_t launch_faces_burgers(const Line1D &ln, const T *P, int selector, const T *u,
+                                const uint8_t *masks_in, T *Fhat, uint8_t *masks_out,
+                                hipStream_t s);
 // evals: scratch of plain_eval_bytes(6, faces, sizeof(T)) bytes.
 template <typename T>
 hipError_t launch_faces_euler1d(const Line1D &ln, const T *P, int selector, const T *q,
@@ -68,7 +72,7 @@ size_t plain_eval_bytes(int nevals, int64_t faces, size_t elem);
 // are not physical when status_out != nullptr.
 // zero_after (may be null): two counters the kernel clears once it has run.
 template <typename T>
-hipError_t launch_diff1d(const Line1D &ln, int nvar, const T *Fhat, const T *q, T *rhs,
+hipError_t launch_diff1d(const Line1D &ln, int equation, const T *Fhat, const T *q, T *rhs,
                          const Stage *st, int32_t *status_out, hipStream_t s,
                          uint32_t *zero_after = nullptr);
 // Per-line time step and status check at the start of a step; t += dt.

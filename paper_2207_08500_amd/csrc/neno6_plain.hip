@@ -30,6 +30,7 @@ N6_DEV unsigned select_mask(int selector, const T *S, const T s[6], unsigned mas
   case 0: return classify_lean<T>(S, s);
   case 1: return 15u;
   case 2: return 0u;
+  case 4: return teno_mask_of<T>(s);
   default: return mask_in & 15u;
   }
 }
@@ -95,6 +96,44 @@ k_faces_advection(Line1D ln, const T *__restrict__ P, int selector, const T *__r
   const unsigned sel = select_mask<T>(selector, S, s, min ? min[g] : 0u);
   Fh[g] = combine_canonical<T>(s, sel);
   if (mout) mout[g] = (uint8_t)sel;
+}
+
+// Burgers (Sec. 4.3): f = u^2/2, Rusanov speed alpha = max |u| over the six
+// cells, f+- = (f +- alpha u)/2; '+' on cells i-2..i+3, '-' mirrored; the face
+// flux is the sum of both reconstructions.
+template <typename T>
+__global__ void __launch_bounds__(TPB)
+k_faces_burgers(Line1D ln, const T *__restrict__ P, int selector, const T *__restrict__ u,
+                const uint8_t *__restrict__ min, T *__restrict__ Fh, uint8_t *__restrict__ mout) {
+  __shared__ T S[S_SIZE];
+  if (selector == 0) {
+    stage_params<T>(P, S);
+    __syncthreads();
+  }
+  const int64_t g = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  if (g >= ln.faces()) return;
+  const int p = line_of_face(ln, g);
+  const int64_t o = ln.offsets[p], n = ln.offsets[p + 1] - o, k = g - o - p;
+  T us[6], alpha = T(0);
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    us[j] = u[o + ghost(k - 3 + j, n, ln.bc)];
+    const T a = abs_<T>(us[j]);
+    alpha = a > alpha ? a : alpha;
+  }
+  T sp[6], sm[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const T f = T(0.5) * (us[j] * us[j]);
+    const T t = alpha * us[j];
+    sp[j] = T(0.5) * (f + t);
+    sm[5 - j] = T(0.5) * (f - t);
+  }
+  const unsigned mi = min ? min[g] : 0u;
+  const unsigned selp = select_mask<T>(selector, S, sp, mi & 15u);
+  const unsigned selm = select_mask<T>(selector, S, sm, (mi >> 4) & 15u);
+  Fh[g] = combine_canonical<T>(sp, selp) + combine_canonical<T>(sm, selm);
+  if (mout) mout[g] = (uint8_t)(selp | (selm << 4));
 }
 
 // Split stencil of characteristic field M and sign sgn ('-' mirrored) of a
@@ -357,7 +396,7 @@ N6_DEV T rk3(int stage, T us, T u0, T L, T dt) {
 
 template <typename T>
 __global__ void __launch_bounds__(TPB)
-k_diff1d(Line1D ln, int nvar, const T *__restrict__ Fh, const T *__restrict__ q,
+k_diff1d(Line1D ln, int equation, const T *__restrict__ Fh, const T *__restrict__ q,
          T *__restrict__ rhs, Stage st, int has_stage, int32_t *__restrict__ status_out,
          uint32_t *__restrict__ zero_after) {
   if (zero_after && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -373,11 +412,14 @@ k_diff1d(Line1D ln, int nvar, const T *__restrict__ Fh, const T *__restrict__ q,
   const int64_t i = g - p;
   if (i >= ln.offsets[p + 1]) return;
   const T dx = (T)ln.dx[p];
-  if (status_out && nvar == 3) {
+  const int nvar = equation == 2 ? 3 : 1;
+  if (status_out && equation == 2) {
     const T qc[3] = {q[i], q[ln.total + i], q[2 * ln.total + i]};
     T u, pr, c;
     prim1d<T>(qc, (T)ln.gamma, u, pr, c);
     if (!physical<T>(qc[0], pr)) status_out[p] = ST_NONPHYSICAL;
+  } else if (status_out && equation == 1 && !__builtin_isfinite(q[i])) {
+    status_out[p] = ST_NONPHYSICAL;
   }
   for (int r = 0; r < nvar; ++r) {
     const T L = (Fh[r * tf + g] - Fh[r * tf + g + 1]) / dx;
@@ -414,6 +456,13 @@ k_cfl1d(Line1D ln, int equation, const T *__restrict__ q, double cfl, double *__
       const double sp = (double)(abs_<T>(u) + c);
       smax = sp > smax ? sp : smax;
     }
+  } else if (equation == 1) {  // Burgers: wave speed |u|
+    for (int64_t i = threadIdx.x; i < n; i += CFL_TPB) {
+      const T v = q[o + i];
+      if (!__builtin_isfinite(v)) b = 1;
+      const double sp = (double)abs_<T>(v);
+      smax = sp > smax ? sp : smax;
+    }
   }
   // the maximum of the (non-NaN) speeds and the OR of the flags do not depend
   // on the reduction order
@@ -446,7 +495,9 @@ k_cfl1d(Line1D ln, int equation, const T *__restrict__ q, double cfl, double *__
       dt[p] = 0.0;
       return;
     }
-    const double d = equation == 2 ? (cfl * ln.dx[p]) / red[0] : cfl * ln.dx[p];
+    // advection: unit speed; Burgers with u identically 0: the advection step
+    const double d = (equation == 2 || (equation == 1 && red[0] > 0.0)) ? (cfl * ln.dx[p]) / red[0]
+                                                                         : cfl * ln.dx[p];
     dt[p] = d;
     t[p] = t[p] + d;
   }
@@ -665,6 +716,15 @@ hipError_t launch_faces_advection(const Line1D &ln, const T *P, int selector, co
 }
 
 template <typename T>
+hipError_t launch_faces_burgers(const Line1D &ln, const T *P, int selector, const T *u,
+                                const uint8_t *masks_in, T *Fhat, uint8_t *masks_out,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_faces_burgers<T>, dim3(nblocks(ln.faces())), dim3(TPB), 0, s, ln, P,
+                     selector, u, masks_in, Fhat, masks_out);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_faces_euler1d(const Line1D &ln, const T *P, int selector, const T *q,
                                 const uint8_t *masks_in, T *Fhat, uint8_t *masks_out,
                                 void *evals, hipStream_t s) {
@@ -681,12 +741,12 @@ hipError_t launch_faces_euler1d(const Line1D &ln, const T *P, int selector, cons
 }
 
 template <typename T>
-hipError_t launch_diff1d(const Line1D &ln, int nvar, const T *Fhat, const T *q, T *rhs,
+hipError_t launch_diff1d(const Line1D &ln, int equation, const T *Fhat, const T *q, T *rhs,
                          const Stage *st, int32_t *status_out, hipStream_t s,
                          uint32_t *zero_after) {
   Stage sv{};
   if (st) sv = *st;
-  hipLaunchKernelGGL(k_diff1d<T>, dim3(nblocks(ln.faces())), dim3(TPB), 0, s, ln, nvar, Fhat, q,
+  hipLaunchKernelGGL(k_diff1d<T>, dim3(nblocks(ln.faces())), dim3(TPB), 0, s, ln, equation, Fhat, q,
                      rhs, sv, st ? 1 : 0, status_out, zero_after);
   return hipGetLastError();
 }
@@ -780,6 +840,8 @@ hipError_t launch_params_to_f32(const double *P, float *P32, hipStream_t s) {
                                            hipStream_t);                                         \
   template hipError_t launch_faces_advection<T>(const Line1D &, const T *, int, const T *,       \
                                                 const uint8_t *, T *, uint8_t *, hipStream_t);   \
+  template hipError_t launch_faces_burgers<T>(const Line1D &, const T *, int, const T *,         \
+                                              const uint8_t *, T *, uint8_t *, hipStream_t);     \
   template hipError_t launch_faces_euler1d<T>(const Line1D &, const T *, int, const T *,         \
                                               const uint8_t *, T *, uint8_t *, void *,           \
                                               hipStream_t);                                      \

@@ -19,9 +19,9 @@ LIB_PATH = os.path.join(HERE, "libneno6.so")
 
 OK, BAD_ARG, BAD_LAYOUT, HIP_ERROR, NONPHYSICAL, UNSUPPORTED, WORKSPACE_SMALL = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32, BF16, FP16 = 0, 1, 2, 3
-ADVECTION, EULER1D, EULER2D = 0, 2, 3
+ADVECTION, BURGERS, EULER1D, EULER2D = 0, 1, 2, 3
 PERIODIC, TRANSMISSIVE = 0, 1
-SEL_MLP, SEL_ALL_SMOOTH, SEL_ALL_DISCARD, SEL_MASKS_IN = 0, 1, 2, 3
+SEL_MLP, SEL_ALL_SMOOTH, SEL_ALL_DISCARD, SEL_MASKS_IN, SEL_TENO = 0, 1, 2, 3, 4
 KEEP_MAP = 1
 NPARAM = 3228
 
@@ -229,7 +229,7 @@ class Problem:
 
     @property
     def nvar(self) -> int:
-        return {ADVECTION: 1, EULER1D: 3, EULER2D: 4}[self.equation]
+        return {ADVECTION: 1, BURGERS: 1, EULER1D: 3, EULER2D: 4}[self.equation]
 
     @property
     def n_faces(self) -> int:

@@ -1,0 +1,167 @@
+"""Inviscid Burgers (NENO6_BURGERS, Sec. 4.3) on the GPU against the oracle.
+
+* FP64: right-hand side, masks and whole runs bit for bit, for every
+  selector, both boundary kinds and batches of uneven lines.
+* The paper's two Burgers cases as workloads: the three-shock collision
+  (N = 175 on [0, 1], open boundaries, CFL 0.1, t = 0.1) and the compound
+  wave (N = 200 on [-4, 4], periodic, CFL 0.2, t = 0.4); FP64 bit for bit,
+  the reduced-precision modes against FP64 (L1 printed and bounded).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_08500_amd import inputs
+from tests._helpers import dev, host, label_flip_rate, need_gpu, trained_params
+
+pytestmark = pytest.mark.gpu
+
+MARGIN = {2: 0.5, 3: 0.25}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    need_gpu()
+    import torch
+    from paper_2207_08500_amd import native
+    return native, torch, trained_params()
+
+
+def _same(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    assert a.shape == b.shape
+    bad = ~((a == b) | (np.isnan(a) & np.isnan(b)))
+    assert not bad.any(), "first mismatch at %s: %r vs %r (%d of %d differ)" % (
+        np.argwhere(bad)[0], a[bad][0], b[bad][0], bad.sum(), bad.size)
+
+
+def _lines(seed, sizes):
+    u = np.concatenate([inputs.advection_c1(seed + i, n) * 2.0 - 0.5 for i, n in enumerate(sizes)])
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    dx = 2.0 / np.asarray(sizes, np.float64)
+    return u, off, dx
+
+
+def _mlp(native, P, prec):
+    return native.Mlp(dev(P), recheck_margin=MARGIN.get(prec, 0.0))
+
+
+@pytest.mark.parametrize("selector", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_burgers_rhs_fp64_bitwise(ctx, selector, bc):
+    native, torch, P = ctx
+    sizes = [1, 5, 64, 65, 200, 777]
+    u, off, dx = _lines(60, sizes)
+    nf = int(off[-1]) + len(sizes)
+    mi = np.random.default_rng(2).integers(0, 256, nf).astype(np.uint8)
+    Po = P if selector == 0 else None
+    r_o, m_o, st_o = oracle.burgers_rhs(u, off, dx, bc, Po, selector, mi if selector == 3 else None)
+    prob = native.Problem(native.BURGERS, native.FP64, selector, bc, off, dx)
+    r = torch.zeros(u.size, dtype=torch.float64, device="cuda")
+    m = torch.zeros(nf, dtype=torch.uint8, device="cuda")
+    st = torch.zeros(len(sizes), dtype=torch.int32, device="cuda")
+    native.neno6_rhs(prob, _mlp(native, P, 0) if selector == 0 else None, dev(u), r,
+                     prob.workspace(), masks_in=dev(mi) if selector == 3 else None, masks_out=m,
+                     status=st)
+    torch.cuda.synchronize()
+    _same(host(st), st_o)
+    _same(host(m), m_o)
+    _same(host(r), r_o)
+
+
+@pytest.mark.parametrize("selector", [0, 4])
+def test_burgers_steps_fp64_bitwise(ctx, selector):
+    native, torch, P = ctx
+    sizes = [40, 150, 301]
+    u, off, dx = _lines(61, sizes)
+    Po = P if selector == 0 else None
+    u_o, t_o, st_o = oracle.burgers_step(u, off, dx, 0.3, 30, oracle.BC_PERIODIC, Po, selector)
+    prob = native.Problem(native.BURGERS, native.FP64, selector, native.PERIODIC, off, dx)
+    ug = dev(u)
+    t = torch.zeros(len(sizes), dtype=torch.float64, device="cuda")
+    st = torch.zeros(len(sizes), dtype=torch.int32, device="cuda")
+    native.neno6_step(prob, _mlp(native, P, 0) if selector == 0 else None, ug, 0.3, 30, t, st,
+                      prob.workspace())
+    torch.cuda.synchronize()
+    _same(host(st), st_o)
+    _same(host(t), t_o)
+    _same(host(ug), u_o)
+
+
+def _collision(n=175):
+    dx = 1.0 / n
+    x = (np.arange(n) + 0.5) * dx
+    u = np.select([x <= 0.2, x <= 0.4, x <= 0.6], [10.0, 6.0, 0.0], -4.0)
+    return u, dx, 0.1, 0.1, native_bc("open")
+
+
+def _compound(n=200):
+    dx = 8.0 / n
+    x = -4.0 + (np.arange(n) + 0.5) * dx
+    u = np.where(np.abs(x) >= 1.0, np.sin(np.pi * x),
+                 np.where(((x > -1.0) & (x <= -0.5)) | ((x > 0.0) & (x <= 0.5)), 3.0,
+                          np.where((x > -0.5) & (x <= 0.0), 1.0, 2.0)))
+    return u, dx, 0.2, 0.4, native_bc("periodic")
+
+
+def native_bc(kind):
+    return 1 if kind == "open" else 0
+
+
+def _run_to(native, torch, P, prec, selector, u0, dx, cfl, t_end, bc, fixed_steps=None):
+    """March with CFL steps until t >= t_end, or exactly fixed_steps steps."""
+    prob = native.Problem(native.BURGERS, prec, selector, bc, [0, u0.size], [dx])
+    u = dev(u0, native.fdtype(prec))
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ws = prob.workspace()
+    mlp = _mlp(native, P, prec) if selector == 0 else None
+    steps = 0
+    if fixed_steps is not None:
+        native.neno6_step(prob, mlp, u, cfl, fixed_steps, t, st, ws)
+        steps = fixed_steps
+    while fixed_steps is None and float(host(t)[0]) < t_end and steps < 10000:
+        native.neno6_step(prob, mlp, u, cfl, 1, t, st, ws)
+        steps += 1
+    torch.cuda.synchronize()
+    assert int(host(st)[0]) == 0
+    return host(u).astype(np.float64), float(host(t)[0]), steps
+
+
+def _labels(native, torch, P, prec, selector, u0, dx, bc):
+    prob = native.Problem(native.BURGERS, prec, selector, bc, [0, u0.size], [dx])
+    u = dev(u0, native.fdtype(prec))
+    m = torch.zeros(prob.mask_count(), dtype=torch.uint8, device="cuda")
+    native.neno6_rhs(prob, _mlp(native, P, prec) if selector == 0 else None, u, torch.zeros_like(u),
+                     prob.workspace(), masks_out=m)
+    torch.cuda.synchronize()
+    return host(m)
+
+
+@pytest.mark.parametrize("case", ["collision", "compound"])
+@pytest.mark.parametrize("selector", [0, 4])
+def test_paper_burgers_cases(ctx, case, selector):
+    native, torch, P = ctx
+    u0, dx, cfl, t_end, bc = _collision() if case == "collision" else _compound()
+    u64, t64, steps = _run_to(native, torch, P, native.FP64, selector, u0, dx, cfl, t_end, bc)
+    u_o, t_o, st_o = oracle.burgers_step(u0, [0, u0.size], dx, cfl, steps, bc,
+                                         P if selector == 0 else None, selector)
+    assert st_o[0] == 0
+    _same(u64, u_o)
+    assert t64 == t_o[0]
+    m64 = _labels(native, torch, P, native.FP64, selector, u0, dx, bc)
+    for prec in (1, 2, 3):
+        ur, tr, _ = _run_to(native, torch, P, prec, selector, u0, dx, cfl, t_end, bc, steps)
+        l1 = np.abs(ur - u64).mean() / np.abs(u64).mean()
+        flip = label_flip_rate(_labels(native, torch, P, prec, selector, u0, dx, bc), m64)
+        print("Burgers %s selector %d prec %d: %d steps to t = %.4f, relative L1 vs FP64 %.3g, "
+              "label flip rate on the initial state %.3g" % (case, selector, prec, steps, t64, l1,
+                                                            flip))
+        assert flip < 1e-3
+        if selector == 4:  # TENO6-opt labels are decided in FP64: the runs stay together
+            assert abs(tr - t64) < 1e-4 * t64 and l1 < 1e-4
+        else:
+            # a classifier label near its cutoff follows the rounding of the state;
+            # over ~2000 steps of colliding shocks a flipped label moves the
+            # shocks (and the CFL steps) by a little
+            assert abs(tr - t64) < 0.05 * t64 and l1 < 0.1
