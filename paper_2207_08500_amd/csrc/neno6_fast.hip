@@ -435,7 +435,7 @@ N6_DEV void enqueue(bool want, u32 entry, u32 *__restrict__ queue, u32 *__restri
 // With xcd != 0 the workgroup numbering is permuted so that the workgroups
 // the hardware places on one XCD (every 8th) take a contiguous run of tiles
 // (the host only sets it when gridDim.x is a multiple of 8).
-template <int PREC, int NV, int W>
+template <int PREC, int NV, int W, bool MLP>
 __global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(2)))
 k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict__ prepared,
              float margin, const float *__restrict__ q, const uint8_t *__restrict__ min,
@@ -450,7 +450,7 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
   const int64_t nb = gridDim.x;
   const int64_t lb = xcd ? (int64_t)(blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8 : blockIdx.x;
   Wts w;
-  if (selector == 0) load_wts<PREC>(prepared, lane, w);
+  if constexpr (MLP) load_wts<PREC>(prepared, lane, w);
   for (int64_t ch = lb * W + wv; ch < nchunk; ch += nb * W) {
     const int64_t f = ch * 64 + lane;
     const bool valid = f < nf;
@@ -462,7 +462,7 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
         setup1d(ln, q, fc, s, R);
       else
         setup2d(gd, dir, q, fc, s, R);
-      if (selector == 0) {
+      if constexpr (MLP) {
 #pragma unroll
         for (int e = 0; e < NE; ++e) feature_pack<PREC>(s[e], fx[e][0], fx[e][1], fx[e][2]);
       }
@@ -478,7 +478,7 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
     u32 sel[NE];
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
-      if (selector == 0) {
+      if constexpr (MLP) {
         __builtin_amdgcn_sched_barrier(0);
         const u32 mk = classify_packed<PREC>(w, fx[e][0], fx[e][1], fx[e][2], margin, nullptr);
         sel[e] = mk & 15u;
@@ -1348,9 +1348,15 @@ hipError_t launch_faces_kernel(const FaceLaunch &L, const FastArgs &fa, hipStrea
                                const Line1D &ln, const Grid2D &g, int dir, const float *q,
                                const uint8_t *mi, float *F, uint8_t *m, u32 *qc) {
 #define N6_FACES(P, W)                                                                        \
-  hipLaunchKernelGGL((k_fast_faces<P, NV, W>), dim3(L.grid), dim3(W * 64), 0, s, ln, g, dir,  \
-                     fa.selector, fa.prepared, fa.margin, q, mi, F, m, fa.scr.queue, qc,      \
+  hipLaunchKernelGGL((k_fast_faces<P, NV, W, true>), dim3(L.grid), dim3(W * 64), 0, s, ln, g,  \
+                     dir, fa.selector, fa.prepared, fa.margin, q, mi, F, m, fa.scr.queue, qc,  \
                      fa.scr.qcap, L.xcd)
+  if (fa.selector != 0) {  // the other selectors: no classifier, one instantiation
+    hipLaunchKernelGGL((k_fast_faces<2, NV, 4, false>), dim3(L.grid), dim3(256), 0, s, ln, g, dir,
+                       fa.selector, fa.prepared, fa.margin, q, mi, F, m, fa.scr.queue, qc,
+                       fa.scr.qcap, L.xcd);
+    return hipGetLastError();
+  }
   // 2D sweeps: two waves per workgroup spill registers, so they take four
   const int waves = (NV == 4 && L.waves == 2) ? 4 : L.waves;
   if constexpr (NV == 3) {
