@@ -6,6 +6,10 @@
 * AdvectionRHS: right-hand side of the advection equation at fixed candidate
   masks (a linear map of u once the selection is fixed); its backward is the
   library's adjoint kernel neno6_rhs_adjoint.
+* RHSFixedLabels: right-hand side of the Burgers or 1D Euler equations with
+  the labels held fixed (a smooth function of the state away from ties in
+  the Rusanov speed); its backward is the library's vector-Jacobian kernel
+  neno6_rhs_vjp (through the fluxes, the Roe average and the eigenvectors).
 
 Only argument marshalling happens here; every arithmetic step runs in
 libneno6.so.
@@ -54,9 +58,34 @@ class AdvectionRHS(torch.autograd.Function):
         return ubar, None, None
 
 
+class RHSFixedLabels(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, q: torch.Tensor, masks: torch.Tensor, prob: "native.Problem"):
+        if prob.equation not in (native.BURGERS, native.EULER1D) or \
+                prob.selector != native.SEL_MASKS_IN:
+            raise ValueError("RHSFixedLabels needs a Burgers or 1D Euler problem with SEL_MASKS_IN")
+        qd = q.detach().contiguous()
+        rhs = torch.empty_like(qd)
+        native.neno6_rhs(prob, None, qd, rhs, prob.workspace(q.device), masks_in=masks)
+        ctx.prob = prob
+        ctx.save_for_backward(qd, masks)
+        return rhs
+
+    @staticmethod
+    def backward(ctx, rbar):
+        qd, masks = ctx.saved_tensors
+        qbar = torch.empty_like(qd)
+        native.neno6_rhs_vjp(ctx.prob, qd, masks, rbar.contiguous(), qbar)
+        return qbar, None, None
+
+
 def classifier_bce(params, s, y, precision=native.FP32):
     return ClassifierBCE.apply(params, s, y, precision)
 
 
 def advection_rhs(u, masks, prob):
     return AdvectionRHS.apply(u, masks, prob)
+
+
+def rhs_fixed_labels(q, masks, prob):
+    return RHSFixedLabels.apply(q, masks, prob)

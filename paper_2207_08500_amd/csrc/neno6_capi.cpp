@@ -530,6 +530,37 @@ int32_t neno6_rhs_adjoint(const neno6_problem *prob, const uint8_t *masks, const
                                              prob->precision == NENO6_FP64, stream));
 }
 
+size_t neno6_vjp_workspace_size(const neno6_problem *prob) {
+  if (check_problem(prob) != NENO6_OK) return 0;
+  if (prob->equation != NENO6_BURGERS && prob->equation != NENO6_EULER1D) return 0;
+  const size_t faces = (size_t)prob->total_cells + prob->n_problems;
+  return align_up(faces * sizeof(int32_t)) +
+         align_up(6 * (size_t)nvar_of(prob->equation) * faces * elem_size(prob->precision));
+}
+
+int32_t neno6_rhs_vjp(const neno6_problem *prob, const void *q, const uint8_t *masks,
+                      const void *rbar, void *qbar, void *ws, size_t ws_bytes,
+                      hipStream_t stream) {
+  if (int32_t c = check_problem(prob)) return c;
+  if (prob->equation != NENO6_BURGERS && prob->equation != NENO6_EULER1D) return NENO6_UNSUPPORTED;
+  if (prob->precision != NENO6_FP64 && prob->precision != NENO6_FP32) return NENO6_BAD_LAYOUT;
+  if (!q || !masks || !rbar || !qbar || !ws) return NENO6_BAD_ARG;
+  const size_t need = neno6_vjp_workspace_size(prob);
+  if (ws_bytes < need) return NENO6_WORKSPACE_SMALL;
+  const size_t faces = (size_t)prob->total_cells + prob->n_problems;
+  int32_t *fmap = (int32_t *)ws;
+  void *scratch = (char *)ws + align_up(faces * sizeof(int32_t));
+  const Line1D ln = line_of(prob, fmap);
+  if (launch_build_fmap(line_of(prob), fmap, stream) != hipSuccess) return NENO6_HIP_ERROR;
+  hipError_t e =
+      prob->precision == NENO6_FP64
+          ? launch_vjp1d<double>(ln, prob->equation, (const double *)q, masks,
+                                 (const double *)rbar, (double *)qbar, (double *)scratch, stream)
+          : launch_vjp1d<float>(ln, prob->equation, (const float *)q, masks, (const float *)rbar,
+                                (float *)qbar, (float *)scratch, stream);
+  return hip_status(e);
+}
+
 size_t neno6_train_workspace_size(int32_t batch) { return train_workspace_bytes(batch); }
 
 int32_t neno6_classifier_train(double *params, double *adam_m, double *adam_v, int64_t *step,

@@ -96,6 +96,12 @@ template <typename T>
 hipError_t launch_cfl2d(const Grid2D &g, const T *q, double cfl, double *part, double *dt,
                         int32_t *status, double *t, hipStream_t s);
 
+// Vector-Jacobian product of the 1D right-hand side (Burgers or Euler) at
+// fixed labels: qbar = (d rhs / d q)^T rbar; scratch holds 6 * nvar * faces
+// values.
+template <typename T>
+hipError_t launch_vjp1d(const Line1D &ln, int equation, const T *q, const uint8_t *masks,
+                        const T *rbar, T *qbar, T *scratch, hipStream_t s);
 // Fixed-mask adjoint of the advection rhs (one line).
 hipError_t launch_adjoint_advection(const Line1D &ln, const uint8_t *masks, const void *rbar,
                                     void *ubar, int is_fp64, hipStream_t s);

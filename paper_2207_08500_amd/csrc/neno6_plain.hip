@@ -670,6 +670,272 @@ k_adjoint_advection(int64_t n, const double *__restrict__ dxp, int bc,
   ubar[c] = acc;
 }
 
+// ---- vector-Jacobian products of the right-hand side at fixed labels --------
+// With the labels of every evaluation held fixed, the face flux is a smooth
+// function of the six stencil states (away from ties in the Rusanov speed
+// max), and rhs_i = (F_i - F_{i+1}) / dx.  The adjoint runs per face in
+// reverse through back-projection, the fixed-weight combine, the split
+// g +- alpha v, the projections, the Rusanov speed (into the cell that
+// attains the max) and the Roe average; per-face contributions to the six
+// stencil cells are then gathered per cell in a fixed order.
+
+// Reverse of the 1D Euler face flux: Fb = dL/dFhat, qb[j][r] += dL/dq_j.
+template <typename T>
+N6_DEV void face_vjp_euler1d(const T qs[6][3], T gamma, const uint8_t msk[3], const T Fb[3],
+                             T qb[6][3]) {
+  const T g1 = gamma - T(1);
+  T u[6], p[6], c[6], F[6][3];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    prim1d<T>(qs[j], gamma, u[j], p[j], c[j]);
+    flux1d<T>(qs[j], u[j], p[j], F[j]);
+  }
+  // Roe average of cells 2, 3 and the eigenvectors (as in roe1d)
+  const T sL = sqrt_<T>(qs[2][0]), sR = sqrt_<T>(qs[3][0]);
+  const T HL = (qs[2][2] + p[2]) / qs[2][0], HR = (qs[3][2] + p[3]) / qs[3][0];
+  const T den = sL + sR;
+  const T ut = (sL * u[2] + sR * u[3]) / den;
+  const T Ht = (sL * HL + sR * HR) / den;
+  const T q2 = T(0.5) * (ut * ut);
+  const T c2 = g1 * (Ht - q2);
+  const T ct = sqrt_<T>(c2);
+  const T b1 = g1 / c2, b2 = b1 * q2, uc = ut / ct, ic = T(1) / ct;
+  const T L[3][3] = {{T(0.5) * (b2 + uc), T(-0.5) * (b1 * ut + ic), T(0.5) * b1},
+                     {T(1) - b2, b1 * ut, -b1},
+                     {T(0.5) * (b2 - uc), T(-0.5) * (b1 * ut - ic), T(0.5) * b1}};
+  const T R[3][3] = {{T(1), T(1), T(1)}, {ut - ct, ut, ut + ct}, {Ht - ut * ct, q2, Ht + ut * ct}};
+  // forward values needed by the reverse sweep
+  T v[6][3], alpha[3], hs[3];
+  int am[3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    alpha[m] = T(0);
+    am[m] = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const T lam = m == 0 ? u[j] - c[j] : (m == 1 ? u[j] : u[j] + c[j]);
+      const T a = abs_<T>(lam);
+      if (a > alpha[m]) {
+        alpha[m] = a;
+        am[m] = j;
+      }
+    }
+  }
+  T sp[3][6], sm[3][6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      v[j][m] = L[m][0] * qs[j][0] + L[m][1] * qs[j][1] + L[m][2] * qs[j][2];
+      const T g = L[m][0] * F[j][0] + L[m][1] * F[j][1] + L[m][2] * F[j][2];
+      sp[m][j] = T(0.5) * (g + alpha[m] * v[j][m]);
+      sm[m][5 - j] = T(0.5) * (g - alpha[m] * v[j][m]);
+    }
+  T Wp[3][6], Wm[3][6];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    face_coeffs<T>(msk[m] & 15u, Wp[m]);
+    face_coeffs<T>((msk[m] >> 4) & 15u, Wm[m]);
+    T h = T(0);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) h = h + Wp[m][j] * sp[m][j] + Wm[m][j] * sm[m][j];
+    hs[m] = h;
+  }
+  // ---- reverse ----
+  T hsb[3], Rb[3][3], Lb[3][3] = {}, ub[6] = {}, pb[6] = {}, cb[6] = {}, Fcb[6][3] = {};
+#pragma unroll
+  for (int m = 0; m < 3; ++m) hsb[m] = R[0][m] * Fb[0] + R[1][m] * Fb[1] + R[2][m] * Fb[2];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) Rb[r][m] = Fb[r] * hs[m];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    T ab = T(0);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const T spb = Wp[m][j] * hsb[m], smb = Wm[m][5 - j] * hsb[m];
+      const T gb = T(0.5) * (spb + smb);
+      const T vb = T(0.5) * alpha[m] * (spb - smb);
+      ab = ab + T(0.5) * v[j][m] * (spb - smb);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        Lb[m][r] = Lb[m][r] + vb * qs[j][r] + gb * F[j][r];
+        qb[j][r] = qb[j][r] + L[m][r] * vb;
+        Fcb[j][r] = Fcb[j][r] + L[m][r] * gb;
+      }
+    }
+    // Rusanov speed: |lambda_m| of the cell that attains the max
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      if (j == am[m]) {
+        const T lam = m == 0 ? u[j] - c[j] : (m == 1 ? u[j] : u[j] + c[j]);
+        const T sb = lam < T(0) ? -ab : ab;
+        ub[j] = ub[j] + sb;
+        if (m == 0) cb[j] = cb[j] - sb;
+        if (m == 2) cb[j] = cb[j] + sb;
+      }
+  }
+  // Roe quantities
+  const T b2b = T(0.5) * Lb[0][0] - Lb[1][0] + T(0.5) * Lb[2][0];
+  const T ucb = T(0.5) * Lb[0][0] - T(0.5) * Lb[2][0];
+  T b1b = T(-0.5) * ut * Lb[0][1] + T(0.5) * Lb[0][2] + ut * Lb[1][1] - Lb[1][2] -
+          T(0.5) * ut * Lb[2][1] + T(0.5) * Lb[2][2];
+  T utb = T(-0.5) * b1 * Lb[0][1] + b1 * Lb[1][1] - T(0.5) * b1 * Lb[2][1];
+  const T icb = T(-0.5) * Lb[0][1] + T(0.5) * Lb[2][1];
+  utb = utb + Rb[1][0] + Rb[1][1] + Rb[1][2] - ct * Rb[2][0] + ct * Rb[2][2];
+  T ctb = -Rb[1][0] + Rb[1][2] - ut * Rb[2][0] + ut * Rb[2][2];
+  T Htb = Rb[2][0] + Rb[2][2];
+  T q2b = Rb[2][1];
+  b1b = b1b + q2 * b2b;
+  q2b = q2b + b1 * b2b;
+  utb = utb + ucb / ct;
+  ctb = ctb - ucb * ut / (ct * ct) - icb / (ct * ct);
+  T c2b = -b1b * g1 / (c2 * c2) + ctb / (T(2) * ct);
+  Htb = Htb + g1 * c2b;
+  q2b = q2b - g1 * c2b;
+  utb = utb + ut * q2b;
+  const T sLb = (u[2] - ut) / den * utb + (HL - Ht) / den * Htb;
+  const T sRb = (u[3] - ut) / den * utb + (HR - Ht) / den * Htb;
+  ub[2] = ub[2] + sL / den * utb;
+  ub[3] = ub[3] + sR / den * utb;
+  const T HLb = sL / den * Htb, HRb = sR / den * Htb;
+  qb[2][2] = qb[2][2] + HLb / qs[2][0];
+  pb[2] = pb[2] + HLb / qs[2][0];
+  qb[2][0] = qb[2][0] - HLb * HL / qs[2][0] + sLb / (T(2) * sL);
+  qb[3][2] = qb[3][2] + HRb / qs[3][0];
+  pb[3] = pb[3] + HRb / qs[3][0];
+  qb[3][0] = qb[3][0] - HRb * HR / qs[3][0] + sRb / (T(2) * sR);
+  // cell fluxes and primitives
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const T m_ = qs[j][1], E = qs[j][2], rho = qs[j][0];
+    qb[j][1] = qb[j][1] + Fcb[j][0] + u[j] * Fcb[j][1];
+    ub[j] = ub[j] + m_ * Fcb[j][1] + (E + p[j]) * Fcb[j][2];
+    pb[j] = pb[j] + Fcb[j][1] + u[j] * Fcb[j][2];
+    qb[j][2] = qb[j][2] + u[j] * Fcb[j][2];
+    // c = sqrt(gamma p / rho)
+    const T wb = cb[j] / (T(2) * c[j]);
+    pb[j] = pb[j] + gamma / rho * wb;
+    qb[j][0] = qb[j][0] - gamma * p[j] / (rho * rho) * wb;
+    // p = g1 (E - m u / 2)
+    qb[j][2] = qb[j][2] + g1 * pb[j];
+    qb[j][1] = qb[j][1] - T(0.5) * g1 * u[j] * pb[j];
+    ub[j] = ub[j] - T(0.5) * g1 * m_ * pb[j];
+    // u = m / rho
+    qb[j][1] = qb[j][1] + ub[j] / rho;
+    qb[j][0] = qb[j][0] - ub[j] * u[j] / rho;
+  }
+}
+
+// Reverse of the Burgers face flux (f = u^2/2, alpha = max |u| over the cells).
+template <typename T>
+N6_DEV void face_vjp_burgers(const T us[6], uint8_t msk, T Fb, T qb[6][3]) {
+  T alpha = T(0);
+  int am = 0;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const T a = abs_<T>(us[j]);
+    if (a > alpha) {
+      alpha = a;
+      am = j;
+    }
+  }
+  T Wp[6], Wm[6];
+  face_coeffs<T>(msk & 15u, Wp);
+  face_coeffs<T>((msk >> 4) & 15u, Wm);
+  T ab = T(0);
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const T spb = Wp[j] * Fb, smb = Wm[5 - j] * Fb;
+    // s+_j = (f + alpha u)/2, s-_{5-j} = (f - alpha u)/2, f' = u
+    qb[j][0] = qb[j][0] + T(0.5) * (us[j] * (spb + smb) + alpha * (spb - smb));
+    ab = ab + T(0.5) * us[j] * (spb - smb);
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j)
+    if (j == am) qb[j][0] = qb[j][0] + (us[j] < T(0) ? -ab : ab);
+}
+
+// Per face: contributions cb[(j * nv + r) * tf + g] to the six stencil cells.
+template <typename T>
+__global__ void __launch_bounds__(TPB)
+k_vjp_faces1d(Line1D ln, int equation, const T *__restrict__ q, const uint8_t *__restrict__ masks,
+              const T *__restrict__ rbar, T *__restrict__ cb) {
+  const int64_t tf = ln.faces();
+  const int64_t g = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  if (g >= tf) return;
+  const int p = line_of_face(ln, g);
+  const int64_t o = ln.offsets[p], n = ln.offsets[p + 1] - o, k = g - o - p;
+  const T dx = (T)ln.dx[p];
+  const int nv = equation == 2 ? 3 : 1;
+  T qb[6][3] = {};
+  T Fb[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    if (r >= nv) break;
+    const T right = k < n ? rbar[r * ln.total + o + k] : T(0);
+    const T left = k > 0 ? rbar[r * ln.total + o + k - 1] : T(0);
+    Fb[r] = (right - left) / dx;
+  }
+  if (equation == 2) {
+    T qs[6][3];
+    uint8_t msk[3];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int64_t ci = o + ghost(k - 3 + j, n, ln.bc);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) qs[j][r] = q[r * ln.total + ci];
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) msk[m] = masks[m * tf + g];
+    face_vjp_euler1d<T>(qs, (T)ln.gamma, msk, Fb, qb);
+  } else {
+    T us[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) us[j] = q[o + ghost(k - 3 + j, n, ln.bc)];
+    face_vjp_burgers<T>(us, masks[g], Fb[0], qb);
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j)
+    for (int r = 0; r < nv; ++r) cb[(int64_t)(j * nv + r) * tf + g] = qb[j][r];
+}
+
+// Per cell: sum of the face contributions that read it, in a fixed order
+// (direct stencil positions by ascending face, then ghost positions).
+template <typename T>
+__global__ void __launch_bounds__(TPB)
+k_vjp_gather1d(Line1D ln, int nv, const T *__restrict__ cb, T *__restrict__ qbar) {
+  const int64_t tf = ln.faces();
+  const int64_t gidx = blockIdx.x * (int64_t)TPB + threadIdx.x;  // face index = left face of the cell
+  if (gidx >= tf) return;
+  const int p = line_of_face(ln, gidx);
+  const int64_t o = ln.offsets[p], n = ln.offsets[p + 1] - o, c = gidx - o - p;
+  if (c >= n) return;
+  const int64_t f0 = o + p;  // global index of face 0 of the line
+  for (int r = 0; r < nv; ++r) {
+    T acc = T(0);
+    // direct: face k reads cell k - 3 + j
+    for (int64_t k = c - 2; k <= c + 3; ++k) {
+      if (k < 0 || k > n) continue;
+      const int j = (int)(c - k + 3);
+      acc = acc + cb[(int64_t)(j * nv + r) * tf + f0 + k];
+    }
+    // ghost positions that map onto cell c
+    if (c < 3 || c > n - 4) {
+      for (int64_t k = 0; k <= n; ++k) {
+        if (k > 5 && k < n - 5) continue;
+        for (int j = 0; j < 6; ++j) {
+          const int64_t cc = k - 3 + j;
+          if (cc >= 0 && cc < n) continue;
+          if (ghost(cc, n, ln.bc) == c) acc = acc + cb[(int64_t)(j * nv + r) * tf + f0 + k];
+        }
+      }
+    }
+    qbar[r * ln.total + o + c] = acc;
+  }
+}
+
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + TPB - 1) / TPB); }
 inline int64_t pad_to_block(int64_t n) { return (n + TPB - 1) / TPB * TPB; }
 
@@ -828,6 +1094,18 @@ hipError_t launch_adjoint_advection(const Line1D &ln, const uint8_t *masks, cons
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_vjp1d(const Line1D &ln, int equation, const T *q, const uint8_t *masks,
+                        const T *rbar, T *qbar, T *scratch, hipStream_t s) {
+  hipLaunchKernelGGL(k_vjp_faces1d<T>, dim3(nblocks(ln.faces())), dim3(TPB), 0, s, ln, equation, q,
+                     masks, rbar, scratch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_vjp_gather1d<T>, dim3(nblocks(ln.faces())), dim3(TPB), 0, s, ln,
+                     equation == 2 ? 3 : 1, scratch, qbar);
+  return hipGetLastError();
+}
+
 hipError_t launch_params_to_f32(const double *P, float *P32, hipStream_t s) {
   hipLaunchKernelGGL(k_params_to_f32, dim3(nblocks(NPARAM)), dim3(TPB), 0, s, P, P32);
   return hipGetLastError();
@@ -855,7 +1133,9 @@ hipError_t launch_params_to_f32(const double *P, float *P32, hipStream_t s) {
   template hipError_t launch_diff2d<T>(const Grid2D &, const T *, const T *, const T *, T *,     \
                                        const Stage *, int32_t *, hipStream_t, uint32_t *);       \
   template hipError_t launch_cfl2d<T>(const Grid2D &, const T *, double, double *, double *,     \
-                                      int32_t *, double *, hipStream_t);
+                                      int32_t *, double *, hipStream_t);                         \
+  template hipError_t launch_vjp1d<T>(const Line1D &, int, const T *, const uint8_t *, const T *, \
+                                      T *, T *, hipStream_t);
 
 N6_INST(double)
 N6_INST(float)

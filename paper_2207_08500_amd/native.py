@@ -29,7 +29,8 @@ EXPORTS = (
     "neno6_status_string", "neno6_version", "neno6_mlp_prepared_bytes", "neno6_mlp_prepare",
     "neno6_mlp_logits", "neno6_reconstruct", "neno6_workspace_size", "neno6_rhs",
     "neno6_face_fluxes", "neno6_recheck_count", "neno6_autotune", "neno6_step",
-    "neno6_rhs_adjoint", "neno6_train_workspace_size", "neno6_classifier_train",
+    "neno6_rhs_adjoint", "neno6_vjp_workspace_size", "neno6_rhs_vjp",
+    "neno6_train_workspace_size", "neno6_classifier_train",
     "neno6_classifier_grad",
 )
 
@@ -92,6 +93,9 @@ def load(path: str = LIB_PATH):
                                        P(TuningStruct), P(C.c_float), vp]
         lib.neno6_step.argtypes = [P(ProblemStruct), P(MlpStruct), vp, f64, i32, vp, vp, vp, sz, vp]
         lib.neno6_rhs_adjoint.argtypes = [P(ProblemStruct), vp, vp, vp, vp]
+        lib.neno6_vjp_workspace_size.argtypes = [P(ProblemStruct)]
+        lib.neno6_vjp_workspace_size.restype = sz
+        lib.neno6_rhs_vjp.argtypes = [P(ProblemStruct), vp, vp, vp, vp, vp, sz, vp]
         lib.neno6_train_workspace_size.argtypes = [i32]
         lib.neno6_train_workspace_size.restype = sz
         lib.neno6_classifier_train.argtypes = [vp, vp, vp, P(C.c_int64), vp, vp, vp, i64, i32, f64,
@@ -332,6 +336,26 @@ def neno6_rhs_adjoint(prob: Problem, masks: torch.Tensor, rbar: torch.Tensor, ub
     ps = prob.struct()
     _check(load().neno6_rhs_adjoint(C.byref(ps), _ptr(masks), _ptr(rbar), _ptr(ubar),
                                     _stream(stream)), "neno6_rhs_adjoint")
+
+
+def neno6_rhs_vjp(prob: Problem, q: torch.Tensor, masks: torch.Tensor, rbar: torch.Tensor,
+                  qbar: torch.Tensor, ws: torch.Tensor | None = None, stream=None):
+    """qbar = (d rhs / d q)^T rbar at q with fixed labels (BURGERS, EULER1D)."""
+    dt = fdtype(prob.precision)
+    for t, nm in ((q, "q"), (rbar, "rbar"), (qbar, "qbar")):
+        _dev(t, dt, nm)
+        if t.numel() != prob.nvar * prob.total_cells:
+            raise ValueError("%s size mismatch" % nm)
+    if masks.numel() != prob.mask_count() or masks.dtype != torch.uint8:
+        raise ValueError("masks must be uint8 with %d entries" % prob.mask_count())
+    ps = prob.struct()
+    if ws is None:
+        nb = int(load().neno6_vjp_workspace_size(C.byref(ps)))
+        if nb == 0:
+            raise Neno6Error("neno6_rhs_vjp: unsupported problem")
+        ws = torch.empty(nb, dtype=torch.uint8, device=q.device)
+    _check(load().neno6_rhs_vjp(C.byref(ps), _ptr(q), _ptr(masks), _ptr(rbar), _ptr(qbar), _ptr(ws),
+                                ws.numel(), _stream(stream)), "neno6_rhs_vjp")
 
 
 def neno6_train_workspace_size(batch: int) -> int:
