@@ -30,6 +30,13 @@ sys.path.insert(0, ROOT)
 N_PROBLEMS, N_CELLS, CFL = 256, 4000, 0.4
 MARGIN = {2: 0.5, 3: 0.25}
 PEAK_MFMA_BF16 = 2500.0  # TFLOP/s dense, MI355X
+# non-packed VALU lane-operations/s: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# algorithmic VALU work per 1D Euler face outside the MFMA contractions:
+# primitives 90, Roe 40, projection + split 180, speeds 20, features 80,
+# one operation per hidden activation 720, output bias + labels 50,
+# combine 180, back-projection 12
+VALU_OPS_PER_FACE = 1350
 FLOP_PER_EVAL = 6208      # 2 x 3104 MAC of the 6-64-32-16-8-4 network
 EVALS_PER_FACE = 6        # 3 characteristic fields x 2 split signs
 
@@ -52,6 +59,14 @@ def _traffic_bytes():
         return int(rec["bytes_per_launch"]) if h.hexdigest() == rec["source_sha256"] else None
     except (OSError, IndexError, KeyError, ValueError):
         return None
+
+
+def _alu(faces, k_ms):
+    """VALU-issue roofline of the fused kernel (the binding one: see the
+    counter profile): algorithmic lane-operations per launch / time."""
+    ach = faces * VALU_OPS_PER_FACE / (k_ms / 1e3) / 1e12
+    return {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "Tlane-op/s",
+            "frac": ach / PEAK_VALU_TOPS, "ops_per_face": VALU_OPS_PER_FACE}
 
 
 def _physical(q, off, gamma=1.4):
@@ -273,6 +288,7 @@ def main():
                      "kernel": "k_fast_faces<BF16, 1D Euler>", "kernel_ms": k_ms,
                      "algorithmic_flop_per_launch": flop,
                      "algorithmic_bytes_per_launch": alg_bytes},
+        "roofline_alu": _alu(faces_stage, k_ms),
         "fp64_plain": {"value": fp64_rate, "unit": "faces/s", "ms_per_step": ms_64 / k64,
                        "steps": k64},
         "fp16_mfma": {"value": fp16_rate, "unit": "faces/s", "ms_per_step": ms_h / a.steps,
@@ -396,6 +412,7 @@ def bench_batched(a, P, dev):
                      "unit": "TFLOP/s", "frac": achieved / PEAK_MFMA_BF16, "traffic": None,
                      "kernel": "k_fast_faces<BF16, 1D Euler>", "kernel_ms": k_ms,
                      "algorithmic_flop_per_launch": flop},
+        "roofline_alu": _alu(faces_stage, k_ms),
         "frozen_problems": {"bf16": int((st != 0).sum()), "of": n_prob},
         "cpu_baseline": cpu,
     }

@@ -435,8 +435,10 @@ N6_DEV void enqueue(bool want, u32 entry, u32 *__restrict__ queue, u32 *__restri
 // With xcd != 0 the workgroup numbering is permuted so that the workgroups
 // the hardware places on one XCD (every 8th) take a contiguous run of tiles
 // (the host only sets it when gridDim.x is a multiple of 8).
+// 1D: three waves per SIMD (a few registers spill, the extra wave hides more
+// of the MFMA -> convert -> MFMA latency); 2D needs its registers: two.
 template <int PREC, int NV, int W, bool MLP>
-__global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(NV == 3 ? 3 : 2)))
 k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict__ prepared,
              float margin, const float *__restrict__ q, const uint8_t *__restrict__ min,
              float *__restrict__ Fh, uint8_t *__restrict__ masks, u32 *__restrict__ queue,
