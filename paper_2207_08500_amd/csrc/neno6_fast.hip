@@ -13,13 +13,17 @@
 //   L2 64 -> 32               : 4 x v_mfma_f32_32x32x16  (bias in the C input)
 //   L3 32 -> 16 (pad 32)      : 2 x v_mfma_f32_32x32x16
 //   L4 16 -> 8  (pad 32)      : 1 x v_mfma_f32_32x32x16
-//   L5 8 -> 4   (pad 32)      : 1 x v_mfma_f32_32x32x16, bias added in FP32
+//   L5 8 -> 4, both tiles     : 1 x v_mfma_f32_32x32x16, bias added in FP32
 // ReLU is applied to the packed 16-bit values with v_pk_max_i16 (a negative
 // BF16/FP16 has its sign bit set, i.e. is a negative int16).
 //
-// One lane computes one face (projection, split, features, combine); the two
-// 32-column tiles of a wave are exchanged between lane halves with
-// v_permlane32_swap.  Evaluations whose smallest |logit| is below the
+// One lane computes one face (projection, split, features, combine).  The
+// L1 inputs of the two 32-column tiles of a wave are exchanged between lane
+// halves with v_permlane32_swap.  The eight L4 outputs of a tile fill only
+// half of the K slots of L5, so the last product takes tile 0 in K slots
+// {0..3, 8..11} and tile 1 in {4..7, 12..15}, with tile 0's logits as rows
+// 0..3 and tile 1's as rows 4..7: every lane then holds its own stencil's
+// four logits in registers 0..3.  Evaluations whose smallest |logit| is below the
 // re-check margin are queued and re-evaluated in FP32 by a second kernel; a
 // third kernel recomputes the fluxes of faces whose label changed.
 #include "neno6_device.h"
@@ -127,12 +131,12 @@ N6_DEV void load_wts(const void *prepared, int lane, Wts &w) {
   for (int k = 0; k < 4; ++k) w.b5[k] = b5[k];
 }
 
-// One 32-evaluation tile through the network; `bin` is the L1 B operand
-// (features 4h..4h+3 of column j, with the constant 1 of the folded L1 bias
-// in slot 6).  Returns L5 without its bias: rows 0..3 (logits) sit in
-// registers 0..3 of lanes 0..31.
+// L1..L4 of one 32-evaluation tile; `bin` is the L1 B operand (features
+// 4h..4h+3 of column j, with the constant 1 of the folded L1 bias in slot 6).
+// Returns the packed L4 activations: neurons 4h..4h+3 of column j (rows 8..31
+// of the L4 product are padding).
 template <int PREC>
-N6_DEV f32x16 mlp_tile(const Wts &w, u32x2 bin) {
+N6_DEV u32x2 mlp_front(const Wts &w, u32x2 bin) {
   const f32x16 zero = {};
   const f32x16 c1a = mma8<PREC>(w.a1[0], bin, zero);
   const f32x16 c1b = mma8<PREC>(w.a1[1], bin, zero);
@@ -160,10 +164,7 @@ N6_DEV f32x16 mlp_tile(const Wts &w, u32x2 bin) {
 #pragma unroll
   for (int p = 0; p < 4; ++p) h3[p] = relu_pack<PREC>(c3[2 * p], c3[2 * p + 1]);
   const f32x16 c4 = mma16<PREC>(w.a4, h3, w.b4);
-  u32x4 h4;
-#pragma unroll
-  for (int p = 0; p < 4; ++p) h4[p] = relu_pack<PREC>(c4[2 * p], c4[2 * p + 1]);
-  return mma16<PREC>(w.a5, h4, zero);
+  return u32x2{relu_pack<PREC>(c4[0], c4[1]), relu_pack<PREC>(c4[2], c4[3])};
 }
 
 // L1 B operand halves of one stencil: X = features 0..3, Y = features 4, 5,
@@ -200,25 +201,18 @@ N6_DEV u32 classify_packed(const Wts &w, u32 x0, u32 x1, u32 y0, float margin, f
   u32 y1 = one_zero<PREC>();
   swap32(x0, y0);  // x0: tile 0 (faces of lanes 0..31), y0: tile 1
   swap32(x1, y1);
-  const f32x16 c0 = mlp_tile<PREC>(w, u32x2{x0, x1});
-  const f32x16 c1 = mlp_tile<PREC>(w, u32x2{y0, y1});
-  float z0[4], z1[4];
+  const u32x2 h0 = mlp_front<PREC>(w, u32x2{x0, x1});
+  const u32x2 h1 = mlp_front<PREC>(w, u32x2{y0, y1});
+  const f32x16 zero = {};
+  const f32x16 c = mma16<PREC>(w.a5, u32x4{h0[0], h0[1], h1[0], h1[1]}, zero);
+  float z[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    z0[k] = c0[k] + w.b5[k];
-    z1[k] = c1[k] + w.b5[k];
-  }
-  u32 m0 = mask_near(z0, margin), m1 = mask_near(z1, margin);
-  swap32(m0, m1);  // lane l now holds its own stencil's result in m0
+  for (int k = 0; k < 4; ++k) z[k] = c[k] + w.b5[k];
   if (z_out) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      u32 a = __builtin_bit_cast(u32, z0[k]), b = __builtin_bit_cast(u32, z1[k]);
-      swap32(a, b);
-      z_out[k] = __builtin_bit_cast(float, a);
-    }
+    for (int k = 0; k < 4; ++k) z_out[k] = z[k];
   }
-  return m0;
+  return mask_near(z, margin);
 }
 
 template <int PREC>
@@ -253,11 +247,13 @@ N6_DEV void setup1d(const Line1D &ln, const float *__restrict__ q, int64_t g, fl
   const int64_t o = ln.offsets[p];
   const int n = (int)(ln.offsets[p + 1] - o), k = (int)(g - o - p);
   const float gm = (float)ln.gamma, g1 = gm - 1.f;
-  const float *qv0 = q + o, *qv1 = q + ln.total + o, *qv2 = q + 2 * ln.total + o;
+  // uniform per-variable bases and 32-bit per-lane offsets (total < 2^29)
+  const float *qv0 = q, *qv1 = q + ln.total, *qv2 = q + 2 * ln.total;
+  const uint32_t o32 = (uint32_t)o;
   float qs[6][3], lam[6][3], F[6][3];
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
-    const int ci = ghost32(k - 3 + j, n, ln.bc);
+    const uint32_t ci = o32 + (uint32_t)ghost32(k - 3 + j, n, ln.bc);
     qs[j][0] = qv0[ci];
     qs[j][1] = qv1[ci];
     qs[j][2] = qv2[ci];
@@ -292,9 +288,11 @@ N6_DEV void setup1d(const Line1D &ln, const float *__restrict__ q, int64_t g, fl
   R[0][0] = 1.f;          R[0][1] = 1.f; R[0][2] = 1.f;
   R[1][0] = ut - ct;      R[1][1] = ut;  R[1][2] = ut + ct;
   R[2][0] = __builtin_fmaf(-ut, ct, Ht); R[2][1] = q2; R[2][2] = __builtin_fmaf(ut, ct, Ht);
-  const float L[3][3] = {{0.5f * (b2 + uc), -0.5f * __builtin_fmaf(b1, ut, ic), 0.5f * b1},
-                         {1.f - b2, b1 * ut, -b1},
-                         {0.5f * (b2 - uc), -0.5f * __builtin_fmaf(b1, ut, -ic), 0.5f * b1}};
+  // H = L / 2: the split (g +- alpha v) / 2 then needs no final halving
+  // (scaling by a power of two is exact, so the values are those of L)
+  const float H[3][3] = {{0.25f * (b2 + uc), -0.25f * __builtin_fmaf(b1, ut, ic), 0.25f * b1},
+                         {0.5f * (1.f - b2), 0.5f * (b1 * ut), -0.5f * b1},
+                         {0.25f * (b2 - uc), -0.25f * __builtin_fmaf(b1, ut, -ic), 0.25f * b1}};
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
     float alpha = 0.f;
@@ -302,10 +300,10 @@ N6_DEV void setup1d(const Line1D &ln, const float *__restrict__ q, int64_t g, fl
     for (int j = 0; j < 6; ++j) alpha = fmaxf(alpha, fabsf(lam[j][m]));
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-      const float v = __builtin_fmaf(L[m][2], qs[j][2], __builtin_fmaf(L[m][1], qs[j][1], L[m][0] * qs[j][0]));
-      const float gg = __builtin_fmaf(L[m][2], F[j][2], __builtin_fmaf(L[m][1], F[j][1], L[m][0] * F[j][0]));
-      s[2 * m][j] = 0.5f * __builtin_fmaf(alpha, v, gg);
-      s[2 * m + 1][5 - j] = 0.5f * __builtin_fmaf(-alpha, v, gg);
+      const float v = __builtin_fmaf(H[m][2], qs[j][2], __builtin_fmaf(H[m][1], qs[j][1], H[m][0] * qs[j][0]));
+      const float gg = __builtin_fmaf(H[m][2], F[j][2], __builtin_fmaf(H[m][1], F[j][1], H[m][0] * F[j][0]));
+      s[2 * m][j] = __builtin_fmaf(alpha, v, gg);
+      s[2 * m + 1][5 - j] = __builtin_fmaf(-alpha, v, gg);
     }
   }
 }
@@ -477,14 +475,14 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
 #pragma unroll
         for (int b = 0; b < NV; ++b) stash[wv][NE * 6 + a * NV + b][lane] = R[a][b];
     }
-    u32 sel[NE];
+    u32 sel[NE], near = 0u;
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
       if constexpr (MLP) {
         __builtin_amdgcn_sched_barrier(0);
         const u32 mk = classify_packed<PREC>(w, fx[e][0], fx[e][1], fx[e][2], margin, nullptr);
         sel[e] = mk & 15u;
-        enqueue(valid && (mk & 16u), (u32)(fc * 8 + e), queue, qcount, qcap);
+        near |= (mk >> 4) << e;
       } else if (selector == 1) {
         sel[e] = 15u;
       } else if (selector == 2) {
@@ -499,6 +497,11 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
       }
     }
     __builtin_amdgcn_sched_barrier(0);
+    if constexpr (MLP) {  // queue the near-cutoff evaluations for the FP32 re-check
+#pragma unroll
+      for (int e = 0; e < NE; ++e)
+        enqueue(valid && ((near >> e) & 1u), (u32)(fc * 8 + e), queue, qcount, qcap);
+    }
     float hs[NV], Fo[NV], R[NV][NV];
 #pragma unroll
     for (int m = 0; m < NV; ++m) {
@@ -931,10 +934,9 @@ __global__ void __launch_bounds__(TPB) k_prepare(const double *__restrict__ P, c
       const int e = 2 * (reg - 28) + q2;
       const int n3 = 8 * (e / 4) + 4 * h + e % 4;
       x = i < 8 ? P[OW4 + i * 16 + n3] : 0.0;
-    } else if (reg < 36) {  // L5
-      const int e = 2 * (reg - 32) + q2;
-      const int n4 = 8 * (e / 4) + 4 * h + e % 4;
-      x = (i < 4 && n4 < 8) ? P[OW5 + i * 8 + n4] : 0.0;
+    } else if (reg < 36) {  // L5: K slots e < 4 carry tile 0 (rows 0..3), e >= 4 tile 1 (rows 4..7)
+      const int e = 2 * (reg - 32) + q2, t5 = e / 4, n4 = 4 * h + e % 4;
+      x = i / 4 == t5 ? P[OW5 + (i % 4) * 8 + n4] : 0.0;
     } else {
       is_bias = true;
     }
@@ -1126,10 +1128,11 @@ k_grad_mfma(const void *__restrict__ prepared, const u32 *__restrict__ btab,
 #pragma unroll
     for (int p = 0; p < 4; ++p) h3[p] = relu_pack<2>(c3[2 * p], c3[2 * p + 1]);
     const f32x16 c4 = mma16<2>(w.a4, u32x4{h3[0], h3[1], h3[2], h3[3]}, w.b4);
-    u32 h4[4];
+    // L4 rows 8..31 are padding; the L5 K slots of the second tile stay zero
+    u32 h4[2];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) h4[p] = relu_pack<2>(c4[2 * p], c4[2 * p + 1]);
-    const f32x16 c5 = mma16<2>(w.a5, u32x4{h4[0], h4[1], h4[2], h4[3]}, zero);
+    for (int p = 0; p < 2; ++p) h4[p] = relu_pack<2>(c4[2 * p], c4[2 * p + 1]);
+    const f32x16 c5 = mma16<2>(w.a5, u32x4{h4[0], h4[1], 0u, 0u}, zero);
     // loss and output deltas (lanes of the first half hold the four logits)
     float d5[4];
 #pragma unroll
