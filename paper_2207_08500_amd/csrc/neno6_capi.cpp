@@ -157,7 +157,7 @@ Work carve_work(const neno6_problem *pb, void *ws) {
     w.scr.masks = c.take<uint8_t>(4 * faces);
     w.scr.queue = c.take<uint32_t>(8 * qfaces);
     w.scr.qflag = c.take<uint8_t>(8 * qfaces);
-    w.scr.qcount = c.take<uint32_t>(2);
+    w.scr.qcount = c.take<uint32_t>(QCOUNTERS);
     w.scr.qcap = (int64_t)(8 * qfaces);
   }
   w.bytes = c.used;
@@ -402,7 +402,17 @@ int32_t neno6_recheck_count(const neno6_problem *prob, const void *ws, size_t ws
   const Work w = carve_work(prob, (void *)ws);
   if (ws_bytes < w.bytes) return NENO6_WORKSPACE_SMALL;
   if (hipStreamSynchronize(stream) != hipSuccess) return NENO6_HIP_ERROR;
-  return hip_status(hipMemcpy(count, w.scr.qcount, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost));
+  uint32_t qc[QCOUNTERS];
+  if (hipMemcpy(qc, w.scr.qcount, sizeof(qc), hipMemcpyDeviceToHost) != hipSuccess)
+    return NENO6_HIP_ERROR;
+  if (prob->equation == NENO6_EULER2D) {
+    count[0] = qc[0];
+    count[1] = qc[1];
+  } else {  // one counter per evaluation kind
+    count[0] = qc[0] + qc[1] + qc[2] + qc[3] + qc[4] + qc[5];
+    count[1] = 0;
+  }
+  return NENO6_OK;
 }
 
 int32_t neno6_autotune(const neno6_problem *prob, const neno6_mlp *mlp, const void *q, void *ws,

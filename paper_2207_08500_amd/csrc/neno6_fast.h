@@ -9,9 +9,10 @@ namespace n6 {
 // Scratch of the fast path, carved from the caller's workspace.
 struct FastScratch {
   uint8_t *masks;       // [nvar][faces] (1D) or x|y masks (2D), when the caller passes none
-  uint32_t *queue;      // re-check entries: face * 8 + (field * 2 + sign)
+  uint32_t *queue;      // re-check entries: face * 8 + (field * 2 + sign); 1D: one
+                        // list of `faces` entries per evaluation kind e at e * faces
   uint8_t *qflag;       // per entry: label changed by the FP32 re-check
-  uint32_t *qcount;     // [2] entries in the queue, per sweep direction
+  uint32_t *qcount;     // [QCOUNTERS] entries queued: 1D per kind, 2D per direction
   int64_t qcap;         // queue capacity
 };
 

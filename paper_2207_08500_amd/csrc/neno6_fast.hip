@@ -423,6 +423,20 @@ N6_DEV void enqueue(bool want, u32 entry, u32 *__restrict__ queue, u32 *__restri
   if (want && (int64_t)(base + off) < qcap) queue[base + off] = entry;
 }
 
+// The same into the list that starts at queue[first] (capacity cap < 2^32).
+N6_DEV void enqueue_at(bool want, u32 entry, u32 *__restrict__ queue, u32 first,
+                       u32 *__restrict__ qcount, u32 cap) {
+  const uint64_t bal = __ballot(want);
+  if (bal == 0) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((unsigned long long)bal) - 1;
+  u32 base = 0;
+  if (lane == leader) base = atomicAdd(qcount, (u32)__popcll(bal));
+  base = __shfl(base, leader);
+  const u32 off = base + (u32)__popcll(bal & ((1ull << lane) - 1));
+  if (want && off < cap) queue[first + off] = entry;
+}
+
 // ---- fused face kernel ------------------------------------------------------------
 // NV = 3: faces of a batch of 1D lines; NV = 4: faces of one 2D sweep.
 // One lane per face, 64 consecutive faces per wave and iteration.  The split
@@ -500,7 +514,11 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
     if constexpr (MLP) {  // queue the near-cutoff evaluations for the FP32 re-check
 #pragma unroll
       for (int e = 0; e < NE; ++e)
-        enqueue(valid && ((near >> e) & 1u), (u32)(fc * 8 + e), queue, qcount, qcap);
+        if constexpr (NV == 3)  // one list per evaluation kind (6 faces < 2^32)
+          enqueue_at(valid && ((near >> e) & 1u), (u32)(fc * 8 + e), queue, (u32)e * (u32)nf,
+                     qcount + e, (u32)nf);
+        else
+          enqueue(valid && ((near >> e) & 1u), (u32)(fc * 8 + e), queue, qcount, qcap);
     }
     float hs[NV], Fo[NV], R[NV][NV];
 #pragma unroll
@@ -671,19 +689,74 @@ N6_DEV void stencil_one(const Line1D &ln, const float *__restrict__ q, int64_t f
   for (int j = 0; j < 6; ++j) se[j] = s[E][j];
 }
 
+// Re-check entry slots.  1D: the six per-kind lists, each padded to a whole
+// number of waves' worth of slots (EPW), laid end to end, so the entries of
+// one wave always share the evaluation kind (and the stencil set-up the wave
+// runs); slot i maps to list e, position j, valid while j < count of e.
+// 2D: one list, slot i is entry i.
+constexpr int EPW = 16;  // re-check entries per wave (one per quad)
+
+struct QueueSlots {
+  int64_t base[6], count[6], total;
+};
+
+template <int DIM>
+N6_DEV QueueSlots queue_slots(const u32 *__restrict__ qcount, int64_t qcap, int64_t nf) {
+  QueueSlots qs{};
+  if constexpr (DIM == 1) {
+    int64_t b = 0;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      const int64_t c = (int64_t)qcount[e] < nf ? (int64_t)qcount[e] : nf;
+      qs.base[e] = b;
+      qs.count[e] = c;
+      b += (c + EPW - 1) / EPW * EPW;
+    }
+    qs.total = b;
+  } else {
+    qs.total = (int64_t)qcount[0] < qcap ? (int64_t)qcount[0] : qcap;
+  }
+  return qs;
+}
+
+// Slot i -> (queue position, evaluation kind); false for a padding slot.
+template <int DIM>
+N6_DEV bool queue_slot(const QueueSlots &qs, int64_t i, int64_t nf, int64_t &pos, int &e) {
+  if constexpr (DIM == 1) {
+    e = 0;
+#pragma unroll
+    for (int k = 1; k < 6; ++k) e += i >= qs.base[k] ? 1 : 0;
+    int64_t b = qs.base[0], c = qs.count[0];
+#pragma unroll
+    for (int k = 1; k < 6; ++k) {
+      b = e == k ? qs.base[k] : b;
+      c = e == k ? qs.count[k] : c;
+    }
+    const int64_t j = i - b;
+    pos = (int64_t)e * nf + j;
+    return j < c;
+  } else {
+    pos = i;
+    e = 0;
+    return true;
+  }
+}
+
 // FP32 re-check of queued evaluations, one quad of lanes per entry; flips the
 // stored nibble where the FP32 label differs and flags the entry.  Every lane
-// of a quad runs the same loop trips (the entry index is per quad), so the
-// cross-lane reads always find their partners active.
+// of a quad runs the same loop trips (the slot index is per quad), so the
+// cross-lane reads always find their partners active.  In 1D the evaluation
+// kind is uniform over the wave, so the wave forms that one stencil.
 template <int DIM>
 __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2)))
 k_recheck(Line1D ln, Grid2D gd, int dir, const void *__restrict__ prepared,
           const float *__restrict__ q, uint8_t *__restrict__ masks, const u32 *__restrict__ queue,
           const u32 *__restrict__ qcount, int64_t qcap, uint8_t *__restrict__ qflag) {
-  constexpr int EPB = TPB / 4;  // entries per workgroup and pass
-  const int64_t nq = (int64_t)*qcount < qcap ? (int64_t)*qcount : qcap;
+  constexpr int EPB = TPB / 4;  // slots per workgroup and pass
+  static_assert(EPB % EPW == 0, "waves take whole groups of slots");
   const int64_t nf = DIM == 1 ? ln.faces() : (dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1));
-  if (blockIdx.x * (int64_t)EPB >= nq) return;  // block-uniform: nothing queued for this block
+  const QueueSlots qs = queue_slots<DIM>(qcount, qcap, nf);
+  if (blockIdx.x * (int64_t)EPB >= qs.total) return;  // block-uniform: nothing queued for this block
   __shared__ __attribute__((aligned(16))) float S[Q_SIZE];
   {
     const float4 *src = (const float4 *)((const char *)prepared + PREP_Q_OFF);
@@ -691,14 +764,17 @@ k_recheck(Line1D ln, Grid2D gd, int dir, const void *__restrict__ prepared,
   }
   __syncthreads();
   const int r = threadIdx.x & 3;
-  for (int64_t i = blockIdx.x * (int64_t)EPB + (threadIdx.x >> 2); i < nq;
+  for (int64_t i = blockIdx.x * (int64_t)EPB + (threadIdx.x >> 2); i < qs.total;
        i += (int64_t)gridDim.x * EPB) {
-    const u32 ent = queue[i];
+    int64_t pos;
+    int e;
+    if (!queue_slot<DIM>(qs, i, nf, pos, e)) continue;
+    const u32 ent = queue[pos];
     const int64_t f = ent >> 3;
-    const int e = ent & 7;
+    e = ent & 7;
     float se[6];
     if constexpr (DIM == 1) {  // 1D: only the queued evaluation's stencil is formed
-      switch (e) {
+      switch (__builtin_amdgcn_readfirstlane(e)) {
       case 0: stencil_one<0>(ln, q, f, se); break;
       case 1: stencil_one<1>(ln, q, f, se); break;
       case 2: stencil_one<2>(ln, q, f, se); break;
@@ -728,7 +804,7 @@ k_recheck(Line1D ln, Grid2D gd, int dir, const void *__restrict__ prepared,
       const u32 old = (masks[mi] >> ((e & 1) * 4)) & 15u;
       const bool flip = old != sel32;
       if (flip) atomicXor(word, (old ^ sel32) << shift);
-      qflag[i] = flip ? 1 : 0;
+      qflag[pos] = flip ? 1 : 0;
     }
   }
 }
@@ -740,12 +816,14 @@ k_fixup(Line1D ln, Grid2D gd, int dir, const float *__restrict__ q,
         const uint8_t *__restrict__ masks, const u32 *__restrict__ queue,
         const u32 *__restrict__ qcount, int64_t qcap, const uint8_t *__restrict__ qflag,
         float *__restrict__ Fh) {
-  const int64_t nq = (int64_t)*qcount < qcap ? (int64_t)*qcount : qcap;
   constexpr int NV = DIM == 1 ? 3 : 4;
   const int64_t nf = DIM == 1 ? ln.faces() : (dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1));
-  for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < nq; i += (int64_t)gridDim.x * TPB) {
-    if (!qflag[i]) continue;
-    const int64_t f = queue[i] >> 3;
+  const QueueSlots qs = queue_slots<DIM>(qcount, qcap, nf);
+  for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < qs.total; i += (int64_t)gridDim.x * TPB) {
+    int64_t pos;
+    int e;
+    if (!queue_slot<DIM>(qs, i, nf, pos, e) || !qflag[pos]) continue;
+    const int64_t f = queue[pos] >> 3;
     float s[8][6], R[4][4], hs[4], Fo[4];
     if (DIM == 1) {
       float R3[3][3];
@@ -892,8 +970,7 @@ k_fast_burgers(Line1D ln, const void *__restrict__ prepared, float margin, int s
 
 // Clears the two re-check counters (one per sweep direction).
 __global__ void k_zero_u32(u32 *p) {
-  p[0] = 0u;
-  p[1] = 0u;
+  if (threadIdx.x < QCOUNTERS) p[threadIdx.x] = 0u;
 }
 
 __global__ void __launch_bounds__(TPB) k_copy_u8(const uint8_t *__restrict__ a, uint8_t *__restrict__ b, int64_t n) {
@@ -1439,7 +1516,7 @@ hipError_t launch_fast_rhs1d(const Line1D &ln, const FastArgs &fa, const float *
 
 hipError_t launch_fast_reset(const FastArgs &fa, hipStream_t s) {
   if (!(fa.selector == 0 && fa.margin > 0.f) || !fa.scr.qcount) return hipSuccess;
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, fa.scr.qcount);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, fa.scr.qcount);
   return hipGetLastError();
 }
 

@@ -9,6 +9,11 @@
 
 namespace n6 {
 
+// Re-check counters in the workspace: 1D uses one per evaluation kind
+// (field * 2 + sign, six), 2D one per sweep direction; all are cleared
+// together.
+constexpr int QCOUNTERS = 8;
+
 struct Line1D {            // a batch of independent 1D lines
   const int64_t *offsets;  // [dev] cell offsets [np+1]
   const double *dx;        // [dev] spacing per line

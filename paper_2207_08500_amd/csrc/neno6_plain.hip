@@ -399,10 +399,7 @@ __global__ void __launch_bounds__(TPB)
 k_diff1d(Line1D ln, int equation, const T *__restrict__ Fh, const T *__restrict__ q,
          T *__restrict__ rhs, Stage st, int has_stage, int32_t *__restrict__ status_out,
          uint32_t *__restrict__ zero_after) {
-  if (zero_after && blockIdx.x == 0 && threadIdx.x == 0) {
-    zero_after[0] = 0u;
-    zero_after[1] = 0u;
-  }
+  if (zero_after && blockIdx.x == 0 && threadIdx.x < QCOUNTERS) zero_after[threadIdx.x] = 0u;
   // one lane per face g; the face to the left of cell i of line p is i + p,
   // and the last face of every line has no cell to its right
   const int64_t tf = ln.faces();
@@ -508,10 +505,7 @@ __global__ void __launch_bounds__(TPB)
 k_diff2d(Grid2D gd, const T *__restrict__ Fx, const T *__restrict__ Gy, const T *__restrict__ q,
          T *__restrict__ rhs, Stage st, int has_stage, int32_t *__restrict__ status_out,
          uint32_t *__restrict__ zero_after) {
-  if (zero_after && blockIdx.x == 0 && threadIdx.x == 0) {
-    zero_after[0] = 0u;
-    zero_after[1] = 0u;
-  }
+  if (zero_after && blockIdx.x == 0 && threadIdx.x < QCOUNTERS) zero_after[threadIdx.x] = 0u;
   const int64_t cells = gd.nx * gd.ny;
   const int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
   if (i >= cells) return;
