@@ -215,11 +215,14 @@ FastArgs fast_args(const neno6_problem *pb, const neno6_mlp *mlp, const Work &w)
 
 // Per-call setup enqueued before the first kernel of an entry point: the
 // face -> line map of a 1D batch and the re-check counters.
-int32_t begin_call(const neno6_problem *pb, const neno6_mlp *mlp, const Work &w, hipStream_t s) {
+// (reset_counters = false: the call's first kernel clears the counters itself.)
+int32_t begin_call(const neno6_problem *pb, const neno6_mlp *mlp, const Work &w, hipStream_t s,
+                   bool reset_counters = true) {
   if (pb->equation != NENO6_EULER2D && !(pb->flags & NENO6_KEEP_MAP) &&
       launch_build_fmap(line_of(pb), w.fmap, s) != hipSuccess)
     return NENO6_HIP_ERROR;
-  if (pb->precision >= NENO6_BF16 && launch_fast_reset(fast_args(pb, mlp, w), s) != hipSuccess)
+  if (reset_counters && pb->precision >= NENO6_BF16 &&
+      launch_fast_reset(fast_args(pb, mlp, w), s) != hipSuccess)
     return NENO6_HIP_ERROR;
   return NENO6_OK;
 }
@@ -495,7 +498,9 @@ int32_t neno6_step(const neno6_problem *prob, const neno6_mlp *mlp, void *q, dou
   if (!q || !t || !status || !ws || n_steps < 0 || !(cfl > 0)) return NENO6_BAD_ARG;
   const Work w = carve_work(prob, ws);
   if (ws_bytes < w.bytes) return NENO6_WORKSPACE_SMALL;
-  if (int32_t c = begin_call(prob, mlp, w, stream)) return c;
+  // 1D: every step's time-step kernel clears the re-check counters
+  const bool is1d_fast = prob->equation != NENO6_EULER2D && prob->precision >= NENO6_BF16;
+  if (int32_t c = begin_call(prob, mlp, w, stream, !(is1d_fast && n_steps > 0))) return c;
   const bool f64 = prob->precision == NENO6_FP64;
   for (int32_t it = 0; it < n_steps; ++it) {
     hipError_t e;
@@ -508,7 +513,7 @@ int32_t neno6_step(const neno6_problem *prob, const neno6_mlp *mlp, void *q, dou
       e = f64 ? launch_cfl1d<double>(ln, prob->equation, (const double *)q, cfl, w.dt, status, t,
                                      stream)
               : launch_cfl1d<float>(ln, prob->equation, (const float *)q, cfl, w.dt, status, t,
-                                    stream);
+                                    stream, is1d_fast ? w.scr.qcount : nullptr);
     }
     if (e != hipSuccess) return NENO6_HIP_ERROR;
     // u1 = stage 1 of q; u2 = stage 2 of u1; q = stage 3 of u2

@@ -83,7 +83,8 @@ hipError_t launch_diff1d(const Line1D &ln, int equation, const T *Fhat, const T 
 // Per-line time step and status check at the start of a step; t += dt.
 template <typename T>
 hipError_t launch_cfl1d(const Line1D &ln, int equation, const T *q, double cfl, double *dt,
-                        int32_t *status, double *t, hipStream_t s);
+                        int32_t *status, double *t, hipStream_t s,
+                        uint32_t *zero_after = nullptr);
 
 // 2D: x faces [4][ny][nx+1], y faces [4][ny+1][nx].
 // evals: scratch of plain_eval_bytes(8, max(x faces, y faces), sizeof(T)).

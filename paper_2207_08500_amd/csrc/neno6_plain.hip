@@ -439,7 +439,9 @@ constexpr int CFL_TPB = 1024;
 template <typename T>
 __global__ void __launch_bounds__(CFL_TPB)
 k_cfl1d(Line1D ln, int equation, const T *__restrict__ q, double cfl, double *__restrict__ dt,
-        int32_t *__restrict__ status, double *__restrict__ t) {
+        int32_t *__restrict__ status, double *__restrict__ t, uint32_t *__restrict__ zero_after) {
+  // the step's first stage starts with empty re-check queues
+  if (zero_after && blockIdx.x == 0 && threadIdx.x < QCOUNTERS) zero_after[threadIdx.x] = 0u;
   const int p = blockIdx.x;
   const int64_t o = ln.offsets[p], n = ln.offsets[p + 1] - o;
   double smax = 0.0;
@@ -1025,9 +1027,9 @@ hipError_t launch_build_fmap(const Line1D &ln, int32_t *fmap, hipStream_t s) {
 
 template <typename T>
 hipError_t launch_cfl1d(const Line1D &ln, int equation, const T *q, double cfl, double *dt,
-                        int32_t *status, double *t, hipStream_t s) {
+                        int32_t *status, double *t, hipStream_t s, uint32_t *zero_after) {
   hipLaunchKernelGGL(k_cfl1d<T>, dim3(ln.np), dim3(CFL_TPB), 0, s, ln, equation, q, cfl, dt,
-                     status, t);
+                     status, t, zero_after);
   return hipGetLastError();
 }
 
@@ -1120,7 +1122,7 @@ hipError_t launch_params_to_f32(const double *P, float *P32, hipStream_t s) {
   template hipError_t launch_diff1d<T>(const Line1D &, int, const T *, const T *, T *,           \
                                        const Stage *, int32_t *, hipStream_t, uint32_t *);       \
   template hipError_t launch_cfl1d<T>(const Line1D &, int, const T *, double, double *,          \
-                                      int32_t *, double *, hipStream_t);                         \
+                                      int32_t *, double *, hipStream_t, uint32_t *);             \
   template hipError_t launch_faces_euler2d<T>(const Grid2D &, const T *, int, const T *,         \
                                               const uint8_t *, const uint8_t *, T *, T *,        \
                                               uint8_t *, uint8_t *, void *, hipStream_t);        \
