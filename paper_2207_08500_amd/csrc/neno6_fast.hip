@@ -53,8 +53,8 @@ constexpr int TAB_BYTES = TAB_REGS * 64 * 4;
 constexpr int PREP_BF16_OFF = 16384;
 constexpr int PREP_F16_OFF = PREP_BF16_OFF + TAB_BYTES;
 constexpr int PREP_B5_OFF = PREP_F16_OFF + TAB_BYTES;
-constexpr int PREP_Q_OFF = 65536;  // FP32 image for the re-check kernel (see Q_SIZE)
-constexpr size_t PREP_BYTES = 81920;
+constexpr int PREP_F32_OFF = 65536;  // FP32 operand table of the re-check (F32_REGS)
+constexpr size_t PREP_BYTES = 98304;
 static_assert(PREP_B5_OFF + 16 <= (int)PREP_BYTES, "prepared block layout");
 
 // ---- packing -----------------------------------------------------------------
@@ -545,138 +545,136 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
   }
 }
 
-// ---- FP32 re-check, four lanes per queued evaluation -------------------------
-// The classifier in FP32 with its work split over the four lanes r = 0..3 of a
-// quad.  Layer 1 and the layer-2 partial sums are split by layer-1 neuron
-// (i = 4k + r) and summed across the quad; layers 3 and 4 are split by output
-// neuron (o = 4j + r), their outputs shared with quad broadcasts; layer 5 runs
-// in every lane.  LDS image of the FP32 parameters for this split:
-//   W1b [64][8]  (W1 row, b1, pad)              rows 4k + r read together
-//   W2T [64][36] (inputs x outputs, padded)     rows start in different banks
-//   b2  [32]
-//   W3q [32][4][4]  W3[4j + r][i] at (i, r, j)  one 16-byte read per lane and input
-//   b3q [4][4]      b3[4j + r]    at (r, j)
-//   W4q [16][4][2]  W4[4j + r][i] at (i, r, j)
-//   b4q [4][2]      b4[4j + r]    at (r, j)
-//   W5T [8][4], b5 [4]
-constexpr int Q_W1 = 0, Q_W2 = 512, Q_W2S = 36, Q_B2 = Q_W2 + 64 * Q_W2S, Q_W3 = Q_B2 + 32,
-              Q_B3 = Q_W3 + 512, Q_W4 = Q_B3 + 16, Q_B4 = Q_W4 + 128, Q_W5 = Q_B4 + 8,
-              Q_B5 = Q_W5 + 32, Q_SIZE = Q_B5 + 4;
+// ---- FP32 re-check on MFMA ---------------------------------------------------
+// The re-check evaluates the classifier in FP32 with v_mfma_f32_32x32x2_f32
+// (FP32 products and accumulation): the same transposed, weight-stationary
+// tiling as the BF16 path with K = 2 per instruction, so the two K slots of
+// step t are the rows that lane halves h = 0, 1 hold in accumulator register
+// t and the activations never move; ReLU runs on the FP32 accumulators.  32
+// evaluations per wave (lanes j and j + 32 carry evaluation j).  Operand
+// table (k_prepare, register-major, one FP32 value per lane and register):
+//   A1 [8]   L1: tile tt = reg / 4 (neurons 32 tt + i), step t = reg % 4 (slots 2t + h;
+//            slot 6 is the folded bias, slot 7 zero)
+//   A2 [32]  L2: register t of the first (reg < 16) or second L1 tile
+//   A3 [16]  L3 (outputs padded to 32 rows), A4 [8] L4, A5 [4] L5
+//   B2, B3, B4 [16 each]  biases of L2..L4 in the accumulator layout
+// b5 is added to the logits afterwards (rows 0..3: registers 0..3 of lanes 0..31).
+constexpr int F32_A1 = 0, F32_A2 = 8, F32_A3 = 40, F32_A4 = 56, F32_A5 = 64, F32_B2 = 68,
+              F32_B3 = 84, F32_B4 = 100, F32_REGS = 116;
 
-static_assert(Q_SIZE % 4 == 0 && PREP_Q_OFF + 4 * Q_SIZE <= (int)PREP_BYTES &&
-                  PREP_B5_OFF + 16 <= PREP_Q_OFF,
+static_assert(PREP_F32_OFF + F32_REGS * 64 * 4 <= (int)PREP_BYTES &&
+                  PREP_B5_OFF + 16 <= PREP_F32_OFF,
               "prepared block layout");
 
-// Element t of the re-check image (written once by k_prepare).
-N6_DEV float quad_image_value(const double *__restrict__ P, int t) {
-  double v = 0.0;
-  {
-    if (t < Q_W2) {
-      const int o = t >> 3, k = t & 7;
-      v = k < 6 ? P[OW1 + o * 6 + k] : (k == 6 ? P[OB1 + o] : 0.0);
-    } else if (t < Q_B2) {
-      const int i = (t - Q_W2) / Q_W2S, o = (t - Q_W2) % Q_W2S;
-      v = o < 32 ? P[OW2 + o * 64 + i] : 0.0;
-    } else if (t < Q_W3) {
-      v = P[OB2 + t - Q_B2];
-    } else if (t < Q_B3) {
-      const int i = (t - Q_W3) >> 4, r = ((t - Q_W3) >> 2) & 3, j = (t - Q_W3) & 3;
-      v = P[OW3 + (4 * j + r) * 32 + i];
-    } else if (t < Q_W4) {
-      const int r = (t - Q_B3) >> 2, j = (t - Q_B3) & 3;
-      v = P[OB3 + 4 * j + r];
-    } else if (t < Q_B4) {
-      const int i = (t - Q_W4) >> 3, r = ((t - Q_W4) >> 1) & 3, j = (t - Q_W4) & 1;
-      v = P[OW4 + (4 * j + r) * 16 + i];
-    } else if (t < Q_W5) {
-      const int r = (t - Q_B4) >> 1, j = (t - Q_B4) & 1;
-      v = P[OB4 + 4 * j + r];
-    } else if (t < Q_B5) {
-      const int i = (t - Q_W5) >> 2, o = (t - Q_W5) & 3;
-      v = P[OW5 + o * 8 + i];
-    } else {
-      v = P[OB5 + t - Q_B5];
-    }
+// Register `reg` of lane `lane` of the FP32 operand table.
+N6_DEV float f32_table_value(const double *__restrict__ P, int reg, int lane) {
+  const int i = lane % 32, h = lane / 32;
+  double x = 0.0;
+  if (reg < F32_A2) {  // L1
+    const int tt = reg / 4, k = 2 * (reg % 4) + h, o = 32 * tt + i;
+    x = k < 6 ? P[OW1 + o * 6 + k] : (k == 6 ? P[OB1 + o] : 0.0);
+  } else if (reg < F32_A3) {  // L2: inputs = L1 rows of accumulator register t
+    const int u = reg - F32_A2, tt = u / 16, t = u % 16;
+    x = P[OW2 + i * 64 + 32 * tt + 8 * (t / 4) + 4 * h + t % 4];
+  } else if (reg < F32_A4) {  // L3
+    const int t = reg - F32_A3;
+    x = i < 16 ? P[OW3 + i * 32 + 8 * (t / 4) + 4 * h + t % 4] : 0.0;
+  } else if (reg < F32_A5) {  // L4: the 16 L3 rows sit in registers 0..7
+    const int t = reg - F32_A4;
+    x = i < 8 ? P[OW4 + i * 16 + 8 * (t / 4) + 4 * h + t % 4] : 0.0;
+  } else if (reg < F32_B2) {  // L5: the 8 L4 rows sit in registers 0..3
+    const int t = reg - F32_A5;
+    x = i < 4 ? P[OW5 + i * 8 + 4 * h + t] : 0.0;
+  } else {  // C register r of lane (j, h) is row 8(r/4) + 4h + r%4
+    const int blk = (reg - F32_B2) / 16, r = (reg - F32_B2) % 16;
+    const int row = 8 * (r / 4) + 4 * h + r % 4;
+    if (blk == 0) x = P[OB2 + row];
+    else if (blk == 1) x = row < 16 ? P[OB3 + row] : 0.0;
+    else x = row < 8 ? P[OB4 + row] : 0.0;
   }
-  return (float)v;
+  return (float)x;
 }
 
-// quad_perm DPP controls: lane l ^ 1, lane l ^ 2, and lane 4(l / 4) + k
-constexpr int DPP_QXOR1 = 0xB1, DPP_QXOR2 = 0x4E;
+struct F32Wts {
+  float a[F32_B2];
+  f32x16 b2, b3, b4;
+  float b5[4];
+};
 
-template <int CTRL>
-N6_DEV float quad_read(float x) {
-  return __builtin_bit_cast(
-      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+N6_DEV void load_f32_wts(const void *prepared, int lane, F32Wts &w) {
+  const float *t = (const float *)((const char *)prepared + PREP_F32_OFF);
+#pragma unroll
+  for (int r = 0; r < F32_B2; ++r) w.a[r] = t[r * 64 + lane];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    w.b2[r] = t[(F32_B2 + r) * 64 + lane];
+    w.b3[r] = t[(F32_B3 + r) * 64 + lane];
+    w.b4[r] = t[(F32_B4 + r) * 64 + lane];
+  }
+  const float *b5 = (const float *)((const char *)prepared + PREP_B5_OFF);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w.b5[k] = b5[k];
 }
 
-// Sum over the four lanes of a quad, (p0 + p1) + (p2 + p3) up to the order of
-// commutative additions, so every lane of the quad holds the same bits.
-N6_DEV float quad_sum(float x) {
-  x = x + quad_read<DPP_QXOR1>(x);
-  return x + quad_read<DPP_QXOR2>(x);
+N6_DEV f32x16 mma32(float a, float b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
-N6_DEV float relu(float a) { return a > 0.f ? a : 0.f; }
+N6_DEV f32x16 relu16(f32x16 c) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) c[r] = fmaxf(c[r], 0.f);
+  return c;
+}
 
-N6_DEV void mlp_quad(const float *S, const float x[6], int r, float z[4]) {
-  // layer 1 (neurons 4k + r) and partial layer-2 sums over them
-  float acc2[32];
+// FP32 logits of the 32 evaluations of a wave: lane (j, h) holds the
+// features x of evaluation j; lanes 0..31 return its four logits.
+N6_DEV void mlp_f32_wave(const F32Wts &w, const float x[6], int h, float z[4]) {
+  const f32x16 zero = {};
+  f32x16 c1a = zero, c1b = zero;
 #pragma unroll
-  for (int o = 0; o < 32; ++o) acc2[o] = 0.f;
-#pragma unroll 1
-  for (int k = 0; k < 16; ++k) {
-    const float *w1 = S + Q_W1 + (4 * k + r) * 8;
-    float a = w1[6];
+  for (int t = 0; t < 4; ++t) {
+    const int k = 2 * t + h;  // lane-half dependent slot: features, bias 1, zero
+    float b = 0.f;
 #pragma unroll
-    for (int j = 0; j < 6; ++j) a = fmaf(w1[j], x[j], a);
-    a = relu(a);
-    const float *w2 = S + Q_W2 + (4 * k + r) * Q_W2S;
+    for (int kk = 0; kk < 6; ++kk) b = k == kk ? x[kk] : b;
+    b = k == 6 ? 1.f : b;
+    c1a = mma32(w.a[F32_A1 + t], b, c1a);
+    c1b = mma32(w.a[F32_A1 + 4 + t], b, c1b);
+  }
+  c1a = relu16(c1a);
+  c1b = relu16(c1b);
+  // L2 in two accumulators (even / odd steps) to halve the dependent chain
+  f32x16 c2 = w.b2, c2o = zero;
 #pragma unroll
-    for (int o = 0; o < 32; ++o) acc2[o] = fmaf(w2[o], a, acc2[o]);
+  for (int t = 0; t < 16; t += 2) {
+    c2 = mma32(w.a[F32_A2 + t], c1a[t], c2);
+    c2o = mma32(w.a[F32_A2 + t + 1], c1a[t + 1], c2o);
   }
 #pragma unroll
-  for (int o = 0; o < 32; ++o) acc2[o] = relu(quad_sum(acc2[o]) + S[Q_B2 + o]);
-  // layer 3: outputs 4j + r over all 32 inputs
-  float a3[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) a3[j] = S[Q_B3 + 4 * r + j];
-#pragma unroll 4
-  for (int i = 0; i < 32; ++i) {
-    const float *w3 = S + Q_W3 + i * 16 + 4 * r;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) a3[j] = fmaf(w3[j], acc2[i], a3[j]);
+  for (int t = 0; t < 16; t += 2) {
+    c2 = mma32(w.a[F32_A2 + 16 + t], c1b[t], c2);
+    c2o = mma32(w.a[F32_A2 + 16 + t + 1], c1b[t + 1], c2o);
   }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) a3[j] = relu(a3[j]);
-  // layer 4: outputs 4j + r over the 16 layer-3 outputs (input 4j' + r' from lane r')
-  float a4[2];
+  for (int r = 0; r < 16; ++r) c2[r] = fmaxf(c2[r] + c2o[r], 0.f);
+  f32x16 c3 = w.b3, c3o = zero;
 #pragma unroll
-  for (int j = 0; j < 2; ++j) a4[j] = S[Q_B4 + 2 * r + j];
-#pragma unroll
-  for (int jp = 0; jp < 4; ++jp) {
-    const float in[4] = {quad_read<0x00>(a3[jp]), quad_read<0x55>(a3[jp]),
-                         quad_read<0xAA>(a3[jp]), quad_read<0xFF>(a3[jp])};
-#pragma unroll
-    for (int rp = 0; rp < 4; ++rp) {
-      const float *w4 = S + Q_W4 + (4 * jp + rp) * 8 + 2 * r;
-#pragma unroll
-      for (int j = 0; j < 2; ++j) a4[j] = fmaf(w4[j], in[rp], a4[j]);
-    }
+  for (int t = 0; t < 16; t += 2) {
+    c3 = mma32(w.a[F32_A3 + t], c2[t], c3);
+    c3o = mma32(w.a[F32_A3 + t + 1], c2[t + 1], c3o);
   }
-  // layer 5 in every lane over the 8 layer-4 outputs
 #pragma unroll
-  for (int o = 0; o < 4; ++o) z[o] = S[Q_B5 + o];
+  for (int r = 0; r < 8; ++r) c3[r] = fmaxf(c3[r] + c3o[r], 0.f);
+  f32x16 c4 = w.b4;
 #pragma unroll
-  for (int jp = 0; jp < 2; ++jp) {
-    const float v = relu(a4[jp]);
-    const float in[4] = {quad_read<0x00>(v), quad_read<0x55>(v), quad_read<0xAA>(v),
-                         quad_read<0xFF>(v)};
+  for (int t = 0; t < 8; ++t) c4 = mma32(w.a[F32_A4 + t], c3[t], c4);
 #pragma unroll
-    for (int rp = 0; rp < 4; ++rp)
+  for (int r = 0; r < 4; ++r) c4[r] = fmaxf(c4[r], 0.f);
+  f32x16 c5 = zero;
 #pragma unroll
-      for (int o = 0; o < 4; ++o) z[o] = fmaf(S[Q_W5 + (4 * jp + rp) * 4 + o], in[rp], z[o]);
-  }
+  for (int t = 0; t < 4; ++t) c5 = mma32(w.a[F32_A5 + t], c4[t], c5);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) z[k] = c5[k] + w.b5[k];
 }
 
 // Split stencil E (field E / 2, sign E % 2) of 1D face f: the full set-up
@@ -694,7 +692,7 @@ N6_DEV void stencil_one(const Line1D &ln, const float *__restrict__ q, int64_t f
 // one wave always share the evaluation kind (and the stencil set-up the wave
 // runs); slot i maps to list e, position j, valid while j < count of e.
 // 2D: one list, slot i is entry i.
-constexpr int EPW = 16;  // re-check entries per wave (one per quad)
+constexpr int EPW = 32;  // re-check entries per wave
 
 struct QueueSlots {
   int64_t base[6], count[6], total;
@@ -742,39 +740,39 @@ N6_DEV bool queue_slot(const QueueSlots &qs, int64_t i, int64_t nf, int64_t &pos
   }
 }
 
-// FP32 re-check of queued evaluations, one quad of lanes per entry; flips the
-// stored nibble where the FP32 label differs and flags the entry.  Every lane
-// of a quad runs the same loop trips (the slot index is per quad), so the
-// cross-lane reads always find their partners active.  In 1D the evaluation
-// kind is uniform over the wave, so the wave forms that one stencil.
+// FP32 re-check of queued evaluations, 32 per wave on FP32 MFMA; flips the
+// stored nibble where the FP32 label differs and flags the entry.  The loop
+// is uniform over the wave (the MFMA products need every lane); slots past
+// the end or in a list's padding compute face 0 and store nothing.  In 1D
+// the evaluation kind is uniform over the wave, so the wave forms that one
+// stencil.
 template <int DIM>
 __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2)))
 k_recheck(Line1D ln, Grid2D gd, int dir, const void *__restrict__ prepared,
           const float *__restrict__ q, uint8_t *__restrict__ masks, const u32 *__restrict__ queue,
           const u32 *__restrict__ qcount, int64_t qcap, uint8_t *__restrict__ qflag) {
-  constexpr int EPB = TPB / 4;  // slots per workgroup and pass
-  static_assert(EPB % EPW == 0, "waves take whole groups of slots");
+  constexpr int EPB = WPB * EPW;  // slots per workgroup and pass
   const int64_t nf = DIM == 1 ? ln.faces() : (dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1));
   const QueueSlots qs = queue_slots<DIM>(qcount, qcap, nf);
   if (blockIdx.x * (int64_t)EPB >= qs.total) return;  // block-uniform: nothing queued for this block
-  __shared__ __attribute__((aligned(16))) float S[Q_SIZE];
-  {
-    const float4 *src = (const float4 *)((const char *)prepared + PREP_Q_OFF);
-    for (int t = threadIdx.x; t < Q_SIZE / 4; t += TPB) ((float4 *)S)[t] = src[t];
-  }
-  __syncthreads();
-  const int r = threadIdx.x & 3;
-  for (int64_t i = blockIdx.x * (int64_t)EPB + (threadIdx.x >> 2); i < qs.total;
-       i += (int64_t)gridDim.x * EPB) {
-    int64_t pos;
-    int e;
-    if (!queue_slot<DIM>(qs, i, nf, pos, e)) continue;
-    const u32 ent = queue[pos];
+  const int lane = threadIdx.x & 63, j = lane & 31, h = lane >> 5;
+  F32Wts w;
+  load_f32_wts(prepared, lane, w);
+  for (int64_t i0 = blockIdx.x * (int64_t)EPB + (threadIdx.x >> 6) * EPW; i0 < qs.total;
+       i0 += (int64_t)gridDim.x * EPB) {
+    const int64_t i = i0 + j;
+    int64_t pos = 0;
+    int e = 0;
+    const bool ok = i < qs.total && queue_slot<DIM>(qs, i, nf, pos, e);
+    const u32 ent = ok ? queue[pos] : 0u;
     const int64_t f = ent >> 3;
-    e = ent & 7;
+    if (ok) e = ent & 7;
     float se[6];
     if constexpr (DIM == 1) {  // 1D: only the queued evaluation's stencil is formed
-      switch (__builtin_amdgcn_readfirstlane(e)) {
+      int ew;
+      int64_t iw;
+      queue_slot<DIM>(qs, i0, nf, iw, ew);  // the wave's kind (slot i0 < total)
+      switch (__builtin_amdgcn_readfirstlane(ew)) {
       case 0: stencil_one<0>(ln, q, f, se); break;
       case 1: stencil_one<1>(ln, q, f, se); break;
       case 2: stencil_one<2>(ln, q, f, se); break;
@@ -786,18 +784,18 @@ k_recheck(Line1D ln, Grid2D gd, int dir, const void *__restrict__ prepared,
       float s[8][6], R[4][4];
       setup2d(gd, dir, q, f, s, R);
 #pragma unroll
-      for (int j = 0; j < 6; ++j) {
-        float v = s[0][j];
+      for (int jj = 0; jj < 6; ++jj) {
+        float v = s[0][jj];
 #pragma unroll
-        for (int k = 1; k < 8; ++k) v = e == k ? s[k][j] : v;
-        se[j] = v;
+        for (int k = 1; k < 8; ++k) v = e == k ? s[k][jj] : v;
+        se[jj] = v;
       }
     }
     float x[6], z[4];
     features<float>(se, x);
-    mlp_quad(S, x, r, z);
-    const u32 sel32 = mask_from_logits<float>(z);
-    if (r == 0) {
+    mlp_f32_wave(w, x, h, z);
+    if (h == 0 && ok) {
+      const u32 sel32 = mask_from_logits<float>(z);
       const int64_t mi = (int64_t)(e >> 1) * nf + f;
       const u32 shift = (u32)((mi & 3) * 8 + (e & 1) * 4);
       u32 *word = (u32 *)(masks + (mi & ~(int64_t)3));
@@ -985,11 +983,14 @@ hipError_t copy_bytes(const uint8_t *a, uint8_t *b, int64_t n, hipStream_t s) {
 
 // Prepared block: FP32 copy of the parameters, the BF16 and FP16 per-lane
 // operand tables, and b5 in FP32.
+constexpr int PREP_THREADS = (TAB_REGS > F32_REGS ? TAB_REGS : F32_REGS) * 64;
+static_assert(NPARAM <= PREP_THREADS, "k_prepare covers every element");
+
 __global__ void __launch_bounds__(TPB) k_prepare(const double *__restrict__ P, char *__restrict__ prep) {
   const int t = blockIdx.x * TPB + threadIdx.x;
   if (t < NPARAM) ((float *)prep)[t] = (float)P[t];
   if (t < 4) ((float *)(prep + PREP_B5_OFF))[t] = (float)P[OB5 + t];
-  if (t < Q_SIZE) ((float *)(prep + PREP_Q_OFF))[t] = quad_image_value(P, t);
+  if (t < F32_REGS * 64) ((float *)(prep + PREP_F32_OFF))[t] = f32_table_value(P, t / 64, t % 64);
   if (t >= TAB_REGS * 64) return;
   const int reg = t / 64, lane = t % 64, i = lane % 32, h = lane / 32;
   float v[2];
@@ -1378,7 +1379,7 @@ hipError_t launch_grad_mfma(const double *P, void *tabs, const float *s, const u
                             hipStream_t st) {
   char *prep = (char *)tabs;
   u32 *btab = (u32 *)(prep + PREP_BYTES);
-  hipLaunchKernelGGL(k_prepare, dim3((TAB_REGS * 64 + TPB - 1) / TPB), dim3(TPB), 0, st, P, prep);
+  hipLaunchKernelGGL(k_prepare, dim3((PREP_THREADS + TPB - 1) / TPB), dim3(TPB), 0, st, P, prep);
   hipLaunchKernelGGL(k_prepare_bwd, dim3((BT_REGS * 64 + TPB - 1) / TPB), dim3(TPB), 0, st, P, btab);
   const int nw = train_mfma_waves(m);
   hipLaunchKernelGGL(k_grad_mfma, dim3(nw / WPB), dim3(TPB), 0, st, prep, btab, s, y, idx, m,
@@ -1390,7 +1391,7 @@ size_t fast_prepared_bytes() { return PREP_BYTES; }
 const void *fast_prepared_f32(const void *prepared) { return prepared; }
 
 hipError_t launch_fast_prepare(const double *P, void *prepared, hipStream_t s) {
-  hipLaunchKernelGGL(k_prepare, dim3((TAB_REGS * 64 + TPB - 1) / TPB), dim3(TPB), 0, s, P,
+  hipLaunchKernelGGL(k_prepare, dim3((PREP_THREADS + TPB - 1) / TPB), dim3(TPB), 0, s, P,
                      (char *)prepared);
   return hipGetLastError();
 }
