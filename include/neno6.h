@@ -253,16 +253,19 @@ int32_t neno6_step(const neno6_problem *prob, const neno6_mlp *mlp, void *q, dou
 int32_t neno6_rhs_adjoint(const neno6_problem *prob, const uint8_t *masks, const void *rbar,
                           void *ubar, hipStream_t stream);
 
-/* Vector-Jacobian product of the BURGERS or EULER1D right-hand side at state
- * q with the labels held fixed: qbar = (d rhs / d q)^T rbar, differentiating
- * the physical flux, the Roe average and eigenvectors, the Rusanov speed (the
- * max over the six stencil cells, into the cell that attains it) and the
- * split; the labels masks [dev] (as returned by neno6_rhs) select the fixed
- * combination weights (eq. TENOweight_renormalize).  q, rbar, qbar [dev] in
- * the state layout, FP64 or FP32 (the problem's precision must be FP64 or
- * FP32).  ws [dev] of neno6_vjp_workspace_size(prob) bytes.  The map is not
- * differentiable where two cells tie for the Rusanov speed; there the first
- * cell in stencil order takes the derivative. */
+/* Vector-Jacobian product of the BURGERS, EULER1D or EULER2D right-hand side
+ * at state q with the labels held fixed: qbar = (d rhs / d q)^T rbar,
+ * differentiating the physical flux, the Roe average and eigenvectors (2D: in
+ * each sweep's normal/shear frame), the Rusanov speed (the max over the six
+ * stencil cells, into the cell that attains it) and the split; the labels
+ * masks [dev] (as returned by neno6_rhs; 2D: the x-face masks followed by the
+ * y-face masks) select the fixed combination weights (eq.
+ * TENOweight_renormalize).  q, rbar, qbar [dev] in the state layout, FP64 or
+ * FP32 (the problem's precision must be FP64 or FP32).  ws [dev] of
+ * neno6_vjp_workspace_size(prob) bytes.  Deterministic: each cell sums its
+ * face contributions in a fixed order.  The map is not differentiable where
+ * two cells tie for the Rusanov speed; there the first cell in stencil order
+ * takes the derivative.  NENO6_UNSUPPORTED for ADVECTION (neno6_rhs_adjoint). */
 size_t neno6_vjp_workspace_size(const neno6_problem *prob);
 int32_t neno6_rhs_vjp(const neno6_problem *prob, const void *q, const uint8_t *masks,
                       const void *rbar, void *qbar, void *ws, size_t ws_bytes,

@@ -61,9 +61,9 @@ class AdvectionRHS(torch.autograd.Function):
 class RHSFixedLabels(torch.autograd.Function):
     @staticmethod
     def forward(ctx, q: torch.Tensor, masks: torch.Tensor, prob: "native.Problem"):
-        if prob.equation not in (native.BURGERS, native.EULER1D) or \
+        if prob.equation not in (native.BURGERS, native.EULER1D, native.EULER2D) or \
                 prob.selector != native.SEL_MASKS_IN:
-            raise ValueError("RHSFixedLabels needs a Burgers or 1D Euler problem with SEL_MASKS_IN")
+            raise ValueError("RHSFixedLabels needs a Burgers or Euler problem with SEL_MASKS_IN")
         qd = q.detach().contiguous()
         rhs = torch.empty_like(qd)
         native.neno6_rhs(prob, None, qd, rhs, prob.workspace(q.device), masks_in=masks)

@@ -547,6 +547,10 @@ int32_t neno6_rhs_adjoint(const neno6_problem *prob, const uint8_t *masks, const
 
 size_t neno6_vjp_workspace_size(const neno6_problem *prob) {
   if (check_problem(prob) != NENO6_OK) return 0;
+  if (prob->equation == NENO6_EULER2D) {
+    const size_t nfx = (size_t)(prob->nx + 1) * prob->ny, nfy = (size_t)prob->nx * (prob->ny + 1);
+    return align_up(24 * (nfx + nfy) * elem_size(prob->precision));
+  }
   if (prob->equation != NENO6_BURGERS && prob->equation != NENO6_EULER1D) return 0;
   const size_t faces = (size_t)prob->total_cells + prob->n_problems;
   return align_up(faces * sizeof(int32_t)) +
@@ -557,11 +561,20 @@ int32_t neno6_rhs_vjp(const neno6_problem *prob, const void *q, const uint8_t *m
                       const void *rbar, void *qbar, void *ws, size_t ws_bytes,
                       hipStream_t stream) {
   if (int32_t c = check_problem(prob)) return c;
-  if (prob->equation != NENO6_BURGERS && prob->equation != NENO6_EULER1D) return NENO6_UNSUPPORTED;
+  if (prob->equation == NENO6_ADVECTION) return NENO6_UNSUPPORTED;
   if (prob->precision != NENO6_FP64 && prob->precision != NENO6_FP32) return NENO6_BAD_LAYOUT;
   if (!q || !masks || !rbar || !qbar || !ws) return NENO6_BAD_ARG;
   const size_t need = neno6_vjp_workspace_size(prob);
   if (ws_bytes < need) return NENO6_WORKSPACE_SMALL;
+  if (prob->equation == NENO6_EULER2D) {
+    const Grid2D g = grid_of(prob);
+    hipError_t e = prob->precision == NENO6_FP64
+                       ? launch_vjp2d<double>(g, (const double *)q, masks, (const double *)rbar,
+                                              (double *)qbar, (double *)ws, stream)
+                       : launch_vjp2d<float>(g, (const float *)q, masks, (const float *)rbar,
+                                             (float *)qbar, (float *)ws, stream);
+    return hip_status(e);
+  }
   const size_t faces = (size_t)prob->total_cells + prob->n_problems;
   int32_t *fmap = (int32_t *)ws;
   void *scratch = (char *)ws + align_up(faces * sizeof(int32_t));

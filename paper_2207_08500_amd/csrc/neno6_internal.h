@@ -108,6 +108,11 @@ hipError_t launch_cfl2d(const Grid2D &g, const T *q, double cfl, double *part, d
 template <typename T>
 hipError_t launch_vjp1d(const Line1D &ln, int equation, const T *q, const uint8_t *masks,
                         const T *rbar, T *qbar, T *scratch, hipStream_t s);
+// 2D Euler: both sweeps; scratch of 24 x (x faces + y faces) values; masks
+// are the x masks [4][x faces] followed by the y masks [4][y faces].
+template <typename T>
+hipError_t launch_vjp2d(const Grid2D &g, const T *q, const uint8_t *masks, const T *rbar, T *qbar,
+                        T *scratch, hipStream_t s);
 // Fixed-mask adjoint of the advection rhs (one line).
 hipError_t launch_adjoint_advection(const Line1D &ln, const uint8_t *masks, const void *rbar,
                                     void *ubar, int is_fp64, hipStream_t s);

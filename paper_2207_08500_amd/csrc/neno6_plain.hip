@@ -854,6 +854,287 @@ N6_DEV void face_vjp_burgers(const T us[6], uint8_t msk, T Fb, T qb[6][3]) {
 }
 
 // Per face: contributions cb[(j * nv + r) * tf + g] to the six stencil cells.
+// Reverse of one 2D Euler face flux in sweep direction dir (the forward is
+// stencil2d for every field and sign, then the back-projection with R):
+// fixed combination weights from the labels; Roe average of cells 2, 3 and
+// its eigenvectors in the (rho, m_n, m_s, E) frame; Rusanov speeds
+// alpha_m = max_j |lambda_m| (lambda = u_n - c, u_n, u_n, u_n + c) into the
+// cell that attains the max.  Fb: cotangent of the face flux; qb[6][4] is
+// accumulated.
+template <typename T>
+N6_DEV void face_vjp_euler2d(const T qs[6][4], T gamma, int dir, const uint8_t msk[4],
+                             const T Fb[4], T qb[6][4]) {
+  const T g1 = gamma - T(1);
+  const int vn = dir == 0 ? 1 : 2, vs = dir == 0 ? 2 : 1;
+  T u[6], w[6], p[6], c[6], F[6][4];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    prim2d<T>(qs[j], gamma, u[j], w[j], p[j], c[j]);
+    flux2d<T>(qs[j], u[j], w[j], p[j], dir, F[j]);
+  }
+  // Roe average of cells 2, 3 (as in roe2d)
+  const T sL = sqrt_<T>(qs[2][0]), sR = sqrt_<T>(qs[3][0]);
+  const T HL = (qs[2][3] + p[2]) / qs[2][0], HR = (qs[3][3] + p[3]) / qs[3][0];
+  const T den = sL + sR;
+  const T ut = (sL * u[2] + sR * u[3]) / den;
+  const T vt = (sL * w[2] + sR * w[3]) / den;
+  const T Ht = (sL * HL + sR * HR) / den;
+  const T q2 = T(0.5) * (ut * ut + vt * vt);
+  const T c2 = g1 * (Ht - q2);
+  const T ct = sqrt_<T>(c2);
+  const T b1 = g1 / c2, b2 = b1 * q2, ic = T(1) / ct;
+  const T un = dir == 0 ? ut : vt, us = dir == 0 ? vt : ut, nc = un / ct;
+  T L[4][4], R[4][4];
+  roe2d<T>(qs[2], qs[3], gamma, dir, L, R);
+  // forward values needed by the reverse sweep
+  T v[6][4], alpha[4], hs[4];
+  int am[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    alpha[m] = T(0);
+    am[m] = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const T unj = dir == 0 ? u[j] : w[j];
+      const T lam = m == 0 ? unj - c[j] : (m == 3 ? unj + c[j] : unj);
+      const T a = abs_<T>(lam);
+      if (a > alpha[m]) {
+        alpha[m] = a;
+        am[m] = j;
+      }
+    }
+  }
+  T Wp[4][6], Wm[4][6];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    face_coeffs<T>(msk[m] & 15u, Wp[m]);
+    face_coeffs<T>((msk[m] >> 4) & 15u, Wm[m]);
+    T h = T(0);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      T av = T(0), ag = T(0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        av = av + L[m][r] * qs[j][r];
+        ag = ag + L[m][r] * F[j][r];
+      }
+      v[j][m] = av;
+      h = h + Wp[m][j] * (T(0.5) * (ag + alpha[m] * av)) + Wm[m][5 - j] * (T(0.5) * (ag - alpha[m] * av));
+    }
+    hs[m] = h;
+  }
+  // ---- reverse ----
+  T hsb[4], Lb[4][4] = {}, Rb[4][4], ub[6] = {}, wb[6] = {}, pb[6] = {}, cb[6] = {};
+  T Fcb[6][4] = {};
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    hsb[m] = T(0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) hsb[m] = hsb[m] + R[r][m] * Fb[r];
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) Rb[r][m] = Fb[r] * hs[m];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    T ab = T(0);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const T spb = Wp[m][j] * hsb[m], smb = Wm[m][5 - j] * hsb[m];
+      const T gb = T(0.5) * (spb + smb);
+      const T vb = T(0.5) * alpha[m] * (spb - smb);
+      ab = ab + T(0.5) * v[j][m] * (spb - smb);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        Lb[m][r] = Lb[m][r] + vb * qs[j][r] + gb * F[j][r];
+        qb[j][r] = qb[j][r] + L[m][r] * vb;
+        Fcb[j][r] = Fcb[j][r] + L[m][r] * gb;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      if (j == am[m]) {
+        const T unj = dir == 0 ? u[j] : w[j];
+        const T lam = m == 0 ? unj - c[j] : (m == 3 ? unj + c[j] : unj);
+        const T sb = lam < T(0) ? -ab : ab;
+        if (dir == 0) ub[j] = ub[j] + sb;
+        else wb[j] = wb[j] + sb;
+        if (m == 0) cb[j] = cb[j] - sb;
+        if (m == 3) cb[j] = cb[j] + sb;
+      }
+  }
+  // to the (rho, m_n, m_s, E) frame
+  T Lnb[4][4], Rnb[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    Lnb[m][0] = Lb[m][0];
+    Lnb[m][1] = Lb[m][vn];
+    Lnb[m][2] = Lb[m][vs];
+    Lnb[m][3] = Lb[m][3];
+    Rnb[0][m] = Rb[0][m];
+    Rnb[1][m] = Rb[vn][m];
+    Rnb[2][m] = Rb[vs][m];
+    Rnb[3][m] = Rb[3][m];
+  }
+  const T b2b = T(0.5) * Lnb[0][0] - Lnb[1][0] + T(0.5) * Lnb[3][0];
+  const T ncb = T(0.5) * Lnb[0][0] - T(0.5) * Lnb[3][0];
+  T b1b = T(-0.5) * un * Lnb[0][1] - T(0.5) * us * Lnb[0][2] + T(0.5) * Lnb[0][3] +
+          un * Lnb[1][1] + us * Lnb[1][2] - Lnb[1][3] - T(0.5) * un * Lnb[3][1] -
+          T(0.5) * us * Lnb[3][2] + T(0.5) * Lnb[3][3];
+  T unb = T(-0.5) * b1 * Lnb[0][1] + b1 * Lnb[1][1] - T(0.5) * b1 * Lnb[3][1];
+  T usb = T(-0.5) * b1 * Lnb[0][2] + b1 * Lnb[1][2] - Lnb[2][0] - T(0.5) * b1 * Lnb[3][2];
+  const T icb = T(-0.5) * Lnb[0][1] + T(0.5) * Lnb[3][1];
+  unb = unb + Rnb[1][0] + Rnb[1][1] + Rnb[1][3] - ct * Rnb[3][0] + ct * Rnb[3][3];
+  T ctb = -Rnb[1][0] + Rnb[1][3] - un * Rnb[3][0] + un * Rnb[3][3];
+  usb = usb + Rnb[2][0] + Rnb[2][1] + Rnb[2][3] + Rnb[3][2];
+  T Htb = Rnb[3][0] + Rnb[3][3];
+  T q2b = Rnb[3][1];
+  b1b = b1b + q2 * b2b;
+  q2b = q2b + b1 * b2b;
+  unb = unb + ncb / ct;
+  ctb = ctb - ncb * un / (ct * ct) - icb / (ct * ct);
+  const T c2b = -b1b * g1 / (c2 * c2) + ctb / (T(2) * ct);
+  Htb = Htb + g1 * c2b;
+  q2b = q2b - g1 * c2b;
+  T utb = ut * q2b, vtb = vt * q2b;
+  if (dir == 0) {
+    utb = utb + unb;
+    vtb = vtb + usb;
+  } else {
+    vtb = vtb + unb;
+    utb = utb + usb;
+  }
+  const T sLb = (u[2] - ut) / den * utb + (w[2] - vt) / den * vtb + (HL - Ht) / den * Htb;
+  const T sRb = (u[3] - ut) / den * utb + (w[3] - vt) / den * vtb + (HR - Ht) / den * Htb;
+  ub[2] = ub[2] + sL / den * utb;
+  ub[3] = ub[3] + sR / den * utb;
+  wb[2] = wb[2] + sL / den * vtb;
+  wb[3] = wb[3] + sR / den * vtb;
+  const T HLb = sL / den * Htb, HRb = sR / den * Htb;
+  qb[2][3] = qb[2][3] + HLb / qs[2][0];
+  pb[2] = pb[2] + HLb / qs[2][0];
+  qb[2][0] = qb[2][0] - HLb * HL / qs[2][0] + sLb / (T(2) * sL);
+  qb[3][3] = qb[3][3] + HRb / qs[3][0];
+  pb[3] = pb[3] + HRb / qs[3][0];
+  qb[3][0] = qb[3][0] - HRb * HR / qs[3][0] + sRb / (T(2) * sR);
+  // cell fluxes and primitives
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const T rho = qs[j][0], mu = qs[j][1], mv = qs[j][2], E = qs[j][3];
+    if (dir == 0) {  // F = (m_u, m_u u + p, m_v u, (E + p) u)
+      qb[j][1] = qb[j][1] + Fcb[j][0] + u[j] * Fcb[j][1];
+      qb[j][2] = qb[j][2] + u[j] * Fcb[j][2];
+      qb[j][3] = qb[j][3] + u[j] * Fcb[j][3];
+      ub[j] = ub[j] + mu * Fcb[j][1] + mv * Fcb[j][2] + (E + p[j]) * Fcb[j][3];
+      pb[j] = pb[j] + Fcb[j][1] + u[j] * Fcb[j][3];
+    } else {  // G = (m_v, m_u v, m_v v + p, (E + p) v)
+      qb[j][2] = qb[j][2] + Fcb[j][0] + w[j] * Fcb[j][2];
+      qb[j][1] = qb[j][1] + w[j] * Fcb[j][1];
+      qb[j][3] = qb[j][3] + w[j] * Fcb[j][3];
+      wb[j] = wb[j] + mu * Fcb[j][1] + mv * Fcb[j][2] + (E + p[j]) * Fcb[j][3];
+      pb[j] = pb[j] + Fcb[j][2] + w[j] * Fcb[j][3];
+    }
+    // c = sqrt(gamma p / rho)
+    const T zb = cb[j] / (T(2) * c[j]);
+    pb[j] = pb[j] + gamma / rho * zb;
+    qb[j][0] = qb[j][0] - gamma * p[j] / (rho * rho) * zb;
+    // p = g1 (E - (m_u u + m_v v) / 2)
+    qb[j][3] = qb[j][3] + g1 * pb[j];
+    const T keb = -g1 * pb[j];
+    qb[j][1] = qb[j][1] + T(0.5) * u[j] * keb;
+    ub[j] = ub[j] + T(0.5) * mu * keb;
+    qb[j][2] = qb[j][2] + T(0.5) * w[j] * keb;
+    wb[j] = wb[j] + T(0.5) * mv * keb;
+    // u = m_u / rho, v = m_v / rho
+    qb[j][1] = qb[j][1] + ub[j] / rho;
+    qb[j][2] = qb[j][2] + wb[j] / rho;
+    qb[j][0] = qb[j][0] - (ub[j] * u[j] + wb[j] * w[j]) / rho;
+  }
+}
+
+// 2D: per face of sweep dir, the 24 contributions (cell j of the stencil,
+// variable r) at cb[(j * 4 + r) * nf + f].
+template <typename T>
+__global__ void __launch_bounds__(TPB)
+k_vjp_faces2d(Grid2D gd, int dir, const T *__restrict__ q, const uint8_t *__restrict__ masks,
+              const T *__restrict__ rbar, T *__restrict__ cb) {
+  const int64_t nf = dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1);
+  const int64_t f = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  if (f >= nf) return;
+  const int64_t cells = gd.nx * gd.ny;
+  // cotangent of the face flux: d rhs(right cell) / dF = 1/h, d rhs(left) / dF = -1/h
+  int64_t cl = -1, cr = -1;
+  T h;
+  if (dir == 0) {
+    const int64_t y = f / (gd.nx + 1), k = f % (gd.nx + 1);
+    if (k > 0) cl = y * gd.nx + k - 1;
+    if (k < gd.nx) cr = y * gd.nx + k;
+    h = (T)gd.dx;
+  } else {
+    const int64_t k = f / gd.nx, x = f % gd.nx;
+    if (k > 0) cl = (k - 1) * gd.nx + x;
+    if (k < gd.ny) cr = k * gd.nx + x;
+    h = (T)gd.dy;
+  }
+  T Fb[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const T right = cr >= 0 ? rbar[r * cells + cr] : T(0);
+    const T left = cl >= 0 ? rbar[r * cells + cl] : T(0);
+    Fb[r] = (right - left) / h;
+  }
+  T qs[6][4];
+  load_stencil2d<T>(gd, dir, q, f, qs);
+  uint8_t msk[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) msk[m] = masks[m * nf + f];
+  T qb[6][4] = {};
+  face_vjp_euler2d<T>(qs, (T)gd.gamma, dir, msk, Fb, qb);
+#pragma unroll
+  for (int j = 0; j < 6; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) cb[(int64_t)(j * 4 + r) * nf + f] = qb[j][r];
+}
+
+// Per cell: the x-sweep then the y-sweep contributions, each in a fixed order
+// (direct stencil positions by ascending face, then ghost positions).
+template <typename T>
+__global__ void __launch_bounds__(TPB)
+k_vjp_gather2d(Grid2D gd, const T *__restrict__ cbx, const T *__restrict__ cby, T *__restrict__ qbar) {
+  const int64_t cells = gd.nx * gd.ny;
+  const int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  if (i >= cells) return;
+  const int64_t y = i / gd.nx, x = i % gd.nx;
+  const int64_t nfx = (gd.nx + 1) * gd.ny, nfy = gd.nx * (gd.ny + 1);
+  for (int r = 0; r < 4; ++r) {
+    T acc = T(0);
+    for (int d = 0; d < 2; ++d) {
+      const T *cb = d == 0 ? cbx : cby;
+      const int64_t n = d == 0 ? gd.nx : gd.ny, c = d == 0 ? x : y;
+      const int64_t nf = d == 0 ? nfx : nfy;
+      // face k of this row (x) / column (y)
+      auto face = [&](int64_t k) { return d == 0 ? y * (gd.nx + 1) + k : k * gd.nx + x; };
+      for (int64_t k = c - 2; k <= c + 3; ++k) {
+        if (k < 0 || k > n) continue;
+        const int j = (int)(c - k + 3);
+        acc = acc + cb[(int64_t)(j * 4 + r) * nf + face(k)];
+      }
+      if (c < 3 || c > n - 4) {
+        for (int64_t k = 0; k <= n; ++k) {
+          if (k > 5 && k < n - 5) continue;
+          for (int j = 0; j < 6; ++j) {
+            const int64_t cc = k - 3 + j;
+            if (cc >= 0 && cc < n) continue;
+            if (ghost(cc, n, gd.bc) == c) acc = acc + cb[(int64_t)(j * 4 + r) * nf + face(k)];
+          }
+        }
+      }
+    }
+    qbar[r * cells + i] = acc;
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(TPB)
 k_vjp_faces1d(Line1D ln, int equation, const T *__restrict__ q, const uint8_t *__restrict__ masks,
@@ -1102,6 +1383,22 @@ hipError_t launch_vjp1d(const Line1D &ln, int equation, const T *q, const uint8_
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_vjp2d(const Grid2D &g, const T *q, const uint8_t *masks, const T *rbar, T *qbar,
+                        T *scratch, hipStream_t s) {
+  const int64_t nfx = (g.nx + 1) * g.ny, nfy = g.nx * (g.ny + 1);
+  T *cbx = scratch, *cby = scratch + 24 * nfx;
+  hipLaunchKernelGGL(k_vjp_faces2d<T>, dim3(nblocks(nfx)), dim3(TPB), 0, s, g, 0, q, masks, rbar,
+                     cbx);
+  hipLaunchKernelGGL(k_vjp_faces2d<T>, dim3(nblocks(nfy)), dim3(TPB), 0, s, g, 1, q,
+                     masks + 4 * nfx, rbar, cby);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_vjp_gather2d<T>, dim3(nblocks(g.nx * g.ny)), dim3(TPB), 0, s, g, cbx, cby,
+                     qbar);
+  return hipGetLastError();
+}
+
 hipError_t launch_params_to_f32(const double *P, float *P32, hipStream_t s) {
   hipLaunchKernelGGL(k_params_to_f32, dim3(nblocks(NPARAM)), dim3(TPB), 0, s, P, P32);
   return hipGetLastError();
@@ -1131,7 +1428,9 @@ hipError_t launch_params_to_f32(const double *P, float *P32, hipStream_t s) {
   template hipError_t launch_cfl2d<T>(const Grid2D &, const T *, double, double *, double *,     \
                                       int32_t *, double *, hipStream_t);                         \
   template hipError_t launch_vjp1d<T>(const Line1D &, int, const T *, const uint8_t *, const T *, \
-                                      T *, T *, hipStream_t);
+                                      T *, T *, hipStream_t);                                    \
+  template hipError_t launch_vjp2d<T>(const Grid2D &, const T *, const uint8_t *, const T *, T *,  \
+                                      T *, hipStream_t);
 
 N6_INST(double)
 N6_INST(float)

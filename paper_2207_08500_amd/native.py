@@ -340,7 +340,7 @@ def neno6_rhs_adjoint(prob: Problem, masks: torch.Tensor, rbar: torch.Tensor, ub
 
 def neno6_rhs_vjp(prob: Problem, q: torch.Tensor, masks: torch.Tensor, rbar: torch.Tensor,
                   qbar: torch.Tensor, ws: torch.Tensor | None = None, stream=None):
-    """qbar = (d rhs / d q)^T rbar at q with fixed labels (BURGERS, EULER1D)."""
+    """qbar = (d rhs / d q)^T rbar at q with fixed labels (BURGERS, EULER1D, EULER2D)."""
     dt = fdtype(prob.precision)
     for t, nm in ((q, "q"), (rbar, "rbar"), (qbar, "qbar")):
         _dev(t, dt, nm)

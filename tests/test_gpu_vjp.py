@@ -1,4 +1,4 @@
-"""Vector-Jacobian product of the Burgers and 1D Euler right-hand sides at
+"""Vector-Jacobian product of the Burgers, 1D Euler and 2D Euler right-hand sides at
 fixed labels (neno6_rhs_vjp): against central finite differences of the FP64
 oracle's right-hand side with the same labels imposed, FP32 against FP64, and
 through torch.autograd.gradcheck of the autograd wrapper.  States are smooth
@@ -98,6 +98,74 @@ def test_rhs_fixed_labels_gradcheck():
     q, off, dx = _euler_state(9, [13])
     masks = dev(np.random.default_rng(10).integers(0, 256, 3 * 14).astype(np.uint8))
     prob = native.Problem(native.EULER1D, native.FP64, native.SEL_MASKS_IN, 1, off, dx)
+    qq = dev(q).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda x: ag.rhs_fixed_labels(x, masks, prob), (qq,), eps=1e-6,
+                                    atol=1e-5, rtol=1e-4)
+
+
+def _euler2d_state(seed, nx, ny, gamma=1.4):
+    g = np.random.default_rng(seed)
+    x = ((np.arange(nx) + 0.5) / nx)[None, :]
+    y = ((np.arange(ny) + 0.5) / ny)[:, None]
+    noise = lambda: 0.05 * g.random((ny, nx))
+    rho = 1.0 + 0.2 * np.sin(2 * np.pi * (x + 0.5 * y) + g.uniform(0, 6)) + noise()
+    u = 0.3 * np.sin(2 * np.pi * (x - y) + g.uniform(0, 6)) + noise()
+    v = 0.25 * np.cos(2 * np.pi * (0.5 * x + y) + g.uniform(0, 6)) + noise()
+    p = 1.0 + 0.3 * np.cos(2 * np.pi * (x + y) + g.uniform(0, 6)) + noise()
+    return np.stack([rho, rho * u, rho * v, p / (gamma - 1) + 0.5 * rho * (u * u + v * v)])
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_euler2d_vjp_against_finite_differences(bc):
+    """Both sweeps: x faces [4][ny][nx+1] and y faces [4][ny+1][nx], random
+    labels imposed; a non-square grid with dx != dy, small enough that every
+    cell is within three cells of a boundary in one direction (ghost
+    positions) and the interior positions are exercised too."""
+    need_gpu()
+    import torch
+    from paper_2207_08500_amd import native
+    nx, ny = 9, 7
+    dx, dy = 1.0 / nx, 0.8 / ny
+    q = _euler2d_state(20 + bc, nx, ny)
+    g = np.random.default_rng(21)
+    mx = g.integers(0, 256, (4, ny, nx + 1)).astype(np.uint8)
+    my = g.integers(0, 256, (4, ny + 1, nx)).astype(np.uint8)
+    rbar = g.standard_normal(q.shape)
+    fn = lambda qq: oracle.euler2d_rhs(qq, dx, dy, 1.4, bc, None, oracle.SEL_MASKS_IN, (mx, my))[0]
+    want = _fd_vjp(fn, q, rbar)
+    masks = np.concatenate([mx.ravel(), my.ravel()])
+    prob = native.Problem(native.EULER2D, native.FP64, native.SEL_MASKS_IN, bc, nx=nx, ny=ny,
+                          dx2d=dx, dy2d=dy)
+    qb = torch.zeros(q.size, dtype=torch.float64, device="cuda")
+    native.neno6_rhs_vjp(prob, dev(q), dev(masks), dev(rbar), qb)
+    torch.cuda.synchronize()
+    got = host(qb).reshape(q.shape)
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print("Euler 2D vjp bc %d: max rel error vs central differences %.3g" % (bc, err))
+    assert err < 1e-6
+    # FP32 path against the FP64 path
+    p32 = native.Problem(native.EULER2D, native.FP32, native.SEL_MASKS_IN, bc, nx=nx, ny=ny,
+                         dx2d=dx, dy2d=dy)
+    qb32 = torch.zeros(q.size, dtype=torch.float32, device="cuda")
+    native.neno6_rhs_vjp(p32, dev(q, torch.float32), dev(masks), dev(rbar, torch.float32), qb32)
+    torch.cuda.synchronize()
+    assert np.abs(host(qb32) - host(qb)).max() < 1e-3 * np.abs(host(qb)).max()
+    # deterministic: a second call gives the same bits
+    qb2 = torch.zeros_like(qb)
+    native.neno6_rhs_vjp(prob, dev(q), dev(masks), dev(rbar), qb2)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(qb2), host(qb))
+
+
+def test_euler2d_rhs_fixed_labels_gradcheck():
+    need_gpu()
+    import torch
+    from paper_2207_08500_amd import autograd as ag, native
+    nx, ny = 6, 5
+    q = _euler2d_state(22, nx, ny)
+    prob = native.Problem(native.EULER2D, native.FP64, native.SEL_MASKS_IN, 1, nx=nx, ny=ny,
+                          dx2d=1.0 / nx, dy2d=1.0 / ny)
+    masks = dev(np.random.default_rng(23).integers(0, 256, prob.mask_count()).astype(np.uint8))
     qq = dev(q).requires_grad_(True)
     assert torch.autograd.gradcheck(lambda x: ag.rhs_fixed_labels(x, masks, prob), (qq,), eps=1e-6,
                                     atol=1e-5, rtol=1e-4)

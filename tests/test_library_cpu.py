@@ -61,6 +61,15 @@ def test_host_argument_checks():
     ps.nx = 8
     assert lib.neno6_workspace_size(C.byref(ps)) > 0
     assert lib.neno6_rhs(C.byref(ps), None, None, None, None, None, None, None, 0, None) == native.BAD_ARG
+    # vector-Jacobian product: 2D scratch of 24 values per x and y face; the
+    # advection right-hand side has its own adjoint entry point
+    ps.precision = native.FP64
+    nf2 = (8 + 1) * 4 + 8 * (4 + 1)
+    assert lib.neno6_vjp_workspace_size(C.byref(ps)) >= 24 * nf2 * 8
+    assert lib.neno6_rhs_vjp(C.byref(ps), None, None, None, None, None, 0, None) == native.BAD_ARG
+    ps.precision = native.BF16
+    assert lib.neno6_rhs_vjp(C.byref(ps), None, None, None, None, None, 0, None) == native.BAD_LAYOUT
+    ps.precision = native.FP64
     # 1D: offsets must start at 0, increase strictly and end at total_cells
     import numpy as np
     off = np.array([0, 5, 5, 9], np.int64)
