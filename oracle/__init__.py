@@ -66,6 +66,7 @@ def _load():
                                        u8, d, u8, i32],
                 "oracle_euler1d_step": [d, i64, C.c_int32, d, C.c_double, C.c_int32, C.c_double,
                                         C.c_int32, d, C.c_int32, d, i32],
+                "oracle_euler1d_stencils": [d, i64, C.c_int32, C.c_double, C.c_int32, d],
                 "oracle_euler2d_rhs": [d, C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double,
                                        C.c_int32, d, C.c_int32, u8, u8, d, u8, u8, i32],
                 "oracle_euler2d_step": [d, C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double,
@@ -226,6 +227,19 @@ def euler1d_rhs(q, offsets, dx, gamma=1.4, bc=BC_TRANSMISSIVE, params=None, sele
                                       _p(mi, C.c_uint8), _p(r, C.c_double), _p(m, C.c_uint8),
                                       _p(st, C.c_int32)), "oracle_euler1d_rhs")
     return r, m, st
+
+
+def euler1d_stencils(q, offsets, gamma=1.4, bc=BC_TRANSMISSIVE):
+    """The classifier inputs of euler1d_rhs: the '+' and '-' characteristic
+    split stencils of every field at every face, [faces][6][6] with
+    evaluation e = 2 m + sign ('-' mirrored), faces numbered as the masks."""
+    q = _f64(q)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    npb = off.size - 1
+    out = np.zeros((int(off[-1]) + npb, 6, 6))
+    _check(_load().oracle_euler1d_stencils(_p(q, C.c_double), _p(off, C.c_int64), npb, gamma, bc,
+                                           _p(out, C.c_double)), "oracle_euler1d_stencils")
+    return out
 
 
 def euler1d_step(q, offsets, dx, cfl, n_steps, gamma=1.4, bc=BC_TRANSMISSIVE, params=None,

@@ -449,9 +449,11 @@ static int physical(double rho, double p) { return rho > 0.0 && p > 0.0 && isfin
 /* Face flux of a 1D Euler line between cells i and i+1 from the six cells
  * i-2..i+3 given in qs[j][var] (j = 0..5), and its masks.
  * mask byte per field: low nibble '+', high nibble '-'. */
-static void euler1d_face(const double qs[6][3], double gamma, const double *P, int selector,
-                         const uint8_t *min, double Fhat[3], uint8_t *mout) {
-  double L[3][3], R[3][3];
+/* Characteristic Rusanov split of the six cells: the '+' and '-' stencils of
+ * every field m (the '-' one mirrored), and the Roe eigenvectors R. */
+static void euler1d_split(const double qs[6][3], double gamma, double spl[3][6], double smi[3][6],
+                          double R[3][3]) {
+  double L[3][3];
   roe1d(qs[2], qs[3], gamma, L, R);
   double v[6][3], g[6][3], lam[6][3];
   for (int j = 0; j < 6; ++j) {
@@ -471,24 +473,31 @@ static void euler1d_face(const double qs[6][3], double gamma, const double *P, i
       g[j][m] = ag;
     }
   }
-  double hs[3];
   for (int m = 0; m < 3; ++m) {
     double alpha = 0.0;
     for (int j = 0; j < 6; ++j) {
       double a = fabs(lam[j][m]);
       if (a > alpha) alpha = a;
     }
-    double sp[6], sm[6];
     for (int j = 0; j < 6; ++j) {
       double t = alpha * v[j][m];
-      sp[j] = 0.5 * (g[j][m] + t);
-      sm[5 - j] = 0.5 * (g[j][m] - t);
+      spl[m][j] = 0.5 * (g[j][m] + t);
+      smi[m][5 - j] = 0.5 * (g[j][m] - t);
     }
+  }
+}
+
+static void euler1d_face(const double qs[6][3], double gamma, const double *P, int selector,
+                         const uint8_t *min, double Fhat[3], uint8_t *mout) {
+  double sp[3][6], sm[3][6], R[3][3];
+  euler1d_split(qs, gamma, sp, sm, R);
+  double hs[3];
+  for (int m = 0; m < 3; ++m) {
     unsigned mi = min ? min[m] : 0u;
-    unsigned selp = select_mask(selector, P, sp, mi & 15u);
-    unsigned selm = select_mask(selector, P, sm, (mi >> 4) & 15u);
-    double hp = combine(sp, selp);
-    double hm = combine(sm, selm);
+    unsigned selp = select_mask(selector, P, sp[m], mi & 15u);
+    unsigned selm = select_mask(selector, P, sm[m], (mi >> 4) & 15u);
+    double hp = combine(sp[m], selp);
+    double hm = combine(sm[m], selm);
     hs[m] = hp + hm;
     if (mout) mout[m] = (uint8_t)(selp | (selm << 4));
   }
@@ -544,6 +553,40 @@ int oracle_euler1d_rhs(const double *q, const int64_t *offsets, int32_t n_proble
     for (int64_t i = 0; i < n; ++i)
       for (int r = 0; r < 3; ++r) rhs[r * total + o + i] = (Fh[i][r] - Fh[i + 1][r]) / dx[pb];
     free(Fh);
+  }
+  return bad ? ST_BAD_ARG : ST_OK;
+}
+
+/* The six split stencils of every face of a batch of 1D Euler lines (the
+ * classifier inputs of the rhs): out[face][e][6], e = 2 m + sign, faces
+ * numbered as the masks of oracle_euler1d_rhs. */
+int oracle_euler1d_stencils(const double *q, const int64_t *offsets, int32_t n_problems,
+                            double gamma, int32_t bc, double *out) {
+  if (n_problems < 0 || (bc != 0 && bc != 1)) return ST_BAD_ARG;
+  const int64_t total = offsets[n_problems];
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
+  for (int32_t pb = 0; pb < n_problems; ++pb) {
+    const int64_t o = offsets[pb];
+    const int64_t n = offsets[pb + 1] - o;
+    if (n < 1) {
+      bad = 1;
+      continue;
+    }
+    for (int64_t k = 0; k <= n; ++k) {
+      double qs[6][3], sp[3][6], sm[3][6], R[3][3];
+      for (int j = 0; j < 6; ++j) {
+        int64_t ci = ghost_index(k - 3 + j, n, bc);
+        for (int r = 0; r < 3; ++r) qs[j][r] = q[r * total + o + ci];
+      }
+      euler1d_split(qs, gamma, sp, sm, R);
+      double *dst = out + (o + pb + k) * 36;
+      for (int m = 0; m < 3; ++m)
+        for (int j = 0; j < 6; ++j) {
+          dst[(2 * m) * 6 + j] = sp[m][j];
+          dst[(2 * m + 1) * 6 + j] = sm[m][j];
+        }
+    }
   }
   return bad ? ST_BAD_ARG : ST_OK;
 }

@@ -12,6 +12,8 @@ cells, 2D Riemann problems of the four-quadrant type, Sec. 4):
   * ``riemann2d``       -- a 2D four-quadrant Riemann problem with a density wave
   * ``uneven_sizes``    -- log-uniform line lengths for batched runs
   * ``classifier_samples`` -- six-point stencils with per-candidate labels
+  * ``alg1_family``     -- the function families of the paper's training-set
+                           construction (Alg. 1 and its parameter table)
   * ``mlp_init``        -- a seeded parameter block for the 6-64-32-16-8-4 network
 """
 from __future__ import annotations
@@ -236,3 +238,70 @@ def random_stencils(seed: int, n: int, scale: float = 1.0) -> np.ndarray:
     base = g.standard_normal((n, 6))
     mag = np.exp(g.uniform(np.log(1e-3), np.log(1e3), n))[:, None]
     return np.ascontiguousarray(scale * base * mag)
+
+
+# --------------------------------------------------------------------------
+# Function families of the training-set construction (Alg. 1 and the
+# appendix table of parameters for training and validation data): a
+# function of family 1..9 drawn on [-1, 1] with its singular points (None
+# where the family has none in closed form).  Readings: a_k ~ U[0.1, 2]
+# (family 2); family 6 with integer exponents; family 8's x0 on a grid
+# interface in [-0.6, 0.6]; family 9 with N_f = N / 4.
+# --------------------------------------------------------------------------
+ALG1_GRIDS = (50, 100, 200)
+ALG1_GRID_SHARE = (0.4, 0.4, 0.2)
+# candidate cell offsets relative to cell i (face x_{i+1/2} between i, i+1)
+ALG1_CAND_CELLS = ((-1, 0, 1), (0, 1, 2), (-2, -1, 0), (0, 1, 2, 3))
+
+
+def alg1_family(g, fam, N):
+    """Returns (f(x) vectorised, list of singular points or None for TENO labels)."""
+    dx = 2.0 / N
+    if fam == 1:
+        k = g.uniform(-5, 5)
+        return (lambda x: k * x), []
+    if fam == 2:
+        k, a = g.uniform(1, 5), g.uniform(0.1, 2.0)
+        return (lambda x: a * np.sin(k * x)), []
+    if fam == 3:
+        a1, a2 = g.uniform(-1, 1, 2)
+        return (lambda x: np.exp(a1 * (x - a2) ** 2)), []
+    if fam == 4:
+        r, P = g.uniform(1, 3), g.uniform(2 * dx, 8 * dx)
+        f = lambda x: (r / P) * (P - np.abs(np.mod(x, 2 * P) - P))
+        kinks = [m * P for m in range(int(np.floor(-1.2 / P)), int(np.ceil(1.2 / P)) + 1)]
+        return f, kinks
+    if fam == 5:
+        b1, x0, c = g.normal(0.0, np.sqrt(0.6)), g.uniform(-0.6, 0.6), g.uniform(0, 1)
+        return (lambda x: np.maximum(0.0, b1 * (x - x0)) + c), [x0]
+    if fam == 6:
+        k1, k2 = g.integers(2, 9, 2)
+        a1, a2 = g.uniform(0, 2, 2)
+        return (lambda x: (x - a1) ** k1 + (x - a2) ** k2), None
+    if fam == 7:
+        al, a = g.uniform(0, 2, 2)
+        al = max(al, 1e-3)
+        f = lambda x: np.sqrt(np.maximum(0.0, 1.0 - al * al * (x - a) ** 2))
+        return f, [a - 1.0 / al, a + 1.0 / al]
+    if fam == 8:
+        xl, xr = g.uniform(0, 2, 2)
+        i0 = int(g.integers(int(0.2 * N), int(0.8 * N)))
+        x0 = -1.0 + i0 * dx  # an interface
+        return (lambda x: np.where(x <= x0, xl, xr)), [x0]
+    a1, x0 = g.uniform(0, 2, 2)
+    Nf = N / 4
+    return (lambda x: a1 * np.sin(Nf * np.pi * (x - x0))), None
+
+
+def alg1_geometric_labels(faces, singular, N):
+    """eta[k] per face index i (face x_{i+1/2}) from singular points."""
+    dx = 2.0 / N
+    y = np.zeros(len(faces), np.uint8)
+    sp = np.asarray(singular, np.float64)
+    for n, i in enumerate(faces):
+        for k, cells in enumerate(ALG1_CAND_CELLS):
+            lo = -1.0 + (i + cells[0]) * dx  # left edge of the first cell
+            hi = -1.0 + (i + cells[-1] + 1) * dx  # right edge of the last cell
+            if np.any((sp > lo) & (sp < hi)):
+                y[n] |= 1 << k
+    return y

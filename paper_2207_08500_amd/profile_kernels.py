@@ -5,9 +5,15 @@ plain device copy of known size that calibrates the memory counters.
         python3 paper_2207_08500_amd/profile_kernels.py
     rocprofv3 --pmc WRITE_SIZE --kernel-trace --output-format csv -d OUT -o run -- \
         python3 paper_2207_08500_amd/profile_kernels.py
+    rocprofv3 --kernel-trace --stats --output-format csv -d OUT -o run -- \
+        python3 paper_2207_08500_amd/profile_kernels.py --steps 20
 
 Workload: 256 independent 1D Euler Riemann problems of 4000 cells (the
 benchmark's), FP32 state, BF16/FP16 classifier; the FP64 plain path once.
+With --steps K: instead, K SSP-RK3 steps of the BF16 path with the re-check
+(margin 0.5), captured once in a HIP graph and replayed after 20 warm-up
+replays; a one-element torch fill right before the timed replays marks where
+they start in a kernel trace.
 """
 import argparse
 import os
@@ -27,6 +33,7 @@ def main():
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--steps", type=int, default=0)
     a = ap.parse_args()
     native.load()
     dev = torch.device("cuda:0")
@@ -34,6 +41,8 @@ def main():
     q0, off, dx = inputs.riemann1d_batch(inputs.BASE_SEED, (4000,) * 256)
     q32 = torch.as_tensor(q0, dtype=torch.float32, device=dev).contiguous()
     faces = int(off[-1]) + 256
+    if a.steps > 0:
+        return step_replay(a.steps, P, q32, off, dx, dev)
     for prec in (native.BF16, native.FP16):
         mlp = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=0.0)
         prob = native.Problem(native.EULER1D, prec, native.SEL_MLP, native.TRANSMISSIVE, off, dx,
@@ -59,6 +68,46 @@ def main():
     torch.cuda.synchronize()
     print("profiled: fused face kernel x%d (BF16, FP16), FP64 path x1, copy %d MiB"
           % (a.reps, a.copy_mib))
+
+
+def step_replay(steps, P, q32, off, dx, dev):
+    from paper_2207_08500_amd import autotune
+    mlp = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=0.5)
+    prob = native.Problem(native.EULER1D, native.BF16, native.SEL_MLP, native.TRANSMISSIVE, off, dx,
+                          device=dev)
+    ws = prob.workspace(dev)
+    shape = autotune.tuned(prob, mlp, q32, ws)[0]
+    n = off.size - 1
+    q = q32.clone()
+    t = torch.zeros(n, dtype=torch.float64, device=dev)
+    st = torch.zeros(n, dtype=torch.int32, device=dev)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        native.neno6_step(prob, mlp, q, 0.4, 1, t, st, ws)  # builds the face map
+    torch.cuda.current_stream().wait_stream(s)
+    prob.flags = native.KEEP_MAP
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        native.neno6_step(prob, mlp, q, 0.4, 1, t, st, ws)
+    q.copy_(q32)
+    t.zero_()
+    st.zero_()
+    for _ in range(20):  # steady clocks
+        g.replay()
+    q.copy_(q32)
+    t.zero_()
+    st.zero_()
+    marker = torch.zeros(1, device=dev)
+    marker.fill_(1.0)  # the timed replays follow this dispatch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    print("profiled: %d graph-replayed BF16 RK3 steps, launch shape %s, %.4f ms per step"
+          % (steps, shape, e0.elapsed_time(e1) / steps))
 
 
 if __name__ == "__main__":
