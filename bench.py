@@ -38,6 +38,11 @@ PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # one operation per hidden activation 720, output bias + labels 50,
 # combine 180, back-projection 12
 VALU_OPS_PER_FACE = 1350
+# 2D Euler face (one sweep): primitives 100, Roe average and eigenvectors 60,
+# projection + split 240, speeds 30, features 104, hidden activations 960,
+# output bias + labels 64, combine 240, back-projection 16
+VALU_OPS_PER_FACE_2D = 1814
+EVALS_PER_FACE_2D = 8
 FLOP_PER_EVAL = 6208      # 2 x 3104 MAC of the 6-64-32-16-8-4 network
 EVALS_PER_FACE = 6        # 3 characteristic fields x 2 split signs
 
@@ -62,13 +67,13 @@ def _traffic_bytes():
         return None
 
 
-def _alu(faces, k_ms):
+def _alu(faces, k_ms, ops_per_face=VALU_OPS_PER_FACE):
     """VALU-issue roofline of the fused kernel (the binding one: see the
     counter profile): algorithmic lane-operations per launch / time against
     256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz."""
-    ach = faces * VALU_OPS_PER_FACE / (k_ms / 1e3) / 1e12
+    ach = faces * ops_per_face / (k_ms / 1e3) / 1e12
     return {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "Tlane-op/s",
-            "frac": ach / PEAK_VALU_TOPS, "ops_per_face": VALU_OPS_PER_FACE}
+            "frac": ach / PEAK_VALU_TOPS, "ops_per_face": ops_per_face}
 
 
 def _physical(q, off, gamma=1.4):
@@ -93,14 +98,15 @@ def _args():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", choices=("c2", "c4"), default="c2",
-                    help="c2: 256 x 4000-cell batch (headline); c4: 4096 uneven problems, "
+    ap.add_argument("--workload", choices=("c2", "c3", "c4"), default="c2",
+                    help="c2: 256 x 4000-cell batch (headline); c3: 2D Euler four-quadrant "
+                         "Riemann problem on 2048 x 2048 cells; c4: 4096 uneven problems, "
                          "ten RK3 steps per graph replay, autotuned launch shapes")
     a = ap.parse_args()
     if a.steps is None:
-        a.steps = 200 if a.workload == "c2" else 20
+        a.steps = {"c2": 200, "c3": 20, "c4": 20}[a.workload]
     if a.warmup is None:
-        a.warmup = 20 if a.workload == "c2" else 3
+        a.warmup = {"c2": 20, "c3": 3, "c4": 3}[a.workload]
     return a
 
 
@@ -120,6 +126,8 @@ def main():
     P = np.load(os.path.join(ROOT, "tests", "golden", "neno6_mlp_trained.npy"), allow_pickle=False)
     if a.workload == "c4":
         return bench_batched(a, P, dev)
+    if a.workload == "c3":
+        return bench_2d(a, P, dev)
     q0, off, dx = inputs.riemann1d_batch(inputs.BASE_SEED, (N_CELLS,) * N_PROBLEMS)
     faces_stage = int(off[-1]) + N_PROBLEMS
     faces_step = 3 * faces_stage
@@ -430,6 +438,129 @@ def bench_batched(a, P, dev):
                           "unit": "TFLOP/s", "frac": achieved / PEAK_MFMA_BF16},
         "frozen_problems": {"bf16": int((st != 0).sum()), "of": n_prob},
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+def bench_2d(a, P, dev):
+    """2D Euler, four-quadrant Riemann problem on 2048 x 2048 cells
+    (transmissive), FP32 state, BF16 classifier with the FP32 re-check; one
+    step = one SSP-RK3 step (x and y sweeps in each stage), HIP graph."""
+    import numpy as np
+    import torch
+
+    from paper_2207_08500_amd import autotune, inputs, native
+
+    nx = ny = 2048
+    q0 = inputs.riemann2d(inputs.BASE_SEED, nx, ny)
+    q32 = torch.as_tensor(q0, dtype=torch.float32, device=dev).contiguous().reshape(-1)
+    q64_from32 = q32.double().contiguous()
+
+    def make(prec):
+        mlp = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=MARGIN.get(prec, 0.0))
+        prob = native.Problem(native.EULER2D, prec, native.SEL_MLP, native.TRANSMISSIVE, nx=nx,
+                              ny=ny, dx2d=1.0 / nx, dy2d=1.0 / ny, device=dev)
+        return mlp, prob, prob.workspace(dev)
+
+    faces_stage = (nx + 1) * ny + nx * (ny + 1)
+    faces_step = 3 * faces_stage
+    shapes = {}
+
+    def run(prec, q_init, steps, warmup):
+        mlp, prob, ws = make(prec)
+        if prec in (native.BF16, native.FP16):
+            shapes[prec] = autotune.tuned(prob, mlp, q_init, ws)[0]
+        q = q_init.clone()
+        t = torch.zeros(1, dtype=torch.float64, device=dev)
+        st = torch.zeros(1, dtype=torch.int32, device=dev)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            native.neno6_step(prob, mlp, q, CFL, 1, t, st, ws)
+        torch.cuda.current_stream().wait_stream(s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            native.neno6_step(prob, mlp, q, CFL, 1, t, st, ws)
+        for _ in range(warmup):
+            g.replay()
+        q.copy_(q_init)
+        t.zero_()
+        st.zero_()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        return q, t, st, e0.elapsed_time(e1)
+
+    qb, tb, stb, ms_b = run(native.BF16, q32, a.steps, a.warmup)
+    value = faces_step * a.steps / (ms_b / 1e3)
+    k64 = max(2, a.steps // 4)
+    _, _, _, ms_64 = run(native.FP64, q64_from32, k64, 1)
+    fp64_rate = faces_step * k64 / (ms_64 / 1e3)
+    q64b, t64b, st64b, _ = run(native.FP64, q64_from32, a.steps, 0)
+    dq = (qb.double() - q64b).abs().reshape(4, -1)
+    l1 = float((dq.mean(dim=1) / q64b.reshape(4, -1).abs().mean(dim=1)).max())
+
+    def labels(prec, q):
+        mlp, prob, ws = make(prec)
+        r = torch.zeros_like(q)
+        m = torch.zeros(prob.mask_count(), dtype=torch.uint8, device=dev)
+        native.neno6_rhs(prob, mlp, q, r, ws, masks_out=m)
+        return m
+
+    x = (labels(native.BF16, q32) ^ labels(native.FP64, q64_from32)).cpu().numpy()
+    flip = float(np.unpackbits(x.reshape(-1, 1), axis=1).sum() / (8.0 * x.size))
+    # both sweeps of the fused face kernel alone (margin 0)
+    mlp0 = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=0.0)
+    _, prob0, ws0 = make(native.BF16)
+    prob0.set_tuning(shapes.get(native.BF16))
+    F = torch.zeros(4 * faces_stage, dtype=torch.float32, device=dev)
+    for _ in range(20):
+        native.neno6_face_fluxes(prob0, mlp0, q32, F, ws0)
+    torch.cuda.synchronize()
+    reps = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        native.neno6_face_fluxes(prob0, mlp0, q32, F, ws0)
+    e1.record()
+    torch.cuda.synchronize()
+    k_ms = e0.elapsed_time(e1) / reps
+    flop = faces_stage * EVALS_PER_FACE_2D * FLOP_PER_EVAL
+    achieved = flop / (k_ms / 1e3) / 1e12
+    out = {
+        "metric": "reconstructed faces/s: plain FP64 vs BF16-MFMA NENO6 at stated flip rate/L1 error",
+        "value": value,
+        "unit": "faces/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_b / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "2D Euler four-quadrant Riemann problem, %d x %d cells, transmissive, "
+                               "FP32 state, BF16-MFMA classifier, re-check margin %.2f, SSP-RK3 "
+                               "CFL %.1f" % (nx, ny, MARGIN[2], CFL),
+                   "faces_per_step": faces_step, "hip_graph": True,
+                   "launch_shapes": shapes.get(native.BF16)},
+        "roofline": dict(_alu(faces_stage, k_ms, VALU_OPS_PER_FACE_2D), traffic=None,
+                         kernel="k_fast_faces<BF16, 2D Euler>, x and y sweeps", kernel_ms=k_ms,
+                         algorithmic_flop_per_launch=flop),
+        "roofline_mfma": {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_BF16,
+                          "unit": "TFLOP/s", "frac": achieved / PEAK_MFMA_BF16},
+        "fp64_plain": {"value": fp64_rate, "unit": "faces/s", "ms_per_step": ms_64 / k64,
+                       "steps": k64},
+        "speedup_bf16_vs_fp64": value / fp64_rate,
+        "flip_rate": flip,
+        "l1_rel_vs_fp64": l1,
+        "status": {"bf16": int(stb[0]), "fp64": int(st64b[0])},
+        "cpu_baseline": None,
     }
     print(json.dumps(out))
 
