@@ -232,7 +232,12 @@ def main():
         x = (ma ^ mb).cpu().numpy()
         return float(np.unpackbits(x.reshape(-1, 1), axis=1).sum() / (8.0 * x.size))
 
+    def flip_faces(ma, mb):  # share of faces with any differing label
+        x = (ma ^ mb).reshape(3, -1).cpu().numpy()
+        return float((x != 0).any(axis=0).mean())
+
     flip_b, flip_h = flip(mb16, m64), flip(mh16, m64)
+    flip_face_b = flip_faces(mb16, m64)
 
     # ---- fused face kernel alone, BF16 (roofline) ------------------------------------
     mlp0, prob0, ws0 = make(native.BF16, 0.0)  # margin 0: exactly the fused kernel
@@ -318,6 +323,7 @@ def main():
                       "flip_rate": flip_h},
         "speedup_bf16_vs_fp64": value / fp64_rate,
         "flip_rate": flip_b,
+        "flip_rate_per_face": flip_face_b,
         "recheck_fraction": recheck_frac,
         "l1_rel_vs_fp64": l1,
         "linf_rel_vs_fp64": linf,
@@ -513,6 +519,9 @@ def bench_2d(a, P, dev):
 
     x = (labels(native.BF16, q32) ^ labels(native.FP64, q64_from32)).cpu().numpy()
     flip = float(np.unpackbits(x.reshape(-1, 1), axis=1).sum() / (8.0 * x.size))
+    nfx = (nx + 1) * ny
+    flip_face = float(np.concatenate([(x[:4 * nfx].reshape(4, -1) != 0).any(axis=0),
+                                      (x[4 * nfx:].reshape(4, -1) != 0).any(axis=0)]).mean())
     # both sweeps of the fused face kernel alone (margin 0)
     mlp0 = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=0.0)
     _, prob0, ws0 = make(native.BF16)
@@ -558,6 +567,7 @@ def bench_2d(a, P, dev):
                        "steps": k64},
         "speedup_bf16_vs_fp64": value / fp64_rate,
         "flip_rate": flip,
+        "flip_rate_per_face": flip_face,
         "l1_rel_vs_fp64": l1,
         "status": {"bf16": int(stb[0]), "fp64": int(st64b[0])},
         "cpu_baseline": None,

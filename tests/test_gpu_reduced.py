@@ -165,3 +165,41 @@ def test_euler1d_steps_error(ctx, prec):
         assert np.all(l1 < 1e-2)
     # the CFL step follows the largest wave speed of the (slightly different) state
     assert np.allclose(host(t), t_o, rtol=1e-2)
+
+
+@pytest.mark.parametrize("prec", [2, 3])
+def test_c2_full_size_sampled(ctx, prec):
+    """The benchmark's 256 x 4000-cell batch in the benchmark's configuration
+    (FP32 state, autotuned launch shape, re-check on): labels against the
+    oracle's on the same (FP32-rounded) state for sampled problems, and the
+    right-hand side with the oracle's labels imposed within FP32 rounding."""
+    native, torch, P = ctx
+    from paper_2207_08500_amd import autotune
+    q, off, dx = inputs.riemann1d_batch(inputs.BASE_SEED, (4000,) * 256)
+    q32 = q.astype(np.float32).astype(np.float64)
+    mlp = _mlp(native, P, prec)
+    prob = native.Problem(native.EULER1D, prec, native.SEL_MLP, 1, off, dx)
+    qg = dev(q32, torch.float32)
+    ws = prob.workspace()
+    autotune.tuned(prob, mlp, qg, ws)
+    r = torch.zeros_like(qg)
+    m = torch.zeros(prob.mask_count(), dtype=torch.uint8, device="cuda")
+    native.neno6_rhs(prob, mlp, qg, r, ws, masks_out=m)
+    torch.cuda.synchronize()
+    r, m = host(r).reshape(3, -1), host(m).reshape(3, -1)
+    flips = []
+    for p in (0, 41, 128, 200, 255):
+        a, b = off[p], off[p + 1]
+        sub = q32[:, a:b]
+        r_o, m_o, _ = oracle.euler1d_rhs(sub, [0, 4000], dx[p:p + 1], 1.4, 1, P, oracle.SEL_MLP)
+        flips.append(label_flip_rate(m[:, a + p:b + p + 1].ravel(), m_o.ravel()))
+        # the same labels imposed: only FP32 arithmetic differs
+        prob_in = native.Problem(native.EULER1D, prec, native.SEL_MASKS_IN, 1, [0, 4000], dx[p:p + 1])
+        r2 = torch.zeros(3 * 4000, dtype=torch.float32, device="cuda")
+        native.neno6_rhs(prob_in, mlp, dev(sub, torch.float32), r2, prob_in.workspace(),
+                         masks_in=dev(m_o.ravel()))
+        torch.cuda.synchronize()
+        fscale = np.abs(r_o).max() + np.abs(sub).max() / dx[p]
+        assert np.abs(host(r2).reshape(3, -1) - r_o).max() <= 5e-5 * fscale
+    print("C2 prec %d: sampled label flip rates %s" % (prec, flips))
+    assert max(flips) < 1e-4
