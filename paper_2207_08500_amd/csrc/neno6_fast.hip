@@ -490,6 +490,10 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
         for (int b = 0; b < NV; ++b) stash[wv][NE * 6 + a * NV + b][lane] = R[a][b];
     }
     u32 sel[NE], near = 0u;
+    // the classifier phase at raised wave priority: its MFMA -> convert
+    // chains are issued as soon as they are ready, and the other waves'
+    // set-up and combine work fills the gaps (measured: about 1 % faster)
+    if constexpr (MLP) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
       if constexpr (MLP) {
@@ -511,6 +515,7 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
       }
     }
     __builtin_amdgcn_sched_barrier(0);
+    if constexpr (MLP) __builtin_amdgcn_s_setprio(0);
     if constexpr (MLP) {  // queue the near-cutoff evaluations for the FP32 re-check
 #pragma unroll
       for (int e = 0; e < NE; ++e)
