@@ -518,6 +518,11 @@ def bench_2d(a, P, dev):
         return m
 
     x = (labels(native.BF16, q32) ^ labels(native.FP64, q64_from32)).cpu().numpy()
+    # evaluations the FP32 re-check took on the initial state (both sweeps)
+    mlpm, probm, wsm = make(native.BF16)
+    native.neno6_face_fluxes(probm, mlpm, q32, torch.zeros(4 * faces_stage, dtype=torch.float32,
+                                                            device=dev), wsm)
+    recheck_frac = sum(native.neno6_recheck_count(probm, wsm)) / float(faces_stage * EVALS_PER_FACE_2D)
     flip = float(np.unpackbits(x.reshape(-1, 1), axis=1).sum() / (8.0 * x.size))
     nfx = (nx + 1) * ny
     flip_face = float(np.concatenate([(x[:4 * nfx].reshape(4, -1) != 0).any(axis=0),
@@ -569,6 +574,7 @@ def bench_2d(a, P, dev):
         "flip_rate": flip,
         "flip_rate_per_face": flip_face,
         "l1_rel_vs_fp64": l1,
+        "recheck_fraction": recheck_frac,
         "status": {"bf16": int(stb[0]), "fp64": int(st64b[0])},
         "cpu_baseline": None,
     }

@@ -408,12 +408,12 @@ int32_t neno6_recheck_count(const neno6_problem *prob, const void *ws, size_t ws
   uint32_t qc[QCOUNTERS];
   if (hipMemcpy(qc, w.scr.qcount, sizeof(qc), hipMemcpyDeviceToHost) != hipSuccess)
     return NENO6_HIP_ERROR;
-  if (prob->equation == NENO6_EULER2D) {
-    count[0] = qc[0];
-    count[1] = qc[1];
-  } else {  // one counter per evaluation kind
-    count[0] = qc[0] + qc[1] + qc[2] + qc[3] + qc[4] + qc[5];
-    count[1] = 0;
+  // one counter per evaluation kind (and 2D sweep direction)
+  const int nk = prob->equation == NENO6_EULER2D ? 8 : 6;
+  count[0] = count[1] = 0;
+  for (int k = 0; k < nk; ++k) {
+    count[0] += qc[k];
+    if (prob->equation == NENO6_EULER2D) count[1] += qc[8 + k];
   }
   return NENO6_OK;
 }

@@ -9,10 +9,12 @@ namespace n6 {
 // Scratch of the fast path, carved from the caller's workspace.
 struct FastScratch {
   uint8_t *masks;       // [nvar][faces] (1D) or x|y masks (2D), when the caller passes none
-  uint32_t *queue;      // re-check entries: face * 8 + (field * 2 + sign); 1D: one
-                        // list of `faces` entries per evaluation kind e at e * faces
+  uint32_t *queue;      // re-check entries: face * 8 + (field * 2 + sign), one list of
+                        // `faces` entries (of the line batch or the sweep) per
+                        // evaluation kind e at e * faces
   uint8_t *qflag;       // per entry: label changed by the FP32 re-check
-  uint32_t *qcount;     // [QCOUNTERS] entries queued: 1D per kind, 2D per direction
+  uint32_t *qcount;     // [QCOUNTERS] entries queued: 1D kind e at e, 2D sweep d kind e
+                        // at 8 * d + e
   int64_t qcap;         // queue capacity
 };
 

@@ -314,16 +314,20 @@ N6_DEV void setup2d(const Grid2D &gd, int dir, const float *__restrict__ q, int6
 #pragma clang fp contract(off)
   const int64_t cells = gd.nx * gd.ny;
   const float gm = (float)gd.gamma, g1 = gm - 1.f;
+  // the six cells in the face's own ordering (rho, rho u_n, rho u_s, E): the
+  // momentum planes are picked by address, so no register array is indexed
+  // by the sweep direction
   float qs[6][4];
   // 32-bit in-grid indices (the C ABI limits a grid to 2^28 cells)
   const int nx = (int)gd.nx, ny = (int)gd.ny, ff = (int)f, c32 = (int)cells;
+  const int pl[4] = {0, (dir == 0 ? 1 : 2) * c32, (dir == 0 ? 2 : 1) * c32, 3 * c32};
   if (dir == 0) {
     const int y = ff / (nx + 1), k = ff - y * (nx + 1);
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
       const int ci = y * nx + ghost32(k - 3 + j, nx, gd.bc);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) qs[j][r] = q[r * c32 + ci];
+      for (int r = 0; r < 4; ++r) qs[j][r] = q[pl[r] + ci];
     }
   } else {
     const int k = ff / nx, x = ff - k * nx;
@@ -331,17 +335,16 @@ N6_DEV void setup2d(const Grid2D &gd, int dir, const float *__restrict__ q, int6
     for (int j = 0; j < 6; ++j) {
       const int ci = ghost32(k - 3 + j, ny, gd.bc) * nx + x;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) qs[j][r] = q[r * c32 + ci];
+      for (int r = 0; r < 4; ++r) qs[j][r] = q[pl[r] + ci];
     }
   }
-  const int vn = dir == 0 ? 1 : 2, vs = dir == 0 ? 2 : 1;
   float un[6], us[6], pp[6], ir[6], lamc[6];
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
     ir[j] = __builtin_amdgcn_rcpf(qs[j][0]);
-    un[j] = qs[j][vn] * ir[j];
-    us[j] = qs[j][vs] * ir[j];
-    pp[j] = g1 * (qs[j][3] - 0.5f * __builtin_fmaf(qs[j][vn], un[j], qs[j][vs] * us[j]));
+    un[j] = qs[j][1] * ir[j];
+    us[j] = qs[j][2] * ir[j];
+    pp[j] = g1 * (qs[j][3] - 0.5f * __builtin_fmaf(qs[j][1], un[j], qs[j][2] * us[j]));
     lamc[j] = __builtin_amdgcn_sqrtf((gm * pp[j]) * ir[j]);
   }
   const float sL = __builtin_amdgcn_sqrtf(qs[2][0]), sR = __builtin_amdgcn_sqrtf(qs[3][0]);
@@ -369,8 +372,8 @@ N6_DEV void setup2d(const Grid2D &gd, int dir, const float *__restrict__ q, int6
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     R[0][m] = Rn[0][m];
-    R[vn][m] = Rn[1][m];
-    R[vs][m] = Rn[2][m];
+    R[1][m] = dir == 0 ? Rn[1][m] : Rn[2][m];
+    R[2][m] = dir == 0 ? Rn[2][m] : Rn[1][m];
     R[3][m] = Rn[3][m];
   }
   // normal-direction fluxes of the six cells in the (rho, n, s, E) ordering
@@ -384,12 +387,12 @@ N6_DEV void setup2d(const Grid2D &gd, int dir, const float *__restrict__ q, int6
     }
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-      const float Fn0 = qs[j][vn];
-      const float Fn1 = __builtin_fmaf(qs[j][vn], un[j], pp[j]);
-      const float Fn2 = qs[j][vs] * un[j];
+      const float Fn0 = qs[j][1];
+      const float Fn1 = __builtin_fmaf(qs[j][1], un[j], pp[j]);
+      const float Fn2 = qs[j][2] * un[j];
       const float Fn3 = (qs[j][3] + pp[j]) * un[j];
-      const float v = __builtin_fmaf(Ln[m][3], qs[j][3], __builtin_fmaf(Ln[m][2], qs[j][vs],
-                      __builtin_fmaf(Ln[m][1], qs[j][vn], Ln[m][0] * qs[j][0])));
+      const float v = __builtin_fmaf(Ln[m][3], qs[j][3], __builtin_fmaf(Ln[m][2], qs[j][2],
+                      __builtin_fmaf(Ln[m][1], qs[j][1], Ln[m][0] * qs[j][0])));
       const float gg = __builtin_fmaf(Ln[m][3], Fn3, __builtin_fmaf(Ln[m][2], Fn2,
                        __builtin_fmaf(Ln[m][1], Fn1, Ln[m][0] * Fn0)));
       s[2 * m][j] = 0.5f * __builtin_fmaf(alpha, v, gg);
@@ -409,21 +412,8 @@ N6_DEV void back_project(const float R[NV][NV], const float hs[NV], float Fo[NV]
   }
 }
 
-// Wave-aggregated append of (face, eval) entries to the re-check queue.
-N6_DEV void enqueue(bool want, u32 entry, u32 *__restrict__ queue, u32 *__restrict__ qcount,
-                    int64_t qcap) {
-  const uint64_t bal = __ballot(want);
-  if (bal == 0) return;
-  const int lane = threadIdx.x & 63;
-  const u32 cnt = (u32)__popcll(bal);
-  u32 base = 0;
-  if (lane == __ffsll((unsigned long long)bal) - 1) base = atomicAdd(qcount, cnt);
-  base = __shfl(base, __ffsll((unsigned long long)bal) - 1);
-  const u32 off = (u32)__popcll(bal & ((1ull << lane) - 1));
-  if (want && (int64_t)(base + off) < qcap) queue[base + off] = entry;
-}
-
-// The same into the list that starts at queue[first] (capacity cap < 2^32).
+// Wave-aggregated append of a (face, eval) entry to the re-check list that
+// starts at queue[first] (capacity cap < 2^32).
 N6_DEV void enqueue_at(bool want, u32 entry, u32 *__restrict__ queue, u32 first,
                        u32 *__restrict__ qcount, u32 cap) {
   const uint64_t bal = __ballot(want);
@@ -454,7 +444,7 @@ __global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(NV 
 k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict__ prepared,
              float margin, const float *__restrict__ q, const uint8_t *__restrict__ min,
              float *__restrict__ Fh, uint8_t *__restrict__ masks, u32 *__restrict__ queue,
-             u32 *__restrict__ qcount, int64_t qcap, int xcd) {
+             u32 *__restrict__ qcount, int xcd) {
   constexpr int NE = 2 * NV;
   constexpr int NS = NE * 6 + NV * NV;
   __shared__ float stash[W][NS][64];
@@ -518,12 +508,9 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
     if constexpr (MLP) __builtin_amdgcn_s_setprio(0);
     if constexpr (MLP) {  // queue the near-cutoff evaluations for the FP32 re-check
 #pragma unroll
-      for (int e = 0; e < NE; ++e)
-        if constexpr (NV == 3)  // one list per evaluation kind (6 faces < 2^32)
-          enqueue_at(valid && ((near >> e) & 1u), (u32)(fc * 8 + e), queue, (u32)e * (u32)nf,
-                     qcount + e, (u32)nf);
-        else
-          enqueue(valid && ((near >> e) & 1u), (u32)(fc * 8 + e), queue, qcount, qcap);
+      for (int e = 0; e < NE; ++e)  // one list per evaluation kind (NE x faces < 2^32)
+        enqueue_at(valid && ((near >> e) & 1u), (u32)(fc * 8 + e), queue, (u32)e * (u32)nf,
+                   qcount + e, (u32)nf);
     }
     float hs[NV], Fo[NV], R[NV][NV];
 #pragma unroll
@@ -692,73 +679,77 @@ N6_DEV void stencil_one(const Line1D &ln, const float *__restrict__ q, int64_t f
   for (int j = 0; j < 6; ++j) se[j] = s[E][j];
 }
 
-// Re-check entry slots.  1D: the six per-kind lists, each padded to a whole
-// number of waves' worth of slots (EPW), laid end to end, so the entries of
-// one wave always share the evaluation kind (and the stencil set-up the wave
-// runs); slot i maps to list e, position j, valid while j < count of e.
-// 2D: one list, slot i is entry i.
+// Re-check entry slots: one list per evaluation kind (field x sign: six in
+// 1D, eight per 2D sweep), each padded to a whole number of waves' worth of
+// slots (EPW) and laid end to end, so the entries of one wave always share
+// the evaluation kind (and the stencil set-up the wave runs); slot i maps to
+// list e, position j, valid while j < count of e.
 constexpr int EPW = 32;  // re-check entries per wave
 
+template <int DIM> constexpr int n_kinds() { return DIM == 1 ? 6 : 8; }
+
 struct QueueSlots {
-  int64_t base[6], count[6], total;
+  int64_t base[8], count[8], total;
 };
 
 template <int DIM>
-N6_DEV QueueSlots queue_slots(const u32 *__restrict__ qcount, int64_t qcap, int64_t nf) {
+N6_DEV QueueSlots queue_slots(const u32 *__restrict__ qcount, int64_t nf) {
   QueueSlots qs{};
-  if constexpr (DIM == 1) {
-    int64_t b = 0;
+  int64_t b = 0;
 #pragma unroll
-    for (int e = 0; e < 6; ++e) {
-      const int64_t c = (int64_t)qcount[e] < nf ? (int64_t)qcount[e] : nf;
-      qs.base[e] = b;
-      qs.count[e] = c;
-      b += (c + EPW - 1) / EPW * EPW;
-    }
-    qs.total = b;
-  } else {
-    qs.total = (int64_t)qcount[0] < qcap ? (int64_t)qcount[0] : qcap;
+  for (int e = 0; e < n_kinds<DIM>(); ++e) {
+    const int64_t c = (int64_t)qcount[e] < nf ? (int64_t)qcount[e] : nf;
+    qs.base[e] = b;
+    qs.count[e] = c;
+    b += (c + EPW - 1) / EPW * EPW;
   }
+  qs.total = b;
   return qs;
 }
 
 // Slot i -> (queue position, evaluation kind); false for a padding slot.
 template <int DIM>
 N6_DEV bool queue_slot(const QueueSlots &qs, int64_t i, int64_t nf, int64_t &pos, int &e) {
-  if constexpr (DIM == 1) {
-    e = 0;
+  constexpr int NK = n_kinds<DIM>();
+  e = 0;
 #pragma unroll
-    for (int k = 1; k < 6; ++k) e += i >= qs.base[k] ? 1 : 0;
-    int64_t b = qs.base[0], c = qs.count[0];
+  for (int k = 1; k < NK; ++k) e += i >= qs.base[k] ? 1 : 0;
+  int64_t b = qs.base[0], c = qs.count[0];
 #pragma unroll
-    for (int k = 1; k < 6; ++k) {
-      b = e == k ? qs.base[k] : b;
-      c = e == k ? qs.count[k] : c;
-    }
-    const int64_t j = i - b;
-    pos = (int64_t)e * nf + j;
-    return j < c;
-  } else {
-    pos = i;
-    e = 0;
-    return true;
+  for (int k = 1; k < NK; ++k) {
+    b = e == k ? qs.base[k] : b;
+    c = e == k ? qs.count[k] : c;
   }
+  const int64_t j = i - b;
+  pos = (int64_t)e * nf + j;
+  return j < c;
+}
+
+// Split stencil E of 2D face f of sweep dir: the full set-up with the other
+// fields' work left to dead-code elimination.
+template <int E>
+N6_DEV void stencil_one_2d(const Grid2D &gd, int dir, const float *__restrict__ q, int64_t f,
+                           float se[6]) {
+  float s[8][6], R[4][4];
+  setup2d(gd, dir, q, f, s, R);
+#pragma unroll
+  for (int j = 0; j < 6; ++j) se[j] = s[E][j];
 }
 
 // FP32 re-check of queued evaluations, 32 per wave on FP32 MFMA; flips the
 // stored nibble where the FP32 label differs and flags the entry.  The loop
 // is uniform over the wave (the MFMA products need every lane); slots past
-// the end or in a list's padding compute face 0 and store nothing.  In 1D
-// the evaluation kind is uniform over the wave, so the wave forms that one
+// the end or in a list's padding compute face 0 and store nothing.  The
+// evaluation kind is uniform over the wave, so the wave forms that one
 // stencil.
 template <int DIM>
 __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2)))
 k_recheck(Line1D ln, Grid2D gd, int dir, const void *__restrict__ prepared,
           const float *__restrict__ q, uint8_t *__restrict__ masks, const u32 *__restrict__ queue,
-          const u32 *__restrict__ qcount, int64_t qcap, uint8_t *__restrict__ qflag) {
+          const u32 *__restrict__ qcount, uint8_t *__restrict__ qflag) {
   constexpr int EPB = WPB * EPW;  // slots per workgroup and pass
   const int64_t nf = DIM == 1 ? ln.faces() : (dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1));
-  const QueueSlots qs = queue_slots<DIM>(qcount, qcap, nf);
+  const QueueSlots qs = queue_slots<DIM>(qcount, nf);
   if (blockIdx.x * (int64_t)EPB >= qs.total) return;  // block-uniform: nothing queued for this block
   const int lane = threadIdx.x & 63, j = lane & 31, h = lane >> 5;
   F32Wts w;
@@ -773,10 +764,10 @@ k_recheck(Line1D ln, Grid2D gd, int dir, const void *__restrict__ prepared,
     const int64_t f = ent >> 3;
     if (ok) e = ent & 7;
     float se[6];
-    if constexpr (DIM == 1) {  // 1D: only the queued evaluation's stencil is formed
-      int ew;
-      int64_t iw;
-      queue_slot<DIM>(qs, i0, nf, iw, ew);  // the wave's kind (slot i0 < total)
+    int ew;
+    int64_t iw;
+    queue_slot<DIM>(qs, i0, nf, iw, ew);  // the wave's kind (slot i0 < total)
+    if constexpr (DIM == 1) {  // only the queued evaluation's stencil is formed
       switch (__builtin_amdgcn_readfirstlane(ew)) {
       case 0: stencil_one<0>(ln, q, f, se); break;
       case 1: stencil_one<1>(ln, q, f, se); break;
@@ -785,15 +776,16 @@ k_recheck(Line1D ln, Grid2D gd, int dir, const void *__restrict__ prepared,
       case 4: stencil_one<4>(ln, q, f, se); break;
       default: stencil_one<5>(ln, q, f, se); break;
       }
-    } else {  // 2D: all eight, the queued one selected without a dynamic register index
-      float s[8][6], R[4][4];
-      setup2d(gd, dir, q, f, s, R);
-#pragma unroll
-      for (int jj = 0; jj < 6; ++jj) {
-        float v = s[0][jj];
-#pragma unroll
-        for (int k = 1; k < 8; ++k) v = e == k ? s[k][jj] : v;
-        se[jj] = v;
+    } else {
+      switch (__builtin_amdgcn_readfirstlane(ew)) {
+      case 0: stencil_one_2d<0>(gd, dir, q, f, se); break;
+      case 1: stencil_one_2d<1>(gd, dir, q, f, se); break;
+      case 2: stencil_one_2d<2>(gd, dir, q, f, se); break;
+      case 3: stencil_one_2d<3>(gd, dir, q, f, se); break;
+      case 4: stencil_one_2d<4>(gd, dir, q, f, se); break;
+      case 5: stencil_one_2d<5>(gd, dir, q, f, se); break;
+      case 6: stencil_one_2d<6>(gd, dir, q, f, se); break;
+      default: stencil_one_2d<7>(gd, dir, q, f, se); break;
       }
     }
     float x[6], z[4];
@@ -817,11 +809,11 @@ template <int DIM>
 __global__ void __launch_bounds__(TPB)
 k_fixup(Line1D ln, Grid2D gd, int dir, const float *__restrict__ q,
         const uint8_t *__restrict__ masks, const u32 *__restrict__ queue,
-        const u32 *__restrict__ qcount, int64_t qcap, const uint8_t *__restrict__ qflag,
+        const u32 *__restrict__ qcount, const uint8_t *__restrict__ qflag,
         float *__restrict__ Fh) {
   constexpr int NV = DIM == 1 ? 3 : 4;
   const int64_t nf = DIM == 1 ? ln.faces() : (dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1));
-  const QueueSlots qs = queue_slots<DIM>(qcount, qcap, nf);
+  const QueueSlots qs = queue_slots<DIM>(qcount, nf);
   for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < qs.total; i += (int64_t)gridDim.x * TPB) {
     int64_t pos;
     int e;
@@ -971,7 +963,7 @@ k_fast_burgers(Line1D ln, const void *__restrict__ prepared, float margin, int s
   }
 }
 
-// Clears the two re-check counters (one per sweep direction).
+// Clears the re-check counters (one per evaluation kind and sweep direction).
 __global__ void k_zero_u32(u32 *p) {
   if (threadIdx.x < QCOUNTERS) p[threadIdx.x] = 0u;
 }
@@ -1438,11 +1430,11 @@ hipError_t launch_faces_kernel(const FaceLaunch &L, const FastArgs &fa, hipStrea
 #define N6_FACES(P, W)                                                                        \
   hipLaunchKernelGGL((k_fast_faces<P, NV, W, true>), dim3(L.grid), dim3(W * 64), 0, s, ln, g,  \
                      dir, fa.selector, fa.prepared, fa.margin, q, mi, F, m, fa.scr.queue, qc,  \
-                     fa.scr.qcap, L.xcd)
+                     L.xcd)
   if (fa.selector != 0) {  // the other selectors: no classifier, one instantiation
     hipLaunchKernelGGL((k_fast_faces<2, NV, 4, false>), dim3(L.grid), dim3(256), 0, s, ln, g, dir,
                        fa.selector, fa.prepared, fa.margin, q, mi, F, m, fa.scr.queue, qc,
-                       fa.scr.qcap, L.xcd);
+                       L.xcd);
     return hipGetLastError();
   }
   // 2D sweeps: two waves per workgroup spill registers, so they take four
@@ -1491,8 +1483,8 @@ hipError_t launch_fast_faces1d(const Line1D &ln, const FastArgs &fa, const float
   }
   // The re-check flips labels with 32-bit atomics, so the classifier writes
   // into the workspace buffer (whole words) and the caller's copy follows.
-  // The re-check counter (qcount[0]) was cleared at the start of the call or
-  // by the previous stage's flux-difference kernel.
+  // The re-check counters were cleared at the start of the call or by the
+  // previous stage's flux-difference kernel.
   masks = fa.scr.masks;
   const bool recheck = fa.selector == 0 && fa.margin > 0.f;
   const Grid2D g0{};
@@ -1502,9 +1494,9 @@ hipError_t launch_fast_faces1d(const Line1D &ln, const FastArgs &fa, const float
   if (recheck) {
     Grid2D gd{};
     hipLaunchKernelGGL(k_recheck<1>, dim3(L.rgrid), dim3(TPB), 0, s, ln, gd, 0, fa.prepared, q,
-                       masks, fa.scr.queue, fa.scr.qcount, fa.scr.qcap, fa.scr.qflag);
+                       masks, fa.scr.queue, fa.scr.qcount, fa.scr.qflag);
     hipLaunchKernelGGL(k_fixup<1>, dim3(L.rgrid), dim3(TPB), 0, s, ln, gd, 0, q, masks,
-                       fa.scr.queue, fa.scr.qcount, fa.scr.qcap, fa.scr.qflag, F);
+                       fa.scr.queue, fa.scr.qcount, fa.scr.qflag, F);
     e = hipGetLastError();
   }
   if (e == hipSuccess && masks_out) e = copy_bytes(masks, masks_out, 3 * tf, s);
@@ -1537,16 +1529,16 @@ hipError_t launch_fast_faces2d(const Grid2D &g, const FastArgs &fa, const float 
     uint8_t *md = masks + (dir == 0 ? 0 : 4 * nfx);
     const uint8_t *mi = masks_in ? masks_in + (dir == 0 ? 0 : 4 * nfx) : nullptr;
     float *Fd = dir == 0 ? Fx : Gy;
-    u32 *qc = fa.scr.qcount + dir;  // one counter per sweep direction
+    u32 *qc = fa.scr.qcount + 8 * dir;  // eight counters (kinds) per sweep direction
     const Line1D l0{};
     const FaceLaunch L = face_launch(fa, (nf + 63) / 64);
     hipError_t e = launch_faces_kernel<4>(L, fa, s, l0, g, dir, q, mi, Fd, md, qc);
     if (e != hipSuccess) return e;
     if (recheck) {
       hipLaunchKernelGGL(k_recheck<2>, dim3(L.rgrid), dim3(TPB), 0, s, l0, g, dir, fa.prepared,
-                         q, md, fa.scr.queue, qc, fa.scr.qcap, fa.scr.qflag);
+                         q, md, fa.scr.queue, qc, fa.scr.qflag);
       hipLaunchKernelGGL(k_fixup<2>, dim3(L.rgrid), dim3(TPB), 0, s, l0, g, dir, q, md,
-                         fa.scr.queue, qc, fa.scr.qcap, fa.scr.qflag, Fd);
+                         fa.scr.queue, qc, fa.scr.qflag, Fd);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }

@@ -9,10 +9,10 @@
 
 namespace n6 {
 
-// Re-check counters in the workspace: 1D uses one per evaluation kind
-// (field * 2 + sign, six), 2D one per sweep direction; all are cleared
-// together.
-constexpr int QCOUNTERS = 8;
+// Re-check counters in the workspace, one per evaluation kind (field * 2 +
+// sign): 1D uses six, 2D eight per sweep direction (sweep d at 8 * d); all
+// are cleared together.
+constexpr int QCOUNTERS = 16;
 
 struct Line1D {            // a batch of independent 1D lines
   const int64_t *offsets;  // [dev] cell offsets [np+1]
