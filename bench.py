@@ -50,10 +50,11 @@ EVALS_PER_FACE = 6        # 3 characteristic fields x 2 split signs
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "euler1d_c2_256x4000_hbm_traffic.md")
 
 
-def _traffic_bytes():
-    """HBM bytes per launch of the fused kernel from the committed FETCH_SIZE /
-    WRITE_SIZE counter runs (scaled by the copy-kernel calibration), or None
-    when the kernel sources changed since the counters were taken."""
+def _traffic_record():
+    """The committed FETCH_SIZE / WRITE_SIZE record of the fused kernel (HBM
+    bytes per launch scaled by the copy-kernel calibration, and the launch
+    shape the counters were taken with), or None when the kernel sources
+    changed since the counters were taken."""
     import hashlib
     try:
         line = [ln for ln in open(TRAFFIC_RECORD) if ln.startswith("traffic-record:")][0]
@@ -62,7 +63,7 @@ def _traffic_bytes():
         for f in rec["sources"]:
             with open(os.path.join(ROOT, f), "rb") as fh:
                 h.update(fh.read())
-        return int(rec["bytes_per_launch"]) if h.hexdigest() == rec["source_sha256"] else None
+        return rec if h.hexdigest() == rec["source_sha256"] else None
     except (OSError, IndexError, KeyError, ValueError):
         return None
 
@@ -94,7 +95,7 @@ def _args():
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default: 200 RK3 steps for c2, as the workload runs; "
                          "20 graph replays for c4)")
-    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 20 / 3)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 400 / 30 / 5)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -106,7 +107,7 @@ def _args():
     if a.steps is None:
         a.steps = {"c2": 200, "c3": 20, "c4": 20}[a.workload]
     if a.warmup is None:
-        a.warmup = {"c2": 20, "c3": 3, "c4": 3}[a.workload]
+        a.warmup = {"c2": 400, "c3": 30, "c4": 5}[a.workload]  # about 0.1 s: steady clocks
     return a
 
 
@@ -245,10 +246,10 @@ def main():
     F = torch.zeros(3 * faces_stage, dtype=torch.float32, device=dev)
     native.neno6_face_fluxes(prob0, mlp0, q32, F, ws0)  # builds the face map once
     prob0.flags = native.KEEP_MAP                      # later calls launch only the kernel
-    for _ in range(200):  # back to steady clocks after the host-side work above
+    for _ in range(2000):  # about 0.1 s: back to steady clocks after the host-side work above
         native.neno6_face_fluxes(prob0, mlp0, q32, F, ws0)
     torch.cuda.synchronize()
-    reps = 50
+    reps = 200
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
@@ -260,7 +261,8 @@ def main():
     # state in, face fluxes and masks out (FP32 state, one mask byte per face and field)
     alg_bytes = 3 * int(off[-1]) * 4 + 3 * faces_stage * 4 + 3 * faces_stage
     achieved = flop / (k_ms / 1e3) / 1e12
-    traffic = _traffic_bytes()
+    trec = _traffic_record()
+    traffic = int(trec["bytes_per_launch"]) if trec else None
     hbm_gbs = (traffic or alg_bytes) / (k_ms / 1e3) / 1e9
     # share of evaluations the FP32 re-check takes at the stated margin
     mlpm, probm, wsm = make(native.BF16, MARGIN[2])
@@ -309,6 +311,7 @@ def main():
         # the binding resource of the fused kernel is VALU issue (the
         # instruction-counter profile); the MFMA and HBM fractions follow
         "roofline": dict(_alu(faces_stage, k_ms), traffic=traffic,
+                         traffic_launch_shape=trec.get("launch_shape") if trec else None,
                          kernel="k_fast_faces<BF16, 1D Euler>", kernel_ms=k_ms,
                          algorithmic_flop_per_launch=flop,
                          algorithmic_bytes_per_launch=alg_bytes),
@@ -390,10 +393,10 @@ def bench_batched(a, P, dev):
     # fused face kernel alone (margin 0) with the tuned shapes
     mlp0 = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=0.0)
     F = torch.zeros(3 * faces_stage, dtype=torch.float32, device=dev)
-    for _ in range(20):  # back to steady clocks after the host-side work above
+    for _ in range(150):  # about 0.1 s: back to steady clocks after the host-side work above
         native.neno6_face_fluxes(prob, mlp0, q32, F, ws)
     torch.cuda.synchronize()
-    reps = 10
+    reps = 20
     e0.record()
     for _ in range(reps):
         native.neno6_face_fluxes(prob, mlp0, q32, F, ws)
@@ -532,7 +535,7 @@ def bench_2d(a, P, dev):
     _, prob0, ws0 = make(native.BF16)
     prob0.set_tuning(shapes.get(native.BF16))
     F = torch.zeros(4 * faces_stage, dtype=torch.float32, device=dev)
-    for _ in range(20):
+    for _ in range(150):  # about 0.1 s: steady clocks
         native.neno6_face_fluxes(prob0, mlp0, q32, F, ws0)
     torch.cuda.synchronize()
     reps = 20

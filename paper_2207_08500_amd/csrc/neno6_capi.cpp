@@ -431,9 +431,16 @@ int32_t neno6_autotune(const neno6_problem *prob, const neno6_mlp *mlp, const vo
   if (ws_bytes < w.bytes) return NENO6_WORKSPACE_SMALL;
   if (int32_t c = begin_call(prob, mlp, w, stream)) return c;
   static const int waves[] = {2, 4, 8};
-  static const int blocks[] = {512, 1024, 2048, 4096, 16384, 65536};
+  static const int fixed_blocks[] = {512, 1024, 2048, 4096, 16384, 65536};
   static const int rblocks[] = {128, 512, 2048};
   const bool is2d = prob->equation == NENO6_EULER2D;
+  // workgroup caps of one and two full rounds of resident waves as well (the
+  // fused kernel holds three waves per SIMD, twelve per compute unit), which
+  // split the tiles evenly over the SIMDs
+  int dev = 0, n_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return NENO6_HIP_ERROR;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
@@ -448,14 +455,42 @@ int32_t neno6_autotune(const neno6_problem *prob, const neno6_mlp *mlp, const vo
                 : launch_fast_faces1d(line_of(prob, w.fmap), fa, (const float *)q, nullptr,
                                       nullptr, (float *)w.F, stream);
   };
+  // about 0.1 s of passes in the default shape first, so that every candidate
+  // is timed at steady clocks
+  {
+    float ms = 0.f;
+    hipError_t e = pass();
+    if (e == hipSuccess) e = hipEventRecord(e0, stream);
+    if (e == hipSuccess) e = pass();
+    if (e == hipSuccess) e = hipEventRecord(e1, stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    const int n_warm = ms > 0.f ? (int)std::min(2000.f, 100.f / ms) : 100;
+    for (int r = 0; r < n_warm && e == hipSuccess; ++r) e = pass();
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return NENO6_HIP_ERROR;
+    }
+  }
   float best_t = -1.f;
   neno6_tuning bt{};
   int32_t rc = NENO6_OK;
   for (int wv : waves) {
     if (is2d && wv == 2) continue;  // 2D sweeps run with 4 or 8 waves
-    for (int nb : blocks)
+    int blocks[8];
+    int nbl = 0;
+    for (int nb : fixed_blocks) blocks[nbl++] = nb;
+    for (int k = 1; k <= 2; ++k) {
+      const int nb = n_cu * 12 / wv * k;
+      bool dup = nb < 1 || nb > 65536;
+      for (int i = 0; i < nbl; ++i) dup = dup || blocks[i] == nb;
+      if (!dup) blocks[nbl++] = nb;
+    }
+    for (int ib = 0; ib < nbl; ++ib)
       for (int xcd = 0; xcd < 2 && rc == NENO6_OK; ++xcd)
         for (int rb : rblocks) {
+          const int nb = blocks[ib];
           fa.face_waves = wv;
           fa.face_blocks = nb;
           fa.recheck_blocks = rb;

@@ -2,16 +2,19 @@
 plain device copy of known size that calibrates the memory counters.
 
     rocprofv3 --pmc FETCH_SIZE --kernel-trace --output-format csv -d OUT -o run -- \
-        python3 paper_2207_08500_amd/profile_kernels.py
+        python3 paper_2207_08500_amd/profile_kernels.py --tuned
     rocprofv3 --pmc WRITE_SIZE --kernel-trace --output-format csv -d OUT -o run -- \
-        python3 paper_2207_08500_amd/profile_kernels.py
+        python3 paper_2207_08500_amd/profile_kernels.py --tuned
     rocprofv3 --kernel-trace --stats --output-format csv -d OUT -o run -- \
         python3 paper_2207_08500_amd/profile_kernels.py --steps 20
 
 Workload: 256 independent 1D Euler Riemann problems of 4000 cells (the
 benchmark's), FP32 state, BF16/FP16 classifier; the FP64 plain path once.
+With --tuned the face launches take the launch shape the autotuner picks for
+the BF16 pass (as the benchmark does; it prints the shape), else the library
+default.
 With --steps K: instead, K SSP-RK3 steps of the BF16 path with the re-check
-(margin 0.5), captured once in a HIP graph and replayed after 20 warm-up
+(margin 0.5), captured once in a HIP graph and replayed after 400 warm-up
 replays; a one-element torch fill right before the timed replays marks where
 they start in a kernel trace.
 """
@@ -34,6 +37,7 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--steps", type=int, default=0)
+    ap.add_argument("--tuned", action="store_true")
     a = ap.parse_args()
     native.load()
     dev = torch.device("cuda:0")
@@ -43,10 +47,20 @@ def main():
     faces = int(off[-1]) + 256
     if a.steps > 0:
         return step_replay(a.steps, P, q32, off, dx, dev)
+    shape = None
+    if a.tuned:
+        from paper_2207_08500_amd import autotune
+        prob = native.Problem(native.EULER1D, native.BF16, native.SEL_MLP, native.TRANSMISSIVE, off,
+                              dx, device=dev)
+        shape = autotune.tuned(prob, native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=0.5),
+                               q32, prob.workspace(dev))[0]
+        torch.cuda.synchronize()
+        print("launch shape %s" % shape, flush=True)
     for prec in (native.BF16, native.FP16):
         mlp = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=0.0)
         prob = native.Problem(native.EULER1D, prec, native.SEL_MLP, native.TRANSMISSIVE, off, dx,
                               device=dev)
+        prob.set_tuning(shape)
         ws = prob.workspace(dev)
         F = torch.zeros(3 * faces, dtype=torch.float32, device=dev)
         for _ in range(a.reps):
@@ -93,7 +107,7 @@ def step_replay(steps, P, q32, off, dx, dev):
     q.copy_(q32)
     t.zero_()
     st.zero_()
-    for _ in range(20):  # steady clocks
+    for _ in range(400):  # about 0.1 s: steady clocks
         g.replay()
     q.copy_(q32)
     t.zero_()
