@@ -222,8 +222,9 @@ int32_t neno6_recheck_count(const neno6_problem *prob, const void *ws, size_t ws
  * face pass (counter reset, classifier kernel, re-check, fix-up) of `prob`
  * on state q [dev] for every launch shape of a candidate set -- waves per
  * workgroup W in {2, 4, 8} (2D: {4, 8}) x workgroup caps {512, 1024, 2048,
- * 4096, 16384, 65536, and k * 12 * CUs / W for k = 1, 2 (whole rounds of
- * resident waves on the current device)} x XCD ordering {0, 1} x re-check
+ * 4096, 16384, 65536, and k * V * CUs / W for k = 1, 2, 3 (whole rounds of
+ * resident waves on the current device, V = 12 waves per CU in 1D, 8 in
+ * 2D)} x XCD ordering {0, 1} x re-check
  * workgroups {128, 512, 2048} -- with HIP events on `stream`, after about
  * 0.1 s of warm-up passes in the default shape, `reps` (1..1000) timed
  * passes each after one warm-up, and writes the fastest to *best [host] (its mean pass

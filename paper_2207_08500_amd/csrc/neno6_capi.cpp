@@ -157,6 +157,7 @@ Work carve_work(const neno6_problem *pb, void *ws) {
     w.scr.masks = c.take<uint8_t>(4 * faces);
     w.scr.queue = c.take<uint32_t>(8 * qfaces);
     w.scr.qflag = c.take<uint8_t>(8 * qfaces);
+    if (pb->equation == NENO6_EULER2D) w.scr.qnear = c.take<uint8_t>((qfaces + 3) / 4 * 4);
     w.scr.qcount = c.take<uint32_t>(QCOUNTERS);
     w.scr.qcap = (int64_t)(8 * qfaces);
   }
@@ -434,9 +435,9 @@ int32_t neno6_autotune(const neno6_problem *prob, const neno6_mlp *mlp, const vo
   static const int fixed_blocks[] = {512, 1024, 2048, 4096, 16384, 65536};
   static const int rblocks[] = {128, 512, 2048};
   const bool is2d = prob->equation == NENO6_EULER2D;
-  // workgroup caps of one and two full rounds of resident waves as well (the
-  // fused kernel holds three waves per SIMD, twelve per compute unit), which
-  // split the tiles evenly over the SIMDs
+  // workgroup caps of one, two and three full rounds of resident waves as
+  // well (the fused kernel holds three waves per SIMD in 1D, twelve per
+  // compute unit, and two in 2D), which split the tiles evenly over the SIMDs
   int dev = 0, n_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -478,11 +479,11 @@ int32_t neno6_autotune(const neno6_problem *prob, const neno6_mlp *mlp, const vo
   int32_t rc = NENO6_OK;
   for (int wv : waves) {
     if (is2d && wv == 2) continue;  // 2D sweeps run with 4 or 8 waves
-    int blocks[8];
+    int blocks[9];
     int nbl = 0;
     for (int nb : fixed_blocks) blocks[nbl++] = nb;
-    for (int k = 1; k <= 2; ++k) {
-      const int nb = n_cu * 12 / wv * k;
+    for (int k = 1; k <= 3; ++k) {
+      const int nb = n_cu * (is2d ? 8 : 12) / wv * k;
       bool dup = nb < 1 || nb > 65536;
       for (int i = 0; i < nbl; ++i) dup = dup || blocks[i] == nb;
       if (!dup) blocks[nbl++] = nb;

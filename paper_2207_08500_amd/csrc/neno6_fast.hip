@@ -308,9 +308,31 @@ N6_DEV void setup1d(const Line1D &ln, const float *__restrict__ q, int64_t g, fl
   }
 }
 
-// 2D Euler face f of sweep dir: s[2m + sign][6], R.
+// Roe state of a 2D face: normal and transverse velocity, sound speed,
+// enthalpy and kinetic energy; R follows from it and the sweep direction.
+struct Roe2 {
+  float nt, st, ct, Ht, q2;
+};
+
+// Right eigenvectors of the face in the (rho, rho u, rho v, E) ordering.
+N6_DEV void roe_R2(int dir, const Roe2 &w, float R[4][4]) {
+  // (rho, rho u_n, rho u_s, E) ordering, permuted into (rho, rho u, rho v, E)
+  const float Rn[4][4] = {{1.f, 1.f, 0.f, 1.f},
+                          {w.nt - w.ct, w.nt, 0.f, w.nt + w.ct},
+                          {w.st, w.st, 1.f, w.st},
+                          {__builtin_fmaf(-w.nt, w.ct, w.Ht), w.q2, w.st, __builtin_fmaf(w.nt, w.ct, w.Ht)}};
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    R[0][m] = Rn[0][m];
+    R[1][m] = dir == 0 ? Rn[1][m] : Rn[2][m];
+    R[2][m] = dir == 0 ? Rn[2][m] : Rn[1][m];
+    R[3][m] = Rn[3][m];
+  }
+}
+
+// 2D Euler face f of sweep dir: s[2m + sign][6] and the face's Roe state.
 N6_DEV void setup2d(const Grid2D &gd, int dir, const float *__restrict__ q, int64_t f,
-                    float s[8][6], float R[4][4]) {
+                    float s[8][6], Roe2 &rw) {
 #pragma clang fp contract(off)
   const int64_t cells = gd.nx * gd.ny;
   const float gm = (float)gd.gamma, g1 = gm - 1.f;
@@ -360,22 +382,11 @@ N6_DEV void setup2d(const Grid2D &gd, int dir, const float *__restrict__ q, int6
   const float b1 = (g1 * ic) * ic;
   const float b2 = b1 * q2;
   const float nc = nt * ic;
-  // (rho, rho u_n, rho u_s, E) ordering, permuted into (rho, rho u, rho v, E)
-  const float Rn[4][4] = {{1.f, 1.f, 0.f, 1.f},
-                          {nt - ct, nt, 0.f, nt + ct},
-                          {st, st, 1.f, st},
-                          {__builtin_fmaf(-nt, ct, Ht), q2, st, __builtin_fmaf(nt, ct, Ht)}};
+  rw = Roe2{nt, st, ct, Ht, q2};
   const float Ln[4][4] = {{0.5f * (b2 + nc), -0.5f * __builtin_fmaf(b1, nt, ic), (-0.5f * b1) * st, 0.5f * b1},
                           {1.f - b2, b1 * nt, b1 * st, -b1},
                           {-st, 0.f, 1.f, 0.f},
                           {0.5f * (b2 - nc), -0.5f * __builtin_fmaf(b1, nt, -ic), (-0.5f * b1) * st, 0.5f * b1}};
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    R[0][m] = Rn[0][m];
-    R[1][m] = dir == 0 ? Rn[1][m] : Rn[2][m];
-    R[2][m] = dir == 0 ? Rn[2][m] : Rn[1][m];
-    R[3][m] = Rn[3][m];
-  }
   // normal-direction fluxes of the six cells in the (rho, n, s, E) ordering
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
@@ -399,6 +410,13 @@ N6_DEV void setup2d(const Grid2D &gd, int dir, const float *__restrict__ q, int6
       s[2 * m + 1][5 - j] = 0.5f * __builtin_fmaf(-alpha, v, gg);
     }
   }
+}
+
+N6_DEV void setup2d(const Grid2D &gd, int dir, const float *__restrict__ q, int64_t f,
+                    float s[8][6], float R[4][4]) {
+  Roe2 rw;
+  setup2d(gd, dir, q, f, s, rw);
+  roe_R2(dir, rw, R);
 }
 
 template <int NV>
@@ -438,15 +456,19 @@ N6_DEV void enqueue_at(bool want, u32 entry, u32 *__restrict__ queue, u32 first,
 // the hardware places on one XCD (every 8th) take a contiguous run of tiles
 // (the host only sets it when gridDim.x is a multiple of 8).
 // 1D: three waves per SIMD (a few registers spill, the extra wave hides more
-// of the MFMA -> convert -> MFMA latency); 2D needs its registers: two.
+// of the MFMA -> convert -> MFMA latency); 2D needs its registers: two (at
+// three, 47 spilled registers made it 30 % slower).  2D stashes the face's
+// five Roe values instead of R (53 floats a lane) and rebuilds R for the
+// back-projection.
 template <int PREC, int NV, int W, bool MLP>
 __global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(NV == 3 ? 3 : 2)))
 k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict__ prepared,
              float margin, const float *__restrict__ q, const uint8_t *__restrict__ min,
              float *__restrict__ Fh, uint8_t *__restrict__ masks, u32 *__restrict__ queue,
-             u32 *__restrict__ qcount, int xcd) {
+             u32 *__restrict__ qcount, uint8_t *__restrict__ nearm, int xcd) {
   constexpr int NE = 2 * NV;
-  constexpr int NS = NE * 6 + NV * NV;
+  constexpr int NR = NV == 3 ? NV * NV : 5;  // R (1D) or the Roe state (2D)
+  constexpr int NS = NE * 6 + NR;
   __shared__ float stash[W][NS][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t nf = NV == 3 ? ln.faces() : (dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1));
@@ -461,11 +483,17 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
     const int64_t fc = valid ? f : nf - 1;
     u32 fx[NE][3];
     {
-      float s[NE][6], R[NV][NV];
-      if constexpr (NV == 3)
-        setup1d(ln, q, fc, s, R);
-      else
-        setup2d(gd, dir, q, fc, s, R);
+      float s[NE][6], R[NR];
+      if constexpr (NV == 3) {
+        float R3[3][3];
+        setup1d(ln, q, fc, s, R3);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) R[a] = R3[a / 3][a % 3];
+      } else {
+        Roe2 rw;
+        setup2d(gd, dir, q, fc, s, rw);
+        R[0] = rw.nt, R[1] = rw.st, R[2] = rw.ct, R[3] = rw.Ht, R[4] = rw.q2;
+      }
       if constexpr (MLP) {
 #pragma unroll
         for (int e = 0; e < NE; ++e) feature_pack<PREC>(s[e], fx[e][0], fx[e][1], fx[e][2]);
@@ -475,9 +503,7 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
 #pragma unroll
         for (int j = 0; j < 6; ++j) stash[wv][e * 6 + j][lane] = s[e][j];
 #pragma unroll
-      for (int a = 0; a < NV; ++a)
-#pragma unroll
-        for (int b = 0; b < NV; ++b) stash[wv][NE * 6 + a * NV + b][lane] = R[a][b];
+      for (int a = 0; a < NR; ++a) stash[wv][NE * 6 + a][lane] = R[a];
     }
     u32 sel[NE], near = 0u;
     // the classifier phase at raised wave priority: its MFMA -> convert
@@ -506,11 +532,19 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
     }
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (MLP) __builtin_amdgcn_s_setprio(0);
-    if constexpr (MLP) {  // queue the near-cutoff evaluations for the FP32 re-check
+    // Near-cutoff evaluations go to the FP32 re-check, one list per evaluation
+    // kind (NE x faces < 2^32).  1D (a few tenths of a percent of the
+    // evaluations queued): one wave-aggregated atomic per kind that has any.
+    // 2D (a few percent): the face's near bits are stored and the compaction
+    // kernel builds the lists with a few atomics per wave-range instead of
+    // one per tile (device-scope atomics cost about 40 us per sweep here).
+    if constexpr (MLP && NV == 3) {
 #pragma unroll
-      for (int e = 0; e < NE; ++e)  // one list per evaluation kind (NE x faces < 2^32)
+      for (int e = 0; e < NE; ++e)
         enqueue_at(valid && ((near >> e) & 1u), (u32)(fc * 8 + e), queue, (u32)e * (u32)nf,
                    qcount + e, (u32)nf);
+    } else if constexpr (MLP) {
+      if (valid) nearm[f] = (uint8_t)near;
     }
     float hs[NV], Fo[NV], R[NV][NV];
 #pragma unroll
@@ -523,10 +557,16 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
       }
       hs[m] = combine_fast(sp, sel[2 * m]) + combine_fast(sm, sel[2 * m + 1]);
     }
+    if constexpr (NV == 3) {
 #pragma unroll
-    for (int a = 0; a < NV; ++a)
+      for (int a = 0; a < NV; ++a)
 #pragma unroll
-      for (int b = 0; b < NV; ++b) R[a][b] = stash[wv][NE * 6 + a * NV + b][lane];
+        for (int b = 0; b < NV; ++b) R[a][b] = stash[wv][NE * 6 + a * NV + b][lane];
+    } else {
+      const Roe2 rw{stash[wv][NE * 6][lane], stash[wv][NE * 6 + 1][lane], stash[wv][NE * 6 + 2][lane],
+                    stash[wv][NE * 6 + 3][lane], stash[wv][NE * 6 + 4][lane]};
+      roe_R2(dir, rw, R);
+    }
     back_project<NV>(R, hs, Fo);
     if (valid) {
 #pragma unroll
@@ -534,6 +574,66 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
 #pragma unroll
       for (int m = 0; m < NV; ++m) masks[m * nf + f] = (uint8_t)(sel[2 * m] | (sel[2 * m + 1] << 4));
     }
+  }
+}
+
+// ---- 2D re-check lists from the near-cutoff bits ----------------------------------
+// One wave per contiguous range of 4-face words of nearm.  Pass 1 counts the
+// range's entries per kind; lane e reserves kind e's slots with one atomic;
+// pass 2 writes the entries (face * 8 + e into list e at queue[e * nf]).
+// Every face adds at most one entry per kind, so no list exceeds nf.
+constexpr int CMP_BLOCKS = 256;
+
+__global__ void __launch_bounds__(TPB) k_compact_near(const uint8_t *__restrict__ nearm, int64_t nf,
+                                                      u32 *__restrict__ queue, u32 *__restrict__ qcount) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = (nf + 3) / 4;
+  const int64_t wave = (blockIdx.x * (int64_t)TPB + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * TPB) >> 6;
+  const int64_t per = (nw + nwaves - 1) / nwaves;
+  const int64_t w0 = wave * per < nw ? wave * per : nw;
+  const int64_t w1 = w0 + per < nw ? w0 + per : nw;
+  const u32 *__restrict__ words = (const u32 *)nearm;
+  auto word_at = [&](int64_t w) -> u32 {  // w < nw; bytes past face nf - 1 masked
+    u32 v = words[w];
+    const int64_t rem = nf - 4 * w;
+    if (rem < 4) v &= (1u << (8 * rem)) - 1u;
+    return v;
+  };
+  u32 c[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+  for (int64_t w = w0 + lane; w < w1; w += 64) {
+    const u32 v = word_at(w);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) c[e] += (u32)__popc(v & (0x01010101u << e));
+  }
+  u32 mine = 0u;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) c[e] += __shfl_xor(c[e], o);
+    mine = lane == e ? c[e] : mine;
+  }
+  u32 base = 0u;
+  if (lane < 8 && mine != 0u) base = atomicAdd(qcount + lane, mine);
+  u32 run[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) run[e] = (u32)__builtin_amdgcn_readlane((int)base, e);
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (int64_t wb = w0; wb < w1; wb += 64) {  // wave-uniform loop
+    const int64_t w = wb + lane;
+    const u32 v = w < w1 ? word_at(w) : 0u;
+    if (__ballot(v != 0u) == 0) continue;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const bool b = (v >> (8 * k + e)) & 1u;
+        const uint64_t bal = __ballot(b);
+        if (bal == 0) continue;
+        const u32 off = run[e] + (u32)__popcll(bal & below);
+        if (b && (int64_t)off < nf) queue[(u32)e * (u32)nf + off] = (u32)((4 * w + k) * 8 + e);
+        run[e] += (u32)__popcll(bal);
+      }
   }
 }
 
@@ -1430,11 +1530,11 @@ hipError_t launch_faces_kernel(const FaceLaunch &L, const FastArgs &fa, hipStrea
 #define N6_FACES(P, W)                                                                        \
   hipLaunchKernelGGL((k_fast_faces<P, NV, W, true>), dim3(L.grid), dim3(W * 64), 0, s, ln, g,  \
                      dir, fa.selector, fa.prepared, fa.margin, q, mi, F, m, fa.scr.queue, qc,  \
-                     L.xcd)
+                     fa.scr.qnear, L.xcd)
   if (fa.selector != 0) {  // the other selectors: no classifier, one instantiation
     hipLaunchKernelGGL((k_fast_faces<2, NV, 4, false>), dim3(L.grid), dim3(256), 0, s, ln, g, dir,
                        fa.selector, fa.prepared, fa.margin, q, mi, F, m, fa.scr.queue, qc,
-                       L.xcd);
+                       fa.scr.qnear, L.xcd);
     return hipGetLastError();
   }
   // 2D sweeps: two waves per workgroup spill registers, so they take four
@@ -1535,6 +1635,8 @@ hipError_t launch_fast_faces2d(const Grid2D &g, const FastArgs &fa, const float 
     hipError_t e = launch_faces_kernel<4>(L, fa, s, l0, g, dir, q, mi, Fd, md, qc);
     if (e != hipSuccess) return e;
     if (recheck) {
+      hipLaunchKernelGGL(k_compact_near, dim3(CMP_BLOCKS), dim3(TPB), 0, s, fa.scr.qnear, nf,
+                         fa.scr.queue, qc);
       hipLaunchKernelGGL(k_recheck<2>, dim3(L.rgrid), dim3(TPB), 0, s, l0, g, dir, fa.prepared,
                          q, md, fa.scr.queue, qc, fa.scr.qflag);
       hipLaunchKernelGGL(k_fixup<2>, dim3(L.rgrid), dim3(TPB), 0, s, l0, g, dir, q, md,
