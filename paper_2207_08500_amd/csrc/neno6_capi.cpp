@@ -157,7 +157,7 @@ Work carve_work(const neno6_problem *pb, void *ws) {
     w.scr.masks = c.take<uint8_t>(4 * faces);
     w.scr.queue = c.take<uint32_t>(8 * qfaces);
     w.scr.qflag = c.take<uint8_t>(8 * qfaces);
-    if (pb->equation == NENO6_EULER2D) w.scr.qnear = c.take<uint8_t>((qfaces + 3) / 4 * 4);
+    if (pb->equation == NENO6_EULER2D) w.scr.qnear = c.take<uint8_t>((qfaces + 63) / 64 * 64);
     w.scr.qcount = c.take<uint32_t>(QCOUNTERS);
     w.scr.qcap = (int64_t)(8 * qfaces);
   }

@@ -14,7 +14,7 @@ struct FastScratch {
                         // evaluation kind e at e * faces
   uint8_t *qflag;       // per entry: label changed by the FP32 re-check
   uint8_t *qnear;       // 2D: near-cutoff bits of each face of the sweep (bit e: kind
-                        // e), 4-byte padded; the compaction kernel builds the lists
+                        // e), 64-byte padded; the compaction kernel builds the lists
   uint32_t *qcount;     // [QCOUNTERS] entries queued: 1D kind e at e, 2D sweep d kind e
                         // at 8 * d + e
   int64_t qcap;         // queue capacity

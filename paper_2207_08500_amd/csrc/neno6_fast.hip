@@ -477,6 +477,9 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
   const int64_t lb = xcd ? (int64_t)(blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8 : blockIdx.x;
   Wts w;
   if constexpr (MLP) load_wts<PREC>(prepared, lane, w);
+  // without the re-check nothing else clears this pass's counters: they then
+  // read 0 (the pass queues nothing)
+  if (!(MLP && margin > 0.f) && blockIdx.x == 0 && threadIdx.x < NE) qcount[threadIdx.x] = 0u;
   for (int64_t ch = lb * W + wv; ch < nchunk; ch += nb * W) {
     const int64_t f = ch * 64 + lane;
     const bool valid = f < nf;
@@ -578,62 +581,65 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
 }
 
 // ---- 2D re-check lists from the near-cutoff bits ----------------------------------
-// One wave per contiguous range of 4-face words of nearm.  Pass 1 counts the
-// range's entries per kind; lane e reserves kind e's slots with one atomic;
-// pass 2 writes the entries (face * 8 + e into list e at queue[e * nf]).
-// Every face adds at most one entry per kind, so no list exceeds nf.
-constexpr int CMP_BLOCKS = 256;
+// Each lane takes CMP_WPL consecutive 4-face words of nearm (64 bytes, one
+// 16-byte load at a time), counts its entries per kind, and a wave-wide
+// prefix sum per kind places them; lane e reserves kind e's slots for the
+// wave with one atomic; then every lane writes its own entries (face * 8 + e
+// into list e at queue[e * nf]).  Every face adds at most one entry per kind,
+// so no list exceeds nf.  nearm is padded to a multiple of 64 bytes; bytes
+// past face nf - 1 are masked.
+constexpr int CMP_WPL = 16;              // words per lane
+constexpr int CMP_WPW = 64 * CMP_WPL;    // words per wave
 
 __global__ void __launch_bounds__(TPB) k_compact_near(const uint8_t *__restrict__ nearm, int64_t nf,
                                                       u32 *__restrict__ queue, u32 *__restrict__ qcount) {
   const int lane = threadIdx.x & 63;
   const int64_t nw = (nf + 3) / 4;
   const int64_t wave = (blockIdx.x * (int64_t)TPB + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * TPB) >> 6;
-  const int64_t per = (nw + nwaves - 1) / nwaves;
-  const int64_t w0 = wave * per < nw ? wave * per : nw;
-  const int64_t w1 = w0 + per < nw ? w0 + per : nw;
-  const u32 *__restrict__ words = (const u32 *)nearm;
-  auto word_at = [&](int64_t w) -> u32 {  // w < nw; bytes past face nf - 1 masked
-    u32 v = words[w];
-    const int64_t rem = nf - 4 * w;
-    if (rem < 4) v &= (1u << (8 * rem)) - 1u;
-    return v;
-  };
-  u32 c[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
-  for (int64_t w = w0 + lane; w < w1; w += 64) {
-    const u32 v = word_at(w);
+  if (wave * CMP_WPW >= nw) return;  // wave-uniform
+  const int64_t wb = wave * CMP_WPW + (int64_t)lane * CMP_WPL;
+  u32 v[CMP_WPL];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) c[e] += (u32)__popc(v & (0x01010101u << e));
+  for (int i = 0; i < CMP_WPL; i += 4) {
+    const uint4 x = wb + i < nw ? *(const uint4 *)(nearm + 4 * (wb + i)) : make_uint4(0u, 0u, 0u, 0u);
+    v[i] = x.x, v[i + 1] = x.y, v[i + 2] = x.z, v[i + 3] = x.w;
   }
-  u32 mine = 0u;
+#pragma unroll
+  for (int i = 0; i < CMP_WPL; ++i) {
+    const int64_t rem = nf - 4 * (wb + i);  // faces in word i
+    v[i] = rem <= 0 ? 0u : (rem < 4 ? v[i] & ((1u << (8 * rem)) - 1u) : v[i]);
+  }
+  u32 pos[8], mine = 0u;
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
+    u32 c = 0u;
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) c[e] += __shfl_xor(c[e], o);
-    mine = lane == e ? c[e] : mine;
+    for (int i = 0; i < CMP_WPL; ++i) c += (u32)__popc(v[i] & (0x01010101u << e));
+    u32 inc = c;  // inclusive prefix sum over the lanes
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const u32 t = __shfl_up(inc, o);
+      inc += lane >= o ? t : 0u;
+    }
+    pos[e] = inc - c;
+    const u32 tot = (u32)__shfl(inc, 63);
+    mine = lane == e ? tot : mine;
   }
   u32 base = 0u;
   if (lane < 8 && mine != 0u) base = atomicAdd(qcount + lane, mine);
-  u32 run[8];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) run[e] = (u32)__builtin_amdgcn_readlane((int)base, e);
-  const uint64_t below = (1ull << lane) - 1ull;
-  for (int64_t wb = w0; wb < w1; wb += 64) {  // wave-uniform loop
-    const int64_t w = wb + lane;
-    const u32 v = w < w1 ? word_at(w) : 0u;
-    if (__ballot(v != 0u) == 0) continue;
+  for (int e = 0; e < 8; ++e) {
+    u32 p = pos[e] + (u32)__builtin_amdgcn_readlane((int)base, e);
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const bool b = (v >> (8 * k + e)) & 1u;
-        const uint64_t bal = __ballot(b);
-        if (bal == 0) continue;
-        const u32 off = run[e] + (u32)__popcll(bal & below);
-        if (b && (int64_t)off < nf) queue[(u32)e * (u32)nf + off] = (u32)((4 * w + k) * 8 + e);
-        run[e] += (u32)__popcll(bal);
+    for (int i = 0; i < CMP_WPL; ++i) {
+      u32 m = v[i] & (0x01010101u << e);
+      while (m) {
+        const int k = (__ffs(m) - 1) >> 3;
+        if ((int64_t)p < nf) queue[(u32)e * (u32)nf + p] = (u32)((4 * (wb + i) + k) * 8 + e);
+        ++p;
+        m &= m - 1u;
       }
+    }
   }
 }
 
@@ -1635,8 +1641,9 @@ hipError_t launch_fast_faces2d(const Grid2D &g, const FastArgs &fa, const float 
     hipError_t e = launch_faces_kernel<4>(L, fa, s, l0, g, dir, q, mi, Fd, md, qc);
     if (e != hipSuccess) return e;
     if (recheck) {
-      hipLaunchKernelGGL(k_compact_near, dim3(CMP_BLOCKS), dim3(TPB), 0, s, fa.scr.qnear, nf,
-                         fa.scr.queue, qc);
+      const int64_t cmp_waves = ((nf + 3) / 4 + CMP_WPW - 1) / CMP_WPW;
+      hipLaunchKernelGGL(k_compact_near, dim3((unsigned)((cmp_waves + WPB - 1) / WPB)), dim3(TPB), 0, s,
+                         fa.scr.qnear, nf, fa.scr.queue, qc);
       hipLaunchKernelGGL(k_recheck<2>, dim3(L.rgrid), dim3(TPB), 0, s, l0, g, dir, fa.prepared,
                          q, md, fa.scr.queue, qc, fa.scr.qflag);
       hipLaunchKernelGGL(k_fixup<2>, dim3(L.rgrid), dim3(TPB), 0, s, l0, g, dir, q, md,

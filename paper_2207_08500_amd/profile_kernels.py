@@ -15,8 +15,9 @@ the BF16 pass (as the benchmark does; it prints the shape), else the library
 default.
 With --steps K: instead, K SSP-RK3 steps of the BF16 path with the re-check
 (margin 0.5), captured once in a HIP graph and replayed after 400 warm-up
-replays; a one-element torch fill right before the timed replays marks where
-they start in a kernel trace.
+replays (40 with --2d); a one-element torch fill right before the timed
+replays marks where they start in a kernel trace.  --2d: the 2D Euler
+four-quadrant Riemann problem on 2048 x 2048 cells instead of the 1D batch.
 """
 import argparse
 import os
@@ -38,6 +39,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--steps", type=int, default=0)
     ap.add_argument("--tuned", action="store_true")
+    ap.add_argument("--2d", dest="two_d", action="store_true")
     a = ap.parse_args()
     native.load()
     dev = torch.device("cuda:0")
@@ -45,6 +47,8 @@ def main():
     q0, off, dx = inputs.riemann1d_batch(inputs.BASE_SEED, (4000,) * 256)
     q32 = torch.as_tensor(q0, dtype=torch.float32, device=dev).contiguous()
     faces = int(off[-1]) + 256
+    if a.steps > 0 and a.two_d:
+        return step_replay_2d(a.steps, P, dev)
     if a.steps > 0:
         return step_replay(a.steps, P, q32, off, dx, dev)
     shape = None
@@ -121,6 +125,47 @@ def step_replay(steps, P, q32, off, dx, dev):
     e1.record()
     torch.cuda.synchronize()
     print("profiled: %d graph-replayed BF16 RK3 steps, launch shape %s, %.4f ms per step"
+          % (steps, shape, e0.elapsed_time(e1) / steps))
+
+
+def step_replay_2d(steps, P, dev):
+    from paper_2207_08500_amd import autotune
+    nx = ny = 2048
+    q0 = inputs.riemann2d(inputs.BASE_SEED, nx, ny)
+    q32 = torch.as_tensor(q0, dtype=torch.float32, device=dev).contiguous().reshape(-1)
+    mlp = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=0.5)
+    prob = native.Problem(native.EULER2D, native.BF16, native.SEL_MLP, native.TRANSMISSIVE, nx=nx,
+                          ny=ny, dx2d=1.0 / nx, dy2d=1.0 / ny, device=dev)
+    ws = prob.workspace(dev)
+    shape = autotune.tuned(prob, mlp, q32, ws)[0]
+    q = q32.clone()
+    t = torch.zeros(1, dtype=torch.float64, device=dev)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        native.neno6_step(prob, mlp, q, 0.4, 1, t, st, ws)
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        native.neno6_step(prob, mlp, q, 0.4, 1, t, st, ws)
+    q.copy_(q32)
+    t.zero_()
+    st.zero_()
+    for _ in range(40):  # about 0.1 s: steady clocks
+        g.replay()
+    q.copy_(q32)
+    t.zero_()
+    st.zero_()
+    marker = torch.zeros(1, device=dev)
+    marker.fill_(1.0)  # the timed replays follow this dispatch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    print("profiled: %d graph-replayed 2D BF16 RK3 steps, launch shape %s, %.4f ms per step"
           % (steps, shape, e0.elapsed_time(e1) / steps))
 
 

@@ -143,6 +143,35 @@ def test_euler2d_rhs_against_oracle(ctx, prec):
 
 
 @pytest.mark.parametrize("prec", [2, 3])
+@pytest.mark.parametrize("nx,ny", [(67, 45), (130, 3)])
+def test_euler2d_recheck_lists_complete(ctx, prec, nx, ny):
+    """With a margin that every logit falls inside, the 2D re-check lists
+    hold every evaluation of both sweeps (eight per face, ragged grids), and
+    the labels then come from the FP32 re-check: FP32-level flip rate
+    against the FP64 oracle.  Margin 0 queues nothing."""
+    native, torch, P = ctx
+    q = inputs.riemann2d(29, nx, ny)
+    _, mx_o, my_o, _ = oracle.euler2d_rhs(q, 1 / nx, 1 / ny, 1.4, 1, P, oracle.SEL_MLP)
+    mo = np.concatenate([mx_o.ravel(), my_o.ravel()])
+    nfx, nfy = (nx + 1) * ny, nx * (ny + 1)
+    qg = dev(q, torch.float32)
+    for margin in (0.0, 1e30):
+        mlp = native.Mlp(dev(P), recheck_margin=margin)
+        prob = native.Problem(native.EULER2D, prec, native.SEL_MLP, 1, nx=nx, ny=ny, dx2d=1 / nx,
+                              dy2d=1 / ny)
+        ws = prob.workspace()
+        F = torch.zeros(4 * (nfx + nfy), dtype=torch.float32, device="cuda")
+        m = torch.zeros(prob.mask_count(), dtype=torch.uint8, device="cuda")
+        native.neno6_face_fluxes(prob, mlp, qg, F, ws, masks_out=m)
+        cnt = native.neno6_recheck_count(prob, ws)
+        assert cnt == ((0, 0) if margin == 0.0 else (8 * nfx, 8 * nfy))
+        if margin > 0.0:
+            flips = label_flip_rate(host(m), mo)
+            print("prec %d %dx%d all re-checked: flip rate %.3g" % (prec, nx, ny, flips))
+            assert flips < 1e-3
+
+
+@pytest.mark.parametrize("prec", [2, 3])
 def test_euler1d_steps_error(ctx, prec):
     """Twenty RK3 steps of a 1D Euler batch against the FP64 oracle run."""
     native, torch, P = ctx
