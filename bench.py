@@ -267,7 +267,7 @@ def main():
     # share of evaluations the FP32 re-check takes at the stated margin
     mlpm, probm, wsm = make(native.BF16, MARGIN[2])
     native.neno6_face_fluxes(probm, mlpm, q32, F, wsm)
-    n_recheck = native.neno6_recheck_count(probm, wsm)[0]
+    n_recheck = native.neno6_recheck_count(probm, mlpm, wsm)[0]
     recheck_frac = n_recheck / float(faces_stage * EVALS_PER_FACE)
 
     # ---- CPU oracle on a bounded sample ------------------------------------------------
@@ -525,7 +525,7 @@ def bench_2d(a, P, dev):
     mlpm, probm, wsm = make(native.BF16)
     native.neno6_face_fluxes(probm, mlpm, q32, torch.zeros(4 * faces_stage, dtype=torch.float32,
                                                             device=dev), wsm)
-    recheck_frac = sum(native.neno6_recheck_count(probm, wsm)) / float(faces_stage * EVALS_PER_FACE_2D)
+    recheck_frac = sum(native.neno6_recheck_count(probm, mlpm, wsm)) / float(faces_stage * EVALS_PER_FACE_2D)
     flip = float(np.unpackbits(x.reshape(-1, 1), axis=1).sum() / (8.0 * x.size))
     nfx = (nx + 1) * ny
     flip_face = float(np.concatenate([(x[:4 * nfx].reshape(4, -1) != 0).any(axis=0),

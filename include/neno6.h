@@ -212,11 +212,13 @@ int32_t neno6_face_fluxes(const neno6_problem *prob, const neno6_mlp *mlp, const
                           uint8_t *masks_out, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Diagnostic (synchronous: waits for `stream`): after neno6_face_fluxes in
- * BF16/FP16 mode, the number of classifier evaluations of each sweep
- * direction (count[0]: 1D or x, count[1]: y) that fell inside the re-check
- * margin and were re-evaluated in FP32.  count [host, 2 values]. */
-int32_t neno6_recheck_count(const neno6_problem *prob, const void *ws, size_t ws_bytes,
-                            uint32_t *count, hipStream_t stream);
+ * BF16/FP16 mode with `mlp`, the number of classifier evaluations of each
+ * sweep direction (count[0]: 1D or x, count[1]: y) that fell inside the
+ * re-check margin and were re-evaluated in FP32 (0 when mlp's margin is 0:
+ * the re-check does not run and its counters are not maintained).
+ * count [host, 2 values]. */
+int32_t neno6_recheck_count(const neno6_problem *prob, const neno6_mlp *mlp, const void *ws,
+                            size_t ws_bytes, uint32_t *count, hipStream_t stream);
 
 /* Autotuner (host-synchronous, not for graph capture): times the fused
  * face pass (counter reset, classifier kernel, re-check, fix-up) of `prob`

@@ -398,20 +398,22 @@ int32_t neno6_face_fluxes(const neno6_problem *prob, const neno6_mlp *mlp, const
   return hip_status(e);
 }
 
-int32_t neno6_recheck_count(const neno6_problem *prob, const void *ws, size_t ws_bytes,
-                            uint32_t *count, hipStream_t stream) {
+int32_t neno6_recheck_count(const neno6_problem *prob, const neno6_mlp *mlp, const void *ws,
+                            size_t ws_bytes, uint32_t *count, hipStream_t stream) {
   if (int32_t c = check_problem(prob)) return c;
-  if (!ws || !count) return NENO6_BAD_ARG;
+  if (!mlp || !ws || !count) return NENO6_BAD_ARG;
   if (prob->precision < NENO6_BF16) return NENO6_BAD_LAYOUT;
   const Work w = carve_work(prob, (void *)ws);
   if (ws_bytes < w.bytes) return NENO6_WORKSPACE_SMALL;
   if (hipStreamSynchronize(stream) != hipSuccess) return NENO6_HIP_ERROR;
+  count[0] = count[1] = 0;
+  // no re-check ran (its counters are then not maintained)
+  if (!(mlp->recheck_margin > 0.f) || prob->selector != NENO6_SEL_MLP) return NENO6_OK;
   uint32_t qc[QCOUNTERS];
   if (hipMemcpy(qc, w.scr.qcount, sizeof(qc), hipMemcpyDeviceToHost) != hipSuccess)
     return NENO6_HIP_ERROR;
   // one counter per evaluation kind (and 2D sweep direction)
   const int nk = prob->equation == NENO6_EULER2D ? 8 : 6;
-  count[0] = count[1] = 0;
   for (int k = 0; k < nk; ++k) {
     count[0] += qc[k];
     if (prob->equation == NENO6_EULER2D) count[1] += qc[8 + k];

@@ -477,9 +477,6 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
   const int64_t lb = xcd ? (int64_t)(blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8 : blockIdx.x;
   Wts w;
   if constexpr (MLP) load_wts<PREC>(prepared, lane, w);
-  // without the re-check nothing else clears this pass's counters: they then
-  // read 0 (the pass queues nothing)
-  if (!(MLP && margin > 0.f) && blockIdx.x == 0 && threadIdx.x < NE) qcount[threadIdx.x] = 0u;
   for (int64_t ch = lb * W + wv; ch < nchunk; ch += nb * W) {
     const int64_t f = ch * 64 + lane;
     const bool valid = f < nf;

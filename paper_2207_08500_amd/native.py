@@ -88,7 +88,7 @@ def load(path: str = LIB_PATH):
         lib.neno6_workspace_size.restype = sz
         lib.neno6_rhs.argtypes = [P(ProblemStruct), P(MlpStruct), vp, vp, vp, vp, vp, vp, sz, vp]
         lib.neno6_face_fluxes.argtypes = [P(ProblemStruct), P(MlpStruct), vp, vp, vp, vp, sz, vp]
-        lib.neno6_recheck_count.argtypes = [P(ProblemStruct), vp, sz, P(C.c_uint32), vp]
+        lib.neno6_recheck_count.argtypes = [P(ProblemStruct), P(MlpStruct), vp, sz, P(C.c_uint32), vp]
         lib.neno6_autotune.argtypes = [P(ProblemStruct), P(MlpStruct), vp, vp, sz, i32,
                                        P(TuningStruct), P(C.c_float), vp]
         lib.neno6_step.argtypes = [P(ProblemStruct), P(MlpStruct), vp, f64, i32, vp, vp, vp, sz, vp]
@@ -291,12 +291,13 @@ def neno6_face_fluxes(prob: Problem, mlp: Mlp | None, q: torch.Tensor, F: torch.
                                     _ptr(ws), ws.numel(), _stream(stream)), "neno6_face_fluxes")
 
 
-def neno6_recheck_count(prob: Problem, ws: torch.Tensor, stream=None):
-    """Evaluations re-checked in FP32 by the last neno6_face_fluxes call (x, y)."""
+def neno6_recheck_count(prob: Problem, mlp: Mlp, ws: torch.Tensor, stream=None):
+    """Evaluations re-checked in FP32 by the last neno6_face_fluxes call with
+    this mlp (x, y); (0, 0) when its margin is 0."""
     cnt = (C.c_uint32 * 2)()
     ps = prob.struct()
-    _check(load().neno6_recheck_count(C.byref(ps), _ptr(ws), ws.numel(), cnt, _stream(stream)),
-           "neno6_recheck_count")
+    _check(load().neno6_recheck_count(C.byref(ps), _mlp(mlp), _ptr(ws), ws.numel(), cnt,
+                                      _stream(stream)), "neno6_recheck_count")
     return int(cnt[0]), int(cnt[1])
 
 

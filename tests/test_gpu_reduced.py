@@ -163,7 +163,7 @@ def test_euler2d_recheck_lists_complete(ctx, prec, nx, ny):
         F = torch.zeros(4 * (nfx + nfy), dtype=torch.float32, device="cuda")
         m = torch.zeros(prob.mask_count(), dtype=torch.uint8, device="cuda")
         native.neno6_face_fluxes(prob, mlp, qg, F, ws, masks_out=m)
-        cnt = native.neno6_recheck_count(prob, ws)
+        cnt = native.neno6_recheck_count(prob, mlp, ws)
         assert cnt == ((0, 0) if margin == 0.0 else (8 * nfx, 8 * nfy))
         if margin > 0.0:
             flips = label_flip_rate(host(m), mo)
