@@ -159,7 +159,6 @@ Work carve_work(const neno6_problem *pb, void *ws) {
     w.scr.qflag = c.take<uint8_t>(8 * qfaces);
     if (pb->equation == NENO6_EULER2D) w.scr.qnear = c.take<uint8_t>((qfaces + 63) / 64 * 64);
     w.scr.qcount = c.take<uint32_t>(QCOUNTERS);
-    w.scr.qcap = (int64_t)(8 * qfaces);
   }
   w.bytes = c.used;
   return w;

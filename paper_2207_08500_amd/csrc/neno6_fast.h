@@ -17,7 +17,6 @@ struct FastScratch {
                         // e), 64-byte padded; the compaction kernel builds the lists
   uint32_t *qcount;     // [QCOUNTERS] entries queued: 1D kind e at e, 2D sweep d kind e
                         // at 8 * d + e
-  int64_t qcap;         // queue capacity
 };
 
 struct FastArgs {
