@@ -99,15 +99,16 @@ def _args():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", choices=("c2", "c3", "c4"), default="c2",
+    ap.add_argument("--workload", choices=("c2", "c3", "c4", "c5"), default="c2",
                     help="c2: 256 x 4000-cell batch (headline); c3: 2D Euler four-quadrant "
                          "Riemann problem on 2048 x 2048 cells; c4: 4096 uneven problems, "
-                         "ten RK3 steps per graph replay, autotuned launch shapes")
+                         "ten RK3 steps per graph replay, autotuned launch shapes; c5: "
+                         "classifier training, 2^24 samples, batch 65536")
     a = ap.parse_args()
     if a.steps is None:
-        a.steps = {"c2": 200, "c3": 20, "c4": 20}[a.workload]
-    if a.warmup is None:
-        a.warmup = {"c2": 400, "c3": 30, "c4": 5}[a.workload]  # about 0.1 s: steady clocks
+        a.steps = {"c2": 200, "c3": 20, "c4": 20, "c5": 179}[a.workload]
+    if a.warmup is None:  # about 0.1 s: steady clocks
+        a.warmup = {"c2": 400, "c3": 30, "c4": 5, "c5": 20}[a.workload]
     return a
 
 
@@ -129,6 +130,8 @@ def main():
         return bench_batched(a, P, dev)
     if a.workload == "c3":
         return bench_2d(a, P, dev)
+    if a.workload == "c5":
+        return bench_train(a, dev)
     q0, off, dx = inputs.riemann1d_batch(inputs.BASE_SEED, (N_CELLS,) * N_PROBLEMS)
     faces_stage = int(off[-1]) + N_PROBLEMS
     faces_step = 3 * faces_stage
@@ -580,6 +583,97 @@ def bench_2d(a, P, dev):
         "recheck_fraction": recheck_frac,
         "status": {"bf16": int(stb[0]), "fp64": int(st64b[0])},
         "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
+# algorithmic work of one training sample: forward 3104 MAC, the deltas of
+# layers 5..2 (32 + 128 + 512 + 2048 MAC; the input needs none) and the
+# weight gradients (3104 MAC): 8928 MAC = 17 856 flop
+TRAIN_FLOP_PER_SAMPLE = 2 * (3104 + 2720 + 3104)
+
+
+def bench_train(a, dev):
+    """C5: classifier training on 2^24 synthetic six-point samples (70 %
+    training, 30 % validation), batch 65536, BF16 MFMA forward and backward
+    with FP32 accumulation, FP64 master weights and Adam.  A step is one Adam
+    step of one mini-batch; the timed steps run as one call over
+    steps x 65536 samples of the epoch's order."""
+    import numpy as np
+    import torch
+
+    from paper_2207_08500_amd import inputs, native
+
+    n, batch = 1 << 24, 65536
+    s, y = inputs.classifier_samples(inputs.BASE_SEED, n)
+    n_train = int(0.7 * n)
+    steps = min(a.steps, n_train // batch)
+    sg = torch.as_tensor(s, dtype=torch.float32, device=dev).contiguous()
+    yg = torch.as_tensor(y, device=dev).contiguous()
+    P0 = inputs.mlp_init(inputs.BASE_SEED)
+    Pg = torch.as_tensor(P0, device=dev).clone()
+    m = torch.zeros(3228, dtype=torch.float64, device=dev)
+    v = torch.zeros(3228, dtype=torch.float64, device=dev)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    ws = torch.empty(native.neno6_train_workspace_size(batch), dtype=torch.uint8, device=dev)
+    perm0 = torch.as_tensor(inputs.epoch_permutation(inputs.BASE_SEED, 0, n_train), device=dev)
+    perm1 = torch.as_tensor(inputs.epoch_permutation(inputs.BASE_SEED, 1, n_train), device=dev)
+    step = native.neno6_classifier_train(Pg, m, v, 0, sg, yg, perm0[: a.warmup * batch].contiguous(),
+                                         batch, 1e-3, loss_out=loss, ws=ws)
+    torch.cuda.synchronize()
+    loss_warm = float(loss.item())
+    idx = perm1[: steps * batch].contiguous()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    step = native.neno6_classifier_train(Pg, m, v, step, sg, yg, idx, batch, 1e-3, loss_out=loss,
+                                         ws=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    value = steps * batch / (ms / 1e3)
+    vloss = torch.zeros(1, dtype=torch.float64, device=dev)
+    g = torch.zeros(3228, dtype=torch.float64, device=dev)
+    native.neno6_classifier_grad(Pg, sg[n_train:n_train + (1 << 20)].contiguous(),
+                                 yg[n_train:n_train + (1 << 20)].contiguous(), native.FP32, g, vloss)
+    torch.cuda.synchronize()
+    achieved = value * TRAIN_FLOP_PER_SAMPLE / 1e12
+    cpu = None
+    if not a.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        Pc, mc, vc = P0.copy(), np.zeros(3228), np.zeros(3228)
+        k = 4
+        c0 = time.perf_counter()
+        oracle.train(Pc, mc, vc, 0, s, y, inputs.epoch_permutation(inputs.BASE_SEED, 0, n_train)[: k * batch],
+                     batch, 1e-3)
+        t_cpu = time.perf_counter() - c0
+        cpu = {"value": k * batch / t_cpu, "unit": "samples/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": "%d Adam steps of batch %d on the same samples (%.1f s), FP64 C oracle"
+                         % (k, batch, t_cpu)}
+    out = {
+        "metric": "classifier training samples/s (BF16-MFMA forward + backward + Adam)",
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "C5 classifier training: 2^24 seeded six-point samples (half smooth, "
+                               "half step/kink), 70 %% training, batch %d, Adam lr 1e-3, BF16 MFMA "
+                               "with FP32 accumulation, FP64 master weights" % batch,
+                   "samples_per_step": batch},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_BF16,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_MFMA_BF16, "traffic": None,
+                     "flop_per_sample": TRAIN_FLOP_PER_SAMPLE},
+        "loss": {"after_warmup": loss_warm, "after_timed_steps": float(loss.item()),
+                 "validation": float(vloss.item())},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out))
 

@@ -160,21 +160,42 @@ k_grad_f32(const float *__restrict__ P32, const float *__restrict__ s, const uin
 
 // Sum of the block partials in block order; then either write the gradient
 // (mode 0) or take one Adam step on the FP64 master parameters (mode 1).
+// Deterministic two-level reduction of the partial rows (per-wave or
+// per-block gradients and losses, in a fixed order) into the gradient, then
+// Adam.  Level 1: RSPLIT contiguous row ranges per parameter (and the loss as
+// column NPARAM), in parallel; level 2 sums the RSPLIT values in order.
+constexpr int RSPLIT = 32;
+
 __global__ void __launch_bounds__(256)
-k_reduce_adam(int nblk, const float *__restrict__ part, const double *__restrict__ lpart,
-              double *__restrict__ P, double *__restrict__ am, double *__restrict__ av,
-              double *__restrict__ grad, double *__restrict__ loss, double loss_scale, int mode,
-              int accumulate_loss, double lr, double b1, double b2, double eps, double c1,
-              double c2) {
+k_reduce_rows(int nblk, const float *__restrict__ part, const double *__restrict__ lpart,
+              double *__restrict__ part2) {
+  const int i = blockIdx.x * 256 + threadIdx.x;  // parameter, NPARAM: the loss
+  const int sp = blockIdx.y;
+  if (i > NPARAM) return;
+  const int b0 = (int)((int64_t)nblk * sp / RSPLIT), b1 = (int)((int64_t)nblk * (sp + 1) / RSPLIT);
+  double g = 0.0;
+  if (i < NPARAM) {
+    for (int b = b0; b < b1; ++b) g += (double)part[(int64_t)b * NPARAM + i];
+  } else {
+    for (int b = b0; b < b1; ++b) g += lpart[b];
+  }
+  part2[(int64_t)sp * (NPARAM + 1) + i] = g;
+}
+
+__global__ void __launch_bounds__(256)
+k_reduce_adam(const double *__restrict__ part2, double *__restrict__ P, double *__restrict__ am,
+              double *__restrict__ av, double *__restrict__ grad, double *__restrict__ loss,
+              double loss_scale, int mode, int accumulate_loss, double lr, double b1, double b2,
+              double eps, double c1, double c2) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i == 0 && loss) {
     double a = 0.0;
-    for (int b = 0; b < nblk; ++b) a += lpart[b];
+    for (int b = 0; b < RSPLIT; ++b) a += part2[(int64_t)b * (NPARAM + 1) + NPARAM];
     *loss = (accumulate_loss ? *loss : 0.0) + a * loss_scale;
   }
   if (i >= NPARAM) return;
   double g = 0.0;
-  for (int b = 0; b < nblk; ++b) g += (double)part[(int64_t)b * NPARAM + i];
+  for (int b = 0; b < RSPLIT; ++b) g += part2[(int64_t)b * (NPARAM + 1) + i];
   if (mode == 0) {
     grad[i] = g;
     return;
@@ -196,6 +217,7 @@ struct TrainWs {
   void *tabs;
   float *part;
   double *lpart;
+  double *part2;  // [RSPLIT][NPARAM + 1] level-1 sums
   size_t bytes;
 };
 
@@ -219,6 +241,7 @@ TrainWs carve(void *ws, int32_t batch) {
   w.tabs = take(train_mfma_tab_bytes());
   w.part = (float *)take(sizeof(float) * NPARAM * (size_t)rows);
   w.lpart = (double *)take(sizeof(double) * (size_t)rows);
+  w.part2 = (double *)take(sizeof(double) * (size_t)RSPLIT * (NPARAM + 1));
   w.bytes = off;
   return w;
 }
@@ -253,9 +276,10 @@ hipError_t launch_train_batch(double *P, double *m, double *v, int64_t step, con
   hipError_t e = grad_pass(P, s, y, idx, mb, precision, w, &rows, st);
   if (e != hipSuccess) return e;
   const double c1 = 1.0 - pow(b1, (double)step), c2 = 1.0 - pow(b2, (double)step);
-  hipLaunchKernelGGL(k_reduce_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, st, rows, w.part,
-                     w.lpart, P, m, v, nullptr, loss_out, loss_scale, 1, first ? 0 : 1, lr, b1, b2,
-                     eps, c1, c2);
+  hipLaunchKernelGGL(k_reduce_rows, dim3((NPARAM + 1 + 255) / 256, RSPLIT), dim3(256), 0, st, rows,
+                     w.part, w.lpart, w.part2);
+  hipLaunchKernelGGL(k_reduce_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, st, w.part2, P, m, v,
+                     nullptr, loss_out, loss_scale, 1, first ? 0 : 1, lr, b1, b2, eps, c1, c2);
   return hipGetLastError();
 }
 
@@ -265,9 +289,11 @@ hipError_t launch_grad(const double *P, const float *s, const uint8_t *y, int64_
   int rows = 0;
   hipError_t e = grad_pass(P, s, y, nullptr, n, precision, w, &rows, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, st, rows, w.part,
-                     w.lpart, nullptr, nullptr, nullptr, grad, loss, 1.0 / (double)n, 0, 0, 0.0,
-                     0.0, 0.0, 0.0, 1.0, 1.0);
+  hipLaunchKernelGGL(k_reduce_rows, dim3((NPARAM + 1 + 255) / 256, RSPLIT), dim3(256), 0, st, rows,
+                     w.part, w.lpart, w.part2);
+  hipLaunchKernelGGL(k_reduce_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, st, w.part2, nullptr,
+                     nullptr, nullptr, grad, loss, 1.0 / (double)n, 0, 0, 0.0, 0.0, 0.0, 0.0, 1.0,
+                     1.0);
   return hipGetLastError();
 }
 
