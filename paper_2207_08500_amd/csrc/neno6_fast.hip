@@ -1086,8 +1086,8 @@ hipError_t copy_bytes(const uint8_t *a, uint8_t *b, int64_t n, hipStream_t s) {
 constexpr int PREP_THREADS = (TAB_REGS > F32_REGS ? TAB_REGS : F32_REGS) * 64;
 static_assert(NPARAM <= PREP_THREADS, "k_prepare covers every element");
 
-__global__ void __launch_bounds__(TPB) k_prepare(const double *__restrict__ P, char *__restrict__ prep) {
-  const int t = blockIdx.x * TPB + threadIdx.x;
+// Entry t of the prepared block (FP32 copy, FP32 and BF16/FP16 operand tables).
+N6_DEV void prepare_entry(const double *__restrict__ P, char *__restrict__ prep, int t) {
   if (t < NPARAM) ((float *)prep)[t] = (float)P[t];
   if (t < 4) ((float *)(prep + PREP_B5_OFF))[t] = (float)P[OB5 + t];
   if (t < F32_REGS * 64) ((float *)(prep + PREP_F32_OFF))[t] = f32_table_value(P, t / 64, t % 64);
@@ -1138,6 +1138,10 @@ __global__ void __launch_bounds__(TPB) k_prepare(const double *__restrict__ P, c
   ((u32 *)(prep + PREP_F16_OFF))[reg * 64 + lane] = wh;
 }
 
+__global__ void __launch_bounds__(TPB) k_prepare(const double *__restrict__ P, char *__restrict__ prep) {
+  prepare_entry(P, prep, blockIdx.x * TPB + threadIdx.x);
+}
+
 inline unsigned grid_for(int64_t items_per_wave_chunks) {
   const int64_t blocks = (items_per_wave_chunks + WPB - 1) / WPB;
   return (unsigned)(blocks < 2048 ? (blocks > 0 ? blocks : 1) : 2048);
@@ -1176,8 +1180,8 @@ FaceLaunch face_launch(const FastArgs &fa, int64_t nchunk) {
 // b1 comes out of the L1 product through the constant input slot.
 constexpr int BT_REGS = 24;  // backward A tables: L5 2, L4 2, L3 4, L2 16
 
-__global__ void __launch_bounds__(TPB) k_prepare_bwd(const double *__restrict__ P, u32 *__restrict__ tab) {
-  const int t = blockIdx.x * TPB + threadIdx.x;
+// Entry t of the backward operand tables.
+N6_DEV void prepare_bwd_entry(const double *__restrict__ P, u32 *__restrict__ tab, int t) {
   if (t >= BT_REGS * 64) return;
   const int reg = t / 64, lane = t % 64, i = lane % 32, h = lane / 32;
   float v[2];
@@ -1200,6 +1204,17 @@ __global__ void __launch_bounds__(TPB) k_prepare_bwd(const double *__restrict__ 
     v[q2] = (float)x;
   }
   tab[reg * 64 + lane] = pack2<2>(v[0], v[1]);
+}
+
+// Both tables of a training step in one launch: the first PREP_BLOCKS
+// workgroups build the forward block, the rest the backward tables.
+constexpr int PREP_BLOCKS = (PREP_THREADS + TPB - 1) / TPB;
+__global__ void __launch_bounds__(TPB) k_prepare_train(const double *__restrict__ P, char *__restrict__ prep,
+                                                       u32 *__restrict__ tab) {
+  if ((int)blockIdx.x < PREP_BLOCKS)
+    prepare_entry(P, prep, blockIdx.x * TPB + threadIdx.x);
+  else
+    prepare_bwd_entry(P, tab, ((int)blockIdx.x - PREP_BLOCKS) * TPB + threadIdx.x);
 }
 
 // Writes rows [0, nrows) of a C-layout FP32 tile (lane (j, h), register r =
@@ -1469,7 +1484,7 @@ k_grad_mfma(const void *__restrict__ prepared, const u32 *__restrict__ btab,
 // Gradient partials of one mini-batch on MFMA: one partial per wave.
 int train_mfma_waves(int64_t m) {
   const int64_t t = (m + 31) / 32;
-  const int64_t nw = t < 512 ? t : 512;
+  const int64_t nw = t < 1024 ? t : 1024;
   return (int)((nw + WPB - 1) / WPB * WPB);
 }
 size_t train_mfma_tab_bytes() { return PREP_BYTES + BT_REGS * 64 * 4; }
@@ -1479,8 +1494,8 @@ hipError_t launch_grad_mfma(const double *P, void *tabs, const float *s, const u
                             hipStream_t st) {
   char *prep = (char *)tabs;
   u32 *btab = (u32 *)(prep + PREP_BYTES);
-  hipLaunchKernelGGL(k_prepare, dim3((PREP_THREADS + TPB - 1) / TPB), dim3(TPB), 0, st, P, prep);
-  hipLaunchKernelGGL(k_prepare_bwd, dim3((BT_REGS * 64 + TPB - 1) / TPB), dim3(TPB), 0, st, P, btab);
+  hipLaunchKernelGGL(k_prepare_train, dim3(PREP_BLOCKS + (BT_REGS * 64 + TPB - 1) / TPB), dim3(TPB), 0,
+                     st, P, prep, btab);
   const int nw = train_mfma_waves(m);
   hipLaunchKernelGGL(k_grad_mfma, dim3(nw / WPB), dim3(TPB), 0, st, prep, btab, s, y, idx, m,
                      (float)(1.0 / (double)m), nw, part, lpart);
