@@ -158,13 +158,13 @@ k_grad_f32(const float *__restrict__ P32, const float *__restrict__ s, const uin
   }
 }
 
-// Sum of the block partials in block order; then either write the gradient
-// (mode 0) or take one Adam step on the FP64 master parameters (mode 1).
 // Deterministic two-level reduction of the partial rows (per-wave or
-// per-block gradients and losses, in a fixed order) into the gradient, then
-// Adam.  Level 1: RSPLIT contiguous row ranges per parameter (and the loss as
-// column NPARAM), in parallel; level 2 sums the RSPLIT values in order.
-constexpr int RSPLIT = 32;
+// per-block gradients and losses, in a fixed order) into the gradient, which
+// is then written (mode 0) or takes one Adam step on the FP64 master
+// parameters (mode 1).  Level 1: RSPLIT contiguous row ranges per parameter (and the loss as
+// column NPARAM), in parallel; level 2 sums the RSPLIT values in order (64: 32
+// and 128 were slower on batch 65536).
+constexpr int RSPLIT = 64;
 
 __global__ void __launch_bounds__(256)
 k_reduce_rows(int nblk, const float *__restrict__ part, const double *__restrict__ lpart,

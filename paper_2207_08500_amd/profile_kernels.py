@@ -2,17 +2,17 @@
 plain device copy of known size that calibrates the memory counters.
 
     rocprofv3 --pmc FETCH_SIZE --kernel-trace --output-format csv -d OUT -o run -- \
-        python3 paper_2207_08500_amd/profile_kernels.py --tuned
+        python3 paper_2207_08500_amd/profile_kernels.py --shape 4,768
     rocprofv3 --pmc WRITE_SIZE --kernel-trace --output-format csv -d OUT -o run -- \
-        python3 paper_2207_08500_amd/profile_kernels.py --tuned
+        python3 paper_2207_08500_amd/profile_kernels.py --shape 4,768
     rocprofv3 --kernel-trace --stats --output-format csv -d OUT -o run -- \
         python3 paper_2207_08500_amd/profile_kernels.py --steps 20
 
 Workload: 256 independent 1D Euler Riemann problems of 4000 cells (the
 benchmark's), FP32 state, BF16/FP16 classifier; the FP64 plain path once.
 With --tuned the face launches take the launch shape the autotuner picks for
-the BF16 pass (as the benchmark does; it prints the shape), else the library
-default.
+the BF16 pass (as the benchmark does; it prints the shape); with --shape W,B
+that many waves per workgroup and workgroups; else the library default.
 With --steps K: instead, K SSP-RK3 steps of the BF16 path with the re-check
 (margin 0.5), captured once in a HIP graph and replayed after 400 warm-up
 replays (40 with --2d); a one-element torch fill right before the timed
@@ -39,6 +39,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--steps", type=int, default=0)
     ap.add_argument("--tuned", action="store_true")
+    ap.add_argument("--shape", default=None, help="W,B: waves per workgroup, workgroups")
     ap.add_argument("--2d", dest="two_d", action="store_true")
     a = ap.parse_args()
     native.load()
@@ -52,7 +53,10 @@ def main():
     if a.steps > 0:
         return step_replay(a.steps, P, q32, off, dx, dev)
     shape = None
-    if a.tuned:
+    if a.shape:
+        w_, b_ = (int(x) for x in a.shape.split(","))
+        shape = {"face_waves": w_, "face_blocks": b_}
+    elif a.tuned:
         from paper_2207_08500_amd import autotune
         prob = native.Problem(native.EULER1D, native.BF16, native.SEL_MLP, native.TRANSMISSIVE, off,
                               dx, device=dev)
