@@ -580,9 +580,11 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
 // ---- 2D re-check lists from the near-cutoff bits ----------------------------------
 // Each lane takes CMP_WPL consecutive 4-face words of nearm (64 bytes, one
 // 16-byte load at a time), counts its entries per kind, and a wave-wide
-// prefix sum per kind places them; lane e reserves kind e's slots for the
-// wave with one atomic; then every lane writes its own entries (face * 8 + e
-// into list e at queue[e * nf]).  Every face adds at most one entry per kind,
+// prefix sum per kind places them; the workgroup reserves its slots of each
+// kind with one atomic (the waves take consecutive parts); then every lane
+// writes its own entries (face * 8 + e into list e at queue[e * nf]).  The
+// whole grid reaches the barriers: waves past the end count nothing.  Every
+// face adds at most one entry per kind,
 // so no list exceeds nf.  nearm is padded to a multiple of 64 bytes; bytes
 // past face nf - 1 are masked.
 constexpr int CMP_WPL = 16;              // words per lane
@@ -593,8 +595,7 @@ __global__ void __launch_bounds__(TPB) k_compact_near(const uint8_t *__restrict_
   const int lane = threadIdx.x & 63;
   const int64_t nw = (nf + 3) / 4;
   const int64_t wave = (blockIdx.x * (int64_t)TPB + threadIdx.x) >> 6;
-  if (wave * CMP_WPW >= nw) return;  // wave-uniform
-  const int64_t wb = wave * CMP_WPW + (int64_t)lane * CMP_WPL;
+  const int64_t wb = wave * CMP_WPW + (int64_t)lane * CMP_WPL;  // words past nw read as 0
   u32 v[CMP_WPL];
 #pragma unroll
   for (int i = 0; i < CMP_WPL; i += 4) {
@@ -622,8 +623,23 @@ __global__ void __launch_bounds__(TPB) k_compact_near(const uint8_t *__restrict_
     const u32 tot = (u32)__shfl(inc, 63);
     mine = lane == e ? tot : mine;
   }
+  // one atomic per kind and workgroup; the waves take consecutive parts
+  __shared__ u32 wtot[WPB][8], bbase[8];
+  const int wv = threadIdx.x >> 6;
+  if (lane < 8) wtot[wv][lane] = mine;
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    u32 t = 0u;
+#pragma unroll
+    for (int k = 0; k < WPB; ++k) t += wtot[k][threadIdx.x];
+    bbase[threadIdx.x] = t != 0u ? atomicAdd(qcount + threadIdx.x, t) : 0u;
+  }
+  __syncthreads();
   u32 base = 0u;
-  if (lane < 8 && mine != 0u) base = atomicAdd(qcount + lane, mine);
+  if (lane < 8) {
+    base = bbase[lane];
+    for (int k = 0; k < wv; ++k) base += wtot[k][lane];
+  }
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     u32 p = pos[e] + (u32)__builtin_amdgcn_readlane((int)base, e);
