@@ -33,10 +33,12 @@ PEAK_MFMA_BF16 = 2500.0  # TFLOP/s dense, MI355X
 PEAK_HBM_GBS = 8000.0    # HBM3E, MI355X
 # non-packed VALU lane-operations/s: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# algorithmic VALU work per 1D Euler face outside the MFMA contractions:
-# primitives 90, Roe 40, projection + split 180, speeds 20, features 80,
-# one operation per hidden activation 720, output bias + labels 50,
-# combine 180, back-projection 12
+# algorithmic VALU work per 1D Euler face outside the MFMA contractions,
+# from rounded item estimates (primitives 90, Roe 40, projection + split 180,
+# speeds 20, features 80, one operation per hidden activation 720, output
+# bias + labels 50, combine 180, back-projection 12: 1372) and a strict
+# one-operation-per-arithmetic-instruction count (1319); the value used lies
+# between them, so the VALU fraction carries about +-2 %
 VALU_OPS_PER_FACE = 1350
 # 2D Euler face (one sweep): primitives 100, Roe average and eigenvectors 60,
 # projection + split 240, speeds 30, features 104, hidden activations 960,
