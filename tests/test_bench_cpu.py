@@ -1,0 +1,48 @@
+"""Host-side checks of bench.py: the one-GPU contract, the roofline
+arithmetic and the committed HBM traffic record (no GPU needed)."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_valu_roofline_arithmetic():
+    # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+    assert abs(bench.PEAK_VALU_TOPS - 39.3216) < 1e-9
+    faces, ms = 1024256, 0.0582
+    r = bench._alu(faces, ms)
+    want = faces * bench.VALU_OPS_PER_FACE / (ms / 1e3) / 1e12
+    assert r["bound"] == "alu" and abs(r["achieved"] - want) < 1e-9
+    assert abs(r["frac"] - want / bench.PEAK_VALU_TOPS) < 1e-12
+    # the training roofline's algorithmic work: forward 3104 MAC, deltas of
+    # layers 5..2 (the input needs none), weight gradients 3104 MAC
+    macs = 6 * 64 + 64 * 32 + 32 * 16 + 16 * 8 + 8 * 4
+    assert macs == 3104
+    assert bench.TRAIN_FLOP_PER_SAMPLE == 2 * (macs + (macs - 6 * 64) + macs)
+
+
+def test_traffic_record_is_consistent():
+    """The committed FETCH/WRITE record parses; when its source hash matches,
+    its bytes per launch cover at least the algorithmic bytes of a launch
+    (state in, fluxes and masks out) and stay within a few times of them."""
+    import json
+    line = [ln for ln in open(bench.TRAFFIC_RECORD) if ln.startswith("traffic-record:")][0]
+    rec = json.loads(line.split(":", 1)[1])
+    scaled = (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024
+    assert abs(scaled - rec["bytes_per_launch"]) / rec["bytes_per_launch"] < 1e-3
+    alg = 3 * 1024000 * 4 + 3 * 1024256 * 4 + 3 * 1024256
+    assert alg <= rec["bytes_per_launch"] < 4 * alg
+    got = bench._traffic_record()
+    assert got is None or got["bytes_per_launch"] == rec["bytes_per_launch"]
