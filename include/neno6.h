@@ -251,8 +251,10 @@ int32_t neno6_step(const neno6_problem *prob, const neno6_mlp *mlp, void *q, dou
                    hipStream_t stream);
 
 /* ---- differentiation ------------------------------------------------------ */
-/* Adjoint of the advection right-hand side with respect to u at fixed masks
- * (the map u -> rhs is linear once the selection is fixed): ubar = A^T rbar.
+/* Adjoint of the advection right-hand side (eq. approximateEq with the
+ * reconstruction of eq. convex / eq. TENOweight_renormalize, Sec. 4.2) with
+ * respect to u at fixed masks: once the selection is fixed the map u -> rhs
+ * is linear, rhs = A u, and this returns ubar = A^T rbar.
  * masks [dev] as returned by neno6_rhs; rbar, ubar [dev] [total_cells].
  * Only NENO6_ADVECTION, one line. */
 int32_t neno6_rhs_adjoint(const neno6_problem *prob, const uint8_t *masks, const void *rbar,
