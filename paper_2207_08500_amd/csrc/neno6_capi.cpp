@@ -145,19 +145,18 @@ Work carve_work(const neno6_problem *pb, void *ws) {
                            : pb->total_cells + pb->n_problems;
     w.evals = c.take<char>(plain_eval_bytes(pb->equation == NENO6_EULER2D ? 8 : 6, nf, es));
   }
-  if (pb->precision >= NENO6_BF16) {
-    // masks of every face (x and y faces in 2D), re-check queue of at most
-    // one entry per evaluation (8 per face slot), its flags and counter
-    const size_t faces = pb->equation == NENO6_EULER2D
-                             ? (size_t)(pb->nx + 1) * pb->ny + (size_t)pb->nx * (pb->ny + 1)
-                             : (size_t)pb->total_cells + pb->n_problems;
-    const size_t qfaces = pb->equation == NENO6_EULER2D
-                              ? std::max((size_t)(pb->nx + 1) * pb->ny, (size_t)pb->nx * (pb->ny + 1))
-                              : faces;
+  if (pb->precision >= NENO6_BF16 && pb->equation == NENO6_EULER2D) {
+    // masks of the x and y faces, re-check queue of at most one entry per
+    // evaluation (8 per face slot), its flags, the near marks and counters
+    const size_t faces = (size_t)(pb->nx + 1) * pb->ny + (size_t)pb->nx * (pb->ny + 1);
+    const size_t qfaces = std::max((size_t)(pb->nx + 1) * pb->ny, (size_t)pb->nx * (pb->ny + 1));
     w.scr.masks = c.take<uint8_t>(4 * faces);
     w.scr.queue = c.take<uint32_t>(8 * qfaces);
     w.scr.qflag = c.take<uint8_t>(8 * qfaces);
-    if (pb->equation == NENO6_EULER2D) w.scr.qnear = c.take<uint8_t>((qfaces + 63) / 64 * 64);
+    w.scr.qnear = c.take<uint8_t>((qfaces + 63) / 64 * 64);
+    w.scr.qcount = c.take<uint32_t>(QCOUNTERS);
+  } else if (pb->precision >= NENO6_BF16) {
+    // 1D: the re-check runs inside the face pass; only its diagnostic counter
     w.scr.qcount = c.take<uint32_t>(QCOUNTERS);
   }
   w.bytes = c.used;
@@ -248,8 +247,31 @@ int32_t rhs_dispatch(const neno6_problem *pb, const neno6_mlp *mlp, const void *
       return hip_status(launch_fast_rhs2d(g, fa, (const float *)q, (float *)rhs, masks_in,
                                           masks_out, status, (float *)w.F, (float *)w.G, st, s));
     }
-    return hip_status(launch_fast_rhs1d(line_of(pb, w.fmap), fa, (const float *)q, (float *)rhs, masks_in,
-                                        masks_out, status, (float *)w.F, st, s));
+    const Line1D ln = line_of(pb, w.fmap);
+    Out1D out;
+    out.masks = masks_out;
+    if (pb->equation != NENO6_EULER1D) {  // scalar laws: face fluxes, then their difference
+      out.mode = OUT_FACES;
+      out.dst = (float *)w.F;
+      hipError_t e = launch_fast_pass1d(ln, fa, (const float *)q, masks_in, out, s);
+      if (e != hipSuccess) return NENO6_HIP_ERROR;
+      return hip_status(launch_diff1d<float>(ln, pb->equation, (const float *)w.F, (const float *)q,
+                                             (float *)rhs, st, status, s));
+    }
+    if (st) {
+      out.mode = OUT_STAGE;
+      out.stage = st->stage;
+      out.dst = (float *)st->out;
+      out.u0 = (const float *)st->u0;
+      out.dt = st->dt;
+      out.frozen = st->status;
+    } else {
+      out.mode = OUT_RHS;
+      out.dst = (float *)rhs;
+      out.status = status;
+      out.nrecheck = w.scr.qcount;
+    }
+    return hip_status(launch_fast_pass1d(ln, fa, (const float *)q, masks_in, out, s));
   }
   }
 }
@@ -355,10 +377,17 @@ int32_t neno6_face_fluxes(const neno6_problem *prob, const neno6_mlp *mlp, const
   hipError_t e;
   if (prob->precision >= NENO6_BF16) {
     const FastArgs fa = fast_args(prob, mlp, w);
-    e = is2d ? launch_fast_faces2d(grid_of(prob), fa, (const float *)q, nullptr, masks_out,
-                                   (float *)F, (float *)F + nfx, stream)
-             : launch_fast_faces1d(line_of(prob, w.fmap), fa, (const float *)q, nullptr, masks_out,
-                                   (float *)F, stream);
+    if (is2d) {
+      e = launch_fast_faces2d(grid_of(prob), fa, (const float *)q, nullptr, masks_out, (float *)F,
+                              (float *)F + nfx, stream);
+    } else {
+      Out1D out;
+      out.mode = OUT_FACES;
+      out.dst = (float *)F;
+      out.masks = masks_out;
+      out.nrecheck = w.scr.qcount;
+      e = launch_fast_pass1d(line_of(prob, w.fmap), fa, (const float *)q, nullptr, out, stream);
+    }
     return hip_status(e);
   }
   const int nv = nvar_of(prob->equation);
@@ -452,10 +481,13 @@ int32_t neno6_autotune(const neno6_problem *prob, const neno6_mlp *mlp, const vo
   auto pass = [&]() -> hipError_t {
     hipError_t e = launch_fast_reset(fa, stream);
     if (e != hipSuccess) return e;
-    return is2d ? launch_fast_faces2d(grid_of(prob), fa, (const float *)q, nullptr, nullptr,
-                                      (float *)w.F, (float *)w.G, stream)
-                : launch_fast_faces1d(line_of(prob, w.fmap), fa, (const float *)q, nullptr,
-                                      nullptr, (float *)w.F, stream);
+    if (is2d)
+      return launch_fast_faces2d(grid_of(prob), fa, (const float *)q, nullptr, nullptr, (float *)w.F,
+                                 (float *)w.G, stream);
+    Out1D out;
+    out.mode = OUT_FACES;
+    out.dst = (float *)w.F;
+    return launch_fast_pass1d(line_of(prob, w.fmap), fa, (const float *)q, nullptr, out, stream);
   };
   // about 0.1 s of passes in the default shape first, so that every candidate
   // is timed at steady clocks
@@ -535,9 +567,7 @@ int32_t neno6_step(const neno6_problem *prob, const neno6_mlp *mlp, void *q, dou
   if (!q || !t || !status || !ws || n_steps < 0 || !(cfl > 0)) return NENO6_BAD_ARG;
   const Work w = carve_work(prob, ws);
   if (ws_bytes < w.bytes) return NENO6_WORKSPACE_SMALL;
-  // 1D: every step's time-step kernel clears the re-check counters
-  const bool is1d_fast = prob->equation != NENO6_EULER2D && prob->precision >= NENO6_BF16;
-  if (int32_t c = begin_call(prob, mlp, w, stream, !(is1d_fast && n_steps > 0))) return c;
+  if (int32_t c = begin_call(prob, mlp, w, stream)) return c;
   const bool f64 = prob->precision == NENO6_FP64;
   for (int32_t it = 0; it < n_steps; ++it) {
     hipError_t e;
@@ -550,7 +580,7 @@ int32_t neno6_step(const neno6_problem *prob, const neno6_mlp *mlp, void *q, dou
       e = f64 ? launch_cfl1d<double>(ln, prob->equation, (const double *)q, cfl, w.dt, status, t,
                                      stream)
               : launch_cfl1d<float>(ln, prob->equation, (const float *)q, cfl, w.dt, status, t,
-                                    stream, is1d_fast ? w.scr.qcount : nullptr);
+                                    stream);
     }
     if (e != hipSuccess) return NENO6_HIP_ERROR;
     // u1 = stage 1 of q; u2 = stage 2 of u1; q = stage 3 of u2

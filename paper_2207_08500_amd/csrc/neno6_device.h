@@ -75,7 +75,10 @@ N6_DEV T combine_canonical(const T s[6], unsigned sel) {
 }
 
 // Branch-free combine for the fast paths (same weights, FP32, one reciprocal).
+// No implicit contraction here or in combine_pair: a face whose flux is
+// computed in two kernels (or twice in one) gives the same bits both times.
 N6_DEV float combine_fast(const float s[6], unsigned sel) {
+#pragma clang fp contract(off)
   float q0, q1, q2, q3;
   candidates<float>(s, q0, q1, q2, q3);
   const float w0 = (sel & 1u) ? Lin<float>::d0 : 0.f;
@@ -85,6 +88,12 @@ N6_DEV float combine_fast(const float s[6], unsigned sel) {
   const float D = (w0 + w1) + (w2 + w3);
   const float num = fmaf(w3, q3, fmaf(w2, q2, fmaf(w1, q1, w0 * q0)));
   return (sel & 15u) ? num * __builtin_amdgcn_rcpf(D) : s[2];
+}
+
+// h+ + h- of one characteristic field (the two split fluxes' reconstructions).
+N6_DEV float combine_pair(const float sp[6], unsigned selp, const float sm[6], unsigned selm) {
+#pragma clang fp contract(off)
+  return combine_fast(sp, selp) + combine_fast(sm, selm);
 }
 
 // Input scaling of the classifier (eq. normalizainput): divide by
@@ -305,6 +314,18 @@ N6_DEV void roe2d(const T qL[4], const T qR[4], T gamma, int dir, T L[4][4], T R
     L[m][vs] = Ln[m][2];
     L[m][3] = Ln[m][3];
   }
+}
+
+// RK3 stage update (Sec. 4.4, SSP-RK3):
+//   stage 1: u1 = u0 + dt L(u0)
+//   stage 2: u2 = 3/4 u0 + 1/4 (u1 + dt L(u1))
+//   stage 3: u  = 1/3 u0 + 2/3 (u2 + dt L(u2))
+template <typename T>
+N6_DEV T rk3(int stage, T us, T u0, T L, T dt) {
+  if (stage == 1) return fma_<T>(dt, L, us);
+  const T t = fma_<T>(dt, L, us);
+  if (stage == 2) return fma_<T>(T(0.25), t, T(0.75) * u0);
+  return fma_<T>(T(2) / T(3), t, (T(1) / T(3)) * u0);
 }
 
 template <typename T>

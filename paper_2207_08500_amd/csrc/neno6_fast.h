@@ -19,6 +19,22 @@ struct FastScratch {
                         // at 8 * d + e
 };
 
+// What the fused 1D Euler pass writes (one mode per launch).
+constexpr int OUT_RHS = 0;    // dst[3][cells] = -(F_{i+1/2} - F_{i-1/2}) / dx
+constexpr int OUT_STAGE = 1;  // dst[3][cells] = RK3 stage `stage` from q (= u_s) and u0
+constexpr int OUT_FACES = 2;  // dst[3][faces] = face fluxes
+struct Out1D {
+  int mode = OUT_RHS;
+  int stage = 1;
+  float *dst = nullptr;
+  const float *u0 = nullptr;        // OUT_STAGE: state at the start of the step
+  const double *dt = nullptr;       // OUT_STAGE: [lines] time step
+  const int32_t *frozen = nullptr;  // OUT_STAGE: [lines] nonzero = not advanced (dst = u0)
+  int32_t *status = nullptr;        // OUT_RHS: [lines] NONPHYSICAL marks, may be null
+  uint8_t *masks = nullptr;         // [3][faces] final labels, may be null
+  uint32_t *nrecheck = nullptr;     // evaluations re-checked in FP32 (diagnostic), may be null
+};
+
 struct FastArgs {
   int equation = 0, precision = 2, selector = 0;
   const void *prepared = nullptr;
@@ -42,17 +58,16 @@ hipError_t launch_fast_reconstruct(const void *prepared, int precision, float ma
 // Clears the re-check counters at the start of an API call (afterwards each
 // stage's flux-difference kernel clears them for the next stage).
 hipError_t launch_fast_reset(const FastArgs &fa, hipStream_t s);
-// Face fluxes with the MFMA classifier (+ re-check when the margin is > 0).
-hipError_t launch_fast_faces1d(const Line1D &ln, const FastArgs &fa, const float *q,
-                               const uint8_t *masks_in, uint8_t *masks_out, float *F,
-                               hipStream_t s);
+// 1D Euler: one fused pass per right-hand side -- set-up, MFMA classifier,
+// in-kernel FP32 re-check of near-cutoff evaluations, combine,
+// back-projection and the output of `out` (face fluxes, right-hand side or
+// RK3 stage).  Advection and Burgers: face fluxes only (out.mode ==
+// OUT_FACES; their flux difference is a separate kernel).
+hipError_t launch_fast_pass1d(const Line1D &ln, const FastArgs &fa, const float *q,
+                              const uint8_t *masks_in, const Out1D &out, hipStream_t s);
 hipError_t launch_fast_faces2d(const Grid2D &g, const FastArgs &fa, const float *q,
                                const uint8_t *masks_in, uint8_t *masks_out, float *Fx, float *Gy,
                                hipStream_t s);
-// Face fluxes with the MFMA classifier + re-check + flux difference/stage.
-hipError_t launch_fast_rhs1d(const Line1D &ln, const FastArgs &fa, const float *q, float *rhs,
-                             const uint8_t *masks_in, uint8_t *masks_out, int32_t *status,
-                             float *F, const Stage *st, hipStream_t s);
 hipError_t launch_fast_rhs2d(const Grid2D &g, const FastArgs &fa, const float *q, float *rhs,
                              const uint8_t *masks_in, uint8_t *masks_out, int32_t *status,
                              float *Fx, float *Gy, const Stage *st, hipStream_t s);

@@ -72,6 +72,82 @@ N6_DEV u32 relu2(u32 x) {
   return __builtin_bit_cast(u32, __builtin_elementwise_max(__builtin_bit_cast(s16x2, x), z));
 }
 template <int PREC> N6_DEV u32 relu_pack(float a, float b) { return relu2(pack2<PREC>(a, b)); }
+// Hidden activations of the inference tables: the conversion's clamp to
+// [0, 1] is the ReLU, because k_prepare scales every hidden neuron by an
+// a-priori bound on its pre-activation (ReLU(s z) = s ReLU(z) for s > 0, and
+// the scaled pre-activation never exceeds 1).  One instruction per pair of
+// activations instead of a conversion and a packed max.  The compiler emits
+// the clamped form only for FP16, so both are written as inline asm, one
+// block per accumulator tile, and the hazard waits the compiler would
+// otherwise insert are part of the block: before the first conversion the
+// MFMA that produced the tile must have written it back (NumPasses + 4 wait
+// states on gfx950: 20 after a 16-pass 32x32x8, 12 after an 8-pass
+// 32x32x16), and after the last one an MFMA may read the results only two
+// wait states later.  Outputs are early-clobber: the block reads its inputs
+// after it has written some outputs.
+//   act_block<PREC, NPAIR, WAIT>(c, first, o): o[p] = pack(c[first + 2p],
+//   c[first + 2p + 1]), activations applied.
+template <int PREC, int NPAIR, int WAIT> struct ActBlock;
+template <> struct ActBlock<2, 8, 20> {
+  static N6_DEV void run(const f32x16 &c, int first, u32 *o) {
+    asm volatile("s_nop 15\n\ts_nop 3\n\tv_cvt_pk_bf16_f32 %0, %8, %9 clamp\n\tv_cvt_pk_bf16_f32 %1, %10, %11 clamp\n\tv_cvt_pk_bf16_f32 %2, %12, %13 clamp\n\tv_cvt_pk_bf16_f32 %3, %14, %15 clamp\n\tv_cvt_pk_bf16_f32 %4, %16, %17 clamp\n\tv_cvt_pk_bf16_f32 %5, %18, %19 clamp\n\tv_cvt_pk_bf16_f32 %6, %20, %21 clamp\n\tv_cvt_pk_bf16_f32 %7, %22, %23 clamp\n\ts_nop 1"
+                 : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3]), "=&v"(o[4]), "=&v"(o[5]), "=&v"(o[6]), "=&v"(o[7])
+                 : "v"(c[first + 0]), "v"(c[first + 1]), "v"(c[first + 2]), "v"(c[first + 3]), "v"(c[first + 4]), "v"(c[first + 5]), "v"(c[first + 6]), "v"(c[first + 7]), "v"(c[first + 8]), "v"(c[first + 9]), "v"(c[first + 10]), "v"(c[first + 11]), "v"(c[first + 12]), "v"(c[first + 13]), "v"(c[first + 14]), "v"(c[first + 15]));
+  }
+};
+template <> struct ActBlock<2, 8, 12> {
+  static N6_DEV void run(const f32x16 &c, int first, u32 *o) {
+    asm volatile("s_nop 11\n\tv_cvt_pk_bf16_f32 %0, %8, %9 clamp\n\tv_cvt_pk_bf16_f32 %1, %10, %11 clamp\n\tv_cvt_pk_bf16_f32 %2, %12, %13 clamp\n\tv_cvt_pk_bf16_f32 %3, %14, %15 clamp\n\tv_cvt_pk_bf16_f32 %4, %16, %17 clamp\n\tv_cvt_pk_bf16_f32 %5, %18, %19 clamp\n\tv_cvt_pk_bf16_f32 %6, %20, %21 clamp\n\tv_cvt_pk_bf16_f32 %7, %22, %23 clamp\n\ts_nop 1"
+                 : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3]), "=&v"(o[4]), "=&v"(o[5]), "=&v"(o[6]), "=&v"(o[7])
+                 : "v"(c[first + 0]), "v"(c[first + 1]), "v"(c[first + 2]), "v"(c[first + 3]), "v"(c[first + 4]), "v"(c[first + 5]), "v"(c[first + 6]), "v"(c[first + 7]), "v"(c[first + 8]), "v"(c[first + 9]), "v"(c[first + 10]), "v"(c[first + 11]), "v"(c[first + 12]), "v"(c[first + 13]), "v"(c[first + 14]), "v"(c[first + 15]));
+  }
+};
+template <> struct ActBlock<2, 4, 12> {
+  static N6_DEV void run(const f32x16 &c, int first, u32 *o) {
+    asm volatile("s_nop 11\n\tv_cvt_pk_bf16_f32 %0, %4, %5 clamp\n\tv_cvt_pk_bf16_f32 %1, %6, %7 clamp\n\tv_cvt_pk_bf16_f32 %2, %8, %9 clamp\n\tv_cvt_pk_bf16_f32 %3, %10, %11 clamp\n\ts_nop 1"
+                 : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3])
+                 : "v"(c[first + 0]), "v"(c[first + 1]), "v"(c[first + 2]), "v"(c[first + 3]), "v"(c[first + 4]), "v"(c[first + 5]), "v"(c[first + 6]), "v"(c[first + 7]));
+  }
+};
+template <> struct ActBlock<2, 2, 12> {
+  static N6_DEV void run(const f32x16 &c, int first, u32 *o) {
+    asm volatile("s_nop 11\n\tv_cvt_pk_bf16_f32 %0, %2, %3 clamp\n\tv_cvt_pk_bf16_f32 %1, %4, %5 clamp\n\ts_nop 1"
+                 : "=&v"(o[0]), "=&v"(o[1])
+                 : "v"(c[first + 0]), "v"(c[first + 1]), "v"(c[first + 2]), "v"(c[first + 3]));
+  }
+};
+template <> struct ActBlock<3, 8, 20> {
+  static N6_DEV void run(const f32x16 &c, int first, u32 *o) {
+    asm volatile("s_nop 15\n\ts_nop 3\n\tv_cvt_pk_f16_f32 %0, %8, %9 clamp\n\tv_cvt_pk_f16_f32 %1, %10, %11 clamp\n\tv_cvt_pk_f16_f32 %2, %12, %13 clamp\n\tv_cvt_pk_f16_f32 %3, %14, %15 clamp\n\tv_cvt_pk_f16_f32 %4, %16, %17 clamp\n\tv_cvt_pk_f16_f32 %5, %18, %19 clamp\n\tv_cvt_pk_f16_f32 %6, %20, %21 clamp\n\tv_cvt_pk_f16_f32 %7, %22, %23 clamp\n\ts_nop 1"
+                 : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3]), "=&v"(o[4]), "=&v"(o[5]), "=&v"(o[6]), "=&v"(o[7])
+                 : "v"(c[first + 0]), "v"(c[first + 1]), "v"(c[first + 2]), "v"(c[first + 3]), "v"(c[first + 4]), "v"(c[first + 5]), "v"(c[first + 6]), "v"(c[first + 7]), "v"(c[first + 8]), "v"(c[first + 9]), "v"(c[first + 10]), "v"(c[first + 11]), "v"(c[first + 12]), "v"(c[first + 13]), "v"(c[first + 14]), "v"(c[first + 15]));
+  }
+};
+template <> struct ActBlock<3, 8, 12> {
+  static N6_DEV void run(const f32x16 &c, int first, u32 *o) {
+    asm volatile("s_nop 11\n\tv_cvt_pk_f16_f32 %0, %8, %9 clamp\n\tv_cvt_pk_f16_f32 %1, %10, %11 clamp\n\tv_cvt_pk_f16_f32 %2, %12, %13 clamp\n\tv_cvt_pk_f16_f32 %3, %14, %15 clamp\n\tv_cvt_pk_f16_f32 %4, %16, %17 clamp\n\tv_cvt_pk_f16_f32 %5, %18, %19 clamp\n\tv_cvt_pk_f16_f32 %6, %20, %21 clamp\n\tv_cvt_pk_f16_f32 %7, %22, %23 clamp\n\ts_nop 1"
+                 : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3]), "=&v"(o[4]), "=&v"(o[5]), "=&v"(o[6]), "=&v"(o[7])
+                 : "v"(c[first + 0]), "v"(c[first + 1]), "v"(c[first + 2]), "v"(c[first + 3]), "v"(c[first + 4]), "v"(c[first + 5]), "v"(c[first + 6]), "v"(c[first + 7]), "v"(c[first + 8]), "v"(c[first + 9]), "v"(c[first + 10]), "v"(c[first + 11]), "v"(c[first + 12]), "v"(c[first + 13]), "v"(c[first + 14]), "v"(c[first + 15]));
+  }
+};
+template <> struct ActBlock<3, 4, 12> {
+  static N6_DEV void run(const f32x16 &c, int first, u32 *o) {
+    asm volatile("s_nop 11\n\tv_cvt_pk_f16_f32 %0, %4, %5 clamp\n\tv_cvt_pk_f16_f32 %1, %6, %7 clamp\n\tv_cvt_pk_f16_f32 %2, %8, %9 clamp\n\tv_cvt_pk_f16_f32 %3, %10, %11 clamp\n\ts_nop 1"
+                 : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3])
+                 : "v"(c[first + 0]), "v"(c[first + 1]), "v"(c[first + 2]), "v"(c[first + 3]), "v"(c[first + 4]), "v"(c[first + 5]), "v"(c[first + 6]), "v"(c[first + 7]));
+  }
+};
+template <> struct ActBlock<3, 2, 12> {
+  static N6_DEV void run(const f32x16 &c, int first, u32 *o) {
+    asm volatile("s_nop 11\n\tv_cvt_pk_f16_f32 %0, %2, %3 clamp\n\tv_cvt_pk_f16_f32 %1, %4, %5 clamp\n\ts_nop 1"
+                 : "=&v"(o[0]), "=&v"(o[1])
+                 : "v"(c[first + 0]), "v"(c[first + 1]), "v"(c[first + 2]), "v"(c[first + 3]));
+  }
+};
+template <int PREC, int NPAIR, int WAIT>
+N6_DEV void act_block(const f32x16 &c, int first, u32 *o) {
+  ActBlock<PREC, NPAIR, WAIT>::run(c, first, o);
+}
 
 template <int PREC> N6_DEV f32x16 mma8(u32x2 a, u32x2 b, f32x16 c);
 template <> N6_DEV f32x16 mma8<2>(u32x2 a, u32x2 b, f32x16 c) {
@@ -140,31 +216,23 @@ N6_DEV u32x2 mlp_front(const Wts &w, u32x2 bin) {
   const f32x16 zero = {};
   const f32x16 c1a = mma8<PREC>(w.a1[0], bin, zero);
   const f32x16 c1b = mma8<PREC>(w.a1[1], bin, zero);
-  u32x4 h1a0, h1a1, h1b0, h1b1;
-#pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    h1a0[p] = relu_pack<PREC>(c1a[2 * p], c1a[2 * p + 1]);
-    h1a1[p] = relu_pack<PREC>(c1a[8 + 2 * p], c1a[9 + 2 * p]);
-    h1b0[p] = relu_pack<PREC>(c1b[2 * p], c1b[2 * p + 1]);
-    h1b1[p] = relu_pack<PREC>(c1b[8 + 2 * p], c1b[9 + 2 * p]);
-  }
-  f32x16 c2 = mma16<PREC>(w.a2[0], h1a0, w.b2);
-  c2 = mma16<PREC>(w.a2[1], h1a1, c2);
-  c2 = mma16<PREC>(w.a2[2], h1b0, c2);
-  c2 = mma16<PREC>(w.a2[3], h1b1, c2);
-  u32x4 h20, h21;
-#pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    h20[p] = relu_pack<PREC>(c2[2 * p], c2[2 * p + 1]);
-    h21[p] = relu_pack<PREC>(c2[8 + 2 * p], c2[9 + 2 * p]);
-  }
-  f32x16 c3 = mma16<PREC>(w.a3[0], h20, w.b3);
-  c3 = mma16<PREC>(w.a3[1], h21, c3);
-  u32x4 h3;
-#pragma unroll
-  for (int p = 0; p < 4; ++p) h3[p] = relu_pack<PREC>(c3[2 * p], c3[2 * p + 1]);
-  const f32x16 c4 = mma16<PREC>(w.a4, h3, w.b4);
-  return u32x2{relu_pack<PREC>(c4[0], c4[1]), relu_pack<PREC>(c4[2], c4[3])};
+  u32 h1a[8], h1b[8];
+  act_block<PREC, 8, 20>(c1a, 0, h1a);
+  act_block<PREC, 8, 20>(c1b, 0, h1b);
+  f32x16 c2 = mma16<PREC>(w.a2[0], u32x4{h1a[0], h1a[1], h1a[2], h1a[3]}, w.b2);
+  c2 = mma16<PREC>(w.a2[1], u32x4{h1a[4], h1a[5], h1a[6], h1a[7]}, c2);
+  c2 = mma16<PREC>(w.a2[2], u32x4{h1b[0], h1b[1], h1b[2], h1b[3]}, c2);
+  c2 = mma16<PREC>(w.a2[3], u32x4{h1b[4], h1b[5], h1b[6], h1b[7]}, c2);
+  u32 h2[8];
+  act_block<PREC, 8, 12>(c2, 0, h2);
+  f32x16 c3 = mma16<PREC>(w.a3[0], u32x4{h2[0], h2[1], h2[2], h2[3]}, w.b3);
+  c3 = mma16<PREC>(w.a3[1], u32x4{h2[4], h2[5], h2[6], h2[7]}, c3);
+  u32 h3[4];
+  act_block<PREC, 4, 12>(c3, 0, h3);
+  const f32x16 c4 = mma16<PREC>(w.a4, u32x4{h3[0], h3[1], h3[2], h3[3]}, w.b4);
+  u32 h4[2];
+  act_block<PREC, 2, 12>(c4, 0, h4);
+  return u32x2{h4[0], h4[1]};
 }
 
 // L1 B operand halves of one stencil: X = features 0..3, Y = features 4, 5,
@@ -222,6 +290,14 @@ N6_DEV u32 classify_wave(const Wts &w, const float s[6], float margin, float *z_
   return classify_packed<PREC>(w, x0, x1, y0, margin, z_out);
 }
 
+// The same pointer, hidden from the optimiser: loads through it are neither
+// hoisted out of a loop nor merged with earlier loads of the same address,
+// so weights reloaded after a flush are not kept live across it.
+N6_DEV const void *opaque(const void *p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
 N6_DEV const float *uniform_f32(const void *prepared) {
   const uint64_t v = (uint64_t)prepared;
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -235,25 +311,51 @@ N6_DEV unsigned classify_f32(const void *prepared, const float s[6]) {
 }
 
 // ---- per-face setup, FP32 -----------------------------------------------------
-// 1D Euler face g of the batch: split stencils s[2m + sign][6] ('-' mirrored)
-// and the right eigenvectors R.
-N6_DEV void setup1d(const Line1D &ln, const float *__restrict__ q, int64_t g, float s[6][6],
-                    float R[3][3]) {
+// Face k of line p of a 1D batch: the line's first cell o and length n.
+struct Face1 {
+  int p, n, k;
+  uint32_t o;
+};
+
+N6_DEV Face1 face1(const Line1D &ln, int64_t g) {
+  Face1 f;
+  f.p = line_of_face(ln, g);
+  const int64_t o = ln.offsets[f.p];
+  f.o = (uint32_t)o;
+  f.n = (int)(ln.offsets[f.p + 1] - o);
+  f.k = (int)(g - o - f.p);
+  return f;
+}
+
+// Roe average of a 1D face; the right eigenvectors R follow from it.
+struct Roe1 {
+  float ut, ct, Ht, q2;
+};
+
+N6_DEV void roe_R1(const Roe1 &w, float R[3][3]) {
+#pragma clang fp contract(off)
+  R[0][0] = 1.f;             R[0][1] = 1.f;  R[0][2] = 1.f;
+  R[1][0] = w.ut - w.ct;     R[1][1] = w.ut; R[1][2] = w.ut + w.ct;
+  R[2][0] = __builtin_fmaf(-w.ut, w.ct, w.Ht); R[2][1] = w.q2; R[2][2] = __builtin_fmaf(w.ut, w.ct, w.Ht);
+}
+
+// 1D Euler face: split stencils s[2m + sign][6] ('-' mirrored), the face's
+// Roe average, and the state qc and pressure pc of the cell to the right of
+// the face (cell k of the line; a ghost for the line's last face).
+N6_DEV void setup1d(const Line1D &ln, const float *__restrict__ q, const Face1 &fa, float s[6][6],
+                    Roe1 &rw, float qc[3], float &pc) {
   // No implicit contraction: every fused multiply-add is written out, so the
   // six cells of a stencil go through the same operations (equal cells give
-  // bitwise equal stencil values).
+  // bitwise equal stencil values) and a face computed twice gives the same bits.
 #pragma clang fp contract(off)
-  const int p = line_of_face(ln, g);
-  const int64_t o = ln.offsets[p];
-  const int n = (int)(ln.offsets[p + 1] - o), k = (int)(g - o - p);
+  const int n = fa.n, k = fa.k;
   const float gm = (float)ln.gamma, g1 = gm - 1.f;
   // uniform per-variable bases and 32-bit per-lane offsets (total < 2^29)
   const float *qv0 = q, *qv1 = q + ln.total, *qv2 = q + 2 * ln.total;
-  const uint32_t o32 = (uint32_t)o;
   float qs[6][3], lam[6][3], F[6][3];
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
-    const uint32_t ci = o32 + (uint32_t)ghost32(k - 3 + j, n, ln.bc);
+    const uint32_t ci = fa.o + (uint32_t)ghost32(k - 3 + j, n, ln.bc);
     qs[j][0] = qv0[ci];
     qs[j][1] = qv1[ci];
     qs[j][2] = qv2[ci];
@@ -272,6 +374,9 @@ N6_DEV void setup1d(const Line1D &ln, const float *__restrict__ q, int64_t g, fl
     F[j][1] = __builtin_fmaf(qs[j][1], uu[j], pp[j]);
     F[j][2] = (qs[j][2] + pp[j]) * uu[j];
   }
+#pragma unroll
+  for (int v = 0; v < 3; ++v) qc[v] = qs[3][v];
+  pc = pp[3];
   // Roe average of cells i (j = 2) and i+1 (j = 3)
   const float sL = __builtin_amdgcn_sqrtf(qs[2][0]), sR = __builtin_amdgcn_sqrtf(qs[3][0]);
   const float id = __builtin_amdgcn_rcpf(sL + sR);
@@ -285,9 +390,7 @@ N6_DEV void setup1d(const Line1D &ln, const float *__restrict__ q, int64_t g, fl
   const float b1 = (g1 * ic) * ic;
   const float b2 = b1 * q2;
   const float uc = ut * ic;
-  R[0][0] = 1.f;          R[0][1] = 1.f; R[0][2] = 1.f;
-  R[1][0] = ut - ct;      R[1][1] = ut;  R[1][2] = ut + ct;
-  R[2][0] = __builtin_fmaf(-ut, ct, Ht); R[2][1] = q2; R[2][2] = __builtin_fmaf(ut, ct, Ht);
+  rw = Roe1{ut, ct, Ht, q2};
   // H = L / 2: the split (g +- alpha v) / 2 then needs no final halving
   // (scaling by a power of two is exact, so the values are those of L)
   const float H[3][3] = {{0.25f * (b2 + uc), -0.25f * __builtin_fmaf(b1, ut, ic), 0.25f * b1},
@@ -421,6 +524,7 @@ N6_DEV void setup2d(const Grid2D &gd, int dir, const float *__restrict__ q, int6
 
 template <int NV>
 N6_DEV void back_project(const float R[NV][NV], const float hs[NV], float Fo[NV]) {
+#pragma clang fp contract(off)
 #pragma unroll
   for (int r = 0; r < NV; ++r) {
     float acc = 0.f;
@@ -430,48 +534,31 @@ N6_DEV void back_project(const float R[NV][NV], const float hs[NV], float Fo[NV]
   }
 }
 
-// Wave-aggregated append of a (face, eval) entry to the re-check list that
-// starts at queue[first] (capacity cap < 2^32).
-N6_DEV void enqueue_at(bool want, u32 entry, u32 *__restrict__ queue, u32 first,
-                       u32 *__restrict__ qcount, u32 cap) {
-  const uint64_t bal = __ballot(want);
-  if (bal == 0) return;
-  const int lane = threadIdx.x & 63;
-  const int leader = __ffsll((unsigned long long)bal) - 1;
-  u32 base = 0;
-  if (lane == leader) base = atomicAdd(qcount, (u32)__popcll(bal));
-  base = __shfl(base, leader);
-  const u32 off = base + (u32)__popcll(bal & ((1ull << lane) - 1));
-  if (want && off < cap) queue[first + off] = entry;
-}
-
-// ---- fused face kernel ------------------------------------------------------------
-// NV = 3: faces of a batch of 1D lines; NV = 4: faces of one 2D sweep.
-// One lane per face, 64 consecutive faces per wave and iteration.  The split
-// stencils and R of the lane's face wait in LDS (a lane-private slot, no
-// barrier) while the classifier runs, so that the live registers during the
-// MFMA phase are the weights, the packed features and one pair of tiles.
+// ---- fused face kernel, 2D sweeps --------------------------------------------------
+// Faces of one 2D sweep.  One lane per face, 64 consecutive faces per wave
+// and iteration.  The split stencils and the face's five Roe values wait in
+// LDS (a lane-private slot, no barrier) while the classifier runs, so that
+// the live registers during the MFMA phase are the weights, the packed
+// features and one pair of tiles; R is rebuilt for the back-projection.
 // W waves per workgroup; the workgroups loop over the tiles (grid-stride).
 // With xcd != 0 the workgroup numbering is permuted so that the workgroups
 // the hardware places on one XCD (every 8th) take a contiguous run of tiles
-// (the host only sets it when gridDim.x is a multiple of 8).
-// 1D: three waves per SIMD (a few registers spill, the extra wave hides more
-// of the MFMA -> convert -> MFMA latency); 2D needs its registers: two (at
-// three, 47 spilled registers made it 30 % slower).  2D stashes the face's
-// five Roe values instead of R (53 floats a lane) and rebuilds R for the
-// back-projection.
-template <int PREC, int NV, int W, bool MLP>
-__global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(NV == 3 ? 3 : 2)))
-k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict__ prepared,
-             float margin, const float *__restrict__ q, const uint8_t *__restrict__ min,
-             float *__restrict__ Fh, uint8_t *__restrict__ masks, u32 *__restrict__ queue,
-             u32 *__restrict__ qcount, uint8_t *__restrict__ nearm, int xcd) {
-  constexpr int NE = 2 * NV;
-  constexpr int NR = NV == 3 ? NV * NV : 5;  // R (1D) or the Roe state (2D)
+// (the host only sets it when gridDim.x is a multiple of 8).  Two waves per
+// SIMD (at three, 47 spilled registers made it 30 % slower).  Near-cutoff
+// evaluations (a few percent in 2D) are marked per face in nearm; the
+// compaction kernel builds the re-check lists from the marks with a few
+// atomics per wave-range instead of one per tile (device-scope atomics cost
+// about 40 us per sweep here).
+template <int PREC, int W, bool MLP>
+__global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(2)))
+k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared, float margin,
+             const float *__restrict__ q, const uint8_t *__restrict__ min, float *__restrict__ Fh,
+             uint8_t *__restrict__ masks, uint8_t *__restrict__ nearm, int xcd) {
+  constexpr int NV = 4, NE = 8, NR = 5;
   constexpr int NS = NE * 6 + NR;
   __shared__ float stash[W][NS][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t nf = NV == 3 ? ln.faces() : (dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1));
+  const int64_t nf = dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1);
   const int64_t nchunk = (nf + 63) / 64;
   const int64_t nb = gridDim.x;
   const int64_t lb = xcd ? (int64_t)(blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8 : blockIdx.x;
@@ -483,17 +570,10 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
     const int64_t fc = valid ? f : nf - 1;
     u32 fx[NE][3];
     {
-      float s[NE][6], R[NR];
-      if constexpr (NV == 3) {
-        float R3[3][3];
-        setup1d(ln, q, fc, s, R3);
-#pragma unroll
-        for (int a = 0; a < 9; ++a) R[a] = R3[a / 3][a % 3];
-      } else {
-        Roe2 rw;
-        setup2d(gd, dir, q, fc, s, rw);
-        R[0] = rw.nt, R[1] = rw.st, R[2] = rw.ct, R[3] = rw.Ht, R[4] = rw.q2;
-      }
+      float s[NE][6];
+      Roe2 rw;
+      setup2d(gd, dir, q, fc, s, rw);
+      const float R[NR] = {rw.nt, rw.st, rw.ct, rw.Ht, rw.q2};
       if constexpr (MLP) {
 #pragma unroll
         for (int e = 0; e < NE; ++e) feature_pack<PREC>(s[e], fx[e][0], fx[e][1], fx[e][2]);
@@ -508,7 +588,7 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
     u32 sel[NE], near = 0u;
     // the classifier phase at raised wave priority: its MFMA -> convert
     // chains are issued as soon as they are ready, and the other waves'
-    // set-up and combine work fills the gaps (measured: about 1 % faster)
+    // set-up and combine work fills the gaps
     if constexpr (MLP) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
@@ -531,19 +611,8 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
       }
     }
     __builtin_amdgcn_sched_barrier(0);
-    if constexpr (MLP) __builtin_amdgcn_s_setprio(0);
-    // Near-cutoff evaluations go to the FP32 re-check, one list per evaluation
-    // kind (NE x faces < 2^32).  1D (a few tenths of a percent of the
-    // evaluations queued): one wave-aggregated atomic per kind that has any.
-    // 2D (a few percent): the face's near bits are stored and the compaction
-    // kernel builds the lists with a few atomics per wave-range instead of
-    // one per tile (device-scope atomics cost about 40 us per sweep here).
-    if constexpr (MLP && NV == 3) {
-#pragma unroll
-      for (int e = 0; e < NE; ++e)
-        enqueue_at(valid && ((near >> e) & 1u), (u32)(fc * 8 + e), queue, (u32)e * (u32)nf,
-                   qcount + e, (u32)nf);
-    } else if constexpr (MLP) {
+    if constexpr (MLP) {
+      __builtin_amdgcn_s_setprio(0);
       if (valid) nearm[f] = (uint8_t)near;
     }
     float hs[NV], Fo[NV], R[NV][NV];
@@ -555,18 +624,11 @@ k_fast_faces(Line1D ln, Grid2D gd, int dir, int selector, const void *__restrict
         sp[j] = stash[wv][(2 * m) * 6 + j][lane];
         sm[j] = stash[wv][(2 * m + 1) * 6 + j][lane];
       }
-      hs[m] = combine_fast(sp, sel[2 * m]) + combine_fast(sm, sel[2 * m + 1]);
+      hs[m] = combine_pair(sp, sel[2 * m], sm, sel[2 * m + 1]);
     }
-    if constexpr (NV == 3) {
-#pragma unroll
-      for (int a = 0; a < NV; ++a)
-#pragma unroll
-        for (int b = 0; b < NV; ++b) R[a][b] = stash[wv][NE * 6 + a * NV + b][lane];
-    } else {
-      const Roe2 rw{stash[wv][NE * 6][lane], stash[wv][NE * 6 + 1][lane], stash[wv][NE * 6 + 2][lane],
-                    stash[wv][NE * 6 + 3][lane], stash[wv][NE * 6 + 4][lane]};
-      roe_R2(dir, rw, R);
-    }
+    const Roe2 rw{stash[wv][NE * 6][lane], stash[wv][NE * 6 + 1][lane], stash[wv][NE * 6 + 2][lane],
+                  stash[wv][NE * 6 + 3][lane], stash[wv][NE * 6 + 4][lane]};
+    roe_R2(dir, rw, R);
     back_project<NV>(R, hs, Fo);
     if (valid) {
 #pragma unroll
@@ -788,16 +850,6 @@ N6_DEV void mlp_f32_wave(const F32Wts &w, const float x[6], int h, float z[4]) {
   for (int k = 0; k < 4; ++k) z[k] = c5[k] + w.b5[k];
 }
 
-// Split stencil E (field E / 2, sign E % 2) of 1D face f: the full set-up
-// with the other fields' work left to dead-code elimination.
-template <int E>
-N6_DEV void stencil_one(const Line1D &ln, const float *__restrict__ q, int64_t f, float se[6]) {
-  float s[6][6], R[3][3];
-  setup1d(ln, q, f, s, R);
-#pragma unroll
-  for (int j = 0; j < 6; ++j) se[j] = s[E][j];
-}
-
 // Re-check entry slots: one list per evaluation kind (field x sign: six in
 // 1D, eight per 2D sweep), each padded to a whole number of waves' worth of
 // slots (EPW) and laid end to end, so the entries of one wave always share
@@ -844,6 +896,70 @@ N6_DEV bool queue_slot(const QueueSlots &qs, int64_t i, int64_t nf, int64_t &pos
   return j < c;
 }
 
+// The same FP32 network with each layer's operands loaded from the table
+// just before the layer (through opaque pointers, so the loads stay there):
+// at most one layer's weights hold registers, for callers that keep other
+// state live around it.
+N6_DEV void mlp_f32_stream(const void *prepared, int lane, const float x[6], int h, float z[4]) {
+  const f32x16 zero = {};
+  const float *base = (const float *)((const char *)prepared + PREP_F32_OFF);
+  const float *t = (const float *)opaque(base) + lane;
+  f32x16 c1a = zero, c1b = zero;
+#pragma unroll
+  for (int tt = 0; tt < 4; ++tt) {
+    const int k = 2 * tt + h;
+    float b = 0.f;
+#pragma unroll
+    for (int kk = 0; kk < 6; ++kk) b = k == kk ? x[kk] : b;
+    b = k == 6 ? 1.f : b;
+    c1a = mma32(t[(F32_A1 + tt) * 64], b, c1a);
+    c1b = mma32(t[(F32_A1 + 4 + tt) * 64], b, c1b);
+  }
+  c1a = relu16(c1a);
+  c1b = relu16(c1b);
+  t = (const float *)opaque(base) + lane;
+  f32x16 c2, c2o = zero;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) c2[r] = t[(F32_B2 + r) * 64];
+#pragma unroll
+  for (int tt = 0; tt < 16; tt += 2) {
+    c2 = mma32(t[(F32_A2 + tt) * 64], c1a[tt], c2);
+    c2o = mma32(t[(F32_A2 + tt + 1) * 64], c1a[tt + 1], c2o);
+  }
+#pragma unroll
+  for (int tt = 0; tt < 16; tt += 2) {
+    c2 = mma32(t[(F32_A2 + 16 + tt) * 64], c1b[tt], c2);
+    c2o = mma32(t[(F32_A2 + 16 + tt + 1) * 64], c1b[tt + 1], c2o);
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) c2[r] = fmaxf(c2[r] + c2o[r], 0.f);
+  t = (const float *)opaque(base) + lane;
+  f32x16 c3, c3o = zero;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) c3[r] = t[(F32_B3 + r) * 64];
+#pragma unroll
+  for (int tt = 0; tt < 16; tt += 2) {
+    c3 = mma32(t[(F32_A3 + tt) * 64], c2[tt], c3);
+    c3o = mma32(t[(F32_A3 + tt + 1) * 64], c2[tt + 1], c3o);
+  }
+#pragma unroll
+  for (int r = 0; r < 8; ++r) c3[r] = fmaxf(c3[r] + c3o[r], 0.f);
+  t = (const float *)opaque(base) + lane;
+  f32x16 c4;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) c4[r] = t[(F32_B4 + r) * 64];
+#pragma unroll
+  for (int tt = 0; tt < 8; ++tt) c4 = mma32(t[(F32_A4 + tt) * 64], c3[tt], c4);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) c4[r] = fmaxf(c4[r], 0.f);
+  f32x16 c5 = zero;
+#pragma unroll
+  for (int tt = 0; tt < 4; ++tt) c5 = mma32(t[(F32_A5 + tt) * 64], c4[tt], c5);
+  const float *b5 = (const float *)((const char *)prepared + PREP_B5_OFF);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) z[k] = c5[k] + b5[k];
+}
+
 // Split stencil E of 2D face f of sweep dir: the full set-up with the other
 // fields' work left to dead-code elimination.
 template <int E>
@@ -855,20 +971,19 @@ N6_DEV void stencil_one_2d(const Grid2D &gd, int dir, const float *__restrict__ 
   for (int j = 0; j < 6; ++j) se[j] = s[E][j];
 }
 
-// FP32 re-check of queued evaluations, 32 per wave on FP32 MFMA; flips the
-// stored nibble where the FP32 label differs and flags the entry.  The loop
-// is uniform over the wave (the MFMA products need every lane); slots past
-// the end or in a list's padding compute face 0 and store nothing.  The
-// evaluation kind is uniform over the wave, so the wave forms that one
-// stencil.
-template <int DIM>
+// FP32 re-check of queued evaluations of a 2D sweep, 32 per wave on FP32
+// MFMA; flips the stored nibble where the FP32 label differs and flags the
+// entry.  The loop is uniform over the wave (the MFMA products need every
+// lane); slots past the end or in a list's padding compute face 0 and store
+// nothing.  The evaluation kind is uniform over the wave, so the wave forms
+// that one stencil.
 __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2)))
-k_recheck(Line1D ln, Grid2D gd, int dir, const void *__restrict__ prepared,
-          const float *__restrict__ q, uint8_t *__restrict__ masks, const u32 *__restrict__ queue,
-          const u32 *__restrict__ qcount, uint8_t *__restrict__ qflag) {
+k_recheck2d(Grid2D gd, int dir, const void *__restrict__ prepared, const float *__restrict__ q,
+            uint8_t *__restrict__ masks, const u32 *__restrict__ queue,
+            const u32 *__restrict__ qcount, uint8_t *__restrict__ qflag) {
   constexpr int EPB = WPB * EPW;  // slots per workgroup and pass
-  const int64_t nf = DIM == 1 ? ln.faces() : (dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1));
-  const QueueSlots qs = queue_slots<DIM>(qcount, nf);
+  const int64_t nf = dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1);
+  const QueueSlots qs = queue_slots<2>(qcount, nf);
   if (blockIdx.x * (int64_t)EPB >= qs.total) return;  // block-uniform: nothing queued for this block
   const int lane = threadIdx.x & 63, j = lane & 31, h = lane >> 5;
   F32Wts w;
@@ -878,34 +993,23 @@ k_recheck(Line1D ln, Grid2D gd, int dir, const void *__restrict__ prepared,
     const int64_t i = i0 + j;
     int64_t pos = 0;
     int e = 0;
-    const bool ok = i < qs.total && queue_slot<DIM>(qs, i, nf, pos, e);
+    const bool ok = i < qs.total && queue_slot<2>(qs, i, nf, pos, e);
     const u32 ent = ok ? queue[pos] : 0u;
     const int64_t f = ent >> 3;
     if (ok) e = ent & 7;
     float se[6];
     int ew;
     int64_t iw;
-    queue_slot<DIM>(qs, i0, nf, iw, ew);  // the wave's kind (slot i0 < total)
-    if constexpr (DIM == 1) {  // only the queued evaluation's stencil is formed
-      switch (__builtin_amdgcn_readfirstlane(ew)) {
-      case 0: stencil_one<0>(ln, q, f, se); break;
-      case 1: stencil_one<1>(ln, q, f, se); break;
-      case 2: stencil_one<2>(ln, q, f, se); break;
-      case 3: stencil_one<3>(ln, q, f, se); break;
-      case 4: stencil_one<4>(ln, q, f, se); break;
-      default: stencil_one<5>(ln, q, f, se); break;
-      }
-    } else {
-      switch (__builtin_amdgcn_readfirstlane(ew)) {
-      case 0: stencil_one_2d<0>(gd, dir, q, f, se); break;
-      case 1: stencil_one_2d<1>(gd, dir, q, f, se); break;
-      case 2: stencil_one_2d<2>(gd, dir, q, f, se); break;
-      case 3: stencil_one_2d<3>(gd, dir, q, f, se); break;
-      case 4: stencil_one_2d<4>(gd, dir, q, f, se); break;
-      case 5: stencil_one_2d<5>(gd, dir, q, f, se); break;
-      case 6: stencil_one_2d<6>(gd, dir, q, f, se); break;
-      default: stencil_one_2d<7>(gd, dir, q, f, se); break;
-      }
+    queue_slot<2>(qs, i0, nf, iw, ew);  // the wave's kind (slot i0 < total)
+    switch (__builtin_amdgcn_readfirstlane(ew)) {  // only that stencil is formed
+    case 0: stencil_one_2d<0>(gd, dir, q, f, se); break;
+    case 1: stencil_one_2d<1>(gd, dir, q, f, se); break;
+    case 2: stencil_one_2d<2>(gd, dir, q, f, se); break;
+    case 3: stencil_one_2d<3>(gd, dir, q, f, se); break;
+    case 4: stencil_one_2d<4>(gd, dir, q, f, se); break;
+    case 5: stencil_one_2d<5>(gd, dir, q, f, se); break;
+    case 6: stencil_one_2d<6>(gd, dir, q, f, se); break;
+    default: stencil_one_2d<7>(gd, dir, q, f, se); break;
     }
     float x[6], z[4];
     features<float>(se, x);
@@ -923,46 +1027,358 @@ k_recheck(Line1D ln, Grid2D gd, int dir, const void *__restrict__ prepared,
   }
 }
 
-// Recomputes the flux of every face whose label the re-check changed.
-template <int DIM>
+// Recomputes the flux of every 2D face whose label the re-check changed.
 __global__ void __launch_bounds__(TPB)
-k_fixup(Line1D ln, Grid2D gd, int dir, const float *__restrict__ q,
-        const uint8_t *__restrict__ masks, const u32 *__restrict__ queue,
-        const u32 *__restrict__ qcount, const uint8_t *__restrict__ qflag,
-        float *__restrict__ Fh) {
-  constexpr int NV = DIM == 1 ? 3 : 4;
-  const int64_t nf = DIM == 1 ? ln.faces() : (dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1));
-  const QueueSlots qs = queue_slots<DIM>(qcount, nf);
+k_fixup2d(Grid2D gd, int dir, const float *__restrict__ q, const uint8_t *__restrict__ masks,
+          const u32 *__restrict__ queue, const u32 *__restrict__ qcount,
+          const uint8_t *__restrict__ qflag, float *__restrict__ Fh) {
+  const int64_t nf = dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1);
+  const QueueSlots qs = queue_slots<2>(qcount, nf);
   for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < qs.total; i += (int64_t)gridDim.x * TPB) {
     int64_t pos;
     int e;
-    if (!queue_slot<DIM>(qs, i, nf, pos, e) || !qflag[pos]) continue;
+    if (!queue_slot<2>(qs, i, nf, pos, e) || !qflag[pos]) continue;
     const int64_t f = queue[pos] >> 3;
     float s[8][6], R[4][4], hs[4], Fo[4];
-    if (DIM == 1) {
-      float R3[3][3];
-      setup1d(ln, q, f, *(float(*)[6][6])s, R3);
+    setup2d(gd, dir, q, f, s, R);
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) R[a][b] = R3[a][b];
-    } else {
-      setup2d(gd, dir, q, f, s, R);
-    }
-#pragma unroll
-    for (int m = 0; m < NV; ++m) {
+    for (int m = 0; m < 4; ++m) {
       const u32 mb = masks[(int64_t)m * nf + f];
-      hs[m] = combine_fast(s[2 * m], mb & 15u) + combine_fast(s[2 * m + 1], mb >> 4);
+      hs[m] = combine_pair(s[2 * m], mb & 15u, s[2 * m + 1], mb >> 4);
     }
+    back_project<4>(R, hs, Fo);
 #pragma unroll
-    for (int r = 0; r < NV; ++r) {
-      float acc = 0.f;
+    for (int r = 0; r < 4; ++r) Fh[(int64_t)r * nf + f] = Fo[r];
+  }
+}
+
+// ---- 1D Euler: one fused pass per right-hand side -------------------------------------
+// Tiles of 64 consecutive faces g = 63 t + lane of the batch, one wave each,
+// overlapping by one face (lane 63's face is lane 0 of the next tile).  Lane
+// l < 63 owns the cell between its face and the next when both are faces of
+// one line, so a tile holds every flux its cells need and no data moves
+// between waves; lane 63 only completes lane 62's cell.  Faces (their
+// fluxes in OUT_FACES mode, their labels) are written by lanes 0..62, and by
+// lane 63 in the last tile.
+//
+// Near-cutoff evaluations: a face with an evaluation whose smallest |logit|
+// lies below the margin is pending, and the cells next to it are not written
+// with the tile.  The face goes into a per-wave list in LDS (face, labels and
+// near bits of it and of its two neighbours, which of its cells the tile
+// owns).  Once a tile brings the list to RFLUSH faces, and after the last
+// tile, the wave flushes it: every near evaluation of the listed faces is
+// evaluated again in FP32 on MFMA (32 per pass) and its label replaces the
+// reduced-precision one; then the fluxes of the pending faces and of their
+// neighbours are recomputed with the final labels, the same arithmetic as in
+// the tile, and the pending cells written.  A pending cell is written once:
+// by its right face's record if that face is pending, else by its left
+// face's.  The stage output of a pending cell reads u0 before anything
+// writes that cell (only its owner touches it), so stage 3 may write the
+// state in place.
+constexpr int RFLUSH = 32;             // flush once this many faces are pending
+constexpr int RCAP = RFLUSH - 1 + 64;  // list capacity per wave
+// Record words: [0] face g; [1] labels of g (byte m: field m, '+' in the low
+// nibble) | its near bits << 24; [2] labels of g - 1 | its near bits << 24 |
+// cell (g-1, g) owned << 30 | face g owned << 31; [3] labels of g + 1 | its
+// near bits << 24 | cell (g, g+1) owned << 30.
+constexpr u32 LAB_MASK = 0xffffffu;
+
+
+// Output of cell kc of the line of fa, between fluxes Fl (left face) and Fr.
+N6_DEV void cell_out(const Line1D &ln, const Out1D &out, const Face1 &fa, int kc, const float qc[3],
+                     float pc, const float Fl[3], const float Fr[3]) {
+#pragma clang fp contract(off)
+  if (out.mode == OUT_FACES) return;
+  const int64_t c = (int64_t)fa.o + kc;
+  const float dx = (float)ln.dx[fa.p];
+  if (out.mode == OUT_RHS) {
 #pragma unroll
-      for (int m = 0; m < NV; ++m) acc = fmaf(R[r][m], hs[m], acc);
-      Fo[r] = acc;
+    for (int v = 0; v < 3; ++v) out.dst[v * ln.total + c] = (Fl[v] - Fr[v]) / dx;
+    if (out.status && !physical<float>(qc[0], pc)) out.status[fa.p] = ST_NONPHYSICAL;
+    return;
+  }
+  const bool frozen = out.frozen[fa.p] != 0;
+  const float dt = (float)out.dt[fa.p];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    const float L = (Fl[v] - Fr[v]) / dx;
+    const float u0 = out.stage == 1 ? qc[v] : out.u0[v * ln.total + c];
+    out.dst[v * ln.total + c] = frozen ? u0 : rk3<float>(out.stage, qc[v], u0, L, dt);
+  }
+}
+
+// Flux of face fa with the given labels, and the state of the cell to its right.
+N6_DEV void face_flux1d(const Line1D &ln, const float *__restrict__ q, const Face1 &fa, u32 labels,
+                        float F[3], float qc[3], float &pc) {
+  float s[6][6], R[3][3], hs[3];
+  Roe1 rw;
+  setup1d(ln, q, fa, s, rw, qc, pc);
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+    hs[m] = combine_pair(s[2 * m], (labels >> (8 * m)) & 15u, s[2 * m + 1], (labels >> (8 * m + 4)) & 15u);
+  roe_R1(rw, R);
+  back_project<3>(R, hs, F);
+}
+
+// Flush of a wave's pending faces (all 64 lanes; see above).  list: scratch
+// for RCAP * 6 entries (the wave's stash, free between tiles).
+N6_DEV void flush1d(const Line1D &ln, const void *__restrict__ prepared, const float *__restrict__ q,
+                    u32 (*rec)[RCAP], u32 *list, int npend, const Out1D &out, int lane) {
+  const int64_t nf = ln.faces();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  // (record, kind) of every near evaluation, in record order
+  int nev = 0;
+  for (int r0 = 0; r0 < npend; r0 += 64) {
+    const int r = r0 + lane;
+    const u32 nb = r < npend ? (rec[1][r] >> 24) & 63u : 0u;
+    const u32 c = (u32)__popc(nb);
+    u32 inc = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const u32 t = __shfl_up(inc, o);
+      inc += lane >= o ? t : 0u;
     }
+    u32 pos = (u32)nev + inc - c, m = nb;
+    while (m) {
+      list[pos++] = ((u32)r << 3) | (u32)(__ffs(m) - 1);
+      m &= m - 1u;
+    }
+    nev += (int)__shfl(inc, 63);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  // FP32 labels: lanes j and j + 32 carry entry j of a pass of 32.  The
+  // stencil is formed first, and the FP32 weights come in layer by layer.
+  {
+    const int j = lane & 31, h = lane >> 5;
+    for (int b0 = 0; b0 < nev; b0 += 32) {
+      const int i = b0 + j;
+      const bool ok = i < nev;
+      const u32 ent = list[ok ? i : b0];
+      const int r = (int)(ent >> 3), e = (int)(ent & 7u);
+      float x[6], z[4];
+      {
+        float s[6][6], qc[3], pc;
+        Roe1 rw;
+        setup1d(ln, q, face1(ln, (int64_t)rec[0][r]), s, rw, qc, pc);
+        float se[6];
 #pragma unroll
-    for (int r = 0; r < NV; ++r) Fh[(int64_t)r * nf + f] = Fo[r];
+        for (int jj = 0; jj < 6; ++jj) {
+          float v = s[0][jj];
+#pragma unroll
+          for (int k = 1; k < 6; ++k) v = e == k ? s[k][jj] : v;
+          se[jj] = v;
+        }
+        features<float>(se, x);
+      }
+      mlp_f32_stream(prepared, lane, x, h, z);
+      if (h == 0 && ok) {
+        const u32 lab = mask_from_logits<float>(z);
+        const u32 sh = 8u * (u32)(e >> 1) + 4u * (u32)(e & 1);
+        const u32 old = (rec[1][r] >> sh) & 15u;  // other kinds of the face touch other nibbles
+        if (old != lab) atomicXor(&rec[1][r], (old ^ lab) << sh);
+      }
+    }
+  }
+  if (out.nrecheck && lane == 0) atomicAdd(out.nrecheck, (u32)nev);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  // pending cells and faces, with the final labels
+  for (int r0 = 0; r0 < npend; r0 += 64) {
+    const int r = r0 + lane;
+    if (r < npend) {
+      const u32 g = rec[0][r], mg = rec[1][r] & LAB_MASK, wl = rec[2][r], wr = rec[3][r];
+      const bool own_face = (wl >> 31) != 0u, own_l = ((wl >> 30) & 1u) != 0u;
+      const bool own_r = ((wr >> 30) & 1u) != 0u && ((wr >> 24) & 63u) == 0u;
+      // a pending left neighbour is the previous record (same tile, lane order)
+      const u32 ml = ((wl >> 24) & 63u) ? rec[1][r - 1] & LAB_MASK : wl & LAB_MASK;
+      const Face1 fa = face1(ln, (int64_t)g);
+      float Fg[3], qg[3], pg;
+      face_flux1d(ln, q, fa, mg, Fg, qg, pg);
+      if (own_l) {  // cell k - 1, between faces g - 1 and g
+        Face1 fl = fa;
+        fl.k -= 1;
+        float Fl[3], ql[3], pl;
+        face_flux1d(ln, q, fl, ml, Fl, ql, pl);
+        cell_out(ln, out, fa, fa.k - 1, ql, pl, Fl, Fg);
+      }
+      if (own_r) {  // cell k, between faces g and g + 1 (not pending)
+        Face1 fr = fa;
+        fr.k += 1;
+        float Fr[3], qr[3], pr;
+        face_flux1d(ln, q, fr, wr & LAB_MASK, Fr, qr, pr);
+        cell_out(ln, out, fa, fa.k, qg, pg, Fg, Fr);
+      }
+      if (own_face) {
+        if (out.mode == OUT_FACES) {
+#pragma unroll
+          for (int v = 0; v < 3; ++v) out.dst[v * nf + g] = Fg[v];
+        }
+        if (out.masks) {
+#pragma unroll
+          for (int m = 0; m < 3; ++m) out.masks[m * nf + g] = (uint8_t)(mg >> (8 * m));
+        }
+      }
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// The fused 1D Euler pass.  Three waves per SIMD (a few registers spill; the
+// third wave hides more of the MFMA -> convert -> MFMA latency).
+template <int PREC, int W, bool MLP>
+__global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(3)))
+k_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float margin,
+          const float *__restrict__ q, const uint8_t *__restrict__ min, Out1D out, int xcd) {
+  // stash slots per lane: the six split stencils, the Roe average, the
+  // state and pressure of the cell to the right, the line
+  constexpr int NE = 6, S_ROE = NE * 6, S_QC = S_ROE + 4, S_LINE = S_QC + 4, NS = S_LINE + 1;
+  __shared__ float stash[W][NS][64];
+  __shared__ u32 rec[W][4][MLP ? RCAP : 1];
+  static_assert(NS * 64 >= RCAP * 6, "the flush list fits in the stash");
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t nf = ln.faces();
+  const int64_t ntile = (nf + 61) / 63;  // faces 63 t .. 63 t + 63 cover 0 .. nf - 1
+  const int64_t nb = gridDim.x;
+  const int64_t lb = xcd ? (int64_t)(blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8 : blockIdx.x;
+  // Segments of tiles between flushes: the weights are loaded at the start
+  // of each, so that they hold no registers while a flush runs.
+  for (int64_t t = lb * W + wv; t < ntile;) {
+  Wts w;
+  if constexpr (MLP) load_wts<PREC>(opaque(prepared), lane, w);
+  int npend = 0;  // wave-uniform
+  for (; t < ntile; t += nb * W) {
+    const int64_t g = t * 63 + lane;
+    const bool valid = g < nf;
+    u32 fx[NE][3];
+    {
+      // the face's line and geometry wait in LDS with the stencils: nothing
+      // but the classifier's operands holds registers through the MFMA phase
+      const Face1 fa = face1(ln, valid ? g : nf - 1);
+      float s[NE][6], qc[3], pc;
+      Roe1 rw;
+      setup1d(ln, q, fa, s, rw, qc, pc);
+      if constexpr (MLP) {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) feature_pack<PREC>(s[e], fx[e][0], fx[e][1], fx[e][2]);
+      }
+#pragma unroll
+      for (int e = 0; e < NE; ++e)
+#pragma unroll
+        for (int j = 0; j < 6; ++j) stash[wv][e * 6 + j][lane] = s[e][j];
+      stash[wv][S_ROE][lane] = rw.ut;
+      stash[wv][S_ROE + 1][lane] = rw.ct;
+      stash[wv][S_ROE + 2][lane] = rw.Ht;
+      stash[wv][S_ROE + 3][lane] = rw.q2;
+#pragma unroll
+      for (int v = 0; v < 3; ++v) stash[wv][S_QC + v][lane] = qc[v];
+      stash[wv][S_QC + 3][lane] = pc;
+      stash[wv][S_LINE][lane] = __builtin_bit_cast(float, fa.p);
+    }
+    u32 sel[NE], near = 0u;
+    // the classifier phase at raised wave priority: its MFMA -> convert
+    // chains are issued as soon as they are ready, and the other waves'
+    // set-up and combine work fills the gaps
+    if constexpr (MLP) __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      if constexpr (MLP) {
+        __builtin_amdgcn_sched_barrier(0);
+        const u32 mk = classify_packed<PREC>(w, fx[e][0], fx[e][1], fx[e][2], margin, nullptr);
+        sel[e] = mk & 15u;
+        near |= (mk >> 4) << e;
+      } else if (selector == 1) {
+        sel[e] = 15u;
+      } else if (selector == 2) {
+        sel[e] = 0u;
+      } else if (selector == 4) {  // TENO6-opt, decided in FP64
+        float se[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) se[j] = stash[wv][e * 6 + j][lane];
+        sel[e] = teno_mask_of<float>(se);
+      } else {
+        sel[e] = (min[(e >> 1) * nf + (valid ? g : nf - 1)] >> ((e & 1) * 4)) & 15u;
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (MLP) __builtin_amdgcn_s_setprio(0);
+    near = valid ? near : 0u;
+    float hs[3], F[3], R[3][3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      float sp[6], sm[6];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        sp[j] = stash[wv][(2 * m) * 6 + j][lane];
+        sm[j] = stash[wv][(2 * m + 1) * 6 + j][lane];
+      }
+      hs[m] = combine_pair(sp, sel[2 * m], sm, sel[2 * m + 1]);
+    }
+    roe_R1(Roe1{stash[wv][S_ROE][lane], stash[wv][S_ROE + 1][lane], stash[wv][S_ROE + 2][lane],
+                stash[wv][S_ROE + 3][lane]},
+           R);
+    back_project<3>(R, hs, F);
+    float qc[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) qc[v] = stash[wv][S_QC + v][lane];
+    const float pc = stash[wv][S_QC + 3][lane];
+    Face1 fa;
+    fa.p = __builtin_bit_cast(int, stash[wv][S_LINE][lane]);
+    {
+      const int64_t o = ln.offsets[fa.p];
+      fa.o = (uint32_t)o;
+      fa.n = (int)(ln.offsets[fa.p + 1] - o);
+      fa.k = (int)((valid ? g : nf - 1) - o - fa.p);
+    }
+    u32 mw = 0u;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) mw |= (sel[2 * m] | (sel[2 * m + 1] << 4)) << (8 * m);
+    // the neighbouring faces of the tile: every lane takes part in the
+    // shuffles (a lane outside a conditional would supply no value), and
+    // the edge lanes' results are masked afterwards
+    float Fr[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) Fr[v] = __shfl_down(F[v], 1);
+    const u32 near_dn = __shfl_down(near, 1), near_up = __shfl_up(near, 1);
+    const u32 mw_dn = __shfl_down(mw, 1), mw_up = __shfl_up(mw, 1);
+    const u32 near_r = lane < 63 ? near_dn : 0u;
+    const bool own_face = valid && (lane < 63 || t == ntile - 1);
+    const bool own_cell = valid && lane < 63 && fa.k < fa.n;
+    if (own_cell && (near | near_r) == 0u) cell_out(ln, out, fa, fa.k, qc, pc, F, Fr);
+    if (own_face && near == 0u) {
+      if (out.mode == OUT_FACES) {
+#pragma unroll
+        for (int v = 0; v < 3; ++v) out.dst[v * nf + g] = F[v];
+      }
+      if (out.masks) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) out.masks[m * nf + g] = (uint8_t)(mw >> (8 * m));
+      }
+    }
+    if constexpr (MLP) {
+      const u32 near_l = lane >= 1 ? near_up : 0u;
+      const u32 mw_l = mw_up, mw_r = mw_dn;
+      const uint64_t bal = __ballot(near != 0u);
+      if (bal != 0ull) {
+        if (near != 0u) {
+          const int pos = npend + (int)__popcll(bal & ((1ull << lane) - 1ull));
+          const bool own_l = lane >= 1 && fa.k >= 1;
+          const bool own_r = lane < 63 && fa.k < fa.n;
+          rec[wv][0][pos] = (u32)g;
+          rec[wv][1][pos] = mw | (near << 24);
+          rec[wv][2][pos] = (mw_l & LAB_MASK) | (near_l << 24) | (own_l ? 1u << 30 : 0u) |
+                            (own_face ? 1u << 31 : 0u);
+          rec[wv][3][pos] = (mw_r & LAB_MASK) | (near_r << 24) | (own_r ? 1u << 30 : 0u);
+        }
+        npend += (int)__popcll(bal);
+        if (npend >= RFLUSH) {
+          t += nb * W;
+          break;
+        }
+      }
+    }
+  }
+  if constexpr (MLP) {
+    if (npend > 0) flush1d(ln, prepared, q, rec[wv], (u32 *)&stash[wv][0][0], npend, out, lane);
+  }
   }
 }
 
@@ -1098,16 +1514,69 @@ hipError_t copy_bytes(const uint8_t *a, uint8_t *b, int64_t n, hipStream_t s) {
 }
 
 // Prepared block: FP32 copy of the parameters, the BF16 and FP16 per-lane
-// operand tables, and b5 in FP32.
+// operand tables, b5 in FP32, the FP32 operand table of the re-check, and the
+// per-neuron scales of the hidden layers.
 constexpr int PREP_THREADS = (TAB_REGS > F32_REGS ? TAB_REGS : F32_REGS) * 64;
 static_assert(NPARAM <= PREP_THREADS, "k_prepare covers every element");
+// Scales of hidden layers 1..4 (64 + 32 + 16 + 8 values, FP64).
+constexpr int SC1 = 0, SC2 = 64, SC3 = 96, SC4 = 112, NSCALE = 120;
+constexpr int PREP_SCALE_OFF = PREP_F32_OFF + F32_REGS * 64 * 4;
+static_assert(PREP_SCALE_OFF + NSCALE * 8 <= (int)PREP_BYTES, "prepared block layout");
 
-// Entry t of the prepared block (FP32 copy, FP32 and BF16/FP16 operand tables).
-N6_DEV void prepare_entry(const double *__restrict__ P, char *__restrict__ prep, int t) {
+// A-priori activation scales (one workgroup of 64 threads).  With inputs
+// |x_i| <= 1 (eq. normalizainput) the pre-activation z_o of a first-layer
+// neuron is at most b_o + sum_i |W_oi|; a deeper neuron, whose inputs are
+// ReLU outputs in [0, U_i], at most b_o + sum_i max(W_oi, 0) U_i.  The scale
+// s_o adds 1/32 of the neuron's absolute sum (|b_o| + sum_i |W_oi| U_i) to
+// that bound, so the BF16/FP16 rounding of the scaled products (a few 2^-8
+// of the absolute sum) cannot push a scaled pre-activation above 1.  A
+// neuron whose bound is <= 0 never fires; its scale is 1.
+__global__ void __launch_bounds__(64) k_prepare_scales(const double *__restrict__ P,
+                                                       double *__restrict__ S) {
+  __shared__ double U[64];
+  const int o = threadIdx.x;
+  double u = P[OB1 + o], a = fabs(P[OB1 + o]);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    u += fabs(P[OW1 + o * 6 + i]);
+    a += fabs(P[OW1 + o * 6 + i]);
+  }
+  S[SC1 + o] = u > 0.0 ? u + a / 32.0 : 1.0;
+  U[o] = u > 0.0 ? u : 0.0;
+  __syncthreads();
+  const int nin[3] = {64, 32, 16}, nout[3] = {32, 16, 8};
+  const int ow[3] = {OW2, OW3, OW4}, ob[3] = {OB2, OB3, OB4}, so[3] = {SC2, SC3, SC4};
+  for (int l = 0; l < 3; ++l) {
+    double ul = 0.0;
+    if (o < nout[l]) {
+      ul = P[ob[l] + o];
+      a = fabs(P[ob[l] + o]);
+      for (int i = 0; i < nin[l]; ++i) {
+        const double w = P[ow[l] + o * nin[l] + i];
+        ul += (w > 0.0 ? w : 0.0) * U[i];
+        a += fabs(w) * U[i];
+      }
+      S[so[l] + o] = ul > 0.0 ? ul + a / 32.0 : 1.0;
+    }
+    __syncthreads();
+    if (o < nout[l]) U[o] = ul > 0.0 ? ul : 0.0;
+    __syncthreads();
+  }
+}
+
+// Entry t of the prepared block (FP32 copy, FP32 and BF16/FP16 operand
+// tables).  With S (the scales above), the BF16/FP16 tables hold the scaled
+// network: hidden neuron o of layer l computes z_o / s_o, so its inputs'
+// weights are W_oi s_i / s_o (s_i = 1 for the six features), its bias b_o /
+// s_o, and the output layer's weights W5_ki s_i; without S (the training
+// tables) the plain weights.
+N6_DEV void prepare_entry(const double *__restrict__ P, const double *__restrict__ S,
+                          char *__restrict__ prep, int t) {
   if (t < NPARAM) ((float *)prep)[t] = (float)P[t];
   if (t < 4) ((float *)(prep + PREP_B5_OFF))[t] = (float)P[OB5 + t];
   if (t < F32_REGS * 64) ((float *)(prep + PREP_F32_OFF))[t] = f32_table_value(P, t / 64, t % 64);
   if (t >= TAB_REGS * 64) return;
+  auto sc = [&](int base, int i) { return S ? S[base + i] : 1.0; };
   const int reg = t / 64, lane = t % 64, i = lane % 32, h = lane / 32;
   float v[2];
   bool is_bias = false;
@@ -1116,21 +1585,22 @@ N6_DEV void prepare_entry(const double *__restrict__ P, char *__restrict__ prep,
     if (reg < 4) {  // L1: tile reg/2, elements e = 2*(reg%2) + q2, K slot 4h + e
       const int tt = reg / 2, e = 2 * (reg % 2) + q2, kk = 4 * h + e, o = 32 * tt + i;
       x = kk < 6 ? P[OW1 + o * 6 + kk] : (kk == 6 ? P[OB1 + o] : 0.0);
+      x /= sc(SC1, o);
     } else if (reg < 20) {  // L2 step s
       const int s = (reg - 4) / 4, e = 2 * ((reg - 4) % 4) + q2;
       const int n1 = 32 * (s / 2) + 16 * (s % 2) + 8 * (e / 4) + 4 * h + e % 4;
-      x = P[OW2 + i * 64 + n1];
+      x = P[OW2 + i * 64 + n1] * sc(SC1, n1) / sc(SC2, i);
     } else if (reg < 28) {  // L3 step s
       const int s = (reg - 20) / 4, e = 2 * ((reg - 20) % 4) + q2;
       const int n2 = 8 * (2 * s + e / 4) + 4 * h + e % 4;
-      x = i < 16 ? P[OW3 + i * 32 + n2] : 0.0;
+      x = i < 16 ? P[OW3 + i * 32 + n2] * sc(SC2, n2) / sc(SC3, i) : 0.0;
     } else if (reg < 32) {  // L4
       const int e = 2 * (reg - 28) + q2;
       const int n3 = 8 * (e / 4) + 4 * h + e % 4;
-      x = i < 8 ? P[OW4 + i * 16 + n3] : 0.0;
+      x = i < 8 ? P[OW4 + i * 16 + n3] * sc(SC3, n3) / sc(SC4, i) : 0.0;
     } else if (reg < 36) {  // L5: K slots e < 4 carry tile 0 (rows 0..3), e >= 4 tile 1 (rows 4..7)
       const int e = 2 * (reg - 32) + q2, t5 = e / 4, n4 = 4 * h + e % 4;
-      x = i / 4 == t5 ? P[OW5 + (i % 4) * 8 + n4] : 0.0;
+      x = i / 4 == t5 ? P[OW5 + (i % 4) * 8 + n4] * sc(SC4, n4) : 0.0;
     } else {
       is_bias = true;
     }
@@ -1145,9 +1615,9 @@ N6_DEV void prepare_entry(const double *__restrict__ P, char *__restrict__ prep,
     const int blk = (reg - 36) / 16, r = (reg - 36) % 16;
     const int row = 8 * (r / 4) + 4 * h + r % 4;
     double x;
-    if (blk == 0) x = P[OB2 + row];
-    else if (blk == 1) x = row < 16 ? P[OB3 + row] : 0.0;
-    else x = row < 8 ? P[OB4 + row] : 0.0;
+    if (blk == 0) x = P[OB2 + row] / sc(SC2, row);
+    else if (blk == 1) x = row < 16 ? P[OB3 + row] / sc(SC3, row) : 0.0;
+    else x = row < 8 ? P[OB4 + row] / sc(SC4, row) : 0.0;
     wb = wh = __builtin_bit_cast(u32, (float)x);
   }
   ((u32 *)(prep + PREP_BF16_OFF))[reg * 64 + lane] = wb;
@@ -1155,7 +1625,7 @@ N6_DEV void prepare_entry(const double *__restrict__ P, char *__restrict__ prep,
 }
 
 __global__ void __launch_bounds__(TPB) k_prepare(const double *__restrict__ P, char *__restrict__ prep) {
-  prepare_entry(P, prep, blockIdx.x * TPB + threadIdx.x);
+  prepare_entry(P, (const double *)(prep + PREP_SCALE_OFF), prep, blockIdx.x * TPB + threadIdx.x);
 }
 
 inline unsigned grid_for(int64_t items_per_wave_chunks) {
@@ -1228,7 +1698,7 @@ constexpr int PREP_BLOCKS = (PREP_THREADS + TPB - 1) / TPB;
 __global__ void __launch_bounds__(TPB) k_prepare_train(const double *__restrict__ P, char *__restrict__ prep,
                                                        u32 *__restrict__ tab) {
   if ((int)blockIdx.x < PREP_BLOCKS)
-    prepare_entry(P, prep, blockIdx.x * TPB + threadIdx.x);
+    prepare_entry(P, nullptr, prep, blockIdx.x * TPB + threadIdx.x);
   else
     prepare_bwd_entry(P, tab, ((int)blockIdx.x - PREP_BLOCKS) * TPB + threadIdx.x);
 }
@@ -1522,6 +1992,8 @@ size_t fast_prepared_bytes() { return PREP_BYTES; }
 const void *fast_prepared_f32(const void *prepared) { return prepared; }
 
 hipError_t launch_fast_prepare(const double *P, void *prepared, hipStream_t s) {
+  hipLaunchKernelGGL(k_prepare_scales, dim3(1), dim3(64), 0, s, P,
+                     (double *)((char *)prepared + PREP_SCALE_OFF));
   hipLaunchKernelGGL(k_prepare, dim3((PREP_THREADS + TPB - 1) / TPB), dim3(TPB), 0, s, P,
                      (char *)prepared);
   return hipGetLastError();
@@ -1557,93 +2029,70 @@ hipError_t launch_fast_reconstruct(const void *prepared, int precision, float ma
   return hipGetLastError();
 }
 
-template <int NV>
-hipError_t launch_faces_kernel(const FaceLaunch &L, const FastArgs &fa, hipStream_t s,
-                               const Line1D &ln, const Grid2D &g, int dir, const float *q,
-                               const uint8_t *mi, float *F, uint8_t *m, u32 *qc) {
+// 2D sweep: the fused face kernel in the tuned shape (four or eight waves;
+// two spill registers), or the selector-only instantiation.
+hipError_t launch_faces2d_kernel(const FaceLaunch &L, const FastArgs &fa, hipStream_t s,
+                                 const Grid2D &g, int dir, const float *q, const uint8_t *mi,
+                                 float *F, uint8_t *m) {
 #define N6_FACES(P, W)                                                                        \
-  hipLaunchKernelGGL((k_fast_faces<P, NV, W, true>), dim3(L.grid), dim3(W * 64), 0, s, ln, g,  \
-                     dir, fa.selector, fa.prepared, fa.margin, q, mi, F, m, fa.scr.queue, qc,  \
-                     fa.scr.qnear, L.xcd)
+  hipLaunchKernelGGL((k_fast_faces<P, W, true>), dim3(L.grid), dim3(W * 64), 0, s, g, dir,     \
+                     fa.selector, fa.prepared, fa.margin, q, mi, F, m, fa.scr.qnear, L.xcd)
   if (fa.selector != 0) {  // the other selectors: no classifier, one instantiation
-    hipLaunchKernelGGL((k_fast_faces<2, NV, 4, false>), dim3(L.grid), dim3(256), 0, s, ln, g, dir,
-                       fa.selector, fa.prepared, fa.margin, q, mi, F, m, fa.scr.queue, qc,
-                       fa.scr.qnear, L.xcd);
+    hipLaunchKernelGGL((k_fast_faces<2, 4, false>), dim3(L.grid), dim3(256), 0, s, g, dir,
+                       fa.selector, fa.prepared, fa.margin, q, mi, F, m, fa.scr.qnear, L.xcd);
     return hipGetLastError();
   }
-  // 2D sweeps: two waves per workgroup spill registers, so they take four
-  const int waves = (NV == 4 && L.waves == 2) ? 4 : L.waves;
-  if constexpr (NV == 3) {
-    if (waves == 2) {
-      if (fa.precision == 2) N6_FACES(2, 2);
-      else N6_FACES(3, 2);
-      return hipGetLastError();
-    }
-  }
   if (fa.precision == 2) {
-    if (waves == 8) N6_FACES(2, 8);
+    if (L.waves == 8) N6_FACES(2, 8);
     else N6_FACES(2, 4);
   } else {
-    if (waves == 8) N6_FACES(3, 8);
+    if (L.waves == 8) N6_FACES(3, 8);
     else N6_FACES(3, 4);
   }
 #undef N6_FACES
   return hipGetLastError();
 }
 
-hipError_t launch_fast_faces1d(const Line1D &ln, const FastArgs &fa, const float *q,
-                               const uint8_t *masks_in, uint8_t *masks_out, float *F,
-                               hipStream_t s) {
+hipError_t launch_fast_pass1d(const Line1D &ln, const FastArgs &fa, const float *q,
+                              const uint8_t *masks_in, const Out1D &out, hipStream_t s) {
   const int64_t tf = ln.faces();
   const unsigned grid = grid_for((tf + 63) / 64);
-  uint8_t *masks = masks_out ? masks_out : fa.scr.masks;
-  if (fa.equation == 0) {
-    if (fa.precision == 2)
-      hipLaunchKernelGGL(k_fast_scalar<2>, dim3(grid), dim3(TPB), 0, s, 1, ln, fa.prepared, fa.margin,
-                         q, tf, 1, fa.selector, masks_in, F, masks, nullptr);
-    else
-      hipLaunchKernelGGL(k_fast_scalar<3>, dim3(grid), dim3(TPB), 0, s, 1, ln, fa.prepared, fa.margin,
-                         q, tf, 1, fa.selector, masks_in, F, masks, nullptr);
+  if (fa.equation == 0 || fa.equation == 1) {  // scalar laws: face fluxes, re-check in place
+    if (out.mode != OUT_FACES) return hipErrorInvalidValue;
+    if (fa.equation == 0) {
+      if (fa.precision == 2)
+        hipLaunchKernelGGL(k_fast_scalar<2>, dim3(grid), dim3(TPB), 0, s, 1, ln, fa.prepared, fa.margin,
+                           q, tf, 1, fa.selector, masks_in, out.dst, out.masks, nullptr);
+      else
+        hipLaunchKernelGGL(k_fast_scalar<3>, dim3(grid), dim3(TPB), 0, s, 1, ln, fa.prepared, fa.margin,
+                           q, tf, 1, fa.selector, masks_in, out.dst, out.masks, nullptr);
+    } else {
+      if (fa.precision == 2)
+        hipLaunchKernelGGL(k_fast_burgers<2>, dim3(grid), dim3(TPB), 0, s, ln, fa.prepared,
+                           fa.margin, fa.selector, q, masks_in, out.dst, out.masks);
+      else
+        hipLaunchKernelGGL(k_fast_burgers<3>, dim3(grid), dim3(TPB), 0, s, ln, fa.prepared,
+                           fa.margin, fa.selector, q, masks_in, out.dst, out.masks);
+    }
     return hipGetLastError();
   }
-  if (fa.equation == 1) {
-    if (fa.precision == 2)
-      hipLaunchKernelGGL(k_fast_burgers<2>, dim3(grid), dim3(TPB), 0, s, ln, fa.prepared,
-                         fa.margin, fa.selector, q, masks_in, F, masks);
-    else
-      hipLaunchKernelGGL(k_fast_burgers<3>, dim3(grid), dim3(TPB), 0, s, ln, fa.prepared,
-                         fa.margin, fa.selector, q, masks_in, F, masks);
-    return hipGetLastError();
+  const FaceLaunch L = face_launch(fa, (tf + 61) / 63);
+#define N6_EULER1D(P, W, MLP)                                                                  \
+  hipLaunchKernelGGL((k_euler1d<P, W, MLP>), dim3(L.grid), dim3(W * 64), 0, s, ln, fa.selector, \
+                     fa.prepared, fa.margin, q, masks_in, out, L.xcd)
+  if (fa.selector != 0) {
+    N6_EULER1D(2, 4, false);
+  } else if (fa.precision == 2) {
+    if (L.waves == 2) N6_EULER1D(2, 2, true);
+    else if (L.waves == 8) N6_EULER1D(2, 8, true);
+    else N6_EULER1D(2, 4, true);
+  } else {
+    if (L.waves == 2) N6_EULER1D(3, 2, true);
+    else if (L.waves == 8) N6_EULER1D(3, 8, true);
+    else N6_EULER1D(3, 4, true);
   }
-  // The re-check flips labels with 32-bit atomics, so the classifier writes
-  // into the workspace buffer (whole words) and the caller's copy follows.
-  // The re-check counters were cleared at the start of the call or by the
-  // previous stage's flux-difference kernel.
-  masks = fa.scr.masks;
-  const bool recheck = fa.selector == 0 && fa.margin > 0.f;
-  const Grid2D g0{};
-  const FaceLaunch L = face_launch(fa, (tf + 63) / 64);
-  hipError_t e = launch_faces_kernel<3>(L, fa, s, ln, g0, 0, q, masks_in, F, masks, fa.scr.qcount);
-  if (e != hipSuccess) return e;
-  if (recheck) {
-    Grid2D gd{};
-    hipLaunchKernelGGL(k_recheck<1>, dim3(L.rgrid), dim3(TPB), 0, s, ln, gd, 0, fa.prepared, q,
-                       masks, fa.scr.queue, fa.scr.qcount, fa.scr.qflag);
-    hipLaunchKernelGGL(k_fixup<1>, dim3(L.rgrid), dim3(TPB), 0, s, ln, gd, 0, q, masks,
-                       fa.scr.queue, fa.scr.qcount, fa.scr.qflag, F);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess && masks_out) e = copy_bytes(masks, masks_out, 3 * tf, s);
-  return e;
-}
-
-hipError_t launch_fast_rhs1d(const Line1D &ln, const FastArgs &fa, const float *q, float *rhs,
-                             const uint8_t *masks_in, uint8_t *masks_out, int32_t *status,
-                             float *F, const Stage *st, hipStream_t s) {
-  hipError_t e = launch_fast_faces1d(ln, fa, q, masks_in, masks_out, F, s);
-  if (e != hipSuccess) return e;
-  return launch_diff1d<float>(ln, fa.equation, F, q, rhs, st, status, s,
-                              fa.scr.qcount);
+#undef N6_EULER1D
+  return hipGetLastError();
 }
 
 hipError_t launch_fast_reset(const FastArgs &fa, hipStream_t s) {
@@ -1664,18 +2113,17 @@ hipError_t launch_fast_faces2d(const Grid2D &g, const FastArgs &fa, const float 
     const uint8_t *mi = masks_in ? masks_in + (dir == 0 ? 0 : 4 * nfx) : nullptr;
     float *Fd = dir == 0 ? Fx : Gy;
     u32 *qc = fa.scr.qcount + 8 * dir;  // eight counters (kinds) per sweep direction
-    const Line1D l0{};
     const FaceLaunch L = face_launch(fa, (nf + 63) / 64);
-    hipError_t e = launch_faces_kernel<4>(L, fa, s, l0, g, dir, q, mi, Fd, md, qc);
+    hipError_t e = launch_faces2d_kernel(L, fa, s, g, dir, q, mi, Fd, md);
     if (e != hipSuccess) return e;
     if (recheck) {
       const int64_t cmp_waves = ((nf + 3) / 4 + CMP_WPW - 1) / CMP_WPW;
       hipLaunchKernelGGL(k_compact_near, dim3((unsigned)((cmp_waves + WPB - 1) / WPB)), dim3(TPB), 0, s,
                          fa.scr.qnear, nf, fa.scr.queue, qc);
-      hipLaunchKernelGGL(k_recheck<2>, dim3(L.rgrid), dim3(TPB), 0, s, l0, g, dir, fa.prepared,
-                         q, md, fa.scr.queue, qc, fa.scr.qflag);
-      hipLaunchKernelGGL(k_fixup<2>, dim3(L.rgrid), dim3(TPB), 0, s, l0, g, dir, q, md,
-                         fa.scr.queue, qc, fa.scr.qflag, Fd);
+      hipLaunchKernelGGL(k_recheck2d, dim3(L.rgrid), dim3(TPB), 0, s, g, dir, fa.prepared, q, md,
+                         fa.scr.queue, qc, fa.scr.qflag);
+      hipLaunchKernelGGL(k_fixup2d, dim3(L.rgrid), dim3(TPB), 0, s, g, dir, q, md, fa.scr.queue, qc,
+                         fa.scr.qflag, Fd);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }

@@ -382,18 +382,6 @@ k_back_euler2d(Grid2D gd, int dir, const T *__restrict__ q, const T *__restrict_
   }
 }
 
-// RK3 stage update (Sec. 4.4, SSP-RK3):
-//   stage 1: u1 = u0 + dt L(u0)
-//   stage 2: u2 = 3/4 u0 + 1/4 (u1 + dt L(u1))
-//   stage 3: u  = 1/3 u0 + 2/3 (u2 + dt L(u2))
-template <typename T>
-N6_DEV T rk3(int stage, T us, T u0, T L, T dt) {
-  if (stage == 1) return fma_<T>(dt, L, us);
-  const T t = fma_<T>(dt, L, us);
-  if (stage == 2) return fma_<T>(T(0.25), t, T(0.75) * u0);
-  return fma_<T>(T(2) / T(3), t, (T(1) / T(3)) * u0);
-}
-
 template <typename T>
 __global__ void __launch_bounds__(TPB)
 k_diff1d(Line1D ln, int equation, const T *__restrict__ Fh, const T *__restrict__ q,

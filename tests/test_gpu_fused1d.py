@@ -1,0 +1,255 @@
+"""The shipped 1D Euler pass in BF16 / FP16 (classifier on MFMA, in-kernel
+FP32 re-check, flux difference and RK3 stage in the same kernel) against the
+FP64 oracle, value by value (Alg. 2; eq. approximateEq; Sec. 4.4).
+
+Reduced-precision labels may legitimately differ from the FP64 labels where
+a logit lies within the precision's error of the cutoff; the flip rate is
+bounded, and the values are compared at every cell whose two faces carry the
+oracle's labels in all three fields.  There only the FP32 rounding of the
+state and of the arithmetic separates the two, so the tolerance is the one
+of the FP32 paths (5e-5 of the flux scale of the line).
+
+Batches are ragged on purpose: lines of 1, 2, 62..65 and 126..128 cells put
+line ends and the 63-face tile seams at every offset."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_08500_amd import inputs
+from tests._helpers import dev, host, label_flip_rate, need_gpu, trained_params
+
+pytestmark = pytest.mark.gpu
+
+MARGIN = {2: 0.5, 3: 0.25}
+SIZES = (1, 2, 3, 7, 62, 63, 64, 65, 126, 127, 128, 500, 1000)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    need_gpu()
+    import torch
+    from paper_2207_08500_amd import native
+    return native, torch, trained_params()
+
+
+def _cells_with_oracle_labels(m, m_o, off):
+    """Cells whose left and right faces carry the oracle's labels (all fields)."""
+    same = np.all(m.reshape(3, -1) == m_o.reshape(3, -1), axis=0)  # per face
+    ok = []
+    for p in range(len(off) - 1):
+        a, b = off[p] + p, off[p + 1] + p  # faces of line p: a .. b
+        ok.append(same[a:b] & same[a + 1:b + 1])
+    return np.concatenate(ok)
+
+
+def _fscale(r_o, q, off, dx):
+    """Per-cell flux scale of the line: the largest |rhs| and |q|/dx."""
+    s = np.zeros(off[-1])
+    for p in range(len(off) - 1):
+        a, b = off[p], off[p + 1]
+        s[a:b] = np.abs(r_o[:, a:b]).max() + np.abs(q[:, a:b]).max() / dx[p]
+    return s
+
+
+def _rhs(native, torch, P, prec, margin, q32, off, dx, tuning=None, bc=1):
+    mlp = native.Mlp(dev(P), recheck_margin=margin)
+    prob = native.Problem(native.EULER1D, prec, native.SEL_MLP, bc, off, dx)
+    prob.set_tuning(tuning)
+    ws = prob.workspace()
+    r = torch.zeros_like(q32)
+    m = torch.zeros(prob.mask_count(), dtype=torch.uint8, device="cuda")
+    F = torch.zeros(3 * prob.n_faces, dtype=torch.float32, device="cuda")
+    mF = torch.zeros_like(m)
+    native.neno6_rhs(prob, mlp, q32, r, ws, masks_out=m)
+    native.neno6_face_fluxes(prob, mlp, q32, F, ws, masks_out=mF)
+    n_re = native.neno6_recheck_count(prob, mlp, ws)[0]
+    torch.cuda.synchronize()
+    return host(r).reshape(3, -1), host(m), host(F).reshape(3, -1), host(mF), n_re
+
+
+def _rhs_masks_in(native, torch, P, prec, q32, off, dx, masks):
+    mlp = native.Mlp(dev(P), recheck_margin=MARGIN[prec])
+    prob = native.Problem(native.EULER1D, prec, native.SEL_MASKS_IN, 1, off, dx)
+    r = torch.zeros_like(q32)
+    native.neno6_rhs(prob, mlp, q32, r, prob.workspace(), masks_in=dev(masks.ravel()))
+    torch.cuda.synchronize()
+    return host(r).reshape(3, -1)
+
+
+@pytest.mark.parametrize("prec", [2, 3])
+@pytest.mark.parametrize("margin", ["stated", "all"])
+def test_rhs_elementwise_against_oracle(ctx, prec, margin):
+    """Labels against the oracle's (flip rate), then values: at every cell
+    whose faces carry the oracle's labels the classifier pass gives exactly
+    the values of the same pass with the oracle's labels imposed (same FP32
+    arithmetic, whether a face was finished in its tile or after the FP32
+    re-check), and those are within FP32 rounding of the oracle's."""
+    native, torch, P = ctx
+    q, off, dx = inputs.riemann1d_batch(31, SIZES, perturb=True)
+    q = q.astype(np.float32).astype(np.float64)  # both sides see the same FP32 state
+    r_o, m_o, _ = oracle.euler1d_rhs(q, off, dx, 1.4, 1, P, oracle.SEL_MLP)
+    mu = MARGIN[prec] if margin == "stated" else 1e30  # 1e30: every evaluation re-checked
+    q32 = dev(q, torch.float32)
+    r, m, F, mF, n_re = _rhs(native, torch, P, prec, mu, q32, off, dx)
+    r_in = _rhs_masks_in(native, torch, P, prec, q32, off, dx, m_o)
+    nf = off[-1] + len(SIZES)
+    if margin == "all":  # lane 63's face of every tile but the last is also the next tile's
+        assert n_re == 6 * (nf + (nf + 61) // 63 - 1)
+    flips = label_flip_rate(m, m_o.ravel())
+    ok = _cells_with_oracle_labels(m, m_o, off)
+    err = np.abs(r_in - r_o) / _fscale(r_o, q, off, dx)
+    print("prec %d margin %s: flip rate %.3g, re-checked %d of %d, cells with oracle labels "
+          "%d of %d, max rel err of the imposed-label values %.3g" %
+          (prec, margin, flips, n_re, 6 * nf, ok.sum(), ok.size, err.max()))
+    # FP32 labels (all re-checked) differ from FP64 only within FP32 round-off of the cutoff
+    assert flips < (2e-3 if margin == "stated" else 1e-3)
+    assert ok.mean() > 0.97
+    assert np.array_equal(r[:, ok].view(np.uint32), r_in[:, ok].view(np.uint32))
+    assert err.max() <= 5e-5
+    # the face pass and the right-hand side use the same labels and the same
+    # face fluxes: rhs_i = (F_{i-1/2} - F_{i+1/2}) / dx exactly, in FP32
+    assert np.array_equal(m, mF)
+    for p in range(len(SIZES)):
+        a, b = off[p], off[p + 1]
+        Fl, Fr = F[:, a + p:b + p], F[:, a + p + 1:b + p + 1]
+        want = (Fl - Fr) / np.float32(dx[p])
+        assert np.array_equal(r[:, a:b].view(np.uint32), want.view(np.uint32)), "line %d" % p
+
+
+@pytest.mark.parametrize("prec", [2, 3])
+def test_masks_in_elementwise(ctx, prec):
+    """With the oracle's labels imposed (the selector-only instantiation of
+    the same pass), every cell matches the oracle to FP32 rounding."""
+    native, torch, P = ctx
+    q, off, dx = inputs.riemann1d_batch(32, SIZES, perturb=True)
+    q = q.astype(np.float32).astype(np.float64)
+    r_o, m_o, _ = oracle.euler1d_rhs(q, off, dx, 1.4, 1, P, oracle.SEL_MLP)
+    mlp = native.Mlp(dev(P), recheck_margin=MARGIN[prec])
+    prob = native.Problem(native.EULER1D, prec, native.SEL_MASKS_IN, 1, off, dx)
+    r = torch.zeros(q.shape, dtype=torch.float32, device="cuda").reshape(-1)
+    native.neno6_rhs(prob, mlp, dev(q, torch.float32), r, prob.workspace(), masks_in=dev(m_o.ravel()))
+    torch.cuda.synchronize()
+    err = np.abs(host(r).reshape(3, -1) - r_o) / _fscale(r_o, q, off, dx)
+    assert err.max() <= 5e-5
+
+
+def _f32(x):
+    return np.asarray(x, np.float64).astype(np.float32)
+
+
+def _fma32(a, b, c):
+    """FP32 fma: the FP64 product of two FP32 values is exact, and the FP64
+    sum rounds to FP32 as the fused operation does, except on the rare FP64
+    results that sit on an FP32 rounding midpoint (about 2^-29 of cases)."""
+    return _f32(np.float64(1) * np.asarray(a, np.float32).astype(np.float64) *
+                np.asarray(b, np.float32).astype(np.float64) + np.asarray(c, np.float32).astype(np.float64))
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_stage_output_matches_rhs(ctx, bc):
+    """One RK3 step of the fused pass equals the SSP-RK3 stage formulas (Sec.
+    4.4) applied in FP32 to the same pass's right-hand side, bit for bit:
+    stage s reads u_s and u0 and writes u_{s+1}, the third in place.  A
+    frozen problem keeps its state and time.  On periodic lines the total of
+    every variable is conserved to FP32 round-off (every face flux enters its
+    two cells with opposite signs, pending faces included)."""
+    native, torch, P = ctx
+    sizes = (64, 65, 200, 7)
+    q, off, dx = inputs.riemann1d_batch(33, sizes, perturb=True)
+    if bc == 0:  # smooth periodic data
+        x = np.concatenate([(np.arange(n) + 0.5) / n for n in sizes])
+        q = inputs.conservative1d(1.0 + 0.3 * np.sin(2 * np.pi * x), 0.5 + 0.0 * x,
+                                  1.0 + 0.2 * np.cos(2 * np.pi * x))
+    q32 = dev(q, torch.float32)
+    mlp = native.Mlp(dev(P), recheck_margin=MARGIN[2])
+    prob = native.Problem(native.EULER1D, native.BF16, native.SEL_MLP, bc, off, dx)
+    ws = prob.workspace()
+    t = torch.zeros(len(sizes), dtype=torch.float64, device="cuda")
+    st = torch.zeros(len(sizes), dtype=torch.int32, device="cuda")
+    st[3] = -4  # a frozen problem
+    qs = q32.clone()
+    native.neno6_step(prob, mlp, qs, 0.4, 1, t, st, ws)
+    torch.cuda.synchronize()
+    assert host(t)[3] == 0.0 and np.all(host(t)[:3] > 0)
+
+    def L(u):
+        r = torch.zeros(u.size, dtype=torch.float32, device="cuda")
+        native.neno6_rhs(prob, mlp, dev(u.ravel(), torch.float32), r, ws)
+        torch.cuda.synchronize()
+        return host(r).reshape(3, -1)
+
+    u0 = host(q32).reshape(3, -1)
+    d = _f32(np.repeat(host(t), sizes))
+    u1 = _fma32(d, L(u0), u0)
+    u2 = _fma32(np.float32(0.25), _fma32(d, L(u1), u1), _f32(np.float32(0.75) * u0.astype(np.float64)))
+    third, two_thirds = np.float32(1.0) / np.float32(3.0), np.float32(2.0) / np.float32(3.0)
+    u3 = _fma32(two_thirds, _fma32(d, L(u2), u2), _f32(third * u0.astype(np.float64)))
+    got = host(qs).reshape(3, -1)
+    live = np.repeat(np.arange(len(sizes)) != 3, sizes)
+    u3[:, ~live] = u0[:, ~live]
+    assert np.array_equal(got.view(np.uint32), u3.view(np.uint32))
+    if bc == 0:
+        for p in range(3):
+            a, b = off[p], off[p + 1]
+            tot0 = u0[:, a:b].astype(np.float64).sum(axis=1)
+            tot1 = got[:, a:b].astype(np.float64).sum(axis=1)
+            assert np.all(np.abs(tot1 - tot0) <= 1e-5 * np.abs(u0[:, a:b]).sum(axis=1))
+
+
+@pytest.mark.parametrize("prec", [2, 3])
+def test_launch_shapes_bitwise(ctx, prec):
+    """Face fluxes, right-hand side and labels do not depend on the launch
+    shape (tiles, waves per workgroup, flush points)."""
+    native, torch, P = ctx
+    q, off, dx = inputs.riemann1d_batch(34, SIZES * 3, perturb=True)
+    q32 = dev(q, torch.float32)
+    res = []
+    for tun in (None, {"face_waves": 2, "face_blocks": 7, "recheck_blocks": 0, "xcd_order": 0},
+                {"face_waves": 8, "face_blocks": 16, "recheck_blocks": 0, "xcd_order": 1},
+                {"face_waves": 4, "face_blocks": 65536, "recheck_blocks": 0, "xcd_order": 0}):
+        res.append(_rhs(native, torch, P, prec, MARGIN[prec], q32, off, dx, tuning=tun))
+    for r, m, F, mF, n_re in res[1:]:
+        assert np.array_equal(r.view(np.uint32), res[0][0].view(np.uint32))
+        assert np.array_equal(m, res[0][1])
+        assert np.array_equal(F.view(np.uint32), res[0][2].view(np.uint32))
+        assert n_re >= res[0][4]  # the overlap faces of the tiles are re-checked by both tiles
+
+
+def test_c2_full_size_evolved_state(ctx):
+    """The 256 x 4000 batch in the benchmark's configuration, on a state that
+    the FP64 path (bit-exact with the oracle) advanced 40 RK3 steps from the
+    Riemann data: labels and right-hand side of the BF16 pass against the
+    oracle on sampled problems of that evolved state."""
+    native, torch, P = ctx
+    from paper_2207_08500_amd import autotune
+    q, off, dx = inputs.riemann1d_batch(inputs.BASE_SEED, (4000,) * 256)
+    q64 = dev(q)
+    p64 = native.Problem(native.EULER1D, native.FP64, native.SEL_MLP, 1, off, dx)
+    t = torch.zeros(256, dtype=torch.float64, device="cuda")
+    st = torch.zeros(256, dtype=torch.int32, device="cuda")
+    native.neno6_step(p64, native.Mlp(dev(P)), q64, 0.4, 40, t, st, p64.workspace())
+    torch.cuda.synchronize()
+    qe = host(q64).reshape(3, -1).astype(np.float32).astype(np.float64)
+    stp = host(st)
+    q32 = dev(qe, torch.float32)
+    mlp = native.Mlp(dev(P), recheck_margin=MARGIN[2])
+    prob = native.Problem(native.EULER1D, native.BF16, native.SEL_MLP, 1, off, dx)
+    ws = prob.workspace()
+    tun, _ = autotune.tuned(prob, mlp, q32, ws)
+    r, m, _, _, n_re = _rhs(native, torch, P, native.BF16, MARGIN[2], q32, off, dx, tuning=tun)
+    flips, worst = [], 0.0
+    live = [p for p in range(256) if stp[p] == 0]
+    for p in live[:: max(1, len(live) // 6)][:6]:
+        a, b = off[p], off[p + 1]
+        sub = qe[:, a:b]
+        r_o, m_o, _ = oracle.euler1d_rhs(sub, [0, 4000], dx[p:p + 1], 1.4, 1, P, oracle.SEL_MLP)
+        mp = m.reshape(3, -1)[:, a + p:b + p + 1]
+        flips.append(label_flip_rate(mp.ravel(), m_o.ravel()))
+        ok = _cells_with_oracle_labels(mp.ravel(), m_o, [0, 4000])
+        err = np.abs(r[:, a:b] - r_o) / _fscale(r_o, sub, [0, 4000], dx[p:p + 1])
+        worst = max(worst, float(err[:, ok].max()))
+        assert ok.mean() > 0.99
+    print("C2 evolved 40 steps: sampled flip rates %s, max rel err at oracle labels %.3g, "
+          "re-checked %.3g of the evaluations" % (flips, worst, n_re / (6.0 * (off[-1] + 256))))
+    assert max(flips) < 1e-3
+    assert worst <= 5e-5
