@@ -195,8 +195,24 @@ int32_t rhs_impl(const neno6_problem *pb, const T *P, const void *q, void *rhs,
   return hip_status(e);
 }
 
+// Compute units of the current device (queried once per device; 256 if the
+// query fails).
+int device_cus() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cus[dev] == 0) {
+    int n = 0;
+    cus[dev] = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0
+                   ? n
+                   : 256;
+  }
+  return cus[dev];
+}
+
 FastArgs fast_args(const neno6_problem *pb, const neno6_mlp *mlp, const Work &w) {
   FastArgs fa;
+  fa.n_cu = device_cus();
   fa.equation = pb->equation;
   fa.precision = pb->precision;
   fa.selector = pb->selector;
@@ -440,11 +456,13 @@ int32_t neno6_recheck_count(const neno6_problem *prob, const neno6_mlp *mlp, con
   uint32_t qc[QCOUNTERS];
   if (hipMemcpy(qc, w.scr.qcount, sizeof(qc), hipMemcpyDeviceToHost) != hipSuccess)
     return NENO6_HIP_ERROR;
-  // one counter per evaluation kind (and 2D sweep direction)
-  const int nk = prob->equation == NENO6_EULER2D ? 8 : 6;
-  for (int k = 0; k < nk; ++k) {
-    count[0] += qc[k];
-    if (prob->equation == NENO6_EULER2D) count[1] += qc[8 + k];
+  if (prob->equation == NENO6_EULER2D) {  // one counter per evaluation kind and sweep
+    for (int k = 0; k < 8; ++k) {
+      count[0] += qc[k];
+      count[1] += qc[8 + k];
+    }
+  } else {  // 1D: the count spread over all slots
+    for (int k = 0; k < QCOUNTERS; ++k) count[0] += qc[k];
   }
   return NENO6_OK;
 }
@@ -567,7 +585,8 @@ int32_t neno6_step(const neno6_problem *prob, const neno6_mlp *mlp, void *q, dou
   if (!q || !t || !status || !ws || n_steps < 0 || !(cfl > 0)) return NENO6_BAD_ARG;
   const Work w = carve_work(prob, ws);
   if (ws_bytes < w.bytes) return NENO6_WORKSPACE_SMALL;
-  if (int32_t c = begin_call(prob, mlp, w, stream)) return c;
+  // 1D steps maintain no counters (the re-check runs inside the face pass)
+  if (int32_t c = begin_call(prob, mlp, w, stream, prob->equation == NENO6_EULER2D)) return c;
   const bool f64 = prob->precision == NENO6_FP64;
   for (int32_t it = 0; it < n_steps; ++it) {
     hipError_t e;

@@ -43,6 +43,7 @@ struct FastArgs {
   // launch shapes (0 = default): waves per workgroup of the fused kernel,
   // its workgroup cap, re-check / fix-up workgroups, XCD-contiguous order
   int face_waves = 0, face_blocks = 0, recheck_blocks = 0, xcd_order = 0;
+  int n_cu = 256;  // compute units of the device (default grid of the 1D pass)
 };
 
 size_t fast_prepared_bytes();

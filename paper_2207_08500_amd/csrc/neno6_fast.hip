@@ -26,6 +26,8 @@
 // four logits in registers 0..3.  Evaluations whose smallest |logit| is below the
 // re-check margin are queued and re-evaluated in FP32 by a second kernel; a
 // third kernel recomputes the fluxes of faces whose label changed.
+#include <algorithm>
+
 #include "neno6_device.h"
 #include "neno6_fast.h"
 
@@ -53,8 +55,9 @@ constexpr int TAB_BYTES = TAB_REGS * 64 * 4;
 constexpr int PREP_BF16_OFF = 16384;
 constexpr int PREP_F16_OFF = PREP_BF16_OFF + TAB_BYTES;
 constexpr int PREP_B5_OFF = PREP_F16_OFF + TAB_BYTES;
-constexpr int PREP_F32_OFF = 65536;  // FP32 operand table of the re-check (F32_REGS)
-constexpr size_t PREP_BYTES = 98304;
+constexpr int PREP_F32_OFF = 65536;  // FP32 operand table of the 2D re-check (F32_REGS)
+constexpr int PREP_F4_OFF = 98304;   // FP32 16x16x4 operand table of the 1D re-check (F4_REGS)
+constexpr size_t PREP_BYTES = 131072;
 static_assert(PREP_B5_OFF + 16 <= (int)PREP_BYTES, "prepared block layout");
 
 // ---- packing -----------------------------------------------------------------
@@ -290,14 +293,6 @@ N6_DEV u32 classify_wave(const Wts &w, const float s[6], float margin, float *z_
   return classify_packed<PREC>(w, x0, x1, y0, margin, z_out);
 }
 
-// The same pointer, hidden from the optimiser: loads through it are neither
-// hoisted out of a loop nor merged with earlier loads of the same address,
-// so weights reloaded after a flush are not kept live across it.
-N6_DEV const void *opaque(const void *p) {
-  asm volatile("" : "+s"(p));
-  return p;
-}
-
 N6_DEV const float *uniform_f32(const void *prepared) {
   const uint64_t v = (uint64_t)prepared;
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -343,7 +338,7 @@ N6_DEV void roe_R1(const Roe1 &w, float R[3][3]) {
 // Roe average, and the state qc and pressure pc of the cell to the right of
 // the face (cell k of the line; a ghost for the line's last face).
 N6_DEV void setup1d(const Line1D &ln, const float *__restrict__ q, const Face1 &fa, float s[6][6],
-                    Roe1 &rw, float qc[3], float &pc) {
+                    Roe1 &rw, float qc[3], float &pc, bool *flat = nullptr) {
   // No implicit contraction: every fused multiply-add is written out, so the
   // six cells of a stencil go through the same operations (equal cells give
   // bitwise equal stencil values) and a face computed twice gives the same bits.
@@ -377,6 +372,12 @@ N6_DEV void setup1d(const Line1D &ln, const float *__restrict__ q, const Face1 &
 #pragma unroll
   for (int v = 0; v < 3; ++v) qc[v] = qs[3][v];
   pc = pp[3];
+  if (flat) {  // six equal cells: every split stencil is constant
+    bool f = true;
+#pragma unroll
+    for (int j = 1; j < 6; ++j) f = f && qs[j][0] == qs[0][0] && qs[j][1] == qs[0][1] && qs[j][2] == qs[0][2];
+    *flat = f;
+  }
   // Roe average of cells i (j = 2) and i+1 (j = 3)
   const float sL = __builtin_amdgcn_sqrtf(qs[2][0]), sR = __builtin_amdgcn_sqrtf(qs[3][0]);
   const float id = __builtin_amdgcn_rcpf(sL + sR);
@@ -896,70 +897,6 @@ N6_DEV bool queue_slot(const QueueSlots &qs, int64_t i, int64_t nf, int64_t &pos
   return j < c;
 }
 
-// The same FP32 network with each layer's operands loaded from the table
-// just before the layer (through opaque pointers, so the loads stay there):
-// at most one layer's weights hold registers, for callers that keep other
-// state live around it.
-N6_DEV void mlp_f32_stream(const void *prepared, int lane, const float x[6], int h, float z[4]) {
-  const f32x16 zero = {};
-  const float *base = (const float *)((const char *)prepared + PREP_F32_OFF);
-  const float *t = (const float *)opaque(base) + lane;
-  f32x16 c1a = zero, c1b = zero;
-#pragma unroll
-  for (int tt = 0; tt < 4; ++tt) {
-    const int k = 2 * tt + h;
-    float b = 0.f;
-#pragma unroll
-    for (int kk = 0; kk < 6; ++kk) b = k == kk ? x[kk] : b;
-    b = k == 6 ? 1.f : b;
-    c1a = mma32(t[(F32_A1 + tt) * 64], b, c1a);
-    c1b = mma32(t[(F32_A1 + 4 + tt) * 64], b, c1b);
-  }
-  c1a = relu16(c1a);
-  c1b = relu16(c1b);
-  t = (const float *)opaque(base) + lane;
-  f32x16 c2, c2o = zero;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) c2[r] = t[(F32_B2 + r) * 64];
-#pragma unroll
-  for (int tt = 0; tt < 16; tt += 2) {
-    c2 = mma32(t[(F32_A2 + tt) * 64], c1a[tt], c2);
-    c2o = mma32(t[(F32_A2 + tt + 1) * 64], c1a[tt + 1], c2o);
-  }
-#pragma unroll
-  for (int tt = 0; tt < 16; tt += 2) {
-    c2 = mma32(t[(F32_A2 + 16 + tt) * 64], c1b[tt], c2);
-    c2o = mma32(t[(F32_A2 + 16 + tt + 1) * 64], c1b[tt + 1], c2o);
-  }
-#pragma unroll
-  for (int r = 0; r < 16; ++r) c2[r] = fmaxf(c2[r] + c2o[r], 0.f);
-  t = (const float *)opaque(base) + lane;
-  f32x16 c3, c3o = zero;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) c3[r] = t[(F32_B3 + r) * 64];
-#pragma unroll
-  for (int tt = 0; tt < 16; tt += 2) {
-    c3 = mma32(t[(F32_A3 + tt) * 64], c2[tt], c3);
-    c3o = mma32(t[(F32_A3 + tt + 1) * 64], c2[tt + 1], c3o);
-  }
-#pragma unroll
-  for (int r = 0; r < 8; ++r) c3[r] = fmaxf(c3[r] + c3o[r], 0.f);
-  t = (const float *)opaque(base) + lane;
-  f32x16 c4;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) c4[r] = t[(F32_B4 + r) * 64];
-#pragma unroll
-  for (int tt = 0; tt < 8; ++tt) c4 = mma32(t[(F32_A4 + tt) * 64], c3[tt], c4);
-#pragma unroll
-  for (int r = 0; r < 4; ++r) c4[r] = fmaxf(c4[r], 0.f);
-  f32x16 c5 = zero;
-#pragma unroll
-  for (int tt = 0; tt < 4; ++tt) c5 = mma32(t[(F32_A5 + tt) * 64], c4[tt], c5);
-  const float *b5 = (const float *)((const char *)prepared + PREP_B5_OFF);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) z[k] = c5[k] + b5[k];
-}
-
 // Split stencil E of 2D face f of sweep dir: the full set-up with the other
 // fields' work left to dead-code elimination.
 template <int E>
@@ -1052,6 +989,152 @@ k_fixup2d(Grid2D gd, int dir, const float *__restrict__ q, const uint8_t *__rest
   }
 }
 
+// ---- FP32 re-check in 16-evaluation passes (1D) --------------------------------------
+// The classifier in FP32 on v_mfma_f32_16x16x4_f32 for up to 16 evaluations,
+// in the same transposed, weight-stationary tiling: lane l = (j, k) with
+// j = l % 16 (evaluation) and k = l / 16 provides K slot k of each step, and
+// the 16x16 accumulator leaves rows 4k + r (r = 0..3) of column j in lane
+// l's register r, which is exactly K slot k of step r of the next layer, so
+// the activations stay in the lanes.  Operand table (k_prepare,
+// register-major, one FP32 value per lane and register):
+//   A1 [8]   L1: output tile T (rows 16T..16T+15) x step s: slot 4s + k
+//            (slots 0..5 features, 6 the folded bias, 7 zero)
+//   A2 [32]  L2: output tile T2 x input tile T1 x register r
+//   A3 [8]   L3: input tile T2 x register r;  A4 [4], A5 [4]: register r
+//            (L4 outputs padded to 16 rows, L5 to 16 rows and 16 inputs)
+//   B2 [8], B3 [4], B4 [4]: biases of L2..L4 in the accumulator layout
+// b5 is added to the logits (rows 0..3: registers 0..3 of lanes 0..15).
+constexpr int F4_A1 = 0, F4_A2 = 8, F4_A3 = 40, F4_A4 = 48, F4_A5 = 52, F4_B2 = 56, F4_B3 = 64,
+              F4_B4 = 68, F4_REGS = 72;
+static_assert(PREP_F4_OFF + F4_REGS * 64 * 4 <= (int)PREP_BYTES &&
+                  PREP_F32_OFF + F32_REGS * 64 * 4 <= PREP_F4_OFF,
+              "prepared block layout");
+
+N6_DEV float f4_table_value(const double *__restrict__ P, int reg, int lane) {
+  const int i = lane % 16, k = lane / 16;
+  double x = 0.0;
+  if (reg < F4_A2) {
+    const int T = reg / 2, slot = 4 * (reg % 2) + k, o = 16 * T + i;
+    x = slot < 6 ? P[OW1 + o * 6 + slot] : (slot == 6 ? P[OB1 + o] : 0.0);
+  } else if (reg < F4_A3) {
+    const int u = reg - F4_A2, T2 = u / 16, T1 = (u % 16) / 4, r = u % 4;
+    x = P[OW2 + (16 * T2 + i) * 64 + 16 * T1 + 4 * k + r];
+  } else if (reg < F4_A4) {
+    const int u = reg - F4_A3, T2 = u / 4, r = u % 4;
+    x = P[OW3 + i * 32 + 16 * T2 + 4 * k + r];
+  } else if (reg < F4_A5) {
+    const int in = 4 * k + (reg - F4_A4);
+    x = i < 8 ? P[OW4 + i * 16 + in] : 0.0;
+  } else if (reg < F4_B2) {
+    const int in = 4 * k + (reg - F4_A5);
+    x = (i < 4 && in < 8) ? P[OW5 + i * 8 + in] : 0.0;
+  } else if (reg < F4_B3) {
+    const int u = reg - F4_B2;
+    x = P[OB2 + 16 * (u / 4) + 4 * k + u % 4];
+  } else if (reg < F4_B4) {
+    x = P[OB3 + 4 * k + (reg - F4_B3)];
+  } else {
+    const int row = 4 * k + (reg - F4_B4);
+    x = row < 8 ? P[OB4 + row] : 0.0;
+  }
+  return (float)x;
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+N6_DEV f32x4 mma4(float a, float b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+N6_DEV f32x4 relu4(f32x4 c) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) c[r] = fmaxf(c[r], 0.f);
+  return c;
+}
+
+// Zero, hidden from the optimiser: loads at an address offset by it are
+// neither hoisted out of a loop nor merged with earlier loads of the same
+// address.
+N6_DEV int opaque_zero() {
+  int z = 0;
+  asm volatile("" : "+s"(z));
+  return z;
+}
+
+// FP32 logits of the 16 evaluations of a pass: lane (j, k) holds the features
+// x of evaluation j; lanes 0..15 return its four logits.  tab: the operand
+// table; b5: the output biases.
+N6_DEV void mlp_f32_16(const float *tab, const float *b5, int lane, const float x[6], float z[4]) {
+  // Each block of operands (L1; each half of L2; L3; L4 with L5) is read
+  // through a freshly hidden offset, all its loads issued before its first
+  // MFMA (the barrier keeps them together): one memory round trip per block,
+  // and the loads are neither hoisted out of the tile loop (72 registers)
+  // nor issued all at the start of the pass.
+  const int k = lane >> 4;
+  const f32x4 zero = {};
+  const float *t = tab + opaque_zero() + lane;
+  float a1[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) a1[i] = t[(F4_A1 + i) * 64];
+  __builtin_amdgcn_sched_barrier(0);
+  f32x4 c1[4] = {zero, zero, zero, zero};
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int slot = 4 * s + k;
+    float b = 0.f;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) b = slot == q ? x[q] : b;
+    b = slot == 6 ? 1.f : b;
+#pragma unroll
+    for (int T = 0; T < 4; ++T) c1[T] = mma4(a1[2 * T + s], b, c1[T]);
+  }
+#pragma unroll
+  for (int T = 0; T < 4; ++T) c1[T] = relu4(c1[T]);
+  f32x4 c2[2];
+#pragma unroll
+  for (int T2 = 0; T2 < 2; ++T2) {
+    t = tab + opaque_zero() + lane;
+    float a2[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) a2[i] = t[(F4_A2 + 16 * T2 + i) * 64];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) c2[T2][r] = t[(F4_B2 + 4 * T2 + r) * 64];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int T1 = 0; T1 < 4; ++T1)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) c2[T2] = mma4(a2[4 * T1 + r], c1[T1][r], c2[T2]);
+    c2[T2] = relu4(c2[T2]);
+  }
+  t = tab + opaque_zero() + lane;
+  float a3[8];
+  f32x4 c3;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) a3[i] = t[(F4_A3 + i) * 64];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) c3[r] = t[(F4_B3 + r) * 64];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int T2 = 0; T2 < 2; ++T2)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) c3 = mma4(a3[4 * T2 + r], c2[T2][r], c3);
+  c3 = relu4(c3);
+  t = tab + opaque_zero() + lane;
+  float a4[4], a5[4];
+  f32x4 c4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    a4[r] = t[(F4_A4 + r) * 64];
+    a5[r] = t[(F4_A5 + r) * 64];
+    c4[r] = t[(F4_B4 + r) * 64];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) c4 = mma4(a4[r], c3[r], c4);
+  c4 = relu4(c4);
+  f32x4 c5 = zero;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) c5 = mma4(a5[r], c4[r], c5);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) z[r] = c5[r] + b5[r];
+}
+
 // ---- 1D Euler: one fused pass per right-hand side -------------------------------------
 // Tiles of 64 consecutive faces g = 63 t + lane of the batch, one wave each,
 // overlapping by one face (lane 63's face is lane 0 of the next tile).  Lane
@@ -1059,30 +1142,16 @@ k_fixup2d(Grid2D gd, int dir, const float *__restrict__ q, const uint8_t *__rest
 // one line, so a tile holds every flux its cells need and no data moves
 // between waves; lane 63 only completes lane 62's cell.  Faces (their
 // fluxes in OUT_FACES mode, their labels) are written by lanes 0..62, and by
-// lane 63 in the last tile.
+// lane 63 in the last tile.  A face computed by two tiles gets the same bits
+// in both: its arithmetic does not depend on the lane it runs in.
 //
-// Near-cutoff evaluations: a face with an evaluation whose smallest |logit|
-// lies below the margin is pending, and the cells next to it are not written
-// with the tile.  The face goes into a per-wave list in LDS (face, labels and
-// near bits of it and of its two neighbours, which of its cells the tile
-// owns).  Once a tile brings the list to RFLUSH faces, and after the last
-// tile, the wave flushes it: every near evaluation of the listed faces is
-// evaluated again in FP32 on MFMA (32 per pass) and its label replaces the
-// reduced-precision one; then the fluxes of the pending faces and of their
-// neighbours are recomputed with the final labels, the same arithmetic as in
-// the tile, and the pending cells written.  A pending cell is written once:
-// by its right face's record if that face is pending, else by its left
-// face's.  The stage output of a pending cell reads u0 before anything
-// writes that cell (only its owner touches it), so stage 3 may write the
-// state in place.
-constexpr int RFLUSH = 32;             // flush once this many faces are pending
-constexpr int RCAP = RFLUSH - 1 + 64;  // list capacity per wave
-// Record words: [0] face g; [1] labels of g (byte m: field m, '+' in the low
-// nibble) | its near bits << 24; [2] labels of g - 1 | its near bits << 24 |
-// cell (g-1, g) owned << 30 | face g owned << 31; [3] labels of g + 1 | its
-// near bits << 24 | cell (g, g+1) owned << 30.
-constexpr u32 LAB_MASK = 0xffffffu;
-
+// Near-cutoff evaluations (smallest |logit| below the margin) are evaluated
+// again in FP32 before the combine, in the tile itself: they are listed in
+// LDS, 16 per FP32 MFMA pass form their features from the stash, and the FP32
+// labels replace the reduced-precision ones.  A few tenths of a percent of
+// the evaluations are near, about one per tile, so a pass costs the tile
+// less than half of its MFMA work, on a pipe the tile keeps less than half
+// busy.
 
 // Output of cell kc of the line of fa, between fluxes Fl (left face) and Fr.
 N6_DEV void cell_out(const Line1D &ln, const Out1D &out, const Face1 &fa, int kc, const float qc[3],
@@ -1107,145 +1176,43 @@ N6_DEV void cell_out(const Line1D &ln, const Out1D &out, const Face1 &fa, int kc
   }
 }
 
-// Flux of face fa with the given labels, and the state of the cell to its right.
-N6_DEV void face_flux1d(const Line1D &ln, const float *__restrict__ q, const Face1 &fa, u32 labels,
-                        float F[3], float qc[3], float &pc) {
-  float s[6][6], R[3][3], hs[3];
-  Roe1 rw;
-  setup1d(ln, q, fa, s, rw, qc, pc);
-#pragma unroll
-  for (int m = 0; m < 3; ++m)
-    hs[m] = combine_pair(s[2 * m], (labels >> (8 * m)) & 15u, s[2 * m + 1], (labels >> (8 * m + 4)) & 15u);
-  roe_R1(rw, R);
-  back_project<3>(R, hs, F);
-}
-
-// Flush of a wave's pending faces (all 64 lanes; see above).  list: scratch
-// for RCAP * 6 entries (the wave's stash, free between tiles).
-N6_DEV void flush1d(const Line1D &ln, const void *__restrict__ prepared, const float *__restrict__ q,
-                    u32 (*rec)[RCAP], u32 *list, int npend, const Out1D &out, int lane) {
-  const int64_t nf = ln.faces();
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  // (record, kind) of every near evaluation, in record order
-  int nev = 0;
-  for (int r0 = 0; r0 < npend; r0 += 64) {
-    const int r = r0 + lane;
-    const u32 nb = r < npend ? (rec[1][r] >> 24) & 63u : 0u;
-    const u32 c = (u32)__popc(nb);
-    u32 inc = c;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const u32 t = __shfl_up(inc, o);
-      inc += lane >= o ? t : 0u;
-    }
-    u32 pos = (u32)nev + inc - c, m = nb;
-    while (m) {
-      list[pos++] = ((u32)r << 3) | (u32)(__ffs(m) - 1);
-      m &= m - 1u;
-    }
-    nev += (int)__shfl(inc, 63);
-  }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  // FP32 labels: lanes j and j + 32 carry entry j of a pass of 32.  The
-  // stencil is formed first, and the FP32 weights come in layer by layer.
-  {
-    const int j = lane & 31, h = lane >> 5;
-    for (int b0 = 0; b0 < nev; b0 += 32) {
-      const int i = b0 + j;
-      const bool ok = i < nev;
-      const u32 ent = list[ok ? i : b0];
-      const int r = (int)(ent >> 3), e = (int)(ent & 7u);
-      float x[6], z[4];
-      {
-        float s[6][6], qc[3], pc;
-        Roe1 rw;
-        setup1d(ln, q, face1(ln, (int64_t)rec[0][r]), s, rw, qc, pc);
-        float se[6];
-#pragma unroll
-        for (int jj = 0; jj < 6; ++jj) {
-          float v = s[0][jj];
-#pragma unroll
-          for (int k = 1; k < 6; ++k) v = e == k ? s[k][jj] : v;
-          se[jj] = v;
-        }
-        features<float>(se, x);
-      }
-      mlp_f32_stream(prepared, lane, x, h, z);
-      if (h == 0 && ok) {
-        const u32 lab = mask_from_logits<float>(z);
-        const u32 sh = 8u * (u32)(e >> 1) + 4u * (u32)(e & 1);
-        const u32 old = (rec[1][r] >> sh) & 15u;  // other kinds of the face touch other nibbles
-        if (old != lab) atomicXor(&rec[1][r], (old ^ lab) << sh);
-      }
-    }
-  }
-  if (out.nrecheck && lane == 0) atomicAdd(out.nrecheck, (u32)nev);
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  // pending cells and faces, with the final labels
-  for (int r0 = 0; r0 < npend; r0 += 64) {
-    const int r = r0 + lane;
-    if (r < npend) {
-      const u32 g = rec[0][r], mg = rec[1][r] & LAB_MASK, wl = rec[2][r], wr = rec[3][r];
-      const bool own_face = (wl >> 31) != 0u, own_l = ((wl >> 30) & 1u) != 0u;
-      const bool own_r = ((wr >> 30) & 1u) != 0u && ((wr >> 24) & 63u) == 0u;
-      // a pending left neighbour is the previous record (same tile, lane order)
-      const u32 ml = ((wl >> 24) & 63u) ? rec[1][r - 1] & LAB_MASK : wl & LAB_MASK;
-      const Face1 fa = face1(ln, (int64_t)g);
-      float Fg[3], qg[3], pg;
-      face_flux1d(ln, q, fa, mg, Fg, qg, pg);
-      if (own_l) {  // cell k - 1, between faces g - 1 and g
-        Face1 fl = fa;
-        fl.k -= 1;
-        float Fl[3], ql[3], pl;
-        face_flux1d(ln, q, fl, ml, Fl, ql, pl);
-        cell_out(ln, out, fa, fa.k - 1, ql, pl, Fl, Fg);
-      }
-      if (own_r) {  // cell k, between faces g and g + 1 (not pending)
-        Face1 fr = fa;
-        fr.k += 1;
-        float Fr[3], qr[3], pr;
-        face_flux1d(ln, q, fr, wr & LAB_MASK, Fr, qr, pr);
-        cell_out(ln, out, fa, fa.k, qg, pg, Fg, Fr);
-      }
-      if (own_face) {
-        if (out.mode == OUT_FACES) {
-#pragma unroll
-          for (int v = 0; v < 3; ++v) out.dst[v * nf + g] = Fg[v];
-        }
-        if (out.masks) {
-#pragma unroll
-          for (int m = 0; m < 3; ++m) out.masks[m * nf + g] = (uint8_t)(mg >> (8 * m));
-        }
-      }
-    }
-  }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-}
+// Counters of re-checked evaluations (diagnostic): a wave adds its count to
+// slot (workgroup * waves + wave) % NRECHECK_SLOTS, so few waves share one.
+constexpr int NRECHECK_SLOTS = QCOUNTERS;
 
 // The fused 1D Euler pass.  Three waves per SIMD (a few registers spill; the
 // third wave hides more of the MFMA -> convert -> MFMA latency).
+//
+// Flat faces (six equal cells): every split stencil is constant, and the
+// re-normalised combination of a constant stencil is that constant for every
+// selection (the weights sum to one), so the pass takes it exactly
+// (h = s_2) and the flux does not depend on the labels.  Near-cutoff
+// evaluations of flat faces are then re-checked only when the caller asks
+// for the labels (out.masks); they are most of the near evaluations of
+// piecewise-constant data.
 template <int PREC, int W, bool MLP>
 __global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(3)))
 k_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float margin,
           const float *__restrict__ q, const uint8_t *__restrict__ min, Out1D out, int xcd) {
   // stash slots per lane: the six split stencils, the Roe average, the
-  // state and pressure of the cell to the right, the line
+  // state and pressure of the cell to the right, the line and the flat flag
   constexpr int NE = 6, S_ROE = NE * 6, S_QC = S_ROE + 4, S_LINE = S_QC + 4, NS = S_LINE + 1;
   __shared__ float stash[W][NS][64];
-  __shared__ u32 rec[W][4][MLP ? RCAP : 1];
-  static_assert(NS * 64 >= RCAP * 6, "the flush list fits in the stash");
+  // re-check list (lane << 3 | kind) and the FP32 labels (kind, lane)
+  __shared__ uint16_t relist[W][MLP ? NE * 64 : 1];
+  __shared__ uint8_t relab[W][MLP ? NE : 1][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t nf = ln.faces();
   const int64_t ntile = (nf + 61) / 63;  // faces 63 t .. 63 t + 63 cover 0 .. nf - 1
   const int64_t nb = gridDim.x;
   const int64_t lb = xcd ? (int64_t)(blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8 : blockIdx.x;
-  // Segments of tiles between flushes: the weights are loaded at the start
-  // of each, so that they hold no registers while a flush runs.
-  for (int64_t t = lb * W + wv; t < ntile;) {
   Wts w;
-  if constexpr (MLP) load_wts<PREC>(opaque(prepared), lane, w);
-  int npend = 0;  // wave-uniform
-  for (; t < ntile; t += nb * W) {
+  const float *b5 = (const float *)((const char *)prepared + PREP_B5_OFF);
+  const float *f4tab = (const float *)((const char *)prepared + PREP_F4_OFF);
+  const bool need_labels = out.masks != nullptr;
+  if constexpr (MLP) load_wts<PREC>(prepared, lane, w);
+  u32 nre = 0u;  // evaluations this wave re-checked
+  for (int64_t t = lb * W + wv; t < ntile; t += nb * W) {
     const int64_t g = t * 63 + lane;
     const bool valid = g < nf;
     u32 fx[NE][3];
@@ -1255,7 +1222,8 @@ k_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float marg
       const Face1 fa = face1(ln, valid ? g : nf - 1);
       float s[NE][6], qc[3], pc;
       Roe1 rw;
-      setup1d(ln, q, fa, s, rw, qc, pc);
+      bool flat;
+      setup1d(ln, q, fa, s, rw, qc, pc, &flat);
       if constexpr (MLP) {
 #pragma unroll
         for (int e = 0; e < NE; ++e) feature_pack<PREC>(s[e], fx[e][0], fx[e][1], fx[e][2]);
@@ -1271,7 +1239,7 @@ k_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float marg
 #pragma unroll
       for (int v = 0; v < 3; ++v) stash[wv][S_QC + v][lane] = qc[v];
       stash[wv][S_QC + 3][lane] = pc;
-      stash[wv][S_LINE][lane] = __builtin_bit_cast(float, fa.p);
+      stash[wv][S_LINE][lane] = __builtin_bit_cast(float, flat ? -1 - fa.p : fa.p);
     }
     u32 sel[NE], near = 0u;
     // the classifier phase at raised wave priority: its MFMA -> convert
@@ -1299,8 +1267,49 @@ k_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float marg
       }
     }
     __builtin_amdgcn_sched_barrier(0);
-    if constexpr (MLP) __builtin_amdgcn_s_setprio(0);
-    near = valid ? near : 0u;
+    const int pl = __builtin_bit_cast(int, stash[wv][S_LINE][lane]);
+    const bool flat = pl < 0;
+    if constexpr (MLP) {
+      __builtin_amdgcn_s_setprio(0);
+      near = valid ? near : 0u;
+      // labels of flat faces do not change the flux (see above)
+      const u32 want = (flat && !need_labels) ? 0u : near;
+      if (__ballot(want != 0u) != 0ull) {  // wave-uniform
+        // list the evaluations: lane l's entries after those of lanes < l
+        const u32 c = (u32)__popc(want);
+        u32 inc = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const u32 tt = __shfl_up(inc, o);
+          inc += lane >= o ? tt : 0u;
+        }
+        const int nnear = (int)__shfl(inc, 63);
+        u32 pos = inc - c, m = want;
+        while (m) {
+          relist[wv][pos++] = (uint16_t)(((u32)lane << 3) | (u32)(__ffs(m) - 1));
+          m &= m - 1u;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const int jcol = lane & 15;
+        for (int b0 = 0; b0 < nnear; b0 += 16) {
+          const int i = b0 + jcol;
+          const bool ok = i < nnear;
+          const u32 ent = relist[wv][ok ? i : b0];
+          const int src = (int)(ent >> 3), e = (int)(ent & 7u);
+          float se[6], x[6], z[4];
+#pragma unroll
+          for (int j = 0; j < 6; ++j) se[j] = stash[wv][e * 6 + j][src];
+          features<float>(se, x);
+          mlp_f32_16(f4tab, b5, lane, x, z);
+          if (lane < 16 && ok) relab[wv][e][src] = (uint8_t)mask_from_logits<float>(z);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+        for (int e = 0; e < NE; ++e)
+          if ((want >> e) & 1u) sel[e] = relab[wv][e][lane];
+        nre += (u32)nnear;
+      }
+    }
     float hs[3], F[3], R[3][3];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
@@ -1310,7 +1319,8 @@ k_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float marg
         sp[j] = stash[wv][(2 * m) * 6 + j][lane];
         sm[j] = stash[wv][(2 * m + 1) * 6 + j][lane];
       }
-      hs[m] = combine_pair(sp, sel[2 * m], sm, sel[2 * m + 1]);
+      // a flat face's combine is its constant, exactly
+      hs[m] = flat ? sp[2] + sm[2] : combine_pair(sp, sel[2 * m], sm, sel[2 * m + 1]);
     }
     roe_R1(Roe1{stash[wv][S_ROE][lane], stash[wv][S_ROE + 1][lane], stash[wv][S_ROE + 2][lane],
                 stash[wv][S_ROE + 3][lane]},
@@ -1321,65 +1331,34 @@ k_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float marg
     for (int v = 0; v < 3; ++v) qc[v] = stash[wv][S_QC + v][lane];
     const float pc = stash[wv][S_QC + 3][lane];
     Face1 fa;
-    fa.p = __builtin_bit_cast(int, stash[wv][S_LINE][lane]);
+    fa.p = flat ? -1 - pl : pl;
     {
       const int64_t o = ln.offsets[fa.p];
       fa.o = (uint32_t)o;
       fa.n = (int)(ln.offsets[fa.p + 1] - o);
       fa.k = (int)((valid ? g : nf - 1) - o - fa.p);
     }
-    u32 mw = 0u;
-#pragma unroll
-    for (int m = 0; m < 3; ++m) mw |= (sel[2 * m] | (sel[2 * m + 1] << 4)) << (8 * m);
-    // the neighbouring faces of the tile: every lane takes part in the
-    // shuffles (a lane outside a conditional would supply no value), and
-    // the edge lanes' results are masked afterwards
+    // the next face's flux: every lane takes part in the shuffle (a lane
+    // outside a conditional would supply no value)
     float Fr[3];
 #pragma unroll
     for (int v = 0; v < 3; ++v) Fr[v] = __shfl_down(F[v], 1);
-    const u32 near_dn = __shfl_down(near, 1), near_up = __shfl_up(near, 1);
-    const u32 mw_dn = __shfl_down(mw, 1), mw_up = __shfl_up(mw, 1);
-    const u32 near_r = lane < 63 ? near_dn : 0u;
     const bool own_face = valid && (lane < 63 || t == ntile - 1);
     const bool own_cell = valid && lane < 63 && fa.k < fa.n;
-    if (own_cell && (near | near_r) == 0u) cell_out(ln, out, fa, fa.k, qc, pc, F, Fr);
-    if (own_face && near == 0u) {
+    if (own_cell) cell_out(ln, out, fa, fa.k, qc, pc, F, Fr);
+    if (own_face) {
       if (out.mode == OUT_FACES) {
 #pragma unroll
         for (int v = 0; v < 3; ++v) out.dst[v * nf + g] = F[v];
       }
       if (out.masks) {
 #pragma unroll
-        for (int m = 0; m < 3; ++m) out.masks[m * nf + g] = (uint8_t)(mw >> (8 * m));
-      }
-    }
-    if constexpr (MLP) {
-      const u32 near_l = lane >= 1 ? near_up : 0u;
-      const u32 mw_l = mw_up, mw_r = mw_dn;
-      const uint64_t bal = __ballot(near != 0u);
-      if (bal != 0ull) {
-        if (near != 0u) {
-          const int pos = npend + (int)__popcll(bal & ((1ull << lane) - 1ull));
-          const bool own_l = lane >= 1 && fa.k >= 1;
-          const bool own_r = lane < 63 && fa.k < fa.n;
-          rec[wv][0][pos] = (u32)g;
-          rec[wv][1][pos] = mw | (near << 24);
-          rec[wv][2][pos] = (mw_l & LAB_MASK) | (near_l << 24) | (own_l ? 1u << 30 : 0u) |
-                            (own_face ? 1u << 31 : 0u);
-          rec[wv][3][pos] = (mw_r & LAB_MASK) | (near_r << 24) | (own_r ? 1u << 30 : 0u);
-        }
-        npend += (int)__popcll(bal);
-        if (npend >= RFLUSH) {
-          t += nb * W;
-          break;
-        }
+        for (int m = 0; m < 3; ++m) out.masks[m * nf + g] = (uint8_t)(sel[2 * m] | (sel[2 * m + 1] << 4));
       }
     }
   }
-  if constexpr (MLP) {
-    if (npend > 0) flush1d(ln, prepared, q, rec[wv], (u32 *)&stash[wv][0][0], npend, out, lane);
-  }
-  }
+  if (MLP && out.nrecheck && lane == 0 && nre)
+    atomicAdd(out.nrecheck + (blockIdx.x * W + wv) % NRECHECK_SLOTS, nre);
 }
 
 // Scalar stencils (reconstruction, advection, classifier on its own): one
@@ -1575,6 +1554,7 @@ N6_DEV void prepare_entry(const double *__restrict__ P, const double *__restrict
   if (t < NPARAM) ((float *)prep)[t] = (float)P[t];
   if (t < 4) ((float *)(prep + PREP_B5_OFF))[t] = (float)P[OB5 + t];
   if (t < F32_REGS * 64) ((float *)(prep + PREP_F32_OFF))[t] = f32_table_value(P, t / 64, t % 64);
+  if (t < F4_REGS * 64) ((float *)(prep + PREP_F4_OFF))[t] = f4_table_value(P, t / 64, t % 64);
   if (t >= TAB_REGS * 64) return;
   auto sc = [&](int base, int i) { return S ? S[base + i] : 1.0; };
   const int reg = t / 64, lane = t % 64, i = lane % 32, h = lane / 32;

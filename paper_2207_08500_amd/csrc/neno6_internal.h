@@ -9,10 +9,11 @@
 
 namespace n6 {
 
-// Re-check counters in the workspace, one per evaluation kind (field * 2 +
-// sign): 1D uses six, 2D eight per sweep direction (sweep d at 8 * d); all
-// are cleared together.
-constexpr int QCOUNTERS = 16;
+// Re-check counters in the workspace: 2D uses one per evaluation kind
+// (field * 2 + sign), eight per sweep direction (sweep d at 8 * d); 1D spreads
+// its diagnostic count of re-checked evaluations over all of them.  All are
+// cleared together.
+constexpr int QCOUNTERS = 64;
 
 struct Line1D {            // a batch of independent 1D lines
   const int64_t *offsets;  // [dev] cell offsets [np+1]

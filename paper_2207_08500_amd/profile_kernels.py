@@ -15,7 +15,8 @@ the BF16 pass (as the benchmark does; it prints the shape); with --shape W,B
 that many waves per workgroup and workgroups; else the library default.
 With --steps K: instead, K SSP-RK3 steps of the BF16 path with the re-check
 (margin 0.5), captured once in a HIP graph and replayed after 400 warm-up
-replays (40 with --2d); a one-element torch fill right before the timed
+replays (40 with --2d), in the --shape launch shape if given, else the
+autotuner's; a one-element torch fill right before the timed
 replays marks where they start in a kernel trace.  --2d: the 2D Euler
 four-quadrant Riemann problem on 2048 x 2048 cells instead of the 1D batch.
 """
@@ -51,7 +52,7 @@ def main():
     if a.steps > 0 and a.two_d:
         return step_replay_2d(a.steps, P, dev)
     if a.steps > 0:
-        return step_replay(a.steps, P, q32, off, dx, dev)
+        return step_replay(a.steps, P, q32, off, dx, dev, a.shape)
     shape = None
     if a.shape:
         w_, b_ = (int(x) for x in a.shape.split(","))
@@ -92,13 +93,18 @@ def main():
           % (a.reps, a.copy_mib))
 
 
-def step_replay(steps, P, q32, off, dx, dev):
+def step_replay(steps, P, q32, off, dx, dev, shape_arg=None):
     from paper_2207_08500_amd import autotune
     mlp = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=0.5)
     prob = native.Problem(native.EULER1D, native.BF16, native.SEL_MLP, native.TRANSMISSIVE, off, dx,
                           device=dev)
     ws = prob.workspace(dev)
-    shape = autotune.tuned(prob, mlp, q32, ws)[0]
+    if shape_arg:
+        w_, b_ = (int(x) for x in shape_arg.split(","))
+        shape = {"face_waves": w_, "face_blocks": b_}
+        prob.set_tuning(shape)
+    else:
+        shape = autotune.tuned(prob, mlp, q32, ws)[0]
     n = off.size - 1
     q = q32.clone()
     t = torch.zeros(n, dtype=torch.float64, device=dev)
