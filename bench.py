@@ -1,23 +1,25 @@
 #!/usr/bin/env python3
 """Reconstructed faces/s of the NENO6 hot path on one MI355X.
 
-Workload: 256 independent 1D Euler Riemann problems of 4000 cells each
-(seeded synthetic states, gamma = 1.4, transmissive boundaries), the
-6-64-32-16-8-4 classifier with oracle-trained weights.  One step = one SSP-RK3
-step of the whole batch (time step from the CFL condition, three right-hand
-sides: characteristic projection, Rusanov split, classifier per field and
-sign, re-normalised combine, back-projection, flux difference, stage update);
-ten steps are captured once in a HIP graph and replayed (one per replay when
-the step counts are not multiples of ten).
+Default workload: 4096 independent 1D Euler Riemann problems with N drawn
+log-uniformly from [256, 16384] (15.6 M cells; seeded synthetic states,
+gamma = 1.4, transmissive boundaries), the 6-64-32-16-8-4 classifier with
+oracle-trained weights.  One step = one SSP-RK3 step of the whole batch (time
+step from the CFL condition, three right-hand sides: characteristic
+projection, Rusanov split, classifier per field and sign with the FP32
+re-check near the cutoff, re-normalised combine, back-projection, flux
+difference, stage update); ten steps are captured once in a HIP graph and
+replayed.
 
-Headline path: FP32 state, classifier in BF16 on MFMA with the FP32 re-check.
-Also measured on the same GPU: the plain FP64 path and FP16-MFMA, the flip
-rate of the BF16 labels against the FP64 labels on the same input state, the
-L1 / Linf distance of the BF16 state from the FP64 state after the timed
-steps, the fused face kernel alone (roofline), and the FP64 CPU oracle on a
-bounded sample (cpu_baseline).
+Headline path: FP32 state, classifier in BF16 on MFMA.  Also measured on the
+same GPU: the plain FP64 path and FP16-MFMA; the labels of the BF16 pass
+against the FP64 labels on the FP64 path's state after the timed steps
+(flip rate); the L1 / Linf distance of the BF16 state from the FP64 state
+after the same steps; the fused kernel alone (roofline); the FP64 CPU oracle
+on a bounded sample (cpu_baseline); and the same measurements for the
+256 x 4000-cell batch (nested under "c2").
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4|c2|c3|c5]
 """
 import argparse
 import json
@@ -28,8 +30,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-N_PROBLEMS, N_CELLS, CFL = 256, 4000, 0.4
-MARGIN = {2: 0.5, 3: 0.25}
+CFL = 0.4
+MARGIN = {2: 0.5, 3: 0.25}  # FP32 re-check margins in logit units (BF16, FP16)
 PEAK_MFMA_BF16 = 2500.0  # TFLOP/s dense, MI355X
 PEAK_HBM_GBS = 8000.0    # HBM3E, MI355X
 # non-packed VALU lane-operations/s: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
@@ -48,16 +50,16 @@ VALU_OPS_PER_FACE_2D = 1814
 EVALS_PER_FACE_2D = 8
 FLOP_PER_EVAL = 6208      # 2 x 3104 MAC of the 6-64-32-16-8-4 network
 EVALS_PER_FACE = 6        # 3 characteristic fields x 2 split signs
+METRIC = "reconstructed faces/s: plain FP64 vs BF16-MFMA NENO6 at stated flip rate/L1 error"
 
-
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "euler1d_c2_256x4000_hbm_traffic.md")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "euler1d_c4_4096_uneven_hbm_traffic.md")
 
 
 def _traffic_record():
-    """The committed FETCH_SIZE / WRITE_SIZE record of the fused kernel (HBM
-    bytes per launch scaled by the copy-kernel calibration, and the launch
-    shape the counters were taken with), or None when the kernel sources
-    changed since the counters were taken."""
+    """The committed FETCH_SIZE / WRITE_SIZE record of the fused kernel on the
+    4096-problem batch (HBM bytes per launch scaled by the copy-kernel
+    calibration, and the launch shape the counters were taken with), or None
+    when the kernel sources changed since the counters were taken."""
     import hashlib
     try:
         line = [ln for ln in open(TRAFFIC_RECORD) if ln.startswith("traffic-record:")][0]
@@ -72,9 +74,9 @@ def _traffic_record():
 
 
 def _alu(faces, k_ms, ops_per_face=VALU_OPS_PER_FACE):
-    """VALU-issue roofline of the fused kernel (the binding one: see the
-    counter profile): algorithmic lane-operations per launch / time against
-    256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz."""
+    """VALU-issue roofline (the binding one of the fused kernel: see the
+    counter profile): algorithmic lane-operations / time against 256 CUs x 4
+    SIMDs x 16 lanes x 2.4 GHz."""
     ach = faces * ops_per_face / (k_ms / 1e3) / 1e12
     return {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "Tlane-op/s",
             "frac": ach / PEAK_VALU_TOPS, "ops_per_face": ops_per_face}
@@ -92,26 +94,35 @@ def _physical(q, off, gamma=1.4):
     return np.minimum.reduceat(good.astype(np.int8), off[:-1]).astype(bool)
 
 
+def _cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def _args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default: 200 RK3 steps for c2, as the workload runs; "
-                         "20 graph replays for c4)")
-    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 400 / 30 / 5)")
+                    help="timed RK3 steps (c4: 50, c2: 200, c3: 20; c5: Adam steps)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (about 0.1 s)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c2", action="store_true", help="c4: skip the nested 256 x 4000 batch")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", choices=("c2", "c3", "c4", "c5"), default="c2",
-                    help="c2: 256 x 4000-cell batch (headline); c3: 2D Euler four-quadrant "
-                         "Riemann problem on 2048 x 2048 cells; c4: 4096 uneven problems, "
-                         "ten RK3 steps per graph replay, autotuned launch shapes; c5: "
-                         "classifier training, 2^24 samples, batch 65536")
+    ap.add_argument("--workload", choices=("c2", "c3", "c4", "c5"), default="c4",
+                    help="c4: 4096 uneven 1D problems (headline); c2: 256 x 4000-cell batch; "
+                         "c3: 2D Euler four-quadrant Riemann problem on 2048 x 2048 cells; "
+                         "c5: classifier training, 2^24 samples, batch 65536")
     a = ap.parse_args()
     if a.steps is None:
-        a.steps = {"c2": 200, "c3": 20, "c4": 20, "c5": 179}[a.workload]
+        a.steps = {"c2": 200, "c3": 20, "c4": 50, "c5": 179}[a.workload]
     if a.warmup is None:  # about 0.1 s: steady clocks
-        a.warmup = {"c2": 400, "c3": 30, "c4": 5, "c5": 20}[a.workload]
+        a.warmup = {"c2": 400, "c3": 30, "c4": 30, "c5": 20}[a.workload]
     return a
 
 
@@ -124,19 +135,46 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2207_08500_amd import autotune, inputs, native
+    from paper_2207_08500_amd import native
 
     native.load()
     dev = torch.device("cuda:0")
     P = np.load(os.path.join(ROOT, "tests", "golden", "neno6_mlp_trained.npy"), allow_pickle=False)
-    if a.workload == "c4":
-        return bench_batched(a, P, dev)
     if a.workload == "c3":
         return bench_2d(a, P, dev)
     if a.workload == "c5":
         return bench_train(a, dev)
-    q0, off, dx = inputs.riemann1d_batch(inputs.BASE_SEED, (N_CELLS,) * N_PROBLEMS)
-    faces_stage = int(off[-1]) + N_PROBLEMS
+    out = bench_1d(a, P, dev, a.workload)
+    if a.workload == "c4" and not a.no_c2:
+        sub = argparse.Namespace(**vars(a))
+        sub.steps, sub.warmup, sub.no_cpu_baseline = 200, 400, True
+        c2 = bench_1d(sub, P, dev, "c2")
+        keep = ("value", "unit", "ms_per_step", "steps", "config", "roofline", "fp64_plain",
+                "fp16_mfma", "speedup_bf16_vs_fp64", "labels", "l1_rel_vs_fp64",
+                "linf_rel_vs_fp64", "frozen_problems", "end_to_end_valu_frac")
+        out["c2"] = {k: c2[k] for k in keep if k in c2}
+    print(json.dumps(out))
+
+
+def bench_1d(a, P, dev, name):
+    """One 1D Euler batch: the BF16 headline, FP16 and FP64 on the same GPU,
+    labels and errors against the FP64 path, the fused kernel alone, the
+    oracle on the host.  Returns the JSON-ready dict."""
+    import numpy as np
+    import torch
+
+    from paper_2207_08500_amd import autotune, inputs, native
+
+    if name == "c4":
+        sizes = inputs.uneven_sizes(inputs.BASE_SEED, 4096, 256, 16384)
+        label = ("1D Euler batch: 4096 Riemann problems, N log-uniform in [256, 16384] (%d cells)"
+                 % int(sizes.sum()))
+    else:
+        sizes = np.full(256, 4000, np.int64)
+        label = "1D Euler Riemann batch: 256 problems x 4000 cells"
+    n_prob = sizes.size
+    q0, off, dx = inputs.riemann1d_batch(inputs.BASE_SEED, sizes)
+    faces_stage = int(off[-1]) + n_prob
     faces_step = 3 * faces_stage
     q32 = torch.as_tensor(q0, dtype=torch.float32, device=dev).contiguous()
     q64_from32 = q32.double().contiguous()  # the same (FP32-rounded) state for both paths
@@ -148,19 +186,17 @@ def main():
         return mlp, prob, prob.workspace(dev)
 
     shapes_used = {}
-    per_graph = {}
 
     def run_steps(prec, q_init, steps, warmup, graph=True):
-        # ten RK3 steps per graph replay when both counts allow (about 1 %
-        # faster than one: fewer replay boundaries), else one
+        """steps RK3 steps from q_init after warmup untimed ones (ten per
+        HIP-graph replay when both counts allow, else one)."""
         per = 10 if graph and steps % 10 == 0 and warmup % 10 == 0 else 1
-        per_graph[prec] = per
         mlp, prob, ws = make(prec, MARGIN.get(prec, 0.0))
         if prec in (native.BF16, native.FP16):  # launch shapes from the autotuner (cached)
             shapes_used[prec] = autotune.tuned(prob, mlp, q_init, ws)[0]
         q = q_init.clone()
-        t = torch.zeros(N_PROBLEMS, dtype=torch.float64, device=dev)
-        st = torch.zeros(N_PROBLEMS, dtype=torch.int32, device=dev)
+        t = torch.zeros(n_prob, dtype=torch.float64, device=dev)
+        st = torch.zeros(n_prob, dtype=torch.int32, device=dev)
 
         def step():
             native.neno6_step(prob, mlp, q, CFL, per, t, st, ws)
@@ -170,12 +206,9 @@ def main():
             s = torch.cuda.Stream()
             s.wait_stream(torch.cuda.current_stream())
             with torch.cuda.stream(s):
-                step()  # one eager step before capture
+                native.neno6_step(prob, mlp, q, CFL, 1, t, st, ws, stream=s)  # builds the face map
             torch.cuda.current_stream().wait_stream(s)
-            q.copy_(q_init)
-            t.zero_()
-            st.zero_()
-            prob.flags = native.KEEP_MAP  # the workspace holds the face map from the eager step
+            prob.flags = native.KEEP_MAP
             try:
                 g = torch.cuda.CUDAGraph()
                 with torch.cuda.graph(g):
@@ -183,10 +216,10 @@ def main():
             except Exception as e:  # pragma: no cover - capture problems are reported
                 print("graph capture failed, eager launches: %s" % e, file=sys.stderr)
                 g = None
-            q.copy_(q_init)
-            t.zero_()
-            st.zero_()
         go = g.replay if g is not None else step
+        q.copy_(q_init)
+        t.zero_()
+        st.zero_()
         for _ in range(warmup // per):
             go()
         torch.cuda.synchronize()
@@ -195,50 +228,58 @@ def main():
         st.zero_()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
         e0.record()
         for _ in range(steps // per):
             go()
         e1.record()
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ms = e0.elapsed_time(e1)
-        return q, t, st, ms, wall, g is not None
+        return q, t, st, e0.elapsed_time(e1), per, g is not None
 
     # ---- headline: BF16-MFMA ---------------------------------------------------
-    qb, tb, stb, ms_b, wall_b, graphed = run_steps(native.BF16, q32, a.steps, a.warmup,
-                                                   graph=not a.no_graph)
+    qb, tb, stb, ms_b, per_b, graphed = run_steps(native.BF16, q32, a.steps, a.warmup,
+                                                  graph=not a.no_graph)
     value = faces_step * a.steps / (ms_b / 1e3)
-    # ---- same GPU: FP64 plain and FP16-MFMA --------------------------------------
-    k64 = max(2, a.steps // 4)
-    q64, t64, st64, ms_64, _, _ = run_steps(native.FP64, q64_from32, k64, 1, graph=not a.no_graph)
-    fp64_rate = faces_step * k64 / (ms_64 / 1e3)
-    qh, th, sth, ms_h, _, _ = run_steps(native.FP16, q32, a.steps, 1, graph=not a.no_graph)
+    # ---- same GPU: FP16-MFMA and the plain FP64 path ------------------------------
+    qh, th, sth, ms_h, _, _ = run_steps(native.FP16, q32, a.steps, a.warmup, graph=not a.no_graph)
     fp16_rate = faces_step * a.steps / (ms_h / 1e3)
-    # accuracy of the timed BF16 run against an FP64 run of the same number of steps
-    q64b, t64b, st64b, _, _, _ = run_steps(native.FP64, q64_from32, a.steps, 0, graph=not a.no_graph)
-    # problems whose state turned non-physical (no positivity limiter in the
-    # scheme) are frozen by the solver and left out of the error norms
-    okp = ((stb == 0) & (st64b == 0)).cpu().numpy() & _physical(qb, off) & _physical(q64b, off)
-    frozen_b, frozen_64 = int((stb != 0).sum()), int((st64b != 0).sum())
-    cell_ok = torch.as_tensor(np.repeat(okp, np.diff(off)), device=dev)
-    dq = (qb.double() - q64b).abs().reshape(3, -1)[:, cell_ok]
-    ref = q64b.reshape(3, -1)[:, cell_ok]
-    l1 = float((dq.mean(dim=1) / ref.abs().mean(dim=1)).max())
-    linf = float((dq.max(dim=1).values / ref.abs().max(dim=1).values).max())
+    k64 = 2 if name == "c4" else max(2, a.steps // 4)
+    _, _, _, ms_64, _, _ = run_steps(native.FP64, q64_from32, k64, 1, graph=not a.no_graph)
+    fp64_rate = faces_step * k64 / (ms_64 / 1e3)
+    # the FP64 path over the timed steps: the accuracy reference
+    q64b, _, st64b, _, _, _ = run_steps(native.FP64, q64_from32, a.steps, 0, graph=not a.no_graph)
 
-    # ---- labels on an identical input state: BF16 (+re-check) vs FP64 ---------------
-    def labels(prec, q):
-        mlp, prob, ws = make(prec, MARGIN.get(prec, 0.0))
+    def errors(qa, sta):
+        # problems whose state turned non-physical (no positivity limiter in
+        # the scheme) are frozen by the solver and left out of the norms
+        okp = ((sta == 0) & (st64b == 0)).cpu().numpy() & _physical(qa, off) & _physical(q64b, off)
+        cell_ok = torch.as_tensor(np.repeat(okp, np.diff(off)), device=dev)
+        dq = (qa.double() - q64b).abs().reshape(3, -1)[:, cell_ok]
+        ref = q64b.reshape(3, -1)[:, cell_ok]
+        return (float((dq.mean(dim=1) / ref.abs().mean(dim=1)).max()),
+                float((dq.max(dim=1).values / ref.abs().max(dim=1).values).max()), int(okp.sum()))
+
+    l1, linf, n_norm = errors(qb, stb)
+    l1_h, linf_h, _ = errors(qh, sth)
+
+    # ---- labels on the evolved state: the FP64 path's state after the timed
+    # steps, rounded to FP32, through the BF16 / FP16 pass (re-check on) and
+    # the FP64 pass -------------------------------------------------------------------
+    q_ev32 = q64b.float().contiguous()
+    q_ev64 = q_ev32.double().contiguous()
+
+    def labels(prec, q, margin):
+        mlp, prob, ws = make(prec, margin)
         r = torch.zeros_like(q)
         m = torch.zeros(prob.mask_count(), dtype=torch.uint8, device=dev)
         native.neno6_rhs(prob, mlp, q, r, ws, masks_out=m)
-        return m
+        n_re = native.neno6_recheck_count(prob, mlp, ws)[0] if prec >= native.BF16 else 0
+        torch.cuda.synchronize()
+        return m, n_re
 
-    m64 = labels(native.FP64, q64_from32)
-    mb16 = labels(native.BF16, q32)
-    mh16 = labels(native.FP16, q32)
-    torch.cuda.synchronize()
+    m64, _ = labels(native.FP64, q_ev64, 0.0)
+    mb16, re_b = labels(native.BF16, q_ev32, MARGIN[2])
+    mb0, _ = labels(native.BF16, q_ev32, 0.0)
+    mh16, _ = labels(native.FP16, q_ev32, MARGIN[3])
 
     def flip(ma, mb):
         x = (ma ^ mb).cpu().numpy()
@@ -248,31 +289,35 @@ def main():
         x = (ma ^ mb).reshape(3, -1).cpu().numpy()
         return float((x != 0).any(axis=0).mean())
 
-    flip_b, flip_h = flip(mb16, m64), flip(mh16, m64)
-    flip_face_b = flip_faces(mb16, m64)
+    n_evals = faces_stage * EVALS_PER_FACE
+    lab = {"state": "FP64 path after the %d timed RK3 steps, rounded to FP32" % a.steps,
+           "flip_rate_bf16": flip(mb16, m64), "flip_rate_per_face_bf16": flip_faces(mb16, m64),
+           "flip_rate_fp16": flip(mh16, m64),
+           "flip_rate_bf16_without_recheck": flip(mb0, m64),
+           "recheck_margin": {"bf16": MARGIN[2], "fp16": MARGIN[3]},
+           # the overlap face of two 64-face tiles is counted by both
+           "recheck_fraction_bf16": re_b / float(n_evals)}
 
-    # ---- fused face kernel alone, BF16 (roofline) ------------------------------------
-    mlp0, prob0, ws0 = make(native.BF16, 0.0)  # margin 0: exactly the fused kernel
-    prob0.set_tuning(shapes_used.get(native.BF16))  # the launch shape of the timed steps
-    F = torch.zeros(3 * faces_stage, dtype=torch.float32, device=dev)
-    native.neno6_face_fluxes(prob0, mlp0, q32, F, ws0)  # builds the face map once
-    prob0.flags = native.KEEP_MAP                      # later calls launch only the kernel
-    for _ in range(2000):  # about 0.1 s: back to steady clocks after the host-side work above
-        native.neno6_face_fluxes(prob0, mlp0, q32, F, ws0)
+    # ---- fused kernel alone: the right-hand-side pass as inside the step ----------------
+    mlpk, probk, wsk = make(native.BF16, MARGIN[2])
+    probk.set_tuning(shapes_used.get(native.BF16))  # the launch shape of the timed steps
+    r = torch.zeros_like(q32)
+    native.neno6_rhs(probk, mlpk, q32, r, wsk)  # builds the face map once
+    probk.flags = native.KEEP_MAP               # later calls launch only the kernel
+    reps = 200 if name == "c2" else 20
+    for _ in range(10 * reps):  # about 0.1 s: back to steady clocks
+        native.neno6_rhs(probk, mlpk, q32, r, wsk)
     torch.cuda.synchronize()
-    # the timed launches back to back in one HIP graph (no host launch gaps
-    # between them); eager launches if capture fails
-    reps = 200
     kg = None
     if not a.no_graph:
-        try:
+        try:  # the launches back to back in one HIP graph (no host gaps between them)
             kg = torch.cuda.CUDAGraph()
             with torch.cuda.graph(kg):
                 for _ in range(reps):
-                    native.neno6_face_fluxes(prob0, mlp0, q32, F, ws0)
+                    native.neno6_rhs(probk, mlpk, q32, r, wsk)
             kg.replay()
             torch.cuda.synchronize()
-        except Exception as e:  # pragma: no cover - capture problems are reported
+        except Exception as e:  # pragma: no cover
             print("kernel graph capture failed, eager launches: %s" % e, file=sys.stderr)
             kg = None
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -281,46 +326,55 @@ def main():
         kg.replay()
     else:
         for _ in range(reps):
-            native.neno6_face_fluxes(prob0, mlp0, q32, F, ws0)
+            native.neno6_rhs(probk, mlpk, q32, r, wsk)
     e1.record()
     torch.cuda.synchronize()
     k_ms = e0.elapsed_time(e1) / reps
     flop = faces_stage * EVALS_PER_FACE * FLOP_PER_EVAL
-    # state in, face fluxes and masks out (FP32 state, one mask byte per face and field)
-    alg_bytes = 3 * int(off[-1]) * 4 + 3 * faces_stage * 4 + 3 * faces_stage
+    # state in, right-hand side out (FP32)
+    alg_bytes = 2 * 3 * int(off[-1]) * 4
     achieved = flop / (k_ms / 1e3) / 1e12
-    trec = _traffic_record()
+    trec = _traffic_record() if name == "c4" else None
     traffic = int(trec["bytes_per_launch"]) if trec else None
-    hbm_gbs = (traffic or alg_bytes) / (k_ms / 1e3) / 1e9
-    # share of evaluations the FP32 re-check takes at the stated margin
-    mlpm, probm, wsm = make(native.BF16, MARGIN[2])
-    native.neno6_face_fluxes(probm, mlpm, q32, F, wsm)
-    n_recheck = native.neno6_recheck_count(probm, mlpm, wsm)[0]
-    recheck_frac = n_recheck / float(faces_stage * EVALS_PER_FACE)
 
     # ---- CPU oracle on a bounded sample ------------------------------------------------
     cpu = None
     if not a.no_cpu_baseline:
         import oracle
         oracle.build()
-        done_faces, t_cpu, p = 0, 0.0, 0
-        while t_cpu < a.cpu_seconds and p < N_PROBLEMS:
-            k = min(16, N_PROBLEMS - p)
-            sub = q0[:, off[p]:off[p + k]]
-            o_sub = off[p:p + k + 1] - off[p]
-            c0 = time.perf_counter()
-            oracle.euler1d_step(sub, o_sub, dx[p:p + k], CFL, 1, 1.4, oracle.BC_TRANSMISSIVE, P,
-                                oracle.SEL_MLP)
-            t_cpu += time.perf_counter() - c0
-            done_faces += 3 * (int(o_sub[-1]) + k)
-            p += k
-        cpu = {"value": done_faces / t_cpu, "unit": "faces/s", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": "%d of the %d problems, one RK3 step each (%d faces, %.1f s), FP64 C oracle"
-                         % (p, N_PROBLEMS, done_faces, t_cpu)}
 
-    out = {
-        "metric": "reconstructed faces/s: plain FP64 vs BF16-MFMA NENO6 at stated flip rate/L1 error",
+        def oracle_rate(threads, budget, max_problems):
+            oracle.set_num_threads(threads)
+            pick = np.random.default_rng(3).permutation(n_prob)
+            done, t_cpu, used = 0, 0.0, 0
+            while t_cpu < budget and used < min(max_problems, n_prob):
+                k = min(16 if threads > 1 else 2, n_prob - used)
+                pp = np.sort(pick[used:used + k])
+                sub = np.concatenate([q0[:, off[p]:off[p + 1]] for p in pp], axis=1)
+                o_sub = np.concatenate([[0], np.cumsum(sizes[pp])])
+                c0 = time.perf_counter()
+                oracle.euler1d_step(sub, o_sub, dx[pp], CFL, 1, 1.4, oracle.BC_TRANSMISSIVE, P,
+                                    oracle.SEL_MLP)
+                t_cpu += time.perf_counter() - c0
+                done += 3 * (int(o_sub[-1]) + k)
+                used += k
+            return done / t_cpu, used, done, t_cpu
+
+        ncpu = os.cpu_count() or 1
+        v_all, used, done, t_all = oracle_rate(ncpu, a.cpu_seconds, 256)
+        v_one, used1, done1, t_one = oracle_rate(1, a.cpu_seconds / 4, 16)
+        oracle.set_num_threads(ncpu)
+        cpu = {"value": v_all, "unit": "faces/s", "cores": ncpu, "kind": "oracle",
+               "cpu_model": _cpu_model(), "nproc": ncpu,
+               "sample": "%d random problems of the %d, one RK3 step each (%d faces, %.1f s), "
+                         "FP64 C oracle, OpenMP over problems" % (used, n_prob, done, t_all),
+               "single_thread": {"value": v_one, "unit": "faces/s",
+                                 "sample": "%d problems, one RK3 step (%d faces, %.1f s)"
+                                           % (used1, done1, t_one)}}
+
+    e2e = value * VALU_OPS_PER_FACE / 1e12 / PEAK_VALU_TOPS
+    return {
+        "metric": METRIC,
         "value": value,
         "unit": "faces/s",
         "n_gpus": 1,
@@ -332,152 +386,43 @@ def main():
         "vs_baseline": None,
         "dtype": "bf16",
         "data": "synthetic",
-        "config": {"workload": "1D Euler Riemann batch: %d problems x %d cells, characteristic NENO6, "
-                               "LF splitting, SSP-RK3 CFL %.1f; FP32 state, BF16-MFMA classifier, "
-                               "FP32 re-check margin %.2f" % (N_PROBLEMS, N_CELLS, CFL, MARGIN[2]),
+        "config": {"workload": "%s; characteristic NENO6, LF splitting, SSP-RK3 CFL %.1f; FP32 "
+                               "state, BF16-MFMA classifier, FP32 re-check margin %.2f"
+                               % (label, CFL, MARGIN[2]),
                    "faces_per_step": faces_step, "hip_graph": graphed,
-                   "rk3_steps_per_graph_replay": per_graph.get(native.BF16, 1)},
+                   "rk3_steps_per_graph_replay": per_b,
+                   "launch_shapes": {"bf16": shapes_used.get(native.BF16),
+                                     "fp16": shapes_used.get(native.FP16)}},
         # the binding resource of the fused kernel is VALU issue (the
         # instruction-counter profile); the MFMA and HBM fractions follow
         "roofline": dict(_alu(faces_stage, k_ms), traffic=traffic,
                          traffic_launch_shape=trec.get("launch_shape") if trec else None,
-                         kernel="k_fast_faces<BF16, 1D Euler>", kernel_ms=k_ms,
+                         kernel="k_euler1d<BF16> (fused faces, FP32 re-check, flux difference; "
+                                "right-hand-side output)", kernel_ms=k_ms,
                          algorithmic_flop_per_launch=flop,
                          algorithmic_bytes_per_launch=alg_bytes),
+        "end_to_end_valu_frac": e2e,
         "roofline_mfma": {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_BF16,
                           "unit": "TFLOP/s", "frac": achieved / PEAK_MFMA_BF16},
-        "roofline_hbm": {"bound": "hbm", "achieved": hbm_gbs, "peak": PEAK_HBM_GBS,
-                         "unit": "GB/s", "frac": hbm_gbs / PEAK_HBM_GBS,
+        "roofline_hbm": {"bound": "hbm",
+                         "achieved": (traffic or alg_bytes) / (k_ms / 1e3) / 1e9,
+                         "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": (traffic or alg_bytes) / (k_ms / 1e3) / 1e9 / PEAK_HBM_GBS,
                          "bytes": "measured traffic" if traffic else "algorithmic"},
         "fp64_plain": {"value": fp64_rate, "unit": "faces/s", "ms_per_step": ms_64 / k64,
                        "steps": k64},
         "fp16_mfma": {"value": fp16_rate, "unit": "faces/s", "ms_per_step": ms_h / a.steps,
-                      "flip_rate": flip_h},
+                      "l1_rel_vs_fp64": l1_h, "linf_rel_vs_fp64": linf_h},
         "speedup_bf16_vs_fp64": value / fp64_rate,
-        "flip_rate": flip_b,
-        "flip_rate_per_face": flip_face_b,
-        "recheck_fraction": recheck_frac,
+        "labels": lab,
+        "flip_rate": lab["flip_rate_bf16"],
         "l1_rel_vs_fp64": l1,
         "linf_rel_vs_fp64": linf,
-        "frozen_problems": {"bf16": frozen_b, "fp64": frozen_64, "of": N_PROBLEMS},
-        "problems_in_error_norms": int(okp.sum()),
-        "launch_shapes": {"bf16": shapes_used.get(native.BF16), "fp16": shapes_used.get(native.FP16)},
+        "frozen_problems": {"bf16": int((stb != 0).sum()), "fp64": int((st64b != 0).sum()),
+                            "of": n_prob},
+        "problems_in_error_norms": n_norm,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out))
-
-
-def bench_batched(a, P, dev):
-    """4096 independent 1D Euler problems, N log-uniform in [256, 16384];
-    FP32 state, BF16 classifier; ten RK3 steps per HIP-graph replay with the
-    autotuned launch shapes.  A step here is one replay (ten RK3 steps)."""
-    import numpy as np
-    import torch
-
-    from paper_2207_08500_amd import autotune, inputs, native
-
-    n_prob, inner = 4096, 10
-    sizes = inputs.uneven_sizes(inputs.BASE_SEED, n_prob, 256, 16384)
-    q0, off, dx = inputs.riemann1d_batch(inputs.BASE_SEED, sizes)
-    faces_stage = int(off[-1]) + n_prob
-    faces_replay = inner * 3 * faces_stage
-    q32 = torch.as_tensor(q0, dtype=torch.float32, device=dev).contiguous()
-    mlp = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=MARGIN[2])
-    prob = native.Problem(native.EULER1D, native.BF16, native.SEL_MLP, native.TRANSMISSIVE, off, dx,
-                          device=dev)
-    ws = prob.workspace(dev)
-    shapes, tune_ms = autotune.tuned(prob, mlp, q32, ws)
-    q = q32.clone()
-    t = torch.zeros(n_prob, dtype=torch.float64, device=dev)
-    st = torch.zeros(n_prob, dtype=torch.int32, device=dev)
-    s = torch.cuda.Stream()
-    s.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(s):
-        native.neno6_step(prob, mlp, q, CFL, 1, t, st, ws, stream=s)  # eager: builds the face map
-    torch.cuda.current_stream().wait_stream(s)
-    prob.flags = native.KEEP_MAP
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        native.neno6_step(prob, mlp, q, CFL, inner, t, st, ws)
-
-    def reset():
-        q.copy_(q32)
-        t.zero_()
-        st.zero_()
-
-    reset()
-    for _ in range(a.warmup):
-        g.replay()
-    torch.cuda.synchronize()
-    reset()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(a.steps):
-        g.replay()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    value = faces_replay * a.steps / (ms / 1e3)
-    # fused face kernel alone (margin 0) with the tuned shapes
-    mlp0 = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=0.0)
-    F = torch.zeros(3 * faces_stage, dtype=torch.float32, device=dev)
-    for _ in range(150):  # about 0.1 s: back to steady clocks after the host-side work above
-        native.neno6_face_fluxes(prob, mlp0, q32, F, ws)
-    torch.cuda.synchronize()
-    reps = 20
-    e0.record()
-    for _ in range(reps):
-        native.neno6_face_fluxes(prob, mlp0, q32, F, ws)
-    e1.record()
-    torch.cuda.synchronize()
-    k_ms = e0.elapsed_time(e1) / reps
-    flop = faces_stage * EVALS_PER_FACE * FLOP_PER_EVAL
-    achieved = flop / (k_ms / 1e3) / 1e12
-    cpu = None
-    if not a.no_cpu_baseline:
-        import oracle
-        oracle.build()
-        pick = np.random.default_rng(3).choice(n_prob, 64, replace=False)
-        sub = np.concatenate([q0[:, off[p]:off[p + 1]] for p in pick], axis=1)
-        o_sub = np.concatenate([[0], np.cumsum(sizes[pick])])
-        c0 = time.perf_counter()
-        oracle.euler1d_step(sub, o_sub, dx[pick], CFL, 1, 1.4, oracle.BC_TRANSMISSIVE, P,
-                            oracle.SEL_MLP)
-        t_cpu = time.perf_counter() - c0
-        n_f = 3 * (int(o_sub[-1]) + 64)
-        cpu = {"value": n_f / t_cpu, "unit": "faces/s", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": "64 random problems of the 4096 (%d cells), one RK3 step (%d faces, "
-                         "%.1f s), FP64 C oracle" % (int(o_sub[-1]), n_f, t_cpu)}
-    out = {
-        "metric": "reconstructed faces/s: plain FP64 vs BF16-MFMA NENO6 at stated flip rate/L1 error",
-        "value": value,
-        "unit": "faces/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": ms / a.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "bf16",
-        "data": "synthetic",
-        "config": {"workload": "1D Euler batch: %d problems, N log-uniform in [256, 16384] (%d cells), "
-                               "FP32 state, BF16-MFMA classifier, re-check margin %.2f; one step = "
-                               "one HIP-graph replay of %d SSP-RK3 steps" % (n_prob, int(off[-1]),
-                                                                           MARGIN[2], inner),
-                   "faces_per_step": faces_replay, "hip_graph": True, "launch_shapes": shapes,
-                   "autotune_ms_per_face_pass": tune_ms},
-        "roofline": dict(_alu(faces_stage, k_ms), traffic=None,
-                         kernel="k_fast_faces<BF16, 1D Euler>", kernel_ms=k_ms,
-                         algorithmic_flop_per_launch=flop),
-        "roofline_mfma": {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_BF16,
-                          "unit": "TFLOP/s", "frac": achieved / PEAK_MFMA_BF16},
-        "frozen_problems": {"bf16": int((st != 0).sum()), "of": n_prob},
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out))
 
 
 def bench_2d(a, P, dev):
@@ -578,7 +523,7 @@ def bench_2d(a, P, dev):
     flop = faces_stage * EVALS_PER_FACE_2D * FLOP_PER_EVAL
     achieved = flop / (k_ms / 1e3) / 1e12
     out = {
-        "metric": "reconstructed faces/s: plain FP64 vs BF16-MFMA NENO6 at stated flip rate/L1 error",
+        "metric": METRIC,
         "value": value,
         "unit": "faces/s",
         "n_gpus": 1,

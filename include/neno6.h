@@ -117,7 +117,8 @@ typedef struct neno6_mlp {
  *                  iteration.
  *  face_blocks:    workgroups of the fused face kernel, which loop over the
  *                  64-face tiles (grid-stride); at most 65536.
- *  recheck_blocks: workgroups of the FP32 re-check and fix-up kernels, 1..65536.
+ *  recheck_blocks: 2D: workgroups of the FP32 re-check and fix-up kernels,
+ *                  1..65536 (1D re-checks inside the face pass and ignores it).
  *  xcd_order:      1 = number the workgroups so that each of the eight XCDs
  *                  (each with its own L2) walks a contiguous run of tiles;
  *                  needs face_blocks to be a multiple of 8 (else ignored). */
@@ -197,7 +198,13 @@ size_t neno6_workspace_size(const neno6_problem *prob);
  * NULL]: for 2D pass x masks then y masks back to back in one buffer
  * ([4][ny][nx+1] followed by [4][ny+1][nx]).  status[n_problems] [dev] is
  * set to NENO6_NONPHYSICAL for a problem with a cell that is not physical
- * (it is never cleared here). */
+ * (it is never cleared here).
+ * 1D Euler in BF16/FP16: one fused kernel computes the face fluxes, the FP32
+ * re-check of near-cutoff evaluations and the flux difference.  A face whose
+ * six stencil cells are equal has a constant split stencil, whose
+ * re-normalised combination is that constant for every selection; the pass
+ * takes it exactly, and re-checks such a face's near-cutoff labels only when
+ * masks_out is given (they cannot change any value). */
 int32_t neno6_rhs(const neno6_problem *prob, const neno6_mlp *mlp, const void *q, void *rhs,
                   const uint8_t *masks_in, uint8_t *masks_out, int32_t *status, void *ws,
                   size_t ws_bytes, hipStream_t stream);
@@ -206,28 +213,33 @@ int32_t neno6_rhs(const neno6_problem *prob, const neno6_mlp *mlp, const void *q
  * problem, without the flux difference): F [dev] receives the face fluxes
  * ([var][faces] for 1D; x faces then y faces for 2D) and masks_out [dev, may
  * be NULL] the kept masks.  In BF16/FP16 modes this launches exactly the fused
- * classifier kernel (the FP32 re-check is skipped when the margin is 0); it
- * exists so that kernel can be timed on its own. */
+ * classifier kernel (1D: the same kernel as neno6_rhs and neno6_step, writing
+ * face fluxes instead of cells; the FP32 re-check is skipped when the margin
+ * is 0); it exists so that kernel can be timed on its own. */
 int32_t neno6_face_fluxes(const neno6_problem *prob, const neno6_mlp *mlp, const void *q, void *F,
                           uint8_t *masks_out, void *ws, size_t ws_bytes, hipStream_t stream);
 
-/* Diagnostic (synchronous: waits for `stream`): after neno6_face_fluxes in
- * BF16/FP16 mode with `mlp`, the number of classifier evaluations of each
- * sweep direction (count[0]: 1D or x, count[1]: y) that fell inside the
- * re-check margin and were re-evaluated in FP32 (0 when mlp's margin is 0:
- * the re-check does not run and its counters are not maintained).
+/* Diagnostic (synchronous: waits for `stream`): after neno6_face_fluxes or
+ * neno6_rhs in BF16/FP16 mode with `mlp`, the number of classifier
+ * evaluations of each sweep direction (count[0]: 1D or x, count[1]: y) that
+ * were re-evaluated in FP32 (0 when mlp's margin is 0: the re-check does not
+ * run and its counters are not maintained).  1D: the pass works in tiles of
+ * 64 faces that overlap by one face, so an overlap face's evaluations are
+ * counted by both tiles; without masks_out the near-cutoff evaluations of
+ * faces with six equal cells are not re-checked (see neno6_rhs).
  * count [host, 2 values]. */
 int32_t neno6_recheck_count(const neno6_problem *prob, const neno6_mlp *mlp, const void *ws,
                             size_t ws_bytes, uint32_t *count, hipStream_t stream);
 
 /* Autotuner (host-synchronous, not for graph capture): times the fused
- * face pass (counter reset, classifier kernel, re-check, fix-up) of `prob`
- * on state q [dev] for every launch shape of a candidate set -- waves per
- * workgroup W in {2, 4, 8} (2D: {4, 8}) x workgroup caps {512, 1024, 2048,
- * 4096, 16384, 65536, and k * V * CUs / W for k = 1, 2, 3 (whole rounds of
- * resident waves on the current device, V = 12 waves per CU in 1D, 8 in
- * 2D)} x XCD ordering {0, 1} x re-check
- * workgroups {128, 512, 2048} -- with HIP events on `stream`, after about
+ * face pass of `prob` (1D: the fused kernel with its in-pass re-check; 2D:
+ * counter reset, classifier kernel, re-check, fix-up) on state q [dev] for
+ * every launch shape of a candidate set -- waves per workgroup W in
+ * {2, 4, 8} (2D: {4, 8}) x workgroup caps {512, 1024, 2048, 4096, 16384,
+ * 65536, and k * V * CUs / W for k = 1, 2, 3 (whole rounds of resident waves
+ * on the current device, V = 12 waves per CU in 1D, 8 in 2D)} x XCD ordering
+ * {0, 1} x (2D only) re-check workgroups {128, 512, 2048} -- with HIP events
+ * on `stream`, after about
  * 0.1 s of warm-up passes in the default shape, `reps` (1..1000) timed
  * passes each after one warm-up, and writes the fastest to *best [host] (its mean pass
  * time in ms to *best_ms [host], may be NULL).  Outputs of the passes land in

@@ -90,6 +90,8 @@ def _load():
                 fn.argtypes = args
                 fn.restype = None
             lib.oracle_num_threads.restype = C.c_int
+            lib.oracle_set_num_threads.argtypes = [C.c_int]
+            lib.oracle_set_num_threads.restype = None
             _lib = lib
     return _lib
 
@@ -113,6 +115,11 @@ def _check(rc, name):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the loops over independent problems (timing only)."""
+    _load().oracle_set_num_threads(int(n))
 
 
 def linear_weights() -> np.ndarray:

@@ -542,6 +542,7 @@ int32_t neno6_autotune(const neno6_problem *prob, const neno6_mlp *mlp, const vo
     for (int ib = 0; ib < nbl; ++ib)
       for (int xcd = 0; xcd < 2 && rc == NENO6_OK; ++xcd)
         for (int rb : rblocks) {
+          if (!is2d && rb != rblocks[0]) break;  // 1D: the re-check runs in the face pass
           const int nb = blocks[ib];
           fa.face_waves = wv;
           fa.face_blocks = nb;

@@ -1,24 +1,27 @@
-"""Launches the hot kernels on the benchmark workload for profiling, plus a
+"""Launches the hot kernels on the benchmark workloads for profiling, plus a
 plain device copy of known size that calibrates the memory counters.
 
     rocprofv3 --pmc FETCH_SIZE --kernel-trace --output-format csv -d OUT -o run -- \
-        python3 paper_2207_08500_amd/profile_kernels.py --shape 4,768
+        python3 paper_2207_08500_amd/profile_kernels.py --tuned --no-fp64
     rocprofv3 --pmc WRITE_SIZE --kernel-trace --output-format csv -d OUT -o run -- \
-        python3 paper_2207_08500_amd/profile_kernels.py --shape 4,768
+        python3 paper_2207_08500_amd/profile_kernels.py --tuned --no-fp64
     rocprofv3 --kernel-trace --stats --output-format csv -d OUT -o run -- \
         python3 paper_2207_08500_amd/profile_kernels.py --steps 20
 
-Workload: 256 independent 1D Euler Riemann problems of 4000 cells (the
-benchmark's), FP32 state, BF16/FP16 classifier; the FP64 plain path once.
-With --tuned the face launches take the launch shape the autotuner picks for
-the BF16 pass (as the benchmark does; it prints the shape); with --shape W,B
-that many waves per workgroup and workgroups; else the library default.
-With --steps K: instead, K SSP-RK3 steps of the BF16 path with the re-check
-(margin 0.5), captured once in a HIP graph and replayed after 400 warm-up
-replays (40 with --2d), in the --shape launch shape if given, else the
-autotuner's; a one-element torch fill right before the timed
+Workloads (--workload): c4, 4096 independent 1D Euler Riemann problems with N
+log-uniform in [256, 16384] (default); c2, 256 problems of 4000 cells.  FP32
+state, BF16/FP16 classifier.  Without --steps: the right-hand-side pass as it
+runs inside a step (the fused face kernel with the FP32 re-check at margin
+0.5 / 0.25 and the flux difference, face map kept) --reps times in BF16 and
+in FP16, the FP64 plain path once, then the copy.  With --tuned the launches
+take the shape the autotuner picks for the BF16 pass (as the benchmark does;
+it prints the shape); with --shape W,B that many waves per workgroup and
+workgroups; else the library default.  With --steps K: instead, K SSP-RK3
+steps of the BF16 path with the re-check, captured once in a HIP graph and
+replayed after about 0.1 s of warm-up replays, in the --shape launch shape if
+given, else the autotuner's; a one-element torch fill right before the timed
 replays marks where they start in a kernel trace.  --2d: the 2D Euler
-four-quadrant Riemann problem on 2048 x 2048 cells instead of the 1D batch.
+four-quadrant Riemann problem on 2048 x 2048 cells instead of a 1D batch.
 """
 import argparse
 import os
@@ -32,6 +35,16 @@ sys.path.insert(0, ROOT)
 
 from paper_2207_08500_amd import inputs, native  # noqa: E402
 
+MARGIN = {native.BF16: 0.5, native.FP16: 0.25}
+
+
+def batch(workload):
+    if workload == "c4":
+        sizes = inputs.uneven_sizes(inputs.BASE_SEED, 4096, 256, 16384)
+    else:
+        sizes = np.full(256, 4000, np.int64)
+    return inputs.riemann1d_batch(inputs.BASE_SEED, sizes)
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -41,16 +54,16 @@ def main():
     ap.add_argument("--steps", type=int, default=0)
     ap.add_argument("--tuned", action="store_true")
     ap.add_argument("--shape", default=None, help="W,B: waves per workgroup, workgroups")
+    ap.add_argument("--workload", choices=("c4", "c2"), default="c4")
     ap.add_argument("--2d", dest="two_d", action="store_true")
     a = ap.parse_args()
     native.load()
     dev = torch.device("cuda:0")
     P = np.load(os.path.join(ROOT, "tests", "golden", "neno6_mlp_trained.npy"), allow_pickle=False)
-    q0, off, dx = inputs.riemann1d_batch(inputs.BASE_SEED, (4000,) * 256)
-    q32 = torch.as_tensor(q0, dtype=torch.float32, device=dev).contiguous()
-    faces = int(off[-1]) + 256
     if a.steps > 0 and a.two_d:
         return step_replay_2d(a.steps, P, dev)
+    q0, off, dx = batch(a.workload)
+    q32 = torch.as_tensor(q0, dtype=torch.float32, device=dev).contiguous()
     if a.steps > 0:
         return step_replay(a.steps, P, q32, off, dx, dev, a.shape)
     shape = None
@@ -61,26 +74,30 @@ def main():
         from paper_2207_08500_amd import autotune
         prob = native.Problem(native.EULER1D, native.BF16, native.SEL_MLP, native.TRANSMISSIVE, off,
                               dx, device=dev)
-        shape = autotune.tuned(prob, native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=0.5),
+        shape = autotune.tuned(prob, native.Mlp(torch.as_tensor(P, device=dev),
+                                                recheck_margin=MARGIN[native.BF16]),
                                q32, prob.workspace(dev))[0]
         torch.cuda.synchronize()
-        print("launch shape %s" % shape, flush=True)
+    print("workload %s, launch shape %s" % (a.workload, shape), flush=True)
     for prec in (native.BF16, native.FP16):
-        mlp = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=0.0)
+        mlp = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=MARGIN[prec])
         prob = native.Problem(native.EULER1D, prec, native.SEL_MLP, native.TRANSMISSIVE, off, dx,
                               device=dev)
         prob.set_tuning(shape)
         ws = prob.workspace(dev)
-        F = torch.zeros(3 * faces, dtype=torch.float32, device=dev)
+        r = torch.zeros_like(q32)
+        native.neno6_rhs(prob, mlp, q32, r, ws)  # builds the face map
+        torch.cuda.synchronize()
+        prob.flags = native.KEEP_MAP             # later calls launch only the fused kernel
         for _ in range(a.reps):
-            native.neno6_face_fluxes(prob, mlp, q32, F, ws)
+            native.neno6_rhs(prob, mlp, q32, r, ws)
         torch.cuda.synchronize()
     if not a.no_fp64:
         mlp = native.Mlp(torch.as_tensor(P, device=dev))
         prob = native.Problem(native.EULER1D, native.FP64, native.SEL_MLP, native.TRANSMISSIVE,
                               off, dx, device=dev)
-        F = torch.zeros(3 * faces, dtype=torch.float64, device=dev)
-        native.neno6_face_fluxes(prob, mlp, q32.double().contiguous(), F, prob.workspace(dev))
+        q64 = q32.double().contiguous()
+        native.neno6_rhs(prob, mlp, q64, torch.zeros_like(q64), prob.workspace(dev))
         torch.cuda.synchronize()
     # calibration: a plain copy of copy_mib MiB (reads and writes that many bytes)
     n = a.copy_mib * (1 << 20) // 4
@@ -89,8 +106,8 @@ def main():
     torch.cuda.synchronize()
     dst.copy_(src)
     torch.cuda.synchronize()
-    print("profiled: fused face kernel x%d (BF16, FP16), FP64 path x1, copy %d MiB"
-          % (a.reps, a.copy_mib))
+    print("profiled: right-hand-side pass x%d (BF16, FP16; after one map-building call each), "
+          "FP64 path x1, copy %d MiB" % (a.reps, a.copy_mib))
 
 
 def step_replay(steps, P, q32, off, dx, dev, shape_arg=None):
@@ -121,14 +138,20 @@ def step_replay(steps, P, q32, off, dx, dev, shape_arg=None):
     q.copy_(q32)
     t.zero_()
     st.zero_()
-    for _ in range(400):  # about 0.1 s: steady clocks
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    for _ in range(max(1, int(100.0 / max(e0.elapsed_time(e1), 1e-3)))):  # about 0.1 s
         g.replay()
     q.copy_(q32)
     t.zero_()
     st.zero_()
     marker = torch.zeros(1, device=dev)
     marker.fill_(1.0)  # the timed replays follow this dispatch
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):
         g.replay()

@@ -34,15 +34,20 @@ def test_valu_roofline_arithmetic():
 
 
 def test_traffic_record_is_consistent():
-    """The committed FETCH/WRITE record parses; when its source hash matches,
-    its bytes per launch cover at least the algorithmic bytes of a launch
-    (state in, fluxes and masks out) and stay within a few times of them."""
+    """The committed FETCH/WRITE record parses; its bytes per launch cover at
+    least the algorithmic bytes of a launch (state in, right-hand side out,
+    FP32, on the 4096-problem batch) and stay within a few times of them;
+    when its source hash matches the tree, bench.py reports it."""
     import json
+
+    from paper_2207_08500_amd import inputs
     line = [ln for ln in open(bench.TRAFFIC_RECORD) if ln.startswith("traffic-record:")][0]
     rec = json.loads(line.split(":", 1)[1])
     scaled = (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024
     assert abs(scaled - rec["bytes_per_launch"]) / rec["bytes_per_launch"] < 1e-3
-    alg = 3 * 1024000 * 4 + 3 * 1024256 * 4 + 3 * 1024256
+    cells = int(inputs.uneven_sizes(inputs.BASE_SEED, 4096, 256, 16384).sum())
+    assert rec["cells"] == cells
+    alg = 2 * 3 * cells * 4
     assert alg <= rec["bytes_per_launch"] < 4 * alg
     got = bench._traffic_record()
     assert got is None or got["bytes_per_launch"] == rec["bytes_per_launch"]
