@@ -51,6 +51,7 @@ extern "C" {
                                    * Burgers: a non-finite value */
 #define NENO6_UNSUPPORTED (-5)    /* feature not available for this equation */
 #define NENO6_WORKSPACE_SMALL (-6)
+#define NENO6_TOO_LARGE (-7)      /* beyond a fixed limit of the library (neno6_rhs_noalloc) */
 
 /* ---- enums ---------------------------------------------------------------- */
 /* Arithmetic of state, reconstruction and classifier.
@@ -208,6 +209,25 @@ size_t neno6_workspace_size(const neno6_problem *prob);
 int32_t neno6_rhs(const neno6_problem *prob, const neno6_mlp *mlp, const void *q, void *rhs,
                   const uint8_t *masks_in, uint8_t *masks_out, int32_t *status, void *ws,
                   size_t ws_bytes, hipStream_t stream);
+
+/* neno6_rhs without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc): it calls no allocating routine.  1D Euler in BF16/FP16
+ * only (else NENO6_UNSUPPORTED); arguments, outputs and the kernels run are
+ * those of neno6_rhs.  Its scratch (the face -> line map, 4 bytes per face) is
+ * a fixed array in device memory that the library owns, one per GPU, held
+ * from module load until the process ends: a batch with more than
+ * NENO6_NOALLOC_MAX_FACES faces (cells + problems) is refused with
+ * NENO6_TOO_LARGE before anything is enqueued.  The face map is rebuilt on
+ * every call (NENO6_KEEP_MAP is ignored) and no re-check counters are kept
+ * (neno6_recheck_count does not see these calls).  All calls on one GPU
+ * share the array: calls that can overlap on one GPU (different streams or
+ * host threads without ordering) race and must be serialised by the caller.
+ * The current device must be the one that q, rhs and stream belong to. */
+#define NENO6_NOALLOC_MAX_FACES ((int64_t)16 * 1024 * 1024)
+int32_t neno6_rhs_noalloc(const neno6_problem *prob, const neno6_mlp *mlp, const void *q,
+                          void *rhs, const uint8_t *masks_in, uint8_t *masks_out, int32_t *status,
+                          hipStream_t stream);
 
 /* Face fluxes only (the reconstruction of Alg. 2 at every face of the
  * problem, without the flux difference): F [dev] receives the face fluxes

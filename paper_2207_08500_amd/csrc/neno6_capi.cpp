@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 
 #include "../../include/neno6.h"
 #include "neno6_fast.h"
@@ -292,6 +293,34 @@ int32_t rhs_dispatch(const neno6_problem *pb, const neno6_mlp *mlp, const void *
   }
 }
 
+// Scratch of neno6_rhs_noalloc: library-owned device memory for the face ->
+// line map of a 1D batch (4 bytes per face), so that entry point allocates
+// nothing.  Each GPU holds its own copy from module load until the process
+// ends; calls on one GPU share it.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)NENO6_NOALLOC_MAX_FACES * sizeof(int32_t);
+static_assert(NENO6_NOALLOC_MAX_FACES == 16777216, "status string states the limit");
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+// Device address of `scratch` on the current device: looked up with
+// hipGetSymbolAddress once per device (with that device current) and kept.
+// The array's name is only a host-side handle; kernels and copies get this
+// address.
+int32_t noalloc_scratch(void **out) {
+  constexpr int MAX_DEVICES = 64;
+  static std::mutex mu;
+  static void *addr[MAX_DEVICES] = {};
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return NENO6_HIP_ERROR;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return NENO6_HIP_ERROR;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return NENO6_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -305,6 +334,9 @@ const char *neno6_status_string(int32_t st) {
   case NENO6_NONPHYSICAL: return "state not physical (rho <= 0, p <= 0 or not finite)";
   case NENO6_UNSUPPORTED: return "unsupported for this equation or precision";
   case NENO6_WORKSPACE_SMALL: return "workspace too small";
+  case NENO6_TOO_LARGE:
+    return "problem too large for the library's static scratch (neno6_rhs_noalloc: at most "
+           "16777216 faces)";
   default: return "unknown status";
   }
 }
@@ -377,6 +409,27 @@ int32_t neno6_rhs(const neno6_problem *prob, const neno6_mlp *mlp, const void *q
   if (ws_bytes < w.bytes) return NENO6_WORKSPACE_SMALL;
   if (int32_t c = begin_call(prob, mlp, w, stream)) return c;
   return rhs_dispatch(prob, mlp, q, rhs, masks_in, masks_out, status, w, nullptr, stream);
+}
+
+int32_t neno6_rhs_noalloc(const neno6_problem *prob, const neno6_mlp *mlp, const void *q,
+                          void *rhs, const uint8_t *masks_in, uint8_t *masks_out, int32_t *status,
+                          hipStream_t stream) {
+  if (int32_t c = check_problem(prob)) return c;
+  if (int32_t c = check_mlp(mlp, prob->selector, prob->precision)) return c;
+  if (prob->equation != NENO6_EULER1D || prob->precision < NENO6_BF16) return NENO6_UNSUPPORTED;
+  if (!q || !rhs) return NENO6_BAD_ARG;
+  if (prob->selector == NENO6_SEL_MASKS_IN && !masks_in) return NENO6_BAD_ARG;
+  if (prob->total_cells + prob->n_problems > NENO6_NOALLOC_MAX_FACES) return NENO6_TOO_LARGE;
+  void *base = nullptr;
+  if (int32_t c = noalloc_scratch(&base)) return c;
+  // the face map is the only scratch; no re-check counters are kept
+  Work w;
+  w.fmap = (int32_t *)base;
+  // another call may have left another batch's map: always rebuild it
+  neno6_problem pb = *prob;
+  pb.flags &= ~NENO6_KEEP_MAP;
+  if (int32_t c = begin_call(&pb, mlp, w, stream)) return c;
+  return rhs_dispatch(&pb, mlp, q, rhs, masks_in, masks_out, status, w, nullptr, stream);
 }
 
 int32_t neno6_face_fluxes(const neno6_problem *prob, const neno6_mlp *mlp, const void *q, void *F,

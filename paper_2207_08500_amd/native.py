@@ -18,6 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libneno6.so")
 
 OK, BAD_ARG, BAD_LAYOUT, HIP_ERROR, NONPHYSICAL, UNSUPPORTED, WORKSPACE_SMALL = 0, -1, -2, -3, -4, -5, -6
+TOO_LARGE = -7
+NOALLOC_MAX_FACES = 16 * 1024 * 1024
 FP64, FP32, BF16, FP16 = 0, 1, 2, 3
 ADVECTION, BURGERS, EULER1D, EULER2D = 0, 1, 2, 3
 PERIODIC, TRANSMISSIVE = 0, 1
@@ -28,7 +30,7 @@ NPARAM = 3228
 EXPORTS = (
     "neno6_status_string", "neno6_version", "neno6_mlp_prepared_bytes", "neno6_mlp_prepare",
     "neno6_mlp_logits", "neno6_reconstruct", "neno6_workspace_size", "neno6_rhs",
-    "neno6_face_fluxes", "neno6_recheck_count", "neno6_autotune", "neno6_step",
+    "neno6_rhs_noalloc", "neno6_face_fluxes", "neno6_recheck_count", "neno6_autotune", "neno6_step",
     "neno6_rhs_adjoint", "neno6_vjp_workspace_size", "neno6_rhs_vjp",
     "neno6_train_workspace_size", "neno6_classifier_train",
     "neno6_classifier_grad",
@@ -87,6 +89,7 @@ def load(path: str = LIB_PATH):
         lib.neno6_workspace_size.argtypes = [P(ProblemStruct)]
         lib.neno6_workspace_size.restype = sz
         lib.neno6_rhs.argtypes = [P(ProblemStruct), P(MlpStruct), vp, vp, vp, vp, vp, vp, sz, vp]
+        lib.neno6_rhs_noalloc.argtypes = [P(ProblemStruct), P(MlpStruct), vp, vp, vp, vp, vp, vp]
         lib.neno6_face_fluxes.argtypes = [P(ProblemStruct), P(MlpStruct), vp, vp, vp, vp, sz, vp]
         lib.neno6_recheck_count.argtypes = [P(ProblemStruct), P(MlpStruct), vp, sz, P(C.c_uint32), vp]
         lib.neno6_autotune.argtypes = [P(ProblemStruct), P(MlpStruct), vp, vp, sz, i32,
@@ -277,6 +280,27 @@ def neno6_rhs(prob: Problem, mlp: Mlp | None, q: torch.Tensor, rhs: torch.Tensor
     _check(load().neno6_rhs(C.byref(ps), _mlp(mlp), _ptr(q), _ptr(rhs), _ptr(masks_in),
                             _ptr(masks_out), _ptr(status), _ptr(ws), ws.numel(), _stream(stream)),
            "neno6_rhs")
+
+
+def neno6_rhs_noalloc(prob: Problem, mlp: Mlp, q: torch.Tensor, rhs: torch.Tensor, masks_in=None,
+                      masks_out=None, status=None, stream=None):
+    """neno6_rhs without a workspace: the library's static device scratch
+    holds the face map (1D Euler, BF16/FP16, at most NOALLOC_MAX_FACES faces;
+    calls on one GPU share it and must not overlap)."""
+    dt = fdtype(prob.precision)
+    _dev(q, dt, "q")
+    _dev(rhs, dt, "rhs")
+    if q.numel() != prob.nvar * prob.total_cells or rhs.numel() != q.numel():
+        raise ValueError("state size mismatch")
+    for m in (masks_in, masks_out):
+        if m is not None and (m.numel() != prob.mask_count() or m.dtype != torch.uint8):
+            raise ValueError("masks must be uint8 with %d entries" % prob.mask_count())
+    if status is not None:
+        _dev(status, torch.int32, "status")
+    ps = prob.struct()
+    _check(load().neno6_rhs_noalloc(C.byref(ps), _mlp(mlp), _ptr(q), _ptr(rhs), _ptr(masks_in),
+                                    _ptr(masks_out), _ptr(status), _stream(stream)),
+           "neno6_rhs_noalloc")
 
 
 def neno6_face_fluxes(prob: Problem, mlp: Mlp | None, q: torch.Tensor, F: torch.Tensor,
