@@ -11,13 +11,18 @@ re-check near the cutoff, re-normalised combine, back-projection, flux
 difference, stage update); ten steps are captured once in a HIP graph and
 replayed.
 
-Headline path: FP32 state, classifier in BF16 on MFMA.  Also measured on the
-same GPU: the plain FP64 path and FP16-MFMA; the labels of the BF16 pass
-against the FP64 labels on the FP64 path's state after the timed steps
-(flip rate); the L1 / Linf distance of the BF16 state from the FP64 state
-after the same steps; the fused kernel alone (roofline); the FP64 CPU oracle
-on a bounded sample (cpu_baseline); and the same measurements for the
-256 x 4000-cell batch (nested under "c2").
+Headline path: FP32 state, classifier layers on MFMA with FP16 operands and
+FP32 accumulation, re-check margin 2x the largest FP16 logit error observed
+on 2^20 training samples.  BF16 operands keep 8 significant bits against
+FP16's 11, so the same rule gives BF16 a margin nine times wider (more
+evaluations go to the FP32 re-check) at the same MFMA rate; the BF16-MFMA
+path is measured beside it.  Also on the same GPU: the plain FP64 path; the
+labels of both reduced paths against the FP64 labels on the FP64 path's
+state after the timed steps (flip rate); the L1 / Linf distance of each
+reduced state from the FP64 state after the same steps; the fused kernel
+alone (roofline); the FP64 CPU oracle on a bounded sample (cpu_baseline);
+and the same measurements for the 256 x 4000-cell batch (nested under
+"c2").
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4|c2|c3|c5]
 """
@@ -31,8 +36,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 CFL = 0.4
-MARGIN = {2: 0.5, 3: 0.25}  # FP32 re-check margins in logit units (BF16, FP16)
-PEAK_MFMA_BF16 = 2500.0  # TFLOP/s dense, MI355X
+MARGINS_FILE = os.path.join(ROOT, "tests", "golden", "neno6_mlp_trained_margins.json")
+
+
+def _margins():
+    """FP32 re-check margins (logit units) of the committed weights: twice the
+    largest reduced-precision logit error observed on 2^20 classifier-training
+    samples, keyed by precision code (2: BF16, 3: FP16)."""
+    with open(MARGINS_FILE) as f:
+        m = json.load(f)["margin"]
+    return {2: float(m["bf16"]), 3: float(m["fp16"])}
+
+
+MARGIN = _margins()
+PEAK_MFMA_16 = 2500.0  # TFLOP/s dense BF16 / FP16, MI355X
 PEAK_HBM_GBS = 8000.0    # HBM3E, MI355X
 # non-packed VALU lane-operations/s: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -149,17 +166,17 @@ def main():
         sub = argparse.Namespace(**vars(a))
         sub.steps, sub.warmup, sub.no_cpu_baseline = 200, 400, True
         c2 = bench_1d(sub, P, dev, "c2")
-        keep = ("value", "unit", "ms_per_step", "steps", "config", "roofline", "fp64_plain",
-                "fp16_mfma", "speedup_bf16_vs_fp64", "labels", "l1_rel_vs_fp64",
+        keep = ("value", "unit", "ms_per_step", "steps", "dtype", "config", "roofline",
+                "fp64_plain", "bf16_mfma", "speedup_vs_fp64", "labels", "l1_rel_vs_fp64",
                 "linf_rel_vs_fp64", "frozen_problems", "end_to_end_valu_frac")
         out["c2"] = {k: c2[k] for k in keep if k in c2}
     print(json.dumps(out))
 
 
 def bench_1d(a, P, dev, name):
-    """One 1D Euler batch: the BF16 headline, FP16 and FP64 on the same GPU,
-    labels and errors against the FP64 path, the fused kernel alone, the
-    oracle on the host.  Returns the JSON-ready dict."""
+    """One 1D Euler batch: the FP16-MFMA headline, BF16-MFMA and FP64 on the
+    same GPU, labels and errors against the FP64 path, the fused kernel alone,
+    the oracle on the host.  Returns the JSON-ready dict."""
     import numpy as np
     import torch
 
@@ -235,13 +252,14 @@ def bench_1d(a, P, dev, name):
         torch.cuda.synchronize()
         return q, t, st, e0.elapsed_time(e1), per, g is not None
 
-    # ---- headline: BF16-MFMA ---------------------------------------------------
-    qb, tb, stb, ms_b, per_b, graphed = run_steps(native.BF16, q32, a.steps, a.warmup,
+    HEAD = native.FP16
+    # ---- headline: FP16-MFMA -----------------------------------------------------
+    qh, th, sth, ms_h, per_h, graphed = run_steps(HEAD, q32, a.steps, a.warmup,
                                                   graph=not a.no_graph)
-    value = faces_step * a.steps / (ms_b / 1e3)
-    # ---- same GPU: FP16-MFMA and the plain FP64 path ------------------------------
-    qh, th, sth, ms_h, _, _ = run_steps(native.FP16, q32, a.steps, a.warmup, graph=not a.no_graph)
-    fp16_rate = faces_step * a.steps / (ms_h / 1e3)
+    value = faces_step * a.steps / (ms_h / 1e3)
+    # ---- same GPU: BF16-MFMA and the plain FP64 path ------------------------------
+    qb, tb, stb, ms_b, _, _ = run_steps(native.BF16, q32, a.steps, a.warmup, graph=not a.no_graph)
+    bf16_rate = faces_step * a.steps / (ms_b / 1e3)
     k64 = 2 if name == "c4" else max(2, a.steps // 4)
     _, _, _, ms_64, _, _ = run_steps(native.FP64, q64_from32, k64, 1, graph=not a.no_graph)
     fp64_rate = faces_step * k64 / (ms_64 / 1e3)
@@ -258,11 +276,11 @@ def bench_1d(a, P, dev, name):
         return (float((dq.mean(dim=1) / ref.abs().mean(dim=1)).max()),
                 float((dq.max(dim=1).values / ref.abs().max(dim=1).values).max()), int(okp.sum()))
 
-    l1, linf, n_norm = errors(qb, stb)
-    l1_h, linf_h, _ = errors(qh, sth)
+    l1, linf, n_norm = errors(qh, sth)
+    l1_b, linf_b, _ = errors(qb, stb)
 
     # ---- labels on the evolved state: the FP64 path's state after the timed
-    # steps, rounded to FP32, through the BF16 / FP16 pass (re-check on) and
+    # steps, rounded to FP32, through the FP16 / BF16 pass (re-check on) and
     # the FP64 pass -------------------------------------------------------------------
     q_ev32 = q64b.float().contiguous()
     q_ev64 = q_ev32.double().contiguous()
@@ -271,15 +289,21 @@ def bench_1d(a, P, dev, name):
         mlp, prob, ws = make(prec, margin)
         r = torch.zeros_like(q)
         m = torch.zeros(prob.mask_count(), dtype=torch.uint8, device=dev)
+        n_re = 0
+        if prec >= native.BF16:
+            # evaluations re-checked as in a step (no labels requested: faces
+            # with six equal cells skip it, their flux does not depend on it)
+            native.neno6_rhs(prob, mlp, q, r, ws)
+            n_re = native.neno6_recheck_count(prob, mlp, ws)[0]
         native.neno6_rhs(prob, mlp, q, r, ws, masks_out=m)
-        n_re = native.neno6_recheck_count(prob, mlp, ws)[0] if prec >= native.BF16 else 0
         torch.cuda.synchronize()
         return m, n_re
 
     m64, _ = labels(native.FP64, q_ev64, 0.0)
+    mh16, re_h = labels(native.FP16, q_ev32, MARGIN[3])
+    mh0, _ = labels(native.FP16, q_ev32, 0.0)
     mb16, re_b = labels(native.BF16, q_ev32, MARGIN[2])
     mb0, _ = labels(native.BF16, q_ev32, 0.0)
-    mh16, _ = labels(native.FP16, q_ev32, MARGIN[3])
 
     def flip(ma, mb):
         x = (ma ^ mb).cpu().numpy()
@@ -291,19 +315,21 @@ def bench_1d(a, P, dev, name):
 
     n_evals = faces_stage * EVALS_PER_FACE
     lab = {"state": "FP64 path after the %d timed RK3 steps, rounded to FP32" % a.steps,
+           "flip_rate_fp16": flip(mh16, m64), "flip_rate_per_face_fp16": flip_faces(mh16, m64),
+           "flip_rate_fp16_without_recheck": flip(mh0, m64),
            "flip_rate_bf16": flip(mb16, m64), "flip_rate_per_face_bf16": flip_faces(mb16, m64),
-           "flip_rate_fp16": flip(mh16, m64),
            "flip_rate_bf16_without_recheck": flip(mb0, m64),
-           "recheck_margin": {"bf16": MARGIN[2], "fp16": MARGIN[3]},
+           "recheck_margin": {"fp16": MARGIN[3], "bf16": MARGIN[2]},
            # the overlap face of two 64-face tiles is counted by both
+           "recheck_fraction_fp16": re_h / float(n_evals),
            "recheck_fraction_bf16": re_b / float(n_evals)}
 
     # ---- fused kernel alone: the right-hand-side pass as inside the step, on
-    # the states of the BF16 trajectory (every tenth step of the timed ones:
+    # the states of the headline trajectory (every tenth step of the timed ones:
     # the classifier's work and the share of flat stencils change as the
     # solution evolves) --------------------------------------------------------------
-    mlpk, probk, wsk = make(native.BF16, MARGIN[2])
-    probk.set_tuning(shapes_used.get(native.BF16))  # the launch shape of the timed steps
+    mlpk, probk, wsk = make(HEAD, MARGIN[HEAD])
+    probk.set_tuning(shapes_used.get(HEAD))  # the launch shape of the timed steps
     snaps = [q32.clone()]
     qs = q32.clone()
     ts = torch.zeros(n_prob, dtype=torch.float64, device=dev)
@@ -400,31 +426,32 @@ def bench_1d(a, P, dev, name):
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": ms_b / a.steps,
+        "ms_per_step": ms_h / a.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": "fp16",
         "data": "synthetic",
         "config": {"workload": "%s; characteristic NENO6, LF splitting, SSP-RK3 CFL %.1f; FP32 "
-                               "state, BF16-MFMA classifier, FP32 re-check margin %.2f"
-                               % (label, CFL, MARGIN[2]),
+                               "state, classifier on MFMA with FP16 operands and FP32 "
+                               "accumulation, FP32 re-check margin %.2f (BF16 operands: "
+                               "bf16_mfma, margin %.2f)" % (label, CFL, MARGIN[3], MARGIN[2]),
                    "faces_per_step": faces_step, "hip_graph": graphed,
-                   "rk3_steps_per_graph_replay": per_b,
-                   "launch_shapes": {"bf16": shapes_used.get(native.BF16),
-                                     "fp16": shapes_used.get(native.FP16)}},
+                   "rk3_steps_per_graph_replay": per_h,
+                   "launch_shapes": {"fp16": shapes_used.get(native.FP16),
+                                     "bf16": shapes_used.get(native.BF16)}},
         # the binding resource of the fused kernel is VALU issue (the
         # instruction-counter profile); the MFMA and HBM fractions follow
         "roofline": dict(_alu(faces_stage, k_ms), traffic=traffic,
                          traffic_launch_shape=trec.get("launch_shape") if trec else None,
-                         kernel="k_euler1d<BF16> (fused faces, FP32 re-check, flux difference; "
+                         kernel="k_euler1d<FP16> (fused faces, FP32 re-check, flux difference; "
                                 "right-hand-side output)", kernel_ms=k_ms,
                          kernel_ms_by_step={str(10 * i): v for i, v in enumerate(k_each)},
                          algorithmic_flop_per_launch=flop,
                          algorithmic_bytes_per_launch=alg_bytes),
         "end_to_end_valu_frac": e2e,
-        "roofline_mfma": {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_BF16,
-                          "unit": "TFLOP/s", "frac": achieved / PEAK_MFMA_BF16},
+        "roofline_mfma": {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_16,
+                          "unit": "TFLOP/s", "frac": achieved / PEAK_MFMA_16},
         "roofline_hbm": {"bound": "hbm",
                          "achieved": (traffic or alg_bytes) / (k_ms / 1e3) / 1e9,
                          "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -432,15 +459,16 @@ def bench_1d(a, P, dev, name):
                          "bytes": "measured traffic" if traffic else "algorithmic"},
         "fp64_plain": {"value": fp64_rate, "unit": "faces/s", "ms_per_step": ms_64 / k64,
                        "steps": k64},
-        "fp16_mfma": {"value": fp16_rate, "unit": "faces/s", "ms_per_step": ms_h / a.steps,
-                      "l1_rel_vs_fp64": l1_h, "linf_rel_vs_fp64": linf_h},
-        "speedup_bf16_vs_fp64": value / fp64_rate,
+        "bf16_mfma": {"value": bf16_rate, "unit": "faces/s", "ms_per_step": ms_b / a.steps,
+                      "recheck_margin": MARGIN[2], "l1_rel_vs_fp64": l1_b,
+                      "linf_rel_vs_fp64": linf_b, "speedup_vs_fp64": bf16_rate / fp64_rate},
+        "speedup_vs_fp64": value / fp64_rate,
         "labels": lab,
-        "flip_rate": lab["flip_rate_bf16"],
+        "flip_rate": lab["flip_rate_fp16"],
         "l1_rel_vs_fp64": l1,
         "linf_rel_vs_fp64": linf,
-        "frozen_problems": {"bf16": int((stb != 0).sum()), "fp64": int((st64b != 0).sum()),
-                            "of": n_prob},
+        "frozen_problems": {"fp16": int((sth != 0).sum()), "bf16": int((stb != 0).sum()),
+                            "fp64": int((st64b != 0).sum()), "of": n_prob},
         "problems_in_error_norms": n_norm,
         "cpu_baseline": cpu,
     }
@@ -448,8 +476,9 @@ def bench_1d(a, P, dev, name):
 
 def bench_2d(a, P, dev):
     """2D Euler, four-quadrant Riemann problem on 2048 x 2048 cells
-    (transmissive), FP32 state, BF16 classifier with the FP32 re-check; one
-    step = one SSP-RK3 step (x and y sweeps in each stage), HIP graph."""
+    (transmissive), FP32 state, classifier on FP16 MFMA with the FP32
+    re-check; one step = one SSP-RK3 step (x and y sweeps in each stage), HIP
+    graph."""
     import numpy as np
     import torch
 
@@ -472,7 +501,7 @@ def bench_2d(a, P, dev):
 
     def run(prec, q_init, steps, warmup):
         mlp, prob, ws = make(prec)
-        if prec in (native.BF16, native.FP16):
+        if prec in (native.FP16, native.FP16):
             shapes[prec] = autotune.tuned(prob, mlp, q_init, ws)[0]
         q = q_init.clone()
         t = torch.zeros(1, dtype=torch.float64, device=dev)
@@ -499,7 +528,7 @@ def bench_2d(a, P, dev):
         torch.cuda.synchronize()
         return q, t, st, e0.elapsed_time(e1)
 
-    qb, tb, stb, ms_b = run(native.BF16, q32, a.steps, a.warmup)
+    qb, tb, stb, ms_b = run(native.FP16, q32, a.steps, a.warmup)
     value = faces_step * a.steps / (ms_b / 1e3)
     k64 = max(2, a.steps // 4)
     _, _, _, ms_64 = run(native.FP64, q64_from32, k64, 1)
@@ -515,9 +544,9 @@ def bench_2d(a, P, dev):
         native.neno6_rhs(prob, mlp, q, r, ws, masks_out=m)
         return m
 
-    x = (labels(native.BF16, q32) ^ labels(native.FP64, q64_from32)).cpu().numpy()
+    x = (labels(native.FP16, q32) ^ labels(native.FP64, q64_from32)).cpu().numpy()
     # evaluations the FP32 re-check took on the initial state (both sweeps)
-    mlpm, probm, wsm = make(native.BF16)
+    mlpm, probm, wsm = make(native.FP16)
     native.neno6_face_fluxes(probm, mlpm, q32, torch.zeros(4 * faces_stage, dtype=torch.float32,
                                                             device=dev), wsm)
     recheck_frac = sum(native.neno6_recheck_count(probm, mlpm, wsm)) / float(faces_stage * EVALS_PER_FACE_2D)
@@ -527,8 +556,8 @@ def bench_2d(a, P, dev):
                                       (x[4 * nfx:].reshape(4, -1) != 0).any(axis=0)]).mean())
     # both sweeps of the fused face kernel alone (margin 0)
     mlp0 = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=0.0)
-    _, prob0, ws0 = make(native.BF16)
-    prob0.set_tuning(shapes.get(native.BF16))
+    _, prob0, ws0 = make(native.FP16)
+    prob0.set_tuning(shapes.get(native.FP16))
     F = torch.zeros(4 * faces_stage, dtype=torch.float32, device=dev)
     for _ in range(150):  # about 0.1 s: steady clocks
         native.neno6_face_fluxes(prob0, mlp0, q32, F, ws0)
@@ -554,26 +583,26 @@ def bench_2d(a, P, dev):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": "fp16",
         "data": "synthetic",
         "config": {"workload": "2D Euler four-quadrant Riemann problem, %d x %d cells, transmissive, "
-                               "FP32 state, BF16-MFMA classifier, re-check margin %.2f, SSP-RK3 "
-                               "CFL %.1f" % (nx, ny, MARGIN[2], CFL),
+                               "FP32 state, FP16-MFMA classifier, re-check margin %.2f, SSP-RK3 "
+                               "CFL %.1f" % (nx, ny, MARGIN[3], CFL),
                    "faces_per_step": faces_step, "hip_graph": True,
-                   "launch_shapes": shapes.get(native.BF16)},
+                   "launch_shapes": shapes.get(native.FP16)},
         "roofline": dict(_alu(faces_stage, k_ms, VALU_OPS_PER_FACE_2D), traffic=None,
-                         kernel="k_fast_faces<BF16, 2D Euler>, x and y sweeps", kernel_ms=k_ms,
+                         kernel="k_fast_faces<FP16, 2D Euler>, x and y sweeps", kernel_ms=k_ms,
                          algorithmic_flop_per_launch=flop),
-        "roofline_mfma": {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_BF16,
-                          "unit": "TFLOP/s", "frac": achieved / PEAK_MFMA_BF16},
+        "roofline_mfma": {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_16,
+                          "unit": "TFLOP/s", "frac": achieved / PEAK_MFMA_16},
         "fp64_plain": {"value": fp64_rate, "unit": "faces/s", "ms_per_step": ms_64 / k64,
                        "steps": k64},
-        "speedup_bf16_vs_fp64": value / fp64_rate,
+        "speedup_vs_fp64": value / fp64_rate,
         "flip_rate": flip,
         "flip_rate_per_face": flip_face,
         "l1_rel_vs_fp64": l1,
         "recheck_fraction": recheck_frac,
-        "status": {"bf16": int(stb[0]), "fp64": int(st64b[0])},
+        "status": {"fp16": int(stb[0]), "fp64": int(st64b[0])},
         "cpu_baseline": None,
     }
     print(json.dumps(out))
@@ -660,8 +689,8 @@ def bench_train(a, dev):
                                "half step/kink), 70 %% training, batch %d, Adam lr 1e-3, BF16 MFMA "
                                "with FP32 accumulation, FP64 master weights" % batch,
                    "samples_per_step": batch},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_BF16,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_MFMA_BF16, "traffic": None,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_16,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_MFMA_16, "traffic": None,
                      "flop_per_sample": TRAIN_FLOP_PER_SAMPLE},
         "loss": {"after_warmup": loss_warm, "after_timed_steps": float(loss.item()),
                  "validation": float(vloss.item())},

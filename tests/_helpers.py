@@ -12,6 +12,15 @@ def trained_params() -> np.ndarray:
     return np.load(os.path.join(GOLDEN, "neno6_mlp_trained.npy"), allow_pickle=False)
 
 
+def stated_margins() -> dict:
+    """Re-check margins (logit units) of the committed weights, keyed by the
+    library's precision codes (2: BF16, 3: FP16)."""
+    import json
+    with open(os.path.join(GOLDEN, "neno6_mlp_trained_margins.json")) as f:
+        m = json.load(f)["margin"]
+    return {2: float(m["bf16"]), 3: float(m["fp16"])}
+
+
 def need_gpu():
     import torch
     if not torch.cuda.is_available():

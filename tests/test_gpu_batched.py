@@ -20,11 +20,11 @@ import pytest
 
 import oracle
 from paper_2207_08500_amd import inputs
-from tests._helpers import dev, host, label_flip_rate, need_gpu, trained_params
+from tests._helpers import dev, host, label_flip_rate, need_gpu, trained_params, stated_margins
 
 pytestmark = pytest.mark.gpu
 
-MARGIN_BF16 = 0.5
+MARGIN_BF16 = stated_margins()[2]
 
 
 @pytest.fixture(scope="module")

@@ -12,11 +12,11 @@ import pytest
 
 import oracle
 from paper_2207_08500_amd import inputs
-from tests._helpers import dev, host, label_flip_rate, need_gpu, trained_params
+from tests._helpers import dev, host, label_flip_rate, need_gpu, trained_params, stated_margins
 
 pytestmark = pytest.mark.gpu
 
-MARGIN = {2: 0.5, 3: 0.25}
+MARGIN = stated_margins()
 
 
 @pytest.fixture(scope="module")

@@ -16,11 +16,11 @@ import pytest
 
 import oracle
 from paper_2207_08500_amd import inputs
-from tests._helpers import dev, host, label_flip_rate, need_gpu, trained_params
+from tests._helpers import dev, host, label_flip_rate, need_gpu, trained_params, stated_margins
 
 pytestmark = pytest.mark.gpu
 
-MARGIN = {2: 0.5, 3: 0.25}
+MARGIN = stated_margins()
 SIZES = (1, 2, 3, 7, 62, 63, 64, 65, 126, 127, 128, 500, 1000)
 
 
@@ -215,11 +215,15 @@ def test_launch_shapes_bitwise(ctx, prec):
         assert n_re >= res[0][4]  # the overlap faces of the tiles are re-checked by both tiles
 
 
-def test_c2_full_size_evolved_state(ctx):
-    """The 256 x 4000 batch in the benchmark's configuration, on a state that
-    the FP64 path (bit-exact with the oracle) advanced 40 RK3 steps from the
-    Riemann data: labels and right-hand side of the BF16 pass against the
-    oracle on sampled problems of that evolved state."""
+@pytest.mark.parametrize("prec", [2, 3])
+def test_c2_full_size_evolved_state(ctx, prec):
+    """The 256 x 4000 batch in the benchmark's configuration on an evolved
+    state: the FP64 path advances the batch 40 RK3 steps from the Riemann
+    data (a realistic state for the whole launch), and six sampled problems
+    are replaced by the oracle's own 40-step evolution of their Riemann data,
+    so that every compared input comes from the oracle.  Labels and
+    right-hand side of the reduced pass on those problems against the
+    oracle's on the same (FP32-rounded) state."""
     native, torch, P = ctx
     from paper_2207_08500_amd import autotune
     q, off, dx = inputs.riemann1d_batch(inputs.BASE_SEED, (4000,) * 256)
@@ -229,17 +233,27 @@ def test_c2_full_size_evolved_state(ctx):
     st = torch.zeros(256, dtype=torch.int32, device="cuda")
     native.neno6_step(p64, native.Mlp(dev(P)), q64, 0.4, 40, t, st, p64.workspace())
     torch.cuda.synchronize()
-    qe = host(q64).reshape(3, -1).astype(np.float32).astype(np.float64)
-    stp = host(st)
+    qe = host(q64).reshape(3, -1).copy()
+    # the sampled problems, evolved by the oracle from the same initial data
+    cand = list(range(0, 256, 37))
+    sub0 = np.concatenate([q[:, off[p]:off[p + 1]] for p in cand], axis=1)
+    q_o, _, st_o = oracle.euler1d_step(sub0, np.arange(len(cand) + 1) * 4000,
+                                       dx[cand], 0.4, 40, 1.4, 1, P, oracle.SEL_MLP)
+    picked = []
+    for i, p in enumerate(cand):
+        if st_o[i] == 0:
+            qe[:, off[p]:off[p + 1]] = q_o[:, 4000 * i:4000 * (i + 1)]
+            picked.append(p)
+    assert len(picked) >= 5
+    qe = qe.astype(np.float32).astype(np.float64)
     q32 = dev(qe, torch.float32)
-    mlp = native.Mlp(dev(P), recheck_margin=MARGIN[2])
-    prob = native.Problem(native.EULER1D, native.BF16, native.SEL_MLP, 1, off, dx)
+    mlp = native.Mlp(dev(P), recheck_margin=MARGIN[prec])
+    prob = native.Problem(native.EULER1D, prec, native.SEL_MLP, 1, off, dx)
     ws = prob.workspace()
     tun, _ = autotune.tuned(prob, mlp, q32, ws)
-    r, m, _, _, n_re = _rhs(native, torch, P, native.BF16, MARGIN[2], q32, off, dx, tuning=tun)
+    r, m, _, _, n_re = _rhs(native, torch, P, prec, MARGIN[prec], q32, off, dx, tuning=tun)
     flips, worst = [], 0.0
-    live = [p for p in range(256) if stp[p] == 0]
-    for p in live[:: max(1, len(live) // 6)][:6]:
+    for p in picked:
         a, b = off[p], off[p + 1]
         sub = qe[:, a:b]
         r_o, m_o, _ = oracle.euler1d_rhs(sub, [0, 4000], dx[p:p + 1], 1.4, 1, P, oracle.SEL_MLP)
@@ -249,7 +263,8 @@ def test_c2_full_size_evolved_state(ctx):
         err = np.abs(r[:, a:b] - r_o) / _fscale(r_o, sub, [0, 4000], dx[p:p + 1])
         worst = max(worst, float(err[:, ok].max()))
         assert ok.mean() > 0.99
-    print("C2 evolved 40 steps: sampled flip rates %s, max rel err at oracle labels %.3g, "
-          "re-checked %.3g of the evaluations" % (flips, worst, n_re / (6.0 * (off[-1] + 256))))
-    assert max(flips) < 1e-3
+    print("C2 evolved 40 steps, prec %d: sampled flip rates %s, max rel err at oracle labels "
+          "%.3g, re-checked %.3g of the evaluations"
+          % (prec, flips, worst, n_re / (6.0 * (off[-1] + 256))))
+    assert max(flips) < 1e-4
     assert worst <= 5e-5
