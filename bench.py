@@ -14,7 +14,7 @@ replayed.
 Headline path: FP32 state, classifier layers on MFMA with FP16 operands and
 FP32 accumulation, re-check margin 2x the largest FP16 logit error observed
 on 2^20 training samples.  BF16 operands keep 8 significant bits against
-FP16's 11, so the same rule gives BF16 a margin nine times wider (more
+FP16's 11, so the same rule gives BF16 a margin about nine times wider (more
 evaluations go to the FP32 re-check) at the same MFMA rate; the BF16-MFMA
 path is measured beside it.  Also on the same GPU: the plain FP64 path; the
 labels of both reduced paths against the FP64 labels on the FP64 path's

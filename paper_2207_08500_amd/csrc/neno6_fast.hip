@@ -50,7 +50,7 @@ typedef u32 u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int TPB = 256;
 constexpr int WPB = TPB / 64;
-constexpr int TAB_REGS = 84;
+constexpr int TAB_REGS = 92;
 constexpr int TAB_BYTES = TAB_REGS * 64 * 4;
 constexpr int PREP_BF16_OFF = 16384;
 constexpr int PREP_F16_OFF = PREP_BF16_OFF + TAB_BYTES;
@@ -69,6 +69,13 @@ template <> N6_DEV u32 pack2<2>(float a, float b) {
 template <> N6_DEV u32 pack2<3>(float a, float b) {
   const f32x2 v = {a, b};
   return __builtin_bit_cast(u32, __builtin_convertvector(v, f16x2));
+}
+template <int PREC> N6_DEV f32x2 unpack2(u32 v);
+template <> N6_DEV f32x2 unpack2<2>(u32 v) {
+  return __builtin_convertvector(__builtin_bit_cast(bf16x2, v), f32x2);
+}
+template <> N6_DEV f32x2 unpack2<3>(u32 v) {
+  return __builtin_convertvector(__builtin_bit_cast(f16x2, v), f32x2);
 }
 N6_DEV u32 relu2(u32 x) {
   const s16x2 z = {0, 0};
@@ -180,7 +187,8 @@ N6_DEV void swap32(u32 &x, u32 &y) {
 
 // ---- classifier registers ------------------------------------------------------
 struct Wts {
-  u32x2 a1[2];
+  u32x2 a1[2];   // L1, K = 8 (the training forward)
+  u32x4 a1x[2];  // L1, K = 16: the features' leading and trailing parts
   u32x4 a2[4], a3[2], a4, a5;
   f32x16 b2, b3, b4;
   float b5[4];
@@ -192,6 +200,8 @@ N6_DEV void load_wts(const void *prepared, int lane, Wts &w) {
 #define N6R(r) t[(r)*64 + lane]
   w.a1[0] = u32x2{N6R(0), N6R(1)};
   w.a1[1] = u32x2{N6R(2), N6R(3)};
+  w.a1x[0] = u32x4{N6R(84), N6R(85), N6R(86), N6R(87)};
+  w.a1x[1] = u32x4{N6R(88), N6R(89), N6R(90), N6R(91)};
 #pragma unroll
   for (int s = 0; s < 4; ++s) w.a2[s] = u32x4{N6R(4 + 4 * s), N6R(5 + 4 * s), N6R(6 + 4 * s), N6R(7 + 4 * s)};
 #pragma unroll
@@ -215,10 +225,10 @@ N6_DEV void load_wts(const void *prepared, int lane, Wts &w) {
 // Returns the packed L4 activations: neurons 4h..4h+3 of column j (rows 8..31
 // of the L4 product are padding).
 template <int PREC>
-N6_DEV u32x2 mlp_front(const Wts &w, u32x2 bin) {
+N6_DEV u32x2 mlp_front(const Wts &w, u32x4 bin) {
   const f32x16 zero = {};
-  const f32x16 c1a = mma8<PREC>(w.a1[0], bin, zero);
-  const f32x16 c1b = mma8<PREC>(w.a1[1], bin, zero);
+  const f32x16 c1a = mma16<PREC>(w.a1x[0], bin, zero);
+  const f32x16 c1b = mma16<PREC>(w.a1x[1], bin, zero);
   u32 h1a[8], h1b[8];
   act_block<PREC, 8, 20>(c1a, 0, h1a);
   act_block<PREC, 8, 20>(c1b, 0, h1b);
@@ -238,17 +248,22 @@ N6_DEV u32x2 mlp_front(const Wts &w, u32x2 bin) {
   return u32x2{h4[0], h4[1]};
 }
 
-// L1 B operand halves of one stencil: X = features 0..3, Y = features 4, 5,
-// the bias slot 1 and a zero.
+// The six features of one stencil as packed pairs: x[0..2] their values
+// rounded to the table precision, x[3..5] what that rounding left (so the
+// first layer sees each feature to about twice the precision's bits).
 template <int PREC>
-N6_DEV void feature_pack(const float s[6], u32 &x0, u32 &x1, u32 &y0) {
+N6_DEV void feature_pack(const float s[6], u32 x[6]) {
   float M = 1.f;
 #pragma unroll
   for (int j = 0; j < 6; ++j) M = fmaxf(M, fabsf(s[j]));
   const float r = __builtin_amdgcn_rcpf(M);
-  x0 = pack2<PREC>(s[0] * r, s[1] * r);
-  x1 = pack2<PREC>(s[2] * r, s[3] * r);
-  y0 = pack2<PREC>(s[4] * r, s[5] * r);
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    const float a = s[2 * p] * r, b = s[2 * p + 1] * r;
+    x[p] = pack2<PREC>(a, b);
+    const f32x2 hi = unpack2<PREC>(x[p]);
+    x[3 + p] = pack2<PREC>(a - hi[0], b - hi[1]);
+  }
 }
 template <int PREC> N6_DEV u32 one_zero() { return pack2<PREC>(1.f, 0.f); }
 
@@ -268,12 +283,22 @@ N6_DEV u32 mask_near(const float z[4], float margin) {
 // call it together).  Returns the lane's mask | near-flag << 4; with z != 0
 // also returns the lane's four logits.
 template <int PREC>
-N6_DEV u32 classify_packed(const Wts &w, u32 x0, u32 x1, u32 y0, float margin, float *z_out) {
-  u32 y1 = one_zero<PREC>();
-  swap32(x0, y0);  // x0: tile 0 (faces of lanes 0..31), y0: tile 1
-  swap32(x1, y1);
-  const u32x2 h0 = mlp_front<PREC>(w, u32x2{x0, x1});
-  const u32x2 h1 = mlp_front<PREC>(w, u32x2{y0, y1});
+N6_DEV u32 classify_packed(const Wts &w, const u32 xin[6], float margin, float *z_out) {
+  // K slots of the first layer: lanes 0..31 carry the leading parts (slots
+  // 0..5) and the bias input 1 (slot 6), lanes 32..63 the trailing parts
+  // (slots 8..13).  Tile 0 (faces of lanes 0..31) keeps the leading parts
+  // of lanes 0..31 and gets the trailing parts of the same faces from lanes
+  // 0..31 moved up; tile 1 the other way round.
+  u32 a[3], b[3];
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    a[p] = xin[p];
+    b[p] = xin[3 + p];
+    swap32(a[p], b[p]);
+  }
+  const u32 cin = (threadIdx.x & 32) ? 0u : one_zero<PREC>();
+  const u32x2 h0 = mlp_front<PREC>(w, u32x4{a[0], a[1], a[2], cin});
+  const u32x2 h1 = mlp_front<PREC>(w, u32x4{b[0], b[1], b[2], cin});
   const f32x16 zero = {};
   const f32x16 c = mma16<PREC>(w.a5, u32x4{h0[0], h0[1], h1[0], h1[1]}, zero);
   float z[4];
@@ -288,9 +313,9 @@ N6_DEV u32 classify_packed(const Wts &w, u32 x0, u32 x1, u32 y0, float margin, f
 
 template <int PREC>
 N6_DEV u32 classify_wave(const Wts &w, const float s[6], float margin, float *z_out) {
-  u32 x0, x1, y0;
-  feature_pack<PREC>(s, x0, x1, y0);
-  return classify_packed<PREC>(w, x0, x1, y0, margin, z_out);
+  u32 x[6];
+  feature_pack<PREC>(s, x);
+  return classify_packed<PREC>(w, x, margin, z_out);
 }
 
 N6_DEV const float *uniform_f32(const void *prepared) {
@@ -569,7 +594,7 @@ k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared
     const int64_t f = ch * 64 + lane;
     const bool valid = f < nf;
     const int64_t fc = valid ? f : nf - 1;
-    u32 fx[NE][3];
+    u32 fx[NE][6];
     {
       float s[NE][6];
       Roe2 rw;
@@ -577,7 +602,7 @@ k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared
       const float R[NR] = {rw.nt, rw.st, rw.ct, rw.Ht, rw.q2};
       if constexpr (MLP) {
 #pragma unroll
-        for (int e = 0; e < NE; ++e) feature_pack<PREC>(s[e], fx[e][0], fx[e][1], fx[e][2]);
+        for (int e = 0; e < NE; ++e) feature_pack<PREC>(s[e], fx[e]);
       }
 #pragma unroll
       for (int e = 0; e < NE; ++e)
@@ -595,7 +620,7 @@ k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared
     for (int e = 0; e < NE; ++e) {
       if constexpr (MLP) {
         __builtin_amdgcn_sched_barrier(0);
-        const u32 mk = classify_packed<PREC>(w, fx[e][0], fx[e][1], fx[e][2], margin, nullptr);
+        const u32 mk = classify_packed<PREC>(w, fx[e], margin, nullptr);
         sel[e] = mk & 15u;
         near |= (mk >> 4) << e;
       } else if (selector == 1) {
@@ -1215,7 +1240,6 @@ k_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float marg
   for (int64_t t = lb * W + wv; t < ntile; t += nb * W) {
     const int64_t g = t * 63 + lane;
     const bool valid = g < nf;
-    u32 fx[NE][3];
     {
       // the face's line and geometry wait in LDS with the stencils: nothing
       // but the classifier's operands holds registers through the MFMA phase
@@ -1224,10 +1248,6 @@ k_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float marg
       Roe1 rw;
       bool flat;
       setup1d(ln, q, fa, s, rw, qc, pc, &flat);
-      if constexpr (MLP) {
-#pragma unroll
-        for (int e = 0; e < NE; ++e) feature_pack<PREC>(s[e], fx[e][0], fx[e][1], fx[e][2]);
-      }
 #pragma unroll
       for (int e = 0; e < NE; ++e)
 #pragma unroll
@@ -1246,11 +1266,24 @@ k_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float marg
     // chains are issued as soon as they are ready, and the other waves'
     // set-up and combine work fills the gaps
     if constexpr (MLP) __builtin_amdgcn_s_setprio(1);
+    // each evaluation's features are formed from its stashed stencil right
+    // before it is classified; the next stencil is read meanwhile
+    float sn[6];
+    if constexpr (MLP) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) sn[j] = stash[wv][j][lane];
+    }
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
       if constexpr (MLP) {
         __builtin_amdgcn_sched_barrier(0);
-        const u32 mk = classify_packed<PREC>(w, fx[e][0], fx[e][1], fx[e][2], margin, nullptr);
+        u32 xe[6];
+        feature_pack<PREC>(sn, xe);
+        if (e + 1 < NE) {
+#pragma unroll
+          for (int j = 0; j < 6; ++j) sn[j] = stash[wv][(e + 1) * 6 + j][lane];
+        }
+        const u32 mk = classify_packed<PREC>(w, xe, margin, nullptr);
         sel[e] = mk & 15u;
         near |= (mk >> 4) << e;
       } else if (selector == 1) {
@@ -1587,7 +1620,20 @@ N6_DEV void prepare_entry(const double *__restrict__ P, const double *__restrict
     v[q2] = (float)x;
   }
   u32 wb, wh;
-  if (!is_bias) {
+  if (reg >= 84) {
+    // L1 with K = 16: lanes (i, 0) slots 0..7 = W1 row o on the leading
+    // parts, b1 on the bias input; lanes (i, 1) slots 8..15 = W1 row o on the
+    // trailing parts
+    const int tt = (reg - 84) / 4, word = (reg - 84) % 4, o = 32 * tt + i;
+    float v2[2];
+    for (int q = 0; q < 2; ++q) {
+      const int k = 2 * word + q;
+      double x = k < 6 ? P[OW1 + o * 6 + k] : (k == 6 && h == 0 ? P[OB1 + o] : 0.0);
+      v2[q] = (float)(x / sc(SC1, o));
+    }
+    wb = pack2<2>(v2[0], v2[1]);
+    wh = pack2<3>(v2[0], v2[1]);
+  } else if (!is_bias) {
     wb = pack2<2>(v[0], v[1]);
     wh = pack2<3>(v[0], v[1]);
   } else {
