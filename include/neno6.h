@@ -312,6 +312,19 @@ int32_t neno6_rhs_vjp(const neno6_problem *prob, const void *q, const uint8_t *m
 
 /* ---- classifier training (Sec. 3.3) ---------------------------------------- */
 /* Workspace bytes for training with mini-batches of `batch` samples. */
+/* Seeded synthetic training samples, generated on the device: the
+ * six-point stencils f(x_c + (j - 2) dx), j = 0..5, of smooth functions
+ * (polynomials of degree <= 5, sines with amplitude 1e-2..1e2) and of
+ * functions with a step or a kink (jump ratio 1e-3..1e3), with the label of
+ * each candidate sub-stencil (bit k set: candidate k crosses the jump) --
+ * the kind of data the classifier of Sec. 3.2 is trained on, N in
+ * {50, 100, 200} at 40/40/20 % as in Alg. 1.  Sample i depends only on
+ * (seed, i) (Philox4x32-10 counters), so any range can be generated in
+ * pieces.  s [dev, n x 6 FP32], y [dev, n bytes]; first >= 0, n >= 0.
+ * Returns NENO6_BAD_ARG for null buffers with n > 0 or negative sizes. */
+int32_t neno6_classifier_samples(uint64_t seed, int64_t first, int64_t n, float *s, uint8_t *y,
+                                 hipStream_t stream);
+
 size_t neno6_train_workspace_size(int32_t batch);
 
 /* Adam on the binary cross entropy averaged over the four outputs and the

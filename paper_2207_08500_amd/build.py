@@ -25,6 +25,7 @@ SOURCES = {
     "neno6_plain.hip": ["-ffp-contract=off"],
     "neno6_fast.hip": [],
     "neno6_train.hip": [],
+    "neno6_datagen.hip": ["-ffp-contract=off"],
     "neno6_capi.cpp": [],
 }
 

@@ -675,6 +675,13 @@ int32_t neno6_step(const neno6_problem *prob, const neno6_mlp *mlp, void *q, dou
   return NENO6_OK;
 }
 
+int32_t neno6_classifier_samples(uint64_t seed, int64_t first, int64_t n, float *s, uint8_t *y,
+                                 hipStream_t stream) {
+  if (first < 0 || n < 0 || first > INT64_MAX - n) return NENO6_BAD_ARG;
+  if (n > 0 && (!s || !y)) return NENO6_BAD_ARG;
+  return hip_status(launch_classifier_samples(seed, first, n, s, y, stream));
+}
+
 int32_t neno6_rhs_adjoint(const neno6_problem *prob, const uint8_t *masks, const void *rbar,
                           void *ubar, hipStream_t stream) {
   if (int32_t c = check_problem(prob)) return c;

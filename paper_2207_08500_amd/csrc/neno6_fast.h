@@ -74,6 +74,9 @@ hipError_t launch_fast_rhs2d(const Grid2D &g, const FastArgs &fa, const float *q
                              float *Fx, float *Gy, const Stage *st, hipStream_t s);
 
 // ---- training ----------------------------------------------------------------
+// Seeded classifier-training samples first .. first+n-1 (s [n][6], y [n]).
+hipError_t launch_classifier_samples(uint64_t seed, int64_t first, int64_t n, float *s, uint8_t *y,
+                                     hipStream_t st);
 size_t train_workspace_bytes(int32_t batch);
 bool train_precision_supported(int precision);
 // BF16 MFMA gradient: per-wave partials part[train_mfma_waves(m)][3228] and

@@ -224,6 +224,91 @@ def classifier_samples(seed: int = BASE_SEED, n: int = 1 << 16):
     return np.ascontiguousarray(s), y
 
 
+# --------------------------------------------------------------------------
+# Counter-based classifier samples: the same distribution as
+# classifier_samples, drawn per sample from Philox4x32-10 (Salmon, Moraes,
+# Dror and Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC 2011) so
+# that any range of samples can be generated on the device independently.
+# This is the host twin of the library's generator: sample i uses the
+# counters (lo(i), hi(i), b, 0x43355331) for b = 0..4 and the key (lo(seed),
+# hi(seed)); a 32-bit word w gives the uniform (w + 1/2) 2^-32; every value is
+# formed in FP64 with separately rounded operations in the order written
+# here, then rounded to FP32.
+# --------------------------------------------------------------------------
+PHILOX_M = (0xD2511F53, 0xCD9E8D57)
+PHILOX_W = (0x9E3779B9, 0xBB67AE85)
+C5_STREAM = 0x43355331
+LN_1EM2, LN_1E2 = float.fromhex("-0x1.26bb1bbb55515p+2"), float.fromhex("0x1.26bb1bbb55516p+2")
+LN_1EM3, LN_1E3 = float.fromhex("-0x1.ba18a998fffa0p+2"), float.fromhex("0x1.ba18a998fffa0p+2")
+TWO_PI = float.fromhex("0x1.921fb54442d18p+2")
+
+
+def philox4x32_10(ctr: np.ndarray, key) -> np.ndarray:
+    """Philox4x32 with 10 rounds: ctr [..., 4] uint32, key (k0, k1)."""
+    c = [np.asarray(ctr[..., i], np.uint32) for i in range(4)]
+    k0, k1 = int(key[0]) & 0xFFFFFFFF, int(key[1]) & 0xFFFFFFFF
+    for r in range(10):
+        if r:
+            k0 = (k0 + PHILOX_W[0]) & 0xFFFFFFFF
+            k1 = (k1 + PHILOX_W[1]) & 0xFFFFFFFF
+        p0 = np.uint64(PHILOX_M[0]) * c[0].astype(np.uint64)
+        p1 = np.uint64(PHILOX_M[1]) * c[2].astype(np.uint64)
+        c = [(p1 >> np.uint64(32)).astype(np.uint32) ^ c[1] ^ np.uint32(k0), p1.astype(np.uint32),
+             (p0 >> np.uint64(32)).astype(np.uint32) ^ c[3] ^ np.uint32(k1), p0.astype(np.uint32)]
+    return np.stack(c, axis=-1)
+
+
+def classifier_samples_philox(seed: int = BASE_SEED, first: int = 0, n: int = 1 << 16):
+    """Samples first .. first+n-1 of the counter-based generator.
+
+    Per sample: N in {50, 100, 200} at 40/40/20 %, dx = 2/N, x_c ~ U[-1, 1],
+    cells x_j = x_c + (j - 2) dx, j = 0..5; smooth with probability 1/2, then
+    a polynomial of degree 0-5 in t = (j - 2) dx (coefficients U[-1, 1],
+    Horner) or A sin(w x + phi) (w ~ U[0.5, 20], phi ~ U[0, 2 pi], A
+    log-uniform in [1e-2, 1e2]), labels 0; else a jump at x_d ~ U(x_0, x_5): a
+    step (a | a r) or a kink ((x - x_d) a | (x - x_d) a r), a = +-U[0.1, 1],
+    r log-uniform in [1e-3, 1e3], and candidate k labelled 1 iff x_d lies
+    strictly inside its span (FP64 comparisons).
+    Returns (s [n][6] FP32, y [n] uint8, s64 [n][6] FP64 before rounding)."""
+    i = np.arange(first, first + n, dtype=np.uint64)
+    ctr = np.zeros((5, n, 4), np.uint32)
+    ctr[:, :, 0] = (i & np.uint64(0xFFFFFFFF)).astype(np.uint32)[None, :]
+    ctr[:, :, 1] = (i >> np.uint64(32)).astype(np.uint32)[None, :]
+    ctr[:, :, 2] = np.arange(5, dtype=np.uint32)[:, None]
+    ctr[:, :, 3] = C5_STREAM
+    words = philox4x32_10(ctr, (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF))  # [5][n][4]
+    u = (words.astype(np.float64) + 0.5) * 2.0 ** -32
+    N = np.where(u[0, :, 0] < 0.4, 50.0, np.where(u[0, :, 0] < 0.8, 100.0, 200.0))
+    dx = 2.0 / N
+    xc = -1.0 + 2.0 * u[0, :, 1]
+    smooth = u[0, :, 2] < 0.5
+    kind = u[0, :, 3] >= 0.5
+    t = np.arange(-2, 4, dtype=np.float64)[None, :] * dx[:, None]
+    xs = xc[:, None] + t
+    deg = np.minimum(np.floor(6.0 * u[1, :, 0]), 5.0)
+    coef = np.stack([u[2, :, 0], u[2, :, 1], u[2, :, 2], u[2, :, 3], u[3, :, 0], u[3, :, 1]], axis=1)
+    coef = np.where(np.arange(6)[None, :] <= deg[:, None], -1.0 + 2.0 * coef, 0.0)
+    poly = np.zeros((n, 6))
+    for d in range(5, -1, -1):
+        poly = poly * t + coef[:, d:d + 1]
+    w = 0.5 + 19.5 * u[1, :, 1]
+    phi = TWO_PI * u[1, :, 2]
+    A = np.exp(LN_1EM2 + u[1, :, 3] * (LN_1E2 - LN_1EM2))
+    sine = A[:, None] * np.sin(w[:, None] * xs + phi[:, None])
+    xd = xs[:, 0] + u[3, :, 2] * (xs[:, 5] - xs[:, 0])
+    a = (0.1 + 0.9 * u[3, :, 3]) * np.where(u[4, :, 0] < 0.5, -1.0, 1.0)
+    r = np.exp(LN_1EM3 + u[4, :, 1] * (LN_1E3 - LN_1EM3))
+    right = xs > xd[:, None]
+    amp = np.where(right, (a * r)[:, None], a[:, None])
+    disc = np.where(kind[:, None], amp * (xs - xd[:, None]), amp)
+    s64 = np.where(smooth[:, None], np.where(kind[:, None], sine, poly), disc)
+    y = np.zeros(n, np.uint8)
+    for k, (lo, hi) in enumerate(CANDIDATE_SPAN):
+        inside = (xd > xs[:, lo]) & (xd < xs[:, hi])
+        y |= np.where(~smooth & inside, np.uint8(1 << k), np.uint8(0)).astype(np.uint8)
+    return np.ascontiguousarray(s64.astype(np.float32)), y, np.ascontiguousarray(s64)
+
+
 def epoch_permutation(seed: int, epoch: int, n: int) -> np.ndarray:
     """The sample order of one training epoch (reshuffled every epoch)."""
     return rng(seed, 6, epoch).permutation(n).astype(np.int64)

@@ -33,7 +33,7 @@ EXPORTS = (
     "neno6_rhs_noalloc", "neno6_face_fluxes", "neno6_recheck_count", "neno6_autotune", "neno6_step",
     "neno6_rhs_adjoint", "neno6_vjp_workspace_size", "neno6_rhs_vjp",
     "neno6_train_workspace_size", "neno6_classifier_train",
-    "neno6_classifier_grad",
+    "neno6_classifier_grad", "neno6_classifier_samples",
 )
 
 
@@ -104,6 +104,7 @@ def load(path: str = LIB_PATH):
         lib.neno6_classifier_train.argtypes = [vp, vp, vp, P(C.c_int64), vp, vp, vp, i64, i32, f64,
                                                f64, f64, f64, i32, vp, vp, sz, vp]
         lib.neno6_classifier_grad.argtypes = [vp, vp, vp, i64, i32, vp, vp, vp, sz, vp]
+        lib.neno6_classifier_samples.argtypes = [C.c_uint64, i64, i64, vp, vp, vp]
         for name in EXPORTS:
             fn = getattr(lib, name)
             if fn.restype is C.c_int:  # default
@@ -412,3 +413,21 @@ def neno6_classifier_grad(params, s, y, precision, grad, loss, ws=None, stream=N
     _check(load().neno6_classifier_grad(_ptr(params), _ptr(s), _ptr(y), n, int(precision),
                                         _ptr(grad), _ptr(loss), _ptr(ws), ws.numel(),
                                         _stream(stream)), "neno6_classifier_grad")
+
+
+def neno6_classifier_samples(seed: int, first: int, n: int, s=None, y=None, device="cuda",
+                             stream=None):
+    """Seeded training samples first .. first+n-1 generated on the device:
+    returns (s [n][6] float32, y [n] uint8) (given tensors are filled)."""
+    if s is None:
+        s = torch.empty((n, 6), dtype=torch.float32, device=device)
+    if y is None:
+        y = torch.empty(n, dtype=torch.uint8, device=device)
+    _dev(s, torch.float32, "s")
+    _dev(y, torch.uint8, "y")
+    if s.numel() != 6 * n or y.numel() != n:
+        raise ValueError("s needs 6 n floats and y n bytes")
+    _check(load().neno6_classifier_samples(int(seed) & 0xFFFFFFFFFFFFFFFF, int(first), int(n),
+                                           _ptr(s), _ptr(y), _stream(stream)),
+           "neno6_classifier_samples")
+    return s, y
