@@ -69,7 +69,7 @@ int32_t check_problem(const neno6_problem *pb) {
     return NENO6_OK;
   }
   if (pb->n_problems < 1 || !pb->offsets || !pb->offsets_host || !pb->dx) return NENO6_BAD_ARG;
-  // re-check queue entries are 32-bit (face * 8 + evaluation)
+  // face indices packed with an evaluation index stay within 32 bits
   if (pb->total_cells < 1 || pb->total_cells + pb->n_problems >= (int64_t(1) << 29))
     return NENO6_BAD_ARG;
   if (pb->offsets_host[0] != 0 || pb->offsets_host[pb->n_problems] != pb->total_cells)
@@ -147,14 +147,9 @@ Work carve_work(const neno6_problem *pb, void *ws) {
     w.evals = c.take<char>(plain_eval_bytes(pb->equation == NENO6_EULER2D ? 8 : 6, nf, es));
   }
   if (pb->precision >= NENO6_BF16 && pb->equation == NENO6_EULER2D) {
-    // masks of the x and y faces, re-check queue of at most one entry per
-    // evaluation (8 per face slot), its flags, the near marks and counters
+    // masks of the x and y faces and the re-check counters
     const size_t faces = (size_t)(pb->nx + 1) * pb->ny + (size_t)pb->nx * (pb->ny + 1);
-    const size_t qfaces = std::max((size_t)(pb->nx + 1) * pb->ny, (size_t)pb->nx * (pb->ny + 1));
     w.scr.masks = c.take<uint8_t>(4 * faces);
-    w.scr.queue = c.take<uint32_t>(8 * qfaces);
-    w.scr.qflag = c.take<uint8_t>(8 * qfaces);
-    w.scr.qnear = c.take<uint8_t>((qfaces + 63) / 64 * 64);
     w.scr.qcount = c.take<uint32_t>(QCOUNTERS);
   } else if (pb->precision >= NENO6_BF16) {
     // 1D: the re-check runs inside the face pass; only its diagnostic counter
@@ -534,7 +529,6 @@ int32_t neno6_autotune(const neno6_problem *prob, const neno6_mlp *mlp, const vo
   if (int32_t c = begin_call(prob, mlp, w, stream)) return c;
   static const int waves[] = {2, 4, 8};
   static const int fixed_blocks[] = {512, 1024, 2048, 4096, 16384, 65536};
-  static const int rblocks[] = {128, 512, 2048};
   const bool is2d = prob->equation == NENO6_EULER2D;
   // workgroup caps of one, two and three full rounds of resident waves as
   // well (the fused kernel holds three waves per SIMD in 1D, twelve per
@@ -593,13 +587,10 @@ int32_t neno6_autotune(const neno6_problem *prob, const neno6_mlp *mlp, const vo
       if (!dup) blocks[nbl++] = nb;
     }
     for (int ib = 0; ib < nbl; ++ib)
-      for (int xcd = 0; xcd < 2 && rc == NENO6_OK; ++xcd)
-        for (int rb : rblocks) {
-          if (!is2d && rb != rblocks[0]) break;  // 1D: the re-check runs in the face pass
+      for (int xcd = 0; xcd < 2 && rc == NENO6_OK; ++xcd) {
           const int nb = blocks[ib];
           fa.face_waves = wv;
           fa.face_blocks = nb;
-          fa.recheck_blocks = rb;
           fa.xcd_order = xcd;
           float ms = 0.f;
           hipError_t e = pass();
@@ -617,7 +608,6 @@ int32_t neno6_autotune(const neno6_problem *prob, const neno6_mlp *mlp, const vo
             best_t = ms;
             bt.face_waves = wv;
             bt.face_blocks = nb;
-            bt.recheck_blocks = rb;
             bt.xcd_order = xcd;
           }
         }
@@ -639,7 +629,7 @@ int32_t neno6_step(const neno6_problem *prob, const neno6_mlp *mlp, void *q, dou
   if (!q || !t || !status || !ws || n_steps < 0 || !(cfl > 0)) return NENO6_BAD_ARG;
   const Work w = carve_work(prob, ws);
   if (ws_bytes < w.bytes) return NENO6_WORKSPACE_SMALL;
-  // 1D steps maintain no counters (the re-check runs inside the face pass)
+  // steps maintain no re-check counters (the 2D time step clears them)
   if (int32_t c = begin_call(prob, mlp, w, stream, prob->equation == NENO6_EULER2D)) return c;
   const bool f64 = prob->precision == NENO6_FP64;
   for (int32_t it = 0; it < n_steps; ++it) {

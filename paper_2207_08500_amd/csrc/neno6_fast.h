@@ -8,15 +8,9 @@ namespace n6 {
 
 // Scratch of the fast path, carved from the caller's workspace.
 struct FastScratch {
-  uint8_t *masks;       // [nvar][faces] (1D) or x|y masks (2D), when the caller passes none
-  uint32_t *queue;      // re-check entries: face * 8 + (field * 2 + sign), one list of
-                        // `faces` entries (of the line batch or the sweep) per
-                        // evaluation kind e at e * faces
-  uint8_t *qflag;       // per entry: label changed by the FP32 re-check
-  uint8_t *qnear;       // 2D: near-cutoff bits of each face of the sweep (bit e: kind
-                        // e), 64-byte padded; the compaction kernel builds the lists
-  uint32_t *qcount;     // [QCOUNTERS] entries queued: 1D kind e at e, 2D sweep d kind e
-                        // at 8 * d + e
+  uint8_t *masks;       // 2D: x|y masks when the caller passes none
+  uint32_t *qcount;     // [QCOUNTERS] evaluations re-checked in FP32 (diagnostic): 1D
+                        // spread over all slots, 2D sweep d over slots 8 d .. 8 d + 7
 };
 
 // What the fused 1D Euler pass writes (one mode per launch).

@@ -55,8 +55,8 @@ constexpr int TAB_BYTES = TAB_REGS * 64 * 4;
 constexpr int PREP_BF16_OFF = 16384;
 constexpr int PREP_F16_OFF = PREP_BF16_OFF + TAB_BYTES;
 constexpr int PREP_B5_OFF = PREP_F16_OFF + TAB_BYTES;
-constexpr int PREP_F32_OFF = 65536;  // FP32 operand table of the 2D re-check (F32_REGS)
-constexpr int PREP_F4_OFF = 98304;   // FP32 16x16x4 operand table of the 1D re-check (F4_REGS)
+constexpr int PREP_SCALE_OFF = 65536;  // per-neuron activation scales (FP64)
+constexpr int PREP_F4_OFF = 98304;     // FP32 16x16x4 operand table of the re-check (F4_REGS)
 constexpr size_t PREP_BYTES = 131072;
 static_assert(PREP_B5_OFF + 16 <= (int)PREP_BYTES, "prepared block layout");
 
@@ -560,6 +560,8 @@ N6_DEV void back_project(const float R[NV][NV], const float hs[NV], float Fo[NV]
   }
 }
 
+N6_DEV void mlp_f32_16(const float *tab, const float *b5, int lane, const float x[6], float z[4]);
+
 // ---- fused face kernel, 2D sweeps --------------------------------------------------
 // Faces of one 2D sweep.  One lane per face, 64 consecutive faces per wave
 // and iteration.  The split stencils and the face's five Roe values wait in
@@ -579,10 +581,16 @@ template <int PREC, int W, bool MLP>
 __global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(2)))
 k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared, float margin,
              const float *__restrict__ q, const uint8_t *__restrict__ min, float *__restrict__ Fh,
-             uint8_t *__restrict__ masks, uint8_t *__restrict__ nearm, int xcd) {
+             uint8_t *__restrict__ masks, u32 *__restrict__ nrecheck, int xcd) {
   constexpr int NV = 4, NE = 8, NR = 5;
   constexpr int NS = NE * 6 + NR;
   __shared__ float stash[W][NS][64];
+  // re-check list (lane << 3 | kind) and the FP32 labels (kind, lane)
+  __shared__ uint16_t relist[W][MLP ? NE * 64 : 1];
+  __shared__ uint8_t relab[W][MLP ? NE : 1][64];
+  const float *b5 = (const float *)((const char *)prepared + PREP_B5_OFF);
+  const float *f4tab = (const float *)((const char *)prepared + PREP_F4_OFF);
+  u32 nre = 0u;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t nf = dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1);
   const int64_t nchunk = (nf + 63) / 64;
@@ -594,16 +602,11 @@ k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared
     const int64_t f = ch * 64 + lane;
     const bool valid = f < nf;
     const int64_t fc = valid ? f : nf - 1;
-    u32 fx[NE][6];
     {
       float s[NE][6];
       Roe2 rw;
       setup2d(gd, dir, q, fc, s, rw);
       const float R[NR] = {rw.nt, rw.st, rw.ct, rw.Ht, rw.q2};
-      if constexpr (MLP) {
-#pragma unroll
-        for (int e = 0; e < NE; ++e) feature_pack<PREC>(s[e], fx[e]);
-      }
 #pragma unroll
       for (int e = 0; e < NE; ++e)
 #pragma unroll
@@ -616,11 +619,24 @@ k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared
     // chains are issued as soon as they are ready, and the other waves'
     // set-up and combine work fills the gaps
     if constexpr (MLP) __builtin_amdgcn_s_setprio(1);
+    // each evaluation's features are formed from its stashed stencil right
+    // before it is classified; the next stencil is read meanwhile
+    float sn[6];
+    if constexpr (MLP) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) sn[j] = stash[wv][j][lane];
+    }
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
       if constexpr (MLP) {
         __builtin_amdgcn_sched_barrier(0);
-        const u32 mk = classify_packed<PREC>(w, fx[e], margin, nullptr);
+        u32 xe[6];
+        feature_pack<PREC>(sn, xe);
+        if (e + 1 < NE) {
+#pragma unroll
+          for (int j = 0; j < 6; ++j) sn[j] = stash[wv][(e + 1) * 6 + j][lane];
+        }
+        const u32 mk = classify_packed<PREC>(w, xe, margin, nullptr);
         sel[e] = mk & 15u;
         near |= (mk >> 4) << e;
       } else if (selector == 1) {
@@ -639,7 +655,43 @@ k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (MLP) {
       __builtin_amdgcn_s_setprio(0);
-      if (valid) nearm[f] = (uint8_t)near;
+      // near-cutoff evaluations of the tile, re-evaluated in FP32 16 at a
+      // time; their FP32 labels replace the reduced-precision ones
+      const u32 want = valid ? near : 0u;
+      if (__ballot(want != 0u) != 0ull) {  // wave-uniform
+        const u32 c = (u32)__popc(want);
+        u32 inc = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const u32 tt = __shfl_up(inc, o);
+          inc += lane >= o ? tt : 0u;
+        }
+        const int nnear = (int)__shfl(inc, 63);
+        u32 pos = inc - c, m = want;
+        while (m) {
+          relist[wv][pos++] = (uint16_t)(((u32)lane << 3) | (u32)(__ffs(m) - 1));
+          m &= m - 1u;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const int jcol = lane & 15;
+        for (int b0 = 0; b0 < nnear; b0 += 16) {
+          const int i = b0 + jcol;
+          const bool ok = i < nnear;
+          const u32 ent = relist[wv][ok ? i : b0];
+          const int src = (int)(ent >> 3), e = (int)(ent & 7u);
+          float se[6], x[6], z[4];
+#pragma unroll
+          for (int j = 0; j < 6; ++j) se[j] = stash[wv][e * 6 + j][src];
+          features<float>(se, x);
+          mlp_f32_16(f4tab, b5, lane, x, z);
+          if (lane < 16 && ok) relab[wv][e][src] = (uint8_t)mask_from_logits<float>(z);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+        for (int e = 0; e < NE; ++e)
+          if ((want >> e) & 1u) sel[e] = relab[wv][e][lane];
+        nre += (u32)nnear;
+      }
     }
     float hs[NV], Fo[NV], R[NV][NV];
 #pragma unroll
@@ -663,355 +715,8 @@ k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared
       for (int m = 0; m < NV; ++m) masks[m * nf + f] = (uint8_t)(sel[2 * m] | (sel[2 * m + 1] << 4));
     }
   }
-}
-
-// ---- 2D re-check lists from the near-cutoff bits ----------------------------------
-// Each lane takes CMP_WPL consecutive 4-face words of nearm (64 bytes, one
-// 16-byte load at a time), counts its entries per kind, and a wave-wide
-// prefix sum per kind places them; the workgroup reserves its slots of each
-// kind with one atomic (the waves take consecutive parts); then every lane
-// writes its own entries (face * 8 + e into list e at queue[e * nf]).  The
-// whole grid reaches the barriers: waves past the end count nothing.  Every
-// face adds at most one entry per kind,
-// so no list exceeds nf.  nearm is padded to a multiple of 64 bytes; bytes
-// past face nf - 1 are masked.
-constexpr int CMP_WPL = 16;              // words per lane
-constexpr int CMP_WPW = 64 * CMP_WPL;    // words per wave
-
-__global__ void __launch_bounds__(TPB) k_compact_near(const uint8_t *__restrict__ nearm, int64_t nf,
-                                                      u32 *__restrict__ queue, u32 *__restrict__ qcount) {
-  const int lane = threadIdx.x & 63;
-  const int64_t nw = (nf + 3) / 4;
-  const int64_t wave = (blockIdx.x * (int64_t)TPB + threadIdx.x) >> 6;
-  const int64_t wb = wave * CMP_WPW + (int64_t)lane * CMP_WPL;  // words past nw read as 0
-  u32 v[CMP_WPL];
-#pragma unroll
-  for (int i = 0; i < CMP_WPL; i += 4) {
-    const uint4 x = wb + i < nw ? *(const uint4 *)(nearm + 4 * (wb + i)) : make_uint4(0u, 0u, 0u, 0u);
-    v[i] = x.x, v[i + 1] = x.y, v[i + 2] = x.z, v[i + 3] = x.w;
-  }
-#pragma unroll
-  for (int i = 0; i < CMP_WPL; ++i) {
-    const int64_t rem = nf - 4 * (wb + i);  // faces in word i
-    v[i] = rem <= 0 ? 0u : (rem < 4 ? v[i] & ((1u << (8 * rem)) - 1u) : v[i]);
-  }
-  u32 pos[8], mine = 0u;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    u32 c = 0u;
-#pragma unroll
-    for (int i = 0; i < CMP_WPL; ++i) c += (u32)__popc(v[i] & (0x01010101u << e));
-    u32 inc = c;  // inclusive prefix sum over the lanes
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const u32 t = __shfl_up(inc, o);
-      inc += lane >= o ? t : 0u;
-    }
-    pos[e] = inc - c;
-    const u32 tot = (u32)__shfl(inc, 63);
-    mine = lane == e ? tot : mine;
-  }
-  // one atomic per kind and workgroup; the waves take consecutive parts
-  __shared__ u32 wtot[WPB][8], bbase[8];
-  const int wv = threadIdx.x >> 6;
-  if (lane < 8) wtot[wv][lane] = mine;
-  __syncthreads();
-  if (threadIdx.x < 8) {
-    u32 t = 0u;
-#pragma unroll
-    for (int k = 0; k < WPB; ++k) t += wtot[k][threadIdx.x];
-    bbase[threadIdx.x] = t != 0u ? atomicAdd(qcount + threadIdx.x, t) : 0u;
-  }
-  __syncthreads();
-  u32 base = 0u;
-  if (lane < 8) {
-    base = bbase[lane];
-    for (int k = 0; k < wv; ++k) base += wtot[k][lane];
-  }
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    u32 p = pos[e] + (u32)__builtin_amdgcn_readlane((int)base, e);
-#pragma unroll
-    for (int i = 0; i < CMP_WPL; ++i) {
-      u32 m = v[i] & (0x01010101u << e);
-      while (m) {
-        const int k = (__ffs(m) - 1) >> 3;
-        if ((int64_t)p < nf) queue[(u32)e * (u32)nf + p] = (u32)((4 * (wb + i) + k) * 8 + e);
-        ++p;
-        m &= m - 1u;
-      }
-    }
-  }
-}
-
-// ---- FP32 re-check on MFMA ---------------------------------------------------
-// The re-check evaluates the classifier in FP32 with v_mfma_f32_32x32x2_f32
-// (FP32 products and accumulation): the same transposed, weight-stationary
-// tiling as the BF16 path with K = 2 per instruction, so the two K slots of
-// step t are the rows that lane halves h = 0, 1 hold in accumulator register
-// t and the activations never move; ReLU runs on the FP32 accumulators.  32
-// evaluations per wave (lanes j and j + 32 carry evaluation j).  Operand
-// table (k_prepare, register-major, one FP32 value per lane and register):
-//   A1 [8]   L1: tile tt = reg / 4 (neurons 32 tt + i), step t = reg % 4 (slots 2t + h;
-//            slot 6 is the folded bias, slot 7 zero)
-//   A2 [32]  L2: register t of the first (reg < 16) or second L1 tile
-//   A3 [16]  L3 (outputs padded to 32 rows), A4 [8] L4, A5 [4] L5
-//   B2, B3, B4 [16 each]  biases of L2..L4 in the accumulator layout
-// b5 is added to the logits afterwards (rows 0..3: registers 0..3 of lanes 0..31).
-constexpr int F32_A1 = 0, F32_A2 = 8, F32_A3 = 40, F32_A4 = 56, F32_A5 = 64, F32_B2 = 68,
-              F32_B3 = 84, F32_B4 = 100, F32_REGS = 116;
-
-static_assert(PREP_F32_OFF + F32_REGS * 64 * 4 <= (int)PREP_BYTES &&
-                  PREP_B5_OFF + 16 <= PREP_F32_OFF,
-              "prepared block layout");
-
-// Register `reg` of lane `lane` of the FP32 operand table.
-N6_DEV float f32_table_value(const double *__restrict__ P, int reg, int lane) {
-  const int i = lane % 32, h = lane / 32;
-  double x = 0.0;
-  if (reg < F32_A2) {  // L1
-    const int tt = reg / 4, k = 2 * (reg % 4) + h, o = 32 * tt + i;
-    x = k < 6 ? P[OW1 + o * 6 + k] : (k == 6 ? P[OB1 + o] : 0.0);
-  } else if (reg < F32_A3) {  // L2: inputs = L1 rows of accumulator register t
-    const int u = reg - F32_A2, tt = u / 16, t = u % 16;
-    x = P[OW2 + i * 64 + 32 * tt + 8 * (t / 4) + 4 * h + t % 4];
-  } else if (reg < F32_A4) {  // L3
-    const int t = reg - F32_A3;
-    x = i < 16 ? P[OW3 + i * 32 + 8 * (t / 4) + 4 * h + t % 4] : 0.0;
-  } else if (reg < F32_A5) {  // L4: the 16 L3 rows sit in registers 0..7
-    const int t = reg - F32_A4;
-    x = i < 8 ? P[OW4 + i * 16 + 8 * (t / 4) + 4 * h + t % 4] : 0.0;
-  } else if (reg < F32_B2) {  // L5: the 8 L4 rows sit in registers 0..3
-    const int t = reg - F32_A5;
-    x = i < 4 ? P[OW5 + i * 8 + 4 * h + t] : 0.0;
-  } else {  // C register r of lane (j, h) is row 8(r/4) + 4h + r%4
-    const int blk = (reg - F32_B2) / 16, r = (reg - F32_B2) % 16;
-    const int row = 8 * (r / 4) + 4 * h + r % 4;
-    if (blk == 0) x = P[OB2 + row];
-    else if (blk == 1) x = row < 16 ? P[OB3 + row] : 0.0;
-    else x = row < 8 ? P[OB4 + row] : 0.0;
-  }
-  return (float)x;
-}
-
-struct F32Wts {
-  float a[F32_B2];
-  f32x16 b2, b3, b4;
-  float b5[4];
-};
-
-N6_DEV void load_f32_wts(const void *prepared, int lane, F32Wts &w) {
-  const float *t = (const float *)((const char *)prepared + PREP_F32_OFF);
-#pragma unroll
-  for (int r = 0; r < F32_B2; ++r) w.a[r] = t[r * 64 + lane];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    w.b2[r] = t[(F32_B2 + r) * 64 + lane];
-    w.b3[r] = t[(F32_B3 + r) * 64 + lane];
-    w.b4[r] = t[(F32_B4 + r) * 64 + lane];
-  }
-  const float *b5 = (const float *)((const char *)prepared + PREP_B5_OFF);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) w.b5[k] = b5[k];
-}
-
-N6_DEV f32x16 mma32(float a, float b, f32x16 c) {
-  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
-}
-
-N6_DEV f32x16 relu16(f32x16 c) {
-#pragma unroll
-  for (int r = 0; r < 16; ++r) c[r] = fmaxf(c[r], 0.f);
-  return c;
-}
-
-// FP32 logits of the 32 evaluations of a wave: lane (j, h) holds the
-// features x of evaluation j; lanes 0..31 return its four logits.
-N6_DEV void mlp_f32_wave(const F32Wts &w, const float x[6], int h, float z[4]) {
-  const f32x16 zero = {};
-  f32x16 c1a = zero, c1b = zero;
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int k = 2 * t + h;  // lane-half dependent slot: features, bias 1, zero
-    float b = 0.f;
-#pragma unroll
-    for (int kk = 0; kk < 6; ++kk) b = k == kk ? x[kk] : b;
-    b = k == 6 ? 1.f : b;
-    c1a = mma32(w.a[F32_A1 + t], b, c1a);
-    c1b = mma32(w.a[F32_A1 + 4 + t], b, c1b);
-  }
-  c1a = relu16(c1a);
-  c1b = relu16(c1b);
-  // L2 in two accumulators (even / odd steps) to halve the dependent chain
-  f32x16 c2 = w.b2, c2o = zero;
-#pragma unroll
-  for (int t = 0; t < 16; t += 2) {
-    c2 = mma32(w.a[F32_A2 + t], c1a[t], c2);
-    c2o = mma32(w.a[F32_A2 + t + 1], c1a[t + 1], c2o);
-  }
-#pragma unroll
-  for (int t = 0; t < 16; t += 2) {
-    c2 = mma32(w.a[F32_A2 + 16 + t], c1b[t], c2);
-    c2o = mma32(w.a[F32_A2 + 16 + t + 1], c1b[t + 1], c2o);
-  }
-#pragma unroll
-  for (int r = 0; r < 16; ++r) c2[r] = fmaxf(c2[r] + c2o[r], 0.f);
-  f32x16 c3 = w.b3, c3o = zero;
-#pragma unroll
-  for (int t = 0; t < 16; t += 2) {
-    c3 = mma32(w.a[F32_A3 + t], c2[t], c3);
-    c3o = mma32(w.a[F32_A3 + t + 1], c2[t + 1], c3o);
-  }
-#pragma unroll
-  for (int r = 0; r < 8; ++r) c3[r] = fmaxf(c3[r] + c3o[r], 0.f);
-  f32x16 c4 = w.b4;
-#pragma unroll
-  for (int t = 0; t < 8; ++t) c4 = mma32(w.a[F32_A4 + t], c3[t], c4);
-#pragma unroll
-  for (int r = 0; r < 4; ++r) c4[r] = fmaxf(c4[r], 0.f);
-  f32x16 c5 = zero;
-#pragma unroll
-  for (int t = 0; t < 4; ++t) c5 = mma32(w.a[F32_A5 + t], c4[t], c5);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) z[k] = c5[k] + w.b5[k];
-}
-
-// Re-check entry slots: one list per evaluation kind (field x sign: six in
-// 1D, eight per 2D sweep), each padded to a whole number of waves' worth of
-// slots (EPW) and laid end to end, so the entries of one wave always share
-// the evaluation kind (and the stencil set-up the wave runs); slot i maps to
-// list e, position j, valid while j < count of e.
-constexpr int EPW = 32;  // re-check entries per wave
-
-template <int DIM> constexpr int n_kinds() { return DIM == 1 ? 6 : 8; }
-
-struct QueueSlots {
-  int64_t base[8], count[8], total;
-};
-
-template <int DIM>
-N6_DEV QueueSlots queue_slots(const u32 *__restrict__ qcount, int64_t nf) {
-  QueueSlots qs{};
-  int64_t b = 0;
-#pragma unroll
-  for (int e = 0; e < n_kinds<DIM>(); ++e) {
-    const int64_t c = (int64_t)qcount[e] < nf ? (int64_t)qcount[e] : nf;
-    qs.base[e] = b;
-    qs.count[e] = c;
-    b += (c + EPW - 1) / EPW * EPW;
-  }
-  qs.total = b;
-  return qs;
-}
-
-// Slot i -> (queue position, evaluation kind); false for a padding slot.
-template <int DIM>
-N6_DEV bool queue_slot(const QueueSlots &qs, int64_t i, int64_t nf, int64_t &pos, int &e) {
-  constexpr int NK = n_kinds<DIM>();
-  e = 0;
-#pragma unroll
-  for (int k = 1; k < NK; ++k) e += i >= qs.base[k] ? 1 : 0;
-  int64_t b = qs.base[0], c = qs.count[0];
-#pragma unroll
-  for (int k = 1; k < NK; ++k) {
-    b = e == k ? qs.base[k] : b;
-    c = e == k ? qs.count[k] : c;
-  }
-  const int64_t j = i - b;
-  pos = (int64_t)e * nf + j;
-  return j < c;
-}
-
-// Split stencil E of 2D face f of sweep dir: the full set-up with the other
-// fields' work left to dead-code elimination.
-template <int E>
-N6_DEV void stencil_one_2d(const Grid2D &gd, int dir, const float *__restrict__ q, int64_t f,
-                           float se[6]) {
-  float s[8][6], R[4][4];
-  setup2d(gd, dir, q, f, s, R);
-#pragma unroll
-  for (int j = 0; j < 6; ++j) se[j] = s[E][j];
-}
-
-// FP32 re-check of queued evaluations of a 2D sweep, 32 per wave on FP32
-// MFMA; flips the stored nibble where the FP32 label differs and flags the
-// entry.  The loop is uniform over the wave (the MFMA products need every
-// lane); slots past the end or in a list's padding compute face 0 and store
-// nothing.  The evaluation kind is uniform over the wave, so the wave forms
-// that one stencil.
-__global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2)))
-k_recheck2d(Grid2D gd, int dir, const void *__restrict__ prepared, const float *__restrict__ q,
-            uint8_t *__restrict__ masks, const u32 *__restrict__ queue,
-            const u32 *__restrict__ qcount, uint8_t *__restrict__ qflag) {
-  constexpr int EPB = WPB * EPW;  // slots per workgroup and pass
-  const int64_t nf = dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1);
-  const QueueSlots qs = queue_slots<2>(qcount, nf);
-  if (blockIdx.x * (int64_t)EPB >= qs.total) return;  // block-uniform: nothing queued for this block
-  const int lane = threadIdx.x & 63, j = lane & 31, h = lane >> 5;
-  F32Wts w;
-  load_f32_wts(prepared, lane, w);
-  for (int64_t i0 = blockIdx.x * (int64_t)EPB + (threadIdx.x >> 6) * EPW; i0 < qs.total;
-       i0 += (int64_t)gridDim.x * EPB) {
-    const int64_t i = i0 + j;
-    int64_t pos = 0;
-    int e = 0;
-    const bool ok = i < qs.total && queue_slot<2>(qs, i, nf, pos, e);
-    const u32 ent = ok ? queue[pos] : 0u;
-    const int64_t f = ent >> 3;
-    if (ok) e = ent & 7;
-    float se[6];
-    int ew;
-    int64_t iw;
-    queue_slot<2>(qs, i0, nf, iw, ew);  // the wave's kind (slot i0 < total)
-    switch (__builtin_amdgcn_readfirstlane(ew)) {  // only that stencil is formed
-    case 0: stencil_one_2d<0>(gd, dir, q, f, se); break;
-    case 1: stencil_one_2d<1>(gd, dir, q, f, se); break;
-    case 2: stencil_one_2d<2>(gd, dir, q, f, se); break;
-    case 3: stencil_one_2d<3>(gd, dir, q, f, se); break;
-    case 4: stencil_one_2d<4>(gd, dir, q, f, se); break;
-    case 5: stencil_one_2d<5>(gd, dir, q, f, se); break;
-    case 6: stencil_one_2d<6>(gd, dir, q, f, se); break;
-    default: stencil_one_2d<7>(gd, dir, q, f, se); break;
-    }
-    float x[6], z[4];
-    features<float>(se, x);
-    mlp_f32_wave(w, x, h, z);
-    if (h == 0 && ok) {
-      const u32 sel32 = mask_from_logits<float>(z);
-      const int64_t mi = (int64_t)(e >> 1) * nf + f;
-      const u32 shift = (u32)((mi & 3) * 8 + (e & 1) * 4);
-      u32 *word = (u32 *)(masks + (mi & ~(int64_t)3));
-      const u32 old = (masks[mi] >> ((e & 1) * 4)) & 15u;
-      const bool flip = old != sel32;
-      if (flip) atomicXor(word, (old ^ sel32) << shift);
-      qflag[pos] = flip ? 1 : 0;
-    }
-  }
-}
-
-// Recomputes the flux of every 2D face whose label the re-check changed.
-__global__ void __launch_bounds__(TPB)
-k_fixup2d(Grid2D gd, int dir, const float *__restrict__ q, const uint8_t *__restrict__ masks,
-          const u32 *__restrict__ queue, const u32 *__restrict__ qcount,
-          const uint8_t *__restrict__ qflag, float *__restrict__ Fh) {
-  const int64_t nf = dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1);
-  const QueueSlots qs = queue_slots<2>(qcount, nf);
-  for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < qs.total; i += (int64_t)gridDim.x * TPB) {
-    int64_t pos;
-    int e;
-    if (!queue_slot<2>(qs, i, nf, pos, e) || !qflag[pos]) continue;
-    const int64_t f = queue[pos] >> 3;
-    float s[8][6], R[4][4], hs[4], Fo[4];
-    setup2d(gd, dir, q, f, s, R);
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const u32 mb = masks[(int64_t)m * nf + f];
-      hs[m] = combine_pair(s[2 * m], mb & 15u, s[2 * m + 1], mb >> 4);
-    }
-    back_project<4>(R, hs, Fo);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) Fh[(int64_t)r * nf + f] = Fo[r];
-  }
+  // diagnostic count of re-checked evaluations, spread over eight counters
+  if (MLP && nrecheck && lane == 0 && nre) atomicAdd(nrecheck + ((blockIdx.x * W + wv) & 7), nre);
 }
 
 // ---- FP32 re-check in 16-evaluation passes (1D) --------------------------------------
@@ -1031,9 +736,7 @@ k_fixup2d(Grid2D gd, int dir, const float *__restrict__ q, const uint8_t *__rest
 // b5 is added to the logits (rows 0..3: registers 0..3 of lanes 0..15).
 constexpr int F4_A1 = 0, F4_A2 = 8, F4_A3 = 40, F4_A4 = 48, F4_A5 = 52, F4_B2 = 56, F4_B3 = 64,
               F4_B4 = 68, F4_REGS = 72;
-static_assert(PREP_F4_OFF + F4_REGS * 64 * 4 <= (int)PREP_BYTES &&
-                  PREP_F32_OFF + F32_REGS * 64 * 4 <= PREP_F4_OFF,
-              "prepared block layout");
+static_assert(PREP_F4_OFF + F4_REGS * 64 * 4 <= (int)PREP_BYTES, "prepared block layout");
 
 N6_DEV float f4_table_value(const double *__restrict__ P, int reg, int lane) {
   const int i = lane % 16, k = lane / 16;
@@ -1526,14 +1229,14 @@ hipError_t copy_bytes(const uint8_t *a, uint8_t *b, int64_t n, hipStream_t s) {
 }
 
 // Prepared block: FP32 copy of the parameters, the BF16 and FP16 per-lane
-// operand tables, b5 in FP32, the FP32 operand table of the re-check, and the
-// per-neuron scales of the hidden layers.
-constexpr int PREP_THREADS = (TAB_REGS > F32_REGS ? TAB_REGS : F32_REGS) * 64;
+// operand tables, b5 in FP32, the per-neuron scales of the hidden layers and
+// the FP32 operand table of the re-check.
+constexpr int PREP_THREADS = (TAB_REGS > F4_REGS ? TAB_REGS : F4_REGS) * 64;
 static_assert(NPARAM <= PREP_THREADS, "k_prepare covers every element");
 // Scales of hidden layers 1..4 (64 + 32 + 16 + 8 values, FP64).
 constexpr int SC1 = 0, SC2 = 64, SC3 = 96, SC4 = 112, NSCALE = 120;
-constexpr int PREP_SCALE_OFF = PREP_F32_OFF + F32_REGS * 64 * 4;
-static_assert(PREP_SCALE_OFF + NSCALE * 8 <= (int)PREP_BYTES, "prepared block layout");
+static_assert(PREP_B5_OFF + 16 <= PREP_SCALE_OFF && PREP_SCALE_OFF + NSCALE * 8 <= PREP_F4_OFF,
+              "prepared block layout");
 
 // A-priori activation scales (one workgroup of 64 threads).  With inputs
 // |x_i| <= 1 (eq. normalizainput) the pre-activation z_o of a first-layer
@@ -1586,7 +1289,6 @@ N6_DEV void prepare_entry(const double *__restrict__ P, const double *__restrict
                           char *__restrict__ prep, int t) {
   if (t < NPARAM) ((float *)prep)[t] = (float)P[t];
   if (t < 4) ((float *)(prep + PREP_B5_OFF))[t] = (float)P[OB5 + t];
-  if (t < F32_REGS * 64) ((float *)(prep + PREP_F32_OFF))[t] = f32_table_value(P, t / 64, t % 64);
   if (t < F4_REGS * 64) ((float *)(prep + PREP_F4_OFF))[t] = f4_table_value(P, t / 64, t % 64);
   if (t >= TAB_REGS * 64) return;
   auto sc = [&](int base, int i) { return S ? S[base + i] : 1.0; };
@@ -1659,11 +1361,9 @@ inline unsigned grid_for(int64_t items_per_wave_chunks) {
   return (unsigned)(blocks < 2048 ? (blocks > 0 ? blocks : 1) : 2048);
 }
 
-constexpr unsigned RECHECK_BLOCKS = 1024;
-
 // Launch shape of the fused face kernel and of the re-check pair.
 struct FaceLaunch {
-  unsigned grid, rgrid;
+  unsigned grid;
   int waves, xcd;
 };
 
@@ -1675,7 +1375,6 @@ FaceLaunch face_launch(const FastArgs &fa, int64_t nchunk) {
   const int64_t g = need < cap ? need : cap;
   L.grid = (unsigned)(g > 0 ? g : 1);
   L.xcd = (fa.xcd_order && L.grid % 8 == 0) ? 1 : 0;
-  L.rgrid = fa.recheck_blocks > 0 ? (unsigned)fa.recheck_blocks : RECHECK_BLOCKS;
   return L;
 }
 
@@ -2062,10 +1761,12 @@ hipError_t launch_faces2d_kernel(const FaceLaunch &L, const FastArgs &fa, hipStr
                                  float *F, uint8_t *m) {
 #define N6_FACES(P, W)                                                                        \
   hipLaunchKernelGGL((k_fast_faces<P, W, true>), dim3(L.grid), dim3(W * 64), 0, s, g, dir,     \
-                     fa.selector, fa.prepared, fa.margin, q, mi, F, m, fa.scr.qnear, L.xcd)
+                     fa.selector, fa.prepared, fa.margin, q, mi, F, m, nrc, L.xcd)
+  // re-check counters of this sweep (diagnostic), only while a margin is set
+  u32 *nrc = fa.margin > 0.f && fa.scr.qcount ? fa.scr.qcount + 8 * dir : nullptr;
   if (fa.selector != 0) {  // the other selectors: no classifier, one instantiation
     hipLaunchKernelGGL((k_fast_faces<2, 4, false>), dim3(L.grid), dim3(256), 0, s, g, dir,
-                       fa.selector, fa.prepared, fa.margin, q, mi, F, m, fa.scr.qnear, L.xcd);
+                       fa.selector, fa.prepared, fa.margin, q, mi, F, m, nullptr, L.xcd);
     return hipGetLastError();
   }
   if (fa.precision == 2) {
@@ -2131,7 +1832,7 @@ hipError_t launch_fast_faces2d(const Grid2D &g, const FastArgs &fa, const float 
                                const uint8_t *masks_in, uint8_t *masks_out, float *Fx, float *Gy,
                                hipStream_t s) {
   const int64_t nfx = (g.nx + 1) * g.ny, nfy = g.nx * (g.ny + 1);
-  uint8_t *masks = fa.scr.masks;  // whole words for the re-check atomics
+  uint8_t *masks = fa.scr.masks;  // both sweeps' labels (copied out if asked for)
   const bool recheck = fa.selector == 0 && fa.margin > 0.f;
   for (int dir = 0; dir < 2; ++dir) {
     const int64_t nf = dir == 0 ? nfx : nfy;
@@ -2142,17 +1843,6 @@ hipError_t launch_fast_faces2d(const Grid2D &g, const FastArgs &fa, const float 
     const FaceLaunch L = face_launch(fa, (nf + 63) / 64);
     hipError_t e = launch_faces2d_kernel(L, fa, s, g, dir, q, mi, Fd, md);
     if (e != hipSuccess) return e;
-    if (recheck) {
-      const int64_t cmp_waves = ((nf + 3) / 4 + CMP_WPW - 1) / CMP_WPW;
-      hipLaunchKernelGGL(k_compact_near, dim3((unsigned)((cmp_waves + WPB - 1) / WPB)), dim3(TPB), 0, s,
-                         fa.scr.qnear, nf, fa.scr.queue, qc);
-      hipLaunchKernelGGL(k_recheck2d, dim3(L.rgrid), dim3(TPB), 0, s, g, dir, fa.prepared, q, md,
-                         fa.scr.queue, qc, fa.scr.qflag);
-      hipLaunchKernelGGL(k_fixup2d, dim3(L.rgrid), dim3(TPB), 0, s, g, dir, q, md, fa.scr.queue, qc,
-                         fa.scr.qflag, Fd);
-      e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    }
   }
   if (masks_out) return copy_bytes(masks, masks_out, 4 * (nfx + nfy), s);
   return hipSuccess;
