@@ -51,6 +51,77 @@ def test_gradient_against_oracle(ctx, n, prec):
         assert cos > 0.98 and rel < 0.3
 
 
+def _bf(x):
+    """Round to BF16 (nearest even) through FP32, as the kernel rounds its
+    FP32 values; returned as float64."""
+    f = np.asarray(x, np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + np.uint64(0x7FFF) + ((u >> np.uint64(16)) & np.uint64(1))) >> np.uint64(16)) << np.uint64(16)
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _bf16_gradient_emulated(P, s, y):
+    """The BCE gradient with the BF16 training kernel's rounding points:
+    weights, features and hidden activations rounded to BF16 for the
+    forward products; the output deltas and every backward delta rounded to
+    BF16 before they enter a product; biases L2..L5 in FP32; all sums exact
+    (FP64).  Written from the kernel's description, independent of it."""
+    n = s.shape[0]
+    (W1, b1), (W2, b2), (W3, b3), (W4, b4), (W5, b5) = inputs.split_params(P)
+    s32 = s.astype(np.float32)
+    M = np.maximum(np.float32(1.0), np.abs(s32).max(axis=1, keepdims=True))
+    x = (s32 / M).astype(np.float64)
+    xh = _bf(x)
+    f32 = lambda v: np.asarray(v, np.float64).astype(np.float32).astype(np.float64)
+    z1 = xh @ _bf(W1).T + _bf(b1)
+    h1 = _bf(np.maximum(z1, 0.0))
+    z2 = h1 @ _bf(W2).T + f32(b2)
+    h2 = _bf(np.maximum(z2, 0.0))
+    z3 = h2 @ _bf(W3).T + f32(b3)
+    h3 = _bf(np.maximum(z3, 0.0))
+    z4 = h3 @ _bf(W4).T + f32(b4)
+    h4 = _bf(np.maximum(z4, 0.0))
+    z5 = h4 @ _bf(W5).T + f32(b5)
+    yk = ((y[:, None] >> np.arange(4)[None, :]) & 1).astype(np.float64)
+    d5 = (1.0 / (1.0 + np.exp(-z5)) - yk) * 0.25 / n
+    d4 = (_bf(d5) @ _bf(W5)) * (h4 > 0)
+    d3 = (_bf(d4) @ _bf(W4)) * (h3 > 0)
+    d2 = (_bf(d3) @ _bf(W3)) * (h2 > 0)
+    d1 = (_bf(d2) @ _bf(W2)) * (h1 > 0)
+    g = []
+    for d, a_in in ((d1, xh), (d2, h1), (d3, h2), (d4, h3), (d5, h4)):
+        g.append((_bf(d).T @ a_in).ravel())
+        g.append((_bf(d) if d is d1 else d).sum(axis=0))
+    return np.concatenate(g)
+
+
+@pytest.mark.parametrize("n", [64, 1000, 4097])
+def test_bf16_gradient_at_trained_weights(ctx, n):
+    """At the trained parameters the gradient is a sum of small residuals,
+    and BF16 rounding of the operands moves it far from the FP64 one (the
+    cosine is printed, not bounded: it is a property of BF16, the same for the
+    emulation below).  What the kernel must do is compute the gradient of its
+    BF16 arithmetic: against an emulation of its rounding points with exact
+    sums, it differs only through FP32 accumulation (and the rare activation
+    whose BF16 rounding that flips)."""
+    native, torch = ctx
+    P = trained_params()
+    s, y = inputs.classifier_samples(60 + n, n)
+    _, g_o = oracle.bce_grad(P, s, y)
+    g_e = _bf16_gradient_emulated(P, s, y)
+    g = torch.zeros(3228, dtype=torch.float64, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    native.neno6_classifier_grad(dev(P), dev(s, torch.float32), dev(y), 2, g, loss)
+    torch.cuda.synchronize()
+    g = host(g)
+    cos = lambda a, b: float(np.dot(a, b) / np.linalg.norm(a) / np.linalg.norm(b))
+    rel = np.abs(g - g_e).max() / np.abs(g_e).max()
+    print("n %d: kernel vs BF16 emulation max rel %.3g cosine %.6f; BF16 emulation vs FP64 "
+          "cosine %.4f; kernel vs FP64 cosine %.4f" % (n, rel, cos(g, g_e), cos(g_e, g_o),
+                                                        cos(g, g_o)))
+    assert cos(g, g_e) > 0.999999 and rel < 1e-4
+
+
 @pytest.mark.parametrize("prec", [1, 2])
 def test_training_run_against_oracle(ctx, prec):
     """Three epochs on 8192 samples (batch 512): the GPU run tracks the FP64
