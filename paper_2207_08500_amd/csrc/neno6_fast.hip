@@ -560,6 +560,8 @@ N6_DEV void back_project(const float R[NV][NV], const float hs[NV], float Fo[NV]
   }
 }
 
+constexpr int F4_A1 = 0, F4_A2 = 8, F4_A3 = 40, F4_A4 = 48, F4_A5 = 52, F4_B2 = 56, F4_B3 = 64,
+              F4_B4 = 68, F4_REGS = 72;
 N6_DEV void mlp_f32_16(const float *tab, const float *b5, int lane, const float x[6], float z[4]);
 
 // ---- fused face kernel, 2D sweeps --------------------------------------------------
@@ -588,8 +590,15 @@ k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared
   // re-check list (lane << 3 | kind) and the FP32 labels (kind, lane)
   __shared__ uint16_t relist[W][MLP ? NE * 64 : 1];
   __shared__ uint8_t relab[W][MLP ? NE : 1][64];
+  // the FP32 operand table of the re-check, staged once per workgroup
+  __shared__ float f4lds[MLP ? F4_REGS * 64 : 1];
   const float *b5 = (const float *)((const char *)prepared + PREP_B5_OFF);
-  const float *f4tab = (const float *)((const char *)prepared + PREP_F4_OFF);
+  if constexpr (MLP) {
+    const float *g4 = (const float *)((const char *)prepared + PREP_F4_OFF);
+    for (int i = threadIdx.x; i < F4_REGS * 64; i += W * 64) f4lds[i] = g4[i];
+    __syncthreads();
+  }
+  const float *f4tab = f4lds;
   u32 nre = 0u;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t nf = dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1);
@@ -734,8 +743,6 @@ k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared
 //            (L4 outputs padded to 16 rows, L5 to 16 rows and 16 inputs)
 //   B2 [8], B3 [4], B4 [4]: biases of L2..L4 in the accumulator layout
 // b5 is added to the logits (rows 0..3: registers 0..3 of lanes 0..15).
-constexpr int F4_A1 = 0, F4_A2 = 8, F4_A3 = 40, F4_A4 = 48, F4_A5 = 52, F4_B2 = 56, F4_B3 = 64,
-              F4_B4 = 68, F4_REGS = 72;
 static_assert(PREP_F4_OFF + F4_REGS * 64 * 4 <= (int)PREP_BYTES, "prepared block layout");
 
 N6_DEV float f4_table_value(const double *__restrict__ P, int reg, int lane) {
