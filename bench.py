@@ -15,7 +15,7 @@ Headline path: FP32 state, classifier layers on MFMA with FP16 operands and
 FP32 accumulation, re-check margin 2x the largest FP16 logit error observed
 on 2^20 training samples.  BF16 operands keep 8 significant bits against
 FP16's 11, so the same rule gives BF16 a margin about nine times wider (more
-evaluations go to the FP32 re-check) at the same MFMA rate; the BF16-MFMA
+evaluations go to the re-check) at the same MFMA rate; the BF16-MFMA
 path is measured beside it.  Also on the same GPU: the plain FP64 path; the
 labels of both reduced paths against the FP64 labels on the FP64 path's
 state after the timed steps (flip rate); the L1 / Linf distance of each
@@ -40,7 +40,7 @@ MARGINS_FILE = os.path.join(ROOT, "tests", "golden", "neno6_mlp_trained_margins.
 
 
 def _margins():
-    """FP32 re-check margins (logit units) of the committed weights: twice the
+    """Re-check margins (logit units) of the committed weights: twice the
     largest reduced-precision logit error observed on 2^20 classifier-training
     samples, keyed by precision code (2: BF16, 3: FP16)."""
     with open(MARGINS_FILE) as f:
@@ -434,8 +434,8 @@ def bench_1d(a, P, dev, name):
         "data": "synthetic",
         "config": {"workload": "%s; characteristic NENO6, LF splitting, SSP-RK3 CFL %.1f; FP32 "
                                "state, classifier on MFMA with FP16 operands and FP32 "
-                               "accumulation, FP32 re-check margin %.2f (BF16 operands: "
-                               "bf16_mfma, margin %.2f)" % (label, CFL, MARGIN[3], MARGIN[2]),
+                               "accumulation, two-part FP16 re-check margin %.2f (BF16 operands: "
+                               "bf16_mfma, FP32 re-check margin %.2f)" % (label, CFL, MARGIN[3], MARGIN[2]),
                    "faces_per_step": faces_step, "hip_graph": graphed,
                    "rk3_steps_per_graph_replay": per_h,
                    "launch_shapes": {"fp16": shapes_used.get(native.FP16),
@@ -444,7 +444,7 @@ def bench_1d(a, P, dev, name):
         # instruction-counter profile); the MFMA and HBM fractions follow
         "roofline": dict(_alu(faces_stage, k_ms), traffic=traffic,
                          traffic_launch_shape=trec.get("launch_shape") if trec else None,
-                         kernel="k_euler1d<FP16> (fused faces, FP32 re-check, flux difference; "
+                         kernel="k_euler1d<FP16> (fused faces, re-check, flux difference; "
                                 "right-hand-side output)", kernel_ms=k_ms,
                          kernel_ms_by_step={str(10 * i): v for i, v in enumerate(k_each)},
                          algorithmic_flop_per_launch=flop,
@@ -545,7 +545,7 @@ def bench_2d(a, P, dev):
         return m
 
     x = (labels(native.FP16, q32) ^ labels(native.FP64, q64_from32)).cpu().numpy()
-    # evaluations the FP32 re-check took on the initial state (both sweeps)
+    # evaluations the re-check took on the initial state (both sweeps)
     mlpm, probm, wsm = make(native.FP16)
     native.neno6_face_fluxes(probm, mlpm, q32, torch.zeros(4 * faces_stage, dtype=torch.float32,
                                                             device=dev), wsm)

@@ -88,7 +88,7 @@ extern "C" {
 /* Classifier handle.  `params` is the FP64 master block [dev]; `prepared` is a
  * device buffer of neno6_mlp_prepared_bytes() bytes that neno6_mlp_prepare()
  * fills with the reduced-precision copies the kernels read.  recheck_margin is
- * in logit units (BF16/FP16 modes); 0 disables the FP32 re-check. */
+ * in logit units (BF16/FP16 modes); 0 disables the re-check. */
 typedef struct neno6_mlp {
   const double *params;
   void *prepared;
@@ -170,8 +170,9 @@ int32_t neno6_mlp_prepare(const neno6_mlp *mlp, hipStream_t stream);
  * stencils s[n][6] [dev] (FP64 when precision = FP64, else FP32), scales each
  * by eq. normalizainput and writes the four output logits z[n][4] [dev]
  * (same float type) and the kept-candidate masks[n] [dev] (may be NULL).
- * In BF16/FP16 modes z holds the reduced-precision logits; masks include the
- * FP32 re-check. */
+ * In BF16/FP16 modes z holds the reduced-precision logits, except for the
+ * evaluations within the re-check margin, which hold the re-check's (BF16:
+ * FP32; FP16: the two-part FP16 passes); masks are the signs of z. */
 int32_t neno6_mlp_logits(const neno6_mlp *mlp, int32_t precision, const void *s, int64_t n,
                          void *z, uint8_t *masks, hipStream_t stream);
 
@@ -234,7 +235,7 @@ int32_t neno6_rhs_noalloc(const neno6_problem *prob, const neno6_mlp *mlp, const
  * ([var][faces] for 1D; x faces then y faces for 2D) and masks_out [dev, may
  * be NULL] the kept masks.  In BF16/FP16 modes this launches exactly the fused
  * classifier kernel (1D: the same kernel as neno6_rhs and neno6_step, writing
- * face fluxes instead of cells; the FP32 re-check is skipped when the margin
+ * face fluxes instead of cells; the re-check is skipped when the margin
  * is 0); it exists so that kernel can be timed on its own. */
 int32_t neno6_face_fluxes(const neno6_problem *prob, const neno6_mlp *mlp, const void *q, void *F,
                           uint8_t *masks_out, void *ws, size_t ws_bytes, hipStream_t stream);

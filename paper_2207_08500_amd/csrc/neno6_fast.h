@@ -9,7 +9,7 @@ namespace n6 {
 // Scratch of the fast path, carved from the caller's workspace.
 struct FastScratch {
   uint8_t *masks;       // 2D: x|y masks when the caller passes none
-  uint32_t *qcount;     // [QCOUNTERS] evaluations re-checked in FP32 (diagnostic): 1D
+  uint32_t *qcount;     // [QCOUNTERS] re-checked evaluations (diagnostic): 1D
                         // spread over all slots, 2D sweep d over slots 8 d .. 8 d + 7
 };
 
@@ -26,7 +26,7 @@ struct Out1D {
   const int32_t *frozen = nullptr;  // OUT_STAGE: [lines] nonzero = not advanced (dst = u0)
   int32_t *status = nullptr;        // OUT_RHS: [lines] NONPHYSICAL marks, may be null
   uint8_t *masks = nullptr;         // [3][faces] final labels, may be null
-  uint32_t *nrecheck = nullptr;     // evaluations re-checked in FP32 (diagnostic), may be null
+  uint32_t *nrecheck = nullptr;     // re-checked evaluations (diagnostic), may be null
 };
 
 struct FastArgs {
@@ -54,7 +54,7 @@ hipError_t launch_fast_reconstruct(const void *prepared, int precision, float ma
 // stage's flux-difference kernel clears them for the next stage).
 hipError_t launch_fast_reset(const FastArgs &fa, hipStream_t s);
 // 1D Euler: one fused pass per right-hand side -- set-up, MFMA classifier,
-// in-kernel FP32 re-check of near-cutoff evaluations, combine,
+// in-kernel re-check of near-cutoff evaluations, combine,
 // back-projection and the output of `out` (face fluxes, right-hand side or
 // RK3 stage).  Advection and Burgers: face fluxes only (out.mode ==
 // OUT_FACES; their flux difference is a separate kernel).

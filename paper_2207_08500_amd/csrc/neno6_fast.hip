@@ -9,13 +9,16 @@
 // holding rows {8b + 4h + r : b, r = 0..3} of column j; the next layer reads
 // its K slots from exactly those registers, so the K order of each weight
 // matrix is permuted at preparation time instead of moving activations.
-//   L1 6(+1 bias slot) -> 64 : 2 x v_mfma_f32_32x32x8   (K = 8)
+//   L1 6(+1 bias slot) -> 64 : 2 x v_mfma_f32_32x32x16 (K = 16: each feature
+//                              as its 16-bit value and the rounding remainder)
 //   L2 64 -> 32               : 4 x v_mfma_f32_32x32x16  (bias in the C input)
 //   L3 32 -> 16 (pad 32)      : 2 x v_mfma_f32_32x32x16
 //   L4 16 -> 8  (pad 32)      : 1 x v_mfma_f32_32x32x16
 //   L5 8 -> 4, both tiles     : 1 x v_mfma_f32_32x32x16, bias added in FP32
-// ReLU is applied to the packed 16-bit values with v_pk_max_i16 (a negative
-// BF16/FP16 has its sign bit set, i.e. is a negative int16).
+// The inference tables hold the network with every hidden neuron scaled by an
+// a-priori bound of its pre-activation, so the clamp of the packed conversion
+// to [0, 1] is the ReLU (the training forward uses plain weights, K = 8 in
+// L1, and a packed integer max as the ReLU).
 //
 // One lane computes one face (projection, split, features, combine).  The
 // L1 inputs of the two 32-column tiles of a wave are exchanged between lane
@@ -23,9 +26,11 @@
 // half of the K slots of L5, so the last product takes tile 0 in K slots
 // {0..3, 8..11} and tile 1 in {4..7, 12..15}, with tile 0's logits as rows
 // 0..3 and tile 1's as rows 4..7: every lane then holds its own stencil's
-// four logits in registers 0..3.  Evaluations whose smallest |logit| is below the
-// re-check margin are queued and re-evaluated in FP32 by a second kernel; a
-// third kernel recomputes the fluxes of faces whose label changed.
+// four logits in registers 0..3.  Evaluations whose smallest |logit| is below
+// the re-check margin are evaluated again inside the same kernel, before the
+// combine: with FP16 operands in two-part FP16 passes (mlp_split32), with
+// BF16 operands in FP32 (mlp_f32_16, or the vector units in the scalar
+// kernels).
 #include <algorithm>
 
 #include "neno6_device.h"
@@ -57,6 +62,7 @@ constexpr int PREP_F16_OFF = PREP_BF16_OFF + TAB_BYTES;
 constexpr int PREP_B5_OFF = PREP_F16_OFF + TAB_BYTES;
 constexpr int PREP_SCALE_OFF = 65536;  // per-neuron activation scales (FP64)
 constexpr int PREP_F4_OFF = 98304;     // FP32 16x16x4 operand table of the re-check (F4_REGS)
+constexpr int PREP_LO_OFF = 118784;    // FP16 remainder table of the two-part re-check (LO_REGS)
 constexpr size_t PREP_BYTES = 131072;
 static_assert(PREP_B5_OFF + 16 <= (int)PREP_BYTES, "prepared block layout");
 
@@ -251,12 +257,13 @@ N6_DEV u32x2 mlp_front(const Wts &w, u32x4 bin) {
 // The six features of one stencil as packed pairs: x[0..2] their values
 // rounded to the table precision, x[3..5] what that rounding left (so the
 // first layer sees each feature to about twice the precision's bits).
+// With `scale` (a power of two) the features times scale.
 template <int PREC>
-N6_DEV void feature_pack(const float s[6], u32 x[6]) {
+N6_DEV void feature_pack(const float s[6], u32 x[6], float scale = 1.f) {
   float M = 1.f;
 #pragma unroll
   for (int j = 0; j < 6; ++j) M = fmaxf(M, fabsf(s[j]));
-  const float r = __builtin_amdgcn_rcpf(M);
+  const float r = __builtin_amdgcn_rcpf(M) * scale;
 #pragma unroll
   for (int p = 0; p < 3; ++p) {
     const float a = s[2 * p] * r, b = s[2 * p + 1] * r;
@@ -323,11 +330,6 @@ N6_DEV const float *uniform_f32(const void *prepared) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
   const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
   return (const float *)(((uint64_t)hi << 32) | lo);
-}
-
-// FP32 re-evaluation on the vector units (the re-check).
-N6_DEV unsigned classify_f32(const void *prepared, const float s[6]) {
-  return classify<float>(uniform_f32(prepared), s);
 }
 
 // ---- per-face setup, FP32 -----------------------------------------------------
@@ -563,6 +565,20 @@ N6_DEV void back_project(const float R[NV][NV], const float hs[NV], float Fo[NV]
 constexpr int F4_A1 = 0, F4_A2 = 8, F4_A3 = 40, F4_A4 = 48, F4_A5 = 52, F4_B2 = 56, F4_B3 = 64,
               F4_B4 = 68, F4_REGS = 72;
 N6_DEV void mlp_f32_16(const float *tab, const float *b5, int lane, const float x[6], float z[4]);
+// Remainder table of the two-part FP16 re-check (registers of u32 pairs,
+// stored as [register / 4][lane][register % 4]).
+constexpr int LO_A1X = 0, LO_A2 = 8, LO_A3 = 24, LO_A4 = 32, LO_A5 = 36, LO_REGS = 40;
+constexpr float SPLIT_SCALE = 256.f;
+N6_DEV void mlp_split32(const Wts &w, const u32 *lotab, int lane, u32x4 bin, float z[4]);
+// First-layer input of a two-part pass for lane (j, h) from the stencil of
+// evaluation j: h = 0 the leading parts and the bias input, h = 1 the
+// trailing parts (features and bias input times SPLIT_SCALE).
+N6_DEV u32x4 split_input(const float s[6], int lane) {
+  u32 xe[6];
+  feature_pack<3>(s, xe, SPLIT_SCALE);
+  return (lane & 32) ? u32x4{xe[3], xe[4], xe[5], 0u}
+                     : u32x4{xe[0], xe[1], xe[2], pack2<3>(SPLIT_SCALE, 0.f)};
+}
 
 // ---- fused face kernel, 2D sweeps --------------------------------------------------
 // Faces of one 2D sweep.  One lane per face, 64 consecutive faces per wave
@@ -575,10 +591,10 @@ N6_DEV void mlp_f32_16(const float *tab, const float *b5, int lane, const float 
 // the hardware places on one XCD (every 8th) take a contiguous run of tiles
 // (the host only sets it when gridDim.x is a multiple of 8).  Two waves per
 // SIMD (at three, 47 spilled registers made it 30 % slower).  Near-cutoff
-// evaluations (a few percent in 2D) are marked per face in nearm; the
-// compaction kernel builds the re-check lists from the marks with a few
-// atomics per wave-range instead of one per tile (device-scope atomics cost
-// about 40 us per sweep here).
+// evaluations (a few percent in 2D) are listed per tile in LDS and evaluated
+// again before the combine: with FP16 operands in two-part FP16 passes of 32
+// (mlp_split32, remainder table in LDS), with BF16 operands in FP32 passes of
+// 16 (mlp_f32_16, its table in LDS).
 template <int PREC, int W, bool MLP>
 __global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(2)))
 k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared, float margin,
@@ -587,18 +603,20 @@ k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared
   constexpr int NV = 4, NE = 8, NR = 5;
   constexpr int NS = NE * 6 + NR;
   __shared__ float stash[W][NS][64];
-  // re-check list (lane << 3 | kind) and the FP32 labels (kind, lane)
+  // re-check list (lane << 3 | kind) and the re-checked labels (kind, lane)
   __shared__ uint16_t relist[W][MLP ? NE * 64 : 1];
   __shared__ uint8_t relab[W][MLP ? NE : 1][64];
-  // the FP32 operand table of the re-check, staged once per workgroup
-  __shared__ float f4lds[MLP ? F4_REGS * 64 : 1];
+  // the re-check's operand table (FP16: remainder table; BF16: FP32 table),
+  // staged once per workgroup
+  constexpr int TREGS = PREC == 3 ? LO_REGS : F4_REGS;
+  __shared__ u32 tlds[MLP ? TREGS * 64 : 1];
   const float *b5 = (const float *)((const char *)prepared + PREP_B5_OFF);
   if constexpr (MLP) {
-    const float *g4 = (const float *)((const char *)prepared + PREP_F4_OFF);
-    for (int i = threadIdx.x; i < F4_REGS * 64; i += W * 64) f4lds[i] = g4[i];
+    const u32 *g = (const u32 *)((const char *)prepared + (PREC == 3 ? PREP_LO_OFF : PREP_F4_OFF));
+    for (int i = threadIdx.x; i < TREGS * 64; i += W * 64) tlds[i] = g[i];
     __syncthreads();
   }
-  const float *f4tab = f4lds;
+  const float *f4tab = (const float *)tlds;
   u32 nre = 0u;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t nf = dir == 0 ? (gd.nx + 1) * gd.ny : gd.nx * (gd.ny + 1);
@@ -664,8 +682,9 @@ k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (MLP) {
       __builtin_amdgcn_s_setprio(0);
-      // near-cutoff evaluations of the tile, re-evaluated in FP32 16 at a
-      // time; their FP32 labels replace the reduced-precision ones
+      // near-cutoff evaluations of the tile, evaluated again (two-part FP16
+      // in passes of 32, or FP32 in passes of 16); their labels replace the
+      // reduced-precision ones
       const u32 want = valid ? near : 0u;
       if (__ballot(want != 0u) != 0ull) {  // wave-uniform
         const u32 c = (u32)__popc(want);
@@ -682,18 +701,33 @@ k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared
           m &= m - 1u;
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        const int jcol = lane & 15;
-        for (int b0 = 0; b0 < nnear; b0 += 16) {
-          const int i = b0 + jcol;
-          const bool ok = i < nnear;
-          const u32 ent = relist[wv][ok ? i : b0];
-          const int src = (int)(ent >> 3), e = (int)(ent & 7u);
-          float se[6], x[6], z[4];
+        if constexpr (PREC == 3) {
+          const int jcol = lane & 31;
+          for (int b0 = 0; b0 < nnear; b0 += 32) {
+            const int i = b0 + jcol;
+            const bool ok = i < nnear;
+            const u32 ent = relist[wv][ok ? i : b0];
+            const int src = (int)(ent >> 3), e = (int)(ent & 7u);
+            float se[6], z[4];
 #pragma unroll
-          for (int j = 0; j < 6; ++j) se[j] = stash[wv][e * 6 + j][src];
-          features<float>(se, x);
-          mlp_f32_16(f4tab, b5, lane, x, z);
-          if (lane < 16 && ok) relab[wv][e][src] = (uint8_t)mask_from_logits<float>(z);
+            for (int j = 0; j < 6; ++j) se[j] = stash[wv][e * 6 + j][src];
+            mlp_split32(w, tlds, lane, split_input(se, lane), z);
+            if (lane < 32 && ok) relab[wv][e][src] = (uint8_t)mask_from_logits<float>(z);
+          }
+        } else {
+          const int jcol = lane & 15;
+          for (int b0 = 0; b0 < nnear; b0 += 16) {
+            const int i = b0 + jcol;
+            const bool ok = i < nnear;
+            const u32 ent = relist[wv][ok ? i : b0];
+            const int src = (int)(ent >> 3), e = (int)(ent & 7u);
+            float se[6], x[6], z[4];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) se[j] = stash[wv][e * 6 + j][src];
+            features<float>(se, x);
+            mlp_f32_16(f4tab, b5, lane, x, z);
+            if (lane < 16 && ok) relab[wv][e][src] = (uint8_t)mask_from_logits<float>(z);
+          }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
@@ -728,7 +762,7 @@ k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared
   if (MLP && nrecheck && lane == 0 && nre) atomicAdd(nrecheck + ((blockIdx.x * W + wv) & 7), nre);
 }
 
-// ---- FP32 re-check in 16-evaluation passes (1D) --------------------------------------
+// ---- FP32 re-check in 16-evaluation passes (BF16 operands) ---------------------------
 // The classifier in FP32 on v_mfma_f32_16x16x4_f32 for up to 16 evaluations,
 // in the same transposed, weight-stationary tiling: lane l = (j, k) with
 // j = l % 16 (evaluation) and k = l / 16 provides K slot k of each step, and
@@ -743,7 +777,9 @@ k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared
 //            (L4 outputs padded to 16 rows, L5 to 16 rows and 16 inputs)
 //   B2 [8], B3 [4], B4 [4]: biases of L2..L4 in the accumulator layout
 // b5 is added to the logits (rows 0..3: registers 0..3 of lanes 0..15).
-static_assert(PREP_F4_OFF + F4_REGS * 64 * 4 <= (int)PREP_BYTES, "prepared block layout");
+static_assert(PREP_F4_OFF + F4_REGS * 64 * 4 <= PREP_LO_OFF &&
+                  PREP_LO_OFF + LO_REGS * 64 * 4 <= (int)PREP_BYTES,
+              "prepared block layout");
 
 N6_DEV float f4_table_value(const double *__restrict__ P, int reg, int lane) {
   const int i = lane % 16, k = lane / 16;
@@ -870,6 +906,99 @@ N6_DEV void mlp_f32_16(const float *tab, const float *b5, int lane, const float 
   for (int r = 0; r < 4; ++r) z[r] = c5[r] + b5[r];
 }
 
+// ---- two-part FP16 re-check in 32-evaluation passes -----------------------------------
+// Every operand in two FP16 parts, FP32 accumulation: weights as their FP16
+// value (the registers of the FP16 classifier) plus the FP16 rounding of what
+// that leaves (the remainder table), activations likewise, carried times
+// SPLIT_SCALE = 2^8 (features, the bias input and the biases of L2..L4 too;
+// the logits are scaled back): most scaled hidden activations are below 2^-3,
+// whose FP16 remainders would otherwise fall among the subnormals and lose
+// bits (the logit error is then about three times larger).  Each product
+// W a = W_hi a_hi + W_hi a_lo + W_lo a_hi drops only W_lo a_lo, so an operand
+// carries about 21 significant bits (FP32: 24) and the three terms are three
+// K steps of the FP16 MFMA on one accumulator: 27 instructions of
+// v_mfma_f32_32x32x16_f16 (32 cycles each) per 32 evaluations, against 56 of
+// v_mfma_f32_16x16x4_f32 (32 cycles each) per 16 in FP32.
+//
+// Split of an accumulator tile into packed leading and trailing parts:
+// ReLU, the FP16 rounding of the activation and the FP16 rounding of what is
+// left (hi[p], lo[p] from elements f + 2p, f + 2p + 1).
+template <int NPAIR>
+N6_DEV void split_tile(const f32x16 &c, int f, u32 *hi, u32 *lo) {
+#pragma unroll
+  for (int p = 0; p < NPAIR; ++p) {
+    const float a = fmaxf(c[f + 2 * p], 0.f), b = fmaxf(c[f + 2 * p + 1], 0.f);
+    hi[p] = pack2<3>(a, b);
+    const f32x2 h = unpack2<3>(hi[p]);
+    lo[p] = pack2<3>(a - h[0], b - h[1]);
+  }
+}
+
+// Logits of the 32 evaluations of a pass: lane (j, h) holds K slots 8h..8h+7
+// of evaluation j's first-layer input (h = 0: leading parts of the features
+// and the bias input 1; h = 1: their trailing parts), as in the FP16
+// classifier; lanes 0..31 return the four logits.  lotab: the remainder
+// table (in LDS).
+N6_DEV void mlp_split32(const Wts &w, const u32 *lotab, int lane, u32x4 bin, float z[4]) {
+  // the scale hidden from the optimiser: the scaled biases are formed in the
+  // pass, not hoisted out of the caller's tile loop (28 registers)
+  float S = SPLIT_SCALE;
+  asm volatile("" : "+v"(S));
+  // table loads through a hidden offset: issued in the pass, not hoisted
+  const u32x4 *lt = (const u32x4 *)lotab + (lane + opaque_zero());
+  const f32x16 zero = {};
+  f32x16 c1a = mma16<3>(w.a1x[0], bin, zero);
+  f32x16 c1b = mma16<3>(w.a1x[1], bin, zero);
+  c1a = mma16<3>(lt[(LO_A1X / 4) * 64], bin, c1a);
+  c1b = mma16<3>(lt[(LO_A1X / 4 + 1) * 64], bin, c1b);
+  u32 h1[16], l1[16];
+  split_tile<8>(c1a, 0, h1, l1);
+  split_tile<8>(c1b, 0, h1 + 8, l1 + 8);
+  f32x16 c2 = w.b2 * S;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const u32x4 H = {h1[4 * s], h1[4 * s + 1], h1[4 * s + 2], h1[4 * s + 3]};
+    const u32x4 L = {l1[4 * s], l1[4 * s + 1], l1[4 * s + 2], l1[4 * s + 3]};
+    c2 = mma16<3>(w.a2[s], H, c2);
+    c2 = mma16<3>(w.a2[s], L, c2);
+    c2 = mma16<3>(lt[(LO_A2 / 4 + s) * 64], H, c2);
+  }
+  u32 h2[8], l2[8];
+  split_tile<8>(c2, 0, h2, l2);
+  f32x16 c3 = w.b3;  // registers 8..15: padding rows (bias 0)
+#pragma unroll
+  for (int r = 0; r < 8; ++r) c3[r] *= S;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const u32x4 H = {h2[4 * s], h2[4 * s + 1], h2[4 * s + 2], h2[4 * s + 3]};
+    const u32x4 L = {l2[4 * s], l2[4 * s + 1], l2[4 * s + 2], l2[4 * s + 3]};
+    c3 = mma16<3>(w.a3[s], H, c3);
+    c3 = mma16<3>(w.a3[s], L, c3);
+    c3 = mma16<3>(lt[(LO_A3 / 4 + s) * 64], H, c3);
+  }
+  u32 h3[4], l3[4];
+  split_tile<4>(c3, 0, h3, l3);
+  f32x16 c4 = w.b4;  // registers 4..15: padding rows
+#pragma unroll
+  for (int r = 0; r < 4; ++r) c4[r] *= S;
+  {
+    const u32x4 H = {h3[0], h3[1], h3[2], h3[3]}, L = {l3[0], l3[1], l3[2], l3[3]};
+    c4 = mma16<3>(w.a4, H, c4);
+    c4 = mma16<3>(w.a4, L, c4);
+    c4 = mma16<3>(lt[(LO_A4 / 4) * 64], H, c4);
+  }
+  u32 h4[2], l4[2];
+  split_tile<2>(c4, 0, h4, l4);
+  // output layer: K slots 8h..8h+3 the leading parts of L4 rows 4h..4h+3,
+  // 8h+4..8h+7 their trailing parts; rows 0..3 of the FP16 table's product
+  // take the leading parts, the remainder table's rows 0..3 the cross terms
+  const u32x4 B5 = {h4[0], h4[1], l4[0], l4[1]};
+  f32x16 c5 = mma16<3>(w.a5, B5, zero);
+  c5 = mma16<3>(lt[(LO_A5 / 4) * 64], B5, c5);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) z[k] = c5[k] * (1.f / SPLIT_SCALE) + w.b5[k];
+}
+
 // ---- 1D Euler: one fused pass per right-hand side -------------------------------------
 // Tiles of 64 consecutive faces g = 63 t + lane of the batch, one wave each,
 // overlapping by one face (lane 63's face is lane 0 of the next tile).  Lane
@@ -881,12 +1010,11 @@ N6_DEV void mlp_f32_16(const float *tab, const float *b5, int lane, const float 
 // in both: its arithmetic does not depend on the lane it runs in.
 //
 // Near-cutoff evaluations (smallest |logit| below the margin) are evaluated
-// again in FP32 before the combine, in the tile itself: they are listed in
-// LDS, 16 per FP32 MFMA pass form their features from the stash, and the FP32
-// labels replace the reduced-precision ones.  A few tenths of a percent of
-// the evaluations are near, about one per tile, so a pass costs the tile
-// less than half of its MFMA work, on a pipe the tile keeps less than half
-// busy.
+// again before the combine, in the tile itself: they are listed in LDS, form
+// their features from the stash in passes of 32 (FP16 operands: two-part FP16,
+// remainder table read through the caches) or 16 (BF16 operands: FP32 MFMA),
+// and the re-check's labels replace the reduced-precision ones.  A few tenths
+// of a percent of the evaluations are near, about one per tile.
 
 // Output of cell kc of the line of fa, between fluxes Fl (left face) and Fr.
 N6_DEV void cell_out(const Line1D &ln, const Out1D &out, const Face1 &fa, int kc, const float qc[3],
@@ -933,7 +1061,7 @@ k_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float marg
   // state and pressure of the cell to the right, the line and the flat flag
   constexpr int NE = 6, S_ROE = NE * 6, S_QC = S_ROE + 4, S_LINE = S_QC + 4, NS = S_LINE + 1;
   __shared__ float stash[W][NS][64];
-  // re-check list (lane << 3 | kind) and the FP32 labels (kind, lane)
+  // re-check list (lane << 3 | kind) and the re-checked labels (kind, lane)
   __shared__ uint16_t relist[W][MLP ? NE * 64 : 1];
   __shared__ uint8_t relab[W][MLP ? NE : 1][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1033,18 +1161,34 @@ k_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float marg
           m &= m - 1u;
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        const int jcol = lane & 15;
-        for (int b0 = 0; b0 < nnear; b0 += 16) {
-          const int i = b0 + jcol;
-          const bool ok = i < nnear;
-          const u32 ent = relist[wv][ok ? i : b0];
-          const int src = (int)(ent >> 3), e = (int)(ent & 7u);
-          float se[6], x[6], z[4];
+        if constexpr (PREC == 3) {
+          const u32 *lot = (const u32 *)((const char *)prepared + PREP_LO_OFF);
+          const int jcol = lane & 31;
+          for (int b0 = 0; b0 < nnear; b0 += 32) {
+            const int i = b0 + jcol;
+            const bool ok = i < nnear;
+            const u32 ent = relist[wv][ok ? i : b0];
+            const int src = (int)(ent >> 3), e = (int)(ent & 7u);
+            float se[6], z[4];
 #pragma unroll
-          for (int j = 0; j < 6; ++j) se[j] = stash[wv][e * 6 + j][src];
-          features<float>(se, x);
-          mlp_f32_16(f4tab, b5, lane, x, z);
-          if (lane < 16 && ok) relab[wv][e][src] = (uint8_t)mask_from_logits<float>(z);
+            for (int j = 0; j < 6; ++j) se[j] = stash[wv][e * 6 + j][src];
+            mlp_split32(w, lot, lane, split_input(se, lane), z);
+            if (lane < 32 && ok) relab[wv][e][src] = (uint8_t)mask_from_logits<float>(z);
+          }
+        } else {
+          const int jcol = lane & 15;
+          for (int b0 = 0; b0 < nnear; b0 += 16) {
+            const int i = b0 + jcol;
+            const bool ok = i < nnear;
+            const u32 ent = relist[wv][ok ? i : b0];
+            const int src = (int)(ent >> 3), e = (int)(ent & 7u);
+            float se[6], x[6], z[4];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) se[j] = stash[wv][e * 6 + j][src];
+            features<float>(se, x);
+            mlp_f32_16(f4tab, b5, lane, x, z);
+            if (lane < 16 && ok) relab[wv][e][src] = (uint8_t)mask_from_logits<float>(z);
+          }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
@@ -1108,6 +1252,81 @@ k_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float marg
 // lane per stencil, re-check done in place (these are the small cases).
 // mode 0: stencils from f[k..k+5] (sign) ; mode 1: advection lines (ghosts);
 // mode 2: raw stencils sten[n][6] -> logits.
+// LDS of one wave for the re-check of the scalar kernels (FP16 operands).
+struct WaveRecheck {
+  float s[6][64];   // the wave's stencils
+  float z[4][64];   // re-check logits
+  uint8_t list[64];
+  uint8_t lab[64];
+};
+
+// MLP label of the stencil s of every lane of the wave (all 64 lanes call
+// it together): the BF16/FP16 classifier, then the re-check of evaluations
+// within the margin -- FP16 operands: two-part FP16 passes of 32 (lot: the
+// remainder table, in LDS); BF16: FP32 on the vector units.  With z, the
+// lane's logits (the re-check's where it ran).
+template <int PREC>
+N6_DEV u32 mlp_select(const Wts &w, const void *prepared, const u32 *lot, WaveRecheck &L,
+                      float margin, const float s[6], bool valid, float *z) {
+  float zl[4];
+  const u32 mk = classify_wave<PREC>(w, s, margin, zl);
+  const bool near = valid && (mk & 16u);
+  u32 sel = mk & 15u;
+  if constexpr (PREC == 3) {
+    const uint64_t bal = __ballot(near);
+    if (bal != 0ull) {  // wave-uniform
+      const int lane = threadIdx.x & 63;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) L.s[j][lane] = s[j];
+      const int nnear = __popcll(bal);
+      if (near) L.list[__builtin_amdgcn_mbcnt_hi((u32)(bal >> 32), __builtin_amdgcn_mbcnt_lo((u32)bal, 0u))] = (uint8_t)lane;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      for (int b0 = 0; b0 < nnear; b0 += 32) {
+        const int i = b0 + (lane & 31);
+        const bool ok = i < nnear;
+        const int src = L.list[ok ? i : b0];
+        float se[6], zz[4];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) se[j] = L.s[j][src];
+        mlp_split32(w, lot, lane, split_input(se, lane), zz);
+        if (lane < 32 && ok) {
+          L.lab[src] = (uint8_t)mask_from_logits<float>(zz);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) L.z[k][src] = zz[k];
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      if (near) {
+        sel = L.lab[lane];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) zl[k] = L.z[k][lane];
+      }
+    }
+  } else if (near) {
+    float x[6];
+    features<float>(s, x);
+    mlp_logits<float>(uniform_f32(prepared), x, zl);
+    sel = mask_from_logits<float>(zl);
+  }
+  if (z) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) z[k] = zl[k];
+  }
+  return sel;
+}
+
+// The re-check's LDS of a scalar kernel: the remainder table (FP16
+// operands), staged once per workgroup, and one WaveRecheck per wave.
+#define N6_SCALAR_RECHECK_LDS(PREC, selector, prepared)                                           \
+  __shared__ u32 lot[(PREC) == 3 ? LO_REGS * 64 : 1];                                            \
+  __shared__ WaveRecheck wrl[(PREC) == 3 ? WPB : 1];                                             \
+  if ((PREC) == 3 && (selector) == 0) {                                                          \
+    const u32 *g_ = (const u32 *)((const char *)(prepared) + PREP_LO_OFF);                       \
+    for (int i_ = threadIdx.x; i_ < LO_REGS * 64; i_ += TPB) lot[i_] = g_[i_];                   \
+    __syncthreads();                                                                             \
+  }                                                                                              \
+  WaveRecheck &wr = wrl[(PREC) == 3 ? (threadIdx.x >> 6) : 0];
+
 template <int PREC>
 __global__ void __launch_bounds__(TPB)
 k_fast_scalar(int mode, Line1D ln, const void *__restrict__ prepared, float margin,
@@ -1116,6 +1335,7 @@ k_fast_scalar(int mode, Line1D ln, const void *__restrict__ prepared, float marg
               float *__restrict__ zout) {
   const int lane = threadIdx.x & 63;
   const int64_t nchunk = (n + 63) / 64;
+  N6_SCALAR_RECHECK_LDS(PREC, selector, prepared)
   Wts w;
   if (selector == 0) load_wts<PREC>(prepared, lane, w);
   for (int64_t ch = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6); ch < nchunk;
@@ -1139,9 +1359,7 @@ k_fast_scalar(int mode, Line1D ln, const void *__restrict__ prepared, float marg
     u32 sel;
     float z[4];
     if (selector == 0) {
-      const u32 mk = classify_wave<PREC>(w, s, margin, mode == 2 ? z : nullptr);
-      sel = mk & 15u;
-      if (valid && (mk & 16u)) sel = classify_f32(prepared, s);
+      sel = mlp_select<PREC>(w, prepared, lot, wr, margin, s, valid, mode == 2 ? z : nullptr);
     } else if (selector == 1) {
       sel = 15u;
     } else if (selector == 2) {
@@ -1165,12 +1383,9 @@ k_fast_scalar(int mode, Line1D ln, const void *__restrict__ prepared, float marg
 // Label of one scalar stencil by the selector; the MFMA classification is a
 // wave-wide operation, so every lane of the wave calls this together.
 template <int PREC>
-N6_DEV u32 scalar_select(const Wts &w, int selector, const void *prepared, float margin,
-                         const float s[6], bool valid, u32 mask_in) {
-  if (selector == 0) {
-    const u32 mk = classify_wave<PREC>(w, s, margin, nullptr);
-    return (valid && (mk & 16u)) ? classify_f32(prepared, s) : (mk & 15u);
-  }
+N6_DEV u32 scalar_select(const Wts &w, int selector, const void *prepared, const u32 *lot,
+                         WaveRecheck &wr, float margin, const float s[6], bool valid, u32 mask_in) {
+  if (selector == 0) return mlp_select<PREC>(w, prepared, lot, wr, margin, s, valid, nullptr);
   if (selector == 1) return 15u;
   if (selector == 2) return 0u;
   if (selector == 4) return teno_mask_of<float>(s);
@@ -1179,8 +1394,8 @@ N6_DEV u32 scalar_select(const Wts &w, int selector, const void *prepared, float
 
 // Burgers faces (Sec. 4.3): one lane per face; f = u^2/2, Rusanov speed
 // alpha = max |u| over the six cells, f+- = (f +- alpha u)/2 ('-' mirrored);
-// both split stencils classified (FP32 re-check in place), face flux = sum of
-// the two reconstructions.
+// both split stencils classified (re-check in place), face flux = sum of the
+// two reconstructions.
 template <int PREC>
 __global__ void __launch_bounds__(TPB)
 k_fast_burgers(Line1D ln, const void *__restrict__ prepared, float margin, int selector,
@@ -1188,6 +1403,7 @@ k_fast_burgers(Line1D ln, const void *__restrict__ prepared, float margin, int s
                float *__restrict__ Fh, uint8_t *__restrict__ mout) {
   const int lane = threadIdx.x & 63;
   const int64_t nf = ln.faces(), nchunk = (nf + 63) / 64;
+  N6_SCALAR_RECHECK_LDS(PREC, selector, prepared)
   Wts w;
   if (selector == 0) load_wts<PREC>(prepared, lane, w);
   for (int64_t ch = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6); ch < nchunk;
@@ -1212,8 +1428,8 @@ k_fast_burgers(Line1D ln, const void *__restrict__ prepared, float margin, int s
       sm[5 - j] = 0.5f * (f - t);
     }
     const u32 mi = min ? min[gc] : 0u;
-    const u32 selp = scalar_select<PREC>(w, selector, prepared, margin, sp, valid, mi);
-    const u32 selm = scalar_select<PREC>(w, selector, prepared, margin, sm, valid, mi >> 4);
+    const u32 selp = scalar_select<PREC>(w, selector, prepared, lot, wr, margin, sp, valid, mi);
+    const u32 selm = scalar_select<PREC>(w, selector, prepared, lot, wr, margin, sm, valid, mi >> 4);
     if (!valid) continue;
     Fh[g] = combine_fast(sp, selp) + combine_fast(sm, selm);
     if (mout) mout[g] = (uint8_t)(selp | (selm << 4));
@@ -1236,8 +1452,8 @@ hipError_t copy_bytes(const uint8_t *a, uint8_t *b, int64_t n, hipStream_t s) {
 }
 
 // Prepared block: FP32 copy of the parameters, the BF16 and FP16 per-lane
-// operand tables, b5 in FP32, the per-neuron scales of the hidden layers and
-// the FP32 operand table of the re-check.
+// operand tables, b5 in FP32, the per-neuron scales of the hidden layers, the
+// FP32 operand table of the BF16 re-check and the FP16 remainder table.
 constexpr int PREP_THREADS = (TAB_REGS > F4_REGS ? TAB_REGS : F4_REGS) * 64;
 static_assert(NPARAM <= PREP_THREADS, "k_prepare covers every element");
 // Scales of hidden layers 1..4 (64 + 32 + 16 + 8 values, FP64).
@@ -1292,61 +1508,98 @@ __global__ void __launch_bounds__(64) k_prepare_scales(const double *__restrict_
 // weights are W_oi s_i / s_o (s_i = 1 for the six features), its bias b_o /
 // s_o, and the output layer's weights W5_ki s_i; without S (the training
 // tables) the plain weights.
+// FP64 value of element q2 (0, 1) of weight register reg (reg < 36 or reg >=
+// 84; the bias registers 36..83 excluded) of lane `lane` of the BF16/FP16
+// operand table, scaled by S (nullptr: unscaled).
+N6_DEV double tab_value(const double *__restrict__ P, const double *__restrict__ S, int reg, int lane,
+                        int q2) {
+  auto sc = [&](int base, int i) { return S ? S[base + i] : 1.0; };
+  const int i = lane % 32, h = lane / 32;
+  if (reg >= 84) {
+    // L1 with K = 16: lanes (i, 0) slots 0..7 = W1 row o on the leading
+    // parts, b1 on the bias input; lanes (i, 1) slots 8..15 = W1 row o on the
+    // trailing parts
+    const int tt = (reg - 84) / 4, k = 2 * ((reg - 84) % 4) + q2, o = 32 * tt + i;
+    const double x = k < 6 ? P[OW1 + o * 6 + k] : (k == 6 && h == 0 ? P[OB1 + o] : 0.0);
+    return x / sc(SC1, o);
+  }
+  if (reg < 4) {  // L1: tile reg/2, elements e = 2*(reg%2) + q2, K slot 4h + e
+    const int tt = reg / 2, e = 2 * (reg % 2) + q2, kk = 4 * h + e, o = 32 * tt + i;
+    const double x = kk < 6 ? P[OW1 + o * 6 + kk] : (kk == 6 ? P[OB1 + o] : 0.0);
+    return x / sc(SC1, o);
+  }
+  if (reg < 20) {  // L2 step s
+    const int s = (reg - 4) / 4, e = 2 * ((reg - 4) % 4) + q2;
+    const int n1 = 32 * (s / 2) + 16 * (s % 2) + 8 * (e / 4) + 4 * h + e % 4;
+    return P[OW2 + i * 64 + n1] * sc(SC1, n1) / sc(SC2, i);
+  }
+  if (reg < 28) {  // L3 step s
+    const int s = (reg - 20) / 4, e = 2 * ((reg - 20) % 4) + q2;
+    const int n2 = 8 * (2 * s + e / 4) + 4 * h + e % 4;
+    return i < 16 ? P[OW3 + i * 32 + n2] * sc(SC2, n2) / sc(SC3, i) : 0.0;
+  }
+  if (reg < 32) {  // L4
+    const int e = 2 * (reg - 28) + q2;
+    const int n3 = 8 * (e / 4) + 4 * h + e % 4;
+    return i < 8 ? P[OW4 + i * 16 + n3] * sc(SC3, n3) / sc(SC4, i) : 0.0;
+  }
+  // L5: K slots e < 4 carry tile 0 (rows 0..3), e >= 4 tile 1 (rows 4..7)
+  const int e = 2 * (reg - 32) + q2, t5 = e / 4, n4 = 4 * h + e % 4;
+  return i / 4 == t5 ? P[OW5 + (i % 4) * 8 + n4] * sc(SC4, n4) : 0.0;
+}
+
+// FP16 value of x and what that rounding leaves, rounded to FP16 again.
+N6_DEV f32x2 f16_parts(double x) {
+  const float hi = (float)(_Float16)(float)x;
+  return f32x2{hi, (float)(_Float16)(float)(x - (double)hi)};
+}
+
+// Register reg of lane `lane` of the remainder table (LO_* layout): the
+// FP16 remainders of the scaled weights, in the operand order of the FP16
+// table's register it pairs with; LO_A5 is the one-tile output layer (rows
+// 0..3: remainder weights on the leading parts, FP16 weights on the
+// remainders of the L4 activations).
+N6_DEV u32 lo_table_value(const double *__restrict__ P, const double *__restrict__ S, int reg,
+                          int lane) {
+  float v[2];
+  for (int q2 = 0; q2 < 2; ++q2) {
+    if (reg < LO_A5) {
+      const int m = reg < LO_A2 ? 84 + reg : (reg < LO_A3 ? 4 + reg - LO_A2 : (reg < LO_A4 ? 20 + reg - LO_A3 : 28 + reg - LO_A4));
+      v[q2] = f16_parts(tab_value(P, S, m, lane, q2))[1];
+    } else {
+      const int i = lane % 32, h = lane / 32, e = 2 * (reg - LO_A5) + q2, n4 = 4 * h + e % 4;
+      const f32x2 w = i < 4 ? f16_parts(P[OW5 + i * 8 + n4] * S[SC4 + n4]) : f32x2{0.f, 0.f};
+      v[q2] = e < 4 ? w[1] : w[0];
+    }
+  }
+  return pack2<3>(v[0], v[1]);
+}
+
+// Entry t of the prepared block (FP32 copy, FP32 and BF16/FP16 operand
+// tables).  With S (the scales above), the BF16/FP16 tables hold the scaled
+// network: hidden neuron o of layer l computes z_o / s_o, so its inputs'
+// weights are W_oi s_i / s_o (s_i = 1 for the six features), its bias b_o /
+// s_o, and the output layer's weights W5_ki s_i; without S (the training
+// tables) the plain weights and no remainder table.
 N6_DEV void prepare_entry(const double *__restrict__ P, const double *__restrict__ S,
                           char *__restrict__ prep, int t) {
   if (t < NPARAM) ((float *)prep)[t] = (float)P[t];
   if (t < 4) ((float *)(prep + PREP_B5_OFF))[t] = (float)P[OB5 + t];
   if (t < F4_REGS * 64) ((float *)(prep + PREP_F4_OFF))[t] = f4_table_value(P, t / 64, t % 64);
-  if (t >= TAB_REGS * 64) return;
-  auto sc = [&](int base, int i) { return S ? S[base + i] : 1.0; };
-  const int reg = t / 64, lane = t % 64, i = lane % 32, h = lane / 32;
-  float v[2];
-  bool is_bias = false;
-  for (int q2 = 0; q2 < 2; ++q2) {
-    double x = 0.0;
-    if (reg < 4) {  // L1: tile reg/2, elements e = 2*(reg%2) + q2, K slot 4h + e
-      const int tt = reg / 2, e = 2 * (reg % 2) + q2, kk = 4 * h + e, o = 32 * tt + i;
-      x = kk < 6 ? P[OW1 + o * 6 + kk] : (kk == 6 ? P[OB1 + o] : 0.0);
-      x /= sc(SC1, o);
-    } else if (reg < 20) {  // L2 step s
-      const int s = (reg - 4) / 4, e = 2 * ((reg - 4) % 4) + q2;
-      const int n1 = 32 * (s / 2) + 16 * (s % 2) + 8 * (e / 4) + 4 * h + e % 4;
-      x = P[OW2 + i * 64 + n1] * sc(SC1, n1) / sc(SC2, i);
-    } else if (reg < 28) {  // L3 step s
-      const int s = (reg - 20) / 4, e = 2 * ((reg - 20) % 4) + q2;
-      const int n2 = 8 * (2 * s + e / 4) + 4 * h + e % 4;
-      x = i < 16 ? P[OW3 + i * 32 + n2] * sc(SC2, n2) / sc(SC3, i) : 0.0;
-    } else if (reg < 32) {  // L4
-      const int e = 2 * (reg - 28) + q2;
-      const int n3 = 8 * (e / 4) + 4 * h + e % 4;
-      x = i < 8 ? P[OW4 + i * 16 + n3] * sc(SC3, n3) / sc(SC4, i) : 0.0;
-    } else if (reg < 36) {  // L5: K slots e < 4 carry tile 0 (rows 0..3), e >= 4 tile 1 (rows 4..7)
-      const int e = 2 * (reg - 32) + q2, t5 = e / 4, n4 = 4 * h + e % 4;
-      x = i / 4 == t5 ? P[OW5 + (i % 4) * 8 + n4] * sc(SC4, n4) : 0.0;
-    } else {
-      is_bias = true;
-    }
-    v[q2] = (float)x;
+  if (S && t < LO_REGS * 64) {
+    const int reg = t / 64, lane = t % 64;
+    ((u32 *)(prep + PREP_LO_OFF))[((reg / 4) * 64 + lane) * 4 + reg % 4] = lo_table_value(P, S, reg, lane);
   }
+  if (t >= TAB_REGS * 64) return;
+  const int reg = t / 64, lane = t % 64, h = lane / 32;
   u32 wb, wh;
-  if (reg >= 84) {
-    // L1 with K = 16: lanes (i, 0) slots 0..7 = W1 row o on the leading
-    // parts, b1 on the bias input; lanes (i, 1) slots 8..15 = W1 row o on the
-    // trailing parts
-    const int tt = (reg - 84) / 4, word = (reg - 84) % 4, o = 32 * tt + i;
-    float v2[2];
-    for (int q = 0; q < 2; ++q) {
-      const int k = 2 * word + q;
-      double x = k < 6 ? P[OW1 + o * 6 + k] : (k == 6 && h == 0 ? P[OB1 + o] : 0.0);
-      v2[q] = (float)(x / sc(SC1, o));
-    }
-    wb = pack2<2>(v2[0], v2[1]);
-    wh = pack2<3>(v2[0], v2[1]);
-  } else if (!is_bias) {
-    wb = pack2<2>(v[0], v[1]);
-    wh = pack2<3>(v[0], v[1]);
+  if (reg < 36 || reg >= 84) {
+    const float v0 = (float)tab_value(P, S, reg, lane, 0), v1 = (float)tab_value(P, S, reg, lane, 1);
+    wb = pack2<2>(v0, v1);
+    wh = pack2<3>(v0, v1);
   } else {
     // bias tuples: C register r of lane (j, h) is row 8(r/4) + 4h + r%4
+    auto sc = [&](int base, int i) { return S ? S[base + i] : 1.0; };
     const int blk = (reg - 36) / 16, r = (reg - 36) % 16;
     const int row = 8 * (r / 4) + 4 * h + r % 4;
     double x;

@@ -317,7 +317,7 @@ def neno6_face_fluxes(prob: Problem, mlp: Mlp | None, q: torch.Tensor, F: torch.
 
 
 def neno6_recheck_count(prob: Problem, mlp: Mlp, ws: torch.Tensor, stream=None):
-    """Evaluations re-checked in FP32 by the last neno6_face_fluxes call with
+    """Evaluations re-checked by the last neno6_face_fluxes call with
     this mlp (x, y); (0, 0) when its margin is 0."""
     cnt = (C.c_uint32 * 2)()
     ps = prob.struct()

@@ -11,7 +11,7 @@ plain device copy of known size that calibrates the memory counters.
 Workloads (--workload): c4, 4096 independent 1D Euler Riemann problems with N
 log-uniform in [256, 16384] (default); c2, 256 problems of 4000 cells.  FP32
 state, FP16/BF16 classifier.  Without --steps: the right-hand-side pass as it
-runs inside a step (the fused face kernel with the FP32 re-check at the
+runs inside a step (the fused face kernel with the re-check at the
 stated margins and the flux difference, face map kept) --reps times in FP16
 and in BF16, the FP64 plain path once, then the copy.  With --tuned the
 launches take the shape the autotuner picks for the FP16 pass (as the benchmark does;
@@ -36,7 +36,7 @@ sys.path.insert(0, ROOT)
 from paper_2207_08500_amd import inputs, native  # noqa: E402
 
 def _margins():
-    """The stated FP32 re-check margins of the committed weights."""
+    """The stated re-check margins of the committed weights."""
     import json
     with open(os.path.join(ROOT, "tests", "golden", "neno6_mlp_trained_margins.json")) as f:
         m = json.load(f)["margin"]

@@ -1,5 +1,5 @@
 """The shipped 1D Euler pass in BF16 / FP16 (classifier on MFMA, in-kernel
-FP32 re-check, flux difference and RK3 stage in the same kernel) against the
+re-check, flux difference and RK3 stage in the same kernel) against the
 FP64 oracle, value by value (Alg. 2; eq. approximateEq; Sec. 4.4).
 
 Reduced-precision labels may legitimately differ from the FP64 labels where
@@ -101,7 +101,7 @@ def test_rhs_elementwise_against_oracle(ctx, prec, margin):
     print("prec %d margin %s: flip rate %.3g, re-checked %d of %d, cells with oracle labels "
           "%d of %d, max rel err of the imposed-label values %.3g" %
           (prec, margin, flips, n_re, 6 * nf, ok.sum(), ok.size, err.max()))
-    # FP32 labels (all re-checked) differ from FP64 only within FP32 round-off of the cutoff
+    # re-checked labels differ from FP64 only within the re-check's rounding of the cutoff
     assert flips < (2e-3 if margin == "stated" else 1e-3)
     assert ok.mean() > 0.97
     assert np.array_equal(r[:, ok].view(np.uint32), r_in[:, ok].view(np.uint32))

@@ -1,9 +1,9 @@
-"""The 2D sweep kernels as shipped (classifier on MFMA, FP32 re-check inside
-the tile, FP16 and BF16 operands) against the FP64 oracle, element by
+"""The 2D sweep kernels as shipped (classifier on MFMA, re-check inside the
+tile, FP16 and BF16 operands) against the FP64 oracle, element by
 element: on ragged grids whose 64-face tiles cross row ends, on the
 four-quadrant data with density waves and on a state the oracle advanced a
 few steps.  Labels: flip rate bound, and with every evaluation re-checked
-the FP32 labels.  Values: at every cell whose four faces carry the oracle's
+the re-checked labels.  Values: at every cell whose four faces carry the oracle's
 labels, the right-hand side equals the one computed with the oracle's labels
 imposed (same FP32 arithmetic after the labels) and lies within FP32
 rounding of the oracle's (Alg. 2, dimension by dimension as in Sec. 4.4)."""

@@ -1,8 +1,8 @@
-"""The FP32 re-check margins of the committed weights, re-derived on the GPU.
+"""The re-check margins of the committed weights, re-derived on the GPU.
 
 The classifier runs its layers on MFMA with BF16 or FP16 operands; an
-evaluation whose smallest |logit| is below the margin is re-evaluated in
-FP32.  The stated margin of each precision is twice the largest
+evaluation whose smallest |logit| is below the margin is evaluated again
+(BF16 operands: in FP32; FP16 operands: in two-part FP16).  The stated margin of each precision is twice the largest
 |z_reduced - z_fp64| over the four logits of 2^20 classifier-training
 samples (the samples of Sec. 3.2: half smooth, half step/kink), with the
 reduced logits taken at margin 0 from FP32-rounded stencils and the FP64

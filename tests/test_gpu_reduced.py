@@ -56,12 +56,44 @@ def test_logits_against_oracle(ctx, prec):
         # this distribution: these samples' errors stay within it
         assert err.max() < MARGIN[prec]
         # labels: an evaluation beyond the margin keeps the reduced-precision
-        # label, which must be the FP64 one; one within it takes the FP32
-        # re-check's label, which differs from FP64 only within FP32 rounding
-        # of the cutoff.  So every differing label has an FP64 logit at 0.
+        # label, which must be the FP64 one; one within it takes the
+        # re-check's label, which differs from FP64 only within the re-check's
+        # rounding of the cutoff.  So every differing label has an FP64 logit
+        # at 0.
         bad = m != want
         assert np.all(np.abs(z_o[bad]).min(axis=1) < 1e-3)
         assert flips < 1e-5
+
+
+@pytest.mark.parametrize("prec", [2, 3])
+def test_recheck_logits_against_oracle(ctx, prec):
+    """With every evaluation inside the margin the logits are the re-check's:
+    BF16 operands -> FP32 on the vector units, held to the FP32 mode's bound;
+    FP16 operands -> the two-part FP16 passes (weights and activations each
+    as an FP16 value plus the FP16 rounding of the remainder, FP32 sums),
+    whose operands carry 21-22 significant bits against FP32's 24: held to
+    eight times that bound.  The labels are the signs of these logits, and a
+    label differs from FP64 only for a logit within 1e-3 of the cutoff."""
+    native, torch, P = ctx
+    n = 1 << 16
+    s, _ = inputs.classifier_samples(20, n)
+    s32 = s.astype(np.float32).astype(np.float64)
+    _, z_o = oracle.mlp_logits(P, s32)
+    mlp = native.Mlp(dev(P), recheck_margin=1e30)
+    z = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
+    m = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    native.neno6_mlp_logits(mlp, prec, dev(s32, torch.float32), z, m)
+    torch.cuda.synchronize()
+    z, m = host(z).astype(np.float64), host(m)
+    err = np.abs(z - z_o)
+    scale = max(1.0, np.abs(z_o).max())
+    print("prec %d, every evaluation re-checked: max |dz| %.3g (%.3g of the largest logit), "
+          "median %.3g" % (prec, err.max(), err.max() / scale, np.median(err)))
+    assert np.array_equal(m, sum(((z[:, k] <= 0).astype(np.uint8) << k) for k in range(4)))
+    assert err.max() <= (1e-4 if prec == 2 else 8e-4) * scale
+    want = sum(((z_o[:, k] <= 0).astype(np.uint8) << k) for k in range(4))
+    bad = m != want
+    assert np.all(np.abs(z_o[bad]).min(axis=1) < 1e-3)
 
 
 @pytest.mark.parametrize("prec", [1, 2, 3])
@@ -145,8 +177,8 @@ def test_euler2d_rhs_against_oracle(ctx, prec):
 def test_euler2d_recheck_lists_complete(ctx, prec, nx, ny):
     """With a margin that every logit falls inside, the 2D re-check lists
     hold every evaluation of both sweeps (eight per face, ragged grids), and
-    the labels then come from the FP32 re-check: FP32-level flip rate
-    against the FP64 oracle.  Margin 0 queues nothing."""
+    the labels then come from the re-check (FP32 or two-part FP16): a flip
+    rate at the re-check's rounding level against the FP64 oracle.  Margin 0 queues nothing."""
     native, torch, P = ctx
     q = inputs.riemann2d(29, nx, ny)
     _, mx_o, my_o, _ = oracle.euler2d_rhs(q, 1 / nx, 1 / ny, 1.4, 1, P, oracle.SEL_MLP)
