@@ -196,21 +196,21 @@ def bench_1d(a, P, dev, name):
     q32 = torch.as_tensor(q0, dtype=torch.float32, device=dev).contiguous()
     q64_from32 = q32.double().contiguous()  # the same (FP32-rounded) state for both paths
 
-    def make(prec, margin=0.0):
-        mlp = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=margin)
+    def make(prec, margin=0.0, mode=native.RECHECK_FP32):
+        mlp = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=margin, recheck_mode=mode)
         prob = native.Problem(native.EULER1D, prec, native.SEL_MLP, native.TRANSMISSIVE, off, dx,
                               device=dev)
         return mlp, prob, prob.workspace(dev)
 
     shapes_used = {}
 
-    def run_steps(prec, q_init, steps, warmup, graph=True):
+    def run_steps(prec, q_init, steps, warmup, graph=True, mode=native.RECHECK_FP32):
         """steps RK3 steps from q_init after warmup untimed ones (ten per
         HIP-graph replay when both counts allow, else one)."""
         per = 10 if graph and steps % 10 == 0 and warmup % 10 == 0 else 1
-        mlp, prob, ws = make(prec, MARGIN.get(prec, 0.0))
+        mlp, prob, ws = make(prec, MARGIN.get(prec, 0.0), mode)
         if prec in (native.BF16, native.FP16):  # launch shapes from the autotuner (cached)
-            shapes_used[prec] = autotune.tuned(prob, mlp, q_init, ws)[0]
+            shapes_used[(prec, mode)] = autotune.tuned(prob, mlp, q_init, ws)[0]
         q = q_init.clone()
         t = torch.zeros(n_prob, dtype=torch.float64, device=dev)
         st = torch.zeros(n_prob, dtype=torch.int32, device=dev)
@@ -260,6 +260,10 @@ def bench_1d(a, P, dev, name):
     # ---- same GPU: BF16-MFMA and the plain FP64 path ------------------------------
     qb, tb, stb, ms_b, _, _ = run_steps(native.BF16, q32, a.steps, a.warmup, graph=not a.no_graph)
     bf16_rate = faces_step * a.steps / (ms_b / 1e3)
+    # FP16 operands with the optional two-part FP16 re-check
+    qx, tx, stx, ms_x, _, _ = run_steps(HEAD, q32, a.steps, a.warmup, graph=not a.no_graph,
+                                        mode=native.RECHECK_FP16X2)
+    x2_rate = faces_step * a.steps / (ms_x / 1e3)
     k64 = 2 if name == "c4" else max(2, a.steps // 4)
     _, _, _, ms_64, _, _ = run_steps(native.FP64, q64_from32, k64, 1, graph=not a.no_graph)
     fp64_rate = faces_step * k64 / (ms_64 / 1e3)
@@ -278,6 +282,7 @@ def bench_1d(a, P, dev, name):
 
     l1, linf, n_norm = errors(qh, sth)
     l1_b, linf_b, _ = errors(qb, stb)
+    l1_x, linf_x, _ = errors(qx, stx)
 
     # ---- labels on the evolved state: the FP64 path's state after the timed
     # steps, rounded to FP32, through the FP16 / BF16 pass (re-check on) and
@@ -285,8 +290,8 @@ def bench_1d(a, P, dev, name):
     q_ev32 = q64b.float().contiguous()
     q_ev64 = q_ev32.double().contiguous()
 
-    def labels(prec, q, margin):
-        mlp, prob, ws = make(prec, margin)
+    def labels(prec, q, margin, mode=native.RECHECK_FP32):
+        mlp, prob, ws = make(prec, margin, mode)
         r = torch.zeros_like(q)
         m = torch.zeros(prob.mask_count(), dtype=torch.uint8, device=dev)
         n_re = 0
@@ -303,6 +308,7 @@ def bench_1d(a, P, dev, name):
     mh16, re_h = labels(native.FP16, q_ev32, MARGIN[3])
     mh0, _ = labels(native.FP16, q_ev32, 0.0)
     mb16, re_b = labels(native.BF16, q_ev32, MARGIN[2])
+    mx16, _ = labels(native.FP16, q_ev32, MARGIN[3], native.RECHECK_FP16X2)
     mb0, _ = labels(native.BF16, q_ev32, 0.0)
 
     def flip(ma, mb):
@@ -319,6 +325,7 @@ def bench_1d(a, P, dev, name):
            "flip_rate_fp16_without_recheck": flip(mh0, m64),
            "flip_rate_bf16": flip(mb16, m64), "flip_rate_per_face_bf16": flip_faces(mb16, m64),
            "flip_rate_bf16_without_recheck": flip(mb0, m64),
+           "flip_rate_fp16_two_part_recheck": flip(mx16, m64),
            "recheck_margin": {"fp16": MARGIN[3], "bf16": MARGIN[2]},
            # the overlap face of two 64-face tiles is counted by both
            "recheck_fraction_fp16": re_h / float(n_evals),
@@ -329,7 +336,7 @@ def bench_1d(a, P, dev, name):
     # the classifier's work and the share of flat stencils change as the
     # solution evolves) --------------------------------------------------------------
     mlpk, probk, wsk = make(HEAD, MARGIN[HEAD])
-    probk.set_tuning(shapes_used.get(HEAD))  # the launch shape of the timed steps
+    probk.set_tuning(shapes_used.get((HEAD, native.RECHECK_FP32)))  # shape of the timed steps
     snaps = [q32.clone()]
     qs = q32.clone()
     ts = torch.zeros(n_prob, dtype=torch.float64, device=dev)
@@ -434,12 +441,13 @@ def bench_1d(a, P, dev, name):
         "data": "synthetic",
         "config": {"workload": "%s; characteristic NENO6, LF splitting, SSP-RK3 CFL %.1f; FP32 "
                                "state, classifier on MFMA with FP16 operands and FP32 "
-                               "accumulation, two-part FP16 re-check margin %.2f (BF16 operands: "
-                               "bf16_mfma, FP32 re-check margin %.2f)" % (label, CFL, MARGIN[3], MARGIN[2]),
+                               "accumulation, FP32 re-check margin %.2f (BF16 operands: "
+                               "bf16_mfma, margin %.2f; the optional two-part FP16 re-check: "
+                               "fp16_two_part_recheck)" % (label, CFL, MARGIN[3], MARGIN[2]),
                    "faces_per_step": faces_step, "hip_graph": graphed,
                    "rk3_steps_per_graph_replay": per_h,
-                   "launch_shapes": {"fp16": shapes_used.get(native.FP16),
-                                     "bf16": shapes_used.get(native.BF16)}},
+                   "launch_shapes": {"fp16": shapes_used.get((native.FP16, native.RECHECK_FP32)),
+                                     "bf16": shapes_used.get((native.BF16, native.RECHECK_FP32))}},
         # the binding resource of the fused kernel is VALU issue (the
         # instruction-counter profile); the MFMA and HBM fractions follow
         "roofline": dict(_alu(faces_stage, k_ms), traffic=traffic,
@@ -462,6 +470,11 @@ def bench_1d(a, P, dev, name):
         "bf16_mfma": {"value": bf16_rate, "unit": "faces/s", "ms_per_step": ms_b / a.steps,
                       "recheck_margin": MARGIN[2], "l1_rel_vs_fp64": l1_b,
                       "linf_rel_vs_fp64": linf_b, "speedup_vs_fp64": bf16_rate / fp64_rate},
+        "fp16_two_part_recheck": {"value": x2_rate, "unit": "faces/s",
+                                  "ms_per_step": ms_x / a.steps, "recheck_margin": MARGIN[3],
+                                  "flip_rate": lab["flip_rate_fp16_two_part_recheck"],
+                                  "l1_rel_vs_fp64": l1_x, "linf_rel_vs_fp64": linf_x,
+                                  "vs_fp32_recheck": x2_rate / value},
         "speedup_vs_fp64": value / fp64_rate,
         "labels": lab,
         "flip_rate": lab["flip_rate_fp16"],
@@ -489,8 +502,9 @@ def bench_2d(a, P, dev):
     q32 = torch.as_tensor(q0, dtype=torch.float32, device=dev).contiguous().reshape(-1)
     q64_from32 = q32.double().contiguous()
 
-    def make(prec):
-        mlp = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=MARGIN.get(prec, 0.0))
+    def make(prec, mode=native.RECHECK_FP32):
+        mlp = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=MARGIN.get(prec, 0.0),
+                         recheck_mode=mode)
         prob = native.Problem(native.EULER2D, prec, native.SEL_MLP, native.TRANSMISSIVE, nx=nx,
                               ny=ny, dx2d=1.0 / nx, dy2d=1.0 / ny, device=dev)
         return mlp, prob, prob.workspace(dev)
@@ -499,10 +513,10 @@ def bench_2d(a, P, dev):
     faces_step = 3 * faces_stage
     shapes = {}
 
-    def run(prec, q_init, steps, warmup):
-        mlp, prob, ws = make(prec)
-        if prec in (native.FP16, native.FP16):
-            shapes[prec] = autotune.tuned(prob, mlp, q_init, ws)[0]
+    def run(prec, q_init, steps, warmup, mode=native.RECHECK_FP32):
+        mlp, prob, ws = make(prec, mode)
+        if prec == native.FP16:
+            shapes[(prec, mode)] = autotune.tuned(prob, mlp, q_init, ws)[0]
         q = q_init.clone()
         t = torch.zeros(1, dtype=torch.float64, device=dev)
         st = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -533,31 +547,40 @@ def bench_2d(a, P, dev):
     k64 = max(2, a.steps // 4)
     _, _, _, ms_64 = run(native.FP64, q64_from32, k64, 1)
     fp64_rate = faces_step * k64 / (ms_64 / 1e3)
+    qx, _, stx, ms_x = run(native.FP16, q32, a.steps, a.warmup, native.RECHECK_FP16X2)
+    x2_rate = faces_step * a.steps / (ms_x / 1e3)
     q64b, t64b, st64b, _ = run(native.FP64, q64_from32, a.steps, 0)
-    dq = (qb.double() - q64b).abs().reshape(4, -1)
-    l1 = float((dq.mean(dim=1) / q64b.reshape(4, -1).abs().mean(dim=1)).max())
 
-    def labels(prec, q):
-        mlp, prob, ws = make(prec)
+    def l1_of(qa):
+        dq = (qa.double() - q64b).abs().reshape(4, -1)
+        return float((dq.mean(dim=1) / q64b.reshape(4, -1).abs().mean(dim=1)).max())
+
+    l1, l1_x = l1_of(qb), l1_of(qx)
+
+    def labels(prec, q, mode=native.RECHECK_FP32):
+        mlp, prob, ws = make(prec, mode)
         r = torch.zeros_like(q)
         m = torch.zeros(prob.mask_count(), dtype=torch.uint8, device=dev)
         native.neno6_rhs(prob, mlp, q, r, ws, masks_out=m)
         return m
 
-    x = (labels(native.FP16, q32) ^ labels(native.FP64, q64_from32)).cpu().numpy()
+    m64 = labels(native.FP64, q64_from32)
+    x = (labels(native.FP16, q32) ^ m64).cpu().numpy()
+    xx = (labels(native.FP16, q32, native.RECHECK_FP16X2) ^ m64).cpu().numpy()
     # evaluations the re-check took on the initial state (both sweeps)
     mlpm, probm, wsm = make(native.FP16)
     native.neno6_face_fluxes(probm, mlpm, q32, torch.zeros(4 * faces_stage, dtype=torch.float32,
                                                             device=dev), wsm)
     recheck_frac = sum(native.neno6_recheck_count(probm, mlpm, wsm)) / float(faces_stage * EVALS_PER_FACE_2D)
     flip = float(np.unpackbits(x.reshape(-1, 1), axis=1).sum() / (8.0 * x.size))
+    flip_x = float(np.unpackbits(xx.reshape(-1, 1), axis=1).sum() / (8.0 * xx.size))
     nfx = (nx + 1) * ny
     flip_face = float(np.concatenate([(x[:4 * nfx].reshape(4, -1) != 0).any(axis=0),
                                       (x[4 * nfx:].reshape(4, -1) != 0).any(axis=0)]).mean())
     # both sweeps of the fused face kernel alone (margin 0)
     mlp0 = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=0.0)
     _, prob0, ws0 = make(native.FP16)
-    prob0.set_tuning(shapes.get(native.FP16))
+    prob0.set_tuning(shapes.get((native.FP16, native.RECHECK_FP32)))
     F = torch.zeros(4 * faces_stage, dtype=torch.float32, device=dev)
     for _ in range(150):  # about 0.1 s: steady clocks
         native.neno6_face_fluxes(prob0, mlp0, q32, F, ws0)
@@ -586,10 +609,11 @@ def bench_2d(a, P, dev):
         "dtype": "fp16",
         "data": "synthetic",
         "config": {"workload": "2D Euler four-quadrant Riemann problem, %d x %d cells, transmissive, "
-                               "FP32 state, FP16-MFMA classifier, re-check margin %.2f, SSP-RK3 "
+                               "FP32 state, FP16-MFMA classifier, FP32 re-check margin %.2f (the "
+                               "optional two-part FP16 re-check: fp16_two_part_recheck), SSP-RK3 "
                                "CFL %.1f" % (nx, ny, MARGIN[3], CFL),
                    "faces_per_step": faces_step, "hip_graph": True,
-                   "launch_shapes": shapes.get(native.FP16)},
+                   "launch_shapes": shapes.get((native.FP16, native.RECHECK_FP32))},
         "roofline": dict(_alu(faces_stage, k_ms, VALU_OPS_PER_FACE_2D), traffic=None,
                          kernel="k_fast_faces<FP16, 2D Euler>, x and y sweeps", kernel_ms=k_ms,
                          algorithmic_flop_per_launch=flop),
@@ -597,6 +621,10 @@ def bench_2d(a, P, dev):
                           "unit": "TFLOP/s", "frac": achieved / PEAK_MFMA_16},
         "fp64_plain": {"value": fp64_rate, "unit": "faces/s", "ms_per_step": ms_64 / k64,
                        "steps": k64},
+        "fp16_two_part_recheck": {"value": x2_rate, "unit": "faces/s",
+                                  "ms_per_step": ms_x / a.steps, "flip_rate": flip_x,
+                                  "l1_rel_vs_fp64": l1_x, "vs_fp32_recheck": x2_rate / value,
+                                  "status": int(stx[0])},
         "speedup_vs_fp64": value / fp64_rate,
         "flip_rate": flip,
         "flip_rate_per_face": flip_face,

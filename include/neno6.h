@@ -85,15 +85,23 @@ extern "C" {
 
 #define NENO6_NPARAM 3228
 
+/* Re-check arithmetic (neno6_mlp.recheck_mode). */
+#define NENO6_RECHECK_FP32 0   /* evaluations within the margin again in FP32 (default) */
+#define NENO6_RECHECK_FP16X2 1 /* FP16 operands only: again on FP16 MFMA with every weight and
+                                  activation as two FP16 parts (value + rounding remainder), FP32
+                                  sums; logit error about 2.5x the FP32 re-check's.  BF16 operands
+                                  are re-checked in FP32 whatever the mode. */
+
 /* Classifier handle.  `params` is the FP64 master block [dev]; `prepared` is a
  * device buffer of neno6_mlp_prepared_bytes() bytes that neno6_mlp_prepare()
  * fills with the reduced-precision copies the kernels read.  recheck_margin is
- * in logit units (BF16/FP16 modes); 0 disables the re-check. */
+ * in logit units (BF16/FP16 modes); 0 disables the re-check.  recheck_mode:
+ * NENO6_RECHECK_FP32 or NENO6_RECHECK_FP16X2 (other values: NENO6_BAD_ARG). */
 typedef struct neno6_mlp {
   const double *params;
   void *prepared;
   float recheck_margin;
-  int32_t reserved;
+  int32_t recheck_mode;
 } neno6_mlp;
 
 /* Problem description (host struct; the pointers in it are [dev]).
@@ -171,8 +179,8 @@ int32_t neno6_mlp_prepare(const neno6_mlp *mlp, hipStream_t stream);
  * by eq. normalizainput and writes the four output logits z[n][4] [dev]
  * (same float type) and the kept-candidate masks[n] [dev] (may be NULL).
  * In BF16/FP16 modes z holds the reduced-precision logits, except for the
- * evaluations within the re-check margin, which hold the re-check's (BF16:
- * FP32; FP16: the two-part FP16 passes); masks are the signs of z. */
+ * evaluations within the re-check margin, which hold the re-check's (FP32, or
+ * two-part FP16 by recheck_mode); masks are the signs of z. */
 int32_t neno6_mlp_logits(const neno6_mlp *mlp, int32_t precision, const void *s, int64_t n,
                          void *z, uint8_t *masks, hipStream_t stream);
 

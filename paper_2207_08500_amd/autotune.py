@@ -27,12 +27,15 @@ def default_path() -> str:
     return os.path.join(base, "neno6_tuning.json")
 
 
-def cache_key(prob: native.Problem, device=None) -> str:
-    """Device name, equation, precision and the face count rounded to a
-    half-octave bucket (shapes tuned at one size serve nearby sizes)."""
+def cache_key(prob: native.Problem, device=None, mlp: native.Mlp | None = None) -> str:
+    """Device name, equation, precision (and the two-part FP16 re-check when
+    mlp selects it) and the face count rounded to a half-octave bucket
+    (shapes tuned at one size serve nearby sizes)."""
     name = torch.cuda.get_device_name(device)
     bucket = round(2.0 * math.log2(max(prob.n_faces, 1))) / 2.0
-    return "%s|eq%d|prec%d|faces~2^%.1f" % (name, prob.equation, prob.precision, bucket)
+    rc = ("|rc%d" % mlp.recheck_mode if mlp is not None and mlp.recheck_mode
+          and prob.precision == native.FP16 else "")
+    return "%s|eq%d|prec%d%s|faces~2^%.1f" % (name, prob.equation, prob.precision, rc, bucket)
 
 
 def _read(path: str) -> dict:
@@ -58,7 +61,7 @@ def tuned(prob: native.Problem, mlp: native.Mlp, q: torch.Tensor, ws: torch.Tens
     missing (or refresh).  Returns (shapes dict, ms per face pass or None if
     the shapes came from the cache)."""
     path = path or default_path()
-    key = cache_key(prob, q.device)
+    key = cache_key(prob, q.device, mlp)
     cache = _read(path)
     ent = cache.get(key)
     fields = [k for k, _ in native.TuningStruct._fields_]

@@ -37,7 +37,14 @@ int32_t check_mlp(const neno6_mlp *mlp, int32_t selector, int32_t precision) {
   if (selector != NENO6_SEL_MLP) return NENO6_OK;
   if (!mlp || !mlp->params) return NENO6_BAD_ARG;
   if (precision != NENO6_FP64 && !mlp->prepared) return NENO6_BAD_ARG;
+  if (mlp->recheck_mode != NENO6_RECHECK_FP32 && mlp->recheck_mode != NENO6_RECHECK_FP16X2)
+    return NENO6_BAD_ARG;
   return NENO6_OK;
+}
+
+// The two-part FP16 re-check applies to FP16 operands only.
+bool split_recheck(const neno6_mlp *mlp, int32_t precision) {
+  return mlp && precision == NENO6_FP16 && mlp->recheck_mode == NENO6_RECHECK_FP16X2;
 }
 
 int nvar_of(int32_t eq) { return eq <= NENO6_BURGERS ? 1 : (eq == NENO6_EULER1D ? 3 : 4); }
@@ -214,6 +221,7 @@ FastArgs fast_args(const neno6_problem *pb, const neno6_mlp *mlp, const Work &w)
   fa.selector = pb->selector;
   fa.prepared = mlp ? mlp->prepared : nullptr;
   fa.margin = mlp ? mlp->recheck_margin : 0.f;
+  fa.split = split_recheck(mlp, pb->precision);
   fa.scr = w.scr;
   if (const neno6_tuning *t = pb->tuning) {
     fa.face_waves = t->face_waves;
@@ -357,7 +365,8 @@ int32_t neno6_mlp_logits(const neno6_mlp *mlp, int32_t precision, const void *s,
     return hip_status(launch_mlp_logits<float>(prepared_f32(mlp), (const float *)s, n, (float *)z,
                                                masks, stream));
   default:
-    return hip_status(launch_fast_logits(mlp->prepared, precision, mlp->recheck_margin,
+    return hip_status(launch_fast_logits(mlp->prepared, precision, split_recheck(mlp, precision),
+                                         mlp->recheck_margin,
                                          (const float *)s, n, (float *)z, masks, stream));
   }
 }
@@ -382,6 +391,7 @@ int32_t neno6_reconstruct(const neno6_mlp *mlp, const void *f, int64_t n_faces, 
                                                 stream));
   default:
     return hip_status(launch_fast_reconstruct(mlp ? mlp->prepared : nullptr, precision,
+                                              split_recheck(mlp, precision),
                                               mlp ? mlp->recheck_margin : 0.f, (const float *)f,
                                               n_faces, sign, selector, masks_in, (float *)fhat,
                                               masks_out, stream));

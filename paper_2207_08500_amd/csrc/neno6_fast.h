@@ -33,6 +33,7 @@ struct FastArgs {
   int equation = 0, precision = 2, selector = 0;
   const void *prepared = nullptr;
   float margin = 0.f;
+  bool split = false;  // FP16 operands: two-part FP16 re-check instead of FP32
   FastScratch scr{};
   // launch shapes (0 = default): waves per workgroup of the fused kernel,
   // its workgroup cap, re-check / fix-up workgroups, XCD-contiguous order
@@ -44,9 +45,11 @@ size_t fast_prepared_bytes();
 const void *fast_prepared_f32(const void *prepared);
 hipError_t launch_fast_prepare(const double *P, void *prepared, hipStream_t s);
 
-hipError_t launch_fast_logits(const void *prepared, int precision, float margin, const float *sten,
-                              int64_t n, float *z, uint8_t *masks, hipStream_t s);
-hipError_t launch_fast_reconstruct(const void *prepared, int precision, float margin,
+// split: FP16 operands re-checked in two-part FP16 instead of FP32.
+hipError_t launch_fast_logits(const void *prepared, int precision, bool split, float margin,
+                              const float *sten, int64_t n, float *z, uint8_t *masks,
+                              hipStream_t s);
+hipError_t launch_fast_reconstruct(const void *prepared, int precision, bool split, float margin,
                                    const float *f, int64_t n_faces, int sign, int selector,
                                    const uint8_t *masks_in, float *fhat, uint8_t *masks_out,
                                    hipStream_t s);

@@ -28,9 +28,9 @@
 // 0..3 and tile 1's as rows 4..7: every lane then holds its own stencil's
 // four logits in registers 0..3.  Evaluations whose smallest |logit| is below
 // the re-check margin are evaluated again inside the same kernel, before the
-// combine: with FP16 operands in two-part FP16 passes (mlp_split32), with
-// BF16 operands in FP32 (mlp_f32_16, or the vector units in the scalar
-// kernels).
+// combine: in FP32 (mlp_f32_16 on MFMA, or the vector units in the scalar
+// kernels), or, as an option for FP16 operands (SPLIT), in two-part FP16
+// passes (mlp_split32).
 #include <algorithm>
 
 #include "neno6_device.h"
@@ -592,10 +592,10 @@ N6_DEV u32x4 split_input(const float s[6], int lane) {
 // (the host only sets it when gridDim.x is a multiple of 8).  Two waves per
 // SIMD (at three, 47 spilled registers made it 30 % slower).  Near-cutoff
 // evaluations (a few percent in 2D) are listed per tile in LDS and evaluated
-// again before the combine: with FP16 operands in two-part FP16 passes of 32
-// (mlp_split32, remainder table in LDS), with BF16 operands in FP32 passes of
-// 16 (mlp_f32_16, its table in LDS).
-template <int PREC, int W, bool MLP>
+// again before the combine: in FP32 passes of 16 (mlp_f32_16, its table in
+// LDS) or, with SPLIT (FP16 operands), in two-part FP16 passes of 32
+// (mlp_split32, remainder table in LDS).
+template <int PREC, int W, bool MLP, bool SPLIT>
 __global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(2)))
 k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared, float margin,
              const float *__restrict__ q, const uint8_t *__restrict__ min, float *__restrict__ Fh,
@@ -606,13 +606,14 @@ k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared
   // re-check list (lane << 3 | kind) and the re-checked labels (kind, lane)
   __shared__ uint16_t relist[W][MLP ? NE * 64 : 1];
   __shared__ uint8_t relab[W][MLP ? NE : 1][64];
-  // the re-check's operand table (FP16: remainder table; BF16: FP32 table),
-  // staged once per workgroup
-  constexpr int TREGS = PREC == 3 ? LO_REGS : F4_REGS;
+  // the re-check's operand table (FP32 table, or with SPLIT the remainder
+  // table), staged once per workgroup
+  static_assert(!SPLIT || PREC == 3, "two-part re-check with FP16 operands only");
+  constexpr int TREGS = SPLIT ? LO_REGS : F4_REGS;
   __shared__ u32 tlds[MLP ? TREGS * 64 : 1];
   const float *b5 = (const float *)((const char *)prepared + PREP_B5_OFF);
   if constexpr (MLP) {
-    const u32 *g = (const u32 *)((const char *)prepared + (PREC == 3 ? PREP_LO_OFF : PREP_F4_OFF));
+    const u32 *g = (const u32 *)((const char *)prepared + (SPLIT ? PREP_LO_OFF : PREP_F4_OFF));
     for (int i = threadIdx.x; i < TREGS * 64; i += W * 64) tlds[i] = g[i];
     __syncthreads();
   }
@@ -682,8 +683,8 @@ k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (MLP) {
       __builtin_amdgcn_s_setprio(0);
-      // near-cutoff evaluations of the tile, evaluated again (two-part FP16
-      // in passes of 32, or FP32 in passes of 16); their labels replace the
+      // near-cutoff evaluations of the tile, evaluated again (FP32 in passes
+      // of 16, or two-part FP16 in passes of 32); their labels replace the
       // reduced-precision ones
       const u32 want = valid ? near : 0u;
       if (__ballot(want != 0u) != 0ull) {  // wave-uniform
@@ -701,7 +702,7 @@ k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared
           m &= m - 1u;
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        if constexpr (PREC == 3) {
+        if constexpr (SPLIT) {
           const int jcol = lane & 31;
           for (int b0 = 0; b0 < nnear; b0 += 32) {
             const int i = b0 + jcol;
@@ -762,7 +763,7 @@ k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared
   if (MLP && nrecheck && lane == 0 && nre) atomicAdd(nrecheck + ((blockIdx.x * W + wv) & 7), nre);
 }
 
-// ---- FP32 re-check in 16-evaluation passes (BF16 operands) ---------------------------
+// ---- FP32 re-check in 16-evaluation passes ------------------------------------------
 // The classifier in FP32 on v_mfma_f32_16x16x4_f32 for up to 16 evaluations,
 // in the same transposed, weight-stationary tiling: lane l = (j, k) with
 // j = l % 16 (evaluation) and k = l / 16 provides K slot k of each step, and
@@ -906,7 +907,7 @@ N6_DEV void mlp_f32_16(const float *tab, const float *b5, int lane, const float 
   for (int r = 0; r < 4; ++r) z[r] = c5[r] + b5[r];
 }
 
-// ---- two-part FP16 re-check in 32-evaluation passes -----------------------------------
+// ---- two-part FP16 re-check in 32-evaluation passes (option, FP16 operands) ----------
 // Every operand in two FP16 parts, FP32 accumulation: weights as their FP16
 // value (the registers of the FP16 classifier) plus the FP16 rounding of what
 // that leaves (the remainder table), activations likewise, carried times
@@ -1011,9 +1012,9 @@ N6_DEV void mlp_split32(const Wts &w, const u32 *lotab, int lane, u32x4 bin, flo
 //
 // Near-cutoff evaluations (smallest |logit| below the margin) are evaluated
 // again before the combine, in the tile itself: they are listed in LDS, form
-// their features from the stash in passes of 32 (FP16 operands: two-part FP16,
-// remainder table read through the caches) or 16 (BF16 operands: FP32 MFMA),
-// and the re-check's labels replace the reduced-precision ones.  A few tenths
+// their features from the stash in passes of 16 (FP32 MFMA) or, with SPLIT
+// (FP16 operands), of 32 (two-part FP16, remainder table read through the
+// caches), and the re-check's labels replace the reduced-precision ones.  A few tenths
 // of a percent of the evaluations are near, about one per tile.
 
 // Output of cell kc of the line of fa, between fluxes Fl (left face) and Fr.
@@ -1053,7 +1054,7 @@ constexpr int NRECHECK_SLOTS = QCOUNTERS;
 // evaluations of flat faces are then re-checked only when the caller asks
 // for the labels (out.masks); they are most of the near evaluations of
 // piecewise-constant data.
-template <int PREC, int W, bool MLP>
+template <int PREC, int W, bool MLP, bool SPLIT>
 __global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(3)))
 k_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float margin,
           const float *__restrict__ q, const uint8_t *__restrict__ min, Out1D out, int xcd) {
@@ -1161,7 +1162,7 @@ k_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float marg
           m &= m - 1u;
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        if constexpr (PREC == 3) {
+        if constexpr (SPLIT) {
           const u32 *lot = (const u32 *)((const char *)prepared + PREP_LO_OFF);
           const int jcol = lane & 31;
           for (int b0 = 0; b0 < nnear; b0 += 32) {
@@ -1252,7 +1253,7 @@ k_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float marg
 // lane per stencil, re-check done in place (these are the small cases).
 // mode 0: stencils from f[k..k+5] (sign) ; mode 1: advection lines (ghosts);
 // mode 2: raw stencils sten[n][6] -> logits.
-// LDS of one wave for the re-check of the scalar kernels (FP16 operands).
+// LDS of one wave for the two-part re-check of the scalar kernels.
 struct WaveRecheck {
   float s[6][64];   // the wave's stencils
   float z[4][64];   // re-check logits
@@ -1262,17 +1263,17 @@ struct WaveRecheck {
 
 // MLP label of the stencil s of every lane of the wave (all 64 lanes call
 // it together): the BF16/FP16 classifier, then the re-check of evaluations
-// within the margin -- FP16 operands: two-part FP16 passes of 32 (lot: the
-// remainder table, in LDS); BF16: FP32 on the vector units.  With z, the
-// lane's logits (the re-check's where it ran).
-template <int PREC>
+// within the margin -- FP32 on the vector units, or with SPLIT two-part FP16
+// passes of 32 (lot: the remainder table, in LDS).  With z, the lane's
+// logits (the re-check's where it ran).
+template <int PREC, bool SPLIT>
 N6_DEV u32 mlp_select(const Wts &w, const void *prepared, const u32 *lot, WaveRecheck &L,
                       float margin, const float s[6], bool valid, float *z) {
   float zl[4];
   const u32 mk = classify_wave<PREC>(w, s, margin, zl);
   const bool near = valid && (mk & 16u);
   u32 sel = mk & 15u;
-  if constexpr (PREC == 3) {
+  if constexpr (SPLIT) {
     const uint64_t bal = __ballot(near);
     if (bal != 0ull) {  // wave-uniform
       const int lane = threadIdx.x & 63;
@@ -1315,19 +1316,19 @@ N6_DEV u32 mlp_select(const Wts &w, const void *prepared, const u32 *lot, WaveRe
   return sel;
 }
 
-// The re-check's LDS of a scalar kernel: the remainder table (FP16
-// operands), staged once per workgroup, and one WaveRecheck per wave.
-#define N6_SCALAR_RECHECK_LDS(PREC, selector, prepared)                                           \
-  __shared__ u32 lot[(PREC) == 3 ? LO_REGS * 64 : 1];                                            \
-  __shared__ WaveRecheck wrl[(PREC) == 3 ? WPB : 1];                                             \
-  if ((PREC) == 3 && (selector) == 0) {                                                          \
+// The two-part re-check's LDS of a scalar kernel: the remainder table,
+// staged once per workgroup, and one WaveRecheck per wave.
+#define N6_SCALAR_RECHECK_LDS(SPLIT, selector, prepared)                                          \
+  __shared__ u32 lot[(SPLIT) ? LO_REGS * 64 : 1];                                                \
+  __shared__ WaveRecheck wrl[(SPLIT) ? WPB : 1];                                                 \
+  if ((SPLIT) && (selector) == 0) {                                                              \
     const u32 *g_ = (const u32 *)((const char *)(prepared) + PREP_LO_OFF);                       \
     for (int i_ = threadIdx.x; i_ < LO_REGS * 64; i_ += TPB) lot[i_] = g_[i_];                   \
     __syncthreads();                                                                             \
   }                                                                                              \
-  WaveRecheck &wr = wrl[(PREC) == 3 ? (threadIdx.x >> 6) : 0];
+  WaveRecheck &wr = wrl[(SPLIT) ? (threadIdx.x >> 6) : 0];
 
-template <int PREC>
+template <int PREC, bool SPLIT>
 __global__ void __launch_bounds__(TPB)
 k_fast_scalar(int mode, Line1D ln, const void *__restrict__ prepared, float margin,
               const float *__restrict__ src, int64_t n, int sign, int selector,
@@ -1335,7 +1336,7 @@ k_fast_scalar(int mode, Line1D ln, const void *__restrict__ prepared, float marg
               float *__restrict__ zout) {
   const int lane = threadIdx.x & 63;
   const int64_t nchunk = (n + 63) / 64;
-  N6_SCALAR_RECHECK_LDS(PREC, selector, prepared)
+  N6_SCALAR_RECHECK_LDS(SPLIT, selector, prepared)
   Wts w;
   if (selector == 0) load_wts<PREC>(prepared, lane, w);
   for (int64_t ch = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6); ch < nchunk;
@@ -1359,7 +1360,7 @@ k_fast_scalar(int mode, Line1D ln, const void *__restrict__ prepared, float marg
     u32 sel;
     float z[4];
     if (selector == 0) {
-      sel = mlp_select<PREC>(w, prepared, lot, wr, margin, s, valid, mode == 2 ? z : nullptr);
+      sel = mlp_select<PREC, SPLIT>(w, prepared, lot, wr, margin, s, valid, mode == 2 ? z : nullptr);
     } else if (selector == 1) {
       sel = 15u;
     } else if (selector == 2) {
@@ -1382,10 +1383,10 @@ k_fast_scalar(int mode, Line1D ln, const void *__restrict__ prepared, float marg
 
 // Label of one scalar stencil by the selector; the MFMA classification is a
 // wave-wide operation, so every lane of the wave calls this together.
-template <int PREC>
+template <int PREC, bool SPLIT>
 N6_DEV u32 scalar_select(const Wts &w, int selector, const void *prepared, const u32 *lot,
                          WaveRecheck &wr, float margin, const float s[6], bool valid, u32 mask_in) {
-  if (selector == 0) return mlp_select<PREC>(w, prepared, lot, wr, margin, s, valid, nullptr);
+  if (selector == 0) return mlp_select<PREC, SPLIT>(w, prepared, lot, wr, margin, s, valid, nullptr);
   if (selector == 1) return 15u;
   if (selector == 2) return 0u;
   if (selector == 4) return teno_mask_of<float>(s);
@@ -1396,14 +1397,14 @@ N6_DEV u32 scalar_select(const Wts &w, int selector, const void *prepared, const
 // alpha = max |u| over the six cells, f+- = (f +- alpha u)/2 ('-' mirrored);
 // both split stencils classified (re-check in place), face flux = sum of the
 // two reconstructions.
-template <int PREC>
+template <int PREC, bool SPLIT>
 __global__ void __launch_bounds__(TPB)
 k_fast_burgers(Line1D ln, const void *__restrict__ prepared, float margin, int selector,
                const float *__restrict__ u, const uint8_t *__restrict__ min,
                float *__restrict__ Fh, uint8_t *__restrict__ mout) {
   const int lane = threadIdx.x & 63;
   const int64_t nf = ln.faces(), nchunk = (nf + 63) / 64;
-  N6_SCALAR_RECHECK_LDS(PREC, selector, prepared)
+  N6_SCALAR_RECHECK_LDS(SPLIT, selector, prepared)
   Wts w;
   if (selector == 0) load_wts<PREC>(prepared, lane, w);
   for (int64_t ch = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6); ch < nchunk;
@@ -1428,8 +1429,8 @@ k_fast_burgers(Line1D ln, const void *__restrict__ prepared, float margin, int s
       sm[5 - j] = 0.5f * (f - t);
     }
     const u32 mi = min ? min[gc] : 0u;
-    const u32 selp = scalar_select<PREC>(w, selector, prepared, lot, wr, margin, sp, valid, mi);
-    const u32 selm = scalar_select<PREC>(w, selector, prepared, lot, wr, margin, sm, valid, mi >> 4);
+    const u32 selp = scalar_select<PREC, SPLIT>(w, selector, prepared, lot, wr, margin, sp, valid, mi);
+    const u32 selm = scalar_select<PREC, SPLIT>(w, selector, prepared, lot, wr, margin, sm, valid, mi >> 4);
     if (!valid) continue;
     Fh[g] = combine_fast(sp, selp) + combine_fast(sm, selm);
     if (mout) mout[g] = (uint8_t)(selp | (selm << 4));
@@ -1984,33 +1985,37 @@ hipError_t launch_fast_prepare(const double *P, void *prepared, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_fast_logits(const void *prepared, int precision, float margin, const float *sten,
-                              int64_t n, float *z, uint8_t *masks, hipStream_t s) {
+// The scalar kernel of an operand precision and re-check arithmetic.
+#define N6_SCALAR(precision, split, ...)                                                        \
+  do {                                                                                        \
+    if ((precision) == 2)                                                                     \
+      hipLaunchKernelGGL((k_fast_scalar<2, false>), __VA_ARGS__);                             \
+    else if (split)                                                                           \
+      hipLaunchKernelGGL((k_fast_scalar<3, true>), __VA_ARGS__);                              \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_fast_scalar<3, false>), __VA_ARGS__);                             \
+  } while (0)
+
+hipError_t launch_fast_logits(const void *prepared, int precision, bool split, float margin,
+                              const float *sten, int64_t n, float *z, uint8_t *masks,
+                              hipStream_t s) {
   if (n == 0) return hipSuccess;
   Line1D ln{};
   const unsigned grid = grid_for((n + 63) / 64);
-  if (precision == 2)
-    hipLaunchKernelGGL(k_fast_scalar<2>, dim3(grid), dim3(TPB), 0, s, 2, ln, prepared, margin, sten,
-                       n, 1, 0, nullptr, nullptr, masks, z);
-  else
-    hipLaunchKernelGGL(k_fast_scalar<3>, dim3(grid), dim3(TPB), 0, s, 2, ln, prepared, margin, sten,
-                       n, 1, 0, nullptr, nullptr, masks, z);
+  N6_SCALAR(precision, split, dim3(grid), dim3(TPB), 0, s, 2, ln, prepared, margin, sten, n, 1, 0,
+            nullptr, nullptr, masks, z);
   return hipGetLastError();
 }
 
-hipError_t launch_fast_reconstruct(const void *prepared, int precision, float margin,
+hipError_t launch_fast_reconstruct(const void *prepared, int precision, bool split, float margin,
                                    const float *f, int64_t n_faces, int sign, int selector,
                                    const uint8_t *masks_in, float *fhat, uint8_t *masks_out,
                                    hipStream_t s) {
   if (n_faces == 0) return hipSuccess;
   Line1D ln{};
   const unsigned grid = grid_for((n_faces + 63) / 64);
-  if (precision == 2)
-    hipLaunchKernelGGL(k_fast_scalar<2>, dim3(grid), dim3(TPB), 0, s, 0, ln, prepared, margin, f,
-                       n_faces, sign, selector, masks_in, fhat, masks_out, nullptr);
-  else
-    hipLaunchKernelGGL(k_fast_scalar<3>, dim3(grid), dim3(TPB), 0, s, 0, ln, prepared, margin, f,
-                       n_faces, sign, selector, masks_in, fhat, masks_out, nullptr);
+  N6_SCALAR(precision, split, dim3(grid), dim3(TPB), 0, s, 0, ln, prepared, margin, f, n_faces,
+            sign, selector, masks_in, fhat, masks_out, nullptr);
   return hipGetLastError();
 }
 
@@ -2019,22 +2024,25 @@ hipError_t launch_fast_reconstruct(const void *prepared, int precision, float ma
 hipError_t launch_faces2d_kernel(const FaceLaunch &L, const FastArgs &fa, hipStream_t s,
                                  const Grid2D &g, int dir, const float *q, const uint8_t *mi,
                                  float *F, uint8_t *m) {
-#define N6_FACES(P, W)                                                                        \
-  hipLaunchKernelGGL((k_fast_faces<P, W, true>), dim3(L.grid), dim3(W * 64), 0, s, g, dir,     \
-                     fa.selector, fa.prepared, fa.margin, q, mi, F, m, nrc, L.xcd)
+#define N6_FACES(P, W, SPLIT)                                                                 \
+  hipLaunchKernelGGL((k_fast_faces<P, W, true, SPLIT>), dim3(L.grid), dim3(W * 64), 0, s, g,   \
+                     dir, fa.selector, fa.prepared, fa.margin, q, mi, F, m, nrc, L.xcd)
   // re-check counters of this sweep (diagnostic), only while a margin is set
   u32 *nrc = fa.margin > 0.f && fa.scr.qcount ? fa.scr.qcount + 8 * dir : nullptr;
   if (fa.selector != 0) {  // the other selectors: no classifier, one instantiation
-    hipLaunchKernelGGL((k_fast_faces<2, 4, false>), dim3(L.grid), dim3(256), 0, s, g, dir,
+    hipLaunchKernelGGL((k_fast_faces<2, 4, false, false>), dim3(L.grid), dim3(256), 0, s, g, dir,
                        fa.selector, fa.prepared, fa.margin, q, mi, F, m, nullptr, L.xcd);
     return hipGetLastError();
   }
   if (fa.precision == 2) {
-    if (L.waves == 8) N6_FACES(2, 8);
-    else N6_FACES(2, 4);
+    if (L.waves == 8) N6_FACES(2, 8, false);
+    else N6_FACES(2, 4, false);
+  } else if (fa.split) {
+    if (L.waves == 8) N6_FACES(3, 8, true);
+    else N6_FACES(3, 4, true);
   } else {
-    if (L.waves == 8) N6_FACES(3, 8);
-    else N6_FACES(3, 4);
+    if (L.waves == 8) N6_FACES(3, 8, false);
+    else N6_FACES(3, 4, false);
   }
 #undef N6_FACES
   return hipGetLastError();
@@ -2047,36 +2055,38 @@ hipError_t launch_fast_pass1d(const Line1D &ln, const FastArgs &fa, const float 
   if (fa.equation == 0 || fa.equation == 1) {  // scalar laws: face fluxes, re-check in place
     if (out.mode != OUT_FACES) return hipErrorInvalidValue;
     if (fa.equation == 0) {
-      if (fa.precision == 2)
-        hipLaunchKernelGGL(k_fast_scalar<2>, dim3(grid), dim3(TPB), 0, s, 1, ln, fa.prepared, fa.margin,
-                           q, tf, 1, fa.selector, masks_in, out.dst, out.masks, nullptr);
-      else
-        hipLaunchKernelGGL(k_fast_scalar<3>, dim3(grid), dim3(TPB), 0, s, 1, ln, fa.prepared, fa.margin,
-                           q, tf, 1, fa.selector, masks_in, out.dst, out.masks, nullptr);
+      N6_SCALAR(fa.precision, fa.split, dim3(grid), dim3(TPB), 0, s, 1, ln, fa.prepared, fa.margin,
+                q, tf, 1, fa.selector, masks_in, out.dst, out.masks, nullptr);
+    } else if (fa.precision == 2) {
+      hipLaunchKernelGGL((k_fast_burgers<2, false>), dim3(grid), dim3(TPB), 0, s, ln, fa.prepared,
+                         fa.margin, fa.selector, q, masks_in, out.dst, out.masks);
+    } else if (fa.split) {
+      hipLaunchKernelGGL((k_fast_burgers<3, true>), dim3(grid), dim3(TPB), 0, s, ln, fa.prepared,
+                         fa.margin, fa.selector, q, masks_in, out.dst, out.masks);
     } else {
-      if (fa.precision == 2)
-        hipLaunchKernelGGL(k_fast_burgers<2>, dim3(grid), dim3(TPB), 0, s, ln, fa.prepared,
-                           fa.margin, fa.selector, q, masks_in, out.dst, out.masks);
-      else
-        hipLaunchKernelGGL(k_fast_burgers<3>, dim3(grid), dim3(TPB), 0, s, ln, fa.prepared,
-                           fa.margin, fa.selector, q, masks_in, out.dst, out.masks);
+      hipLaunchKernelGGL((k_fast_burgers<3, false>), dim3(grid), dim3(TPB), 0, s, ln, fa.prepared,
+                         fa.margin, fa.selector, q, masks_in, out.dst, out.masks);
     }
     return hipGetLastError();
   }
   const FaceLaunch L = face_launch(fa, (tf + 61) / 63);
-#define N6_EULER1D(P, W, MLP)                                                                  \
-  hipLaunchKernelGGL((k_euler1d<P, W, MLP>), dim3(L.grid), dim3(W * 64), 0, s, ln, fa.selector, \
-                     fa.prepared, fa.margin, q, masks_in, out, L.xcd)
+#define N6_EULER1D(P, W, MLP, SPLIT)                                                           \
+  hipLaunchKernelGGL((k_euler1d<P, W, MLP, SPLIT>), dim3(L.grid), dim3(W * 64), 0, s, ln,        \
+                     fa.selector, fa.prepared, fa.margin, q, masks_in, out, L.xcd)
   if (fa.selector != 0) {
-    N6_EULER1D(2, 4, false);
+    N6_EULER1D(2, 4, false, false);
   } else if (fa.precision == 2) {
-    if (L.waves == 2) N6_EULER1D(2, 2, true);
-    else if (L.waves == 8) N6_EULER1D(2, 8, true);
-    else N6_EULER1D(2, 4, true);
+    if (L.waves == 2) N6_EULER1D(2, 2, true, false);
+    else if (L.waves == 8) N6_EULER1D(2, 8, true, false);
+    else N6_EULER1D(2, 4, true, false);
+  } else if (fa.split) {
+    if (L.waves == 2) N6_EULER1D(3, 2, true, true);
+    else if (L.waves == 8) N6_EULER1D(3, 8, true, true);
+    else N6_EULER1D(3, 4, true, true);
   } else {
-    if (L.waves == 2) N6_EULER1D(3, 2, true);
-    else if (L.waves == 8) N6_EULER1D(3, 8, true);
-    else N6_EULER1D(3, 4, true);
+    if (L.waves == 2) N6_EULER1D(3, 2, true, false);
+    else if (L.waves == 8) N6_EULER1D(3, 8, true, false);
+    else N6_EULER1D(3, 4, true, false);
   }
 #undef N6_EULER1D
   return hipGetLastError();

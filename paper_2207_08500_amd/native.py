@@ -24,6 +24,7 @@ FP64, FP32, BF16, FP16 = 0, 1, 2, 3
 ADVECTION, BURGERS, EULER1D, EULER2D = 0, 1, 2, 3
 PERIODIC, TRANSMISSIVE = 0, 1
 SEL_MLP, SEL_ALL_SMOOTH, SEL_ALL_DISCARD, SEL_MASKS_IN, SEL_TENO = 0, 1, 2, 3, 4
+RECHECK_FP32, RECHECK_FP16X2 = 0, 1
 KEEP_MAP = 1
 NPARAM = 3228
 
@@ -43,7 +44,7 @@ class Neno6Error(RuntimeError):
 
 class MlpStruct(C.Structure):
     _fields_ = [("params", C.c_void_p), ("prepared", C.c_void_p), ("recheck_margin", C.c_float),
-                ("reserved", C.c_int32)]
+                ("recheck_mode", C.c_int32)]
 
 
 class TuningStruct(C.Structure):
@@ -151,7 +152,10 @@ def fdtype(precision: int):
 class Mlp:
     """Classifier handle: FP64 master parameters and the prepared block on device."""
 
-    def __init__(self, params: torch.Tensor, recheck_margin: float = 0.0, prepare: bool = True):
+    def __init__(self, params: torch.Tensor, recheck_margin: float = 0.0, prepare: bool = True,
+                 recheck_mode: int = 0):
+        """recheck_mode: RECHECK_FP32 (default) or RECHECK_FP16X2 (FP16 operands
+        re-checked in two-part FP16 on MFMA)."""
         _dev(params, torch.float64, "params")
         if params.numel() != NPARAM:
             raise ValueError("params must hold %d values" % NPARAM)
@@ -159,11 +163,13 @@ class Mlp:
         nb = int(load().neno6_mlp_prepared_bytes())
         self.prepared = torch.empty(nb, dtype=torch.uint8, device=params.device)
         self.recheck_margin = float(recheck_margin)
+        self.recheck_mode = int(recheck_mode)
         if prepare:
             neno6_mlp_prepare(self)
 
     def struct(self) -> MlpStruct:
-        return MlpStruct(self.params.data_ptr(), self.prepared.data_ptr(), self.recheck_margin, 0)
+        return MlpStruct(self.params.data_ptr(), self.prepared.data_ptr(), self.recheck_margin,
+                         self.recheck_mode)
 
 
 def _mlp(mlp):

@@ -42,8 +42,8 @@ def _lines(seed, sizes):
     return u, off, dx
 
 
-def _mlp(native, P, prec):
-    return native.Mlp(dev(P), recheck_margin=MARGIN.get(prec, 0.0))
+def _mlp(native, P, prec, mode=0):
+    return native.Mlp(dev(P), recheck_margin=MARGIN.get(prec, 0.0), recheck_mode=mode)
 
 
 @pytest.mark.parametrize("selector", [0, 1, 2, 3, 4])
@@ -108,14 +108,14 @@ def native_bc(kind):
     return 1 if kind == "open" else 0
 
 
-def _run_to(native, torch, P, prec, selector, u0, dx, cfl, t_end, bc, fixed_steps=None):
+def _run_to(native, torch, P, prec, selector, u0, dx, cfl, t_end, bc, fixed_steps=None, mode=0):
     """March with CFL steps until t >= t_end, or exactly fixed_steps steps."""
     prob = native.Problem(native.BURGERS, prec, selector, bc, [0, u0.size], [dx])
     u = dev(u0, native.fdtype(prec))
     t = torch.zeros(1, dtype=torch.float64, device="cuda")
     st = torch.zeros(1, dtype=torch.int32, device="cuda")
     ws = prob.workspace()
-    mlp = _mlp(native, P, prec) if selector == 0 else None
+    mlp = _mlp(native, P, prec, mode) if selector == 0 else None
     steps = 0
     if fixed_steps is not None:
         native.neno6_step(prob, mlp, u, cfl, fixed_steps, t, st, ws)
@@ -128,11 +128,11 @@ def _run_to(native, torch, P, prec, selector, u0, dx, cfl, t_end, bc, fixed_step
     return host(u).astype(np.float64), float(host(t)[0]), steps
 
 
-def _labels(native, torch, P, prec, selector, u0, dx, bc):
+def _labels(native, torch, P, prec, selector, u0, dx, bc, mode=0):
     prob = native.Problem(native.BURGERS, prec, selector, bc, [0, u0.size], [dx])
     u = dev(u0, native.fdtype(prec))
     m = torch.zeros(prob.mask_count(), dtype=torch.uint8, device="cuda")
-    native.neno6_rhs(prob, _mlp(native, P, prec) if selector == 0 else None, u, torch.zeros_like(u),
+    native.neno6_rhs(prob, _mlp(native, P, prec, mode) if selector == 0 else None, u, torch.zeros_like(u),
                      prob.workspace(), masks_out=m)
     torch.cuda.synchronize()
     return host(m)
@@ -150,13 +150,14 @@ def test_paper_burgers_cases(ctx, case, selector):
     _same(u64, u_o)
     assert t64 == t_o[0]
     m64 = _labels(native, torch, P, native.FP64, selector, u0, dx, bc)
-    for prec in (1, 2, 3):
-        ur, tr, _ = _run_to(native, torch, P, prec, selector, u0, dx, cfl, t_end, bc, steps)
+    for prec, mode in ((1, 0), (2, 0), (3, 0), (3, 1)):
+        ur, tr, _ = _run_to(native, torch, P, prec, selector, u0, dx, cfl, t_end, bc, steps,
+                            mode=mode)
         l1 = np.abs(ur - u64).mean() / np.abs(u64).mean()
-        flip = label_flip_rate(_labels(native, torch, P, prec, selector, u0, dx, bc), m64)
-        print("Burgers %s selector %d prec %d: %d steps to t = %.4f, relative L1 vs FP64 %.3g, "
-              "label flip rate on the initial state %.3g" % (case, selector, prec, steps, t64, l1,
-                                                            flip))
+        flip = label_flip_rate(_labels(native, torch, P, prec, selector, u0, dx, bc, mode), m64)
+        print("Burgers %s selector %d prec %d mode %d: %d steps to t = %.4f, relative L1 vs FP64 "
+              "%.3g, label flip rate on the initial state %.3g" % (case, selector, prec, mode,
+                                                                   steps, t64, l1, flip))
         assert flip < 1e-3
         if selector == 4:  # TENO6-opt labels are decided in FP64: the runs stay together
             assert abs(tr - t64) < 1e-4 * t64 and l1 < 1e-4

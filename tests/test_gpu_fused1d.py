@@ -51,8 +51,8 @@ def _fscale(r_o, q, off, dx):
     return s
 
 
-def _rhs(native, torch, P, prec, margin, q32, off, dx, tuning=None, bc=1):
-    mlp = native.Mlp(dev(P), recheck_margin=margin)
+def _rhs(native, torch, P, prec, margin, q32, off, dx, tuning=None, bc=1, mode=0):
+    mlp = native.Mlp(dev(P), recheck_margin=margin, recheck_mode=mode)
     prob = native.Problem(native.EULER1D, prec, native.SEL_MLP, bc, off, dx)
     prob.set_tuning(tuning)
     ws = prob.workspace()
@@ -76,9 +76,9 @@ def _rhs_masks_in(native, torch, P, prec, q32, off, dx, masks):
     return host(r).reshape(3, -1)
 
 
-@pytest.mark.parametrize("prec", [2, 3])
+@pytest.mark.parametrize("prec,mode", [(2, 0), (3, 0), (3, 1)])
 @pytest.mark.parametrize("margin", ["stated", "all"])
-def test_rhs_elementwise_against_oracle(ctx, prec, margin):
+def test_rhs_elementwise_against_oracle(ctx, prec, mode, margin):
     """Labels against the oracle's (flip rate), then values: at every cell
     whose faces carry the oracle's labels the classifier pass gives exactly
     the values of the same pass with the oracle's labels imposed (same FP32
@@ -215,8 +215,8 @@ def test_launch_shapes_bitwise(ctx, prec):
         assert n_re >= res[0][4]  # the overlap faces of the tiles are re-checked by both tiles
 
 
-@pytest.mark.parametrize("prec", [2, 3])
-def test_c2_full_size_evolved_state(ctx, prec):
+@pytest.mark.parametrize("prec,mode", [(2, 0), (3, 0), (3, 1)])
+def test_c2_full_size_evolved_state(ctx, prec, mode):
     """The 256 x 4000 batch in the benchmark's configuration on an evolved
     state: the FP64 path advances the batch 40 RK3 steps from the Riemann
     data (a realistic state for the whole launch), and six sampled problems
@@ -247,11 +247,12 @@ def test_c2_full_size_evolved_state(ctx, prec):
     assert len(picked) >= 5
     qe = qe.astype(np.float32).astype(np.float64)
     q32 = dev(qe, torch.float32)
-    mlp = native.Mlp(dev(P), recheck_margin=MARGIN[prec])
+    mlp = native.Mlp(dev(P), recheck_margin=MARGIN[prec], recheck_mode=mode)
     prob = native.Problem(native.EULER1D, prec, native.SEL_MLP, 1, off, dx)
     ws = prob.workspace()
     tun, _ = autotune.tuned(prob, mlp, q32, ws)
-    r, m, _, _, n_re = _rhs(native, torch, P, prec, MARGIN[prec], q32, off, dx, tuning=tun)
+    r, m, _, _, n_re = _rhs(native, torch, P, prec, MARGIN[prec], q32, off, dx, tuning=tun,
+                            mode=mode)
     flips, worst = [], 0.0
     for p in picked:
         a, b = off[p], off[p + 1]

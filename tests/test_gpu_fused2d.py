@@ -45,16 +45,16 @@ def _cells_with_oracle_labels(mx, my, mx_o, my_o):
     return sx[:, :-1] & sx[:, 1:] & sy[:-1, :] & sy[1:, :]
 
 
-@pytest.mark.parametrize("prec", [3, 2])
+@pytest.mark.parametrize("prec,mode", [(3, 0), (3, 1), (2, 0)])
 @pytest.mark.parametrize("margin", ["stated", "all"])
-def test_rhs2d_elementwise_against_oracle(ctx, prec, margin):
+def test_rhs2d_elementwise_against_oracle(ctx, prec, mode, margin):
     native, torch, P = ctx
     mu = MARGIN[prec] if margin == "stated" else 1e30
     for name, q in _states():
         _, ny, nx = q.shape
         q32 = q.astype(np.float32).astype(np.float64)
         r_o, mx_o, my_o, _ = oracle.euler2d_rhs(q32, 1 / nx, 1 / ny, 1.4, 1, P, oracle.SEL_MLP)
-        mlp = native.Mlp(dev(P), recheck_margin=mu)
+        mlp = native.Mlp(dev(P), recheck_margin=mu, recheck_mode=mode)
         prob = native.Problem(native.EULER2D, prec, native.SEL_MLP, 1, nx=nx, ny=ny, dx2d=1 / nx,
                               dy2d=1 / ny)
         qg = dev(q32, torch.float32)
@@ -77,9 +77,9 @@ def test_rhs2d_elementwise_against_oracle(ctx, prec, margin):
         fscale = np.abs(r_o).max() + np.abs(q).max() * max(nx, ny)
         err = np.abs(r - r_o)[:, ok].max() / fscale
         same = np.array_equal(r[:, ok].view(np.uint32), r_in[:, ok].view(np.uint32))
-        print("%s prec %d margin %s: flip rate %.3g, %.4f of the cells with oracle labels, max "
+        print("%s prec %d mode %d margin %s: flip rate %.3g, %.4f of the cells with oracle labels, max "
               "rel err %.3g, bitwise equal to the imposed-label pass: %s"
-              % (name, prec, margin, flips, ok.mean(), err, same))
+              % (name, prec, mode, margin, flips, ok.mean(), err, same))
         assert flips < (2e-4 if margin == "all" else 2e-3)
         assert ok.mean() > 0.98
         assert same

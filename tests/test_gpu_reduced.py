@@ -26,8 +26,8 @@ def ctx():
     return native, torch, P
 
 
-def _mlp(native, P, prec):
-    return native.Mlp(dev(P), recheck_margin=MARGIN.get(prec, 0.0))
+def _mlp(native, P, prec, mode=0):
+    return native.Mlp(dev(P), recheck_margin=MARGIN.get(prec, 0.0), recheck_mode=mode)
 
 
 @pytest.mark.parametrize("prec", [1, 2, 3])
@@ -65,21 +65,21 @@ def test_logits_against_oracle(ctx, prec):
         assert flips < 1e-5
 
 
-@pytest.mark.parametrize("prec", [2, 3])
-def test_recheck_logits_against_oracle(ctx, prec):
+@pytest.mark.parametrize("prec,mode", [(2, 0), (3, 0), (3, 1)])
+def test_recheck_logits_against_oracle(ctx, prec, mode):
     """With every evaluation inside the margin the logits are the re-check's:
-    BF16 operands -> FP32 on the vector units, held to the FP32 mode's bound;
-    FP16 operands -> the two-part FP16 passes (weights and activations each
-    as an FP16 value plus the FP16 rounding of the remainder, FP32 sums),
-    whose operands carry 21-22 significant bits against FP32's 24: held to
-    eight times that bound.  The labels are the signs of these logits, and a
+    FP32 on the vector units (the default re-check arithmetic), held to the
+    FP32 mode's bound; with the two-part FP16 re-check (FP16 operands;
+    weights and activations each as an FP16 value plus the FP16 rounding of
+    the remainder, FP32 sums), whose operands carry 21-22 significant bits
+    against FP32's 24: held to eight times that bound.  The labels are the signs of these logits, and a
     label differs from FP64 only for a logit within 1e-3 of the cutoff."""
     native, torch, P = ctx
     n = 1 << 16
     s, _ = inputs.classifier_samples(20, n)
     s32 = s.astype(np.float32).astype(np.float64)
     _, z_o = oracle.mlp_logits(P, s32)
-    mlp = native.Mlp(dev(P), recheck_margin=1e30)
+    mlp = native.Mlp(dev(P), recheck_margin=1e30, recheck_mode=mode)
     z = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
     m = torch.zeros(n, dtype=torch.uint8, device="cuda")
     native.neno6_mlp_logits(mlp, prec, dev(s32, torch.float32), z, m)
@@ -87,23 +87,23 @@ def test_recheck_logits_against_oracle(ctx, prec):
     z, m = host(z).astype(np.float64), host(m)
     err = np.abs(z - z_o)
     scale = max(1.0, np.abs(z_o).max())
-    print("prec %d, every evaluation re-checked: max |dz| %.3g (%.3g of the largest logit), "
-          "median %.3g" % (prec, err.max(), err.max() / scale, np.median(err)))
+    print("prec %d mode %d, every evaluation re-checked: max |dz| %.3g (%.3g of the largest "
+          "logit), median %.3g" % (prec, mode, err.max(), err.max() / scale, np.median(err)))
     assert np.array_equal(m, sum(((z[:, k] <= 0).astype(np.uint8) << k) for k in range(4)))
-    assert err.max() <= (1e-4 if prec == 2 else 8e-4) * scale
+    assert err.max() <= (8e-4 if mode == native.RECHECK_FP16X2 else 1e-4) * scale
     want = sum(((z_o[:, k] <= 0).astype(np.uint8) << k) for k in range(4))
     bad = m != want
     assert np.all(np.abs(z_o[bad]).min(axis=1) < 1e-3)
 
 
-@pytest.mark.parametrize("prec", [1, 2, 3])
+@pytest.mark.parametrize("prec,mode", [(1, 0), (2, 0), (3, 0), (3, 1)])
 @pytest.mark.parametrize("sign", [1, -1])
-def test_reconstruct_against_oracle(ctx, prec, sign):
+def test_reconstruct_against_oracle(ctx, prec, mode, sign):
     native, torch, P = ctx
     n = 3001
     f = inputs.random_stencils(21, (n + 10) // 6 + 1).ravel()[: n + 5]
     fh_o, m_o = oracle.reconstruct(f, sign, P, oracle.SEL_MLP)
-    mlp = _mlp(native, P, prec)
+    mlp = _mlp(native, P, prec, mode)
     fh = torch.zeros(n, dtype=torch.float32, device="cuda")
     m = torch.zeros(n, dtype=torch.uint8, device="cuda")
     native.neno6_reconstruct(mlp, dev(f, torch.float32), sign, prec, native.SEL_MLP, fh, masks_out=m)
@@ -172,9 +172,9 @@ def test_euler2d_rhs_against_oracle(ctx, prec):
     assert np.abs(host(r2).reshape(q.shape) - r_o).max() <= 5e-5 * fscale
 
 
-@pytest.mark.parametrize("prec", [2, 3])
+@pytest.mark.parametrize("prec,mode", [(2, 0), (3, 0), (3, 1)])
 @pytest.mark.parametrize("nx,ny", [(67, 45), (130, 3)])
-def test_euler2d_recheck_lists_complete(ctx, prec, nx, ny):
+def test_euler2d_recheck_lists_complete(ctx, prec, mode, nx, ny):
     """With a margin that every logit falls inside, the 2D re-check lists
     hold every evaluation of both sweeps (eight per face, ragged grids), and
     the labels then come from the re-check (FP32 or two-part FP16): a flip
@@ -186,7 +186,7 @@ def test_euler2d_recheck_lists_complete(ctx, prec, nx, ny):
     nfx, nfy = (nx + 1) * ny, nx * (ny + 1)
     qg = dev(q, torch.float32)
     for margin in (0.0, 1e30):
-        mlp = native.Mlp(dev(P), recheck_margin=margin)
+        mlp = native.Mlp(dev(P), recheck_margin=margin, recheck_mode=mode)
         prob = native.Problem(native.EULER2D, prec, native.SEL_MLP, 1, nx=nx, ny=ny, dx2d=1 / nx,
                               dy2d=1 / ny)
         ws = prob.workspace()

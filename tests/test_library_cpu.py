@@ -109,6 +109,10 @@ def test_host_argument_checks():
     p2.offsets_host = big.ctypes.data
     assert lib.neno6_workspace_size(C.byref(p2)) == 0
     assert lib.neno6_reconstruct(None, None, 10, 2, 0, 1, None, None, None, None) == native.BAD_ARG
+    # re-check arithmetic: FP32 or two-part FP16 only (placeholders, never dereferenced)
+    bad_mode = native.MlpStruct(1, 1, 0.5, 2)
+    assert lib.neno6_mlp_logits(C.byref(bad_mode), native.FP16, C.c_void_p(1), 10, C.c_void_p(1), None,
+                                None) == native.BAD_ARG
     assert lib.neno6_reconstruct(None, None, 10, 1, 0, 0, None, None, None, None) == native.BAD_ARG
     assert lib.neno6_classifier_train(None, None, None, None, None, None, None, 0, 0, 0.0, 0.9,
                                       0.999, 1e-8, native.BF16, None, None, 0, None) == native.BAD_ARG
