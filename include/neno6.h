@@ -118,7 +118,23 @@ typedef struct neno6_mlp {
  *    uses var = field = 1 with both nibbles.
  *  2D (EULER2D): one nx x ny grid (nx, ny <= 2^20, nx * ny <= 2^28), SoA
  *    [4][ny][nx] (x fastest), spacings dx2d, dy2d; x-face masks
- *    [4][ny][nx+1], y-face masks [4][ny+1][nx]. */
+ *    [4][ny][nx+1], y-face masks [4][ny+1][nx].
+ *  A batch of 2D grids (EULER2D with grids_host != NULL): n_problems grids
+ *    (1..65536) of their own sizes and spacings, each within the limits
+ *    above; nx, ny, dx2d, dy2d and total_cells are then ignored.  Grid p's
+ *    state is its own [4][ny_p][nx_p] block, following grid p-1's (it starts
+ *    at element 4 sum_{r<p} nx_r ny_r), and so are its masks and face
+ *    fluxes (x then y faces of grid p after those of grid p-1); time and
+ *    status arrays hold one entry per grid.  The grids run one after another
+ *    on the stream, each with the launches of a single grid (so a batch is
+ *    captured into a HIP graph like a single grid; for many small grids the
+ *    launch count, not the GPU, sets the pace).  neno6_recheck_count and
+ *    neno6_rhs_noalloc do not take batches (NENO6_UNSUPPORTED); the autotuner
+ *    tunes on the grid with the most faces. */
+typedef struct neno6_grid2d {
+  int64_t nx, ny;
+  double dx, dy;
+} neno6_grid2d;
 /* Launch shapes of the BF16/FP16 kernels (from neno6_autotune, or chosen by
  * hand).  Any field left 0 takes the built-in default.
  *  face_waves:     64-lane waves per workgroup of the fused face kernel
@@ -158,6 +174,7 @@ typedef struct neno6_problem {
   double dx2d, dy2d;
   double gamma;
   const neno6_tuning *tuning;  /* [host, may be NULL] launch shapes; NULL = defaults */
+  const neno6_grid2d *grids_host; /* [host] EULER2D batch: grids[n_problems]; NULL = one grid */
 } neno6_problem;
 
 /* ---- library ------------------------------------------------------------- */
@@ -209,7 +226,7 @@ size_t neno6_workspace_size(const neno6_problem *prob);
  * ([4][ny][nx+1] followed by [4][ny+1][nx]).  status[n_problems] [dev] is
  * set to NENO6_NONPHYSICAL for a problem with a cell that is not physical
  * (it is never cleared here).
- * 1D Euler in BF16/FP16: one fused kernel computes the face fluxes, the FP32
+ * 1D Euler in BF16/FP16: one fused kernel computes the face fluxes, the
  * re-check of near-cutoff evaluations and the flux difference.  A face whose
  * six stencil cells are equal has a constant split stencil, whose
  * re-normalised combination is that constant for every selection; the pass
@@ -251,7 +268,7 @@ int32_t neno6_face_fluxes(const neno6_problem *prob, const neno6_mlp *mlp, const
 /* Diagnostic (synchronous: waits for `stream`): after neno6_face_fluxes or
  * neno6_rhs in BF16/FP16 mode with `mlp`, the number of classifier
  * evaluations of each sweep direction (count[0]: 1D or x, count[1]: y) that
- * were re-evaluated in FP32 (0 when mlp's margin is 0: the re-check does not
+ * were re-checked (0 when mlp's margin is 0: the re-check does not
  * run and its counters are not maintained).  1D: the pass works in tiles of
  * 64 faces that overlap by one face, so an overlap face's evaluations are
  * counted by both tiles; without masks_out the near-cutoff evaluations of
@@ -262,13 +279,12 @@ int32_t neno6_recheck_count(const neno6_problem *prob, const neno6_mlp *mlp, con
 
 /* Autotuner (host-synchronous, not for graph capture): times the fused
  * face pass of `prob` (1D: the fused kernel with its in-pass re-check; 2D:
- * counter reset, classifier kernel, re-check, fix-up) on state q [dev] for
- * every launch shape of a candidate set -- waves per workgroup W in
+ * both sweeps of the sweep kernel with its in-tile re-check) on state q [dev]
+ * for every launch shape of a candidate set -- waves per workgroup W in
  * {2, 4, 8} (2D: {4, 8}) x workgroup caps {512, 1024, 2048, 4096, 16384,
  * 65536, and k * V * CUs / W for k = 1, 2, 3 (whole rounds of resident waves
  * on the current device, V = 12 waves per CU in 1D, 8 in 2D)} x XCD ordering
- * {0, 1} x (2D only) re-check workgroups {128, 512, 2048} -- with HIP events
- * on `stream`, after about
+ * {0, 1} -- with HIP events on `stream`, after about
  * 0.1 s of warm-up passes in the default shape, `reps` (1..1000) timed
  * passes each after one warm-up, and writes the fastest to *best [host] (its mean pass
  * time in ms to *best_ms [host], may be NULL).  Outputs of the passes land in
@@ -286,7 +302,8 @@ int32_t neno6_autotune(const neno6_problem *prob, const neno6_mlp *mlp, const vo
  * when u is identically 0) -- and advances only problems whose
  * status word is 0; a problem whose state is not physical at that point gets
  * NENO6_NONPHYSICAL and stays frozen.  t[n_problems] [dev, FP64] advances by
- * the dt taken.  status [dev]: one int32 per problem (2D: one). */
+ * the dt taken.  status [dev]: one int32 per problem (one 2D grid: one; a
+ * batch of 2D grids: one per grid). */
 int32_t neno6_step(const neno6_problem *prob, const neno6_mlp *mlp, void *q, double cfl,
                    int32_t n_steps, double *t, int32_t *status, void *ws, size_t ws_bytes,
                    hipStream_t stream);

@@ -324,6 +324,57 @@ int32_t noalloc_scratch(void **out) {
   return NENO6_OK;
 }
 
+// ---- batches of 2D grids ------------------------------------------------------
+// A 2D problem with grids_host runs its grids one after another on the
+// stream, each as a one-grid problem; grid p's state, masks and face fluxes
+// follow grid p-1's.
+bool is_batch2d(const neno6_problem *pb) {
+  return pb && pb->equation == NENO6_EULER2D && pb->grids_host;
+}
+
+neno6_problem grid_problem(const neno6_problem *pb, int32_t p) {
+  neno6_problem s = *pb;
+  const neno6_grid2d &g = pb->grids_host[p];
+  s.n_problems = 1;
+  s.nx = g.nx;
+  s.ny = g.ny;
+  s.dx2d = g.dx;
+  s.dy2d = g.dy;
+  s.total_cells = g.nx * g.ny;
+  s.grids_host = nullptr;
+  return s;
+}
+
+int32_t check_batch2d(const neno6_problem *pb) {
+  if (pb->n_problems < 1 || pb->n_problems > 65536) return NENO6_BAD_ARG;
+  for (int32_t p = 0; p < pb->n_problems; ++p) {
+    const neno6_problem s = grid_problem(pb, p);
+    if (int32_t c = check_problem(&s)) return c;
+  }
+  return NENO6_OK;
+}
+
+// Walks the grids of a batch: for each, f(sub-problem, p, cells before it,
+// faces (x + y) before it); stops at the first error.
+template <typename Fn>
+int32_t for_each_grid(const neno6_problem *pb, Fn f) {
+  if (int32_t c = check_batch2d(pb)) return c;
+  int64_t cells = 0, faces = 0;
+  for (int32_t p = 0; p < pb->n_problems; ++p) {
+    const neno6_problem s = grid_problem(pb, p);
+    if (int32_t c = f(s, p, cells, faces)) return c;
+    cells += s.nx * s.ny;
+    faces += (s.nx + 1) * s.ny + s.nx * (s.ny + 1);
+  }
+  return NENO6_OK;
+}
+
+template <typename T> T *at(T *base, int64_t offset) { return base ? base + offset : nullptr; }
+inline const char *at_elems(const void *b, int64_t n, size_t es) {
+  return b ? (const char *)b + n * (int64_t)es : nullptr;
+}
+inline char *at_elems(void *b, int64_t n, size_t es) { return b ? (char *)b + n * (int64_t)es : nullptr; }
+
 }  // namespace
 
 extern "C" {
@@ -399,6 +450,14 @@ int32_t neno6_reconstruct(const neno6_mlp *mlp, const void *f, int64_t n_faces, 
 }
 
 size_t neno6_workspace_size(const neno6_problem *prob) {
+  if (is_batch2d(prob)) {  // the largest grid's: the grids run one after another
+    size_t most = 0;
+    const int32_t c = for_each_grid(prob, [&](const neno6_problem &s, int32_t, int64_t, int64_t) {
+      most = std::max(most, neno6_workspace_size(&s));
+      return NENO6_OK;
+    });
+    return c == NENO6_OK ? most : 0;
+  }
   if (check_problem(prob) != NENO6_OK) return 0;
   return carve_work(prob, nullptr).bytes;
 }
@@ -406,6 +465,15 @@ size_t neno6_workspace_size(const neno6_problem *prob) {
 int32_t neno6_rhs(const neno6_problem *prob, const neno6_mlp *mlp, const void *q, void *rhs,
                   const uint8_t *masks_in, uint8_t *masks_out, int32_t *status, void *ws,
                   size_t ws_bytes, hipStream_t stream) {
+  if (is_batch2d(prob)) {
+    if (!q || !rhs) return NENO6_BAD_ARG;
+    const size_t es = elem_size(prob->precision);
+    return for_each_grid(prob, [&](const neno6_problem &s, int32_t p, int64_t cells, int64_t faces) {
+      return neno6_rhs(&s, mlp, at_elems(q, 4 * cells, es), at_elems(rhs, 4 * cells, es),
+                       at(masks_in, 4 * faces), at(masks_out, 4 * faces), at(status, p), ws, ws_bytes,
+                       stream);
+    });
+  }
   if (int32_t c = check_problem(prob)) return c;
   if (int32_t c = check_mlp(mlp, prob->selector, prob->precision)) return c;
   if (!q || !rhs || !ws) return NENO6_BAD_ARG;
@@ -419,6 +487,7 @@ int32_t neno6_rhs(const neno6_problem *prob, const neno6_mlp *mlp, const void *q
 int32_t neno6_rhs_noalloc(const neno6_problem *prob, const neno6_mlp *mlp, const void *q,
                           void *rhs, const uint8_t *masks_in, uint8_t *masks_out, int32_t *status,
                           hipStream_t stream) {
+  if (is_batch2d(prob)) return NENO6_UNSUPPORTED;
   if (int32_t c = check_problem(prob)) return c;
   if (int32_t c = check_mlp(mlp, prob->selector, prob->precision)) return c;
   if (prob->equation != NENO6_EULER1D || prob->precision < NENO6_BF16) return NENO6_UNSUPPORTED;
@@ -439,6 +508,14 @@ int32_t neno6_rhs_noalloc(const neno6_problem *prob, const neno6_mlp *mlp, const
 
 int32_t neno6_face_fluxes(const neno6_problem *prob, const neno6_mlp *mlp, const void *q, void *F,
                           uint8_t *masks_out, void *ws, size_t ws_bytes, hipStream_t stream) {
+  if (is_batch2d(prob)) {
+    if (!q || !F) return NENO6_BAD_ARG;
+    const size_t es = elem_size(prob->precision);
+    return for_each_grid(prob, [&](const neno6_problem &s, int32_t, int64_t cells, int64_t faces) {
+      return neno6_face_fluxes(&s, mlp, at_elems(q, 4 * cells, es), at_elems(F, 4 * faces, es),
+                               at(masks_out, 4 * faces), ws, ws_bytes, stream);
+    });
+  }
   if (int32_t c = check_problem(prob)) return c;
   if (int32_t c = check_mlp(mlp, prob->selector, prob->precision)) return c;
   if (prob->selector == NENO6_SEL_MASKS_IN) return NENO6_UNSUPPORTED;
@@ -502,6 +579,7 @@ int32_t neno6_face_fluxes(const neno6_problem *prob, const neno6_mlp *mlp, const
 
 int32_t neno6_recheck_count(const neno6_problem *prob, const neno6_mlp *mlp, const void *ws,
                             size_t ws_bytes, uint32_t *count, hipStream_t stream) {
+  if (is_batch2d(prob)) return NENO6_UNSUPPORTED;
   if (int32_t c = check_problem(prob)) return c;
   if (!mlp || !ws || !count) return NENO6_BAD_ARG;
   if (prob->precision < NENO6_BF16) return NENO6_BAD_LAYOUT;
@@ -528,6 +606,19 @@ int32_t neno6_recheck_count(const neno6_problem *prob, const neno6_mlp *mlp, con
 int32_t neno6_autotune(const neno6_problem *prob, const neno6_mlp *mlp, const void *q, void *ws,
                        size_t ws_bytes, int32_t reps, neno6_tuning *best, float *best_ms,
                        hipStream_t stream) {
+  if (is_batch2d(prob)) {  // tuned on the grid with the most faces
+    if (!q) return NENO6_BAD_ARG;
+    neno6_problem big{};
+    int64_t most = -1, at_cells = 0;
+    if (int32_t c = for_each_grid(prob, [&](const neno6_problem &s, int32_t, int64_t cells, int64_t) {
+          const int64_t nf = (s.nx + 1) * s.ny + s.nx * (s.ny + 1);
+          if (nf > most) most = nf, big = s, at_cells = cells;
+          return NENO6_OK;
+        }))
+      return c;
+    return neno6_autotune(&big, mlp, at_elems(q, 4 * at_cells, elem_size(prob->precision)), ws,
+                          ws_bytes, reps, best, best_ms, stream);
+  }
   if (int32_t c = check_problem(prob)) return c;
   if (prob->precision < NENO6_BF16 || prob->selector != NENO6_SEL_MLP ||
       prob->equation <= NENO6_BURGERS)
@@ -633,6 +724,14 @@ int32_t neno6_autotune(const neno6_problem *prob, const neno6_mlp *mlp, const vo
 int32_t neno6_step(const neno6_problem *prob, const neno6_mlp *mlp, void *q, double cfl,
                    int32_t n_steps, double *t, int32_t *status, void *ws, size_t ws_bytes,
                    hipStream_t stream) {
+  if (is_batch2d(prob)) {
+    if (!q || !t || !status) return NENO6_BAD_ARG;
+    const size_t es = elem_size(prob->precision);
+    return for_each_grid(prob, [&](const neno6_problem &s, int32_t p, int64_t cells, int64_t) {
+      return neno6_step(&s, mlp, at_elems(q, 4 * cells, es), cfl, n_steps, t + p, status + p, ws,
+                        ws_bytes, stream);
+    });
+  }
   if (int32_t c = check_problem(prob)) return c;
   if (int32_t c = check_mlp(mlp, prob->selector, prob->precision)) return c;
   if (prob->selector == NENO6_SEL_MASKS_IN) return NENO6_UNSUPPORTED;
@@ -693,6 +792,14 @@ int32_t neno6_rhs_adjoint(const neno6_problem *prob, const uint8_t *masks, const
 }
 
 size_t neno6_vjp_workspace_size(const neno6_problem *prob) {
+  if (is_batch2d(prob)) {
+    size_t most = 0;
+    const int32_t c = for_each_grid(prob, [&](const neno6_problem &s, int32_t, int64_t, int64_t) {
+      most = std::max(most, neno6_vjp_workspace_size(&s));
+      return NENO6_OK;
+    });
+    return c == NENO6_OK ? most : 0;
+  }
   if (check_problem(prob) != NENO6_OK) return 0;
   if (prob->equation == NENO6_EULER2D) {
     const size_t nfx = (size_t)(prob->nx + 1) * prob->ny, nfy = (size_t)prob->nx * (prob->ny + 1);
@@ -707,6 +814,15 @@ size_t neno6_vjp_workspace_size(const neno6_problem *prob) {
 int32_t neno6_rhs_vjp(const neno6_problem *prob, const void *q, const uint8_t *masks,
                       const void *rbar, void *qbar, void *ws, size_t ws_bytes,
                       hipStream_t stream) {
+  if (is_batch2d(prob)) {
+    if (!q || !masks || !rbar || !qbar) return NENO6_BAD_ARG;
+    const size_t es = elem_size(prob->precision);
+    return for_each_grid(prob, [&](const neno6_problem &s, int32_t, int64_t cells, int64_t faces) {
+      return neno6_rhs_vjp(&s, at_elems(q, 4 * cells, es), masks + 4 * faces,
+                           at_elems(rbar, 4 * cells, es), at_elems(qbar, 4 * cells, es), ws,
+                           ws_bytes, stream);
+    });
+  }
   if (int32_t c = check_problem(prob)) return c;
   if (prob->equation == NENO6_ADVECTION) return NENO6_UNSUPPORTED;
   if (prob->precision != NENO6_FP64 && prob->precision != NENO6_FP32) return NENO6_BAD_LAYOUT;

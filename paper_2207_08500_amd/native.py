@@ -61,7 +61,11 @@ class ProblemStruct(C.Structure):
                 ("total_cells", C.c_int64), ("nx", C.c_int64), ("ny", C.c_int64),
                 ("offsets", C.c_void_p), ("offsets_host", C.c_void_p), ("dx", C.c_void_p),
                 ("dx2d", C.c_double), ("dy2d", C.c_double), ("gamma", C.c_double),
-                ("tuning", C.POINTER(TuningStruct))]
+                ("tuning", C.POINTER(TuningStruct)), ("grids_host", C.c_void_p)]
+
+
+class Grid2DStruct(C.Structure):
+    _fields_ = [("nx", C.c_int64), ("ny", C.c_int64), ("dx", C.c_double), ("dy", C.c_double)]
 
 
 _lock = threading.Lock()
@@ -212,13 +216,26 @@ class Problem:
 
     def __init__(self, equation: int, precision: int, selector: int = SEL_MLP, bc: int = TRANSMISSIVE,
                  offsets=None, dx=None, nx: int = 0, ny: int = 0, dx2d: float = 0.0,
-                 dy2d: float = 0.0, gamma: float = 1.4, device="cuda", tuning=None):
+                 dy2d: float = 0.0, gamma: float = 1.4, device="cuda", tuning=None, grids=None):
+        """1D: offsets[n+1] and dx[n] of the lines.  2D: one grid (nx, ny, dx2d,
+        dy2d), or a batch `grids` = [(nx, ny, dx, dy), ...] whose states,
+        masks and face fluxes follow one another grid by grid."""
         self.equation, self.precision, self.selector, self.bc = equation, precision, selector, bc
         self.gamma = float(gamma)
         self.flags = 0  # KEEP_MAP once the caller's workspace holds the face map
         self.tuning = None
         self.set_tuning(tuning)
-        if equation == EULER2D:
+        self.grids = None
+        if equation == EULER2D and grids is not None:
+            g = [(int(a), int(b), float(c), float(d)) for a, b, c, d in grids]
+            self.grids = (Grid2DStruct * len(g))(*[Grid2DStruct(*x) for x in g])
+            self.grid_list = g
+            self.n_problems = len(g)
+            self.total_cells = sum(a * b for a, b, _, _ in g)
+            self.nx = self.ny = 0
+            self.dx2d = self.dy2d = 0.0
+            self.offsets_host = self.offsets = self.dx = None
+        elif equation == EULER2D:
             self.nx, self.ny, self.dx2d, self.dy2d = int(nx), int(ny), float(dx2d), float(dy2d)
             self.n_problems = 1
             self.total_cells = self.nx * self.ny
@@ -247,6 +264,8 @@ class Problem:
 
     @property
     def n_faces(self) -> int:
+        if self.equation == EULER2D and self.grids is not None:
+            return sum((a + 1) * b + a * (b + 1) for a, b, _, _ in self.grid_list)
         if self.equation == EULER2D:
             return (self.nx + 1) * self.ny + self.nx * (self.ny + 1)
         return self.total_cells + self.n_problems
@@ -262,7 +281,8 @@ class Problem:
                              None if self.offsets_host is None else self.offsets_host.data_ptr(),
                              None if self.dx is None else self.dx.data_ptr(),
                              self.dx2d, self.dy2d, self.gamma,
-                             None if self.tuning is None else C.pointer(self.tuning))
+                             None if self.tuning is None else C.pointer(self.tuning),
+                             None if self.grids is None else C.addressof(self.grids))
 
     def workspace(self, device="cuda") -> torch.Tensor:
         nb = int(load().neno6_workspace_size(C.byref(self.struct())))

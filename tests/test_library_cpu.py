@@ -109,6 +109,21 @@ def test_host_argument_checks():
     p2.offsets_host = big.ctypes.data
     assert lib.neno6_workspace_size(C.byref(p2)) == 0
     assert lib.neno6_reconstruct(None, None, 10, 2, 0, 1, None, None, None, None) == native.BAD_ARG
+    # batches of 2D grids: workspace of the largest grid, every grid checked,
+    # no re-check counters and no allocation-free entry point for batches
+    g3 = [(67, 45, 1 / 67, 1 / 45), (130, 3, 1 / 130, 1 / 3), (64, 64, 1 / 64, 1 / 64)]
+    pb = native.Problem(native.EULER2D, native.FP16, grids=g3, device="cpu")
+    sizes = [native.Problem(native.EULER2D, native.FP16, nx=a, ny=b_, dx2d=c, dy2d=d,
+                            device="cpu") for a, b_, c, d in g3]
+    assert lib.neno6_workspace_size(C.byref(pb.struct())) == max(
+        lib.neno6_workspace_size(C.byref(x.struct())) for x in sizes)
+    assert pb.n_faces == sum(x.n_faces for x in sizes) and pb.total_cells == 67 * 45 + 130 * 3 + 64 * 64
+    bad = native.Problem(native.EULER2D, native.FP16, grids=g3 + [(0, 5, 0.1, 0.1)], device="cpu")
+    assert lib.neno6_workspace_size(C.byref(bad.struct())) == 0
+    cnt = (C.c_uint32 * 2)()
+    assert lib.neno6_recheck_count(C.byref(pb.struct()), None, None, 0, cnt, None) == native.UNSUPPORTED
+    assert lib.neno6_rhs_noalloc(C.byref(pb.struct()), None, None, None, None, None, None,
+                                 None) == native.UNSUPPORTED
     # re-check arithmetic: FP32 or two-part FP16 only (placeholders, never dereferenced)
     bad_mode = native.MlpStruct(1, 1, 0.5, 2)
     assert lib.neno6_mlp_logits(C.byref(bad_mode), native.FP16, C.c_void_p(1), 10, C.c_void_p(1), None,
