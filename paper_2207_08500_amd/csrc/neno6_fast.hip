@@ -92,17 +92,20 @@ template <int PREC> N6_DEV u32 relu_pack(float a, float b) { return relu2(pack2<
 // [0, 1] is the ReLU, because k_prepare scales every hidden neuron by an
 // a-priori bound on its pre-activation (ReLU(s z) = s ReLU(z) for s > 0, and
 // the scaled pre-activation never exceeds 1).  One instruction per pair of
-// activations instead of a conversion and a packed max.  The compiler emits
-// the clamped form only for FP16, so both are written as inline asm, one
-// block per accumulator tile, and the hazard waits the compiler would
-// otherwise insert are part of the block: before the first conversion the
-// MFMA that produced the tile must have written it back (NumPasses + 4 wait
-// states on gfx950: 20 after a 16-pass 32x32x8, 12 after an 8-pass
-// 32x32x16), and after the last one an MFMA may read the results only two
-// wait states later.  Outputs are early-clobber: the block reads its inputs
-// after it has written some outputs.
+// activations instead of a conversion and a packed max.
 //   act_block<PREC, NPAIR, WAIT>(c, first, o): o[p] = pack(c[first + 2p],
 //   c[first + 2p + 1]), activations applied.
+// FP16: plain code (a conversion followed by a clamp of the packed halves to
+// [0, 1], which the compiler folds into the conversion's clamp); the compiler
+// then places the MFMA -> VALU hazard waits itself and fills them with
+// independent work.  BF16: the compiler does not fold the clamp there, so the
+// blocks are inline asm, one per accumulator tile, with the hazard waits as
+// part of the block: before the first conversion the MFMA that produced the
+// tile must have written it back (NumPasses + 4 wait states on gfx950: 20
+// after a 16-pass 32x32x8, 12 after an 8-pass 32x32x16), and after the last
+// one an MFMA may read the results only two wait states later (WAIT: the
+// first of these).  Outputs are early-clobber: the block reads its inputs
+// after it has written some outputs.
 template <int PREC, int NPAIR, int WAIT> struct ActBlock;
 template <> struct ActBlock<2, 8, 20> {
   static N6_DEV void run(const f32x16 &c, int first, u32 *o) {
@@ -132,32 +135,15 @@ template <> struct ActBlock<2, 2, 12> {
                  : "v"(c[first + 0]), "v"(c[first + 1]), "v"(c[first + 2]), "v"(c[first + 3]));
   }
 };
-template <> struct ActBlock<3, 8, 20> {
+template <int NPAIR, int WAIT> struct ActBlock<3, NPAIR, WAIT> {
   static N6_DEV void run(const f32x16 &c, int first, u32 *o) {
-    asm volatile("s_nop 15\n\ts_nop 3\n\tv_cvt_pk_f16_f32 %0, %8, %9 clamp\n\tv_cvt_pk_f16_f32 %1, %10, %11 clamp\n\tv_cvt_pk_f16_f32 %2, %12, %13 clamp\n\tv_cvt_pk_f16_f32 %3, %14, %15 clamp\n\tv_cvt_pk_f16_f32 %4, %16, %17 clamp\n\tv_cvt_pk_f16_f32 %5, %18, %19 clamp\n\tv_cvt_pk_f16_f32 %6, %20, %21 clamp\n\tv_cvt_pk_f16_f32 %7, %22, %23 clamp\n\ts_nop 1"
-                 : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3]), "=&v"(o[4]), "=&v"(o[5]), "=&v"(o[6]), "=&v"(o[7])
-                 : "v"(c[first + 0]), "v"(c[first + 1]), "v"(c[first + 2]), "v"(c[first + 3]), "v"(c[first + 4]), "v"(c[first + 5]), "v"(c[first + 6]), "v"(c[first + 7]), "v"(c[first + 8]), "v"(c[first + 9]), "v"(c[first + 10]), "v"(c[first + 11]), "v"(c[first + 12]), "v"(c[first + 13]), "v"(c[first + 14]), "v"(c[first + 15]));
-  }
-};
-template <> struct ActBlock<3, 8, 12> {
-  static N6_DEV void run(const f32x16 &c, int first, u32 *o) {
-    asm volatile("s_nop 11\n\tv_cvt_pk_f16_f32 %0, %8, %9 clamp\n\tv_cvt_pk_f16_f32 %1, %10, %11 clamp\n\tv_cvt_pk_f16_f32 %2, %12, %13 clamp\n\tv_cvt_pk_f16_f32 %3, %14, %15 clamp\n\tv_cvt_pk_f16_f32 %4, %16, %17 clamp\n\tv_cvt_pk_f16_f32 %5, %18, %19 clamp\n\tv_cvt_pk_f16_f32 %6, %20, %21 clamp\n\tv_cvt_pk_f16_f32 %7, %22, %23 clamp\n\ts_nop 1"
-                 : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3]), "=&v"(o[4]), "=&v"(o[5]), "=&v"(o[6]), "=&v"(o[7])
-                 : "v"(c[first + 0]), "v"(c[first + 1]), "v"(c[first + 2]), "v"(c[first + 3]), "v"(c[first + 4]), "v"(c[first + 5]), "v"(c[first + 6]), "v"(c[first + 7]), "v"(c[first + 8]), "v"(c[first + 9]), "v"(c[first + 10]), "v"(c[first + 11]), "v"(c[first + 12]), "v"(c[first + 13]), "v"(c[first + 14]), "v"(c[first + 15]));
-  }
-};
-template <> struct ActBlock<3, 4, 12> {
-  static N6_DEV void run(const f32x16 &c, int first, u32 *o) {
-    asm volatile("s_nop 11\n\tv_cvt_pk_f16_f32 %0, %4, %5 clamp\n\tv_cvt_pk_f16_f32 %1, %6, %7 clamp\n\tv_cvt_pk_f16_f32 %2, %8, %9 clamp\n\tv_cvt_pk_f16_f32 %3, %10, %11 clamp\n\ts_nop 1"
-                 : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3])
-                 : "v"(c[first + 0]), "v"(c[first + 1]), "v"(c[first + 2]), "v"(c[first + 3]), "v"(c[first + 4]), "v"(c[first + 5]), "v"(c[first + 6]), "v"(c[first + 7]));
-  }
-};
-template <> struct ActBlock<3, 2, 12> {
-  static N6_DEV void run(const f32x16 &c, int first, u32 *o) {
-    asm volatile("s_nop 11\n\tv_cvt_pk_f16_f32 %0, %2, %3 clamp\n\tv_cvt_pk_f16_f32 %1, %4, %5 clamp\n\ts_nop 1"
-                 : "=&v"(o[0]), "=&v"(o[1])
-                 : "v"(c[first + 0]), "v"(c[first + 1]), "v"(c[first + 2]), "v"(c[first + 3]));
+    const f16x2 z = {0, 0}, one = {1, 1};
+#pragma unroll
+    for (int p = 0; p < NPAIR; ++p) {
+      const f32x2 v = {c[first + 2 * p], c[first + 2 * p + 1]};
+      const f16x2 h = __builtin_convertvector(v, f16x2);
+      o[p] = __builtin_bit_cast(u32, __builtin_elementwise_min(__builtin_elementwise_max(h, z), one));
+    }
   }
 };
 template <int PREC, int NPAIR, int WAIT>
