@@ -643,7 +643,6 @@ k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
       if constexpr (MLP) {
-        __builtin_amdgcn_sched_barrier(0);
         u32 xe[6];
         feature_pack<PREC>(sn, xe);
         if (e + 1 < NE) {
@@ -1101,7 +1100,6 @@ k_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float marg
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
       if constexpr (MLP) {
-        __builtin_amdgcn_sched_barrier(0);
         u32 xe[6];
         feature_pack<PREC>(sn, xe);
         if (e + 1 < NE) {
