@@ -55,12 +55,15 @@ typedef u32 u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int TPB = 256;
 constexpr int WPB = TPB / 64;
-constexpr int TAB_REGS = 92;
+constexpr int TAB_REGS = 112;
+// registers of the inference L3..L5 on v_mfma_f32_16x16x32 (the rows before
+// them: L1 / L2 and the training layout of L3..L5 and its biases)
+constexpr int R_T3 = 92, R_T4 = 96, R_T5 = 100, R_C3 = 104, R_C4 = 108;
 constexpr int TAB_BYTES = TAB_REGS * 64 * 4;
 constexpr int PREP_BF16_OFF = 16384;
 constexpr int PREP_F16_OFF = PREP_BF16_OFF + TAB_BYTES;
 constexpr int PREP_B5_OFF = PREP_F16_OFF + TAB_BYTES;
-constexpr int PREP_SCALE_OFF = 65536;  // per-neuron activation scales (FP64)
+constexpr int PREP_SCALE_OFF = 81920;  // per-neuron activation scales (FP64)
 constexpr int PREP_F4_OFF = 98304;     // FP32 16x16x4 operand table of the re-check (F4_REGS)
 constexpr int PREP_LO_OFF = 118784;    // FP16 remainder table of the two-part re-check (LO_REGS)
 constexpr size_t PREP_BYTES = 131072;
@@ -170,6 +173,44 @@ template <> N6_DEV f32x16 mma16<3>(u32x4 a, u32x4 b, f32x16 c) {
                                                 __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
 }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+template <int PREC> N6_DEV f32x4 mma4x(u32x4 a, u32x4 b, f32x4 c);
+template <> N6_DEV f32x4 mma4x<2>(u32x4 a, u32x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+template <> N6_DEV f32x4 mma4x<3>(u32x4 a, u32x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
+                                                __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+}
+
+// Activations of a 16x16 accumulator tile (four values a lane, two pairs),
+// as act_block: FP16 in plain code, BF16 as inline asm with the hazard waits
+// (a v_mfma_f32_16x16x32 needs fewer than the 12 wait states waited here).
+template <int PREC> N6_DEV void act4(const f32x4 &c, u32 *o);
+template <> N6_DEV void act4<3>(const f32x4 &c, u32 *o) {
+  const f16x2 z = {0, 0}, one = {1, 1};
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const f32x2 v = {c[2 * p], c[2 * p + 1]};
+    o[p] = __builtin_bit_cast(u32, __builtin_elementwise_min(
+                                       __builtin_elementwise_max(__builtin_convertvector(v, f16x2), z), one));
+  }
+}
+template <> N6_DEV void act4<2>(const f32x4 &c, u32 *o) {
+  asm volatile("s_nop 11\n\tv_cvt_pk_bf16_f32 %0, %2, %3 clamp\n\tv_cvt_pk_bf16_f32 %1, %4, %5 clamp\n\ts_nop 1"
+               : "=&v"(o[0]), "=&v"(o[1])
+               : "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]));
+}
+
+// Swap lanes 16..31 of x with lanes 0..15 of y, and lanes 48..63 of x with
+// lanes 32..47 of y.
+N6_DEV void swap16(u32 &x, u32 &y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+  x = r[0];
+  y = r[1];
+}
+
 // Swap lanes 32..63 of x with lanes 0..31 of y.
 N6_DEV void swap32(u32 &x, u32 &y) {
   const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
@@ -178,9 +219,22 @@ N6_DEV void swap32(u32 &x, u32 &y) {
 }
 
 // ---- classifier registers ------------------------------------------------------
+// Inference: L1 (K = 16, the features in two parts) and L2 on
+// v_mfma_f32_32x32x16, L3..L5 on v_mfma_f32_16x16x32 (operands t3, t4, t5,
+// biases c3, c4 in the 16x16 accumulator layout).
 struct Wts {
-  u32x2 a1[2];   // L1, K = 8 (the training forward)
   u32x4 a1x[2];  // L1, K = 16: the features' leading and trailing parts
+  u32x4 a2[4];
+  f32x16 b2;
+  u32x4 t3, t4, t5;
+  f32x4 c3, c4;
+  float b5[4];
+};
+
+// Training (BF16): L1 with K = 8 and L2..L5 on v_mfma_f32_32x32x*, the
+// layout its backward tables are permuted for.
+struct WtsT {
+  u32x2 a1[2];
   u32x4 a2[4], a3[2], a4, a5;
   f32x16 b2, b3, b4;
   float b5[4];
@@ -190,10 +244,30 @@ template <int PREC>
 N6_DEV void load_wts(const void *prepared, int lane, Wts &w) {
   const u32 *t = (const u32 *)((const char *)prepared + (PREC == 2 ? PREP_BF16_OFF : PREP_F16_OFF));
 #define N6R(r) t[(r)*64 + lane]
+#define N6R4(r) u32x4{N6R(r), N6R((r) + 1), N6R((r) + 2), N6R((r) + 3)}
+  w.a1x[0] = N6R4(84);
+  w.a1x[1] = N6R4(88);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) w.a2[s] = N6R4(4 + 4 * s);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) w.b2[r] = __builtin_bit_cast(float, N6R(36 + r));
+  w.t3 = N6R4(R_T3);
+  w.t4 = N6R4(R_T4);
+  w.t5 = N6R4(R_T5);
+  w.c3 = __builtin_bit_cast(f32x4, N6R4(R_C3));
+  w.c4 = __builtin_bit_cast(f32x4, N6R4(R_C4));
+#undef N6R4
+#undef N6R
+  const float *b5 = (const float *)((const char *)prepared + PREP_B5_OFF);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w.b5[k] = b5[k];
+}
+
+N6_DEV void load_wts_train(const void *prepared, int lane, WtsT &w) {
+  const u32 *t = (const u32 *)((const char *)prepared + PREP_BF16_OFF);
+#define N6R(r) t[(r)*64 + lane]
   w.a1[0] = u32x2{N6R(0), N6R(1)};
   w.a1[1] = u32x2{N6R(2), N6R(3)};
-  w.a1x[0] = u32x4{N6R(84), N6R(85), N6R(86), N6R(87)};
-  w.a1x[1] = u32x4{N6R(88), N6R(89), N6R(90), N6R(91)};
 #pragma unroll
   for (int s = 0; s < 4; ++s) w.a2[s] = u32x4{N6R(4 + 4 * s), N6R(5 + 4 * s), N6R(6 + 4 * s), N6R(7 + 4 * s)};
 #pragma unroll
@@ -212,10 +286,24 @@ N6_DEV void load_wts(const void *prepared, int lane, Wts &w) {
   for (int k = 0; k < 4; ++k) w.b5[k] = b5[k];
 }
 
-// L1..L4 of one 32-evaluation tile; `bin` is the L1 B operand (features
-// 4h..4h+3 of column j, with the constant 1 of the folded L1 bias in slot 6).
-// Returns the packed L4 activations: neurons 4h..4h+3 of column j (rows 8..31
-// of the L4 product are padding).
+// L1..L4 of one 32-evaluation tile; `bin` is the L1 B operand of lane (j, h)
+// (K slots 8h..8h+7 of column j: h = 0 the leading parts of the features and
+// the constant 1 of the folded L1 bias, h = 1 their trailing parts).
+//
+// L3..L4 run on v_mfma_f32_16x16x32 with the tile's columns in two blocks of
+// 16 (block A: columns 0..15, block B: 16..31).  Lane group G = l / 16 of a
+// 16x16x32 product supplies K slots 8G..8G+7 of column l % 16, and its
+// result holds rows 4G..4G+3 of that column.  After L2, lane (j, h) holds the
+// packed activations of L2 rows {8b + 4h + r} of column j in h2[0..7]
+// (X = h2[0..3]: b = 0, 1; Y = h2[4..7]: b = 2, 3); swapping X of groups 1, 3
+// with Y of groups 0, 2 gives every group block A's data in X and block B's
+// in Y, in the same K order for both blocks (group G: X or Y of h = G / 2),
+// which the L3 operand table follows.  L3 leaves neurons 4G..4G+3 of each
+// block in group G; L4 takes both blocks in one product, K slots 8G..8G+3
+// from block A and 8G+4..8G+7 from block B, with block A's eight neurons as
+// rows 0..7 and block B's as rows 8..15 (block-diagonal weights).  Returns
+// the packed L4 activations of group G: rows 4G..4G+3 (G = 0, 1: block A,
+// neurons 4G..4G+3; G = 2, 3: block B, neurons 4G-8..4G-5).
 template <int PREC>
 N6_DEV u32x2 mlp_front(const Wts &w, u32x4 bin) {
   const f32x16 zero = {};
@@ -230,13 +318,16 @@ N6_DEV u32x2 mlp_front(const Wts &w, u32x4 bin) {
   c2 = mma16<PREC>(w.a2[3], u32x4{h1b[4], h1b[5], h1b[6], h1b[7]}, c2);
   u32 h2[8];
   act_block<PREC, 8, 12>(c2, 0, h2);
-  f32x16 c3 = mma16<PREC>(w.a3[0], u32x4{h2[0], h2[1], h2[2], h2[3]}, w.b3);
-  c3 = mma16<PREC>(w.a3[1], u32x4{h2[4], h2[5], h2[6], h2[7]}, c3);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) swap16(h2[q], h2[4 + q]);
+  const f32x4 c3a = mma4x<PREC>(w.t3, u32x4{h2[0], h2[1], h2[2], h2[3]}, w.c3);
+  const f32x4 c3b = mma4x<PREC>(w.t3, u32x4{h2[4], h2[5], h2[6], h2[7]}, w.c3);
   u32 h3[4];
-  act_block<PREC, 4, 12>(c3, 0, h3);
-  const f32x16 c4 = mma16<PREC>(w.a4, u32x4{h3[0], h3[1], h3[2], h3[3]}, w.b4);
+  act4<PREC>(c3a, h3);
+  act4<PREC>(c3b, h3 + 2);
+  const f32x4 c4 = mma4x<PREC>(w.t4, u32x4{h3[0], h3[1], h3[2], h3[3]}, w.c4);
   u32 h4[2];
-  act_block<PREC, 2, 12>(c4, 0, h4);
+  act4<PREC>(c4, h4);
   return u32x2{h4[0], h4[1]};
 }
 
@@ -273,8 +364,9 @@ N6_DEV u32 mask_near(const float z[4], float margin) {
 }
 
 // Classifies the stencil held by every lane of the wave (all 64 lanes must
-// call it together).  Returns the lane's mask | near-flag << 4; with z != 0
-// also returns the lane's four logits.
+// call it together): tile 0 = the stencils of lanes 0..31, tile 1 = lanes
+// 32..63.  Returns the lane's mask | near-flag << 4; with z != 0 also returns
+// the lane's four logits.
 template <int PREC>
 N6_DEV u32 classify_packed(const Wts &w, const u32 xin[6], float margin, float *z_out) {
   // K slots of the first layer: lanes 0..31 carry the leading parts (slots
@@ -292,8 +384,12 @@ N6_DEV u32 classify_packed(const Wts &w, const u32 xin[6], float margin, float *
   const u32 cin = (threadIdx.x & 32) ? 0u : one_zero<PREC>();
   const u32x2 h0 = mlp_front<PREC>(w, u32x4{a[0], a[1], a[2], cin});
   const u32x2 h1 = mlp_front<PREC>(w, u32x4{b[0], b[1], b[2], cin});
-  const f32x16 zero = {};
-  const f32x16 c = mma16<PREC>(w.a5, u32x4{h0[0], h0[1], h1[0], h1[1]}, zero);
+  // L5 for the four 16-column blocks at once: K slots 8G..8G+3 from tile 0,
+  // 8G+4..8G+7 from tile 1 (each group's L4 rows), output rows 4B..4B+3 the
+  // logits of block B = (tile 0 A, tile 0 B, tile 1 A, tile 1 B): lane group G
+  // ends with the logits of the block its own stencil is in
+  const f32x4 zero = {};
+  const f32x4 c = mma4x<PREC>(w.t5, u32x4{h0[0], h0[1], h1[0], h1[1]}, zero);
   float z[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) z[k] = c[k] + w.b5[k];
@@ -553,7 +649,7 @@ constexpr int F4_A1 = 0, F4_A2 = 8, F4_A3 = 40, F4_A4 = 48, F4_A5 = 52, F4_B2 = 
 N6_DEV void mlp_f32_16(const float *tab, const float *b5, int lane, const float x[6], float z[4]);
 // Remainder table of the two-part FP16 re-check (registers of u32 pairs,
 // stored as [register / 4][lane][register % 4]).
-constexpr int LO_A1X = 0, LO_A2 = 8, LO_A3 = 24, LO_A4 = 32, LO_A5 = 36, LO_REGS = 40;
+constexpr int LO_A1X = 0, LO_A2 = 8, LO_T3 = 24, LO_T4 = 28, LO_S5A = 32, LO_S5B = 36, LO_REGS = 40;
 constexpr float SPLIT_SCALE = 256.f;
 N6_DEV void mlp_split32(const Wts &w, const u32 *lotab, int lane, u32x4 bin, float z[4]);
 // First-layer input of a two-part pass for lane (j, h) from the stencil of
@@ -797,7 +893,6 @@ N6_DEV float f4_table_value(const double *__restrict__ P, int reg, int lane) {
   return (float)x;
 }
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 N6_DEV f32x4 mma4(float a, float b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 N6_DEV f32x4 relu4(f32x4 c) {
 #pragma unroll
@@ -919,12 +1014,21 @@ N6_DEV void split_tile(const f32x16 &c, int f, u32 *hi, u32 *lo) {
     lo[p] = pack2<3>(a - h[0], b - h[1]);
   }
 }
+N6_DEV void split_quad(const f32x4 &c, u32 *hi, u32 *lo) {
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const float a = fmaxf(c[2 * p], 0.f), b = fmaxf(c[2 * p + 1], 0.f);
+    hi[p] = pack2<3>(a, b);
+    const f32x2 h = unpack2<3>(hi[p]);
+    lo[p] = pack2<3>(a - h[0], b - h[1]);
+  }
+}
 
 // Logits of the 32 evaluations of a pass: lane (j, h) holds K slots 8h..8h+7
 // of evaluation j's first-layer input (h = 0: leading parts of the features
 // and the bias input 1; h = 1: their trailing parts), as in the FP16
-// classifier; lanes 0..31 return the four logits.  lotab: the remainder
-// table (in LDS).
+// classifier; every lane returns the four logits of evaluation j.  lotab: the
+// remainder table (in LDS or through the caches).
 N6_DEV void mlp_split32(const Wts &w, const u32 *lotab, int lane, u32x4 bin, float z[4]) {
   // the scale hidden from the optimiser: the scaled biases are formed in the
   // pass, not hoisted out of the caller's tile loop (28 registers)
@@ -951,36 +1055,38 @@ N6_DEV void mlp_split32(const Wts &w, const u32 *lotab, int lane, u32x4 bin, flo
   }
   u32 h2[8], l2[8];
   split_tile<8>(c2, 0, h2, l2);
-  f32x16 c3 = w.b3;  // registers 8..15: padding rows (bias 0)
+  // L3..L5 on 16x16x32 as in mlp_front, each product in three parts
 #pragma unroll
-  for (int r = 0; r < 8; ++r) c3[r] *= S;
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    const u32x4 H = {h2[4 * s], h2[4 * s + 1], h2[4 * s + 2], h2[4 * s + 3]};
-    const u32x4 L = {l2[4 * s], l2[4 * s + 1], l2[4 * s + 2], l2[4 * s + 3]};
-    c3 = mma16<3>(w.a3[s], H, c3);
-    c3 = mma16<3>(w.a3[s], L, c3);
-    c3 = mma16<3>(lt[(LO_A3 / 4 + s) * 64], H, c3);
+  for (int q = 0; q < 4; ++q) {
+    swap16(h2[q], h2[4 + q]);
+    swap16(l2[q], l2[4 + q]);
   }
+  const u32x4 t3lo = lt[(LO_T3 / 4) * 64], t4lo = lt[(LO_T4 / 4) * 64];
+  f32x4 c3[2];
   u32 h3[4], l3[4];
-  split_tile<4>(c3, 0, h3, l3);
-  f32x16 c4 = w.b4;  // registers 4..15: padding rows
 #pragma unroll
-  for (int r = 0; r < 4; ++r) c4[r] *= S;
+  for (int b = 0; b < 2; ++b) {
+    const u32x4 H = {h2[4 * b], h2[4 * b + 1], h2[4 * b + 2], h2[4 * b + 3]};
+    const u32x4 L = {l2[4 * b], l2[4 * b + 1], l2[4 * b + 2], l2[4 * b + 3]};
+    c3[b] = w.c3 * S;
+    c3[b] = mma4x<3>(w.t3, H, c3[b]);
+    c3[b] = mma4x<3>(w.t3, L, c3[b]);
+    c3[b] = mma4x<3>(t3lo, H, c3[b]);
+    split_quad(c3[b], h3 + 2 * b, l3 + 2 * b);
+  }
+  f32x4 c4 = w.c4 * S;
   {
     const u32x4 H = {h3[0], h3[1], h3[2], h3[3]}, L = {l3[0], l3[1], l3[2], l3[3]};
-    c4 = mma16<3>(w.a4, H, c4);
-    c4 = mma16<3>(w.a4, L, c4);
-    c4 = mma16<3>(lt[(LO_A4 / 4) * 64], H, c4);
+    c4 = mma4x<3>(w.t4, H, c4);
+    c4 = mma4x<3>(w.t4, L, c4);
+    c4 = mma4x<3>(t4lo, H, c4);
   }
   u32 h4[2], l4[2];
-  split_tile<2>(c4, 0, h4, l4);
-  // output layer: K slots 8h..8h+3 the leading parts of L4 rows 4h..4h+3,
-  // 8h+4..8h+7 their trailing parts; rows 0..3 of the FP16 table's product
-  // take the leading parts, the remainder table's rows 0..3 the cross terms
+  split_quad(c4, h4, l4);
   const u32x4 B5 = {h4[0], h4[1], l4[0], l4[1]};
-  f32x16 c5 = mma16<3>(w.a5, B5, zero);
-  c5 = mma16<3>(lt[(LO_A5 / 4) * 64], B5, c5);
+  const f32x4 zero4 = {};
+  f32x4 c5 = mma4x<3>(lt[(LO_S5A / 4) * 64], B5, zero4);
+  c5 = mma4x<3>(lt[(LO_S5B / 4) * 64], B5, c5);
 #pragma unroll
   for (int k = 0; k < 4; ++k) z[k] = c5[k] * (1.f / SPLIT_SCALE) + w.b5[k];
 }
@@ -1493,14 +1599,14 @@ __global__ void __launch_bounds__(64) k_prepare_scales(const double *__restrict_
 // weights are W_oi s_i / s_o (s_i = 1 for the six features), its bias b_o /
 // s_o, and the output layer's weights W5_ki s_i; without S (the training
 // tables) the plain weights.
-// FP64 value of element q2 (0, 1) of weight register reg (reg < 36 or reg >=
-// 84; the bias registers 36..83 excluded) of lane `lane` of the BF16/FP16
+// FP64 value of element q2 (0, 1) of weight register reg (reg < 36 or 84 <=
+// reg < R_C3; the bias registers excluded) of lane `lane` of the BF16/FP16
 // operand table, scaled by S (nullptr: unscaled).
 N6_DEV double tab_value(const double *__restrict__ P, const double *__restrict__ S, int reg, int lane,
                         int q2) {
   auto sc = [&](int base, int i) { return S ? S[base + i] : 1.0; };
   const int i = lane % 32, h = lane / 32;
-  if (reg >= 84) {
+  if (reg >= 84 && reg < R_T3) {
     // L1 with K = 16: lanes (i, 0) slots 0..7 = W1 row o on the leading
     // parts, b1 on the bias input; lanes (i, 1) slots 8..15 = W1 row o on the
     // trailing parts
@@ -1528,9 +1634,25 @@ N6_DEV double tab_value(const double *__restrict__ P, const double *__restrict__
     const int n3 = 8 * (e / 4) + 4 * h + e % 4;
     return i < 8 ? P[OW4 + i * 16 + n3] * sc(SC3, n3) / sc(SC4, i) : 0.0;
   }
-  // L5: K slots e < 4 carry tile 0 (rows 0..3), e >= 4 tile 1 (rows 4..7)
-  const int e = 2 * (reg - 32) + q2, t5 = e / 4, n4 = 4 * h + e % 4;
-  return i / 4 == t5 ? P[OW5 + (i % 4) * 8 + n4] * sc(SC4, n4) : 0.0;
+  if (reg < 36) {  // L5: K slots e < 4 carry tile 0 (rows 0..3), e >= 4 tile 1 (rows 4..7)
+    const int e = 2 * (reg - 32) + q2, t5 = e / 4, n4 = 4 * h + e % 4;
+    return i / 4 == t5 ? P[OW5 + (i % 4) * 8 + n4] * sc(SC4, n4) : 0.0;
+  }
+  // inference L3..L5 on 16x16x32: lane (m, G) = (lane % 16, lane / 16), K
+  // slot 8G + tt of the A operand, tt = 2 (reg % 4) + q2
+  const int m = lane % 16, G = lane / 16, tt = 2 * ((reg - R_T3) % 4) + q2;
+  if (reg < R_T4) {  // L3: row m; K slot -> L2 row of X / Y of h = G / 2
+    const int ii = tt + 8 * (G % 2), n2 = 8 * (ii / 4) + 4 * (G / 2) + ii % 4;
+    return P[OW3 + m * 32 + n2] * sc(SC2, n2) / sc(SC3, m);
+  }
+  if (reg < R_T5) {  // L4, both blocks: rows m < 8 block A, m >= 8 block B
+    const int n3 = 4 * G + tt % 4;
+    return (tt < 4) == (m < 8) ? P[OW4 + (m % 8) * 16 + n3] * sc(SC3, n3) / sc(SC4, m % 8) : 0.0;
+  }
+  // L5, four blocks: row m = 4 B + k, block B = 2 tile + half; K slot 8G + tt
+  // holds tile tt / 4, half G / 2, L4 neuron 4 (G % 2) + tt % 4
+  const int blk = m / 4, n4 = 4 * (G % 2) + tt % 4;
+  return (tt / 4 == blk / 2 && G / 2 == blk % 2) ? P[OW5 + (m % 4) * 8 + n4] * sc(SC4, n4) : 0.0;
 }
 
 // FP16 value of x and what that rounding leaves, rounded to FP16 again.
@@ -1541,20 +1663,24 @@ N6_DEV f32x2 f16_parts(double x) {
 
 // Register reg of lane `lane` of the remainder table (LO_* layout): the
 // FP16 remainders of the scaled weights, in the operand order of the FP16
-// table's register it pairs with; LO_A5 is the one-tile output layer (rows
-// 0..3: remainder weights on the leading parts, FP16 weights on the
-// remainders of the L4 activations).
+// table's register it pairs with (L1, L2, and L3 / L4 on 16x16x32); LO_S5A /
+// LO_S5B the output layer of one 32-evaluation tile on 16x16x32: K slots
+// 8G..8G+3 the leading parts, 8G+4..8G+7 the trailing parts of lane group
+// G's L4 rows (block G / 2, neurons 4 (G % 2)..), output rows 4B..4B+3 the
+// logits of block B % 2; S5A the FP16 weights on both parts, S5B the
+// remainder weights on the leading parts.
 N6_DEV u32 lo_table_value(const double *__restrict__ P, const double *__restrict__ S, int reg,
                           int lane) {
   float v[2];
   for (int q2 = 0; q2 < 2; ++q2) {
-    if (reg < LO_A5) {
-      const int m = reg < LO_A2 ? 84 + reg : (reg < LO_A3 ? 4 + reg - LO_A2 : (reg < LO_A4 ? 20 + reg - LO_A3 : 28 + reg - LO_A4));
+    if (reg < LO_S5A) {
+      const int m = reg < LO_A2 ? 84 + reg : (reg < LO_T3 ? 4 + reg - LO_A2 : (reg < LO_T4 ? R_T3 + reg - LO_T3 : R_T4 + reg - LO_T4));
       v[q2] = f16_parts(tab_value(P, S, m, lane, q2))[1];
     } else {
-      const int i = lane % 32, h = lane / 32, e = 2 * (reg - LO_A5) + q2, n4 = 4 * h + e % 4;
-      const f32x2 w = i < 4 ? f16_parts(P[OW5 + i * 8 + n4] * S[SC4 + n4]) : f32x2{0.f, 0.f};
-      v[q2] = e < 4 ? w[1] : w[0];
+      const int m = lane % 16, G = lane / 16, tt = 2 * (reg % 4) + q2, n4 = 4 * (G % 2) + tt % 4;
+      const f32x2 w = (G / 2 == (m / 4) % 2) ? f16_parts(P[OW5 + (m % 4) * 8 + n4] * S[SC4 + n4])
+                                             : f32x2{0.f, 0.f};
+      v[q2] = reg < LO_S5B ? w[0] : (tt < 4 ? w[1] : 0.f);
     }
   }
   return pack2<3>(v[0], v[1]);
@@ -1578,10 +1704,16 @@ N6_DEV void prepare_entry(const double *__restrict__ P, const double *__restrict
   if (t >= TAB_REGS * 64) return;
   const int reg = t / 64, lane = t % 64, h = lane / 32;
   u32 wb, wh;
-  if (reg < 36 || reg >= 84) {
+  if (reg < 36 || (reg >= 84 && reg < R_C3)) {
     const float v0 = (float)tab_value(P, S, reg, lane, 0), v1 = (float)tab_value(P, S, reg, lane, 1);
     wb = pack2<2>(v0, v1);
     wh = pack2<3>(v0, v1);
+  } else if (reg >= R_C3) {
+    // biases of the 16x16 tiles: register r of lane group G is row 4G + r
+    auto sc = [&](int base, int i) { return S ? S[base + i] : 1.0; };
+    const int row = 4 * (lane / 16) + (reg - R_C3) % 4;
+    const double x = reg < R_C4 ? P[OB3 + row] / sc(SC3, row) : P[OB4 + row % 8] / sc(SC4, row % 8);
+    wb = wh = __builtin_bit_cast(u32, (float)x);
   } else {
     // bias tuples: C register r of lane (j, h) is row 8(r/4) + 4h + r%4
     auto sc = [&](int base, int i) { return S ? S[base + i] : 1.0; };
@@ -1714,8 +1846,8 @@ k_grad_mfma(const void *__restrict__ prepared, const u32 *__restrict__ btab,
   __shared__ __attribute__((aligned(16))) __bf16 Ta[WPB][64][32];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, j = lane & 31, h = lane >> 5;
   const int wid = blockIdx.x * WPB + wv;
-  Wts w;
-  load_wts<2>(prepared, lane, w);
+  WtsT w;
+  load_wts_train(prepared, lane, w);
   u32x2 bt5, bt4;
   u32x4 bt3, bt2[2][2];
   bt5 = u32x2{btab[0 * 64 + lane], btab[1 * 64 + lane]};
