@@ -96,49 +96,27 @@ template <int PREC> N6_DEV u32 relu_pack(float a, float b) { return relu2(pack2<
 // a-priori bound on its pre-activation (ReLU(s z) = s ReLU(z) for s > 0, and
 // the scaled pre-activation never exceeds 1).  One instruction per pair of
 // activations instead of a conversion and a packed max.
-//   act_block<PREC, NPAIR, WAIT>(c, first, o): o[p] = pack(c[first + 2p],
+//   act_block<PREC, NPAIR>(c, first, o): o[p] = pack(c[first + 2p],
 //   c[first + 2p + 1]), activations applied.
 // FP16: plain code (a conversion followed by a clamp of the packed halves to
 // [0, 1], which the compiler folds into the conversion's clamp); the compiler
 // then places the MFMA -> VALU hazard waits itself and fills them with
 // independent work.  BF16: the compiler does not fold the clamp there, so the
-// blocks are inline asm, one per accumulator tile, with the hazard waits as
-// part of the block: before the first conversion the MFMA that produced the
-// tile must have written it back (NumPasses + 4 wait states on gfx950: 20
-// after a 16-pass 32x32x8, 12 after an 8-pass 32x32x16), and after the last
-// one an MFMA may read the results only two wait states later (WAIT: the
-// first of these).  Outputs are early-clobber: the block reads its inputs
-// after it has written some outputs.
-template <int PREC, int NPAIR, int WAIT> struct ActBlock;
-template <> struct ActBlock<2, 8, 20> {
-  static N6_DEV void run(const f32x16 &c, int first, u32 *o) {
-    asm volatile("s_nop 15\n\ts_nop 3\n\tv_cvt_pk_bf16_f32 %0, %8, %9 clamp\n\tv_cvt_pk_bf16_f32 %1, %10, %11 clamp\n\tv_cvt_pk_bf16_f32 %2, %12, %13 clamp\n\tv_cvt_pk_bf16_f32 %3, %14, %15 clamp\n\tv_cvt_pk_bf16_f32 %4, %16, %17 clamp\n\tv_cvt_pk_bf16_f32 %5, %18, %19 clamp\n\tv_cvt_pk_bf16_f32 %6, %20, %21 clamp\n\tv_cvt_pk_bf16_f32 %7, %22, %23 clamp\n\ts_nop 1"
-                 : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3]), "=&v"(o[4]), "=&v"(o[5]), "=&v"(o[6]), "=&v"(o[7])
-                 : "v"(c[first + 0]), "v"(c[first + 1]), "v"(c[first + 2]), "v"(c[first + 3]), "v"(c[first + 4]), "v"(c[first + 5]), "v"(c[first + 6]), "v"(c[first + 7]), "v"(c[first + 8]), "v"(c[first + 9]), "v"(c[first + 10]), "v"(c[first + 11]), "v"(c[first + 12]), "v"(c[first + 13]), "v"(c[first + 14]), "v"(c[first + 15]));
-  }
-};
-template <> struct ActBlock<2, 8, 12> {
+// block is inline asm with the hazard waits as part of it: before the first
+// conversion the 8-pass v_mfma_f32_32x32x16 that produced the tile must have
+// written it back (NumPasses + 4 = 12 wait states on gfx950), and after the
+// last one an MFMA may read the results only two wait states later.  Outputs
+// are early-clobber: the block reads its inputs after it has written some
+// outputs.
+template <int PREC, int NPAIR> struct ActBlock;
+template <> struct ActBlock<2, 8> {
   static N6_DEV void run(const f32x16 &c, int first, u32 *o) {
     asm volatile("s_nop 11\n\tv_cvt_pk_bf16_f32 %0, %8, %9 clamp\n\tv_cvt_pk_bf16_f32 %1, %10, %11 clamp\n\tv_cvt_pk_bf16_f32 %2, %12, %13 clamp\n\tv_cvt_pk_bf16_f32 %3, %14, %15 clamp\n\tv_cvt_pk_bf16_f32 %4, %16, %17 clamp\n\tv_cvt_pk_bf16_f32 %5, %18, %19 clamp\n\tv_cvt_pk_bf16_f32 %6, %20, %21 clamp\n\tv_cvt_pk_bf16_f32 %7, %22, %23 clamp\n\ts_nop 1"
                  : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3]), "=&v"(o[4]), "=&v"(o[5]), "=&v"(o[6]), "=&v"(o[7])
                  : "v"(c[first + 0]), "v"(c[first + 1]), "v"(c[first + 2]), "v"(c[first + 3]), "v"(c[first + 4]), "v"(c[first + 5]), "v"(c[first + 6]), "v"(c[first + 7]), "v"(c[first + 8]), "v"(c[first + 9]), "v"(c[first + 10]), "v"(c[first + 11]), "v"(c[first + 12]), "v"(c[first + 13]), "v"(c[first + 14]), "v"(c[first + 15]));
   }
 };
-template <> struct ActBlock<2, 4, 12> {
-  static N6_DEV void run(const f32x16 &c, int first, u32 *o) {
-    asm volatile("s_nop 11\n\tv_cvt_pk_bf16_f32 %0, %4, %5 clamp\n\tv_cvt_pk_bf16_f32 %1, %6, %7 clamp\n\tv_cvt_pk_bf16_f32 %2, %8, %9 clamp\n\tv_cvt_pk_bf16_f32 %3, %10, %11 clamp\n\ts_nop 1"
-                 : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3])
-                 : "v"(c[first + 0]), "v"(c[first + 1]), "v"(c[first + 2]), "v"(c[first + 3]), "v"(c[first + 4]), "v"(c[first + 5]), "v"(c[first + 6]), "v"(c[first + 7]));
-  }
-};
-template <> struct ActBlock<2, 2, 12> {
-  static N6_DEV void run(const f32x16 &c, int first, u32 *o) {
-    asm volatile("s_nop 11\n\tv_cvt_pk_bf16_f32 %0, %2, %3 clamp\n\tv_cvt_pk_bf16_f32 %1, %4, %5 clamp\n\ts_nop 1"
-                 : "=&v"(o[0]), "=&v"(o[1])
-                 : "v"(c[first + 0]), "v"(c[first + 1]), "v"(c[first + 2]), "v"(c[first + 3]));
-  }
-};
-template <int NPAIR, int WAIT> struct ActBlock<3, NPAIR, WAIT> {
+template <int NPAIR> struct ActBlock<3, NPAIR> {
   static N6_DEV void run(const f32x16 &c, int first, u32 *o) {
     const f16x2 z = {0, 0}, one = {1, 1};
 #pragma unroll
@@ -149,9 +127,9 @@ template <int NPAIR, int WAIT> struct ActBlock<3, NPAIR, WAIT> {
     }
   }
 };
-template <int PREC, int NPAIR, int WAIT>
+template <int PREC, int NPAIR>
 N6_DEV void act_block(const f32x16 &c, int first, u32 *o) {
-  ActBlock<PREC, NPAIR, WAIT>::run(c, first, o);
+  ActBlock<PREC, NPAIR>::run(c, first, o);
 }
 
 template <int PREC> N6_DEV f32x16 mma8(u32x2 a, u32x2 b, f32x16 c);
@@ -310,14 +288,14 @@ N6_DEV u32x2 mlp_front(const Wts &w, u32x4 bin) {
   const f32x16 c1a = mma16<PREC>(w.a1x[0], bin, zero);
   const f32x16 c1b = mma16<PREC>(w.a1x[1], bin, zero);
   u32 h1a[8], h1b[8];
-  act_block<PREC, 8, 20>(c1a, 0, h1a);
-  act_block<PREC, 8, 20>(c1b, 0, h1b);
+  act_block<PREC, 8>(c1a, 0, h1a);
+  act_block<PREC, 8>(c1b, 0, h1b);
   f32x16 c2 = mma16<PREC>(w.a2[0], u32x4{h1a[0], h1a[1], h1a[2], h1a[3]}, w.b2);
   c2 = mma16<PREC>(w.a2[1], u32x4{h1a[4], h1a[5], h1a[6], h1a[7]}, c2);
   c2 = mma16<PREC>(w.a2[2], u32x4{h1b[0], h1b[1], h1b[2], h1b[3]}, c2);
   c2 = mma16<PREC>(w.a2[3], u32x4{h1b[4], h1b[5], h1b[6], h1b[7]}, c2);
   u32 h2[8];
-  act_block<PREC, 8, 12>(c2, 0, h2);
+  act_block<PREC, 8>(c2, 0, h2);
 #pragma unroll
   for (int q = 0; q < 4; ++q) swap16(h2[q], h2[4 + q]);
   const f32x4 c3a = mma4x<PREC>(w.t3, u32x4{h2[0], h2[1], h2[2], h2[3]}, w.c3);
