@@ -162,7 +162,8 @@ def test_paper_burgers_cases(ctx, case, selector):
         if selector == 4:  # TENO6-opt labels are decided in FP64: the runs stay together
             assert abs(tr - t64) < 1e-4 * t64 and l1 < 1e-4
         else:
-            # a classifier label near its cutoff follows the rounding of the state;
-            # over ~2000 steps of colliding shocks a flipped label moves the
-            # shocks (and the CFL steps) by a little
-            assert abs(tr - t64) < 0.05 * t64 and l1 < 0.1
+            # a classifier label near its cutoff follows the rounding of the
+            # state; over ~2000 steps of colliding shocks a flipped label can
+            # move a shock by a fraction of a cell (about 1e-3 of the L1 norm
+            # on these grids; the runs differ by 6e-5 at most)
+            assert abs(tr - t64) < 1e-3 * t64 and l1 < 1e-3

@@ -221,9 +221,12 @@ def test_euler1d_steps_error(ctx, prec):
         a, b = off[p], off[p + 1]
         l1 = np.abs(qf[:, a:b] - q_o[:, a:b]).mean(axis=1) / np.abs(q_o[:, a:b]).mean(axis=1)
         print("prec %d problem %d relative L1 %s" % (prec, p, l1))
-        assert np.all(l1 < 1e-2)
-    # the CFL step follows the largest wave speed of the (slightly different) state
-    assert np.allclose(host(t), t_o, rtol=1e-2)
+        # FP32 state rounding over 20 steps (a few 1e-7 relative per step);
+        # a label flipped near a shock would move a few cells by O(1e-3) of
+        # the jump, about 1e-5 of the L1 norm of a 256-cell line
+        assert np.all(l1 < 1e-4)
+    # the CFL step follows the largest wave speed of the (FP32-rounded) state
+    assert np.allclose(host(t), t_o, rtol=1e-5)
 
 
 @pytest.mark.parametrize("prec", [2, 3])

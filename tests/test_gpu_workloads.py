@@ -81,6 +81,9 @@ def test_c1_advection_full_run(ctx, prec):
     d = np.abs(out[prec] - out[native.FP64])
     l1 = d.mean() / np.abs(out[native.FP64]).mean()
     print("C1 prec %d: relative L1 %.3g, Linf %.3g" % (prec, l1, d.max()))
-    assert l1 < 1e-2
+    # FP32 state only: rounding over 500 steps (1.6e-5); BF16 / FP16
+    # classifier: a label decided differently early in the run moves the
+    # whole solution by a few 1e-4 (2.8e-4 for both with the committed weights)
+    assert l1 < {1: 1e-4, 2: 2e-3, 3: 2e-3}[prec]
     # conservation on the periodic line, FP32 state
     assert abs(out[prec].sum() - u0.sum()) < 1e-3 * np.abs(u0).sum()
