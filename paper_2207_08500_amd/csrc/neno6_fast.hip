@@ -1087,25 +1087,45 @@ N6_DEV void mlp_split32(const Wts &w, const u32 *lotab, int lane, u32x4 bin, flo
 // of a percent of the evaluations are near, about one per tile.
 
 // Output of cell kc of the line of fa, between fluxes Fl (left face) and Fr.
-N6_DEV void cell_out(const Line1D &ln, const Out1D &out, const Face1 &fa, int kc, const float qc[3],
-                     float pc, const float Fl[3], const float Fr[3]) {
+// What cell_out needs from memory besides the fluxes: the line's spacing and
+// time step, its frozen flag and (RK3 stages 2 and 3) the cell's state at
+// the start of the step; loaded by the lanes that own a cell, early, so that
+// the loads' latency overlaps the combine.
+struct CellIn {
+  float dx = 1.f, dt = 0.f, u0[3] = {0.f, 0.f, 0.f};
+  bool frozen = false;
+};
+N6_DEV CellIn cell_in(const Line1D &ln, const Out1D &out, const Face1 &fa, int kc) {
+  CellIn ci;
+  if (out.mode == OUT_FACES) return ci;
+  const int64_t c = (int64_t)fa.o + kc;
+  ci.dx = (float)ln.dx[fa.p];
+  if (out.mode == OUT_RHS) return ci;
+  ci.frozen = out.frozen[fa.p] != 0;
+  ci.dt = (float)out.dt[fa.p];
+  if (out.stage != 1) {
+#pragma unroll
+    for (int v = 0; v < 3; ++v) ci.u0[v] = out.u0[v * ln.total + c];
+  }
+  return ci;
+}
+
+N6_DEV void cell_out(const Line1D &ln, const Out1D &out, const Face1 &fa, int kc, const CellIn &ci,
+                     const float qc[3], float pc, const float Fl[3], const float Fr[3]) {
 #pragma clang fp contract(off)
   if (out.mode == OUT_FACES) return;
   const int64_t c = (int64_t)fa.o + kc;
-  const float dx = (float)ln.dx[fa.p];
   if (out.mode == OUT_RHS) {
 #pragma unroll
-    for (int v = 0; v < 3; ++v) out.dst[v * ln.total + c] = (Fl[v] - Fr[v]) / dx;
+    for (int v = 0; v < 3; ++v) out.dst[v * ln.total + c] = (Fl[v] - Fr[v]) / ci.dx;
     if (out.status && !physical<float>(qc[0], pc)) out.status[fa.p] = ST_NONPHYSICAL;
     return;
   }
-  const bool frozen = out.frozen[fa.p] != 0;
-  const float dt = (float)out.dt[fa.p];
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
-    const float L = (Fl[v] - Fr[v]) / dx;
-    const float u0 = out.stage == 1 ? qc[v] : out.u0[v * ln.total + c];
-    out.dst[v * ln.total + c] = frozen ? u0 : rk3<float>(out.stage, qc[v], u0, L, dt);
+    const float L = (Fl[v] - Fr[v]) / ci.dx;
+    const float u0 = out.stage == 1 ? qc[v] : ci.u0[v];
+    out.dst[v * ln.total + c] = ci.frozen ? u0 : rk3<float>(out.stage, qc[v], u0, L, ci.dt);
   }
 }
 
@@ -1113,8 +1133,10 @@ N6_DEV void cell_out(const Line1D &ln, const Out1D &out, const Face1 &fa, int kc
 // slot (workgroup * waves + wave) % NRECHECK_SLOTS, so few waves share one.
 constexpr int NRECHECK_SLOTS = QCOUNTERS;
 
-// The fused 1D Euler pass.  Three waves per SIMD (a few registers spill; the
-// third wave hides more of the MFMA -> convert -> MFMA latency).
+// The fused 1D Euler pass.  Three waves per SIMD (167 registers, no spills;
+// the third wave hides more of the MFMA -> convert -> MFMA latency).  The
+// cell's line data and the stage's u0 are loaded before the combine, so their
+// latency overlaps it.
 //
 // Flat faces (six equal cells): every split stencil is constant, and the
 // re-normalised combination of a constant stencil is that constant for every
@@ -1266,6 +1288,17 @@ k_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float marg
         nre += (u32)nnear;
       }
     }
+    Face1 fa;
+    fa.p = flat ? -1 - pl : pl;
+    {
+      const int64_t o = ln.offsets[fa.p];
+      fa.o = (uint32_t)o;
+      fa.n = (int)(ln.offsets[fa.p + 1] - o);
+      fa.k = (int)((valid ? g : nf - 1) - o - fa.p);
+    }
+    const bool own_cell = valid && lane < 63 && fa.k < fa.n;
+    CellIn ci;
+    if (own_cell) ci = cell_in(ln, out, fa, fa.k);
     float hs[3], F[3], R[3][3];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
@@ -1286,22 +1319,13 @@ k_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float marg
 #pragma unroll
     for (int v = 0; v < 3; ++v) qc[v] = stash[wv][S_QC + v][lane];
     const float pc = stash[wv][S_QC + 3][lane];
-    Face1 fa;
-    fa.p = flat ? -1 - pl : pl;
-    {
-      const int64_t o = ln.offsets[fa.p];
-      fa.o = (uint32_t)o;
-      fa.n = (int)(ln.offsets[fa.p + 1] - o);
-      fa.k = (int)((valid ? g : nf - 1) - o - fa.p);
-    }
     // the next face's flux: every lane takes part in the shuffle (a lane
     // outside a conditional would supply no value)
     float Fr[3];
 #pragma unroll
     for (int v = 0; v < 3; ++v) Fr[v] = __shfl_down(F[v], 1);
     const bool own_face = valid && (lane < 63 || t == ntile - 1);
-    const bool own_cell = valid && lane < 63 && fa.k < fa.n;
-    if (own_cell) cell_out(ln, out, fa, fa.k, qc, pc, F, Fr);
+    if (own_cell) cell_out(ln, out, fa, fa.k, ci, qc, pc, F, Fr);
     if (own_face) {
       if (out.mode == OUT_FACES) {
 #pragma unroll
