@@ -72,20 +72,57 @@ METRIC = "reconstructed faces/s: plain FP64 vs BF16-MFMA NENO6 at stated flip ra
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "euler1d_c4_4096_uneven_hbm_traffic.md")
 
 
+def _strip_comments(text):
+    """C++ source text without its comments (string and character literals
+    kept) and with every run of white space collapsed to one blank."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            out.append(" ")
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
+def code_digest(paths, read=None):
+    """SHA-256 over the given sources (paths relative to the repository root)
+    with comments and layout removed: it changes when the code changes, not
+    when a comment does."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in paths:
+        if read is None:
+            with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+                text = fh.read()
+        else:
+            text = read(f)
+        h.update(_strip_comments(text).encode())
+        h.update(b"\0")
+    return h.hexdigest()
+
+
 def _traffic_record():
     """The committed FETCH_SIZE / WRITE_SIZE record of the fused kernel on the
     4096-problem batch (HBM bytes per launch scaled by the copy-kernel
     calibration, and the launch shape the counters were taken with), or None
-    when the kernel sources changed since the counters were taken."""
-    import hashlib
+    when the kernel code changed since the counters were taken."""
     try:
         line = [ln for ln in open(TRAFFIC_RECORD) if ln.startswith("traffic-record:")][0]
         rec = json.loads(line.split(":", 1)[1])
-        h = hashlib.sha256()
-        for f in rec["sources"]:
-            with open(os.path.join(ROOT, f), "rb") as fh:
-                h.update(fh.read())
-        return rec if h.hexdigest() == rec["source_sha256"] else None
+        return rec if code_digest(rec["sources"]) == rec["code_sha256"] else None
     except (OSError, IndexError, KeyError, ValueError):
         return None
 

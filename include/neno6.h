@@ -142,8 +142,8 @@ typedef struct neno6_grid2d {
  *                  iteration.
  *  face_blocks:    workgroups of the fused face kernel, which loop over the
  *                  64-face tiles (grid-stride); at most 65536.
- *  recheck_blocks: reserved, 0..65536 and otherwise ignored: the FP32
- *                  re-check runs inside the face kernels.
+ *  recheck_blocks: reserved, 0..65536 and otherwise ignored: the re-check
+ *                  runs inside the face kernels.
  *  xcd_order:      1 = number the workgroups so that each of the eight XCDs
  *                  (each with its own L2) walks a contiguous run of tiles;
  *                  needs face_blocks to be a multiple of 8 (else ignored). */

@@ -36,7 +36,7 @@ struct FastArgs {
   bool split = false;  // FP16 operands: two-part FP16 re-check instead of FP32
   FastScratch scr{};
   // launch shapes (0 = default): waves per workgroup of the fused kernel,
-  // its workgroup cap, re-check / fix-up workgroups, XCD-contiguous order
+  // its workgroup cap, recheck_blocks (reserved, unused), XCD-contiguous order
   int face_waves = 0, face_blocks = 0, recheck_blocks = 0, xcd_order = 0;
   int n_cu = 256;  // compute units of the device (default grid of the 1D pass)
 };

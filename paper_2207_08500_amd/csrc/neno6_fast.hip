@@ -650,7 +650,9 @@ N6_DEV u32x4 split_input(const float s[6], int lane) {
 // With xcd != 0 the workgroup numbering is permuted so that the workgroups
 // the hardware places on one XCD (every 8th) take a contiguous run of tiles
 // (the host only sets it when gridDim.x is a multiple of 8).  Two waves per
-// SIMD (at three, 47 spilled registers made it 30 % slower).  Near-cutoff
+// SIMD: the kernel holds 212 registers and a four-wave workgroup 78.8 KB of
+// LDS (a build trimmed to three waves spilled 47 registers and was 30 %
+// slower).  Near-cutoff
 // evaluations (a few percent in 2D) are listed per tile in LDS and evaluated
 // again before the combine: in FP32 passes of 16 (mlp_f32_16, its table in
 // LDS) or, with SPLIT (FP16 operands), in two-part FP16 passes of 32
@@ -2137,8 +2139,8 @@ hipError_t launch_fast_reconstruct(const void *prepared, int precision, bool spl
   return hipGetLastError();
 }
 
-// 2D sweep: the fused face kernel in the tuned shape (four or eight waves;
-// two spill registers), or the selector-only instantiation.
+// 2D sweep: the fused face kernel in the tuned shape (four or eight waves),
+// or the selector-only instantiation.
 hipError_t launch_faces2d_kernel(const FaceLaunch &L, const FastArgs &fa, hipStream_t s,
                                  const Grid2D &g, int dir, const float *q, const uint8_t *mi,
                                  float *F, uint8_t *m) {

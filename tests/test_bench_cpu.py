@@ -51,3 +51,18 @@ def test_traffic_record_is_consistent():
     assert alg <= rec["bytes_per_launch"] < 4 * alg
     got = bench._traffic_record()
     assert got is None or got["bytes_per_launch"] == rec["bytes_per_launch"]
+
+
+def test_code_digest_ignores_comments_only():
+    """The traffic record's digest: comments and layout do not change it,
+    code (including string and character literals) does."""
+    import bench
+    base = 'int f(int a) {\n  return a + 1;  // one\n}\nconst char* s = "// kept";\n'
+    same = '/* header */\nint f(int a) { return a + 1; }\n// note\nconst char* s = "// kept";'
+    code = 'int f(int a) {\n  return a - 1;  // one\n}\nconst char* s = "// kept";\n'
+    lit = 'int f(int a) {\n  return a + 1;  // one\n}\nconst char* s = "// kepT";\n'
+    d = {k: bench.code_digest(["x"], read=lambda _, t=t: t)
+         for k, t in [("base", base), ("same", same), ("code", code), ("lit", lit)]}
+    assert d["base"] == d["same"]
+    assert d["base"] != d["code"] and d["base"] != d["lit"]
+    assert bench._strip_comments("char c = '\\''; // q") == "char c = '\\'';"
