@@ -12,21 +12,23 @@
 //   L1 6(+1 bias slot) -> 64 : 2 x v_mfma_f32_32x32x16 (K = 16: each feature
 //                              as its 16-bit value and the rounding remainder)
 //   L2 64 -> 32               : 4 x v_mfma_f32_32x32x16  (bias in the C input)
-//   L3 32 -> 16 (pad 32)      : 2 x v_mfma_f32_32x32x16
-//   L4 16 -> 8  (pad 32)      : 1 x v_mfma_f32_32x32x16
-//   L5 8 -> 4, both tiles     : 1 x v_mfma_f32_32x32x16, bias added in FP32
+//   L3 32 -> 16               : 2 x v_mfma_f32_16x16x32 (the tile's columns in
+//                              two blocks of 16, bias in the C input)
+//   L4 16 -> 8, both blocks   : 1 x v_mfma_f32_16x16x32 (block-diagonal)
+//   L5 8 -> 4, both tiles     : 1 x v_mfma_f32_16x16x32 (four diagonal blocks),
+//                              bias added in FP32
 // The inference tables hold the network with every hidden neuron scaled by an
 // a-priori bound of its pre-activation, so the clamp of the packed conversion
 // to [0, 1] is the ReLU (the training forward uses plain weights, K = 8 in
-// L1, and a packed integer max as the ReLU).
+// L1, L3..L5 on v_mfma_f32_32x32x*, and a packed integer max as the ReLU).
 //
 // One lane computes one face (projection, split, features, combine).  The
 // L1 inputs of the two 32-column tiles of a wave are exchanged between lane
-// halves with v_permlane32_swap.  The eight L4 outputs of a tile fill only
-// half of the K slots of L5, so the last product takes tile 0 in K slots
-// {0..3, 8..11} and tile 1 in {4..7, 12..15}, with tile 0's logits as rows
-// 0..3 and tile 1's as rows 4..7: every lane then holds its own stencil's
-// four logits in registers 0..3.  Evaluations whose smallest |logit| is below
+// halves with v_permlane32_swap, the L2 outputs between lane groups with
+// v_permlane16_swap.  The last product takes the L4 outputs of both tiles at
+// once, and each lane group ends with the logits of the 16 columns its own
+// stencils are in: every lane then holds its own stencil's four logits in
+// registers 0..3.  Evaluations whose smallest |logit| is below
 // the re-check margin are evaluated again inside the same kernel, before the
 // combine: in FP32 (mlp_f32_16 on MFMA, or the vector units in the scalar
 // kernels), or, as an option for FP16 operands (SPLIT), in two-part FP16
