@@ -96,6 +96,63 @@ N6_DEV float combine_pair(const float sp[6], unsigned selp, const float sm[6], u
   return combine_fast(sp, selp) + combine_fast(sm, selm);
 }
 
+// The re-normalised combination as one linear stencil per selection: with
+// the candidates in sel kept, h = sum_j c_j(sel) s_j, where c(sel) is the
+// combination of the unit stencils (sel = 0: the fallback s_2).  The
+// weights of every selection sum to one, so h = s_2 + sum_{j != 2} c_j
+// (s_j - s_2): the form the fused Euler kernels evaluate, whose rounding
+// scales with the stencil's variation rather than its size (a constant
+// stencil gives s_2 exactly).  They hold the 16 x 6 table in LDS,
+// coefficient j of selection m at [j][m] (lanes with different selections
+// read different banks, lanes with the same one the same word), and take
+// five differences and five products per reconstruction instead of four
+// candidates and their weights.
+struct CombTab {
+  float c[6][16];
+};
+// The candidates' coefficients on cells i-2..i+3 (those of candidates()) and
+// the table, both evaluated at compile time: entry [j][m] is the FP64
+// combination of the unit stencil e_j, rounded to FP32.
+constexpr double kCand[4][6] = {{0.0, -1.0 / 6, 5.0 / 6, 1.0 / 3, 0.0, 0.0},
+                                {0.0, 0.0, 1.0 / 3, 5.0 / 6, -1.0 / 6, 0.0},
+                                {1.0 / 3, -7.0 / 6, 11.0 / 6, 0.0, 0.0, 0.0},
+                                {0.0, 0.0, 1.0 / 4, 13.0 / 12, -5.0 / 12, 1.0 / 12}};
+constexpr CombTab make_comb_tab() {
+  const double d[4] = {Lin<double>::d0, Lin<double>::d1, Lin<double>::d2, Lin<double>::d3};
+  CombTab t{};
+  for (int m = 0; m < 16; ++m) {
+    double D = 0.0;
+    for (int k = 0; k < 4; ++k)
+      if (m >> k & 1) D += d[k];
+    for (int j = 0; j < 6; ++j) {
+      double c = m == 0 && j == 2 ? 1.0 : 0.0;
+      for (int k = 0; k < 4; ++k)
+        if (m >> k & 1) c += d[k] / D * kCand[k][j];
+      t.c[j][m] = (float)c;
+    }
+  }
+  return t;
+}
+// Copies the table into LDS; every thread of the workgroup calls it (it
+// ends with a barrier).
+N6_DEV void comb_fill(CombTab &t) {
+  constexpr CombTab k = make_comb_tab();
+  for (int i = (int)threadIdx.x; i < 96; i += (int)blockDim.x) t.c[i >> 4][i & 15] = k.c[i >> 4][i & 15];
+  __syncthreads();
+}
+// sel < 16 (a selection).
+N6_DEV float comb_tab(const CombTab &t, const float s[6], unsigned sel) {
+  float d = t.c[0][sel] * (s[0] - s[2]);
+  d = fmaf(t.c[1][sel], s[1] - s[2], d);
+  d = fmaf(t.c[3][sel], s[3] - s[2], d);
+  d = fmaf(t.c[4][sel], s[4] - s[2], d);
+  d = fmaf(t.c[5][sel], s[5] - s[2], d);
+  return s[2] + d;
+}
+N6_DEV float comb_pair_tab(const CombTab &t, const float sp[6], unsigned selp, const float sm[6], unsigned selm) {
+  return comb_tab(t, sp, selp) + comb_tab(t, sm, selm);
+}
+
 // Input scaling of the classifier (eq. normalizainput): divide by
 // max(|s_0|, ..., |s_5|, 1).
 template <typename T>

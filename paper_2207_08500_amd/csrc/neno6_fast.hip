@@ -675,6 +675,8 @@ k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared
   static_assert(!SPLIT || PREC == 3, "two-part re-check with FP16 operands only");
   constexpr int TREGS = SPLIT ? LO_REGS : F4_REGS;
   __shared__ u32 tlds[MLP ? TREGS * 64 : 1];
+  __shared__ CombTab ctab;
+  comb_fill(ctab);
   const float *b5 = (const float *)((const char *)prepared + PREP_B5_OFF);
   if constexpr (MLP) {
     const u32 *g = (const u32 *)((const char *)prepared + (SPLIT ? PREP_LO_OFF : PREP_F4_OFF));
@@ -809,7 +811,7 @@ k_fast_faces(Grid2D gd, int dir, int selector, const void *__restrict__ prepared
         sp[j] = stash[wv][(2 * m) * 6 + j][lane];
         sm[j] = stash[wv][(2 * m + 1) * 6 + j][lane];
       }
-      hs[m] = combine_pair(sp, sel[2 * m], sm, sel[2 * m + 1]);
+      hs[m] = comb_pair_tab(ctab, sp, sel[2 * m], sm, sel[2 * m + 1]);
     }
     const Roe2 rw{stash[wv][NE * 6][lane], stash[wv][NE * 6 + 1][lane], stash[wv][NE * 6 + 2][lane],
                   stash[wv][NE * 6 + 3][lane], stash[wv][NE * 6 + 4][lane]};
@@ -1144,8 +1146,8 @@ constexpr int NRECHECK_SLOTS = QCOUNTERS;
 //
 // Flat faces (six equal cells): every split stencil is constant, and the
 // re-normalised combination of a constant stencil is that constant for every
-// selection (the weights sum to one), so the pass takes it exactly
-// (h = s_2) and the flux does not depend on the labels.  Near-cutoff
+// selection (the weights sum to one); the difference form of the combine
+// gives it exactly (h = s_2), so the flux does not depend on the labels.  Near-cutoff
 // evaluations of flat faces are then re-checked only when the caller asks
 // for the labels (out.masks); they are most of the near evaluations of
 // piecewise-constant data.
@@ -1160,6 +1162,8 @@ k_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float marg
   // re-check list (lane << 3 | kind) and the re-checked labels (kind, lane)
   __shared__ uint16_t relist[W][MLP ? NE * 64 : 1];
   __shared__ uint8_t relab[W][MLP ? NE : 1][64];
+  __shared__ CombTab ctab;
+  comb_fill(ctab);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t nf = ln.faces();
   const int64_t ntile = (nf + 61) / 63;  // faces 63 t .. 63 t + 63 cover 0 .. nf - 1
@@ -1312,8 +1316,9 @@ k_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float marg
         sp[j] = stash[wv][(2 * m) * 6 + j][lane];
         sm[j] = stash[wv][(2 * m + 1) * 6 + j][lane];
       }
-      // a flat face's combine is its constant, exactly
-      hs[m] = flat ? sp[2] + sm[2] : combine_pair(sp, sel[2 * m], sm, sel[2 * m + 1]);
+      // a flat face's combine is its constant (the value the combine gives):
+      // waves whose faces are all flat skip the combine
+      hs[m] = flat ? sp[2] + sm[2] : comb_pair_tab(ctab, sp, sel[2 * m], sm, sel[2 * m + 1]);
     }
     roe_R1(Roe1{stash[wv][S_ROE][lane], stash[wv][S_ROE + 1][lane], stash[wv][S_ROE + 2][lane],
                 stash[wv][S_ROE + 3][lane]},

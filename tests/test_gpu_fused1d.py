@@ -133,6 +133,31 @@ def test_masks_in_elementwise(ctx, prec):
     assert err.max() <= 5e-5
 
 
+@pytest.mark.parametrize("prec", [2, 3])
+def test_masks_in_every_selection(ctx, prec):
+    """Imposed labels drawn at random (every one of the 16 x 16 selection
+    pairs of a characteristic field occurs): the pass's combine, one
+    coefficient stencil per selection, matches the oracle's re-normalised
+    combination to FP32 rounding at every cell, on smooth and on
+    discontinuous data."""
+    native, torch, P = ctx
+    q, off, dx = inputs.riemann1d_batch(34, SIZES, perturb=True)
+    q = q.astype(np.float32).astype(np.float64)
+    nf = off[-1] + len(SIZES)
+    mi = np.random.default_rng(35).integers(0, 256, 3 * nf).astype(np.uint8)
+    assert len(np.unique(mi)) == 256
+    r_o, m_o, _ = oracle.euler1d_rhs(q, off, dx, 1.4, 1, P, oracle.SEL_MASKS_IN, masks_in=mi)
+    assert np.array_equal(m_o.ravel(), mi)
+    mlp = native.Mlp(dev(P), recheck_margin=MARGIN[prec])
+    prob = native.Problem(native.EULER1D, prec, native.SEL_MASKS_IN, 1, off, dx)
+    r = torch.zeros(q.shape, dtype=torch.float32, device="cuda").reshape(-1)
+    native.neno6_rhs(prob, mlp, dev(q, torch.float32), r, prob.workspace(), masks_in=dev(mi))
+    torch.cuda.synchronize()
+    err = np.abs(host(r).reshape(3, -1) - r_o) / _fscale(r_o, q, off, dx)
+    print("prec %d: max rel err %.3g" % (prec, err.max()))
+    assert err.max() <= 5e-5
+
+
 def _f32(x):
     return np.asarray(x, np.float64).astype(np.float32)
 

@@ -84,3 +84,33 @@ def test_rhs2d_elementwise_against_oracle(ctx, prec, mode, margin):
         assert ok.mean() > 0.98
         assert same
         assert err <= 5e-5
+
+
+@pytest.mark.parametrize("prec", [2, 3])
+def test_rhs2d_masks_in_every_selection(ctx, prec):
+    """Imposed labels drawn at random (all 256 selection pairs occur in both
+    sweeps): the sweep's combine, one coefficient stencil per selection,
+    matches the oracle's re-normalised combination to FP32 rounding."""
+    native, torch, P = ctx
+    q = inputs.riemann2d(45, 67, 45)
+    _, ny, nx = q.shape
+    q32 = q.astype(np.float32).astype(np.float64)
+    nm = 4 * ((nx + 1) * ny + nx * (ny + 1))
+    mi = np.random.default_rng(46).integers(0, 256, nm).astype(np.uint8)
+    assert len(np.unique(mi)) == 256
+    nfx = 4 * (nx + 1) * ny
+    r_o, mx_o, my_o, _ = oracle.euler2d_rhs(q32, 1 / nx, 1 / ny, 1.4, 1, P, oracle.SEL_MASKS_IN,
+                                             masks_in=(mi[:nfx], mi[nfx:]))
+    assert np.array_equal(np.concatenate([mx_o.ravel(), my_o.ravel()]), mi)
+    mlp = native.Mlp(dev(P), recheck_margin=MARGIN[prec])
+    pin = native.Problem(native.EULER2D, prec, native.SEL_MASKS_IN, 1, nx=nx, ny=ny, dx2d=1 / nx,
+                         dy2d=1 / ny)
+    qg = dev(q32, torch.float32)
+    r = torch.zeros_like(qg)
+    native.neno6_rhs(pin, mlp, qg, r, pin.workspace(), masks_in=dev(mi))
+    torch.cuda.synchronize()
+    r = host(r).reshape(q.shape)
+    fscale = np.abs(r_o).max() + np.abs(q).max() * max(nx, ny)
+    err = np.abs(r - r_o).max() / fscale
+    print("prec %d: max rel err %.3g" % (prec, err))
+    assert err <= 5e-5

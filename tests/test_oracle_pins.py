@@ -168,6 +168,10 @@ def _mask_row(mask):
 def test_sixteen_masks_brute_force():
     s = inputs.random_stencils(3, 64)
     for mask in range(16):
+        # every selection's stencil weights sum to one exactly (each candidate
+        # reproduces constants and the kept weights are re-normalised), so
+        # h = s_2 + sum_{j != 2} c_j (s_j - s_2) for every selection
+        assert sum(_mask_row(mask)) == 1
         row = np.array([float(c) for c in _mask_row(mask)])
         for e in range(s.shape[0]):
             f = np.concatenate([s[e], np.zeros(5)])
