@@ -56,14 +56,17 @@ PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # algorithmic VALU work per 1D Euler face outside the MFMA contractions,
 # from rounded item estimates (primitives 90, Roe 40, projection + split 180,
 # speeds 20, features 80, one operation per hidden activation 720, output
-# bias + labels 50, combine 180, back-projection 12: 1372) and a strict
-# one-operation-per-arithmetic-instruction count (1319); the value used lies
-# between them, so the VALU fraction carries about +-2 %
-VALU_OPS_PER_FACE = 1350
+# bias + labels 50, combine 69, back-projection 12: 1261) and a strict
+# one-operation-per-arithmetic-instruction count (1208); the value used lies
+# between them, so the VALU fraction carries about +-2 %.  The combine is
+# counted in its table form: per reconstruction five differences, five
+# products and one sum (the re-normalised combination of a selection is one
+# linear stencil), plus the sum of the two split reconstructions
+VALU_OPS_PER_FACE = 1235
 # 2D Euler face (one sweep): primitives 100, Roe average and eigenvectors 60,
 # projection + split 240, speeds 30, features 104, hidden activations 960,
-# output bias + labels 64, combine 240, back-projection 16
-VALU_OPS_PER_FACE_2D = 1814
+# output bias + labels 64, combine 92, back-projection 16: 1666; strict count 1651
+VALU_OPS_PER_FACE_2D = 1660
 EVALS_PER_FACE_2D = 8
 FLOP_PER_EVAL = 6208      # 2 x 3104 MAC of the 6-64-32-16-8-4 network
 EVALS_PER_FACE = 6        # 3 characteristic fields x 2 split signs
@@ -167,6 +170,8 @@ def _args():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c2", action="store_true", help="c4: skip the nested 256 x 4000 batch")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="c4: skip the nested batch with a density wave in every other problem")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--workload", choices=("c2", "c3", "c4", "c5"), default="c4",
                     help="c4: 4096 uneven 1D problems (headline); c2: 256 x 4000-cell batch; "
@@ -307,13 +312,15 @@ def bench_1d(a, P, dev, name):
     # the FP64 path over the timed steps: the accuracy reference
     q64b, _, st64b, _, _, _ = run_steps(native.FP64, q64_from32, a.steps, 0, graph=not a.no_graph)
 
-    def errors(qa, sta):
+    def errors(qa, sta, qref=None, stref=None):
         # problems whose state turned non-physical (no positivity limiter in
         # the scheme) are frozen by the solver and left out of the norms
-        okp = ((sta == 0) & (st64b == 0)).cpu().numpy() & _physical(qa, off) & _physical(q64b, off)
+        qref = q64b if qref is None else qref
+        stref = st64b if stref is None else stref
+        okp = ((sta == 0) & (stref == 0)).cpu().numpy() & _physical(qa, off) & _physical(qref, off)
         cell_ok = torch.as_tensor(np.repeat(okp, np.diff(off)), device=dev)
-        dq = (qa.double() - q64b).abs().reshape(3, -1)[:, cell_ok]
-        ref = q64b.reshape(3, -1)[:, cell_ok]
+        dq = (qa.double() - qref).abs().reshape(3, -1)[:, cell_ok]
+        ref = qref.reshape(3, -1)[:, cell_ok]
         return (float((dq.mean(dim=1) / ref.abs().mean(dim=1)).max()),
                 float((dq.max(dim=1).values / ref.abs().max(dim=1).values).max()), int(okp.sum()))
 
@@ -357,6 +364,40 @@ def bench_1d(a, P, dev, name):
         return float((x != 0).any(axis=0).mean())
 
     n_evals = faces_stage * EVALS_PER_FACE
+
+    # ---- the same batch with a density wave in every other problem (the
+    # Riemann states of the headline and perturbed ones): smooth regions
+    # instead of constant states -------------------------------------------------------
+    mixed = None
+    if name == "c4" and not a.no_mixed:
+        qm0, _, _ = inputs.riemann1d_batch(inputs.BASE_SEED, sizes, perturb="odd")
+        qm32 = torch.as_tensor(qm0, dtype=torch.float32, device=dev).contiguous()
+        qmh, _, stmh, ms_mh, _, _ = run_steps(HEAD, qm32, a.steps, a.warmup, graph=not a.no_graph)
+        qmb, _, stmb, ms_mb, _, _ = run_steps(native.BF16, qm32, a.steps, a.warmup,
+                                              graph=not a.no_graph)
+        qm64, _, stm64, _, _, _ = run_steps(native.FP64, qm32.double().contiguous(), a.steps, 0,
+                                            graph=not a.no_graph)
+        l1_m, linf_m, n_m = errors(qmh, stmh, qm64, stm64)
+        l1_mb, linf_mb, _ = errors(qmb, stmb, qm64, stm64)
+        qm_ev32 = qm64.float().contiguous()
+        mm64, _ = labels(native.FP64, qm_ev32.double().contiguous(), 0.0)
+        mmh, re_mh = labels(native.FP16, qm_ev32, MARGIN[3])
+        mmb, re_mb = labels(native.BF16, qm_ev32, MARGIN[2])
+        mixed = {"workload": "the same 4096 problems, those of odd index with the density "
+                             "multiplied by 1 + 0.2 sin(2 pi k x), k in 1..8",
+                 "value": faces_step * a.steps / (ms_mh / 1e3), "unit": "faces/s",
+                 "ms_per_step": ms_mh / a.steps, "l1_rel_vs_fp64": l1_m,
+                 "linf_rel_vs_fp64": linf_m, "flip_rate": flip(mmh, mm64),
+                 "recheck_fraction": re_mh / float(n_evals),
+                 "bf16_mfma": {"value": faces_step * a.steps / (ms_mb / 1e3), "unit": "faces/s",
+                               "ms_per_step": ms_mb / a.steps, "l1_rel_vs_fp64": l1_mb,
+                               "linf_rel_vs_fp64": linf_mb, "flip_rate": flip(mmb, mm64),
+                               "recheck_fraction": re_mb / float(n_evals)},
+                 "frozen_problems": {"fp16": int((stmh != 0).sum()),
+                                     "bf16": int((stmb != 0).sum()),
+                                     "fp64": int((stm64 != 0).sum())},
+                 "problems_in_error_norms": n_m}
+
     lab = {"state": "FP64 path after the %d timed RK3 steps, rounded to FP32" % a.steps,
            "flip_rate_fp16": flip(mh16, m64), "flip_rate_per_face_fp16": flip_faces(mh16, m64),
            "flip_rate_fp16_without_recheck": flip(mh0, m64),
@@ -520,6 +561,7 @@ def bench_1d(a, P, dev, name):
         "frozen_problems": {"fp16": int((sth != 0).sum()), "bf16": int((stb != 0).sum()),
                             "fp64": int((st64b != 0).sum()), "of": n_prob},
         "problems_in_error_norms": n_norm,
+        "perturbed_half": mixed,
         "cpu_baseline": cpu,
     }
 

@@ -119,14 +119,18 @@ def conservative2d(rho, u, v, p, gamma=GAMMA):
     return np.stack([rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
 
 
-def riemann1d_batch(seed: int = BASE_SEED, sizes=(4000,) * 256, perturb: bool = False,
+def riemann1d_batch(seed: int = BASE_SEED, sizes=(4000,) * 256, perturb=False,
                     gamma: float = GAMMA):
     """Concatenated 1D Riemann problems on [0, 1].
 
     Left/right states: rho ~ U[0.1, 1], u ~ U[-1, 1], p ~ log-uniform[0.1, 1000];
     diaphragm at x0 ~ U[0.2, 0.8].  With ``perturb`` the density also carries
-    a sinusoidal wave (amplitude 0.2, wavenumber 1-8), multiplicative.
+    a sinusoidal wave (amplitude 0.2, wavenumber 1-8), multiplicative; with
+    ``perturb="odd"`` only the problems of odd index do (the others are
+    those of the unperturbed batch).
     Returns (q [3][total] FP64, offsets [n+1] int64, dx [n] FP64)."""
+    if perturb not in (False, True, "odd"):
+        raise ValueError("perturb: False, True or 'odd'")
     sizes = np.asarray(sizes, dtype=np.int64)
     g = rng(seed, 2, int(sizes.size))
     offsets = np.zeros(sizes.size + 1, np.int64)
@@ -141,7 +145,7 @@ def riemann1d_batch(seed: int = BASE_SEED, sizes=(4000,) * 256, perturb: bool = 
         x = cell_centres(int(n), 0.0, 1.0)
         left = x < x0[i]
         rho = np.where(left, rl[i], rr[i])
-        if perturb:
+        if perturb is True or (perturb == "odd" and i % 2 == 1):
             rho = rho * (1.0 + 0.2 * np.sin(2 * np.pi * kw[i] * x))
         u = np.where(left, ul[i], ur[i])
         p = np.where(left, pl[i], pr[i])

@@ -66,3 +66,23 @@ def test_code_digest_ignores_comments_only():
     assert d["base"] == d["same"]
     assert d["base"] != d["code"] and d["base"] != d["lit"]
     assert bench._strip_comments("char c = '\\''; // q") == "char c = '\\'';"
+
+
+def test_perturbed_half_batch():
+    """The benchmark's second 4096-problem batch: problems of even index are
+    those of the plain Riemann batch, those of odd index those of the fully
+    perturbed one (same draws)."""
+    import numpy as np
+    import pytest
+
+    from paper_2207_08500_amd import inputs
+    sizes = np.array([300, 257, 1000, 64, 5])
+    a, off, _ = inputs.riemann1d_batch(9, sizes)
+    b, _, _ = inputs.riemann1d_batch(9, sizes, perturb=True)
+    c, _, _ = inputs.riemann1d_batch(9, sizes, perturb="odd")
+    for i in range(sizes.size):
+        want = (b if i % 2 else a)[:, off[i]:off[i + 1]]
+        assert np.array_equal(c[:, off[i]:off[i + 1]], want)
+        assert not np.array_equal(a[:, off[i]:off[i + 1]], b[:, off[i]:off[i + 1]])
+    with pytest.raises(ValueError):
+        inputs.riemann1d_batch(9, sizes, perturb="even")
