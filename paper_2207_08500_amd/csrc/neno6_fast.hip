@@ -311,6 +311,71 @@ N6_DEV u32x2 mlp_front(const Wts &w, u32x4 bin) {
   return u32x2{h4[0], h4[1]};
 }
 
+// mlp_front for both 32-evaluation tiles of a wave, their chains
+// interleaved: each phase issues one tile's MFMAs while the other tile's
+// conversions of the previous layer run, so a wave has MFMA work queued
+// while it waits for results (the scheduling barriers keep the phase order;
+// tile 1's L1 products are issued between tile 0's L1 conversions, which
+// keeps the live accumulators to three 32x32 tiles).  Used by the 1D pass
+// with FP16 operands (3.5 % shorter steps there); with BF16 operands, whose
+// conversion blocks carry fixed waits, and in the 2D sweep kernel (two
+// waves per SIMD) it measured 1-2 % slower than two mlp_front calls.
+template <int PREC>
+N6_DEV void mlp_front2(const Wts &w, u32x4 bin0, u32x4 bin1, u32x2 &o0, u32x2 &o1) {
+  const f32x16 zero = {};
+  const f32x16 a0 = mma16<PREC>(w.a1x[0], bin0, zero);
+  const f32x16 b0 = mma16<PREC>(w.a1x[1], bin0, zero);
+  __builtin_amdgcn_sched_barrier(0);
+  u32 p0[8], q0[8];
+  act_block<PREC, 8>(a0, 0, p0);
+  const f32x16 a1 = mma16<PREC>(w.a1x[0], bin1, zero);
+  act_block<PREC, 8>(b0, 0, q0);
+  const f32x16 b1 = mma16<PREC>(w.a1x[1], bin1, zero);
+  __builtin_amdgcn_sched_barrier(0);
+  f32x16 c20 = mma16<PREC>(w.a2[0], u32x4{p0[0], p0[1], p0[2], p0[3]}, w.b2);
+  c20 = mma16<PREC>(w.a2[1], u32x4{p0[4], p0[5], p0[6], p0[7]}, c20);
+  c20 = mma16<PREC>(w.a2[2], u32x4{q0[0], q0[1], q0[2], q0[3]}, c20);
+  c20 = mma16<PREC>(w.a2[3], u32x4{q0[4], q0[5], q0[6], q0[7]}, c20);
+  __builtin_amdgcn_sched_barrier(0);
+  u32 p1[8], q1[8];
+  act_block<PREC, 8>(a1, 0, p1);
+  act_block<PREC, 8>(b1, 0, q1);
+  f32x16 c21 = mma16<PREC>(w.a2[0], u32x4{p1[0], p1[1], p1[2], p1[3]}, w.b2);
+  c21 = mma16<PREC>(w.a2[1], u32x4{p1[4], p1[5], p1[6], p1[7]}, c21);
+  c21 = mma16<PREC>(w.a2[2], u32x4{q1[0], q1[1], q1[2], q1[3]}, c21);
+  c21 = mma16<PREC>(w.a2[3], u32x4{q1[4], q1[5], q1[6], q1[7]}, c21);
+  __builtin_amdgcn_sched_barrier(0);
+  u32 h20[8];
+  act_block<PREC, 8>(c20, 0, h20);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) swap16(h20[q], h20[4 + q]);
+  const f32x4 c3a0 = mma4x<PREC>(w.t3, u32x4{h20[0], h20[1], h20[2], h20[3]}, w.c3);
+  const f32x4 c3b0 = mma4x<PREC>(w.t3, u32x4{h20[4], h20[5], h20[6], h20[7]}, w.c3);
+  __builtin_amdgcn_sched_barrier(0);
+  u32 h21[8];
+  act_block<PREC, 8>(c21, 0, h21);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) swap16(h21[q], h21[4 + q]);
+  const f32x4 c3a1 = mma4x<PREC>(w.t3, u32x4{h21[0], h21[1], h21[2], h21[3]}, w.c3);
+  const f32x4 c3b1 = mma4x<PREC>(w.t3, u32x4{h21[4], h21[5], h21[6], h21[7]}, w.c3);
+  __builtin_amdgcn_sched_barrier(0);
+  u32 h30[4];
+  act4<PREC>(c3a0, h30);
+  act4<PREC>(c3b0, h30 + 2);
+  const f32x4 c40 = mma4x<PREC>(w.t4, u32x4{h30[0], h30[1], h30[2], h30[3]}, w.c4);
+  __builtin_amdgcn_sched_barrier(0);
+  u32 h31[4];
+  act4<PREC>(c3a1, h31);
+  act4<PREC>(c3b1, h31 + 2);
+  const f32x4 c41 = mma4x<PREC>(w.t4, u32x4{h31[0], h31[1], h31[2], h31[3]}, w.c4);
+  __builtin_amdgcn_sched_barrier(0);
+  u32 h40[2], h41[2];
+  act4<PREC>(c40, h40);
+  act4<PREC>(c41, h41);
+  o0 = u32x2{h40[0], h40[1]};
+  o1 = u32x2{h41[0], h41[1]};
+}
+
 // The six features of one stencil as packed pairs: x[0..2] their values
 // rounded to the table precision, x[3..5] what that rounding left (so the
 // first layer sees each feature to about twice the precision's bits).
@@ -346,8 +411,9 @@ N6_DEV u32 mask_near(const float z[4], float margin) {
 // Classifies the stencil held by every lane of the wave (all 64 lanes must
 // call it together): tile 0 = the stencils of lanes 0..31, tile 1 = lanes
 // 32..63.  Returns the lane's mask | near-flag << 4; with z != 0 also returns
-// the lane's four logits.
-template <int PREC>
+// the lane's four logits.  PAIR: the two tiles' chains interleaved
+// (mlp_front2); same results.
+template <int PREC, bool PAIR = false>
 N6_DEV u32 classify_packed(const Wts &w, const u32 xin[6], float margin, float *z_out) {
   // K slots of the first layer: lanes 0..31 carry the leading parts (slots
   // 0..5) and the bias input 1 (slot 6), lanes 32..63 the trailing parts
@@ -362,8 +428,13 @@ N6_DEV u32 classify_packed(const Wts &w, const u32 xin[6], float margin, float *
     swap32(a[p], b[p]);
   }
   const u32 cin = (threadIdx.x & 32) ? 0u : one_zero<PREC>();
-  const u32x2 h0 = mlp_front<PREC>(w, u32x4{a[0], a[1], a[2], cin});
-  const u32x2 h1 = mlp_front<PREC>(w, u32x4{b[0], b[1], b[2], cin});
+  u32x2 h0, h1;
+  if constexpr (PAIR) {
+    mlp_front2<PREC>(w, u32x4{a[0], a[1], a[2], cin}, u32x4{b[0], b[1], b[2], cin}, h0, h1);
+  } else {
+    h0 = mlp_front<PREC>(w, u32x4{a[0], a[1], a[2], cin});
+    h1 = mlp_front<PREC>(w, u32x4{b[0], b[1], b[2], cin});
+  }
   // L5 for the four 16-column blocks at once: K slots 8G..8G+3 from tile 0,
   // 8G+4..8G+7 from tile 1 (each group's L4 rows), output rows 4B..4B+3 the
   // logits of block B = (tile 0 A, tile 0 B, tile 1 A, tile 1 B): lane group G
@@ -1139,8 +1210,10 @@ N6_DEV void cell_out(const Line1D &ln, const Out1D &out, const Face1 &fa, int kc
 // slot (workgroup * waves + wave) % NRECHECK_SLOTS, so few waves share one.
 constexpr int NRECHECK_SLOTS = QCOUNTERS;
 
-// The fused 1D Euler pass.  Three waves per SIMD (167 registers, no spills;
-// the third wave hides more of the MFMA -> convert -> MFMA latency).  The
+// The fused 1D Euler pass.  Three waves per SIMD (168 registers; one value
+// used only after the tile loop waits in scratch; the third wave hides more
+// of the MFMA -> convert -> MFMA latency).  With FP16 operands the two
+// tiles' classifier chains are interleaved (mlp_front2).  The
 // cell's line data and the stage's u0 are loaded before the combine, so their
 // latency overlaps it.
 //
@@ -1220,7 +1293,7 @@ k_euler1d(Line1D ln, int selector, const void *__restrict__ prepared, float marg
 #pragma unroll
           for (int j = 0; j < 6; ++j) sn[j] = stash[wv][(e + 1) * 6 + j][lane];
         }
-        const u32 mk = classify_packed<PREC>(w, xe, margin, nullptr);
+        const u32 mk = classify_packed<PREC, PREC == 3>(w, xe, margin, nullptr);
         sel[e] = mk & 15u;
         near |= (mk >> 4) << e;
       } else if (selector == 1) {
