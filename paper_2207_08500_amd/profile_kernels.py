@@ -22,6 +22,8 @@ replayed after about 0.1 s of warm-up replays, in the --shape launch shape if
 given, else the autotuner's; a one-element torch fill right before the timed
 replays marks where they start in a kernel trace.  --2d: the 2D Euler
 four-quadrant Riemann problem on 2048 x 2048 cells instead of a 1D batch.
+--perturb-odd: the 1D batch with the density wave in every problem of odd
+index (smooth regions where the plain batch has constant states).
 """
 import argparse
 import os
@@ -46,12 +48,12 @@ def _margins():
 MARGIN = _margins()
 
 
-def batch(workload):
+def batch(workload, perturb=False):
     if workload == "c4":
         sizes = inputs.uneven_sizes(inputs.BASE_SEED, 4096, 256, 16384)
     else:
         sizes = np.full(256, 4000, np.int64)
-    return inputs.riemann1d_batch(inputs.BASE_SEED, sizes)
+    return inputs.riemann1d_batch(inputs.BASE_SEED, sizes, perturb=perturb)
 
 
 def main():
@@ -64,13 +66,15 @@ def main():
     ap.add_argument("--shape", default=None, help="W,B: waves per workgroup, workgroups")
     ap.add_argument("--workload", choices=("c4", "c2"), default="c4")
     ap.add_argument("--2d", dest="two_d", action="store_true")
+    ap.add_argument("--perturb-odd", action="store_true",
+                    help="every problem of odd index with the density wave (no constant states)")
     a = ap.parse_args()
     native.load()
     dev = torch.device("cuda:0")
     P = np.load(os.path.join(ROOT, "tests", "golden", "neno6_mlp_trained.npy"), allow_pickle=False)
     if a.steps > 0 and a.two_d:
         return step_replay_2d(a.steps, P, dev)
-    q0, off, dx = batch(a.workload)
+    q0, off, dx = batch(a.workload, "odd" if a.perturb_odd else False)
     q32 = torch.as_tensor(q0, dtype=torch.float32, device=dev).contiguous()
     if a.steps > 0:
         return step_replay(a.steps, P, q32, off, dx, dev, a.shape)
@@ -86,7 +90,8 @@ def main():
                                                 recheck_margin=MARGIN[native.FP16]),
                                q32, prob.workspace(dev))[0]
         torch.cuda.synchronize()
-    print("workload %s, launch shape %s" % (a.workload, shape), flush=True)
+    print("workload %s%s, launch shape %s" % (a.workload, ", density wave in every other problem"
+                                              if a.perturb_odd else "", shape), flush=True)
     for prec in (native.FP16, native.BF16):
         mlp = native.Mlp(torch.as_tensor(P, device=dev), recheck_margin=MARGIN[prec])
         prob = native.Problem(native.EULER1D, prec, native.SEL_MLP, native.TRANSMISSIVE, off, dx,
