@@ -281,9 +281,9 @@ int32_t neno6_recheck_count(const neno6_problem *prob, const neno6_mlp *mlp, con
  * face pass of `prob` (1D: the fused kernel with its in-pass re-check; 2D:
  * both sweeps of the sweep kernel with its in-tile re-check) on state q [dev]
  * for every launch shape of a candidate set -- waves per workgroup W in
- * {2, 4, 8} (2D: {4, 8}) x workgroup caps {512, 1024, 2048, 4096, 16384,
- * 65536, and k * V * CUs / W for k = 1, 2, 3 (whole rounds of resident waves
- * on the current device, V = 12 waves per CU in 1D, 8 in 2D)} x XCD ordering
+ * {2, 4, 8} (2D: {4, 8}) x workgroup caps {16384, 65536, and k rounds of
+ * resident workgroups for k = 1, 2, 3, 4, 6 (on the current device: 12 / W
+ * workgroups per CU in 1D, one of eight waves; 8 / W in 2D)} x XCD ordering
  * {0, 1} -- with HIP events on `stream`, after about
  * 0.1 s of warm-up passes in the default shape, `reps` (1..1000) timed
  * passes each after one warm-up, and writes the fastest to *best [host] (its mean pass
