@@ -294,3 +294,37 @@ def test_c2_full_size_evolved_state(ctx, prec, mode):
           % (prec, flips, worst, n_re / (6.0 * (off[-1] + 256))))
     assert max(flips) < 1e-4
     assert worst <= 5e-5
+
+
+@pytest.mark.parametrize("prec", [2, 3])
+def test_steps_in_one_call_equal_one_call_per_step(ctx, prec):
+    """Forty SSP-RK3 steps (Sec. 4.4) in one neno6_step call and in forty
+    calls of one step give the same states, times and statuses bit for bit,
+    with a frozen problem and problems that turn non-physical on the way
+    (their time step, status and freezing within a call)."""
+    native, torch, P = ctx
+    rng = np.random.default_rng(37)
+    sizes = tuple(int(n) for n in rng.integers(1, 300, 256))
+    q, off, dx = inputs.riemann1d_batch(38, sizes)
+    mlp = native.Mlp(dev(P), recheck_margin=MARGIN[prec])
+    prob = native.Problem(native.EULER1D, prec, native.SEL_MLP, 1, off, dx)
+    ws = prob.workspace()
+    n = len(sizes)
+
+    def run(calls, per):
+        qq = dev(q, torch.float32)
+        t = torch.zeros(n, dtype=torch.float64, device="cuda")
+        st = torch.zeros(n, dtype=torch.int32, device="cuda")
+        st[5] = -4  # frozen from the start
+        for _ in range(calls):
+            native.neno6_step(prob, mlp, qq, 0.4, per, t, st, ws)
+        torch.cuda.synchronize()
+        return host(qq), host(t), host(st)
+
+    qa, ta, sa = run(1, 40)
+    qb, tb, sb = run(40, 1)
+    print("prec %d: %d of %d problems non-physical after 40 steps" % (prec, (sa != 0).sum() - 1, n))
+    assert (sa != 0).sum() >= 2  # the frozen one and at least one that turned non-physical
+    assert np.array_equal(sa, sb)
+    assert np.array_equal(ta.view(np.uint64), tb.view(np.uint64))
+    assert np.array_equal(qa.view(np.uint32), qb.view(np.uint32))
